@@ -1,0 +1,268 @@
+"""CPU oracle for on-device spiking-network construction -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``snnc_oracle.c`` (plain,
+single-threaded C; see the header of that file for what it computes and which
+passages of arXiv:2512.09502 each step follows) through ctypes.  It shares no
+code with the GPU library and never imports it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "snnc_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+RULES = {"one_to_one": 0, "fixed_indegree": 1, "fixed_outdegree": 2,
+         "fixed_total_number": 3, "pairwise_bernoulli": 4}
+DISTS = {"const": 0, "normal": 1}
+
+# array ids and dtypes (same numbering as the C file's accessor enum)
+ARRAYS = {
+    "gen_src": (0, np.uint32), "gen_tgt": (1, np.uint32), "gen_delay": (2, np.uint16),
+    "gen_weight": (3, np.float32), "gen_e": (4, np.uint64), "call_off": (5, np.uint64),
+    "src": (10, np.int32), "tgt": (11, np.int32), "delay": (12, np.uint16),
+    "weight": (13, np.float32), "row_ptr": (14, np.uint64),
+    "r_off": (20, np.uint64), "r_val": (21, np.int32), "img_base": (22, np.int64),
+    "s_off": (30, np.uint64), "s_val": (31, np.int32), "tp_ptr": (32, np.uint64),
+    "t_val": (33, np.uint32), "p_val": (34, np.uint32),
+    "groups": (40, np.int32), "h_off": (41, np.uint64), "h_val": (42, np.int32),
+    "i_val": (43, np.int32), "gq_ptr": (44, np.uint64), "g_val": (45, np.int32),
+    "q_val": (46, np.uint32),
+}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        u32, u64, i32, i64, dbl = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
+                                   ctypes.c_int64, ctypes.c_double)
+        vp = ctypes.c_void_p
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_uniform_index.argtypes = [u32, u32, u64]
+        L.orc_uniform_index.restype = u64
+        L.orc_normal_weight.argtypes = [u32, u32, dbl, dbl]
+        L.orc_normal_weight.restype = ctypes.c_float
+        L.orc_delay_table.argtypes = [dbl, dbl, dbl, dbl, vp, u64, vp]
+        L.orc_delay_table.restype = i64
+        L.orc_new.argtypes = [u32, u32, u32, dbl]
+        L.orc_new.restype = vp
+        L.orc_free.argtypes = [vp]
+        L.orc_last_error.argtypes = [vp]
+        L.orc_last_error.restype = ctypes.c_char_p
+        L.orc_create.argtypes = [vp, u32, u32, vp]
+        conn_args = [vp, vp, u32, vp, u32, ctypes.c_int, u64, dbl, ctypes.c_int, ctypes.c_int,
+                     ctypes.c_int, dbl, dbl, ctypes.c_int, dbl, dbl, dbl, i32, vp]
+        L.orc_connect.argtypes = conn_args
+        L.orc_declare.argtypes = conn_args
+        L.orc_prepare.argtypes = [vp]
+        L.orc_len.argtypes = [vp, ctypes.c_int]
+        L.orc_len.restype = i64
+        L.orc_copy.argtypes = [vp, ctypes.c_int, vp, u64]
+        L.orc_neurons.argtypes = [vp, u32]
+        L.orc_neurons.restype = u32
+        L.orc_call_range.argtypes = [vp, u32, u32, u64, u64, vp, vp, vp, vp, vp, u64]
+        L.orc_call_range.restype = i64
+        L.orc_sort_csr.argtypes = [u64, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp]
+        L.orc_transpose_lists.argtypes = [u32, vp, vp, u32, vp, vp, vp]
+        L.orc_transpose_lists.restype = u64
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------- primitives
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniform_index(lo: int, hi: int, n: int) -> int:
+    return int(lib().orc_uniform_index(lo, hi, n))
+
+
+def normal_weight(w0: int, w1: int, mean: float, sd: float) -> float:
+    return float(lib().orc_normal_weight(w0, w1, mean, sd))
+
+
+def delay_table(mean: float, sd: float, lo: float, dt: float):
+    """Return (k_lo, thresholds uint32[]) or None if it does not fit."""
+    buf = np.zeros(65536, np.uint32)
+    klo = np.zeros(1, np.uint32)
+    n = lib().orc_delay_table(mean, sd, lo, dt, _ptr(buf), buf.size, _ptr(klo))
+    if n < 0:
+        return None
+    return int(klo[0]), buf[:n].copy()
+
+
+def sort_csr(src, tgt, delay, weight, n_rows: int) -> dict:
+    """The source-major sort and first-index step on given arrays."""
+    src = np.ascontiguousarray(src, np.int32)
+    tgt = np.ascontiguousarray(tgt, np.uint32)
+    delay = np.ascontiguousarray(delay, np.uint16)
+    weight = np.ascontiguousarray(weight, np.float32)
+    n = src.size
+    out = {"src": np.zeros(n, np.int32), "tgt": np.zeros(n, np.int32),
+           "delay": np.zeros(n, np.uint16), "weight": np.zeros(n, np.float32),
+           "row_ptr": np.zeros(n_rows + 1, np.uint64)}
+    lib().orc_sort_csr(n, _ptr(src), _ptr(tgt), _ptr(delay), _ptr(weight), n_rows,
+                       _ptr(out["src"]), _ptr(out["tgt"]), _ptr(out["delay"]), _ptr(out["weight"]),
+                       _ptr(out["row_ptr"]))
+    return out
+
+
+def transpose_lists(lists, M: int):
+    """Per-neuron (list index, position) pairs of sorted lists (T/P, G/Q)."""
+    off = np.zeros(len(lists) + 1, np.uint64)
+    for k, l in enumerate(lists):
+        off[k + 1] = off[k] + len(l)
+    val = np.ascontiguousarray(np.concatenate([np.asarray(l, np.int32) for l in lists])
+                               if lists else np.zeros(0, np.int32), np.int32)
+    ptr = np.zeros(M + 1, np.uint64)
+    cap = max(1, int(off[-1]))
+    which = np.zeros(cap, np.uint32)
+    pos = np.zeros(cap, np.uint32)
+    n = lib().orc_transpose_lists(len(lists), _ptr(off), _ptr(val), M, _ptr(ptr), _ptr(which), _ptr(pos))
+    return ptr, which[:n], pos[:n]
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"oracle status {code}: {msg}")
+        self.code = code
+
+
+# ---------------------------------------------------------------- network
+def _triples(segs) -> np.ndarray:
+    a = np.asarray(segs, dtype=np.uint32).reshape(-1, 3)
+    return np.ascontiguousarray(a)
+
+
+def _dist(d):
+    if d is None:
+        return 0, 0.0, 0.0, 0.0
+    kind = DISTS[d.get("kind", "const")]
+    return kind, float(d.get("mean", 0.0)), float(d.get("sd", 0.0)), float(d.get("lo", 0.0))
+
+
+class OracleNet:
+    """One host's share of a network, built by the C oracle."""
+
+    def __init__(self, P: int, P_local: int, seed: int, dt: float):
+        self._h = lib().orc_new(P, P_local, seed, dt)
+        if not self._h:
+            raise OracleError(-1, "invalid P/P_local/dt")
+        self.P, self.P_local = P, P_local
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_free(h)
+            self._h = None
+
+    def _check(self, st):
+        if st != 0:
+            raise OracleError(st, lib().orc_last_error(self._h).decode())
+
+    def create(self, host: int, n: int) -> tuple:
+        first = np.zeros(1, np.uint32)
+        self._check(lib().orc_create(self._h, host, n, _ptr(first)))
+        return (host, int(first[0]), n)
+
+    def _conn(self, fn, src, tgt, conn, syn, alpha):
+        s, t = _triples(src), _triples(tgt)
+        wk, wm, wsd, _ = _dist(syn.get("weight"))
+        dk, dm, dsd, dlo = _dist(syn.get("delay"))
+        cid = np.zeros(1, np.uint32)
+        st = fn(self._h, _ptr(s), s.shape[0], _ptr(t), t.shape[0], RULES[conn["rule"]],
+                int(conn.get("n", 0)), float(conn.get("p", 0.0)),
+                int(conn.get("autapses", True)), int(conn.get("multapses", True)),
+                wk, wm, wsd, dk, dm, dsd, dlo, int(alpha), _ptr(cid))
+        self._check(st)
+        return int(cid[0])
+
+    def connect(self, src, tgt, conn, syn, alpha=-1) -> int:
+        return self._conn(lib().orc_connect, src, tgt, conn, syn, alpha)
+
+    def declare(self, src, tgt, conn, syn, alpha=-1) -> int:
+        return self._conn(lib().orc_declare, src, tgt, conn, syn, alpha)
+
+    def prepare(self):
+        self._check(lib().orc_prepare(self._h))
+
+    def neurons(self, host: int) -> int:
+        return int(lib().orc_neurons(self._h, host))
+
+    def array(self, name: str) -> np.ndarray:
+        which, dt = ARRAYS[name]
+        n = lib().orc_len(self._h, which)
+        if n < 0:
+            raise OracleError(-4, f"array {name} not available")
+        out = np.zeros(n, dt)
+        self._check(lib().orc_copy(self._h, which, _ptr(out), out.nbytes))
+        return out
+
+    def call_range(self, call_id: int, host: int, lo: int, hi: int, cap: int) -> dict:
+        """Draws of one call on one host's share, primary ordinal in [lo, hi)."""
+        src = np.zeros(cap, np.uint32)
+        tgt = np.zeros(cap, np.uint32)
+        e = np.zeros(cap, np.uint64)
+        w = np.zeros(cap, np.float32)
+        d = np.zeros(cap, np.uint16)
+        n = lib().orc_call_range(self._h, call_id, host, lo, hi, _ptr(src), _ptr(tgt), _ptr(e),
+                                 _ptr(w), _ptr(d), cap)
+        if n < 0:
+            raise OracleError(-1, "call_range: capacity too small or bad call id")
+        return {"src": src[:n], "tgt": tgt[:n], "e": e[:n], "weight": w[:n], "delay": d[:n]}
+
+
+def run_script(script, P_local: int, declare_only: bool = False, skip_invalid: bool = False):
+    """Replay a workload script (see ``paper_2512_09502_amd.workloads``) on host
+    P_local.  With ``skip_invalid`` a rejected connect is recorded in
+    ``net.rejected`` as (op index, status) and the replay goes on."""
+    net = OracleNet(script["P"], P_local, script["seed"], script["dt"])
+    net.rejected = []
+    for k, op in enumerate(script["ops"]):
+        if op[0] == "create":
+            net.create(op[1], op[2])
+            continue
+        _, src, tgt, conn, syn, alpha = op
+        try:
+            if declare_only:
+                net.declare(src, tgt, conn, syn, alpha)
+            else:
+                net.connect(src, tgt, conn, syn, alpha)
+        except OracleError as err:
+            if not skip_invalid:
+                raise
+            net.rejected.append((k, err.code))
+    if not declare_only:
+        net.prepare()
+    return net

@@ -1,0 +1,216 @@
+"""Seeded synthetic workload scripts.
+
+A script is a plain dict ``{"P", "seed", "dt", "ops"}``; ``ops`` is a list of
+
+* ``("create", host, n)`` -- Create(population, n) on a virtual host, and
+* ``("connect", src_segments, tgt_segments, conn_spec, syn_spec, alpha)`` --
+  Connect over node sets given as ``(host, first, n)`` segments (the position
+  of a neuron in a set is its rank in the concatenation of the segments);
+  ``alpha = -1`` marks point-to-point exchange, ``alpha >= 0`` a collective
+  group.
+
+The same script is replayed on every virtual host (the paper's premise that
+all processes run the same script), by the GPU library and by the oracle
+alike.  This module only makes structural choices (population sizes,
+probabilities, in-degrees, request streams) with ``numpy`` generators seeded
+per workload; it contains none of the construction arithmetic.
+
+The workloads stand in for the paper's two models (the multi-area model, whose
+connectivity data is not available here, and the scalable balanced network of
+the HPC benchmark) with synthetic networks of the same shape.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+DT = 0.1          # ms, the paper's simulation resolution
+SEED = 1          # Philox seed for every workload
+
+W_E = {"kind": "normal", "mean": 0.1, "sd": 0.01}
+W_I = {"kind": "normal", "mean": -0.5, "sd": 0.05}
+D_CONST_15 = {"kind": "const", "mean": 1.5}
+
+
+def _round_half_away(x: float) -> int:
+    return int(math.floor(x + 0.5)) if x >= 0 else -int(math.floor(-x + 0.5))
+
+
+class _Builder:
+    def __init__(self, P: int, seed: int = SEED, dt: float = DT):
+        self.P, self.seed, self.dt = P, seed, dt
+        self.M = [0] * P
+        self.ops = []
+
+    def create(self, host: int, n: int) -> tuple:
+        seg = (host, self.M[host], n)
+        self.M[host] += n
+        self.ops.append(("create", host, n))
+        return seg
+
+    def connect(self, src, tgt, conn, syn, alpha=-1):
+        self.ops.append(("connect", [tuple(s) for s in src], [tuple(t) for t in tgt],
+                         dict(conn), dict(syn), int(alpha)))
+
+    def script(self, name: str, **info) -> dict:
+        return {"name": name, "P": self.P, "seed": self.seed, "dt": self.dt,
+                "ops": self.ops, "info": info}
+
+
+def balanced_small(n_e: int = 800, n_i: int = 200, k_e: int = 80, k_i: int = 20) -> dict:
+    """Balanced E/I network on one host: 1,000 neurons, fixed in-degree 100
+    (80 E + 20 I), no autapses, delay 1.5 ms, normal weights; 1e5 connections."""
+    b = _Builder(1)
+    e = b.create(0, n_e)
+    i = b.create(0, n_i)
+    allset = [e, i]
+    conn_e = {"rule": "fixed_indegree", "n": k_e, "autapses": False, "multapses": True}
+    conn_i = {"rule": "fixed_indegree", "n": k_i, "autapses": False, "multapses": True}
+    b.connect([e], allset, conn_e, {"weight": W_E, "delay": D_CONST_15})
+    b.connect([i], allset, conn_i, {"weight": W_I, "delay": D_CONST_15})
+    return b.script("balanced_1k_k100", conns=(n_e + n_i) * (k_e + k_i))
+
+
+COLUMN_BASE = (20000, 5800, 22000, 5500, 4900, 1100, 14000, 2900)
+
+
+def column8(scale: float = 1.0, seed: int = 1002) -> dict:
+    """8-population cortical-column-shaped network on one host.  Sizes are
+    seeded around 20k/5.8k/22k/5.5k/4.9k/1.1k/14k/2.9k (even index =
+    excitatory); every ordered pair (i -> j) is one fixed-total-number call with
+    N_ij = round(p_ij N_i N_j), p_ij ~ U(0.01, 0.15); autapses and multapses
+    allowed; delays N(1.5, 0.75) ms clipped at 0.1 ms; weights by source type."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal(8)
+    p = rng.uniform(0.01, 0.15, size=(8, 8))
+    sizes = [max(1, _round_half_away(base * scale * (1.0 + 0.05 * gi))) for base, gi in zip(COLUMN_BASE, g)]
+    b = _Builder(1)
+    pops = [b.create(0, n) for n in sizes]
+    delay = {"kind": "normal", "mean": 1.5, "sd": 0.75, "lo": 0.1}
+    total = 0
+    for i in range(8):
+        for j in range(8):
+            n_ij = _round_half_away(p[i, j] * sizes[i] * sizes[j])
+            total += n_ij
+            conn = {"rule": "fixed_total_number", "n": n_ij, "autapses": True, "multapses": True}
+            b.connect([pops[i]], [pops[j]], conn, {"weight": W_E if i % 2 == 0 else W_I, "delay": delay})
+    return b.script("column8_total_number", conns=total, sizes=sizes, scale=scale)
+
+
+def multiarea_p2p(P: int = 32, n_e: int = 104000, n_i: int = 26000, k_e: int = 2800, k_i: int = 700,
+                  k_remote_max: int = 96, seed: int = 1003) -> dict:
+    """One rank's view of a P-area model with point-to-point exchange.  Each
+    host holds one area (E and I populations).  For each target host tau, the
+    local E and I populations connect to all of tau's neurons with fixed
+    in-degree (no autapses); then each other area sigma projects its E
+    population onto tau with in-degree K ~ U{0..k_remote_max} (skipped when 0)."""
+    rng = np.random.default_rng(seed)
+    kr = rng.integers(0, k_remote_max + 1, size=(P, P))
+    b = _Builder(P)
+    E, I = [], []
+    for h in range(P):
+        E.append(b.create(h, n_e))
+        I.append(b.create(h, n_i))
+    d_local = {"kind": "normal", "mean": 1.5, "sd": 0.75, "lo": 0.1}
+    d_remote = {"kind": "normal", "mean": 3.0, "sd": 1.5, "lo": 0.1}
+    for tau in range(P):
+        tgt = [E[tau], I[tau]]
+        b.connect([E[tau]], tgt, {"rule": "fixed_indegree", "n": k_e, "autapses": False, "multapses": True},
+                  {"weight": W_E, "delay": d_local})
+        b.connect([I[tau]], tgt, {"rule": "fixed_indegree", "n": k_i, "autapses": False, "multapses": True},
+                  {"weight": W_I, "delay": d_local})
+        for sigma in range(P):
+            if sigma == tau or kr[sigma, tau] == 0:
+                continue
+            b.connect([E[sigma]], tgt, {"rule": "fixed_indegree", "n": int(kr[sigma, tau]),
+                                        "autapses": True, "multapses": True},
+                      {"weight": W_E, "delay": d_remote}, alpha=-1)
+    return b.script("multiarea_p2p", k_remote=kr.tolist())
+
+
+def balanced_collective(P: int = 1024, n_e: int = 160000, n_i: int = 40000, k_e: int = 9000,
+                        k_i: int = 2250) -> dict:
+    """One rank's share of the scalable balanced network (HPC-benchmark
+    shaped) distributed over P hosts with collective exchange (group 0):
+    E_all -> ALL_all with in-degree k_e and I_all -> ALL_all with k_i,
+    autapses and multapses allowed, delay 1.5 ms, normal weights."""
+    b = _Builder(P)
+    E, I = [], []
+    for h in range(P):
+        E.append(b.create(h, n_e))
+        I.append(b.create(h, n_i))
+    allset = [(h, 0, n_e + n_i) for h in range(P)]
+    b.connect(E, allset, {"rule": "fixed_indegree", "n": k_e, "autapses": True, "multapses": True},
+              {"weight": W_E, "delay": D_CONST_15}, alpha=0)
+    b.connect(I, allset, {"rule": "fixed_indegree", "n": k_i, "autapses": True, "multapses": True},
+              {"weight": W_I, "delay": D_CONST_15}, alpha=0)
+    return b.script("balanced_collective", conns_per_host=(n_e + n_i) * (k_e + k_i))
+
+
+def random_tiny(seed: int, P: int | None = None) -> dict:
+    """A small random script mixing all rules, flags, groups and segment
+    layouts over a few virtual hosts, for property and parity tests."""
+    rng = np.random.default_rng(10_000 + seed)
+    if P is None:
+        P = int(rng.integers(1, 5))
+    b = _Builder(P, seed=int(rng.integers(0, 2**32)), dt=0.1)
+    pops = []
+    for _ in range(int(rng.integers(2, 6))):
+        h = int(rng.integers(0, P))
+        pops.append(b.create(h, int(rng.integers(1, 40))))
+    rules = ["one_to_one", "fixed_indegree", "fixed_outdegree", "fixed_total_number", "pairwise_bernoulli"]
+
+    def pick_set():
+        k = int(rng.integers(1, min(3, len(pops)) + 1))
+        idx = rng.choice(len(pops), size=k, replace=False)
+        segs = []
+        for i in idx:
+            h, f, n = pops[i]
+            a = int(rng.integers(0, n))
+            c = int(rng.integers(a + 1, n + 1))
+            segs.append((h, f + a, c - a))
+        return segs
+
+    for _ in range(int(rng.integers(1, 8))):
+        rule = rules[int(rng.integers(0, 5))]
+        src, tgt = pick_set(), pick_set()
+        ns, nt = sum(s[2] for s in src), sum(t[2] for t in tgt)
+        aut, mult = bool(rng.integers(0, 2)), bool(rng.integers(0, 2))
+        conn = {"rule": rule, "autapses": aut, "multapses": mult}
+        if rule == "one_to_one":
+            m = min(ns, nt)
+            src, tgt = _truncate(src, m), _truncate(tgt, m)
+        elif rule == "fixed_indegree":
+            conn["n"] = int(rng.integers(0, max(1, ns - 1) + 1)) if not mult else int(rng.integers(0, 12))
+        elif rule == "fixed_outdegree":
+            conn["n"] = int(rng.integers(0, max(1, nt - 1) + 1)) if not mult else int(rng.integers(0, 12))
+        elif rule == "fixed_total_number":
+            th = tgt[0][0]
+            tgt = [t for t in tgt if t[0] == th]
+            nt = sum(t[2] for t in tgt)
+            conn["n"] = int(rng.integers(0, max(1, ns * nt // 2) + 1))
+        else:
+            conn["p"] = float(rng.choice([0.0, 0.05, 0.3, 0.7, 1.0]))
+        wkind = "normal" if rng.integers(0, 2) else "const"
+        w = {"kind": wkind, "mean": float(rng.normal()), "sd": 0.1}
+        if rng.integers(0, 2):
+            d = {"kind": "normal", "mean": float(rng.uniform(0.5, 3.0)), "sd": float(rng.uniform(0.1, 1.0)),
+                 "lo": 0.1 * int(rng.integers(1, 4))}
+        else:
+            d = {"kind": "const", "mean": 0.1 * int(rng.integers(1, 40))}
+        alpha = int(rng.integers(-1, 2))
+        b.connect(src, tgt, conn, {"weight": w, "delay": d}, alpha)
+    return b.script(f"random_tiny_{seed}")
+
+
+def _truncate(segs, m):
+    out = []
+    for h, f, n in segs:
+        if m <= 0:
+            break
+        k = min(n, m)
+        out.append((h, f, k))
+        m -= k
+    return out
+
