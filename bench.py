@@ -1,0 +1,186 @@
+"""Benchmark: connections built and indexed per second on one MI355X.
+
+One step is one whole construction of one host's share of a synthetic
+network on the GPU: a fresh context, Create for every population, every
+Connect call (generation), and Prepare (image map, remap, source-major sort,
+first-index array, point-to-point and collective send lists).  Inputs are the
+workload script (a few KB); everything else is built in HBM inside the timed
+region.  Prints one JSON line.
+
+Default workload: the 8-population cortical-column-shaped network (about 77k
+neurons, 64 fixed-total-number calls, about 4.6e8 connections, one host).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def workload(name: str, scale: float):
+    from paper_2512_09502_amd import workloads as W
+    if name == "column8":
+        return W.column8(scale=scale)
+    if name == "balanced":
+        return W.balanced_small()
+    if name == "multiarea":
+        return W.multiarea_p2p()
+    if name == "collective":
+        return W.balanced_collective()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def expected_conns(script) -> int:
+    info = script.get("info", {})
+    return int(info.get("conns", info.get("conns_per_host", 0)))
+
+
+def build_once(script, P_local: int, timing: bool):
+    import paper_2512_09502_amd as snnc
+    net = snnc.Network(script["P"], P_local, script["seed"], script["dt"])
+    if timing:
+        net.set_timing(True)
+    hint = expected_conns(script)
+    if hint:
+        net.reserve(hint)
+    for op in script["ops"]:
+        if op[0] == "create":
+            net.create(op[1], op[2])
+        else:
+            _, src, tgt, conn, syn, alpha = op
+            net.connect(src, tgt, conn, syn, alpha)
+    net.prepare()
+    return net
+
+
+# algorithmic bytes per element of the kernels whose roofline is reported
+def kernel_roofline(name: str, launches: int, ms: float, n_conn: int, n_passes: int):
+    if name == "sort_pass":
+        per_launch = n_conn * 24.0      # read and write one 8-byte key and one 4-byte payload
+    elif name == "sort_pass_final":
+        per_launch = n_conn * 26.0      # read key + payload (12 B), write src, tgt, delay, weight (14 B)
+    elif name.startswith("gen_"):
+        per_launch = None
+    else:
+        per_launch = None
+    return per_launch
+
+
+def cpu_baseline(script, calls: int = 3):
+    """The oracle, single-threaded, on the first `calls` Connect calls of the
+    same workload (then Prepare)."""
+    import oracle
+    ops, seen = [], 0
+    for op in script["ops"]:
+        if op[0] == "connect":
+            if seen == calls:
+                continue
+            seen += 1
+        ops.append(op)
+    sub = dict(script)
+    sub["ops"] = ops
+    t0 = time.perf_counter()
+    net = oracle.run_script(sub, 0)
+    dt = time.perf_counter() - t0
+    n = int(net.array("row_ptr")[-1])
+    return {"value": n / dt / 1e9, "unit": "Gconn/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {calls} of the {seen if seen < calls else sum(1 for o in script['ops'] if o[0] == 'connect')} "
+                      f"Connect calls of the same workload ({n} connections), then Prepare; {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="column8")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-calls", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the construction of one host's share needs no second GPU "
+              "(each host builds its share without communication); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    script = workload(args.workload, args.scale)
+
+    for _ in range(args.warmup):
+        net = build_once(script, 0, timing=False)
+        net.close()
+    torch.cuda.synchronize()
+
+    # timed steps (kernel timing by HIP events on the library stream)
+    times, n_conn, kt_total, stats = [], 0, {}, None
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        t0 = time.perf_counter()
+        net = build_once(script, 0, timing=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        n_conn = net.count("src")
+        stats = net.stats()
+        for k, (l, ms) in net.kernel_times().items():
+            a = kt_total.setdefault(k, [0, 0.0])
+            a[0] += l
+            a[1] += ms
+        net.close()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    ms_per_step = 1e3 * total / args.steps
+    value = n_conn * args.steps / total / 1e9
+
+    # dominant kernel and its roofline
+    dom = max(kt_total.items(), key=lambda kv: kv[1][1])
+    roof = None
+    sort_like = {k: v for k, v in kt_total.items() if k in ("sort_pass", "sort_pass_final")}
+    if sort_like:
+        name, (launches, ms) = max(sort_like.items(), key=lambda kv: kv[1][1])
+        per = kernel_roofline(name, launches, ms, n_conn, stats["sort_passes"])
+        avg_ms = ms / launches
+        achieved = per / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": name,
+                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": per}
+
+    out = {
+        "metric": "connections built+indexed/sec (Gconn/s) on 1 MI355X",
+        "value": round(value, 4),
+        "unit": "Gconn/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64 int + f64->f32 weights",
+        "data": "synthetic",
+        "config": {"workload": script["name"], "connections": n_conn, "calls": stats["n_calls"],
+                   "neurons": stats["M_local"], "images": stats["n_images"], "key_bits": stats["key_bits"],
+                   "sort_passes": stats["sort_passes"], "scale": args.scale},
+        "step_ms": {"min": round(1e3 * min(times), 3), "median": round(1e3 * sorted(times)[len(times) // 2], 3)},
+        "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in sorted(kt_total.items(), key=lambda kv: -kv[1][1])},
+        "dominant_kernel": dom[0],
+        "roofline": roof,
+        "peak_hbm_bytes": stats["bytes_peak"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(script, args.cpu_calls)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,293 @@
+/*
+ * snnc.h -- C ABI of the MI355X (gfx950) spiking-network construction library.
+ *
+ * The library builds, on one GPU, the share of a distributed spiking-network
+ * connectivity that belongs to one virtual host P_local of P hosts, following
+ * the construction method of Golosio, Tiddia, Villamar et al., "Scalable
+ * Construction of Spiking Neural Networks using up to thousands of GPUs"
+ * (arXiv:2512.09502), section Methods ("Remote connections" and its
+ * subsections).  Other hosts exist only as ranges of neuron ids: each host
+ * runs the same script and builds its own share without communication
+ * (Results, first subsection; Methods, point-to-point creation subsection).
+ *
+ * Calls follow the paper's problem statement: Create(population, n),
+ * Connect / RemoteConnect(sigma, s, tau, t, p, C, D, alpha) (Methods,
+ * "Creation of the remote connection structures for point-to-point MPI
+ * communication"), and the simulation-preparation phase (Methods,
+ * "Simulation phases and optimization").  Connect and RemoteConnect are one
+ * call here: every node set lists its segments with their host.
+ *
+ * Conventions
+ *  - Every function returns an snnc_status; nothing is thrown across the ABI.
+ *    snnc_last_error() gives a message for the last failure of a context.
+ *    A failed call leaves the context as it was before the call.
+ *  - Device memory: the context owns every device buffer.  It allocates
+ *    through the caller's snnc_allocator (for instance a framework's caching
+ *    allocator) or, if none is given, with hipMalloc.  Pointers handed out by
+ *    snnc_get_array() are device pointers, valid until the next mutating call
+ *    (connect, prepare, destroy) on the context.
+ *  - Streams: all device work of a context is ordered on the HIP stream given
+ *    at init (0 = the null stream).  Calls return once the work is enqueued,
+ *    except where a host-visible result (a count, a status) requires a
+ *    synchronisation; snnc_sync() waits for the stream.
+ *  - Determinism: the call id of a Connect is its ordinal among the accepted
+ *    connect calls of the context.  Every random number is a Philox4x32-10
+ *    block keyed by (seed, call id) with counter (element index e, purpose),
+ *    so every host regenerates any draw of any call exactly.  Results do not
+ *    depend on launch shapes.
+ */
+#ifndef SNNC_H
+#define SNNC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct snnc_ctx snnc_ctx;
+
+typedef enum {
+    SNNC_OK = 0,
+    SNNC_EINVAL = -1,       /* invalid argument or connection spec              */
+    SNNC_ENOMEM = -2,       /* the allocator returned NULL                      */
+    SNNC_EBUDGET = -3,      /* the device-memory budget would be exceeded       */
+    SNNC_ESTATE = -4,       /* call not allowed in the current state            */
+    SNNC_EUNSUPPORTED = -5, /* valid request outside what this library builds   */
+    SNNC_EDEVICE = -6       /* a HIP runtime call or a kernel reported an error */
+} snnc_status;
+
+/* A range of local neuron ids [first, first + n) on virtual host `host`. */
+typedef struct {
+    uint32_t host, first, n;
+} snnc_segment;
+
+/* A node set: the concatenation of its segments.  The position of a neuron in
+ * the set (its ordinal) is its rank in that concatenation.  A set lists each
+ * neuron at most once.  Host memory, read during the call only. */
+typedef struct {
+    const snnc_segment* seg;
+    uint32_t n_seg;
+} snnc_nodeset;
+
+/* Connection rules (the paper's rule dictionary C, rules as defined in the
+ * connectivity-concepts reference it cites). */
+typedef enum {
+    SNNC_ONE_TO_ONE = 0,          /* s_i -> t_i, n_s == n_t                         */
+    SNNC_FIXED_INDEGREE = 1,      /* n sources drawn for every target               */
+    SNNC_FIXED_OUTDEGREE = 2,     /* n targets drawn for every source               */
+    SNNC_FIXED_TOTAL_NUMBER = 3,  /* n connections drawn over all pairs             */
+    SNNC_PAIRWISE_BERNOULLI = 4   /* every pair connected with probability p        */
+} snnc_rule_kind;
+
+typedef struct {
+    uint32_t kind;            /* snnc_rule_kind                                   */
+    uint32_t allow_autapses;  /* 0: no connection from a neuron to itself         */
+    uint32_t allow_multapses; /* 0: at most one connection per (source, target)   */
+    uint32_t reserved;
+    uint64_t n;               /* in-degree, out-degree or total number            */
+    double p;                 /* Bernoulli probability                            */
+} snnc_conn_spec;
+
+typedef enum { SNNC_CONST = 0, SNNC_NORMAL = 1 } snnc_dist_kind;
+
+/* CONST uses mean.  NORMAL draws N(mean, sd); for delays the draw is clipped
+ * from below at lo (ms) before it is turned into an integer number of steps. */
+typedef struct {
+    uint32_t kind;
+    uint32_t reserved;
+    double mean, sd, lo;
+} snnc_dist;
+
+/* The synapse dictionary D: weight (stored as fp32) and delay in ms (stored
+ * as uint16 time steps of dt, see snnc_delay_table); receptor port p must be
+ * 0 (ports are not stored). */
+typedef struct {
+    snnc_dist weight;
+    snnc_dist delay_ms;
+    uint32_t port;
+    uint32_t reserved;
+} snnc_syn_spec;
+
+/* Device-memory callbacks.  alloc returns NULL on failure; the library then
+ * returns SNNC_ENOMEM.  `stream` is the context's stream. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* stream, void* user);
+    void (*free)(void* ptr, void* user);
+    void* user;
+} snnc_allocator;
+
+/* ---------------------------------------------------------------- lifecycle */
+
+/* Create a context for host P_local of P virtual hosts.  seed keys every
+ * Philox stream; dt_ms is the time step that delays are counted in.
+ * `alloc` may be NULL (hipMalloc/hipFree).  budget_bytes > 0 caps the device
+ * bytes the context may hold at once (SNNC_EBUDGET beyond).  The current HIP
+ * device at the time of the call is the context's device.
+ * Errors: SNNC_EINVAL for P == 0, P_local >= P, dt_ms <= 0. */
+snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t seed, double dt_ms,
+                      const snnc_allocator* alloc, void* hip_stream, uint64_t budget_bytes);
+
+/* Free every device buffer of the context (after waiting for its stream). */
+snnc_status snnc_destroy(snnc_ctx* ctx);
+
+/* Message of the last failed call on this context ("" if none). */
+const char* snnc_last_error(const snnc_ctx* ctx);
+
+/* Wait for all work enqueued by the context. */
+snnc_status snnc_sync(snnc_ctx* ctx);
+
+/* ---------------------------------------------------------------- building */
+
+/* Create(population, n): n neurons on `host` get the next free local ids of
+ * that host; *out receives the segment.  Every host's context must see the
+ * same creates in the same order.  Host-side bookkeeping only.
+ * Errors: SNNC_EINVAL (host >= P, more than 2^31-1 neurons on a host),
+ * SNNC_ESTATE after snnc_prepare. */
+snnc_status snnc_create(snnc_ctx* ctx, uint32_t host, uint32_t n, snnc_segment* out);
+
+/* Connect(src, tgt, rule, syn_spec) with group alpha (-1: point-to-point
+ * exchange; >= 0: collective group alpha).  Generates on the GPU, in
+ * canonical generation order (element index e ascending), every connection
+ * of the call whose target lives on P_local: the source as its ordinal in
+ * `src` (the paper's temporary source position), the target as its local id,
+ * the delay in steps and the fp32 weight.  *call_id_out gets the call id.
+ * Element index and draws per rule:
+ *   fixed in-degree K:   e = t_ord * K + j; source ordinal from block IDX(e);
+ *                        without multapses Robert Floyd's sampling over the
+ *                        K draws of a target, then sorted ascending;
+ *                        without autapses the draw skips the target itself;
+ *   fixed out-degree K:  mirror image with sources and targets swapped;
+ *   fixed total number:  candidate c draws (source, target) from IDX(c); the
+ *                        first n candidates that are valid (no autapse if
+ *                        excluded, no repeated pair if multapses excluded)
+ *                        are the connections, e = c; targets on one host only;
+ *   pairwise Bernoulli:  pair q = t_ord * n_s + s_ord connects iff word q%4 of
+ *                        block BERN(q/4) is below floor(p 2^32); e = q;
+ *   one-to-one:          e = i.
+ * Synapse values of element e come from block SYN(e) of the same call.
+ * Errors: SNNC_EINVAL (bad segment, overlapping segments within a set, rule
+ * parameters impossible for the sets, port != 0, delay below one step or
+ * beyond 65535 steps, sd < 0), SNNC_EUNSUPPORTED (fixed total number with
+ * targets on several hosts; more than 2^32-1 neurons in a set),
+ * SNNC_ESTATE after prepare, SNNC_ENOMEM / SNNC_EBUDGET, SNNC_EDEVICE. */
+snnc_status snnc_connect(snnc_ctx* ctx, const snnc_nodeset* src, const snnc_nodeset* tgt,
+                         const snnc_conn_spec* conn, const snnc_syn_spec* syn, int32_t alpha,
+                         uint32_t* call_id_out);
+
+/* Reserve room for n generated connections (optional; avoids regrowth). */
+snnc_status snnc_reserve(snnc_ctx* ctx, uint64_t n_connections);
+
+/* Simulation preparation (Methods, point-to-point and collective creation
+ * subsections; "GPU memory levels" for the source-major order):
+ *  1. image map: for every map index a = alpha + 1 and remote host sigma, R
+ *     = sorted unique local ids of the sigma-sources used by local
+ *     connections of group-alpha calls; images are numbered after the M_local
+ *     local neurons, in (a, sigma, source id) order, L = img_base + position;
+ *  2. remap: every connection's source becomes its local id (source on
+ *     P_local) or its image index;
+ *  3. sort: all connections by (source, target), ties in generation order;
+ *  4. first-index array row_ptr over M_local + n_images sources;
+ *  5. point-to-point send lists: S_tau = sorted local sources that host tau's
+ *     share of the alpha = -1 calls uses (regenerated here, no communication),
+ *     and per local source the (tau, position in S_tau) pairs T/P;
+ *  6. collective arrays per group alpha: H_{alpha,sigma} = sorted union of the
+ *     sigma-sources passed to group-alpha calls, I aligned with H (image index
+ *     on P_local or -1; -1 for sigma = P_local), and per local source the
+ *     (alpha, position in H_{alpha,P_local}) pairs G/Q.
+ * Errors: SNNC_ESTATE if already prepared, SNNC_EUNSUPPORTED if
+ * bits(sources) + bits(targets) > 48, SNNC_ENOMEM/EBUDGET, SNNC_EDEVICE. */
+snnc_status snnc_prepare(snnc_ctx* ctx);
+
+/* ---------------------------------------------------------------- results */
+
+typedef enum {
+    /* generation order (available after connect, until prepare) */
+    SNNC_GEN_SRC = 0,      /* uint32 source ordinal in the call's source set  */
+    SNNC_GEN_TGT = 1,      /* uint32 target local id                           */
+    SNNC_GEN_DELAY = 2,    /* uint16 steps                                     */
+    SNNC_GEN_WEIGHT = 3,   /* float                                            */
+    SNNC_CALL_OFF = 5,     /* uint64 [n_calls + 1] first generated index/call  */
+    /* after prepare */
+    SNNC_SRC = 10,         /* int32 source' (local id or image index), sorted  */
+    SNNC_TGT = 11,         /* int32 target local id                            */
+    SNNC_DELAY = 12,       /* uint16                                           */
+    SNNC_WEIGHT = 13,      /* float                                            */
+    SNNC_ROW_PTR = 14,     /* uint64 [M_local + n_img + 1]                     */
+    SNNC_R_OFF = 20,       /* uint64 [n_a * P + 1] offsets of R per (a, sigma) */
+    SNNC_R_VAL = 21,       /* int32 remote source ids                          */
+    SNNC_IMG_BASE = 22,    /* int64 [n_a * P] first image index per (a, sigma) */
+    SNNC_S_OFF = 30,       /* uint64 [P + 1] offsets of S per target host      */
+    SNNC_S_VAL = 31,       /* int32 local source ids                           */
+    SNNC_TP_PTR = 32,      /* uint64 [M_local + 1]                             */
+    SNNC_T_VAL = 33,       /* uint32 target host                               */
+    SNNC_P_VAL = 34,       /* uint32 position in S_tau (= in R_{tau,P_local})  */
+    SNNC_GROUPS = 40,      /* int32 [n_groups] group ids ascending             */
+    SNNC_H_OFF = 41,       /* uint64 [n_groups * P + 1]                        */
+    SNNC_H_VAL = 42,       /* int32 source ids                                 */
+    SNNC_I_VAL = 43,       /* int32 image index or -1, aligned with H          */
+    SNNC_GQ_PTR = 44,      /* uint64 [M_local + 1]                             */
+    SNNC_G_VAL = 45,       /* int32 group                                      */
+    SNNC_Q_VAL = 46        /* uint32 position in H_{group, P_local}            */
+} snnc_array_id;
+
+/* Device pointer and element count of an array (count 0 and ptr NULL for an
+ * empty array).  SNNC_ESTATE if the array does not exist in this state. */
+snnc_status snnc_get_array(const snnc_ctx* ctx, int32_t id, const void** dev_ptr, uint64_t* count);
+
+/* Copy an array to dst (host or device memory, hipMemcpyDefault), waiting
+ * for completion.  SNNC_EINVAL if cap_bytes is too small. */
+snnc_status snnc_copy_array(snnc_ctx* ctx, int32_t id, void* dst, uint64_t cap_bytes);
+
+/* Copy elements [first, first + count) of an array to dst (host or device
+ * memory), waiting for completion.  SNNC_EINVAL if the range is outside the
+ * array. */
+snnc_status snnc_copy_range(snnc_ctx* ctx, int32_t id, uint64_t first, uint64_t count, void* dst);
+
+/* Counters of the context. */
+typedef struct {
+    uint64_t n_connections;   /* local-share connections generated       */
+    uint64_t n_images;        /* image neurons (after prepare)            */
+    uint32_t n_calls;
+    uint32_t M_local;
+    uint64_t bytes_live;      /* device bytes held now                    */
+    uint64_t bytes_peak;      /* high-water mark                          */
+    uint32_t sort_passes;     /* radix passes of the last prepare         */
+    uint32_t key_bits;        /* bits(sources) + bits(targets)            */
+    double ms_connect;        /* GPU time of all connect calls (events)   */
+    double ms_prepare;        /* GPU time of prepare                      */
+} snnc_stats_t;
+
+snnc_status snnc_stats(snnc_ctx* ctx, snnc_stats_t* out);
+
+/* Per-kernel GPU timing with HIP events on the context stream.  While
+ * enabled, every kernel launch is bracketed by an event pair; snnc_kernel_times
+ * reports, per kernel name, the launch count and the summed milliseconds
+ * (names as NUL-terminated strings of at most 47 characters). */
+snnc_status snnc_set_timing(snnc_ctx* ctx, int enable);
+snnc_status snnc_kernel_times(snnc_ctx* ctx, uint32_t cap, char (*names)[48], uint64_t* launches,
+                              double* ms, uint32_t* n_out);
+
+/* ---------------------------------------------------------------- helpers */
+
+/* The delay-step table of a NORMAL(mean, sd) delay clipped at lo (ms) for
+ * time step dt (ms): k_lo = round(lo / dt) and thresholds
+ * t_k = ceil(Phi(((k + 1/2) dt - mean) / sd) 2^32) for k = k_lo, k_lo+1, ...
+ * while below 2^32; a 32-bit uniform word w maps to k_lo + #{k : w >= t_k}.
+ * Host computation.  *len_out = number of thresholds.
+ * Errors: SNNC_EINVAL if lo < dt, sd <= 0 or the steps would exceed 65535
+ * or cap entries. */
+snnc_status snnc_delay_table(double mean, double sd, double lo, double dt, uint32_t* table,
+                             uint64_t cap, uint32_t* k_lo_out, uint64_t* len_out);
+
+/* Device check of the random stream: out[4 i .. 4 i + 3] = Philox4x32-10
+ * block for key (seed, call_id) and counter (e_begin + i, purpose) for
+ * i < n.  `out` is device memory of 4 n uint32; runs on the context stream. */
+snnc_status snnc_philox_blocks(snnc_ctx* ctx, uint32_t seed, uint32_t call_id, uint64_t e_begin,
+                               uint32_t purpose, uint64_t n, uint32_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNNC_H */

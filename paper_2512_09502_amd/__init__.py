@@ -1,0 +1,296 @@
+"""MI355X (gfx950) spiking-network construction: Python binding of libsnnc.
+
+A thin ctypes layer over the C ABI declared in ``include/snnc.h``: it only
+marshals arguments.  Every step of the construction runs in the HIP library;
+there is no CPU fallback -- if ``libsnnc.so`` is missing or no GPU is
+visible, the calls raise.  PyTorch provides device memory (its caching
+allocator, through the library's allocator callbacks) and the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import workloads  # noqa: F401  (seeded workload scripts)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnnc.so")
+
+RULES = {"one_to_one": 0, "fixed_indegree": 1, "fixed_outdegree": 2,
+         "fixed_total_number": 3, "pairwise_bernoulli": 4}
+DISTS = {"const": 0, "normal": 1}
+STATUS = {0: "SNNC_OK", -1: "SNNC_EINVAL", -2: "SNNC_ENOMEM", -3: "SNNC_EBUDGET",
+          -4: "SNNC_ESTATE", -5: "SNNC_EUNSUPPORTED", -6: "SNNC_EDEVICE"}
+
+# array name -> (snnc_array_id, numpy dtype)
+ARRAYS = {
+    "gen_src": (0, np.uint32), "gen_tgt": (1, np.uint32), "gen_delay": (2, np.uint16),
+    "gen_weight": (3, np.float32), "call_off": (5, np.uint64),
+    "src": (10, np.int32), "tgt": (11, np.int32), "delay": (12, np.uint16),
+    "weight": (13, np.float32), "row_ptr": (14, np.uint64),
+    "r_off": (20, np.uint64), "r_val": (21, np.int32), "img_base": (22, np.int64),
+    "s_off": (30, np.uint64), "s_val": (31, np.int32), "tp_ptr": (32, np.uint64),
+    "t_val": (33, np.uint32), "p_val": (34, np.uint32),
+    "groups": (40, np.int32), "h_off": (41, np.uint64), "h_val": (42, np.int32),
+    "i_val": (43, np.int32), "gq_ptr": (44, np.uint64), "g_val": (45, np.int32),
+    "q_val": (46, np.uint32),
+}
+
+
+class Segment(ctypes.Structure):
+    _fields_ = [("host", ctypes.c_uint32), ("first", ctypes.c_uint32), ("n", ctypes.c_uint32)]
+
+
+class NodeSet(ctypes.Structure):
+    _fields_ = [("seg", ctypes.POINTER(Segment)), ("n_seg", ctypes.c_uint32)]
+
+
+class ConnSpec(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("allow_autapses", ctypes.c_uint32),
+                ("allow_multapses", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("n", ctypes.c_uint64), ("p", ctypes.c_double)]
+
+
+class Dist(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("mean", ctypes.c_double), ("sd", ctypes.c_double), ("lo", ctypes.c_double)]
+
+
+class SynSpec(ctypes.Structure):
+    _fields_ = [("weight", Dist), ("delay_ms", Dist), ("port", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_connections", ctypes.c_uint64), ("n_images", ctypes.c_uint64),
+                ("n_calls", ctypes.c_uint32), ("M_local", ctypes.c_uint32),
+                ("bytes_live", ctypes.c_uint64), ("bytes_peak", ctypes.c_uint64),
+                ("sort_passes", ctypes.c_uint32), ("key_bits", ctypes.c_uint32),
+                ("ms_connect", ctypes.c_double), ("ms_prepare", ctypes.c_double)]
+
+
+EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_create", "snnc_connect",
+           "snnc_reserve", "snnc_prepare", "snnc_get_array", "snnc_copy_array", "snnc_copy_range",
+           "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks"]
+
+_lib = None
+
+
+def lib():
+    """Load libsnnc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2512_09502_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64, i32, dbl = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double
+        st = ctypes.c_int
+        L.snnc_init.argtypes = [ctypes.POINTER(vp), u32, u32, u32, dbl, ctypes.POINTER(Allocator), vp, u64]
+        L.snnc_destroy.argtypes = [vp]
+        L.snnc_last_error.argtypes = [vp]
+        L.snnc_last_error.restype = ctypes.c_char_p
+        L.snnc_sync.argtypes = [vp]
+        L.snnc_create.argtypes = [vp, u32, u32, ctypes.POINTER(Segment)]
+        L.snnc_connect.argtypes = [vp, ctypes.POINTER(NodeSet), ctypes.POINTER(NodeSet), ctypes.POINTER(ConnSpec),
+                                   ctypes.POINTER(SynSpec), i32, ctypes.POINTER(u32)]
+        L.snnc_reserve.argtypes = [vp, u64]
+        L.snnc_prepare.argtypes = [vp]
+        L.snnc_get_array.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(u64)]
+        L.snnc_copy_array.argtypes = [vp, i32, vp, u64]
+        L.snnc_copy_range.argtypes = [vp, i32, u64, u64, vp]
+        L.snnc_stats.argtypes = [vp, ctypes.POINTER(Stats)]
+        L.snnc_set_timing.argtypes = [vp, ctypes.c_int]
+        L.snnc_kernel_times.argtypes = [vp, u32, vp, vp, vp, ctypes.POINTER(u32)]
+        L.snnc_delay_table.argtypes = [dbl, dbl, dbl, dbl, vp, u64, ctypes.POINTER(u32), ctypes.POINTER(u64)]
+        L.snnc_philox_blocks.argtypes = [vp, u32, u32, u64, u32, u64, vp]
+        for name in EXPORTS:
+            getattr(L, name).restype = st if name != "snnc_last_error" else ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+class SnncError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _dist(d) -> Dist:
+    d = d or {"kind": "const", "mean": 0.0}
+    return Dist(DISTS[d.get("kind", "const")], 0, float(d.get("mean", 0.0)), float(d.get("sd", 0.0)),
+                float(d.get("lo", 0.0)))
+
+
+def _nodeset(segs):
+    arr = (Segment * max(1, len(segs)))(*[Segment(int(h), int(f), int(n)) for h, f, n in segs])
+    return NodeSet(arr, len(segs)), arr
+
+
+def delay_table(mean: float, sd: float, lo: float, dt: float):
+    """The library's host-built delay table: (k_lo, thresholds) or None."""
+    buf = np.zeros(65536, np.uint32)
+    klo = ctypes.c_uint32()
+    n = ctypes.c_uint64()
+    st = lib().snnc_delay_table(mean, sd, lo, dt, buf.ctypes.data, buf.size, ctypes.byref(klo), ctypes.byref(n))
+    if st != 0:
+        return None
+    return int(klo.value), buf[: n.value].copy()
+
+
+class Network:
+    """One virtual host's share of a network, built on the current GPU."""
+
+    def __init__(self, P: int, P_local: int, seed: int, dt: float, budget_bytes: int = 0,
+                 torch_allocator: bool = True, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the construction library runs on the GPU only")
+        self._torch = torch
+        self.device = torch.cuda.current_device()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._alloc = None
+        if torch_allocator:
+            dev, strm = self.device, self.stream
+
+            def _a(nbytes, _stream, _user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, strm)
+                except Exception:   # out of memory: the library reports SNNC_ENOMEM
+                    return None
+
+            def _f(ptr, _user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc_cbs = (ALLOC_FN(_a), FREE_FN(_f))
+            self._alloc = Allocator(self._alloc_cbs[0], self._alloc_cbs[1], None)
+        h = ctypes.c_void_p()
+        st = lib().snnc_init(ctypes.byref(h), P, P_local, seed & 0xFFFFFFFF, dt,
+                             ctypes.byref(self._alloc) if self._alloc is not None else None,
+                             ctypes.c_void_p(self.stream.cuda_stream), budget_bytes)
+        if st != 0:
+            raise SnncError(st, "snnc_init failed")
+        self._h = h
+        self.P, self.P_local = P, P_local
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().snnc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise SnncError(st, lib().snnc_last_error(self._h).decode())
+
+    def create(self, host: int, n: int) -> tuple:
+        seg = Segment()
+        self._check(lib().snnc_create(self._h, host, n, ctypes.byref(seg)))
+        return (seg.host, seg.first, seg.n)
+
+    def connect(self, src, tgt, conn, syn, alpha: int = -1) -> int:
+        s, s_keep = _nodeset(src)
+        t, t_keep = _nodeset(tgt)
+        cs = ConnSpec(RULES[conn["rule"]], int(conn.get("autapses", True)), int(conn.get("multapses", True)), 0,
+                      int(conn.get("n", 0)), float(conn.get("p", 0.0)))
+        ss = SynSpec(_dist(syn.get("weight")), _dist(syn.get("delay")), int(syn.get("port", 0)), 0)
+        cid = ctypes.c_uint32()
+        self._check(lib().snnc_connect(self._h, ctypes.byref(s), ctypes.byref(t), ctypes.byref(cs),
+                                       ctypes.byref(ss), int(alpha), ctypes.byref(cid)))
+        return int(cid.value)
+
+    def reserve(self, n: int):
+        self._check(lib().snnc_reserve(self._h, int(n)))
+
+    def prepare(self):
+        self._check(lib().snnc_prepare(self._h))
+
+    def sync(self):
+        self._check(lib().snnc_sync(self._h))
+
+    def count(self, name: str) -> int:
+        which, _ = ARRAYS[name]
+        p, n = ctypes.c_void_p(), ctypes.c_uint64()
+        self._check(lib().snnc_get_array(self._h, which, ctypes.byref(p), ctypes.byref(n)))
+        return int(n.value)
+
+    def array(self, name: str) -> np.ndarray:
+        """Host copy of a result array."""
+        which, dt = ARRAYS[name]
+        out = np.zeros(self.count(name), dt)
+        self._check(lib().snnc_copy_array(self._h, which, out.ctypes.data, out.nbytes))
+        return out
+
+    def array_range(self, name: str, first: int, count: int) -> np.ndarray:
+        which, dt = ARRAYS[name]
+        out = np.zeros(count, dt)
+        self._check(lib().snnc_copy_range(self._h, which, int(first), int(count), out.ctypes.data))
+        return out
+
+    def tensor(self, name: str):
+        """Device copy of a result array as a torch tensor (same dtype widths)."""
+        torch = self._torch
+        which, dt = ARRAYS[name]
+        n = self.count(name)
+        tdt = {np.uint32: torch.int32, np.int32: torch.int32, np.uint16: torch.int16, np.float32: torch.float32,
+               np.uint64: torch.int64, np.int64: torch.int64}[dt]
+        out = torch.empty(n, dtype=tdt, device=f"cuda:{self.device}")
+        self._check(lib().snnc_copy_array(self._h, which, ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size()))
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(lib().snnc_stats(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def set_timing(self, on: bool):
+        self._check(lib().snnc_set_timing(self._h, int(on)))
+
+    def kernel_times(self) -> dict:
+        cap = 64
+        names = (ctypes.c_char * 48 * cap)()
+        launches = (ctypes.c_uint64 * cap)()
+        ms = (ctypes.c_double * cap)()
+        n = ctypes.c_uint32()
+        self._check(lib().snnc_kernel_times(self._h, cap, names, launches, ms, ctypes.byref(n)))
+        return {names[i].value.decode(): (int(launches[i]), float(ms[i])) for i in range(min(n.value, cap))}
+
+    def philox_blocks(self, seed: int, call_id: int, e_begin: int, purpose: int, n: int) -> np.ndarray:
+        torch = self._torch
+        out = torch.empty(4 * n, dtype=torch.int32, device=f"cuda:{self.device}")
+        self._check(lib().snnc_philox_blocks(self._h, seed, call_id, e_begin, purpose, n,
+                                             ctypes.c_void_p(out.data_ptr())))
+        return out.cpu().numpy().view(np.uint32).reshape(n, 4)
+
+
+def run_script(script: dict, P_local: int, prepare: bool = True, skip_invalid: bool = False, **kw) -> Network:
+    """Replay a workload script on the GPU for host P_local."""
+    net = Network(script["P"], P_local, script["seed"], script["dt"], **kw)
+    net.rejected = []
+    for k, op in enumerate(script["ops"]):
+        if op[0] == "create":
+            net.create(op[1], op[2])
+            continue
+        _, src, tgt, conn, syn, alpha = op
+        try:
+            net.connect(src, tgt, conn, syn, alpha)
+        except SnncError as err:
+            if not skip_invalid or err.code not in (-1, -5):
+                raise
+            net.rejected.append((k, err.code))
+    if prepare:
+        net.prepare()
+    return net

@@ -1,0 +1,611 @@
+// C ABI and host planner: context state, allocation against the budget,
+// validation of Connect specs, kernel timing, array access.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <stdexcept>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace snnc {
+
+[[noreturn]] void raise(snnc_status code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) raise(SNNC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* dalloc(Ctx& c, size_t bytes) {
+    if (bytes == 0) bytes = 1;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (c.budget && c.bytes_live + bytes > c.budget)
+        raise(SNNC_EBUDGET, "device-memory budget exceeded (" + std::to_string(c.bytes_live + bytes) + " > " +
+                                std::to_string(c.budget) + " bytes)");
+    void* p = nullptr;
+    if (c.has_alloc) {
+        p = c.alloc.alloc(bytes, (void*)c.stream, c.alloc.user);
+        if (!p) raise(SNNC_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            raise(SNNC_ENOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+        }
+    }
+    c.live[p] = bytes;
+    c.bytes_live += bytes;
+    c.bytes_peak = std::max(c.bytes_peak, c.bytes_live);
+    return p;
+}
+
+void dfree(Ctx& c, void* p) {
+    if (!p) return;
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;
+    c.bytes_live -= it->second;
+    c.live.erase(it);
+    if (c.has_alloc) {
+        c.alloc.free(p, c.alloc.user);
+    } else {
+        (void)hipFree(p);
+    }
+}
+
+static hipEvent_t get_event(Ctx& c) {
+    if (!c.event_pool.empty()) {
+        hipEvent_t e = c.event_pool.back();
+        c.event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+}
+
+void tstart(Ctx& c, const char* name) {
+    if (!c.timing) return;
+    Ctx::Pending p;
+    p.name = name;
+    p.a = get_event(c);
+    p.b = get_event(c);
+    HIPCHK(hipEventRecord(p.a, c.stream));
+    c.pending.push_back(p);
+}
+
+void tstop(Ctx& c) {
+    if (!c.timing || c.pending.empty()) return;
+    HIPCHK(hipEventRecord(c.pending.back().b, c.stream));
+}
+
+void resolve_times(Ctx& c) {
+    if (c.pending.empty()) return;
+    HIPCHK(hipStreamSynchronize(c.stream));
+    for (auto& p : c.pending) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+        auto& k = c.ktimes[p.name];
+        k.launches += 1;
+        k.ms += ms;
+        c.event_pool.push_back(p.a);
+        c.event_pool.push_back(p.b);
+    }
+    c.pending.clear();
+}
+
+void upload(Ctx& c, void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+}
+
+void download(Ctx& c, void* dst, const void* src, size_t bytes) {
+    if (!bytes) return;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+}
+
+void sync(Ctx& c) { HIPCHK(hipStreamSynchronize(c.stream)); }
+
+// ------------------------------------------------------------------ node sets
+bool set_lookup_host(const HostSet& s, uint64_t ord, uint32_t& host, uint32_t& local) {
+    if (ord >= s.total) return false;
+    size_t k = std::upper_bound(s.ord_begin.begin(), s.ord_begin.end(), ord) - s.ord_begin.begin() - 1;
+    host = s.seg[k].host;
+    local = s.seg[k].first + (uint32_t)(ord - s.ord_begin[k]);
+    return true;
+}
+
+static HostSet make_set(const Ctx& c, const snnc_nodeset* ns) {
+    HostSet s;
+    if (!ns) raise(SNNC_EINVAL, "null node set");
+    if (ns->n_seg && !ns->seg) raise(SNNC_EINVAL, "node set without segments array");
+    std::vector<snnc_segment> order;
+    for (uint32_t i = 0; i < ns->n_seg; ++i) {
+        const snnc_segment g = ns->seg[i];
+        if (g.host >= c.P) raise(SNNC_EINVAL, "segment host out of range");
+        if ((uint64_t)g.first + g.n > c.M[g.host]) raise(SNNC_EINVAL, "segment outside the created neurons");
+        if (g.n == 0) continue;     // empty segments hold no ordinals
+        s.seg.push_back(g);
+        s.ord_begin.push_back(s.total);
+        s.total += g.n;
+        order.push_back(g);
+    }
+    if (s.total > 0xffffffffull) raise(SNNC_EUNSUPPORTED, "node set larger than 2^32-1 neurons");
+    std::sort(order.begin(), order.end(), [](const snnc_segment& a, const snnc_segment& b) {
+        return a.host != b.host ? a.host < b.host : a.first < b.first;
+    });
+    for (size_t i = 1; i < order.size(); ++i)
+        if (order[i].host == order[i - 1].host && order[i].first < (uint64_t)order[i - 1].first + order[i - 1].n)
+            raise(SNNC_EINVAL, "segments of a node set overlap");
+    return s;
+}
+
+// neurons present in both sets
+static uint64_t set_overlap(const HostSet& a, const HostSet& b) {
+    uint64_t total = 0;
+    std::vector<snnc_segment> x = a.seg, y = b.seg;
+    auto key = [](const snnc_segment& s) { return ((uint64_t)s.host << 32) | s.first; };
+    std::sort(x.begin(), x.end(), [&](auto& p, auto& q) { return key(p) < key(q); });
+    std::sort(y.begin(), y.end(), [&](auto& p, auto& q) { return key(p) < key(q); });
+    size_t i = 0, j = 0;
+    while (i < x.size() && j < y.size()) {
+        const uint64_t xa = key(x[i]), xb = xa + x[i].n, ya = key(y[j]), yb = ya + y[j].n;
+        const uint64_t lo = std::max(xa, ya), hi = std::min(xb, yb);
+        if (hi > lo) total += hi - lo;
+        if (xb < yb) ++i; else ++j;
+    }
+    return total;
+}
+
+static bool one_host(const HostSet& s, uint32_t& host) {
+    host = 0xffffffffu;
+    for (auto& g : s.seg) {
+        if (host == 0xffffffffu) host = g.host;
+        else if (g.host != host) return false;
+    }
+    return true;
+}
+
+// Standard normal CDF via the complementary error function.
+static double phi(double x) { return 0.5 * std::erfc(-x / 1.41421356237309504880168872420969808); }
+
+static bool build_delay_table(double mean, double sd, double lo, double dt, std::vector<uint32_t>& tab,
+                              uint32_t& klo, uint64_t cap) {
+    const double klo_d = std::round(lo / dt);
+    if (!(klo_d >= 1.0) || klo_d > 65535.0) return false;
+    klo = (uint32_t)klo_d;
+    tab.clear();
+    for (uint64_t k = klo;; ++k) {
+        const double x = (((double)k + 0.5) * dt - mean) / sd;
+        const double t = std::ceil(phi(x) * 4294967296.0);
+        if (t >= 4294967296.0) break;
+        if (k >= 65535 || tab.size() >= cap) return false;
+        tab.push_back((uint32_t)t);
+    }
+    return true;
+}
+
+static void validate(const Ctx& c, Call& cl, const snnc_syn_spec* syn) {
+    const uint64_t ns = cl.S.total, nt = cl.T.total;
+    const uint64_t ov = cl.autapses ? 0 : set_overlap(cl.S, cl.T);
+    switch (cl.rule) {
+    case SNNC_ONE_TO_ONE:
+        if (ns != nt) raise(SNNC_EINVAL, "one-to-one needs equal set sizes");
+        break;
+    case SNNC_FIXED_INDEGREE:
+    case SNNC_FIXED_OUTDEGREE: {
+        const bool in = cl.rule == SNNC_FIXED_INDEGREE;
+        const uint64_t units = in ? nt : ns, cand = in ? ns : nt;
+        if (cl.n > 0 && units > 0) {
+            const uint64_t n_eff = cand - (ov > 0 ? 1 : 0);
+            if (cand == 0 || n_eff == 0) raise(SNNC_EINVAL, "no candidate to draw from");
+            if (!cl.multapses && cl.n > n_eff) raise(SNNC_EINVAL, "degree exceeds the candidates without multapses");
+            if (!cl.multapses && cl.n > 8192) raise(SNNC_EUNSUPPORTED, "degree above 8192 without multapses");
+            if (cl.n > 0xffffffffull) raise(SNNC_EUNSUPPORTED, "degree above 2^32-1");
+        }
+        break;
+    }
+    case SNNC_FIXED_TOTAL_NUMBER: {
+        uint32_t th;
+        if (!one_host(cl.T, th)) raise(SNNC_EUNSUPPORTED, "fixed total number over targets on several hosts");
+        if (cl.n > 0) {
+            if (ns == 0 || nt == 0) raise(SNNC_EINVAL, "empty node set");
+            const unsigned __int128 pairs = (unsigned __int128)ns * nt - ov;
+            if (pairs == 0) raise(SNNC_EINVAL, "no valid pair");
+            if (!cl.multapses && (unsigned __int128)cl.n > pairs) raise(SNNC_EINVAL, "total number exceeds the pairs without multapses");
+            if (cl.n > 0xffffffffull) raise(SNNC_EUNSUPPORTED, "total number above 2^32-1");
+        }
+        break;
+    }
+    case SNNC_PAIRWISE_BERNOULLI:
+        if (!(cl.p >= 0.0 && cl.p <= 1.0)) raise(SNNC_EINVAL, "probability outside [0, 1]");
+        break;
+    default:
+        raise(SNNC_EINVAL, "unknown rule");
+    }
+    if (cl.alpha < -1) raise(SNNC_EINVAL, "group index below -1");
+    if (!syn) raise(SNNC_EINVAL, "null synapse spec");
+    if (syn->port != 0) raise(SNNC_EINVAL, "receptor port must be 0");
+    cl.w = syn->weight;
+    cl.d = syn->delay_ms;
+    if (cl.w.kind == SNNC_CONST) cl.w_const = (float)cl.w.mean;
+    else if (cl.w.kind == SNNC_NORMAL) {
+        if (!(cl.w.sd >= 0.0)) raise(SNNC_EINVAL, "weight sd < 0");
+    } else raise(SNNC_EINVAL, "unknown weight distribution");
+    if (cl.d.kind == SNNC_CONST) {
+        if (!(cl.d.mean >= c.dt)) raise(SNNC_EINVAL, "delay below one time step");
+        const double steps = std::round(cl.d.mean / c.dt);
+        if (steps > 65535.0) raise(SNNC_EINVAL, "delay beyond 65535 steps");
+        cl.d_const = (uint16_t)steps;
+    } else if (cl.d.kind == SNNC_NORMAL) {
+        if (!(cl.d.sd > 0.0)) raise(SNNC_EINVAL, "delay sd must be > 0");
+        if (!(cl.d.lo >= c.dt)) raise(SNNC_EINVAL, "delay clip below one time step");
+        if (!build_delay_table(cl.d.mean, cl.d.sd, cl.d.lo, c.dt, cl.dtab, cl.d_klo, 65536))
+            raise(SNNC_EINVAL, "delay distribution does not fit uint16 steps");
+    } else raise(SNNC_EINVAL, "unknown delay distribution");
+}
+
+// device copies of a call's sets and delay table (one allocation)
+static void upload_meta(Ctx& c, Call& cl) {
+    const size_t nS = std::max<size_t>(cl.S.seg.size(), 1), nT = std::max<size_t>(cl.T.seg.size(), 1);
+    const size_t bytes = (nS + nT) * sizeof(SegD) + std::max<size_t>(cl.dtab.size(), 1) * sizeof(uint32_t);
+    std::vector<char> host(bytes, 0);
+    SegD* hS = reinterpret_cast<SegD*>(host.data());
+    SegD* hT = hS + nS;
+    for (size_t i = 0; i < cl.S.seg.size(); ++i) hS[i] = SegD{cl.S.ord_begin[i], cl.S.seg[i].host, cl.S.seg[i].first};
+    for (size_t i = 0; i < cl.T.seg.size(); ++i) hT[i] = SegD{cl.T.ord_begin[i], cl.T.seg[i].host, cl.T.seg[i].first};
+    if (!cl.dtab.empty()) memcpy(hT + nT, cl.dtab.data(), cl.dtab.size() * sizeof(uint32_t));
+    cl.meta = dalloc(c, bytes);
+    cl.meta_bytes = bytes;
+    upload(c, cl.meta, host.data(), bytes);
+    cl.dS = static_cast<SegD*>(cl.meta);
+    cl.dT = cl.dS + nS;
+    cl.dtab_dev = reinterpret_cast<uint32_t*>(cl.dT + nT);
+}
+
+void grow_gen(Ctx& c, uint64_t need) {
+    if (need <= c.cap_gen) return;
+    uint64_t cap = std::max<uint64_t>(c.cap_gen ? c.cap_gen : 1 << 16, 1 << 16);
+    while (cap < need) cap *= 2;
+    if (c.cap_gen && need <= c.cap_gen + (c.cap_gen >> 2)) cap = std::max(cap, need);
+    uint32_t* s = dalloc_n<uint32_t>(c, cap);
+    uint32_t* t = nullptr;
+    uint16_t* d = nullptr;
+    float* w = nullptr;
+    try {
+        t = dalloc_n<uint32_t>(c, cap);
+        d = dalloc_n<uint16_t>(c, cap);
+        w = dalloc_n<float>(c, cap);
+    } catch (...) {
+        dfree(c, s); dfree(c, t); dfree(c, d);
+        throw;
+    }
+    if (c.n_gen) {
+        HIPCHK(hipMemcpyAsync(s, c.g_src, c.n_gen * 4, hipMemcpyDeviceToDevice, c.stream));
+        HIPCHK(hipMemcpyAsync(t, c.g_tgt, c.n_gen * 4, hipMemcpyDeviceToDevice, c.stream));
+        HIPCHK(hipMemcpyAsync(d, c.g_delay, c.n_gen * 2, hipMemcpyDeviceToDevice, c.stream));
+        HIPCHK(hipMemcpyAsync(w, c.g_weight, c.n_gen * 4, hipMemcpyDeviceToDevice, c.stream));
+        sync(c);
+    }
+    dfree(c, c.g_src); dfree(c, c.g_tgt); dfree(c, c.g_delay); dfree(c, c.g_weight);
+    c.g_src = s; c.g_tgt = t; c.g_delay = d; c.g_weight = w;
+    c.cap_gen = cap;
+}
+
+static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
+                         const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
+    if (c.prepared) raise(SNNC_ESTATE, "connect after prepare");
+    if (!conn || !call_id_out) raise(SNNC_EINVAL, "null argument");
+    Call cl;
+    cl.id = (uint32_t)c.calls.size();
+    cl.rule = conn->kind;
+    cl.n = conn->n;
+    cl.p = conn->p;
+    cl.autapses = conn->allow_autapses != 0;
+    cl.multapses = conn->allow_multapses != 0;
+    cl.alpha = alpha;
+    cl.S = make_set(c, src);
+    cl.T = make_set(c, tgt);
+    validate(c, cl, syn);
+    upload_meta(c, cl);
+    try {
+        HIPCHK(hipEventRecord(c.phase_a, c.stream));
+        cl.gen_begin = c.n_gen;
+        cl.gen_count = gen_local(c, cl);
+        HIPCHK(hipEventRecord(c.phase_b, c.stream));
+        HIPCHK(hipEventSynchronize(c.phase_b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c.phase_a, c.phase_b));
+        c.ms_connect += ms;
+        HIPCHK(hipGetLastError());
+    } catch (...) {
+        dfree(c, cl.meta);
+        throw;
+    }
+    c.n_gen += cl.gen_count;
+    c.calls.push_back(std::move(cl));
+    *call_id_out = c.calls.back().id;
+}
+
+static void free_results(Ctx& c) {
+    for (auto& kv : c.arrays) dfree(c, kv.second.p);
+    c.arrays.clear();
+    c.counts.clear();
+}
+
+}  // namespace snnc
+
+using namespace snnc;
+
+template <class F>
+static snnc_status guarded(snnc_ctx* ctx, F&& f) {
+    try {
+        if (ctx) HIPCHK(hipSetDevice(ctx->device));
+        f();
+        if (ctx) ctx->last_error.clear();
+        return SNNC_OK;
+    } catch (const Error& e) {
+        if (ctx) ctx->last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (ctx) ctx->last_error = "host allocation failed";
+        return SNNC_ENOMEM;
+    } catch (const std::exception& e) {
+        if (ctx) ctx->last_error = e.what();
+        return SNNC_EDEVICE;
+    }
+}
+
+extern "C" {
+
+snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t seed, double dt_ms,
+                      const snnc_allocator* alloc, void* hip_stream, uint64_t budget_bytes) {
+    if (!out) return SNNC_EINVAL;
+    *out = nullptr;
+    if (P == 0 || P_local >= P || !(dt_ms > 0.0)) return SNNC_EINVAL;
+    if (alloc && (!alloc->alloc || !alloc->free)) return SNNC_EINVAL;
+    snnc_ctx* c = new (std::nothrow) snnc_ctx();
+    if (!c) return SNNC_ENOMEM;
+    c->P = P;
+    c->P_local = P_local;
+    c->seed = seed;
+    c->dt = dt_ms;
+    c->stream = (hipStream_t)hip_stream;
+    c->budget = budget_bytes;
+    if (alloc) {
+        c->alloc = *alloc;
+        c->has_alloc = true;
+    }
+    c->M.assign(P, 0);
+    snnc_status st = guarded(nullptr, [&] {
+        HIPCHK(hipGetDevice(&c->device));
+        HIPCHK(hipEventCreate(&c->phase_a));
+        HIPCHK(hipEventCreate(&c->phase_b));
+        c->d_status = dalloc_n<uint32_t>(*c, 1);
+        HIPCHK(hipMemsetAsync(c->d_status, 0, 4, c->stream));
+        sync(*c);
+    });
+    if (st != SNNC_OK) {
+        snnc_destroy(c);
+        return st;
+    }
+    *out = c;
+    return SNNC_OK;
+}
+
+snnc_status snnc_destroy(snnc_ctx* c) {
+    if (!c) return SNNC_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    std::vector<void*> ptrs;
+    for (auto& kv : c->live) ptrs.push_back(kv.first);
+    for (void* p : ptrs) dfree(*c, p);
+    for (auto& p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->phase_a) (void)hipEventDestroy(c->phase_a);
+    if (c->phase_b) (void)hipEventDestroy(c->phase_b);
+    delete c;
+    return SNNC_OK;
+}
+
+const char* snnc_last_error(const snnc_ctx* c) { return c ? c->last_error.c_str() : "null context"; }
+
+snnc_status snnc_sync(snnc_ctx* c) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] { sync(*c); });
+}
+
+snnc_status snnc_create(snnc_ctx* c, uint32_t host, uint32_t n, snnc_segment* out) {
+    if (!c || !out) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (c->prepared) raise(SNNC_ESTATE, "create after prepare");
+        if (host >= c->P) raise(SNNC_EINVAL, "host out of range");
+        if ((uint64_t)c->M[host] + n > 0x7fffffffull) raise(SNNC_EINVAL, "more than 2^31-1 neurons on a host");
+        out->host = host;
+        out->first = c->M[host];
+        out->n = n;
+        c->M[host] += n;
+    });
+}
+
+snnc_status snnc_connect(snnc_ctx* c, const snnc_nodeset* src, const snnc_nodeset* tgt,
+                         const snnc_conn_spec* conn, const snnc_syn_spec* syn, int32_t alpha,
+                         uint32_t* call_id_out) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] { connect_impl(*c, src, tgt, conn, syn, alpha, call_id_out); });
+}
+
+snnc_status snnc_reserve(snnc_ctx* c, uint64_t n) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (c->prepared) raise(SNNC_ESTATE, "reserve after prepare");
+        grow_gen(*c, n);
+    });
+}
+
+snnc_status snnc_prepare(snnc_ctx* c) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (c->prepared) raise(SNNC_ESTATE, "prepare called twice");
+        HIPCHK(hipEventRecord(c->phase_a, c->stream));
+        try {
+            prepare_all(*c);
+        } catch (...) {
+            free_results(*c);
+            throw;
+        }
+        HIPCHK(hipEventRecord(c->phase_b, c->stream));
+        HIPCHK(hipEventSynchronize(c->phase_b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->phase_a, c->phase_b));
+        c->ms_prepare = ms;
+        uint32_t status = 0;
+        download(*c, &status, c->d_status, 4);
+        if (status) raise(SNNC_EDEVICE, "a device wait exceeded its bound (status " + std::to_string(status) + ")");
+        c->prepared = true;
+    });
+}
+
+snnc_status snnc_get_array(const snnc_ctx* cc, int32_t id, const void** ptr, uint64_t* count) {
+    snnc_ctx* c = const_cast<snnc_ctx*>(cc);
+    if (!c || !ptr || !count) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        *ptr = nullptr;
+        *count = 0;
+        switch (id) {
+        case SNNC_GEN_SRC: case SNNC_GEN_TGT: case SNNC_GEN_DELAY: case SNNC_GEN_WEIGHT:
+            if (c->prepared) raise(SNNC_ESTATE, "generation-order arrays are consumed by prepare");
+            *count = c->n_gen;
+            *ptr = id == SNNC_GEN_SRC ? (const void*)c->g_src
+                 : id == SNNC_GEN_TGT ? (const void*)c->g_tgt
+                 : id == SNNC_GEN_DELAY ? (const void*)c->g_delay : (const void*)c->g_weight;
+            if (!c->n_gen) *ptr = nullptr;
+            return;
+        default:
+            break;
+        }
+        auto it = c->arrays.find(id);
+        if (it == c->arrays.end()) {
+            if (id == SNNC_CALL_OFF || !c->prepared) {
+                if (id != SNNC_CALL_OFF) raise(SNNC_ESTATE, "array not available before prepare");
+            }
+            if (id != SNNC_CALL_OFF) raise(SNNC_EINVAL, "unknown array id");
+        }
+        if (id == SNNC_CALL_OFF) {
+            // host-derived; materialised on demand
+            std::vector<uint64_t> off(c->calls.size() + 1);
+            for (size_t i = 0; i < c->calls.size(); ++i) off[i] = c->calls[i].gen_begin;
+            off.back() = c->n_gen;
+            auto& a = c->arrays[SNNC_CALL_OFF];
+            dfree(*c, a.p);
+            a.p = dalloc(*c, off.size() * 8);
+            a.bytes = off.size() * 8;
+            upload(*c, a.p, off.data(), off.size() * 8);
+            c->counts[SNNC_CALL_OFF] = off.size();
+            it = c->arrays.find(id);
+        }
+        *count = c->counts[id];
+        *ptr = *count ? it->second.p : nullptr;
+    });
+}
+
+static size_t elem_size(int32_t id) {
+    switch (id) {
+    case SNNC_GEN_DELAY: case SNNC_DELAY: return 2;
+    case SNNC_CALL_OFF: case SNNC_ROW_PTR: case SNNC_R_OFF: case SNNC_IMG_BASE: case SNNC_S_OFF:
+    case SNNC_TP_PTR: case SNNC_H_OFF: case SNNC_GQ_PTR: return 8;
+    default: return 4;
+    }
+}
+
+snnc_status snnc_copy_array(snnc_ctx* c, int32_t id, void* dst, uint64_t cap_bytes) {
+    if (!c) return SNNC_EINVAL;
+    const void* p = nullptr;
+    uint64_t n = 0;
+    snnc_status st = snnc_get_array(c, id, &p, &n);
+    if (st != SNNC_OK) return st;
+    return guarded(c, [&] {
+        const uint64_t bytes = n * elem_size(id);
+        if (bytes > cap_bytes) raise(SNNC_EINVAL, "destination too small");
+        if (!bytes) return;
+        HIPCHK(hipMemcpyAsync(dst, p, bytes, hipMemcpyDefault, c->stream));
+        sync(*c);
+    });
+}
+
+snnc_status snnc_copy_range(snnc_ctx* c, int32_t id, uint64_t first, uint64_t count, void* dst) {
+    if (!c) return SNNC_EINVAL;
+    const void* p = nullptr;
+    uint64_t n = 0;
+    snnc_status st = snnc_get_array(c, id, &p, &n);
+    if (st != SNNC_OK) return st;
+    return guarded(c, [&] {
+        if (first > n || count > n - first) raise(SNNC_EINVAL, "range outside the array");
+        if (!count) return;
+        const size_t es = elem_size(id);
+        HIPCHK(hipMemcpyAsync(dst, static_cast<const char*>(p) + first * es, count * es, hipMemcpyDefault, c->stream));
+        sync(*c);
+    });
+}
+
+snnc_status snnc_stats(snnc_ctx* c, snnc_stats_t* out) {
+    if (!c || !out) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        out->n_connections = c->n_gen;
+        out->n_images = c->n_img;
+        out->n_calls = (uint32_t)c->calls.size();
+        out->M_local = c->M[c->P_local];
+        out->bytes_live = c->bytes_live;
+        out->bytes_peak = c->bytes_peak;
+        out->sort_passes = c->sort_passes;
+        out->key_bits = c->key_bits;
+        out->ms_connect = c->ms_connect;
+        out->ms_prepare = c->ms_prepare;
+    });
+}
+
+snnc_status snnc_set_timing(snnc_ctx* c, int enable) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        resolve_times(*c);
+        c->timing = enable != 0;
+        if (enable) c->ktimes.clear();
+    });
+}
+
+snnc_status snnc_kernel_times(snnc_ctx* c, uint32_t cap, char (*names)[48], uint64_t* launches, double* ms,
+                              uint32_t* n_out) {
+    if (!c || !n_out) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        resolve_times(*c);
+        uint32_t i = 0;
+        for (auto& kv : c->ktimes) {
+            if (i < cap) {
+                snprintf(names[i], 48, "%s", kv.first.c_str());
+                launches[i] = kv.second.launches;
+                ms[i] = kv.second.ms;
+            }
+            ++i;
+        }
+        *n_out = i;
+    });
+}
+
+snnc_status snnc_delay_table(double mean, double sd, double lo, double dt, uint32_t* table, uint64_t cap,
+                             uint32_t* k_lo_out, uint64_t* len_out) {
+    if (!table || !k_lo_out || !len_out) return SNNC_EINVAL;
+    if (!(sd > 0.0) || !(dt > 0.0) || !(lo >= dt)) return SNNC_EINVAL;
+    std::vector<uint32_t> tab;
+    uint32_t klo = 0;
+    if (!build_delay_table(mean, sd, lo, dt, tab, klo, cap)) return SNNC_EINVAL;
+    memcpy(table, tab.data(), tab.size() * sizeof(uint32_t));
+    *k_lo_out = klo;
+    *len_out = tab.size();
+    return SNNC_OK;
+}
+
+}  // extern "C"

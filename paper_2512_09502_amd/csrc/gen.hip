@@ -1,0 +1,794 @@
+// Connection generation on the GPU: one thread per element (or per Philox
+// block for Bernoulli), coalesced structure-of-arrays stores, per-thread
+// Philox counters.  Rules with a data-dependent count run a counting pass,
+// a scan of the per-tile counts and a writing pass that compacts in element
+// order with a workgroup scan.
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace snnc {
+
+namespace {
+
+constexpr int NT = 256;          // threads per workgroup
+constexpr int IPT = 4;           // items per thread
+constexpr uint64_t TILE = NT * IPT;
+constexpr uint64_t MAX_TILES_PER_LAUNCH = 1u << 22;
+
+enum Mode { DIRECT = 0, COUNT = 1, WRITE = 2, MARK = 3 };
+
+struct Res {
+    uint32_t src;   // source ordinal
+    uint32_t tgt;   // target local id
+    uint64_t e;     // element index
+};
+
+// ------------------------------------------------------------------ sinks
+struct WriteSink {
+    uint32_t* src;
+    uint32_t* tgt;
+    uint16_t* delay;
+    float* weight;
+    uint64_t base;
+    SynD syn;
+    uint32_t seed, call;
+    __device__ __forceinline__ void put(uint64_t pos, const Res& r) const {
+        float w;
+        uint16_t d;
+        syn_values(syn, seed, call, r.e, w, d);
+        const uint64_t i = base + pos;
+        src[i] = r.src;
+        tgt[i] = r.tgt;
+        delay[i] = d;
+        weight[i] = w;
+    }
+    __device__ __forceinline__ void mark(const Res&) const {}
+};
+
+// Point-to-point regeneration: set the bit of every source that lives on
+// `host` (one bit row over that host's neurons).
+struct MarkSink {
+    const SegD* S;
+    uint32_t nS;
+    uint32_t host;
+    uint32_t* bits;
+    __device__ __forceinline__ void mark(const Res& r) const {
+        uint32_t h, l;
+        set_lookup(S, nS, r.src, h, l);
+        if (h == host) atomicOr(bits + (l >> 5), 1u << (l & 31));
+    }
+    __device__ __forceinline__ void put(uint64_t, const Res& r) const { mark(r); }
+};
+
+__device__ __forceinline__ uint32_t find_chunk(const TChunk* ch, uint32_t nch, uint64_t g) {
+    uint32_t a = 0, b = nch;
+    while (b - a > 1) {
+        const uint32_t m = (a + b) >> 1;
+        if (ch[m].out_begin <= g) a = m; else b = m;
+    }
+    return a;
+}
+
+// ------------------------------------------------------------------ rules
+// Fixed in-degree with multapses: element e = t_ord K + j draws its source
+// ordinal from IDX(e) over the n_s candidates (n_s - 1 with the target itself
+// skipped when autapses are excluded).
+struct InDegree {
+    static constexpr int R = 1;
+    const TChunk* ch;
+    uint32_t nch;
+    uint32_t K;
+    FastDiv fk;
+    uint32_t n_s;
+    uint32_t seed, call;
+    __device__ __forceinline__ int eval(uint64_t g, Res* r) const {
+        const TChunk c = ch[find_chunk(ch, nch, g)];
+        const uint32_t rel = (uint32_t)(g - c.out_begin);
+        const uint32_t t_rel = fastdiv(rel, fk);
+        const uint32_t j = rel - t_rel * K;
+        const uint64_t t_ord = c.t_ord + t_rel;
+        const uint64_t e = t_ord * K + j;
+        const bool skip = c.self_base >= 0;
+        const uint4 b = draw(seed, call, e, PURPOSE_IDX);
+        uint32_t s = uniform_index(b.x, b.y, n_s - (skip ? 1u : 0u));
+        if (skip && s >= (uint64_t)c.self_base + t_rel) ++s;
+        r[0] = Res{s, c.local_first + t_rel, e};
+        return 1;
+    }
+};
+
+// Fixed out-degree with multapses: element e = s_ord K + j draws a target
+// ordinal; the connection belongs to the share of the target's host.
+struct OutDegree {
+    static constexpr int R = 1;
+    const TChunk* ch;   // runs of source ordinals (local_first unused)
+    uint32_t nch;
+    uint32_t K;
+    FastDiv fk;
+    uint32_t n_t;
+    const SegD* T;
+    uint32_t nT;
+    uint32_t host;
+    uint32_t seed, call;
+    __device__ __forceinline__ int eval(uint64_t g, Res* r) const {
+        const TChunk c = ch[find_chunk(ch, nch, g)];
+        const uint32_t rel = (uint32_t)(g - c.out_begin);
+        const uint32_t s_rel = fastdiv(rel, fk);
+        const uint32_t j = rel - s_rel * K;
+        const uint64_t s_ord = c.t_ord + s_rel;
+        const uint64_t e = s_ord * K + j;
+        const bool skip = c.self_base >= 0;
+        const uint4 b = draw(seed, call, e, PURPOSE_IDX);
+        uint32_t t = uniform_index(b.x, b.y, n_t - (skip ? 1u : 0u));
+        if (skip && t >= (uint64_t)c.self_base + s_rel) ++t;
+        uint32_t h, l;
+        set_lookup(T, nT, t, h, l);
+        if (h != host) return 0;
+        r[0] = Res{(uint32_t)s_ord, l, e};
+        return 1;
+    }
+};
+
+// Fixed total number: candidate c draws (source, target) ordinals from the
+// two halves of IDX(c).  Invalid candidates: autapses when excluded, and
+// repeats of an earlier valid pair when multapses are excluded (first[c] = 0).
+struct Total {
+    static constexpr int R = 1;
+    const SegD* S;
+    uint32_t nS;
+    const SegD* T;
+    uint32_t nT;
+    uint32_t n_s, n_t;
+    uint32_t autapses;
+    const uint8_t* first;   // null when multapses are allowed
+    uint32_t seed, call;
+    __device__ __forceinline__ int eval(uint64_t cand, Res* r) const {
+        const uint4 b = draw(seed, call, cand, PURPOSE_IDX);
+        const uint32_t s = uniform_index(b.x, b.y, n_s);
+        const uint32_t t = uniform_index(b.z, b.w, n_t);
+        uint32_t th, tl;
+        set_lookup(T, nT, t, th, tl);
+        if (!autapses) {
+            uint32_t sh, sl;
+            set_lookup(S, nS, s, sh, sl);
+            if (sh == th && sl == tl) return 0;
+        }
+        if (first && !first[cand]) return 0;
+        r[0] = Res{s, tl, cand};
+        return 1;
+    }
+};
+
+// Pairwise Bernoulli: pair q = t_ord n_s + s_ord connects iff word (q mod 4)
+// of BERN(q / 4) is below floor(p 2^32).  Item = (target, block of that
+// target's pair range); a block shared by two targets is drawn by both and
+// each keeps its own pairs.
+struct Bernoulli {
+    static constexpr int R = 4;
+    const TChunk* ch;
+    uint32_t nch;
+    uint32_t nb;      // blocks per target item range
+    FastDiv fnb;
+    uint32_t n_s;
+    uint64_t thr;     // floor(p 2^32), 2^32 for p = 1
+    uint32_t autapses;
+    uint32_t seed, call;
+    __device__ __forceinline__ int eval(uint64_t g, Res* r) const {
+        const TChunk c = ch[find_chunk(ch, nch, g)];
+        const uint32_t rel = (uint32_t)(g - c.out_begin);
+        const uint32_t t_rel = fastdiv(rel, fnb);
+        const uint32_t k = rel - t_rel * nb;
+        const uint64_t t_ord = c.t_ord + t_rel;
+        const uint64_t q0 = t_ord * n_s, q1 = q0 + n_s;
+        const uint64_t blk = (q0 >> 2) + k;
+        if (blk * 4 >= q1) return 0;
+        const uint4 b = draw(seed, call, blk, PURPOSE_BERN);
+        const uint32_t w[4] = {b.x, b.y, b.z, b.w};
+        const int64_t self = c.self_base >= 0 ? c.self_base + t_rel : -1;
+        int n = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint64_t q = blk * 4 + i;
+            if (q < q0 || q >= q1) continue;
+            if ((uint64_t)w[i] >= thr) continue;
+            const uint64_t s = q - q0;
+            if (!autapses && (int64_t)s == self) continue;
+            r[n++] = Res{(uint32_t)s, c.local_first + t_rel, q};
+        }
+        return n;
+    }
+};
+
+// One-to-one: element i connects source ordinal i to target ordinal i; it is
+// an autapse exactly when the target's own source ordinal equals i.
+struct OneToOne {
+    static constexpr int R = 1;
+    const TChunk* ch;
+    uint32_t nch;
+    uint32_t autapses;
+    __device__ __forceinline__ int eval(uint64_t g, Res* r) const {
+        const TChunk c = ch[find_chunk(ch, nch, g)];
+        const uint32_t rel = (uint32_t)(g - c.out_begin);
+        const uint64_t i = c.t_ord + rel;
+        if (!autapses && c.self_base >= 0 && (uint64_t)c.self_base + rel == i) return 0;
+        r[0] = Res{(uint32_t)i, c.local_first + rel, i};
+        return 1;
+    }
+};
+
+// ------------------------------------------------------------------ generic kernel
+template <class Rule, class Sink, int MODE>
+__global__ __launch_bounds__(NT) void k_gen(Rule rule, Sink sink, uint64_t n_items, uint64_t tile0,
+                                            uint32_t* tile_counts, const uint64_t* tile_offsets, uint64_t limit) {
+    __shared__ uint32_t scratch[NT / 64];
+    const uint64_t tile = tile0 + blockIdx.x;
+    const uint64_t base = tile * TILE;
+    uint64_t running = 0;
+    if constexpr (MODE == WRITE) running = tile_offsets[tile];
+    uint32_t counted = 0;
+#pragma unroll 1
+    for (int it = 0; it < IPT; ++it) {
+        const uint64_t item = base + (uint64_t)it * NT + threadIdx.x;
+        Res r[Rule::R];
+        int n = 0;
+        if (item < n_items) n = rule.eval(item, r);
+        if constexpr (MODE == DIRECT) {
+            if (n) sink.put(item, r[0]);
+        } else if constexpr (MODE == MARK) {
+            for (int k = 0; k < n; ++k) sink.mark(r[k]);
+        } else if constexpr (MODE == COUNT) {
+            counted += (uint32_t)n;
+        } else {
+            uint32_t tot;
+            const uint32_t pre = block_excl_scan<NT>((uint32_t)n, scratch, &tot);
+            for (int k = 0; k < n; ++k) {
+                const uint64_t pos = running + pre + k;
+                if (pos < limit) sink.put(pos, r[k]);
+            }
+            running += tot;
+        }
+    }
+    if constexpr (MODE == COUNT) {
+        uint32_t tot;
+        block_excl_scan<NT>(counted, scratch, &tot);
+        if (threadIdx.x == 0) tile_counts[tile] = tot;
+    }
+}
+
+template <class Rule, class Sink, int MODE>
+void launch_gen(Ctx& c, const char* name, const Rule& rule, const Sink& sink, uint64_t n_items,
+                uint32_t* tile_counts, const uint64_t* tile_offsets, uint64_t limit) {
+    const uint64_t tiles = (n_items + TILE - 1) / TILE;
+    for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
+        const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
+        tstart(c, name);
+        hipLaunchKernelGGL((k_gen<Rule, Sink, MODE>), dim3(nb), dim3(NT), 0, c.stream, rule, sink, n_items, t0,
+                           tile_counts, tile_offsets, limit);
+        tstop(c);
+        HIPCHK(hipGetLastError());
+    }
+}
+
+// Count, scan, write: returns the number of results kept (at most `limit`,
+// the first ones in element order).  `provide(n)` returns the sink for the
+// n results (or null to only count).
+template <class Rule, class Provider>
+uint64_t count_and_write(Ctx& c, const char* name, const Rule& rule, Provider provide, uint64_t n_items,
+                         uint64_t limit) {
+    using SinkPtr = decltype(provide(0));
+    using Sink = std::remove_cv_t<std::remove_pointer_t<SinkPtr>>;
+    const uint64_t tiles = (n_items + TILE - 1) / TILE;
+    if (!tiles) return 0;
+    uint32_t* counts = dalloc_n<uint32_t>(c, tiles);
+    uint64_t* offs = dalloc_n<uint64_t>(c, tiles + 1);
+    uint64_t total = 0;
+    try {
+        launch_gen<Rule, Sink, COUNT>(c, name, rule, Sink{}, n_items, counts, nullptr, 0);
+        total = scan_u32_u64(c, counts, offs, tiles, true);
+        const uint64_t kept = std::min(total, limit);
+        if (kept) {
+            SinkPtr sink = provide(kept);
+            if (sink) launch_gen<Rule, Sink, WRITE>(c, name, rule, *sink, n_items, counts, offs, limit);
+        }
+    } catch (...) {
+        dfree(c, counts);
+        dfree(c, offs);
+        throw;
+    }
+    dfree(c, counts);
+    dfree(c, offs);
+    return std::min(total, limit);
+}
+
+// ------------------------------------------------------------------ Floyd's sampling
+// One workgroup (one wave) per unit draws K distinct values in [0, n_eff):
+// lanes draw r_j = index(IDX(base + j), n_eff - K + j + 1) in parallel, lane
+// 0 runs Floyd's insertions sequentially with an LDS hash set, the wave
+// sorts the K chosen values (bitonic network in LDS) and emits them in
+// ascending order (j = rank).  In-degree: unit = target, all K kept.
+// Out-degree: unit = source, a value is kept when its target is on `host`.
+struct FloydArgs {
+    const TChunk* ch;
+    uint32_t nch;
+    uint64_t n_units;
+    uint32_t K, n_set;     // draws per unit, candidate set size
+    uint32_t in_degree;
+    const SegD* T;         // out-degree: target set
+    uint32_t nT;
+    uint32_t host;
+    uint32_t cap;          // hash capacity (power of two >= 2K)
+    uint32_t kpad;         // power of two >= K
+    uint32_t seed, call;
+};
+
+template <class Sink, int MODE>
+__global__ __launch_bounds__(64) void k_floyd(FloydArgs a, Sink sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
+    extern __shared__ uint32_t lds[];
+    uint32_t* table = lds;               // cap entries
+    uint32_t* vals = lds + a.cap;        // kpad entries
+    const uint32_t lane = threadIdx.x;
+    for (uint64_t u = blockIdx.x; u < a.n_units; u += gridDim.x) {
+        // unit -> chunk (units are laid out as chunk.out_begin / K)
+        uint32_t lo = 0, hi = a.nch;
+        const uint64_t g = u * a.K;
+        while (hi - lo > 1) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (a.ch[m].out_begin <= g) lo = m; else hi = m;
+        }
+        const TChunk c = a.ch[lo];
+        const uint32_t rel = (uint32_t)((g - c.out_begin) / a.K);
+        const uint64_t ord = c.t_ord + rel;
+        const int64_t self = c.self_base >= 0 ? c.self_base + rel : -1;
+        const uint32_t n_eff = a.n_set - (self >= 0 ? 1u : 0u);
+        const uint64_t e0 = ord * a.K;
+        for (uint32_t i = lane; i < a.cap; i += 64) table[i] = 0xffffffffu;
+        for (uint32_t j = lane; j < a.kpad; j += 64) {
+            if (j < a.K) {
+                const uint4 b = draw(a.seed, a.call, e0 + j, PURPOSE_IDX);
+                vals[j] = uniform_index(b.x, b.y, n_eff - a.K + j + 1);
+            } else {
+                vals[j] = 0xffffffffu;
+            }
+        }
+        __syncthreads();
+        if (lane == 0) {
+            const uint32_t mask = a.cap - 1;
+            for (uint32_t j = 0; j < a.K; ++j) {
+                const uint32_t r = vals[j];
+                uint32_t h = (r * 2654435761u) & mask;
+                bool found = false;
+                while (table[h] != 0xffffffffu) {
+                    if (table[h] == r) { found = true; break; }
+                    h = (h + 1) & mask;
+                }
+                uint32_t x = r;
+                if (found) {
+                    x = n_eff - a.K + j;           // never chosen before step j
+                    h = (x * 2654435761u) & mask;
+                    while (table[h] != 0xffffffffu) h = (h + 1) & mask;
+                }
+                table[h] = x;
+                vals[j] = x;
+            }
+        }
+        __syncthreads();
+        // bitonic sort of vals[0..kpad)
+        for (uint32_t size = 2; size <= a.kpad; size <<= 1) {
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (uint32_t i = lane; i < a.kpad / 2; i += 64) {
+                    const uint32_t lo_i = 2 * i - (i & (stride - 1));
+                    const uint32_t hi_i = lo_i + stride;
+                    const bool up = ((lo_i & size) == 0);
+                    const uint32_t x = vals[lo_i], y = vals[hi_i];
+                    if ((x > y) == up) {
+                        vals[lo_i] = y;
+                        vals[hi_i] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // emit in ascending order
+        uint64_t running = 0;
+        if constexpr (MODE == WRITE) running = unit_offsets[u];
+        uint32_t counted = 0;
+        for (uint32_t j0 = 0; j0 < a.K; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            Res r{};
+            bool ok = false;
+            if (j < a.K) {
+                uint32_t v = vals[j];
+                if (self >= 0 && v >= (uint64_t)self) ++v;
+                if (a.in_degree) {
+                    r = Res{v, c.local_first + rel, e0 + j};
+                    ok = true;
+                } else {
+                    uint32_t h, l;
+                    set_lookup(a.T, a.nT, v, h, l);
+                    r = Res{(uint32_t)ord, l, e0 + j};
+                    ok = (h == a.host);
+                }
+            }
+            const uint64_t ballot = __ballot(ok);
+            if constexpr (MODE == DIRECT) {
+                if (ok) sink.put(c.out_begin + (uint64_t)rel * a.K + j, r);
+            } else if constexpr (MODE == MARK) {
+                if (ok) sink.mark(r);
+            } else if constexpr (MODE == COUNT) {
+                counted += (uint32_t)__popcll(ballot);
+            } else {
+                const uint32_t before = (uint32_t)__popcll(ballot & ((1ull << lane) - 1));
+                if (ok) sink.put(running + before, r);
+                running += (uint32_t)__popcll(ballot);
+            }
+        }
+        if constexpr (MODE == COUNT) {
+            if (lane == 0) unit_counts[u] = counted;
+        }
+        __syncthreads();
+    }
+}
+
+template <class Sink, int MODE>
+void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
+    if (!a.n_units) return;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(a.n_units, 65536);
+    const size_t shmem = (size_t)(a.cap + a.kpad) * 4;
+    if (shmem > 160 * 1024) raise(SNNC_EUNSUPPORTED, "degree too large for the LDS sampler");
+    if (shmem > 64 * 1024)
+        HIPCHK(hipFuncSetAttribute((const void*)k_floyd<Sink, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)shmem));
+    tstart(c, "gen_floyd");
+    hipLaunchKernelGGL((k_floyd<Sink, MODE>), dim3(grid), dim3(64), shmem, c.stream, a, sink, unit_counts, unit_offsets);
+    tstop(c);
+    HIPCHK(hipGetLastError());
+}
+
+uint32_t next_pow2(uint32_t x) {
+    uint32_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// ------------------------------------------------------------------ total number, restricted
+// First-occurrence flags for the multapse-free total number: sort the
+// candidates' (source, target) pair keys stably and keep the first of every
+// run of equal keys.
+__global__ void k_total_keys(const Total t, uint64_t n, uint32_t n_t, uint64_t* keys, uint32_t* vals) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 b = draw(t.seed, t.call, i, PURPOSE_IDX);
+    const uint32_t s = uniform_index(b.x, b.y, t.n_s);
+    const uint32_t tt = uniform_index(b.z, b.w, t.n_t);
+    keys[i] = (uint64_t)s * n_t + tt;
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_first_flags(const uint64_t* keys, const uint32_t* vals, uint64_t n, uint8_t* first) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    first[vals[i]] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+struct DeviceChunks {
+    TChunk* d = nullptr;
+    uint32_t n = 0;
+    uint64_t items = 0;
+};
+
+DeviceChunks upload_chunks(Ctx& c, const std::vector<TChunk>& v, uint64_t items) {
+    DeviceChunks dc;
+    dc.n = (uint32_t)v.size();
+    dc.items = items;
+    if (v.empty()) return dc;
+    dc.d = dalloc_n<TChunk>(c, v.size());
+    upload(c, dc.d, v.data(), v.size() * sizeof(TChunk));
+    return dc;
+}
+
+// Runs of units of set U (optionally only those on `host`) with their self
+// positions in set O (when autapses are excluded), each run holding at most
+// max_elems / per_unit units; out_begin counts per_unit elements per unit.
+std::vector<TChunk> unit_runs(const HostSet& U, const HostSet* O, int64_t host, uint64_t per_unit,
+                              uint64_t max_elems) {
+    std::vector<TChunk> out;
+    uint64_t acc = 0;
+    const uint64_t max_units = std::max<uint64_t>(1, max_elems / std::max<uint64_t>(per_unit, 1));
+    auto emit = [&](uint64_t ord, uint32_t local, uint64_t n, int64_t self) {
+        while (n) {
+            const uint64_t k = std::min(n, max_units);
+            out.push_back(TChunk{ord, acc, self, local, (uint32_t)k});
+            acc += k * per_unit;
+            ord += k;
+            local += (uint32_t)k;
+            if (self >= 0) self += (int64_t)k;
+            n -= k;
+        }
+    };
+    for (size_t i = 0; i < U.seg.size(); ++i) {
+        const snnc_segment g = U.seg[i];
+        if (host >= 0 && g.host != (uint32_t)host) continue;
+        const uint64_t ord0 = U.ord_begin[i];
+        if (!O) {
+            emit(ord0, g.first, g.n, -1);
+            continue;
+        }
+        // pieces of g inside the other set's segments on the same host
+        std::vector<std::pair<uint32_t, uint32_t>> cuts;   // [lo, hi) local ranges with self mapping
+        std::vector<int64_t> selfs;
+        for (size_t j = 0; j < O->seg.size(); ++j) {
+            const snnc_segment o = O->seg[j];
+            if (o.host != g.host) continue;
+            const uint64_t lo = std::max<uint64_t>(g.first, o.first);
+            const uint64_t hi = std::min<uint64_t>((uint64_t)g.first + g.n, (uint64_t)o.first + o.n);
+            if (hi <= lo) continue;
+            cuts.push_back({(uint32_t)lo, (uint32_t)hi});
+            selfs.push_back((int64_t)(O->ord_begin[j] + (lo - o.first)));
+        }
+        std::vector<size_t> idx(cuts.size());
+        for (size_t k = 0; k < idx.size(); ++k) idx[k] = k;
+        std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return cuts[x].first < cuts[y].first; });
+        uint32_t cur = g.first;
+        const uint32_t end = g.first + g.n;
+        for (size_t k : idx) {
+            if (cuts[k].first > cur) emit(ord0 + (cur - g.first), cur, cuts[k].first - cur, -1);
+            emit(ord0 + (cuts[k].first - g.first), cuts[k].first, cuts[k].second - cuts[k].first, selfs[k]);
+            cur = cuts[k].second;
+        }
+        if (cur < end) emit(ord0 + (cur - g.first), cur, end - cur, -1);
+    }
+    return out;
+}
+
+constexpr uint64_t MAX_RUN_ELEMS = 1ull << 30;
+
+uint64_t runs_elems(const std::vector<TChunk>& v, uint64_t per_unit) {
+    return v.empty() ? 0 : v.back().out_begin + (uint64_t)v.back().n * per_unit;
+}
+
+SynD syn_of(const Call& cl) {
+    SynD s{};
+    s.w_mean = cl.w.mean;
+    s.w_sd = cl.w.sd;
+    s.w_const = cl.w_const;
+    s.w_normal = cl.w.kind == SNNC_NORMAL;
+    s.d_normal = cl.d.kind == SNNC_NORMAL;
+    s.d_const = cl.d_const;
+    s.dtab = cl.dtab_dev;
+    s.dtab_len = (uint32_t)cl.dtab.size();
+    s.d_klo = cl.d_klo;
+    return s;
+}
+
+// The whole generation of one call on one host's share: with mark_bits set,
+// mark the sources on P_local (regeneration for the send lists); otherwise
+// append the connections to the context's generation-order arrays.
+uint64_t run_call(Ctx& c, Call& cl, uint32_t host, uint32_t* mark_bits) {
+    const bool mark = mark_bits != nullptr;
+    WriteSink ws{};
+    MarkSink ms{};
+    if (mark) ms = MarkSink{cl.dS, (uint32_t)cl.S.seg.size(), c.P_local, mark_bits};
+    // room for n more connections; returns the sink writing them
+    auto reserve = [&](uint64_t n) -> WriteSink* {
+        grow_gen(c, c.n_gen + n);
+        ws = WriteSink{c.g_src, c.g_tgt, c.g_delay, c.g_weight, c.n_gen, syn_of(cl), c.seed, cl.id};
+        return &ws;
+    };
+
+    const uint32_t nS = (uint32_t)cl.S.seg.size(), nT = (uint32_t)cl.T.seg.size();
+    const uint64_t ns = cl.S.total, nt = cl.T.total;
+    uint64_t result = 0;
+    std::vector<void*> temps;
+    auto cleanup = [&] {
+        for (void* p : temps) dfree(c, p);
+    };
+    try {
+        switch (cl.rule) {
+        case SNNC_FIXED_INDEGREE: {
+            const uint64_t K = cl.n;
+            if (!K || !ns) break;
+            auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, K, MAX_RUN_ELEMS);
+            const uint64_t items = runs_elems(runs, K);
+            result = items;
+            if (!items) break;
+            DeviceChunks dc = upload_chunks(c, runs, items);
+            temps.push_back(dc.d);
+            if (cl.multapses) {
+                InDegree r{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)ns, c.seed, cl.id};
+                if (mark) launch_gen<InDegree, MarkSink, MARK>(c, "gen_indegree", r, ms, items, nullptr, nullptr, 0);
+                else launch_gen<InDegree, WriteSink, DIRECT>(c, "gen_indegree", r, *reserve(items), items, nullptr, nullptr, 0);
+            } else {
+                FloydArgs a{dc.d, dc.n, items / K, (uint32_t)K, (uint32_t)ns, 1, cl.dT, nT, host,
+                            next_pow2((uint32_t)(2 * K)), next_pow2((uint32_t)K), c.seed, cl.id};
+                if (mark) launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
+                else launch_floyd<WriteSink, DIRECT>(c, a, *reserve(items), nullptr, nullptr);
+            }
+            break;
+        }
+        case SNNC_FIXED_OUTDEGREE: {
+            const uint64_t K = cl.n;
+            if (!K || !nt) break;
+            // regeneration for the point-to-point lists only needs the sources on the marked host
+            const int64_t unit_host = mark ? (int64_t)c.P_local : -1;
+            auto runs = unit_runs(cl.S, cl.autapses ? nullptr : &cl.T, unit_host, K, MAX_RUN_ELEMS);
+            const uint64_t items = runs_elems(runs, K);
+            if (!items) break;
+            DeviceChunks dc = upload_chunks(c, runs, items);
+            temps.push_back(dc.d);
+            uint64_t on_host = 0;
+            for (auto& g : cl.T.seg) if (g.host == host) on_host += g.n;
+            const bool all_local = on_host == nt;
+            if (cl.multapses) {
+                OutDegree r{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt, cl.dT, nT, host,
+                            c.seed, cl.id};
+                if (mark) {
+                    launch_gen<OutDegree, MarkSink, MARK>(c, "gen_outdegree", r, ms, items, nullptr, nullptr, 0);
+                } else if (all_local) {
+                    result = items;
+                    launch_gen<OutDegree, WriteSink, DIRECT>(c, "gen_outdegree", r, *reserve(items), items, nullptr, nullptr, 0);
+                } else {
+                    result = count_and_write<OutDegree>(c, "gen_outdegree", r, reserve, items, UINT64_MAX);
+                }
+            } else {
+                const uint64_t units = items / K;
+                FloydArgs a{dc.d, dc.n, units, (uint32_t)K, (uint32_t)nt, 0, cl.dT, nT, host,
+                            next_pow2((uint32_t)(2 * K)), next_pow2((uint32_t)K), c.seed, cl.id};
+                if (mark) {
+                    launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
+                } else if (all_local) {
+                    result = items;
+                    launch_floyd<WriteSink, DIRECT>(c, a, *reserve(items), nullptr, nullptr);
+                } else {
+                    uint32_t* cnt = dalloc_n<uint32_t>(c, units);
+                    temps.push_back(cnt);
+                    uint64_t* off = dalloc_n<uint64_t>(c, units + 1);
+                    temps.push_back(off);
+                    launch_floyd<WriteSink, COUNT>(c, a, ws, cnt, nullptr);
+                    result = scan_u32_u64(c, cnt, off, units, true);
+                    if (result) launch_floyd<WriteSink, WRITE>(c, a, *reserve(result), cnt, off);
+                }
+            }
+            break;
+        }
+        case SNNC_FIXED_TOTAL_NUMBER: {
+            uint32_t th = 0xffffffffu;
+            for (auto& g : cl.T.seg) { th = g.host; break; }
+            if (th != host || !cl.n) break;
+            const uint64_t N = cl.n;
+            Total r{cl.dS, nS, cl.dT, nT, (uint32_t)ns, (uint32_t)nt, cl.autapses ? 1u : 0u, nullptr, c.seed, cl.id};
+            if (cl.autapses && cl.multapses) {
+                result = N;
+                if (mark) launch_gen<Total, MarkSink, MARK>(c, "gen_total", r, ms, N, nullptr, nullptr, 0);
+                else launch_gen<Total, WriteSink, DIRECT>(c, "gen_total", r, *reserve(N), N, nullptr, nullptr, 0);
+                break;
+            }
+            result = N;
+            // candidate window: enough draws for N valid ones (expected), grown until it is
+            const double V = (double)ns * (double)nt;
+            double est = (double)N * 1.05 + 1024.0;
+            if (!cl.multapses) {
+                const double frac = std::min(0.999999, (double)N / V);
+                est = std::max(est, -V * std::log1p(-frac) * 1.05 + 1024.0);
+            }
+            uint64_t C = (uint64_t)std::min(est, 4.0e9);
+            for (;;) {
+                uint8_t* first = nullptr;
+                if (!cl.multapses) {
+                    uint64_t* k0 = dalloc_n<uint64_t>(c, C);
+                    uint64_t* k1 = dalloc_n<uint64_t>(c, C);
+                    uint32_t* v0 = dalloc_n<uint32_t>(c, C);
+                    uint32_t* v1 = dalloc_n<uint32_t>(c, C);
+                    first = dalloc_n<uint8_t>(c, C);
+                    temps.insert(temps.end(), {k0, k1, v0, v1, first});
+                    tstart(c, "gen_total_keys");
+                    hipLaunchKernelGGL(k_total_keys, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream, r, C,
+                                       (uint32_t)nt, k0, v0);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                    uint32_t bits = 0;
+                    while (bits < 64 && (ns * nt - 1) >> bits) ++bits;
+                    const int which = radix_sort(c, k0, v0, k1, v1, C, 0, bits, nullptr, nullptr);
+                    tstart(c, "gen_total_first");
+                    hipLaunchKernelGGL(k_first_flags, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream,
+                                       which ? k1 : k0, which ? v1 : v0, C, first);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                    dfree(c, k0); dfree(c, k1); dfree(c, v0); dfree(c, v1);
+                    temps.resize(temps.size() - 5);
+                    temps.push_back(first);
+                }
+                Total rr = r;
+                rr.first = first;
+                auto no_sink = [](uint64_t) -> WriteSink* { return nullptr; };
+                const uint64_t valid = count_and_write<Total>(c, "gen_total", rr, no_sink, C, UINT64_MAX);
+                if (valid >= N) {
+                    if (mark) count_and_write<Total>(c, "gen_total", rr, [&](uint64_t) { return &ms; }, C, N);
+                    else count_and_write<Total>(c, "gen_total", rr, reserve, C, N);
+                    break;
+                }
+                if (first) {
+                    dfree(c, first);
+                    temps.pop_back();
+                }
+                if (C >= 4000000000ull) raise(SNNC_EUNSUPPORTED, "total number needs more than 4e9 candidates");
+                C = std::min<uint64_t>(C * 2, 4000000000ull);
+            }
+            break;
+        }
+        case SNNC_PAIRWISE_BERNOULLI: {
+            if (!ns || !nt) break;
+            const uint32_t nb = (uint32_t)((ns + 3) / 4 + 1);
+            auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, nb, MAX_RUN_ELEMS);
+            const uint64_t items = runs_elems(runs, nb);
+            if (!items) break;
+            DeviceChunks dc = upload_chunks(c, runs, items);
+            temps.push_back(dc.d);
+            const uint64_t thr = cl.p >= 1.0 ? (1ull << 32) : (uint64_t)std::floor(cl.p * 4294967296.0);
+            Bernoulli r{dc.d, dc.n, nb, make_fastdiv(nb), (uint32_t)ns, thr, cl.autapses ? 1u : 0u, c.seed, cl.id};
+            if (mark) launch_gen<Bernoulli, MarkSink, MARK>(c, "gen_bernoulli", r, ms, items, nullptr, nullptr, 0);
+            else result = count_and_write<Bernoulli>(c, "gen_bernoulli", r, reserve, items, UINT64_MAX);
+            break;
+        }
+        case SNNC_ONE_TO_ONE: {
+            auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, 1, MAX_RUN_ELEMS);
+            const uint64_t items = runs_elems(runs, 1);
+            if (!items) break;
+            DeviceChunks dc = upload_chunks(c, runs, items);
+            temps.push_back(dc.d);
+            OneToOne r{dc.d, dc.n, cl.autapses ? 1u : 0u};
+            if (mark) launch_gen<OneToOne, MarkSink, MARK>(c, "gen_one_to_one", r, ms, items, nullptr, nullptr, 0);
+            else result = count_and_write<OneToOne>(c, "gen_one_to_one", r, reserve, items, UINT64_MAX);
+            break;
+        }
+        default:
+            raise(SNNC_EINVAL, "unknown rule");
+        }
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    if (!temps.empty()) sync(c);
+    cleanup();
+    return result;
+}
+
+__global__ void k_philox_blocks(uint32_t seed, uint32_t call, uint64_t e0, uint32_t purpose, uint64_t n, uint4* out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = draw(seed, call, e0 + i, purpose);
+}
+
+}  // namespace
+
+uint64_t gen_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, nullptr); }
+
+void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits) { run_call(c, cl, host, bits); }
+
+std::vector<TChunk> target_chunks(const Call& cl, uint32_t host, uint64_t K, uint64_t max_elems) {
+    return unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, K, max_elems);
+}
+
+}  // namespace snnc
+
+extern "C" snnc_status snnc_philox_blocks(snnc_ctx* ctx, uint32_t seed, uint32_t call_id, uint64_t e_begin,
+                                          uint32_t purpose, uint64_t n, uint32_t* out) {
+    using namespace snnc;
+    Ctx* c = ctx;
+    if (!c || (!out && n)) return SNNC_EINVAL;
+    try {
+        HIPCHK(hipSetDevice(c->device));
+        if (n) {
+            hipLaunchKernelGGL(k_philox_blocks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, seed,
+                               call_id, e_begin, purpose, n, reinterpret_cast<uint4*>(out));
+            HIPCHK(hipGetLastError());
+            sync(*c);
+        }
+        return SNNC_OK;
+    } catch (const Error& e) {
+        c->last_error = e.msg;
+        return e.code;
+    }
+}

@@ -1,0 +1,215 @@
+// Internal declarations of the construction library (host planner side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/snnc.h"
+
+namespace snnc {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+    snnc_status code;
+    std::string msg;
+};
+
+[[noreturn]] void raise(snnc_status code, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define HIPCHK(x) ::snnc::hip_check((x), #x)
+
+// ------------------------------------------------------------------ device-side descriptors
+// A segment of a node set: ordinals [ord_begin, ord_begin + n) are the local
+// ids [first, first + n) on `host`.
+struct SegD {
+    uint64_t ord_begin;
+    uint32_t host, first;
+};
+
+// A run of consecutive target ordinals that live on the generating host, for
+// the rules whose unit is a target.  Within a run the "self position" (the
+// ordinal of the same neuron in the source set, for autapse exclusion) is
+// either absent (self_base < 0) or self_base + (t - t_ord).
+struct TChunk {
+    uint64_t t_ord;      // first target ordinal of the run
+    uint64_t out_begin;  // first element of the run in the call's element space
+    int64_t self_base;   // source ordinal of the first target, or -1
+    uint32_t local_first;
+    uint32_t n;          // targets in the run
+};
+
+// Synapse-value parameters of a call.
+struct SynD {
+    double w_mean, w_sd;
+    const uint32_t* dtab;  // delay thresholds (device)
+    uint32_t dtab_len;
+    uint32_t d_klo;
+    float w_const;
+    uint32_t w_normal;     // 1: normal weight, 0: constant
+    uint32_t d_normal;     // 1: table delay, 0: constant
+    uint32_t d_const;
+};
+
+// ------------------------------------------------------------------ host-side call record
+struct HostSet {
+    std::vector<snnc_segment> seg;
+    std::vector<uint64_t> ord_begin;
+    uint64_t total = 0;
+};
+
+struct Call {
+    uint32_t id = 0;
+    uint32_t rule = 0;
+    uint64_t n = 0;
+    double p = 0.0;
+    bool autapses = true, multapses = true;
+    int32_t alpha = -1;
+    HostSet S, T;
+    snnc_dist w{}, d{};
+    float w_const = 0.f;
+    uint16_t d_const = 0;
+    uint32_t d_klo = 0;
+    std::vector<uint32_t> dtab;
+    // device copies
+    void* meta = nullptr;       // one allocation: S segs, T segs, delay table
+    size_t meta_bytes = 0;
+    SegD* dS = nullptr;
+    SegD* dT = nullptr;
+    uint32_t* dtab_dev = nullptr;
+    uint64_t gen_begin = 0, gen_count = 0;
+};
+
+// ------------------------------------------------------------------ context
+struct DevArray {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct KernelTime {
+    uint64_t launches = 0;
+    double ms = 0.0;
+};
+
+struct Ctx {
+    uint32_t P = 1, P_local = 0, seed = 0;
+    double dt = 0.1;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    snnc_allocator alloc{};
+    bool has_alloc = false;
+    uint64_t budget = 0;
+    uint64_t bytes_live = 0, bytes_peak = 0;
+    std::map<void*, size_t> live;
+    std::string last_error;
+
+    std::vector<uint32_t> M;          // neurons per host
+    std::vector<Call> calls;
+    bool prepared = false;
+
+    // generation-order arrays (local share), capacity cap_gen
+    uint32_t* g_src = nullptr;
+    uint32_t* g_tgt = nullptr;
+    uint16_t* g_delay = nullptr;
+    float* g_weight = nullptr;
+    uint64_t n_gen = 0, cap_gen = 0;
+
+    // results of prepare
+    std::map<int32_t, DevArray> arrays;    // by snnc_array_id
+    std::map<int32_t, uint64_t> counts;
+    uint64_t n_img = 0;
+    uint32_t sort_passes = 0, key_bits = 0;
+
+    // timing
+    bool timing = false;
+    struct Pending {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::map<std::string, KernelTime> ktimes;
+    double ms_connect = 0.0, ms_prepare = 0.0;
+    hipEvent_t phase_a = nullptr, phase_b = nullptr;
+
+    // device status word for bounded waits (0 = fine)
+    uint32_t* d_status = nullptr;
+    // radix-sort look-back epoch (never reset, so status tables need no clearing)
+    uint32_t sort_epoch = 0;
+    void* lookback = nullptr;
+    size_t lookback_bytes = 0;
+};
+
+// allocation through the context (budget-checked); throws on failure
+void* dalloc(Ctx& c, size_t bytes);
+void dfree(Ctx& c, void* p);
+template <class T>
+T* dalloc_n(Ctx& c, uint64_t n) {
+    return static_cast<T*>(dalloc(c, (size_t)(n ? n : 1) * sizeof(T)));
+}
+
+// kernel timing brackets (no-ops unless timing is enabled)
+void tstart(Ctx& c, const char* name);
+void tstop(Ctx& c);
+void resolve_times(Ctx& c);
+
+// upload helpers (synchronous w.r.t. the host buffer)
+void upload(Ctx& c, void* dst, const void* src, size_t bytes);
+void download(Ctx& c, void* dst, const void* src, size_t bytes);
+void sync(Ctx& c);
+
+// ------------------------------------------------------------------ entry points of the device code
+// Generation of one call (gen.hip).
+// gen_local: the call's connections on P_local's share, appended to the
+//   context's generation-order arrays (grown once the count is known);
+//   returns the number appended.
+// gen_mark: regenerate the draws of the call on `host`'s share and set, in
+//   the bit row `bits` (over P_local's neurons), the bit of every source that
+//   lives on P_local (point-to-point send lists).
+uint64_t gen_local(Ctx& c, Call& cl);
+void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits);
+// grow the generation-order arrays to hold `need` connections
+void grow_gen(Ctx& c, uint64_t need);
+
+// host-side helpers shared by the planner files
+std::vector<TChunk> target_chunks(const Call& cl, uint32_t host, uint64_t K, uint64_t max_elems);
+bool set_lookup_host(const HostSet& s, uint64_t ord, uint32_t& host, uint32_t& local);
+
+// device-wide scans (scan.hip)
+// out[i] = sum_{k<i} in[i] for i <= n (out has n + 1 entries); returns total
+// after synchronising when want_total.
+uint64_t scan_u32_u64(Ctx& c, const uint32_t* in, uint64_t* out, uint64_t n, bool want_total);
+// the same over popcounts of 32-bit words
+uint64_t scan_popc_u64(Ctx& c, const uint32_t* words, uint64_t* out, uint64_t n_words, bool want_total);
+uint64_t scan_u64_u64(Ctx& c, const uint64_t* in, uint64_t* out, uint64_t n, bool want_total);
+
+// stable LSD radix sort on bits [bit_lo, bit_hi) of 64-bit keys with a
+// 32-bit payload (sort.hip).  Ping-pong buffers are supplied by the caller;
+// returns 0 if the result is in (keys0, vals0), 1 if in (keys1, vals1).
+// When `final_out` is set, the last pass writes the unpacked connection
+// arrays instead (see sort.hip).
+struct FinalOut {
+    int32_t* src;
+    int32_t* tgt;
+    uint16_t* delay;
+    float* weight;
+    uint32_t tgt_shift;   // key = src << tgt_shift | tgt << 16 | delay
+    uint64_t tgt_mask;
+};
+int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, uint64_t n,
+               uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist /* may be null */,
+               const FinalOut* final_out);
+// digit histograms for all passes of a sort (radix 256, D bits per pass)
+void radix_plan(uint32_t bits, uint32_t& passes, uint32_t& digit_bits);
+
+// prepare pipeline (prepare.hip)
+void prepare_all(Ctx& c);
+
+}  // namespace snnc
+
+// The opaque handle of the C ABI is the context itself.
+struct snnc_ctx : public snnc::Ctx {};

@@ -1,0 +1,313 @@
+// Stable LSD radix sort of 64-bit keys with a 32-bit payload, one pass per
+// 8-bit (or narrower) digit, in the single-pass "onesweep" form: every
+// workgroup takes the next tile in launch order, ranks its keys within the
+// tile with wave64 ballots, publishes its per-digit count, resolves the
+// counts of all earlier tiles by decoupled look-back, stages the tile in LDS
+// in digit order and writes runs of equal digits with consecutive stores.
+// The digit histograms of all passes come from one reading pass (fused into
+// the key builder in the prepare pipeline).
+#include <algorithm>
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace snnc {
+
+namespace {
+
+constexpr int RNT = 256;                 // threads (4 waves)
+constexpr int RIPT = 16;                 // keys per thread
+constexpr int RTILE = RNT * RIPT;        // 4096 keys per tile
+constexpr int RADIX = 256;
+constexpr int WAVES = RNT / 64;
+
+// look-back status word: [63:62] flag, [61:40] epoch, [39:0] count
+constexpr uint64_t FLAG_AGG = 1ull << 62;
+constexpr uint64_t FLAG_INC = 2ull << 62;
+constexpr uint64_t VALUE_MASK = (1ull << 40) - 1;
+constexpr uint32_t EPOCH_MAX = (1u << 22) - 1;
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+__device__ __forceinline__ uint64_t pack_status(uint64_t flag, uint32_t epoch, uint64_t v) {
+    return flag | ((uint64_t)epoch << 40) | (v & VALUE_MASK);
+}
+
+__global__ __launch_bounds__(RNT) void k_hist(const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t dbits,
+                                              uint32_t passes, uint64_t* hist) {
+    __shared__ uint32_t h[8 * RADIX];
+    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += RNT) h[i] = 0;
+    __syncthreads();
+    const uint32_t mask = (1u << dbits) - 1;
+    for (uint64_t i = (uint64_t)blockIdx.x * RNT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * RNT) {
+        const uint64_t k = keys[i];
+        for (uint32_t p = 0; p < passes; ++p) atomicAdd(&h[p * RADIX + ((k >> (bit_lo + p * dbits)) & mask)], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += RNT)
+        if (h[i]) atomicAdd((unsigned long long*)&hist[i], (unsigned long long)h[i]);
+}
+
+// exclusive scan over the RADIX buckets of each pass (one workgroup per pass)
+__global__ __launch_bounds__(RADIX) void k_hist_scan(const uint64_t* hist, uint64_t* off) {
+    __shared__ uint64_t scratch[RADIX / 64];
+    const uint64_t v = hist[blockIdx.x * RADIX + threadIdx.x];
+    uint64_t tot;
+    const uint64_t ex = block_excl_scan<RADIX, uint64_t>(v, scratch, &tot);
+    off[blockIdx.x * RADIX + threadIdx.x] = ex;
+}
+
+template <bool FINAL>
+__global__ __launch_bounds__(RNT) void k_onesweep(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                  uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n,
+                                                  uint32_t shift, uint32_t dbits, const uint64_t* __restrict__ digit_off,
+                                                  uint64_t* lookback, uint32_t* tile_counter, uint32_t epoch,
+                                                  uint32_t* status, FinalOut fo) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t wave_hist[WAVES][RADIX];
+    __shared__ uint32_t tile_start[RADIX];       // first LDS slot of each digit in the tile
+    __shared__ uint64_t glob_base[RADIX];        // global position of the tile's first key of each digit
+    __shared__ uint64_t scan_scratch[RADIX / 64];
+    __shared__ uint64_t stage_k[RTILE];
+    __shared__ uint32_t stage_v[RTILE];
+
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    for (uint32_t i = threadIdx.x; i < WAVES * RADIX; i += RNT) (&wave_hist[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    const uint64_t base = tile * RTILE;
+    const uint32_t mask = (1u << dbits) - 1;
+
+    // striped load within each wave: item k of lane l is element base + wave*64*RIPT + k*64 + l
+    uint64_t key[RIPT];
+    uint32_t val[RIPT];
+    uint32_t rank[RIPT];
+    const uint64_t wbase = base + (uint64_t)wave * 64 * RIPT + lane;
+#pragma unroll
+    for (int k = 0; k < RIPT; ++k) {
+        const uint64_t i = wbase + (uint64_t)k * 64;
+        if (i < n) {
+            key[k] = kin[i];
+            val[k] = vin[i];
+        }
+    }
+    const uint64_t lt_mask = (1ull << lane) - 1;
+#pragma unroll
+    for (int k = 0; k < RIPT; ++k) {
+        const uint64_t i = wbase + (uint64_t)k * 64;
+        const bool valid = i < n;
+        const uint32_t d = valid ? (uint32_t)((key[k] >> shift) & mask) : 0u;
+        uint64_t peers = __ballot(valid);
+        for (uint32_t b = 0; b < dbits; ++b) {
+            const uint64_t bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        uint32_t r = 0;
+        if (valid) {
+            const uint32_t before = wave_hist[wave][d];
+            r = before + (uint32_t)__popcll(peers & lt_mask);
+            // the highest peer advances the wave's counter of this digit
+            if ((peers >> lane) == 1ull) wave_hist[wave][d] = before + (uint32_t)__popcll(peers);
+        }
+        rank[k] = r;
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // per digit: tile count, per-wave offsets, look-back over earlier tiles
+    const uint32_t d = threadIdx.x;   // RNT == RADIX
+    uint32_t cnt = 0;
+    uint32_t woff[WAVES];
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) {
+        woff[w] = cnt;
+        cnt += wave_hist[w][d];
+    }
+    uint64_t* my = lookback + tile * RADIX + d;
+    uint64_t excl = 0;
+    if (tile == 0) {
+        __hip_atomic_store(my, pack_status(FLAG_INC, epoch, cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_store(my, pack_status(FLAG_AGG, epoch, cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t pred = (int64_t)tile - 1;
+        uint32_t spins = 0;
+        while (pred >= 0) {
+            const uint64_t st = __hip_atomic_load(lookback + (uint64_t)pred * RADIX + d, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t flag = st & (3ull << 62);
+            const uint32_t ep = (uint32_t)((st >> 40) & EPOCH_MAX);
+            if (flag != 0 && ep == epoch) {
+                excl += st & VALUE_MASK;
+                if (flag == FLAG_INC) break;
+                --pred;
+                continue;
+            }
+            if (++spins > SPIN_LIMIT || __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                atomicOr(status, 1u);   // bounded wait exceeded: flag the failure and finish the tile
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        __hip_atomic_store(my, pack_status(FLAG_INC, epoch, excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // digit start within the tile (exclusive scan over digits)
+    uint64_t tot;
+    const uint32_t start = (uint32_t)block_excl_scan<RNT, uint64_t>((uint64_t)cnt, scan_scratch, &tot);
+    tile_start[d] = start;
+    glob_base[d] = digit_off[d] + excl;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) wave_hist[w][d] = start + woff[w];
+    __syncthreads();
+
+    // stage in digit order
+#pragma unroll
+    for (int k = 0; k < RIPT; ++k) {
+        const uint64_t i = wbase + (uint64_t)k * 64;
+        if (i < n) {
+            const uint32_t dd = (uint32_t)((key[k] >> shift) & mask);
+            const uint32_t slot = wave_hist[wave][dd] + rank[k];
+            stage_k[slot] = key[k];
+            stage_v[slot] = val[k];
+        }
+    }
+    __syncthreads();
+
+    const uint32_t tile_n = (uint32_t)min((uint64_t)RTILE, n - base);
+#pragma unroll 4
+    for (uint32_t s = threadIdx.x; s < tile_n; s += RNT) {
+        const uint64_t k = stage_k[s];
+        const uint32_t dd = (uint32_t)((k >> shift) & mask);
+        const uint64_t g = glob_base[dd] + (s - tile_start[dd]);
+        if constexpr (FINAL) {
+            fo.src[g] = (int32_t)(k >> fo.tgt_shift);
+            fo.tgt[g] = (int32_t)((k >> 16) & fo.tgt_mask);
+            fo.delay[g] = (uint16_t)(k & 0xffffu);
+            fo.weight[g] = __uint_as_float(stage_v[s]);
+        } else {
+            kout[g] = k;
+            vout[g] = stage_v[s];
+        }
+    }
+}
+
+__global__ void k_unpack(const uint64_t* keys, const uint32_t* vals, uint64_t n, FinalOut fo) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t k = keys[i];
+    fo.src[i] = (int32_t)(k >> fo.tgt_shift);
+    fo.tgt[i] = (int32_t)((k >> 16) & fo.tgt_mask);
+    fo.delay[i] = (uint16_t)(k & 0xffffu);
+    fo.weight[i] = __uint_as_float(vals[i]);
+}
+
+}  // namespace
+
+void radix_plan(uint32_t bits, uint32_t& passes, uint32_t& digit_bits) {
+    passes = (bits + 7) / 8;
+    digit_bits = passes ? (bits + passes - 1) / passes : 0;
+}
+
+void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t dbits, uint32_t passes,
+                 uint64_t* hist) {
+    HIPCHK(hipMemsetAsync(hist, 0, (size_t)passes * RADIX * 8, c.stream));
+    if (!n || !passes) return;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((n + RNT - 1) / RNT, 4096);
+    tstart(c, "sort_hist");
+    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(RNT), 0, c.stream, keys, n, bit_lo, dbits, passes, hist);
+    tstop(c);
+    HIPCHK(hipGetLastError());
+}
+
+int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, uint64_t n,
+               uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist, const FinalOut* final_out) {
+    uint32_t passes, dbits;
+    radix_plan(bit_hi > bit_lo ? bit_hi - bit_lo : 0, passes, dbits);
+    if (passes > 8) raise(SNNC_EUNSUPPORTED, "radix sort over more than 64 bits");
+    std::vector<void*> temps;
+    auto cleanup = [&] {
+        for (void* p : temps) dfree(c, p);
+    };
+    int cur = 0;
+    try {
+        const uint64_t tiles = (n + RTILE - 1) / RTILE;
+        std::vector<uint64_t> hh((size_t)passes * RADIX, 0);
+        uint64_t* off = nullptr;
+        if (passes && n) {
+            uint64_t* hist = const_cast<uint64_t*>(digit_hist);
+            if (!hist) {
+                hist = dalloc_n<uint64_t>(c, (uint64_t)passes * RADIX);
+                temps.push_back(hist);
+                launch_hist(c, keys0, n, bit_lo, dbits, passes, hist);
+            }
+            off = dalloc_n<uint64_t>(c, (uint64_t)passes * RADIX);
+            temps.push_back(off);
+            tstart(c, "sort_hist_scan");
+            hipLaunchKernelGGL(k_hist_scan, dim3(passes), dim3(RADIX), 0, c.stream, hist, off);
+            tstop(c);
+            HIPCHK(hipGetLastError());
+            download(c, hh.data(), hist, hh.size() * 8);
+            // look-back table: tiles x RADIX status words, zeroed once when (re)allocated
+            const size_t need = (size_t)tiles * RADIX * 8;
+            if (c.lookback_bytes < need) {
+                dfree(c, c.lookback);
+                c.lookback = nullptr;
+                c.lookback_bytes = 0;
+                c.lookback = dalloc(c, need);
+                c.lookback_bytes = need;
+                HIPCHK(hipMemsetAsync(c.lookback, 0, need, c.stream));
+                c.sort_epoch = 0;
+            }
+        }
+        uint32_t* counter = dalloc_n<uint32_t>(c, std::max<uint32_t>(passes, 1));
+        temps.push_back(counter);
+        HIPCHK(hipMemsetAsync(counter, 0, std::max<uint32_t>(passes, 1) * 4, c.stream));
+        // passes whose digit is the same for every key leave the order unchanged
+        std::vector<uint32_t> live;
+        for (uint32_t p = 0; p < passes; ++p) {
+            bool trivial = false;
+            for (int b = 0; b < RADIX; ++b)
+                if (hh[(size_t)p * RADIX + b] == n) trivial = true;
+            if (!trivial) live.push_back(p);
+        }
+        c.sort_passes = (uint32_t)live.size();
+        uint64_t* kb[2] = {keys0, keys1};
+        uint32_t* vb[2] = {vals0, vals1};
+        for (size_t li = 0; li < live.size(); ++li) {
+            const uint32_t p = live[li];
+            if (++c.sort_epoch > EPOCH_MAX) {
+                HIPCHK(hipMemsetAsync(c.lookback, 0, c.lookback_bytes, c.stream));
+                c.sort_epoch = 1;
+            }
+            const bool last = (li + 1 == live.size()) && final_out;
+            const uint32_t shift = bit_lo + p * dbits;
+            FinalOut fo = final_out ? *final_out : FinalOut{};
+            tstart(c, last ? "sort_pass_final" : "sort_pass");
+            if (last)
+                hipLaunchKernelGGL(k_onesweep<true>, dim3((unsigned)tiles), dim3(RNT), 0, c.stream, kb[cur], vb[cur],
+                                   kb[cur ^ 1], vb[cur ^ 1], n, shift, dbits, off + (size_t)p * RADIX,
+                                   (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status, fo);
+            else
+                hipLaunchKernelGGL(k_onesweep<false>, dim3((unsigned)tiles), dim3(RNT), 0, c.stream, kb[cur], vb[cur],
+                                   kb[cur ^ 1], vb[cur ^ 1], n, shift, dbits, off + (size_t)p * RADIX,
+                                   (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status, fo);
+            tstop(c);
+            HIPCHK(hipGetLastError());
+            cur ^= 1;
+        }
+        if (final_out && live.empty() && n) {
+            tstart(c, "sort_unpack");
+            hipLaunchKernelGGL(k_unpack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, kb[cur], vb[cur], n,
+                               *final_out);
+            tstop(c);
+            HIPCHK(hipGetLastError());
+        }
+        sync(c);
+    } catch (...) {
+        cleanup();
+        throw;
+    }
+    cleanup();
+    return cur;
+}
+
+}  // namespace snnc

@@ -1,0 +1,136 @@
+"""GPU parity: the HIP library against the oracle on the same seeded scripts,
+every output array element by element (integers bit-exact, weights within
+2 fp32 ulp), at sizes that span many tiles and ragged tails."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import compare, compare_all, log
+from paper_2512_09502_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+
+
+def test_philox_blocks_match_oracle():
+    import paper_2512_09502_amd as snnc
+    net = snnc.Network(1, 0, 1, 0.1)
+    rng = np.random.default_rng(1)
+    for seed, call, e0, purpose in [(1, 0, 0, 0), (0xFFFFFFFF, 7, 2**32 - 3, 1), (12345, 99, 2**40 + 17, 2)]:
+        got = net.philox_blocks(seed, call, e0, purpose, 300)
+        for i in rng.integers(0, 300, size=40):
+            e = e0 + int(i)
+            ref = oracle.philox([e & 0xFFFFFFFF, e >> 32, purpose, 0], [seed, call])
+            assert got[i].tolist() == ref.tolist()
+    net.close()
+
+
+def test_balanced_small_full():
+    n = compare_all(W.balanced_small(), 0)
+    assert n == 100000
+
+
+@pytest.mark.parametrize("scale", [0.02, 0.05])
+def test_column8_scaled(scale):
+    s = W.column8(scale=scale)
+    n = compare_all(s, 0)
+    log(f"column8 scale={scale}: {n} connections")
+
+
+def test_multiarea_p2p_scaled():
+    s = W.multiarea_p2p(P=6, n_e=800, n_i=200, k_e=40, k_i=10, k_remote_max=12)
+    for pl in (0, 3):
+        compare_all(s, pl)
+
+
+def test_balanced_collective_scaled():
+    s = W.balanced_collective(P=12, n_e=400, n_i=100, k_e=90, k_i=22)
+    for pl in (0, 11):
+        compare_all(s, pl)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_tiny(seed):
+    s = W.random_tiny(seed)
+    for pl in range(s["P"]):
+        compare_all(s, pl)
+
+
+SYN_N = {"weight": {"kind": "normal", "mean": 0.3, "sd": 0.2},
+         "delay": {"kind": "normal", "mean": 2.0, "sd": 1.0, "lo": 0.2}}
+
+
+def _one(rule_conn, n_src=3000, n_tgt=2500, P=1, src_host=0, tgt_host=0, alpha=-1):
+    b = W._Builder(P, seed=77)
+    pops = {}
+    for h in range(P):
+        pops[h] = b.create(h, max(n_src, n_tgt))
+    src = [(src_host, 0, n_src)]
+    tgt = [(tgt_host, 100, n_tgt - 100)] if n_tgt > 100 else [(tgt_host, 0, n_tgt)]
+    b.connect(src, tgt, rule_conn, SYN_N, alpha)
+    return b.script("one_" + rule_conn["rule"])
+
+
+@pytest.mark.parametrize("conn", [
+    {"rule": "fixed_indegree", "n": 37, "autapses": False, "multapses": False},
+    {"rule": "fixed_indegree", "n": 300, "autapses": True, "multapses": False},
+    {"rule": "fixed_outdegree", "n": 41, "autapses": False, "multapses": True},
+    {"rule": "fixed_outdegree", "n": 23, "autapses": False, "multapses": False},
+    {"rule": "fixed_total_number", "n": 200000, "autapses": False, "multapses": True},
+    {"rule": "fixed_total_number", "n": 150000, "autapses": True, "multapses": False},
+    {"rule": "fixed_total_number", "n": 120000, "autapses": False, "multapses": False},
+    {"rule": "pairwise_bernoulli", "p": 0.013, "autapses": False},
+    {"rule": "pairwise_bernoulli", "p": 1.0, "autapses": True},
+    {"rule": "one_to_one", "autapses": False},
+])
+def test_rules_with_flags(conn):
+    if conn["rule"] == "one_to_one":
+        s = _one(conn, n_src=2400, n_tgt=2500)
+    elif conn["rule"] == "pairwise_bernoulli":
+        s = _one(conn, n_src=900, n_tgt=700)
+    else:
+        s = _one(conn)
+    compare_all(s, 0)
+
+
+@pytest.mark.parametrize("rule", ["fixed_outdegree", "pairwise_bernoulli", "fixed_indegree", "one_to_one"])
+def test_remote_rules_all_hosts(rule):
+    # sources on host 1, targets spread over hosts 0..2: every host's share,
+    # including the regenerated point-to-point lists on host 1
+    b = W._Builder(3, seed=5)
+    p = [b.create(h, 500) for h in range(3)]
+    conn = {"rule": rule, "n": 9, "p": 0.05, "autapses": True, "multapses": rule != "fixed_outdegree"}
+    tgt = [(0, 0, 500), (2, 0, 500), (1, 0, 500)]
+    src = [(1, 0, 500)] if rule != "one_to_one" else [(1, 0, 500), (0, 0, 500), (2, 0, 500)]
+    b.connect(src, tgt, conn, SYN_N, -1)
+    b.connect(src, tgt, conn, SYN_N, 0)
+    s = b.script("remote_" + rule)
+    for pl in range(3):
+        compare_all(s, pl)
+
+
+def test_edge_cases():
+    b = W._Builder(2, seed=3)
+    a = b.create(0, 1)
+    c = b.create(1, 5)
+    d0 = {"kind": "const", "mean": 0.1}
+    syn = {"weight": {"kind": "const", "mean": 1.0}, "delay": d0}
+    b.connect([a], [a], {"rule": "fixed_indegree", "n": 0}, syn)                    # K = 0
+    b.connect([a], [a], {"rule": "pairwise_bernoulli", "p": 0.0}, syn)              # p = 0
+    b.connect([a], [a], {"rule": "fixed_indegree", "n": 3}, syn)                    # single neuron, autapses
+    b.connect([c], [a], {"rule": "fixed_total_number", "n": 7}, syn, 0)             # remote sources, group 0
+    b.connect([a, c], [a], {"rule": "one_to_one", "autapses": False}, syn)          # invalid: sizes differ
+    s = b.script("edge")
+    for pl in range(2):
+        compare_all(s, pl)
+    # no connection at all
+    b = W._Builder(1)
+    b.create(0, 10)
+    compare_all(b.script("empty"), 0)
