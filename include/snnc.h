@@ -179,6 +179,42 @@ snnc_status snnc_connect(snnc_ctx* ctx, const snnc_nodeset* src, const snnc_node
 /* Reserve room for n generated connections (optional; avoids regrowth). */
 snnc_status snnc_reserve(snnc_ctx* ctx, uint64_t n_connections);
 
+/* ---------------------------------------------------------------- served construction
+ * A construction server keeps the growing network resident in HBM and admits
+ * each Connect request against a budget on the resident network: 14 bytes
+ * per connection (source, target, delay, weight) plus the request's metadata.
+ * Admission uses the exact connection count of the request on P_local's share
+ * (a counting pass where the count depends on the draws), in submission
+ * order, so it is deterministic; a rejected request changes nothing and gets
+ * no call id.  The budget applies to snnc_connect as well, so per-call and
+ * batched construction of the same request stream admit the same requests
+ * and build bit-identical networks.  (This is the served form of the paper's
+ * dynamic construction, where the maps are kept in blocks allocated as they
+ * grow; the budget plays the role of the GPU memory limit that bounds the
+ * paper's scaling.) */
+
+/* Set the resident budget in bytes (0 = none).  SNNC_ESTATE after prepare. */
+snnc_status snnc_set_resident_budget(snnc_ctx* ctx, uint64_t bytes);
+
+/* Submit a Connect request (arguments as snnc_connect): validate, count,
+ * admit and reserve its positions now; generate it at the next snnc_flush.
+ * *call_id_out receives its call id.  Errors: as snnc_connect, plus
+ * SNNC_EBUDGET when the request does not fit the resident budget. */
+snnc_status snnc_submit(snnc_ctx* ctx, const snnc_nodeset* src, const snnc_nodeset* tgt,
+                        const snnc_conn_spec* conn, const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out);
+
+/* Launch every submitted, not yet generated request as one batch: requests
+ * whose connections are one per element (fixed in-degree and out-degree with
+ * multapses, fixed total number with autapses and multapses, one-to-one
+ * without skipped autapses) run in one persistent launch replayed from a
+ * captured HIP graph; the others run their own launches.  Returns once the
+ * batch is enqueued. */
+snnc_status snnc_flush(snnc_ctx* ctx);
+
+/* *done = 1 when the call's connections are generated (its batch has
+ * completed on the device, or it was made by snnc_connect), 0 otherwise. */
+snnc_status snnc_poll(snnc_ctx* ctx, uint32_t call_id, int32_t* done);
+
 /* Simulation preparation (Methods, point-to-point and collective creation
  * subsections; "GPU memory levels" for the source-major order):
  *  1. image map: for every map index a = alpha + 1 and remote host sigma, R
@@ -269,7 +305,24 @@ snnc_status snnc_set_timing(snnc_ctx* ctx, int enable);
 snnc_status snnc_kernel_times(snnc_ctx* ctx, uint32_t cap, char (*names)[48], uint64_t* launches,
                               double* ms, uint32_t* n_out);
 
+/* Tuning knobs of the context, by name.  "sort_variant": tile shape of the
+ * radix-sort passes, 0 .. 5 (threads x keys per thread: 256x16, 256x8,
+ * 512x8, 512x16, 1024x8, 256x12).  SNNC_EINVAL for an unknown key or value. */
+snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
+/* Further keys: "fuse_batches" (0/1, default 1) and "fused_wgs_per_cu"
+ * (workgroups per compute unit of the persistent batch launch, 1 .. 64). */
+
 /* ---------------------------------------------------------------- helpers */
+
+/* The source-major sort of Prepare on its own: stable LSD radix sort of n
+ * (key, payload) pairs in device memory by key bits [bit_lo, bit_hi) (ties
+ * keep their input order), on the context stream, with the context's sort
+ * variant.  keys_tmp/vals_tmp are device scratch of the same sizes.  On
+ * return *result_in_tmp says whether the sorted pairs are in (keys, vals)
+ * (0) or in (keys_tmp, vals_tmp) (1).  Errors: SNNC_EINVAL for bad bit
+ * ranges or null pointers, SNNC_EDEVICE if a device wait exceeded its bound. */
+snnc_status snnc_sort_pairs(snnc_ctx* ctx, uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
+                            uint64_t n, uint32_t bit_lo, uint32_t bit_hi, int32_t* result_in_tmp);
 
 /* The delay-step table of a NORMAL(mean, sd) delay clipped at lo (ms) for
  * time step dt (ms): k_lo = round(lo / dt) and thresholds

@@ -80,7 +80,8 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_create", "snnc_connect",
            "snnc_reserve", "snnc_prepare", "snnc_get_array", "snnc_copy_array", "snnc_copy_range",
-           "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks"]
+           "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks",
+           "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_flush", "snnc_poll"]
 
 _lib = None
 
@@ -112,6 +113,12 @@ def lib():
         L.snnc_kernel_times.argtypes = [vp, u32, vp, vp, vp, ctypes.POINTER(u32)]
         L.snnc_delay_table.argtypes = [dbl, dbl, dbl, dbl, vp, u64, ctypes.POINTER(u32), ctypes.POINTER(u64)]
         L.snnc_philox_blocks.argtypes = [vp, u32, u32, u64, u32, u64, vp]
+        L.snnc_tune.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
+        L.snnc_sort_pairs.argtypes = [vp, vp, vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int32)]
+        L.snnc_set_resident_budget.argtypes = [vp, u64]
+        L.snnc_submit.argtypes = L.snnc_connect.argtypes
+        L.snnc_flush.argtypes = [vp]
+        L.snnc_poll.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_int32)]
         for name in EXPORTS:
             getattr(L, name).restype = st if name != "snnc_last_error" else ctypes.c_char_p
         _lib = L
@@ -201,16 +208,34 @@ class Network:
         self._check(lib().snnc_create(self._h, host, n, ctypes.byref(seg)))
         return (seg.host, seg.first, seg.n)
 
-    def connect(self, src, tgt, conn, syn, alpha: int = -1) -> int:
+    def _connect_like(self, fn, src, tgt, conn, syn, alpha):
         s, s_keep = _nodeset(src)
         t, t_keep = _nodeset(tgt)
         cs = ConnSpec(RULES[conn["rule"]], int(conn.get("autapses", True)), int(conn.get("multapses", True)), 0,
                       int(conn.get("n", 0)), float(conn.get("p", 0.0)))
         ss = SynSpec(_dist(syn.get("weight")), _dist(syn.get("delay")), int(syn.get("port", 0)), 0)
         cid = ctypes.c_uint32()
-        self._check(lib().snnc_connect(self._h, ctypes.byref(s), ctypes.byref(t), ctypes.byref(cs),
-                                       ctypes.byref(ss), int(alpha), ctypes.byref(cid)))
+        self._check(fn(self._h, ctypes.byref(s), ctypes.byref(t), ctypes.byref(cs), ctypes.byref(ss), int(alpha),
+                       ctypes.byref(cid)))
         return int(cid.value)
+
+    def connect(self, src, tgt, conn, syn, alpha: int = -1) -> int:
+        return self._connect_like(lib().snnc_connect, src, tgt, conn, syn, alpha)
+
+    def submit(self, src, tgt, conn, syn, alpha: int = -1) -> int:
+        """Served mode: admit and reserve now, generate at the next flush()."""
+        return self._connect_like(lib().snnc_submit, src, tgt, conn, syn, alpha)
+
+    def flush(self):
+        self._check(lib().snnc_flush(self._h))
+
+    def poll(self, call_id: int) -> bool:
+        done = ctypes.c_int32()
+        self._check(lib().snnc_poll(self._h, int(call_id), ctypes.byref(done)))
+        return bool(done.value)
+
+    def set_resident_budget(self, nbytes: int):
+        self._check(lib().snnc_set_resident_budget(self._h, int(nbytes)))
 
     def reserve(self, n: int):
         self._check(lib().snnc_reserve(self._h, int(n)))
@@ -267,6 +292,20 @@ class Network:
         n = ctypes.c_uint32()
         self._check(lib().snnc_kernel_times(self._h, cap, names, launches, ms, ctypes.byref(n)))
         return {names[i].value.decode(): (int(launches[i]), float(ms[i])) for i in range(min(n.value, cap))}
+
+    def tune(self, key: str, value: int):
+        self._check(lib().snnc_tune(self._h, key.encode(), int(value)))
+
+    def sort_pairs(self, keys, vals, bit_lo: int, bit_hi: int):
+        """Stable radix sort of device tensors keys (int64) / vals (int32) by
+        key bits [bit_lo, bit_hi); returns the sorted (keys, vals) tensors."""
+        torch = self._torch
+        kt, vt = torch.empty_like(keys), torch.empty_like(vals)
+        where = ctypes.c_int32()
+        self._check(lib().snnc_sort_pairs(self._h, ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+                                          ctypes.c_void_p(kt.data_ptr()), ctypes.c_void_p(vt.data_ptr()),
+                                          keys.numel(), bit_lo, bit_hi, ctypes.byref(where)))
+        return (kt, vt) if where.value else (keys, vals)
 
     def philox_blocks(self, seed: int, call_id: int, e_begin: int, purpose: int, n: int) -> np.ndarray:
         torch = self._torch

@@ -27,10 +27,11 @@ void* dalloc(Ctx& c, size_t bytes) {
         p = c.alloc.alloc(bytes, (void*)c.stream, c.alloc.user);
         if (!p) raise(SNNC_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
     } else {
-        hipError_t e = hipMalloc(&p, bytes);
+        // stream-ordered: a buffer freed after enqueued work is reused only by later work
+        hipError_t e = hipMallocAsync(&p, bytes, c.stream);
         if (e != hipSuccess || !p) {
             (void)hipGetLastError();
-            raise(SNNC_ENOMEM, "hipMalloc failed for " + std::to_string(bytes) + " bytes");
+            raise(SNNC_ENOMEM, "hipMallocAsync failed for " + std::to_string(bytes) + " bytes");
         }
     }
     c.live[p] = bytes;
@@ -48,7 +49,7 @@ void dfree(Ctx& c, void* p) {
     if (c.has_alloc) {
         c.alloc.free(p, c.alloc.user);
     } else {
-        (void)hipFree(p);
+        (void)hipFreeAsync(p, c.stream);
     }
 }
 
@@ -95,8 +96,22 @@ void resolve_times(Ctx& c) {
 
 void upload(Ctx& c, void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
-    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.stream));
-    HIPCHK(hipStreamSynchronize(c.stream));
+    if (!c.stage || bytes > c.stage_bytes) {
+        HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        return;
+    }
+    const size_t at = (c.stage_used + 255) & ~(size_t)255;
+    if (at + bytes > c.stage_bytes) {
+        // every earlier copy out of the staging area must have run before reuse
+        HIPCHK(hipEventSynchronize(c.stage_done));
+        c.stage_used = 0;
+        return upload(c, dst, src, bytes);
+    }
+    memcpy(c.stage + at, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, c.stage + at, bytes, hipMemcpyHostToDevice, c.stream));
+    HIPCHK(hipEventRecord(c.stage_done, c.stream));
+    c.stage_used = at + bytes;
 }
 
 void download(Ctx& c, void* dst, const void* src, size_t bytes) {
@@ -293,10 +308,11 @@ void grow_gen(Ctx& c, uint64_t need) {
     c.cap_gen = cap;
 }
 
-static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
-                         const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
+// A validated call record with its device metadata (not yet admitted).
+static Call make_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
+                      const snnc_syn_spec* syn, int32_t alpha) {
     if (c.prepared) raise(SNNC_ESTATE, "connect after prepare");
-    if (!conn || !call_id_out) raise(SNNC_EINVAL, "null argument");
+    if (!conn) raise(SNNC_EINVAL, "null argument");
     Call cl;
     cl.id = (uint32_t)c.calls.size();
     cl.rule = conn->kind;
@@ -309,23 +325,79 @@ static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
     cl.T = make_set(c, tgt);
     validate(c, cl, syn);
     upload_meta(c, cl);
+    return cl;
+}
+
+// resident bytes of a call with n connections: 14 B per connection + metadata
+static uint64_t resident_cost(const Call& cl, uint64_t n) { return n * 14 + cl.meta_bytes; }
+
+static void admit(Ctx& c, Call& cl, uint64_t n) {
+    const uint64_t cost = resident_cost(cl, n);
+    if (c.resident_budget && c.resident_bytes + cost > c.resident_budget)
+        raise(SNNC_EBUDGET, "request of " + std::to_string(n) + " connections exceeds the resident budget");
+}
+
+static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
+                         const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
+    if (!call_id_out) raise(SNNC_EINVAL, "null argument");
+    Call cl = make_call(c, src, tgt, conn, syn, alpha);
     try {
-        HIPCHK(hipEventRecord(c.phase_a, c.stream));
+        if (c.resident_budget) admit(c, cl, gen_count_local(c, cl));
+        if (!c.conn_started) {
+            HIPCHK(hipEventRecord(c.conn_first, c.stream));
+            c.conn_started = true;
+        }
         cl.gen_begin = c.n_gen;
         cl.gen_count = gen_local(c, cl);
-        HIPCHK(hipEventRecord(c.phase_b, c.stream));
-        HIPCHK(hipEventSynchronize(c.phase_b));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, c.phase_a, c.phase_b));
-        c.ms_connect += ms;
+        HIPCHK(hipEventRecord(c.conn_last, c.stream));
         HIPCHK(hipGetLastError());
     } catch (...) {
         dfree(c, cl.meta);
         throw;
     }
     c.n_gen += cl.gen_count;
+    c.resident_bytes += resident_cost(cl, cl.gen_count);
     c.calls.push_back(std::move(cl));
     *call_id_out = c.calls.back().id;
+}
+
+// Served mode: count, admit and reserve now; generate at the next flush.
+static void submit_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
+                        const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
+    if (!call_id_out) raise(SNNC_EINVAL, "null argument");
+    Call cl = make_call(c, src, tgt, conn, syn, alpha);
+    try {
+        const uint64_t n = gen_count_local(c, cl);
+        admit(c, cl, n);
+        grow_gen(c, c.n_gen + n);
+        if (!c.conn_started) {
+            HIPCHK(hipEventRecord(c.conn_first, c.stream));
+            c.conn_started = true;
+        }
+        cl.gen_begin = c.n_gen;
+        cl.gen_count = n;
+    } catch (...) {
+        dfree(c, cl.meta);
+        throw;
+    }
+    c.n_gen += cl.gen_count;
+    c.resident_bytes += resident_cost(cl, cl.gen_count);
+    c.queued.push_back(cl.id);
+    c.calls.push_back(std::move(cl));
+    *call_id_out = c.calls.back().id;
+}
+
+void flush_pending(Ctx& c) {
+    if (c.queued.empty()) return;
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    c.batch_done.push_back(ev);
+    const int32_t b = (int32_t)c.batch_done.size() - 1;
+    std::vector<uint32_t> ids;
+    ids.swap(c.queued);
+    for (uint32_t id : ids) c.calls[id].batch = b;
+    flush_batch(c, ids, ev);
+    HIPCHK(hipEventRecord(c.conn_last, c.stream));
 }
 
 static void free_results(Ctx& c) {
@@ -382,6 +454,11 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
         HIPCHK(hipGetDevice(&c->device));
         HIPCHK(hipEventCreate(&c->phase_a));
         HIPCHK(hipEventCreate(&c->phase_b));
+        HIPCHK(hipEventCreate(&c->conn_first));
+        HIPCHK(hipEventCreate(&c->conn_last));
+        HIPCHK(hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming));
+        c->stage_bytes = 4u << 20;
+        HIPCHK(hipHostMalloc((void**)&c->stage, c->stage_bytes, hipHostMallocDefault));
         c->d_status = dalloc_n<uint32_t>(*c, 1);
         HIPCHK(hipMemsetAsync(c->d_status, 0, 4, c->stream));
         sync(*c);
@@ -408,6 +485,13 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
     if (c->phase_a) (void)hipEventDestroy(c->phase_a);
     if (c->phase_b) (void)hipEventDestroy(c->phase_b);
+    if (c->conn_first) (void)hipEventDestroy(c->conn_first);
+    if (c->conn_last) (void)hipEventDestroy(c->conn_last);
+    if (c->stage_done) (void)hipEventDestroy(c->stage_done);
+    if (c->stage) (void)hipHostFree(c->stage);
+    for (auto e : c->batch_done) (void)hipEventDestroy(e);
+    if (c->fused_exec) (void)hipGraphExecDestroy(c->fused_exec);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
     return SNNC_OK;
 }
@@ -439,6 +523,50 @@ snnc_status snnc_connect(snnc_ctx* c, const snnc_nodeset* src, const snnc_nodese
     return guarded(c, [&] { connect_impl(*c, src, tgt, conn, syn, alpha, call_id_out); });
 }
 
+snnc_status snnc_set_resident_budget(snnc_ctx* c, uint64_t bytes) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (c->prepared) raise(SNNC_ESTATE, "budget after prepare");
+        c->resident_budget = bytes;
+    });
+}
+
+snnc_status snnc_submit(snnc_ctx* c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
+                        const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] { submit_impl(*c, src, tgt, conn, syn, alpha, call_id_out); });
+}
+
+snnc_status snnc_flush(snnc_ctx* c) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (c->prepared) raise(SNNC_ESTATE, "flush after prepare");
+        flush_pending(*c);
+    });
+}
+
+snnc_status snnc_poll(snnc_ctx* c, uint32_t call_id, int32_t* done) {
+    if (!c || !done) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (call_id >= c->calls.size()) raise(SNNC_EINVAL, "unknown call id");
+        const int32_t b = c->calls[call_id].batch;
+        if (b < 0) {   // generated by connect, or waiting for a flush
+            *done = 0;
+            for (uint32_t id : c->queued)
+                if (id == call_id) return;
+            *done = 1;
+            return;
+        }
+        const hipError_t e = hipEventQuery(c->batch_done[b]);
+        if (e == hipErrorNotReady) {
+            *done = 0;
+            return;
+        }
+        HIPCHK(e);
+        *done = 1;
+    });
+}
+
 snnc_status snnc_reserve(snnc_ctx* c, uint64_t n) {
     if (!c) return SNNC_EINVAL;
     return guarded(c, [&] {
@@ -451,8 +579,19 @@ snnc_status snnc_prepare(snnc_ctx* c) {
     if (!c) return SNNC_EINVAL;
     return guarded(c, [&] {
         if (c->prepared) raise(SNNC_ESTATE, "prepare called twice");
+        flush_pending(*c);
+        if (c->conn_started) {
+            HIPCHK(hipEventSynchronize(c->conn_last));
+            float cms = 0.f;
+            HIPCHK(hipEventElapsedTime(&cms, c->conn_first, c->conn_last));
+            c->ms_connect = cms;
+        }
         HIPCHK(hipEventRecord(c->phase_a, c->stream));
         try {
+            for (auto& cl : c->calls) {   // per-call launch tables are no longer needed (stream order)
+                for (void* p : cl.owned) dfree(*c, p);
+                cl.owned.clear();
+            }
             prepare_all(*c);
         } catch (...) {
             free_results(*c);
@@ -565,6 +704,25 @@ snnc_status snnc_stats(snnc_ctx* c, snnc_stats_t* out) {
         out->key_bits = c->key_bits;
         out->ms_connect = c->ms_connect;
         out->ms_prepare = c->ms_prepare;
+    });
+}
+
+snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
+    if (!c || !key) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (!strcmp(key, "sort_variant")) {
+            if (value < 0 || value >= sort_variant_count()) raise(SNNC_EINVAL, "sort_variant out of range");
+            c->sort_variant = (int)value;
+        } else if (!strcmp(key, "fuse_batches")) {
+            c->fuse_batches = value != 0;
+        } else if (!strcmp(key, "fused_wgs_per_cu")) {
+            if (value < 1 || value > 64) raise(SNNC_EINVAL, "fused_wgs_per_cu out of range");
+            c->fused_wgs_per_cu = (int)value;
+            if (c->fused_exec) HIPCHK(hipGraphExecDestroy(c->fused_exec));
+            c->fused_exec = nullptr;
+        } else {
+            raise(SNNC_EINVAL, std::string("unknown tuning key ") + key);
+        }
     });
 }
 

@@ -116,6 +116,22 @@ __device__ __forceinline__ uint32_t fastdiv(uint32_t x, const FastDiv& f) {
     return (uint32_t)(((uint64_t)x * f.m) >> f.shift);
 }
 
+// Add 1 to bin `bin` of an LDS histogram for every valid lane; when the
+// whole wave hits one bin (common for the high digits of sorted-ish data) a
+// single atomic adds the wave's count.  Call with the whole wave converged.
+__device__ __forceinline__ void wave_hist_add(uint32_t* h, uint32_t bin, bool valid) {
+    const uint64_t act = __ballot(valid);
+    if (!act) return;
+    const int leader = __ffsll((unsigned long long)act) - 1;
+    const uint32_t b0 = __shfl(bin, leader, 64);
+    const uint64_t same = __ballot(valid && bin == b0);
+    if (same == act) {
+        if ((int)(threadIdx.x & 63) == leader) atomicAdd(&h[b0], (uint32_t)__popcll(act));
+    } else if (valid) {
+        atomicAdd(&h[bin], 1u);
+    }
+}
+
 // ------------------------------------------------------------------ scans
 // Inclusive prefix sum across a wave64 (Hillis-Steele with shuffles).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {

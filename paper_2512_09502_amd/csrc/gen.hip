@@ -564,18 +564,36 @@ SynD syn_of(const Call& cl) {
     return s;
 }
 
-// The whole generation of one call on one host's share: with mark_bits set,
-// mark the sources on P_local (regeneration for the send lists); otherwise
-// append the connections to the context's generation-order arrays.
-uint64_t run_call(Ctx& c, Call& cl, uint32_t host, uint32_t* mark_bits) {
-    const bool mark = mark_bits != nullptr;
+// Thrown by the output provider in counting mode, once the count is known.
+struct CountOnly {
+    uint64_t n;
+};
+
+enum class Out { APPEND, AT_BASE, COUNT, MARK };
+
+// The whole generation of one call on one host's share.
+//   APPEND:  append the connections to the generation-order arrays;
+//   AT_BASE: write them at [cl.gen_begin, cl.gen_begin + cl.gen_count), room
+//            reserved by the caller (served batches);
+//   COUNT:   only count them (launches counting passes where the count
+//            depends on the draws);
+//   MARK:    mark the sources on P_local (point-to-point regeneration).
+uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits) {
+    const bool mark = mode == Out::MARK;
     WriteSink ws{};
     MarkSink ms{};
     if (mark) ms = MarkSink{cl.dS, (uint32_t)cl.S.seg.size(), c.P_local, mark_bits};
-    // room for n more connections; returns the sink writing them
+    // room for the n connections; returns the sink writing them
     auto reserve = [&](uint64_t n) -> WriteSink* {
-        grow_gen(c, c.n_gen + n);
-        ws = WriteSink{c.g_src, c.g_tgt, c.g_delay, c.g_weight, c.n_gen, syn_of(cl), c.seed, cl.id};
+        uint64_t base = c.n_gen;
+        if (mode == Out::COUNT) throw CountOnly{n};
+        if (mode == Out::AT_BASE) {
+            if (n != cl.gen_count) raise(SNNC_EDEVICE, "generated count differs from the admitted count");
+            base = cl.gen_begin;
+        } else {
+            grow_gen(c, c.n_gen + n);
+        }
+        ws = WriteSink{c.g_src, c.g_tgt, c.g_delay, c.g_weight, base, syn_of(cl), c.seed, cl.id};
         return &ws;
     };
 
@@ -747,13 +765,130 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, uint32_t* mark_bits) {
         default:
             raise(SNNC_EINVAL, "unknown rule");
         }
+    } catch (const CountOnly& co) {
+        cleanup();
+        return co.n;
     } catch (...) {
         cleanup();
         throw;
     }
-    if (!temps.empty()) sync(c);
+    // buffers are released in stream order: later work on the stream may reuse them
     cleanup();
+    if (mode == Out::COUNT) return result;
     return result;
+}
+
+// ------------------------------------------------------------------ fused batches
+// Many small calls whose connections are written one per element (no count
+// depends on the draws) run as one persistent launch: a descriptor per call
+// gives its item range in the batch and its rule parameters; every item finds
+// its call by binary search and is generated exactly as in the per-call
+// kernel, at the position the call was admitted to.
+enum FusedKind : uint32_t { F_INDEGREE = 0, F_TOTAL = 1, F_OUTDEGREE = 2, F_ONE_TO_ONE = 3 };
+
+struct FusedReq {
+    uint64_t item_begin;
+    uint64_t out_base;
+    uint32_t kind, call;
+    SynD syn;
+    InDegree ind;
+    OutDegree outd;
+    Total tot;
+    OneToOne o2o;
+};
+
+struct FusedHdr {
+    uint64_t n_req, total;
+    uint32_t* src;
+    uint32_t* tgt;
+    uint16_t* delay;
+    float* weight;
+    uint32_t seed;
+};
+
+__global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs, const FusedHdr* __restrict__ hdr) {
+    const FusedHdr h = *hdr;
+    for (uint64_t tile = blockIdx.x; tile * TILE < h.total; tile += gridDim.x) {
+#pragma unroll 1
+        for (int it = 0; it < IPT; ++it) {
+            const uint64_t item = tile * TILE + (uint64_t)it * NT + threadIdx.x;
+            if (item >= h.total) continue;
+            uint32_t a = 0, b = (uint32_t)h.n_req;
+            while (b - a > 1) {
+                const uint32_t m = (a + b) >> 1;
+                if (reqs[m].item_begin <= item) a = m; else b = m;
+            }
+            const FusedReq* q = reqs + a;
+            const uint64_t local = item - q->item_begin;
+            Res r[1];
+            int n = 0;
+            switch (q->kind) {
+            case F_INDEGREE: n = q->ind.eval(local, r); break;
+            case F_TOTAL: n = q->tot.eval(local, r); break;
+            case F_OUTDEGREE: n = q->outd.eval(local, r); break;
+            default: n = q->o2o.eval(local, r); break;
+            }
+            if (n) {
+                const WriteSink ws{h.src, h.tgt, h.delay, h.weight, q->out_base, q->syn, h.seed, q->call};
+                ws.put(local, r[0]);
+            }
+        }
+    }
+}
+
+// Descriptor of a call for the fused launch, or false if the call needs its
+// own launches (counting passes, Floyd's sampling, restricted total number).
+// Chunk tables go to `owned` (kept until the batch has run).
+bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<void*>& owned) {
+    const uint32_t host = c.P_local;
+    const uint32_t nS = (uint32_t)cl.S.seg.size(), nT = (uint32_t)cl.T.seg.size();
+    const uint64_t ns = cl.S.total, nt = cl.T.total;
+    memset(&q, 0, sizeof q);
+    q.out_base = cl.gen_begin;
+    q.call = cl.id;
+    q.syn = syn_of(cl);
+    if (!cl.gen_count) return false;
+    switch (cl.rule) {
+    case SNNC_FIXED_INDEGREE: {
+        if (!cl.multapses) return false;
+        const uint64_t K = cl.n;
+        auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, K, MAX_RUN_ELEMS);
+        DeviceChunks dc = upload_chunks(c, runs, runs_elems(runs, K));
+        owned.push_back(dc.d);
+        q.kind = F_INDEGREE;
+        q.ind = InDegree{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)ns, c.seed, cl.id};
+        return true;
+    }
+    case SNNC_FIXED_OUTDEGREE: {
+        if (!cl.multapses) return false;
+        uint64_t on_host = 0;
+        for (auto& g : cl.T.seg) if (g.host == host) on_host += g.n;
+        if (on_host != nt) return false;
+        const uint64_t K = cl.n;
+        auto runs = unit_runs(cl.S, cl.autapses ? nullptr : &cl.T, -1, K, MAX_RUN_ELEMS);
+        DeviceChunks dc = upload_chunks(c, runs, runs_elems(runs, K));
+        owned.push_back(dc.d);
+        q.kind = F_OUTDEGREE;
+        q.outd = OutDegree{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt, cl.dT, nT, host, c.seed, cl.id};
+        return true;
+    }
+    case SNNC_FIXED_TOTAL_NUMBER:
+        if (!cl.autapses || !cl.multapses) return false;
+        q.kind = F_TOTAL;
+        q.tot = Total{cl.dS, nS, cl.dT, nT, (uint32_t)ns, (uint32_t)nt, 1u, nullptr, c.seed, cl.id};
+        return true;
+    case SNNC_ONE_TO_ONE: {
+        auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, 1, MAX_RUN_ELEMS);
+        if (runs_elems(runs, 1) != cl.gen_count) return false;   // some autapses are skipped
+        DeviceChunks dc = upload_chunks(c, runs, cl.gen_count);
+        owned.push_back(dc.d);
+        q.kind = F_ONE_TO_ONE;
+        q.o2o = OneToOne{dc.d, dc.n, cl.autapses ? 1u : 0u};
+        return true;
+    }
+    default:
+        return false;
+    }
 }
 
 __global__ void k_philox_blocks(uint32_t seed, uint32_t call, uint64_t e0, uint32_t purpose, uint64_t n, uint4* out) {
@@ -763,9 +898,63 @@ __global__ void k_philox_blocks(uint32_t seed, uint32_t call, uint64_t e0, uint3
 
 }  // namespace
 
-uint64_t gen_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, nullptr); }
+uint64_t gen_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, Out::APPEND, nullptr); }
 
-void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits) { run_call(c, cl, host, bits); }
+uint64_t gen_count_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, Out::COUNT, nullptr); }
+
+void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits) { run_call(c, cl, host, Out::MARK, bits); }
+
+// One batch of admitted calls: the fusable ones in one persistent launch
+// (replayed from a captured graph), the others with their own launches, all
+// writing at their admitted positions.  Records the batch's completion event.
+void flush_batch(Ctx& c, const std::vector<uint32_t>& ids, hipEvent_t done) {
+    std::vector<FusedReq> reqs;
+    std::vector<uint32_t> rest;
+    uint64_t total = 0;
+    for (uint32_t id : ids) {
+        Call& cl = c.calls[id];
+        FusedReq q;
+        if (c.fuse_batches && fused_desc(c, cl, q, cl.owned)) {
+            q.item_begin = total;
+            total += cl.gen_count;
+            reqs.push_back(q);
+        } else if (cl.gen_count) {
+            rest.push_back(id);
+        }
+    }
+    if (!reqs.empty()) {
+        // device descriptor table and header at fixed addresses, so that one
+        // captured graph serves every batch
+        if (c.fused_cap < reqs.size() || !c.fused_exec) {
+            if (c.fused_exec) HIPCHK(hipGraphExecDestroy(c.fused_exec));
+            c.fused_exec = nullptr;
+            dfree(c, c.fused_reqs);
+            dfree(c, c.fused_hdr);
+            c.fused_cap = std::max<size_t>(reqs.size() * 2, 256);
+            c.fused_reqs = dalloc(c, c.fused_cap * sizeof(FusedReq));
+            c.fused_hdr = dalloc(c, sizeof(FusedHdr));
+            if (!c.capture_stream) HIPCHK(hipStreamCreateWithFlags(&c.capture_stream, hipStreamNonBlocking));
+            int cus = 256;
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device);
+            const unsigned grid = (unsigned)std::max(1, cus * c.fused_wgs_per_cu);
+            hipGraph_t g;
+            HIPCHK(hipStreamBeginCapture(c.capture_stream, hipStreamCaptureModeRelaxed));
+            hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), 0, c.capture_stream,
+                               static_cast<const FusedReq*>(c.fused_reqs), static_cast<const FusedHdr*>(c.fused_hdr));
+            HIPCHK(hipStreamEndCapture(c.capture_stream, &g));
+            HIPCHK(hipGraphInstantiate(&c.fused_exec, g, nullptr, nullptr, 0));
+            HIPCHK(hipGraphDestroy(g));
+        }
+        FusedHdr h{reqs.size(), total, c.g_src, c.g_tgt, c.g_delay, c.g_weight, c.seed};
+        upload(c, c.fused_reqs, reqs.data(), reqs.size() * sizeof(FusedReq));
+        upload(c, c.fused_hdr, &h, sizeof h);
+        tstart(c, "gen_fused");
+        HIPCHK(hipGraphLaunch(c.fused_exec, c.stream));
+        tstop(c);
+    }
+    for (uint32_t id : rest) run_call(c, c.calls[id], c.P_local, Out::AT_BASE, nullptr);
+    HIPCHK(hipEventRecord(done, c.stream));
+}
 
 std::vector<TChunk> target_chunks(const Call& cl, uint32_t host, uint64_t K, uint64_t max_elems) {
     return unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, K, max_elems);

@@ -82,6 +82,8 @@ struct Call {
     SegD* dT = nullptr;
     uint32_t* dtab_dev = nullptr;
     uint64_t gen_begin = 0, gen_count = 0;
+    std::vector<void*> owned;   // device tables kept until the call's batch has run
+    int32_t batch = -1;         // served mode: batch that generates the call (-1: not yet flushed)
 };
 
 // ------------------------------------------------------------------ context
@@ -142,6 +144,30 @@ struct Ctx {
     uint32_t sort_epoch = 0;
     void* lookback = nullptr;
     size_t lookback_bytes = 0;
+    int sort_variant = 0;                // tile shape of the radix passes (tunable)
+
+    // pinned staging for host-to-device uploads (no synchronisation per upload)
+    char* stage = nullptr;
+    size_t stage_bytes = 0, stage_used = 0;
+    hipEvent_t stage_done = nullptr;     // last copy out of the staging area
+    // connect timing: first connect start, last connect end
+    hipEvent_t conn_first = nullptr, conn_last = nullptr;
+    bool conn_started = false;
+
+    // admission: bytes of the resident network (14 B per connection plus call
+    // metadata) may not exceed this (0: no limit)
+    uint64_t resident_budget = 0;
+    uint64_t resident_bytes = 0;
+    // served mode: admitted calls waiting for a flush, and the batches
+    std::vector<uint32_t> queued;
+    std::vector<hipEvent_t> batch_done;
+    bool fuse_batches = true;
+    int fused_wgs_per_cu = 8;
+    size_t fused_cap = 0;
+    void* fused_reqs = nullptr;
+    void* fused_hdr = nullptr;
+    hipGraphExec_t fused_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
 };
 
 // allocation through the context (budget-checked); throws on failure
@@ -157,7 +183,8 @@ void tstart(Ctx& c, const char* name);
 void tstop(Ctx& c);
 void resolve_times(Ctx& c);
 
-// upload helpers (synchronous w.r.t. the host buffer)
+// upload helpers: the host buffer may be reused as soon as upload returns
+// (small copies go through the pinned staging area without a stream sync)
 void upload(Ctx& c, void* dst, const void* src, size_t bytes);
 void download(Ctx& c, void* dst, const void* src, size_t bytes);
 void sync(Ctx& c);
@@ -172,6 +199,13 @@ void sync(Ctx& c);
 //   lives on P_local (point-to-point send lists).
 uint64_t gen_local(Ctx& c, Call& cl);
 void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits);
+// exact number of connections the call has on P_local's share (may launch a
+// counting pass)
+uint64_t gen_count_local(Ctx& c, Call& cl);
+// generate the admitted calls `ids` at their reserved positions as one batch
+void flush_batch(Ctx& c, const std::vector<uint32_t>& ids, hipEvent_t done);
+// served mode: flush whatever is pending (no-op if nothing is)
+void flush_pending(Ctx& c);
 // grow the generation-order arrays to hold `need` connections
 void grow_gen(Ctx& c, uint64_t need);
 
@@ -205,6 +239,7 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
                const FinalOut* final_out);
 // digit histograms for all passes of a sort (radix 256, D bits per pass)
 void radix_plan(uint32_t bits, uint32_t& passes, uint32_t& digit_bits);
+int sort_variant_count();
 
 // prepare pipeline (prepare.hip)
 void prepare_all(Ctx& c);

@@ -57,8 +57,8 @@ __device__ __forceinline__ void source_of(const Lookup& L, const uint32_t* g_src
     bit = (uint64_t)c.a * L.G + L.host_base[host] + local;
 }
 
-__global__ __launch_bounds__(PNT) void k_mark(Lookup L, const uint32_t* g_src, uint64_t n, uint32_t* bits) {
-    for (uint64_t i = (uint64_t)blockIdx.x * PNT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * PNT) {
+__global__ __launch_bounds__(PNT) void k_mark(Lookup L, const uint32_t* g_src, uint64_t lo, uint64_t n, uint32_t* bits) {
+    for (uint64_t i = lo + (uint64_t)blockIdx.x * PNT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * PNT) {
         uint32_t h, l;
         uint64_t bit;
         source_of(L, g_src, i, h, l, bit);
@@ -118,14 +118,20 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
     for (uint32_t i = threadIdx.x; i < passes * 256; i += PNT) h[i] = 0;
     __syncthreads();
     const uint32_t dmask = (1u << dbits) - 1;
-    for (uint64_t i = (uint64_t)blockIdx.x * PNT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * PNT) {
-        uint32_t host, local;
-        uint64_t bit;
-        source_of(L, g_src, i, host, local, bit);
-        const uint64_t src2 = host == L.PL ? local : (uint64_t)M_local + rank_of(bits, word_rank, bit);
-        const uint64_t key = (src2 << tgt_shift) | ((uint64_t)g_tgt[i] << 16) | g_delay[i];
-        keys[i] = key;
-        for (uint32_t p = 0; p < passes; ++p) atomicAdd(&h[p * 256 + ((key >> (16 + p * dbits)) & dmask)], 1u);
+    for (uint64_t base = (uint64_t)blockIdx.x * PNT; base < n; base += (uint64_t)gridDim.x * PNT) {
+        const uint64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        uint64_t key = 0;
+        if (valid) {
+            uint32_t host, local;
+            uint64_t bit;
+            source_of(L, g_src, i, host, local, bit);
+            const uint64_t src2 = host == L.PL ? local : (uint64_t)M_local + rank_of(bits, word_rank, bit);
+            key = (src2 << tgt_shift) | ((uint64_t)g_tgt[i] << 16) | g_delay[i];
+            keys[i] = key;
+        }
+        for (uint32_t p = 0; p < passes; ++p)
+            wave_hist_add(&h[p * 256], (uint32_t)((key >> (16 + p * dbits)) & dmask), valid);
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < passes * 256; i += PNT)
@@ -309,9 +315,21 @@ void prepare_all(Ctx& c) {
         const uint64_t n_words = n_bits / 32 + 1;    // one spare word: rank of the end bit
         uint32_t* bits = static_cast<uint32_t*>(tmp(n_words * 4));
         HIPCHK(hipMemsetAsync(bits, 0, n_words * 4, c.stream));
-        if (N) {
+        // only the connections of calls with a source segment off P_local can need an image
+        std::vector<std::pair<uint64_t, uint64_t>> mark_ranges;
+        for (auto& cl : c.calls) {
+            bool remote = false;
+            for (auto& g : cl.S.seg) remote |= (g.host != PL);
+            if (!remote || !cl.gen_count) continue;
+            if (!mark_ranges.empty() && mark_ranges.back().second == cl.gen_begin)
+                mark_ranges.back().second += cl.gen_count;
+            else
+                mark_ranges.push_back({cl.gen_begin, cl.gen_begin + cl.gen_count});
+        }
+        for (auto& r : mark_ranges) {
             tstart(c, "prep_mark");
-            hipLaunchKernelGGL(k_mark, dim3(grid_for(N)), dim3(PNT), 0, c.stream, L, c.g_src, N, bits);
+            hipLaunchKernelGGL(k_mark, dim3(grid_for(r.second - r.first)), dim3(PNT), 0, c.stream, L, c.g_src, r.first,
+                               r.second, bits);
             tstop(c);
             HIPCHK(hipGetLastError());
         }
@@ -358,8 +376,7 @@ void prepare_all(Ctx& c) {
                                N, bits, word_rank, M_local, 16 + tbits, dbits, passes, keys0, hist);
             tstop(c);
             HIPCHK(hipGetLastError());
-            sync(c);
-            // the source ordinals, targets and delays now live in the keys
+            // the source ordinals, targets and delays now live in the keys (released in stream order)
             dfree(c, c.g_src); c.g_src = nullptr;
             dfree(c, c.g_tgt); c.g_tgt = nullptr;
             dfree(c, c.g_delay); c.g_delay = nullptr;

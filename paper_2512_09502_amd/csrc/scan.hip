@@ -93,8 +93,7 @@ void scan_impl(Ctx& c, L load, uint64_t n, uint64_t* out) {
         dfree(c, off);
         throw;
     }
-    // the scans are stream-ordered; the temporaries may go once the stream has run them
-    sync(c);
+    // released in stream order: only later work on the stream can reuse them
     dfree(c, partial);
     dfree(c, off);
 }

@@ -1,11 +1,12 @@
 // Stable LSD radix sort of 64-bit keys with a 32-bit payload, one pass per
-// 8-bit (or narrower) digit, in the single-pass "onesweep" form: every
+// digit of at most 8 bits, in the single-pass "onesweep" form: every
 // workgroup takes the next tile in launch order, ranks its keys within the
 // tile with wave64 ballots, publishes its per-digit count, resolves the
 // counts of all earlier tiles by decoupled look-back, stages the tile in LDS
 // in digit order and writes runs of equal digits with consecutive stores.
 // The digit histograms of all passes come from one reading pass (fused into
-// the key builder in the prepare pipeline).
+// the key builder in the prepare pipeline).  Tile shapes (threads x keys per
+// thread) are template variants; the context picks one (tunable).
 #include <algorithm>
 
 #include "device_common.h"
@@ -15,11 +16,7 @@ namespace snnc {
 
 namespace {
 
-constexpr int RNT = 256;                 // threads (4 waves)
-constexpr int RIPT = 16;                 // keys per thread
-constexpr int RTILE = RNT * RIPT;        // 4096 keys per tile
 constexpr int RADIX = 256;
-constexpr int WAVES = RNT / 64;
 
 // look-back status word: [63:62] flag, [61:40] epoch, [39:0] count
 constexpr uint64_t FLAG_AGG = 1ull << 62;
@@ -32,18 +29,34 @@ __device__ __forceinline__ uint64_t pack_status(uint64_t flag, uint32_t epoch, u
     return flag | ((uint64_t)epoch << 40) | (v & VALUE_MASK);
 }
 
-__global__ __launch_bounds__(RNT) void k_hist(const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t dbits,
-                                              uint32_t passes, uint64_t* hist) {
+}  // namespace
+
+namespace {
+
+constexpr int HNT = 256;
+
+// digit width of pass p: dbits, narrowed for the last pass to end at bit_hi
+__host__ __device__ __forceinline__ uint32_t pass_width(uint32_t bit_lo, uint32_t bit_hi, uint32_t dbits, uint32_t p) {
+    const uint32_t shift = bit_lo + p * dbits;
+    return bit_hi - shift < dbits ? bit_hi - shift : dbits;
+}
+
+__global__ __launch_bounds__(HNT) void k_hist(const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t bit_hi,
+                                              uint32_t dbits, uint32_t passes, uint64_t* hist) {
     __shared__ uint32_t h[8 * RADIX];
-    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += RNT) h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += HNT) h[i] = 0;
     __syncthreads();
-    const uint32_t mask = (1u << dbits) - 1;
-    for (uint64_t i = (uint64_t)blockIdx.x * RNT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * RNT) {
-        const uint64_t k = keys[i];
-        for (uint32_t p = 0; p < passes; ++p) atomicAdd(&h[p * RADIX + ((k >> (bit_lo + p * dbits)) & mask)], 1u);
+    for (uint64_t base = (uint64_t)blockIdx.x * HNT; base < n; base += (uint64_t)gridDim.x * HNT) {
+        const uint64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        const uint64_t k = valid ? keys[i] : 0;
+        for (uint32_t p = 0; p < passes; ++p) {
+            const uint32_t mask = (1u << pass_width(bit_lo, bit_hi, dbits, p)) - 1;
+            wave_hist_add(&h[p * RADIX], (uint32_t)((k >> (bit_lo + p * dbits)) & mask), valid);
+        }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += RNT)
+    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += HNT)
         if (h[i]) atomicAdd((unsigned long long*)&hist[i], (unsigned long long)h[i]);
 }
 
@@ -56,35 +69,38 @@ __global__ __launch_bounds__(RADIX) void k_hist_scan(const uint64_t* hist, uint6
     off[blockIdx.x * RADIX + threadIdx.x] = ex;
 }
 
-template <bool FINAL>
-__global__ __launch_bounds__(RNT) void k_onesweep(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                  uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n,
-                                                  uint32_t shift, uint32_t dbits, const uint64_t* __restrict__ digit_off,
-                                                  uint64_t* lookback, uint32_t* tile_counter, uint32_t epoch,
-                                                  uint32_t* status, FinalOut fo) {
+template <int NT, int IPT, bool FINAL>
+__global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                 uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n,
+                                                 uint32_t shift, uint32_t dbits, const uint64_t* __restrict__ digit_off,
+                                                 uint64_t* lookback, uint32_t* tile_counter, uint32_t epoch,
+                                                 uint32_t* status, FinalOut fo) {
+    constexpr int TILE = NT * IPT;
+    constexpr int WAVES = NT / 64;
+    static_assert(NT >= RADIX, "one thread per digit");
     __shared__ uint32_t s_tile;
     __shared__ uint32_t wave_hist[WAVES][RADIX];
     __shared__ uint32_t tile_start[RADIX];       // first LDS slot of each digit in the tile
     __shared__ uint64_t glob_base[RADIX];        // global position of the tile's first key of each digit
-    __shared__ uint64_t scan_scratch[RADIX / 64];
-    __shared__ uint64_t stage_k[RTILE];
-    __shared__ uint32_t stage_v[RTILE];
+    __shared__ uint64_t scan_scratch[NT / 64];
+    __shared__ uint64_t stage_k[TILE];
+    __shared__ uint32_t stage_v[TILE];
 
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-    for (uint32_t i = threadIdx.x; i < WAVES * RADIX; i += RNT) (&wave_hist[0][0])[i] = 0;
+    for (uint32_t i = threadIdx.x; i < WAVES * RADIX; i += NT) (&wave_hist[0][0])[i] = 0;
     __syncthreads();
     const uint64_t tile = s_tile;
-    const uint64_t base = tile * RTILE;
+    const uint64_t base = tile * TILE;
     const uint32_t mask = (1u << dbits) - 1;
 
-    // striped load within each wave: item k of lane l is element base + wave*64*RIPT + k*64 + l
-    uint64_t key[RIPT];
-    uint32_t val[RIPT];
-    uint32_t rank[RIPT];
-    const uint64_t wbase = base + (uint64_t)wave * 64 * RIPT + lane;
+    // striped load within each wave: item k of lane l is element base + wave*64*IPT + k*64 + l
+    uint64_t key[IPT];
+    uint32_t val[IPT];
+    uint32_t rank[IPT];
+    const uint64_t wbase = base + (uint64_t)wave * 64 * IPT + lane;
 #pragma unroll
-    for (int k = 0; k < RIPT; ++k) {
+    for (int k = 0; k < IPT; ++k) {
         const uint64_t i = wbase + (uint64_t)k * 64;
         if (i < n) {
             key[k] = kin[i];
@@ -93,7 +109,7 @@ __global__ __launch_bounds__(RNT) void k_onesweep(const uint64_t* __restrict__ k
     }
     const uint64_t lt_mask = (1ull << lane) - 1;
 #pragma unroll
-    for (int k = 0; k < RIPT; ++k) {
+    for (int k = 0; k < IPT; ++k) {
         const uint64_t i = wbase + (uint64_t)k * 64;
         const bool valid = i < n;
         const uint32_t d = valid ? (uint32_t)((key[k] >> shift) & mask) : 0u;
@@ -115,53 +131,59 @@ __global__ __launch_bounds__(RNT) void k_onesweep(const uint64_t* __restrict__ k
     __syncthreads();
 
     // per digit: tile count, per-wave offsets, look-back over earlier tiles
-    const uint32_t d = threadIdx.x;   // RNT == RADIX
+    const uint32_t d = threadIdx.x;
+    const bool digit_thread = d < RADIX;
     uint32_t cnt = 0;
     uint32_t woff[WAVES];
-#pragma unroll
-    for (int w = 0; w < WAVES; ++w) {
-        woff[w] = cnt;
-        cnt += wave_hist[w][d];
-    }
-    uint64_t* my = lookback + tile * RADIX + d;
     uint64_t excl = 0;
-    if (tile == 0) {
-        __hip_atomic_store(my, pack_status(FLAG_INC, epoch, cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-        __hip_atomic_store(my, pack_status(FLAG_AGG, epoch, cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int64_t pred = (int64_t)tile - 1;
-        uint32_t spins = 0;
-        while (pred >= 0) {
-            const uint64_t st = __hip_atomic_load(lookback + (uint64_t)pred * RADIX + d, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t flag = st & (3ull << 62);
-            const uint32_t ep = (uint32_t)((st >> 40) & EPOCH_MAX);
-            if (flag != 0 && ep == epoch) {
-                excl += st & VALUE_MASK;
-                if (flag == FLAG_INC) break;
-                --pred;
-                continue;
-            }
-            if (++spins > SPIN_LIMIT || __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                atomicOr(status, 1u);   // bounded wait exceeded: flag the failure and finish the tile
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
+    if (digit_thread) {
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            woff[w] = cnt;
+            cnt += wave_hist[w][d];
         }
-        __hip_atomic_store(my, pack_status(FLAG_INC, epoch, excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t* my = lookback + tile * RADIX + d;
+        if (tile == 0) {
+            __hip_atomic_store(my, pack_status(FLAG_INC, epoch, cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(my, pack_status(FLAG_AGG, epoch, cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t pred = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            while (pred >= 0) {
+                const uint64_t st = __hip_atomic_load(lookback + (uint64_t)pred * RADIX + d, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t flag = st & (3ull << 62);
+                const uint32_t ep = (uint32_t)((st >> 40) & EPOCH_MAX);
+                if (flag != 0 && ep == epoch) {
+                    excl += st & VALUE_MASK;
+                    if (flag == FLAG_INC) break;
+                    --pred;
+                    continue;
+                }
+                if (++spins > SPIN_LIMIT || __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    atomicOr(status, 1u);   // bounded wait exceeded: flag the failure and finish the tile
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __hip_atomic_store(my, pack_status(FLAG_INC, epoch, excl + cnt), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     // digit start within the tile (exclusive scan over digits)
     uint64_t tot;
-    const uint32_t start = (uint32_t)block_excl_scan<RNT, uint64_t>((uint64_t)cnt, scan_scratch, &tot);
-    tile_start[d] = start;
-    glob_base[d] = digit_off[d] + excl;
+    const uint32_t start = (uint32_t)block_excl_scan<NT, uint64_t>((uint64_t)cnt, scan_scratch, &tot);
+    if (digit_thread) {
+        tile_start[d] = start;
+        glob_base[d] = digit_off[d] + excl;
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) wave_hist[w][d] = start + woff[w];
+        for (int w = 0; w < WAVES; ++w) wave_hist[w][d] = start + woff[w];
+    }
     __syncthreads();
 
     // stage in digit order
 #pragma unroll
-    for (int k = 0; k < RIPT; ++k) {
+    for (int k = 0; k < IPT; ++k) {
         const uint64_t i = wbase + (uint64_t)k * 64;
         if (i < n) {
             const uint32_t dd = (uint32_t)((key[k] >> shift) & mask);
@@ -172,9 +194,9 @@ __global__ __launch_bounds__(RNT) void k_onesweep(const uint64_t* __restrict__ k
     }
     __syncthreads();
 
-    const uint32_t tile_n = (uint32_t)min((uint64_t)RTILE, n - base);
+    const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, n - base);
 #pragma unroll 4
-    for (uint32_t s = threadIdx.x; s < tile_n; s += RNT) {
+    for (uint32_t s = threadIdx.x; s < tile_n; s += NT) {
         const uint64_t k = stage_k[s];
         const uint32_t dd = (uint32_t)((k >> shift) & mask);
         const uint64_t g = glob_base[dd] + (s - tile_start[dd]);
@@ -200,20 +222,67 @@ __global__ void k_unpack(const uint64_t* keys, const uint32_t* vals, uint64_t n,
     fo.weight[i] = __uint_as_float(vals[i]);
 }
 
+struct PassArgs {
+    const uint64_t* kin;
+    const uint32_t* vin;
+    uint64_t* kout;
+    uint32_t* vout;
+    uint64_t n;
+    uint32_t shift, dbits;
+    const uint64_t* off;
+    uint64_t* lookback;
+    uint32_t* counter;
+    uint32_t epoch;
+    uint32_t* status;
+    FinalOut fo;
+};
+
+template <int NT, int IPT>
+void launch_pass(Ctx& c, const PassArgs& a, bool final) {
+    constexpr int TILE = NT * IPT;
+    const uint64_t tiles = (a.n + TILE - 1) / TILE;
+    if (final)
+        hipLaunchKernelGGL((k_onesweep<NT, IPT, true>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin, a.vin, a.kout,
+                           a.vout, a.n, a.shift, a.dbits, a.off, a.lookback, a.counter, a.epoch, a.status, a.fo);
+    else
+        hipLaunchKernelGGL((k_onesweep<NT, IPT, false>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin, a.vin,
+                           a.kout, a.vout, a.n, a.shift, a.dbits, a.off, a.lookback, a.counter, a.epoch, a.status, a.fo);
+}
+
+struct Variant {
+    int nt, ipt;
+};
+// tile shapes available to the tuner; index 0 is the default
+constexpr Variant VARIANTS[] = {{256, 16}, {256, 8}, {512, 8}, {512, 16}, {1024, 8}, {256, 12}};
+constexpr int N_VARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
+
+void launch_variant(Ctx& c, int v, const PassArgs& a, bool final) {
+    switch (v) {
+    case 1: launch_pass<256, 8>(c, a, final); break;
+    case 2: launch_pass<512, 8>(c, a, final); break;
+    case 3: launch_pass<512, 16>(c, a, final); break;
+    case 4: launch_pass<1024, 8>(c, a, final); break;
+    case 5: launch_pass<256, 12>(c, a, final); break;
+    default: launch_pass<256, 16>(c, a, final); break;
+    }
+}
+
 }  // namespace
+
+int sort_variant_count() { return N_VARIANTS; }
 
 void radix_plan(uint32_t bits, uint32_t& passes, uint32_t& digit_bits) {
     passes = (bits + 7) / 8;
     digit_bits = passes ? (bits + passes - 1) / passes : 0;
 }
 
-void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t dbits, uint32_t passes,
-                 uint64_t* hist) {
+void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t bit_hi, uint32_t dbits,
+                 uint32_t passes, uint64_t* hist) {
     HIPCHK(hipMemsetAsync(hist, 0, (size_t)passes * RADIX * 8, c.stream));
     if (!n || !passes) return;
-    const uint32_t grid = (uint32_t)std::min<uint64_t>((n + RNT - 1) / RNT, 4096);
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((n + HNT - 1) / HNT, 4096);
     tstart(c, "sort_hist");
-    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(RNT), 0, c.stream, keys, n, bit_lo, dbits, passes, hist);
+    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(HNT), 0, c.stream, keys, n, bit_lo, bit_hi, dbits, passes, hist);
     tstop(c);
     HIPCHK(hipGetLastError());
 }
@@ -223,13 +292,15 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
     uint32_t passes, dbits;
     radix_plan(bit_hi > bit_lo ? bit_hi - bit_lo : 0, passes, dbits);
     if (passes > 8) raise(SNNC_EUNSUPPORTED, "radix sort over more than 64 bits");
+    const int variant = (c.sort_variant >= 0 && c.sort_variant < N_VARIANTS) ? c.sort_variant : 0;
+    const uint64_t tile = (uint64_t)VARIANTS[variant].nt * VARIANTS[variant].ipt;
     std::vector<void*> temps;
     auto cleanup = [&] {
         for (void* p : temps) dfree(c, p);
     };
     int cur = 0;
     try {
-        const uint64_t tiles = (n + RTILE - 1) / RTILE;
+        const uint64_t tiles = (n + tile - 1) / tile;
         std::vector<uint64_t> hh((size_t)passes * RADIX, 0);
         uint64_t* off = nullptr;
         if (passes && n) {
@@ -237,7 +308,7 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
             if (!hist) {
                 hist = dalloc_n<uint64_t>(c, (uint64_t)passes * RADIX);
                 temps.push_back(hist);
-                launch_hist(c, keys0, n, bit_lo, dbits, passes, hist);
+                launch_hist(c, keys0, n, bit_lo, bit_hi, dbits, passes, hist);
             }
             off = dalloc_n<uint64_t>(c, (uint64_t)passes * RADIX);
             temps.push_back(off);
@@ -279,17 +350,12 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
                 c.sort_epoch = 1;
             }
             const bool last = (li + 1 == live.size()) && final_out;
-            const uint32_t shift = bit_lo + p * dbits;
-            FinalOut fo = final_out ? *final_out : FinalOut{};
+            PassArgs a{kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, bit_lo + p * dbits,
+                       pass_width(bit_lo, bit_hi, dbits, p),
+                       off + (size_t)p * RADIX, (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status,
+                       final_out ? *final_out : FinalOut{}};
             tstart(c, last ? "sort_pass_final" : "sort_pass");
-            if (last)
-                hipLaunchKernelGGL(k_onesweep<true>, dim3((unsigned)tiles), dim3(RNT), 0, c.stream, kb[cur], vb[cur],
-                                   kb[cur ^ 1], vb[cur ^ 1], n, shift, dbits, off + (size_t)p * RADIX,
-                                   (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status, fo);
-            else
-                hipLaunchKernelGGL(k_onesweep<false>, dim3((unsigned)tiles), dim3(RNT), 0, c.stream, kb[cur], vb[cur],
-                                   kb[cur ^ 1], vb[cur ^ 1], n, shift, dbits, off + (size_t)p * RADIX,
-                                   (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status, fo);
+            launch_variant(c, variant, a, last);
             tstop(c);
             HIPCHK(hipGetLastError());
             cur ^= 1;
@@ -301,7 +367,6 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
             tstop(c);
             HIPCHK(hipGetLastError());
         }
-        sync(c);
     } catch (...) {
         cleanup();
         throw;
@@ -311,3 +376,22 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
 }
 
 }  // namespace snnc
+
+extern "C" snnc_status snnc_sort_pairs(snnc_ctx* ctx, uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
+                                       uint32_t* vals_tmp, uint64_t n, uint32_t bit_lo, uint32_t bit_hi,
+                                       int32_t* result_in_tmp) {
+    using namespace snnc;
+    if (!ctx || !result_in_tmp || (n && (!keys || !vals || !keys_tmp || !vals_tmp)) || bit_hi > 64 || bit_lo > bit_hi)
+        return SNNC_EINVAL;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        *result_in_tmp = radix_sort(*ctx, keys, vals, keys_tmp, vals_tmp, n, bit_lo, bit_hi, nullptr, nullptr);
+        uint32_t status = 0;
+        download(*ctx, &status, ctx->d_status, 4);
+        if (status) raise(SNNC_EDEVICE, "a device wait exceeded its bound");
+        return SNNC_OK;
+    } catch (const Error& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+}

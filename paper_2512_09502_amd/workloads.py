@@ -148,6 +148,67 @@ def balanced_collective(P: int = 1024, n_e: int = 160000, n_i: int = 40000, k_e:
     return b.script("balanced_collective", conns_per_host=(n_e + n_i) * (k_e + k_i))
 
 
+def served_requests(n_requests: int = 10000, n_pops: int = 64, pop_min: int = 1000, pop_max: int = 200000,
+                    size_min: float = 1e2, size_max: float = 1e7, seed: int = 1005) -> dict:
+    """A stream of Connect requests of uneven size on one host: 64
+    populations with log-uniform sizes in [1e3, 2e5]; request sizes S
+    log-uniform in [1e2, 1e7]; rule uniform over the five rules; source and
+    target populations uniform; autapse and multapse flags coin flips.
+    in-degree: n_t = min(N_t, S) targets, K = max(1, S // n_t); out-degree:
+    the mirror; total number: N = S; one-to-one: n = min(S, N_s, N_t);
+    Bernoulli: p ~ U(0.001, 0.2) on the first n_t = min(N_t, ceil(sqrt(S/p)))
+    targets and n_s = min(N_s, ceil(S / (p n_t))) sources.  Without
+    multapses the degree is capped at min(8192, candidates) and the total
+    number at half the pairs.  Poisson arrival times for an offered rate of
+    one request per unit time are in info['arrival']."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(math.log(pop_min), math.log(pop_max), size=n_pops)).astype(np.int64)
+    b = _Builder(1)
+    pops = [b.create(0, int(n)) for n in sizes]
+    rules = ["fixed_indegree", "fixed_outdegree", "fixed_total_number", "pairwise_bernoulli", "one_to_one"]
+    delay = {"kind": "normal", "mean": 1.5, "sd": 0.75, "lo": 0.1}
+    offered = 0
+    for _ in range(n_requests):
+        S = int(math.exp(rng.uniform(math.log(size_min), math.log(size_max))))
+        rule = rules[int(rng.integers(0, 5))]
+        i, j = int(rng.integers(0, n_pops)), int(rng.integers(0, n_pops))
+        aut, mult = bool(rng.integers(0, 2)), bool(rng.integers(0, 2))
+        h, fi, Ni = pops[i]
+        _, fj, Nj = pops[j]
+        conn = {"rule": rule, "autapses": aut, "multapses": mult}
+        if rule == "fixed_indegree":
+            nt = min(Nj, S)
+            K = max(1, S // nt)
+            if not mult:
+                K = min(K, 8192, Ni - 1)
+            src, tgt, conn["n"] = [(h, fi, Ni)], [(h, fj, nt)], K
+            offered += nt * K
+        elif rule == "fixed_outdegree":
+            ns = min(Ni, S)
+            K = max(1, S // ns)
+            if not mult:
+                K = min(K, 8192, Nj - 1)
+            src, tgt, conn["n"] = [(h, fi, ns)], [(h, fj, Nj)], K
+            offered += ns * K
+        elif rule == "fixed_total_number":
+            N = S if mult else min(S, Ni * Nj // 2)
+            src, tgt, conn["n"] = [(h, fi, Ni)], [(h, fj, Nj)], N
+            offered += N
+        elif rule == "one_to_one":
+            n = min(S, Ni, Nj)
+            src, tgt = [(h, fi, n)], [(h, fj, n)]
+            offered += n
+        else:
+            p = float(rng.uniform(0.001, 0.2))
+            nt = min(Nj, int(math.ceil(math.sqrt(S / p))))
+            ns = min(Ni, int(math.ceil(S / (p * nt))))
+            src, tgt, conn["p"] = [(h, fi, ns)], [(h, fj, nt)], p
+            offered += int(p * ns * nt)
+        b.connect(src, tgt, conn, {"weight": W_E if i % 2 == 0 else W_I, "delay": delay})
+    arrival = np.cumsum(rng.exponential(1.0, size=n_requests)).tolist()
+    return b.script("served_requests", offered=offered, arrival=arrival, pop_sizes=sizes.tolist())
+
+
 def random_tiny(seed: int, P: int | None = None) -> dict:
     """A small random script mixing all rules, flags, groups and segment
     layouts over a few virtual hosts, for property and parity tests."""

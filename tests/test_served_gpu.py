@@ -1,0 +1,99 @@
+"""GPU checks of served (batched) construction: a stream of uneven requests
+admitted against a resident budget gives bit-identical networks whether it
+is built per call or in fused batches, and both equal the oracle's build of
+the admitted requests."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2512_09502_amd as snnc
+from gpu_util import GEN_ARRAYS, PREP_ARRAYS, compare, log
+from paper_2512_09502_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _served_script(n=120, size_max=3e4, seed=7):
+    return W.served_requests(n_requests=n, n_pops=12, pop_min=200, pop_max=3000, size_min=10, size_max=size_max,
+                             seed=seed)
+
+
+def _build(script, mode, budget, batch=17, fuse=True):
+    import torch
+    torch.cuda.set_device(0)
+    net = snnc.Network(1, 0, script["seed"], script["dt"])
+    net.tune("fuse_batches", int(fuse))
+    if budget:
+        net.set_resident_budget(budget)
+    rejected, submitted = [], 0
+    for k, op in enumerate(script["ops"]):
+        if op[0] == "create":
+            net.create(op[1], op[2])
+            continue
+        _, src, tgt, conn, syn, alpha = op
+        fn = net.connect if mode == "per_call" else net.submit
+        try:
+            fn(src, tgt, conn, syn, alpha)
+            submitted += 1
+        except snnc.SnncError as e:
+            rejected.append((k, e.code))
+            continue
+        if mode == "batched" and submitted % batch == 0:
+            net.flush()
+    if mode == "batched":
+        net.flush()
+    gen = {k: net.array(k) for k in GEN_ARRAYS} if mode != "batched" else None
+    net.sync()
+    if mode == "batched":
+        gen = {k: net.array(k) for k in GEN_ARRAYS}
+    net.prepare()
+    out = {k: net.array(k) for k in PREP_ARRAYS}
+    out.update(gen)
+    net.close()
+    return out, rejected
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+def test_batched_equals_per_call_under_budget(fuse):
+    script = _served_script()
+    total = sum(int(op[3].get("n", 0)) for op in script["ops"] if op[0] == "connect")
+    budget = 14 * 200000 + 50000      # rejects part of the stream
+    a, rej_a = _build(script, "per_call", budget)
+    b, rej_b = _build(script, "batched", budget, fuse=fuse)
+    log(f"served: {len(rej_a)} rejected of {len(script['ops'])} ops, {a['src'].size} connections")
+    assert rej_a == rej_b
+    assert any(code == -3 for _, code in rej_a), "the budget should reject some requests"
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    # and the oracle on the admitted requests
+    kept = dict(script)
+    drop = {k for k, _ in rej_a}
+    kept["ops"] = [op for k, op in enumerate(script["ops"]) if k not in drop]
+    ref = oracle.run_script(kept, 0)
+    for k in GEN_ARRAYS + PREP_ARRAYS:
+        compare(k, b[k], ref.array(k), "served")
+
+
+def test_served_poll_and_flush_order():
+    import torch
+    torch.cuda.set_device(0)
+    script = _served_script(n=40, seed=9)
+    net = snnc.Network(1, 0, script["seed"], script["dt"])
+    ids = []
+    for op in script["ops"]:
+        if op[0] == "create":
+            net.create(op[1], op[2])
+        else:
+            _, src, tgt, conn, syn, alpha = op
+            try:
+                ids.append(net.submit(src, tgt, conn, syn, alpha))
+            except snnc.SnncError:
+                pass
+    assert not any(net.poll(i) for i in ids[:3])      # nothing flushed yet
+    net.flush()
+    net.sync()
+    assert all(net.poll(i) for i in ids)
+    net.prepare()
+    with pytest.raises(snnc.SnncError):
+        net.flush()
+    net.close()

@@ -1,0 +1,35 @@
+"""GPU checks of the radix sort on its own: every tile-shape variant against
+numpy's stable argsort on random keys (ragged sizes, narrow and wide bit
+ranges, many equal keys)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def net():
+    import torch
+    import paper_2512_09502_amd as snnc
+    torch.cuda.set_device(0)
+    n = snnc.Network(1, 0, 1, 0.1)
+    yield n
+    n.close()
+
+
+@pytest.mark.parametrize("variant", range(6))
+@pytest.mark.parametrize("n,lo,hi", [(1, 0, 8), (4095, 16, 50), (100003, 16, 50), (333333, 0, 64), (77777, 3, 9),
+                                     (250000, 16, 20)])
+def test_sort_pairs_matches_stable_argsort(net, variant, n, lo, hi):
+    import torch
+    rng = np.random.default_rng(n + variant + 31 * lo)
+    keys = rng.integers(0, 2**63, size=n, dtype=np.int64).view(np.uint64)
+    if hi - lo <= 8:
+        keys &= np.uint64(((1 << 64) - 1) ^ (((1 << 4) - 1) << lo))    # only half the digit values: many ties
+    vals = np.arange(n, dtype=np.int32)
+    net.tune("sort_variant", variant)
+    k, v = net.sort_pairs(torch.from_numpy(keys.view(np.int64)).cuda(), torch.from_numpy(vals).cuda(), lo, hi)
+    mask = np.uint64(((1 << (hi - lo)) - 1) << lo) if hi - lo < 64 else np.uint64((1 << 64) - 1)
+    order = np.argsort(keys & mask, kind="stable")
+    np.testing.assert_array_equal(v.cpu().numpy(), order.astype(np.int32))
+    np.testing.assert_array_equal(k.cpu().numpy().view(np.uint64), keys[order])
