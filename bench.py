@@ -73,6 +73,22 @@ def kernel_roofline(name: str, launches: int, ms: float, n_conn: int, n_passes: 
     return per_launch
 
 
+def measured_traffic(kernel: str, n_elem: int):
+    """HBM bytes per launch from the committed rocprofv3 counter table, or
+    None when the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        table = json.load(open(path))
+        entry = table[kernel]
+        src = open(os.path.join(ROOT, entry["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha1(src).hexdigest() != entry["sha1"]:
+        return None
+    return round(n_elem * (entry["read_bytes_per_elem"] + entry["write_bytes_per_elem"]))
+
+
 def cpu_baseline(script, budget_conns: float = 1.2e7):
     """The oracle (single-threaded C) on a bounded sample of the same
     workload: the Connect calls taken in script order while their declared
@@ -99,6 +115,113 @@ def cpu_baseline(script, budget_conns: float = 1.2e7):
                       f"fit {budget_conns:.0e} connections ({n} connections), then Prepare; {dt:.1f} s on one core"}
 
 
+def served(args):
+    """Served construction of a stream of uneven Connect requests against a
+    resident budget: throughput with all requests arriving at once, per call
+    and in fused batches, then per-request latency under open-loop Poisson
+    arrivals at half the measured batched capacity; each run ends with the
+    final sort and first-index array (Prepare)."""
+    import numpy as np
+    import torch
+
+    import paper_2512_09502_amd as snnc
+    from paper_2512_09502_amd import workloads as W
+
+    script = W.served_requests(n_requests=args.requests)
+    budget = int(args.budget_gib * 2**30)
+    creates = [op for op in script["ops"] if op[0] == "create"]
+    reqs = [op for op in script["ops"] if op[0] == "connect"]
+
+    def fresh():
+        net = snnc.Network(1, 0, script["seed"], script["dt"])
+        net.set_resident_budget(budget)
+        net.reserve(budget // 14)
+        for op in creates:
+            net.create(op[1], op[2])
+        return net
+
+    def run(mode):
+        net = fresh()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        admitted = 0
+        for k, op in enumerate(reqs):
+            _, src, tgt, conn, syn, alpha = op
+            try:
+                if mode == "per_call":
+                    net.connect(src, tgt, conn, syn, alpha)
+                else:
+                    net.submit(src, tgt, conn, syn, alpha)
+                admitted += 1
+            except snnc.SnncError as e:
+                if e.code != -3:
+                    raise
+            if mode == "batched" and (k + 1) % args.batch == 0:
+                net.flush()
+        net.flush() if mode == "batched" else None
+        net.sync()
+        t_gen = time.perf_counter() - t0
+        net.prepare()
+        net.sync()
+        t_all = time.perf_counter() - t0
+        n = net.count("src")
+        st = net.stats()
+        net.close()
+        return {"connections": n, "admitted": admitted, "rejected": len(reqs) - admitted, "gen_s": round(t_gen, 4),
+                "total_s": round(t_all, 4), "Gconn_s": round(n / t_all / 1e9, 4),
+                "gen_Gconn_s": round(n / t_gen / 1e9, 4), "sort_passes": st["sort_passes"]}
+
+    res_b = run("batched")
+    res_p = run("per_call")
+
+    # open-loop latency at half the batched capacity (requests per second of generation)
+    cap = res_b["admitted"] / res_b["gen_s"]
+    lam = 0.5 * cap
+    arrival = np.asarray(script["info"]["arrival"]) / lam
+    net = fresh()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, outstanding, k, last_batch = [], [], 0, None
+    while k < len(reqs) or outstanding:
+        now = time.perf_counter() - t0
+        while k < len(reqs) and arrival[k] <= now:
+            _, src, tgt, conn, syn, alpha = reqs[k]
+            try:
+                cid = net.submit(src, tgt, conn, syn, alpha)
+                outstanding.append((cid, arrival[k]))
+            except snnc.SnncError as e:
+                if e.code != -3:
+                    raise
+            k += 1
+        if outstanding and (last_batch is None or net.poll(last_batch)):
+            net.flush()
+            last_batch = outstanding[-1][0]
+        still = []
+        for cid, arr in outstanding:
+            if net.poll(cid):
+                lat.append(time.perf_counter() - t0 - arr)
+            else:
+                still.append((cid, arr))
+        outstanding = still
+        if k < len(reqs) and not outstanding:
+            time.sleep(max(0.0, min(arrival[k] - (time.perf_counter() - t0), 0.001)))
+    net.prepare()
+    net.close()
+    lat_ms = np.asarray(lat) * 1e3
+    out = {
+        "metric": "connections built+indexed/sec (Gconn/s) on 1 MI355X; p50/p99 Connect latency",
+        "value": res_b["Gconn_s"], "unit": "Gconn/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(1e3 * res_b["total_s"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32/u64 int + f64->f32 weights", "data": "synthetic",
+        "config": {"workload": script["name"], "requests": len(reqs), "budget_gib": args.budget_gib,
+                   "offered_connections": script["info"]["offered"], "batch": args.batch},
+        "batched": res_b, "per_call": res_p,
+        "latency": {"lambda_req_per_s": round(lam, 1), "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+                    "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "n": int(lat_ms.size)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +230,9 @@ def main():
     ap.add_argument("--workload", default="column8")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=10000)
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--batch", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the construction of one host's share needs no second GPU "
@@ -117,6 +243,8 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.workload == "served":
+        return served(args)
     script = workload(args.workload, args.scale)
 
     for _ in range(args.warmup):
@@ -155,8 +283,8 @@ def main():
         avg_ms = ms / launches
         achieved = per / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": name,
-                "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": per}
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, n_conn),
+                "kernel": name, "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": per}
 
     out = {
         "metric": "connections built+indexed/sec (Gconn/s) on 1 MI355X",

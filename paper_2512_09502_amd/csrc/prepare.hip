@@ -57,11 +57,61 @@ __device__ __forceinline__ void source_of(const Lookup& L, const uint32_t* g_src
     bit = (uint64_t)c.a * L.G + L.host_base[host] + local;
 }
 
-__global__ __launch_bounds__(PNT) void k_mark(Lookup L, const uint32_t* g_src, uint64_t lo, uint64_t n, uint32_t* bits) {
-    for (uint64_t i = lo + (uint64_t)blockIdx.x * PNT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * PNT) {
+// The same with a per-thread cache of the current call and source segment:
+// a thread walks increasing positions, so the binary searches run only when
+// the position leaves the cached call or the ordinal leaves the cached segment.
+struct SourceCursor {
+    uint64_t call_lo = 1, call_hi = 0;   // cached call covers [call_lo, call_hi)
+    CallD call{};
+    uint64_t seg_lo = 1, seg_hi = 0;     // cached segment covers ordinals [seg_lo, seg_hi)
+    uint32_t seg_host = 0, seg_first = 0;
+    uint64_t bit_base = 0;               // a G + host_base[seg_host] + seg_first - seg_lo
+
+    __device__ __forceinline__ void at(const Lookup& L, uint64_t i, uint32_t ord, uint32_t& host, uint32_t& local,
+                                       uint64_t& bit) {
+        if (i < call_lo || i >= call_hi) {
+            const uint32_t k = find_call(L.calls, L.ncalls, i);
+            call = L.calls[k];
+            call_lo = call.gen_begin;
+            call_hi = k + 1 < L.ncalls ? L.calls[k + 1].gen_begin : ~0ull;
+            seg_lo = 1;
+            seg_hi = 0;
+        }
+        if (ord < seg_lo || ord >= seg_hi) {
+            uint32_t a = 0, b = call.nS;
+            while (b - a > 1) {
+                const uint32_t m = (a + b) >> 1;
+                if (call.S[m].ord_begin <= ord) a = m; else b = m;
+            }
+            const SegD s = call.S[a];
+            seg_lo = s.ord_begin;
+            seg_hi = a + 1 < call.nS ? call.S[a + 1].ord_begin : ~0ull;
+            seg_host = s.host;
+            seg_first = s.first;
+            bit_base = (uint64_t)call.a * L.G + L.host_base[s.host] + s.first - s.ord_begin;
+        }
+        host = seg_host;
+        local = seg_first + (uint32_t)(ord - seg_lo);
+        bit = bit_base + ord;
+    }
+};
+
+// contiguous range of positions for workgroup b of g over n (multiple of the block size)
+__device__ __forceinline__ void block_range(uint64_t n, uint64_t& lo, uint64_t& hi) {
+    const uint64_t per = ((n + gridDim.x - 1) / gridDim.x + PNT - 1) / PNT * PNT;
+    lo = (uint64_t)blockIdx.x * per;
+    hi = lo + per < n ? lo + per : n;
+}
+
+__global__ __launch_bounds__(PNT) void k_mark(Lookup L, const uint32_t* g_src, uint64_t first, uint64_t end,
+                                              uint32_t* bits) {
+    uint64_t lo, hi;
+    block_range(end - first, lo, hi);
+    SourceCursor cur;
+    for (uint64_t i = first + lo + threadIdx.x; i < first + hi; i += PNT) {
         uint32_t h, l;
         uint64_t bit;
-        source_of(L, g_src, i, h, l, bit);
+        cur.at(L, i, g_src[i], h, l, bit);
         if (h != L.PL) atomicOr(bits + (bit >> 5), 1u << (bit & 31));
     }
 }
@@ -118,14 +168,17 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
     for (uint32_t i = threadIdx.x; i < passes * 256; i += PNT) h[i] = 0;
     __syncthreads();
     const uint32_t dmask = (1u << dbits) - 1;
-    for (uint64_t base = (uint64_t)blockIdx.x * PNT; base < n; base += (uint64_t)gridDim.x * PNT) {
+    uint64_t lo, hi;
+    block_range(n, lo, hi);
+    SourceCursor cur;
+    for (uint64_t base = lo; base < hi; base += PNT) {
         const uint64_t i = base + threadIdx.x;
-        const bool valid = i < n;
+        const bool valid = i < hi;
         uint64_t key = 0;
         if (valid) {
             uint32_t host, local;
             uint64_t bit;
-            source_of(L, g_src, i, host, local, bit);
+            cur.at(L, i, g_src[i], host, local, bit);
             const uint64_t src2 = host == L.PL ? local : (uint64_t)M_local + rank_of(bits, word_rank, bit);
             key = (src2 << tgt_shift) | ((uint64_t)g_tgt[i] << 16) | g_delay[i];
             keys[i] = key;
@@ -139,11 +192,26 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
 }
 
 // first-index array: row_ptr[r] = first position with source >= r
+// Each thread takes 4 consecutive positions with one 16-byte load; position
+// i closes the rows (src[i-1], src[i]] (position n closes the rest).
 __global__ __launch_bounds__(PNT) void k_csr(const int32_t* src, uint64_t n, uint64_t n_rows, uint64_t* row_ptr) {
-    for (uint64_t i = (uint64_t)blockIdx.x * PNT + threadIdx.x; i <= n; i += (uint64_t)gridDim.x * PNT) {
-        const int64_t prev = i == 0 ? -1 : (int64_t)src[i - 1];
-        const int64_t cur = i == n ? (int64_t)n_rows : (int64_t)src[i];
-        for (int64_t r = prev + 1; r <= cur; ++r) row_ptr[r] = i;
+    const uint64_t quads = n / 4 + 1;   // the last quad holds the tail and position n
+    for (uint64_t q = (uint64_t)blockIdx.x * PNT + threadIdx.x; q < quads; q += (uint64_t)gridDim.x * PNT) {
+        const uint64_t i0 = q * 4;
+        int64_t v[4];
+        if (i0 + 4 <= n) {
+            const int4 x = *reinterpret_cast<const int4*>(src + i0);
+            v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+        } else {
+            for (int k = 0; k < 4; ++k) v[k] = i0 + k < n ? (int64_t)src[i0 + k] : (int64_t)n_rows;
+        }
+        int64_t prev = i0 == 0 ? -1 : (int64_t)src[i0 - 1];
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t i = i0 + k;
+            if (i > n) break;
+            for (int64_t r = prev + 1; r <= v[k]; ++r) row_ptr[r] = i;
+            prev = v[k];
+        }
     }
 }
 
@@ -328,7 +396,7 @@ void prepare_all(Ctx& c) {
         }
         for (auto& r : mark_ranges) {
             tstart(c, "prep_mark");
-            hipLaunchKernelGGL(k_mark, dim3(grid_for(r.second - r.first)), dim3(PNT), 0, c.stream, L, c.g_src, r.first,
+            hipLaunchKernelGGL(k_mark, dim3(grid_for(r.second - r.first, 8192)), dim3(PNT), 0, c.stream, L, c.g_src, r.first,
                                r.second, bits);
             tstop(c);
             HIPCHK(hipGetLastError());
@@ -363,10 +431,7 @@ void prepare_all(Ctx& c) {
         if (sbits + tbits > 48) raise(SNNC_EUNSUPPORTED, "source and target ids need more than 48 key bits");
         uint32_t passes, dbits;
         radix_plan(sbits + tbits, passes, dbits);
-        int32_t* o_src = result<int32_t>(c, SNNC_SRC, N);
-        int32_t* o_tgt = result<int32_t>(c, SNNC_TGT, N);
-        uint16_t* o_delay = result<uint16_t>(c, SNNC_DELAY, N);
-        float* o_weight = result<float>(c, SNNC_WEIGHT, N);
+        int32_t* o_src = nullptr;
         if (N) {
             uint64_t* keys0 = static_cast<uint64_t*>(tmp(N * 8));
             uint64_t* hist = static_cast<uint64_t*>(tmp(8 * 256 * 8));
@@ -382,10 +447,20 @@ void prepare_all(Ctx& c) {
             dfree(c, c.g_delay); c.g_delay = nullptr;
             uint64_t* keys1 = static_cast<uint64_t*>(tmp(N * 8));
             uint32_t* vals1 = static_cast<uint32_t*>(tmp(N * 4));
+            // outputs allocated only now, so they reuse the memory just released
+            o_src = result<int32_t>(c, SNNC_SRC, N);
+            int32_t* o_tgt = result<int32_t>(c, SNNC_TGT, N);
+            uint16_t* o_delay = result<uint16_t>(c, SNNC_DELAY, N);
+            float* o_weight = result<float>(c, SNNC_WEIGHT, N);
             FinalOut fo{o_src, o_tgt, o_delay, o_weight, 16 + tbits, (1ull << tbits) - 1};
             if (tbits == 0) fo.tgt_mask = 0;
             radix_sort(c, keys0, reinterpret_cast<uint32_t*>(c.g_weight), keys1, vals1, N, 16, 16 + sbits + tbits,
                        hist, &fo);
+        } else {
+            o_src = result<int32_t>(c, SNNC_SRC, 0);
+            result<int32_t>(c, SNNC_TGT, 0);
+            result<uint16_t>(c, SNNC_DELAY, 0);
+            result<float>(c, SNNC_WEIGHT, 0);
         }
         dfree(c, c.g_src); c.g_src = nullptr;
         dfree(c, c.g_tgt); c.g_tgt = nullptr;
@@ -396,7 +471,7 @@ void prepare_all(Ctx& c) {
         // ---------------------------------------------------------- 5 first-index array
         uint64_t* row_ptr = result<uint64_t>(c, SNNC_ROW_PTR, n_rows + 1);
         tstart(c, "prep_csr");
-        hipLaunchKernelGGL(k_csr, dim3(grid_for(N + 1)), dim3(PNT), 0, c.stream, o_src, N, n_rows, row_ptr);
+        hipLaunchKernelGGL(k_csr, dim3(grid_for(N / 4 + 1, 16384)), dim3(PNT), 0, c.stream, o_src, N, n_rows, row_ptr);
         tstop(c);
         HIPCHK(hipGetLastError());
 
