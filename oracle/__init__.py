@@ -29,6 +29,7 @@ ARRAYS = {
     "src": (10, np.int32), "tgt": (11, np.int32), "delay": (12, np.uint16),
     "weight": (13, np.float32), "row_ptr": (14, np.uint64),
     "r_off": (20, np.uint64), "r_val": (21, np.int32), "img_base": (22, np.int64),
+    "l_val": (23, np.int32),
     "s_off": (30, np.uint64), "s_val": (31, np.int32), "tp_ptr": (32, np.uint64),
     "t_val": (33, np.uint32), "p_val": (34, np.uint32),
     "groups": (40, np.int32), "h_off": (41, np.uint64), "h_val": (42, np.int32),
@@ -77,6 +78,7 @@ def lib():
         L.orc_connect.argtypes = conn_args
         L.orc_declare.argtypes = conn_args
         L.orc_prepare.argtypes = [vp]
+        L.orc_set_map_policy.argtypes = [vp, ctypes.c_int, ctypes.c_int, dbl]
         L.orc_len.argtypes = [vp, ctypes.c_int]
         L.orc_len.restype = i64
         L.orc_copy.argtypes = [vp, ctypes.c_int, vp, u64]
@@ -84,6 +86,8 @@ def lib():
         L.orc_neurons.restype = u32
         L.orc_call_range.argtypes = [vp, u32, u32, u64, u64, vp, vp, vp, vp, vp, u64]
         L.orc_call_range.restype = i64
+        L.orc_call_element.argtypes = [vp, u32, u64, vp, vp, vp, vp, vp]
+        L.orc_call_element.restype = ctypes.c_int
         L.orc_sort_csr.argtypes = [u64, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp]
         L.orc_transpose_lists.argtypes = [u32, vp, vp, u32, vp, vp, vp]
         L.orc_transpose_lists.restype = u64
@@ -214,6 +218,11 @@ class OracleNet:
     def declare(self, src, tgt, conn, syn, alpha=-1) -> int:
         return self._conn(lib().orc_declare, src, tgt, conn, syn, alpha)
 
+    def set_map_policy(self, numbering: int, sources: int, xi: float = 1.0):
+        """numbering: 0 canonical, 1 in call order; sources: 0 used,
+        1 threshold heuristic with xi, 2 all passed sources."""
+        self._check(lib().orc_set_map_policy(self._h, int(numbering), int(sources), float(xi)))
+
     def prepare(self):
         self._check(lib().orc_prepare(self._h))
 
@@ -228,6 +237,19 @@ class OracleNet:
         out = np.zeros(n, dt)
         self._check(lib().orc_copy(self._h, which, _ptr(out), out.nbytes))
         return out
+
+    def element(self, call_id: int, e: int):
+        """One element of a call computed on its own: None if it is not a
+        connection; raises for rules whose elements depend on each other."""
+        so, th, tl = (ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32())
+        w, d = ctypes.c_float(), ctypes.c_uint16()
+        r = lib().orc_call_element(self._h, call_id, e, ctypes.byref(so), ctypes.byref(th), ctypes.byref(tl),
+                                   ctypes.byref(w), ctypes.byref(d))
+        if r < 0:
+            raise OracleError(-1, "element not computable on its own for this call")
+        if r == 0:
+            return None
+        return {"src": so.value, "tgt_host": th.value, "tgt": tl.value, "weight": w.value, "delay": d.value}
 
     def call_range(self, call_id: int, host: int, lo: int, hi: int, cap: int) -> dict:
         """Draws of one call on one host's share, primary ordinal in [lo, hi)."""
@@ -248,6 +270,8 @@ def run_script(script, P_local: int, declare_only: bool = False, skip_invalid: b
     P_local.  With ``skip_invalid`` a rejected connect is recorded in
     ``net.rejected`` as (op index, status) and the replay goes on."""
     net = OracleNet(script["P"], P_local, script["seed"], script["dt"])
+    if script.get("map_policy") is not None:
+        net.set_map_policy(*script["map_policy"])
     net.rejected = []
     for k, op in enumerate(script["ops"]):
         if op[0] == "create":

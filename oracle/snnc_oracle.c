@@ -190,10 +190,15 @@ typedef struct orc_net {
     uint64_t n_gen, cap_gen;
     uint64_t* call_off;
     int prepared;
+    /* map policy: image numbering (0 canonical, 1 in call order) and which
+     * sources get images (0 used, 1 threshold heuristic, 2 all passed) */
+    int numbering, img_sources;
+    double xi;
     /* image map */
     uint32_t n_a;
     uint64_t* r_off;
     int32_t* r_val;
+    int32_t* l_val;
     int64_t* img_base;
     uint64_t n_img;
     /* sorted connections and first-index array */
@@ -235,12 +240,22 @@ orc_net* orc_new(uint32_t P, uint32_t P_local, uint32_t seed, double dt)
     orc_net* net = (orc_net*)calloc(1, sizeof(orc_net));
     net->P = P; net->P_local = P_local; net->seed = seed; net->dt = dt;
     net->M = (uint32_t*)calloc(P, sizeof(uint32_t));
+    net->xi = 1.0;
     return net;
+}
+
+int orc_set_map_policy(orc_net* net, int numbering, int img_sources, double xi)
+{
+    if (net->prepared) return fail(net, ORC_ESTATE, "map policy after prepare");
+    if (numbering < 0 || numbering > 1 || img_sources < 0 || img_sources > 2 || !(xi >= 0.0) || xi > 1e300)
+        return fail(net, ORC_EINVAL, "bad map policy");
+    net->numbering = numbering; net->img_sources = img_sources; net->xi = xi;
+    return ORC_OK;
 }
 
 static void free_prepared(orc_net* net)
 {
-    free(net->r_off); free(net->r_val); free(net->img_base);
+    free(net->r_off); free(net->r_val); free(net->l_val); free(net->img_base);
     free(net->s_src); free(net->s_tgt); free(net->s_delay); free(net->s_weight); free(net->row_ptr);
     free(net->S_off); free(net->S_val); free(net->TP_ptr); free(net->T_val); free(net->P_val);
     free(net->groups); free(net->H_off); free(net->H_val); free(net->I_val);
@@ -693,17 +708,6 @@ static uint64_t sort_unique_i32(int32_t* v, uint64_t n)
     return m;
 }
 
-/* first position with v[pos] >= x (v sorted ascending) */
-static uint64_t lower_bound_i32(const int32_t* v, uint64_t n, int32_t x)
-{
-    uint64_t a = 0, b = n;
-    while (a < b) {
-        uint64_t m = (a + b) / 2;
-        if (v[m] < x) a = m + 1; else b = m;
-    }
-    return a;
-}
-
 /* growable int32 list */
 typedef struct { int32_t* v; uint64_t n, cap; } ilist;
 
@@ -799,6 +803,75 @@ static int32_t max_alpha(const orc_net* net)
     return a;
 }
 
+/* (R, L) map of one (alpha+1, sigma): R sorted ascending except while a
+ * call appends to it. */
+typedef struct { int32_t* r; int32_t* l; uint64_t n, cap; } omap;
+
+static void omap_append(omap* m, int32_t r, int32_t l)
+{
+    if (m->n == m->cap) {
+        m->cap = m->cap ? 2 * m->cap : 16;
+        m->r = (int32_t*)realloc(m->r, m->cap * sizeof(int32_t));
+        m->l = (int32_t*)realloc(m->l, m->cap * sizeof(int32_t));
+    }
+    m->r[m->n] = r; m->l[m->n] = l; m->n++;
+}
+
+/* position of r among the first n (sorted) entries, or -1: binary search */
+static int64_t omap_find(const omap* m, uint64_t n, int32_t r)
+{
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) / 2;
+        if (m->r[mid] < r) lo = mid + 1; else hi = mid;
+    }
+    return (lo < n && m->r[lo] == r) ? (int64_t)lo : -1;
+}
+
+static void omap_sort(omap* m)   /* insertion sort by R (carries L) */
+{
+    for (uint64_t i = 1; i < m->n; i++) {
+        int32_t r = m->r[i], l = m->l[i];
+        uint64_t j = i;
+        while (j > 0 && m->r[j - 1] > r) { m->r[j] = m->r[j - 1]; m->l[j] = m->l[j - 1]; j--; }
+        m->r[j] = r; m->l[j] = l;
+    }
+}
+
+/* Number of neurons of a set that live on `host`. */
+static uint64_t set_count_on(const orc_set* s, uint32_t host)
+{
+    uint64_t n = 0;
+    for (uint32_t i = 0; i < s->nseg; i++)
+        if (s->seg[i].host == host) n += s->seg[i].n;
+    return n;
+}
+
+/* Does call c map only its used sources onto host tau (flagging), or all the
+ * sources passed to it?  Policy 0 always flags, policy 2 never does.  Policy 1
+ * is the threshold heuristic of the point-to-point creation subsection:
+ * flag when the rule draws its source indices at random and the estimated
+ * number of new connections on tau divided by the number of sources is below
+ * xi.  Estimates (reading): fixed in-degree K N_t, fixed total number N (its
+ * targets live on tau), pairwise Bernoulli p N_s N_t, with N_t the call's
+ * targets on tau and N_s all its sources; one-to-one and fixed out-degree use
+ * every source and are never flagged. */
+static int flag_sources(const orc_net* net, const orc_call* c, uint32_t tau)
+{
+    if (net->img_sources == 0) return 1;
+    if (net->img_sources == 2) return 0;
+    const double n_s = (double)c->S.total, n_t = (double)set_count_on(&c->T, tau);
+    if (n_s == 0.0) return 1;
+    double est;
+    switch (c->rule) {
+    case R_INDEGREE: est = (double)c->n * n_t; break;
+    case R_TOTAL: est = n_t > 0.0 ? (double)c->n : 0.0; break;
+    case R_BERNOULLI: est = c->p * n_s * n_t; break;
+    default: return 0;
+    }
+    return est / n_s < net->xi;
+}
+
 int orc_prepare(orc_net* net)
 {
     if (net->prepared) return fail(net, ORC_ESTATE, "prepare called twice");
@@ -810,53 +883,94 @@ int orc_prepare(orc_net* net)
     for (uint32_t c = 0; c < net->ncalls; c++) net->call_off[c] = net->calls[c].gen_begin;
     net->call_off[net->ncalls] = N;
 
-    /* --- image map (flag used sources, sort-unique, number the images) ---
-     * Reading: every remote source used by a local connection of a group-
-     * alpha call gets one image per (alpha+1, sigma); the images are numbered
-     * after all local neurons, in (alpha+1, sigma, source id) order. */
+    /* --- image maps (R, L) per (alpha+1, sigma), built call by call in the
+     * order of the point-to-point creation subsection: for every call with
+     * targets on P_local and every source host sigma != P_local (ascending),
+     * flag b over the call's sources on sigma (the used ones, or all of them
+     * when the call is not flagged, see flag_sources), compact to u~ / s~,
+     * sort by s~, search each s~_j in R: found -> its L; not found ->
+     * append (s~_j, M), M += 1; re-sort the map by R.  M starts at the
+     * number of local neurons (reading: all Create calls precede the remote
+     * connections).  With the canonical numbering the finished maps are
+     * renumbered after the local neurons in (alpha+1, sigma, s) order. --- */
     net->n_a = (uint32_t)(max_alpha(net) + 2);
     const uint32_t n_a = net->n_a;
-    ilist* used = (ilist*)calloc((size_t)n_a * P, sizeof(ilist));
+    omap* maps = (omap*)calloc((size_t)n_a * P, sizeof(omap));
     uint32_t* conn_host = (uint32_t*)malloc((N ? N : 1) * sizeof(uint32_t));
     uint32_t* conn_local = (uint32_t*)malloc((N ? N : 1) * sizeof(uint32_t));
     uint32_t* conn_a = (uint32_t*)malloc((N ? N : 1) * sizeof(uint32_t));
+    uint32_t M_next = M_local;
     for (uint32_t c = 0; c < net->ncalls; c++) {
         const orc_call* cl = &net->calls[c];
         for (uint64_t i = cl->gen_begin; i < cl->gen_begin + cl->gen_count; i++) {
-            uint32_t h, l;
-            set_at(&cl->S, net->g_src[i], &h, &l);
-            conn_host[i] = h; conn_local[i] = l; conn_a[i] = (uint32_t)(cl->alpha + 1);
-            if (h != PL) ilist_push(&used[(size_t)conn_a[i] * P + h], (int32_t)l);
+            set_at(&cl->S, net->g_src[i], &conn_host[i], &conn_local[i]);
+            conn_a[i] = (uint32_t)(cl->alpha + 1);
         }
+        if (set_count_on(&cl->T, PL) == 0 || cl->S.total == 0) continue;
+        const int flagged = flag_sources(net, cl, PL);
+        unsigned char* b = (unsigned char*)calloc(cl->S.total, 1);
+        if (flagged) {
+            for (uint64_t i = cl->gen_begin; i < cl->gen_begin + cl->gen_count; i++) b[net->g_src[i]] = 1;
+        } else {
+            memset(b, 1, cl->S.total);
+        }
+        const uint32_t a = (uint32_t)(cl->alpha + 1);
+        for (uint32_t sigma = 0; sigma < P; sigma++) {
+            if (sigma == PL) continue;
+            ilist st = {0};   /* s~ : flagged sources on sigma */
+            uint64_t ord = 0;
+            for (uint32_t k = 0; k < cl->S.nseg; k++) {
+                const orc_seg* sg = &cl->S.seg[k];
+                for (uint32_t x = 0; x < sg->n; x++, ord++)
+                    if (sg->host == sigma && b[ord]) ilist_push(&st, (int32_t)(sg->first + x));
+            }
+            if (st.n == 0) { free(st.v); continue; }
+            qsort(st.v, st.n, sizeof(int32_t), cmp_i32);
+            omap* m = &maps[(size_t)a * P + sigma];
+            const uint64_t n_before = m->n;
+            for (uint64_t j = 0; j < st.n; j++) {
+                if (omap_find(m, n_before, st.v[j]) >= 0) continue;   /* already has an image */
+                omap_append(m, st.v[j], (int32_t)M_next);
+                M_next++;
+            }
+            omap_sort(m);
+            free(st.v);
+        }
+        free(b);
     }
     net->r_off = (uint64_t*)calloc((size_t)n_a * P + 1, sizeof(uint64_t));
     net->img_base = (int64_t*)calloc((size_t)n_a * P, sizeof(int64_t));
     uint64_t total = 0;
     for (uint64_t k = 0; k < (uint64_t)n_a * P; k++) {
-        used[k].n = sort_unique_i32(used[k].v, used[k].n);
         net->r_off[k] = total;
-        net->img_base[k] = (int64_t)M_local + (int64_t)total;
-        total += used[k].n;
+        total += maps[k].n;
     }
     net->r_off[(size_t)n_a * P] = total;
     net->n_img = total;
     net->r_val = (int32_t*)malloc((total ? total : 1) * sizeof(int32_t));
-    for (uint64_t k = 0; k < (uint64_t)n_a * P; k++)
-        if (used[k].n) memcpy(net->r_val + net->r_off[k], used[k].v, used[k].n * sizeof(int32_t));
+    net->l_val = (int32_t*)malloc((total ? total : 1) * sizeof(int32_t));
+    for (uint64_t k = 0; k < (uint64_t)n_a * P; k++) {
+        for (uint64_t i = 0; i < maps[k].n; i++) {
+            net->r_val[net->r_off[k] + i] = maps[k].r[i];
+            if (net->numbering == 0) maps[k].l[i] = (int32_t)(M_local + net->r_off[k] + i);
+            net->l_val[net->r_off[k] + i] = maps[k].l[i];
+        }
+        net->img_base[k] = net->numbering == 0 ? (int64_t)M_local + (int64_t)net->r_off[k] : -1;
+    }
 
-    /* --- remap: source' = local id, or the image index of the source --- */
+    /* --- remap: source' = local id, or the image index L of the source --- */
     int32_t* src2 = (int32_t*)malloc((N ? N : 1) * sizeof(int32_t));
     for (uint64_t i = 0; i < N; i++) {
         if (conn_host[i] == PL) {
             src2[i] = (int32_t)conn_local[i];
         } else {
-            size_t k = (size_t)conn_a[i] * P + conn_host[i];
-            uint64_t pos = lower_bound_i32(used[k].v, used[k].n, (int32_t)conn_local[i]);
-            src2[i] = (int32_t)(net->img_base[k] + (int64_t)pos);
+            const omap* m = &maps[(size_t)conn_a[i] * P + conn_host[i]];
+            int64_t pos = omap_find(m, m->n, (int32_t)conn_local[i]);
+            src2[i] = pos >= 0 ? m->l[pos] : -1;   /* -1 is not reached: every remote source has an image */
         }
     }
-    for (uint64_t k = 0; k < (uint64_t)n_a * P; k++) free(used[k].v);
-    free(used);
+    for (uint64_t k = 0; k < (uint64_t)n_a * P; k++) { free(maps[k].r); free(maps[k].l); }
+    free(maps);
     free(conn_host); free(conn_local); free(conn_a);
 
     /* --- source-major sort and first-index array --- */
@@ -870,20 +984,27 @@ int orc_prepare(orc_net* net)
                  net->s_src, net->s_tgt, net->s_delay, net->s_weight, net->row_ptr);
     free(src2);
 
-    /* --- point-to-point send lists.  For each target host tau, regenerate
-     * the draws of every alpha = -1 call for tau's share (the source-process
-     * variant of RemoteConnect) and keep the sources on P_local:
-     * S_tau = their sorted unique local ids.  Then T/P: for each local s,
+    /* --- point-to-point send lists.  For each target host tau and every
+     * alpha = -1 call with targets on tau: when the call is flagged for tau,
+     * regenerate its draws for tau's share (the source-process variant of
+     * RemoteConnect) and keep the sources on P_local; otherwise take all its
+     * sources on P_local.  S_tau = their sorted unique local ids.  Then T/P: for each local s,
      * the (tau, position of s in S_tau), tau ascending. --- */
     ilist* S = (ilist*)calloc(P, sizeof(ilist));
     for (uint32_t tau = 0; tau < P; tau++) {
         if (tau == PL) continue;
         for (uint32_t c = 0; c < net->ncalls; c++) {
             const orc_call* cl = &net->calls[c];
-            if (cl->alpha != -1) continue;
-            mark_ctx mctx = { &S[tau], PL, cl };
-            sink_t sink = { emit_mark_local_source, &mctx };
-            gen_call(net, cl, tau, 0, UINT64_MAX, sink);
+            if (cl->alpha != -1 || set_count_on(&cl->T, tau) == 0) continue;
+            if (flag_sources(net, cl, tau)) {
+                mark_ctx mctx = { &S[tau], PL, cl };
+                sink_t sink = { emit_mark_local_source, &mctx };
+                gen_call(net, cl, tau, 0, UINT64_MAX, sink);
+            } else {   /* not flagged: every source of the call on P_local */
+                for (uint32_t k = 0; k < cl->S.nseg; k++)
+                    if (cl->S.seg[k].host == PL)
+                        for (uint32_t x = 0; x < cl->S.seg[k].n; x++) ilist_push(&S[tau], (int32_t)(cl->S.seg[k].first + x));
+            }
         }
         S[tau].n = sort_unique_i32(S[tau].v, S[tau].n);
     }
@@ -951,7 +1072,7 @@ int orc_prepare(orc_net* net)
                 int32_t img = -1;
                 if (sigma != PL) {
                     for (uint64_t i = 0; i < rn; i++)
-                        if (R[i] == hv) { img = (int32_t)(net->img_base[rk] + (int64_t)i); break; }
+                        if (R[i] == hv) { img = net->l_val[net->r_off[rk] + i]; break; }
                 }
                 net->I_val[net->H_off[k] + j] = img;
             }
@@ -983,7 +1104,7 @@ int orc_prepare(orc_net* net)
 enum {
     A_GEN_SRC = 0, A_GEN_TGT = 1, A_GEN_DELAY = 2, A_GEN_WEIGHT = 3, A_GEN_E = 4, A_CALL_OFF = 5,
     A_SRC = 10, A_TGT = 11, A_DELAY = 12, A_WEIGHT = 13, A_ROW_PTR = 14,
-    A_R_OFF = 20, A_R_VAL = 21, A_IMG_BASE = 22,
+    A_R_OFF = 20, A_R_VAL = 21, A_IMG_BASE = 22, A_L_VAL = 23,
     A_S_OFF = 30, A_S_VAL = 31, A_TP_PTR = 32, A_T_VAL = 33, A_P_VAL = 34,
     A_GROUPS = 40, A_H_OFF = 41, A_H_VAL = 42, A_I_VAL = 43, A_GQ_PTR = 44, A_G_VAL = 45, A_Q_VAL = 46
 };
@@ -1002,7 +1123,7 @@ int64_t orc_len(const orc_net* net, int which)
     case A_SRC: case A_TGT: case A_DELAY: case A_WEIGHT: return (int64_t)net->n_gen;
     case A_ROW_PTR: return (int64_t)net->n_rows + 1;
     case A_R_OFF: return (int64_t)net->n_a * net->P + 1;
-    case A_R_VAL: return (int64_t)net->n_img;
+    case A_R_VAL: case A_L_VAL: return (int64_t)net->n_img;
     case A_IMG_BASE: return (int64_t)net->n_a * net->P;
     case A_S_OFF: return net->P + 1;
     case A_S_VAL: case A_T_VAL: case A_P_VAL: return (int64_t)net->S_off[net->P];
@@ -1032,6 +1153,7 @@ static const void* array_ptr(const orc_net* net, int which, size_t* elem)
     case A_R_OFF: *elem = 8; return net->r_off;
     case A_R_VAL: *elem = 4; return net->r_val;
     case A_IMG_BASE: *elem = 8; return net->img_base;
+    case A_L_VAL: *elem = 4; return net->l_val;
     case A_S_OFF: *elem = 8; return net->S_off;
     case A_S_VAL: *elem = 4; return net->S_val;
     case A_TP_PTR: *elem = 8; return net->TP_ptr;
@@ -1098,6 +1220,99 @@ int64_t orc_call_range(const orc_net* net, uint32_t call_id, uint32_t host, uint
     sink_t sink = { emit_range, &ctx };
     gen_call(net, &net->calls[call_id], host, lo, hi, sink);
     return ctx.overflow ? -1 : (int64_t)ctx.n;
+}
+
+/* One element of a call, computed on its own, for the rules whose elements
+ * do not depend on each other: fixed in-degree and out-degree with
+ * multapses (element e = unit * K + j), fixed total number with autapses and
+ * multapses (candidate e), pairwise Bernoulli (pair e) and one-to-one (e).
+ * Returns 1 and the element's values when the element is a connection, 0
+ * when it is not (a pair that does not connect, a skipped autapse), -1 for
+ * a rule or flag combination where elements depend on each other. */
+int orc_call_element(const orc_net* net, uint32_t call_id, uint64_t e, uint32_t* src_ord, uint32_t* tgt_host,
+                     uint32_t* tgt_local, float* weight, uint16_t* delay)
+{
+    if (call_id >= net->ncalls) return -1;
+    const orc_call* c = &net->calls[call_id];
+    const uint64_t ns = c->S.total, nt = c->T.total;
+    uint64_t s = 0, t = 0;
+    uint32_t h, l, h2, l2;
+    switch (c->rule) {
+    case R_INDEGREE: {
+        if (!c->multapses || c->n == 0) return -1;
+        t = e / c->n;
+        if (t >= nt) return -1;
+        set_at(&c->T, t, &h2, &l2);
+        int64_t self_pos = c->autapses ? -1 : set_pos(&c->S, h2, l2);
+        uint64_t pick;
+        draw_k(net, c, e, 1, ns, self_pos, &pick);     /* one draw with element index e */
+        s = pick;
+        break;
+    }
+    case R_OUTDEGREE: {
+        if (!c->multapses || c->n == 0) return -1;
+        s = e / c->n;
+        if (s >= ns) return -1;
+        set_at(&c->S, s, &h, &l);
+        int64_t self_pos = c->autapses ? -1 : set_pos(&c->T, h, l);
+        uint64_t pick;
+        draw_k(net, c, e, 1, nt, self_pos, &pick);
+        t = pick;
+        set_at(&c->T, t, &h2, &l2);
+        break;
+    }
+    case R_TOTAL: {
+        if (!c->autapses || !c->multapses) return -1;
+        uint32_t w[4];
+        draw_block(net->seed, c->id, e, PURPOSE_IDX, w);
+        s = orc_uniform_index(w[0], w[1], ns);
+        t = orc_uniform_index(w[2], w[3], nt);
+        set_at(&c->T, t, &h2, &l2);
+        break;
+    }
+    case R_BERNOULLI: {
+        if (ns == 0) return -1;
+        t = e / ns;
+        s = e % ns;
+        if (t >= nt) return -1;
+        uint64_t thr = (uint64_t)floor(c->p * 4294967296.0);
+        uint32_t w[4];
+        draw_block(net->seed, c->id, e >> 2, PURPOSE_BERN, w);
+        if ((uint64_t)w[e & 3] >= thr) return 0;
+        set_at(&c->T, t, &h2, &l2);
+        if (!c->autapses) {
+            set_at(&c->S, s, &h, &l);
+            if (h == h2 && l == l2) return 0;
+        }
+        break;
+    }
+    case R_ONE_TO_ONE: {
+        if (e >= nt) return -1;
+        s = t = e;
+        set_at(&c->T, t, &h2, &l2);
+        if (!c->autapses) {
+            set_at(&c->S, s, &h, &l);
+            if (h == h2 && l == l2) return 0;
+        }
+        break;
+    }
+    default:
+        return -1;
+    }
+    uint32_t w[4] = { 0, 0, 0, 0 };
+    if (c->w.kind != D_CONST || c->d.kind != D_CONST) draw_block(net->seed, c->id, e, PURPOSE_SYN, w);
+    *weight = (c->w.kind == D_CONST) ? c->w_const : orc_normal_weight(w[0], w[1], c->w.mean, c->w.sd);
+    if (c->d.kind == D_CONST) {
+        *delay = c->d_const;
+    } else {
+        uint32_t count = 0;
+        for (uint32_t k = 0; k < c->dtab_len; k++) if (w[2] >= c->dtab[k]) count++;
+        *delay = (uint16_t)(c->d_klo + count);
+    }
+    *src_ord = (uint32_t)s;
+    *tgt_host = h2;
+    *tgt_local = l2;
+    return 1;
 }
 
 /* A connect that only records the call (no local generation): lets sampled
