@@ -253,7 +253,9 @@ typedef enum {
     SNNC_ROW_PTR = 14,     /* uint64 [M_local + n_img + 1]                     */
     SNNC_R_OFF = 20,       /* uint64 [n_a * P + 1] offsets of R per (a, sigma) */
     SNNC_R_VAL = 21,       /* int32 remote source ids                          */
-    SNNC_IMG_BASE = 22,    /* int64 [n_a * P] first image index per (a, sigma) */
+    SNNC_IMG_BASE = 22,    /* int64 [n_a * P] first image index per (a, sigma); */
+                           /* -1 under SNNC_NUMBER_CALL_ORDER (not contiguous) */
+    SNNC_L_VAL = 23,       /* int32 image index L, aligned with R              */
     SNNC_S_OFF = 30,       /* uint64 [P + 1] offsets of S per target host      */
     SNNC_S_VAL = 31,       /* int32 local source ids                           */
     SNNC_TP_PTR = 32,      /* uint64 [M_local + 1]                             */
@@ -305,12 +307,47 @@ snnc_status snnc_set_timing(snnc_ctx* ctx, int enable);
 snnc_status snnc_kernel_times(snnc_ctx* ctx, uint32_t cap, char (*names)[48], uint64_t* launches,
                               double* ms, uint32_t* n_out);
 
+/* Map policy (Methods, point-to-point creation subsection; used for the
+ * collective maps alike), set before snnc_prepare.
+ * numbering: SNNC_NUMBER_CANONICAL numbers all images after the local neurons
+ *   in (alpha+1, sigma, s) order; SNNC_NUMBER_CALL_ORDER is the paper's
+ *   incremental numbering: calls in order, each call's new images in
+ *   (sigma, s) order, the counter starting at M_local.
+ * image_sources: SNNC_IMAGES_USED gives images only to remote sources used by
+ *   a local connection (flagging on every call); SNNC_IMAGES_ALL to every
+ *   source passed to a call with targets on this host (no flagging, the
+ *   paper's GPU memory levels >= 1); SNNC_IMAGES_THRESHOLD decides per call
+ *   and target host: flag when the rule draws sources at random (fixed
+ *   in-degree, fixed total number, pairwise Bernoulli) and the estimated
+ *   connections on that host per source, K N_t / N_s, N / N_s or p N_t, is
+ *   below xi; fixed out-degree and one-to-one calls are never flagged.
+ * The point-to-point send lists S follow the same decision on the source
+ * host, so S_{tau,sigma} stays equal to R_{tau,sigma}.  Default: CANONICAL,
+ * USED, xi = 1.  Errors: SNNC_EINVAL for unknown values or xi < 0 / not
+ * finite, SNNC_ESTATE after snnc_prepare. */
+typedef enum { SNNC_NUMBER_CANONICAL = 0, SNNC_NUMBER_CALL_ORDER = 1 } snnc_numbering;
+typedef enum { SNNC_IMAGES_USED = 0, SNNC_IMAGES_THRESHOLD = 1, SNNC_IMAGES_ALL = 2 } snnc_image_sources;
+snnc_status snnc_set_map_policy(snnc_ctx* ctx, int32_t numbering, int32_t image_sources, double xi);
+
 /* Tuning knobs of the context, by name.  "sort_variant": tile shape of the
  * radix-sort passes, 0 .. 5 (threads x keys per thread: 256x16, 256x8,
  * 512x8, 512x16, 1024x8, 256x12).  SNNC_EINVAL for an unknown key or value. */
 snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
-/* Further keys: "fuse_batches" (0/1, default 1) and "fused_wgs_per_cu"
- * (workgroups per compute unit of the persistent batch launch, 1 .. 64). */
+/* "sort_mode": 0 = single-pass onesweep passes (decoupled look-back), 1 =
+ * reduce-then-scan passes (per-tile digit counts, one scan, scatter).
+ * Further keys: "fuse_batches" (0/1, default 1), "fused_wgs_per_cu"
+ * (workgroups per compute unit of the persistent batch launch, 1 .. 64) and
+ * "map_path" (0: automatic, 1: number images before the sort even under the
+ * default map policy, the path the other policies take). */
+
+/* Autotuner of the source-major sort: times every pass algorithm and tile
+ * shape (sort_mode x sort_variant) on n synthetic keys with `bits` sorted
+ * bits (1 .. 48), on the context's device, and sets the fastest on the
+ * context.  Results are cached per (floor(log2 n), bits) for the process: a
+ * cached size class returns at once with *ms_out = -1.  Allocates scratch of
+ * about 24 n bytes.  Errors: SNNC_EINVAL, SNNC_ENOMEM, SNNC_EDEVICE. */
+snnc_status snnc_autotune_sort(snnc_ctx* ctx, uint64_t n, uint32_t bits, int32_t* mode_out, int32_t* variant_out,
+                               float* ms_out);
 
 /* ---------------------------------------------------------------- helpers */
 

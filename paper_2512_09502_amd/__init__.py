@@ -31,6 +31,7 @@ ARRAYS = {
     "src": (10, np.int32), "tgt": (11, np.int32), "delay": (12, np.uint16),
     "weight": (13, np.float32), "row_ptr": (14, np.uint64),
     "r_off": (20, np.uint64), "r_val": (21, np.int32), "img_base": (22, np.int64),
+    "l_val": (23, np.int32),
     "s_off": (30, np.uint64), "s_val": (31, np.int32), "tp_ptr": (32, np.uint64),
     "t_val": (33, np.uint32), "p_val": (34, np.uint32),
     "groups": (40, np.int32), "h_off": (41, np.uint64), "h_val": (42, np.int32),
@@ -81,7 +82,8 @@ class Stats(ctypes.Structure):
 EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_create", "snnc_connect",
            "snnc_reserve", "snnc_prepare", "snnc_get_array", "snnc_copy_array", "snnc_copy_range",
            "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks",
-           "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_flush", "snnc_poll"]
+           "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_flush", "snnc_poll",
+           "snnc_autotune_sort", "snnc_set_map_policy"]
 
 _lib = None
 
@@ -105,6 +107,7 @@ def lib():
                                    ctypes.POINTER(SynSpec), i32, ctypes.POINTER(u32)]
         L.snnc_reserve.argtypes = [vp, u64]
         L.snnc_prepare.argtypes = [vp]
+        L.snnc_set_map_policy.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.snnc_get_array.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(u64)]
         L.snnc_copy_array.argtypes = [vp, i32, vp, u64]
         L.snnc_copy_range.argtypes = [vp, i32, u64, u64, vp]
@@ -119,6 +122,8 @@ def lib():
         L.snnc_submit.argtypes = L.snnc_connect.argtypes
         L.snnc_flush.argtypes = [vp]
         L.snnc_poll.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_int32)]
+        L.snnc_autotune_sort.argtypes = [vp, u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_float)]
         for name in EXPORTS:
             getattr(L, name).restype = st if name != "snnc_last_error" else ctypes.c_char_p
         _lib = L
@@ -240,6 +245,11 @@ class Network:
     def reserve(self, n: int):
         self._check(lib().snnc_reserve(self._h, int(n)))
 
+    def set_map_policy(self, numbering: int, sources: int, xi: float = 1.0):
+        """numbering: 0 canonical, 1 in call order; sources: 0 used, 1
+        threshold heuristic with xi, 2 all passed sources."""
+        self._check(lib().snnc_set_map_policy(self._h, int(numbering), int(sources), float(xi)))
+
     def prepare(self):
         self._check(lib().snnc_prepare(self._h))
 
@@ -296,6 +306,14 @@ class Network:
     def tune(self, key: str, value: int):
         self._check(lib().snnc_tune(self._h, key.encode(), int(value)))
 
+    def autotune_sort(self, n: int, bits: int) -> dict:
+        """Pick the fastest radix-pass algorithm and tile shape for n keys of
+        `bits` sorted bits (cached per size class for the process)."""
+        m, v, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+        self._check(lib().snnc_autotune_sort(self._h, int(n), int(bits), ctypes.byref(m), ctypes.byref(v),
+                                             ctypes.byref(ms)))
+        return {"sort_mode": m.value, "sort_variant": v.value, "ms": ms.value}
+
     def sort_pairs(self, keys, vals, bit_lo: int, bit_hi: int):
         """Stable radix sort of device tensors keys (int64) / vals (int32) by
         key bits [bit_lo, bit_hi); returns the sorted (keys, vals) tensors."""
@@ -318,6 +336,8 @@ class Network:
 def run_script(script: dict, P_local: int, prepare: bool = True, skip_invalid: bool = False, **kw) -> Network:
     """Replay a workload script on the GPU for host P_local."""
     net = Network(script["P"], P_local, script["seed"], script["dt"], **kw)
+    if script.get("map_policy") is not None:
+        net.set_map_policy(*script["map_policy"])
     net.rejected = []
     for k, op in enumerate(script["ops"]):
         if op[0] == "create":

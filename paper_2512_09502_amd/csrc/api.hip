@@ -71,16 +71,22 @@ void tstart(Ctx& c, const char* name) {
     p.a = get_event(c);
     p.b = get_event(c);
     HIPCHK(hipEventRecord(p.a, c.stream));
+    c.open_timers.push_back(c.pending.size());
     c.pending.push_back(p);
 }
 
+// closes the innermost open bracket (brackets nest: a scan inside a sort pass)
 void tstop(Ctx& c) {
-    if (!c.timing || c.pending.empty()) return;
-    HIPCHK(hipEventRecord(c.pending.back().b, c.stream));
+    if (!c.timing || c.open_timers.empty()) return;
+    const size_t k = c.open_timers.back();
+    c.open_timers.pop_back();
+    HIPCHK(hipEventRecord(c.pending[k].b, c.stream));
 }
 
 void resolve_times(Ctx& c) {
     if (c.pending.empty()) return;
+    for (size_t k : c.open_timers) HIPCHK(hipEventRecord(c.pending[k].b, c.stream));   // left open by an error
+    c.open_timers.clear();
     HIPCHK(hipStreamSynchronize(c.stream));
     for (auto& p : c.pending) {
         float ms = 0.f;
@@ -713,6 +719,12 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
         if (!strcmp(key, "sort_variant")) {
             if (value < 0 || value >= sort_variant_count()) raise(SNNC_EINVAL, "sort_variant out of range");
             c->sort_variant = (int)value;
+        } else if (!strcmp(key, "sort_mode")) {
+            if (value < 0 || value > 1) raise(SNNC_EINVAL, "sort_mode out of range");
+            c->sort_mode = (int)value;
+        } else if (!strcmp(key, "map_path")) {
+            if (value < 0 || value > 1) raise(SNNC_EINVAL, "map_path out of range");
+            c->force_map_path = value == 1;
         } else if (!strcmp(key, "fuse_batches")) {
             c->fuse_batches = value != 0;
         } else if (!strcmp(key, "fused_wgs_per_cu")) {
@@ -723,6 +735,19 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
         } else {
             raise(SNNC_EINVAL, std::string("unknown tuning key ") + key);
         }
+    });
+}
+
+snnc_status snnc_set_map_policy(snnc_ctx* c, int32_t numbering, int32_t image_sources, double xi) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (c->prepared) raise(SNNC_ESTATE, "map policy after prepare");
+        if (numbering < 0 || numbering > 1) raise(SNNC_EINVAL, "numbering out of range");
+        if (image_sources < 0 || image_sources > 2) raise(SNNC_EINVAL, "image_sources out of range");
+        if (!(xi >= 0.0) || !std::isfinite(xi)) raise(SNNC_EINVAL, "xi must be finite and >= 0");
+        c->numbering = numbering;
+        c->img_sources = image_sources;
+        c->xi = xi;
     });
 }
 

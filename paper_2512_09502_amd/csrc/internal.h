@@ -133,6 +133,7 @@ struct Ctx {
         hipEvent_t a, b;
     };
     std::vector<Pending> pending;
+    std::vector<size_t> open_timers;      // indices into pending of brackets not yet closed
     std::vector<hipEvent_t> event_pool;
     std::map<std::string, KernelTime> ktimes;
     double ms_connect = 0.0, ms_prepare = 0.0;
@@ -145,6 +146,12 @@ struct Ctx {
     void* lookback = nullptr;
     size_t lookback_bytes = 0;
     int sort_variant = 0;                // tile shape of the radix passes (tunable)
+    int sort_mode = 0;                   // 0: onesweep (look-back), 1: reduce-then-scan (tunable)
+    // map policy: image numbering (0 canonical, 1 call order), image sources
+    // (0 used, 1 threshold heuristic, 2 all passed), threshold xi
+    int numbering = 0, img_sources = 0;
+    double xi = 1.0;
+    bool force_map_path = false;         // number images before the sort under the default policy
 
     // pinned staging for host-to-device uploads (no synchronisation per upload)
     char* stage = nullptr;

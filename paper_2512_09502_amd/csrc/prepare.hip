@@ -1,13 +1,17 @@
 // Simulation preparation on the GPU:
-//  1. mark every remote source used by a local connection in a bit set over
-//     (a = alpha + 1, global neuron id), global id = host base + local id;
-//  2. popcount prefix of the bit set = image numbering in (a, sigma, source)
-//     order; R = the set bits per (a, sigma);
-//  3. remap each connection's source (local id, or M_local + rank of its bit:
-//     the lower_bound of the source in R plus the map's first image) and
-//     build the 64-bit sort key (source', target, delay), with the digit
-//     histograms of every radix pass in the same read;
-//  4. source-major radix sort, unpacked into the result arrays;
+//  1. build the 64-bit sort key of every connection, (source prefix, target,
+//     delay), with the digit histograms of every radix pass in the same
+//     read; the source prefix is the local id of a local source, and
+//     M_local + (alpha+1) G + global id of a remote one (global id = host
+//     base + local id), an order that agrees with (alpha+1, sigma, source);
+//  2. source-major radix sort;
+//  3. without remote sources the last pass unpacks the result arrays; with
+//     them, one scan over the sorted keys numbers the images: the first
+//     connection of every distinct remote prefix starts the next image after
+//     the local neurons (the sorted-unique map R of every (alpha+1, sigma) and
+//     the remap of the paper's flag/compact/sort/search/append steps in one
+//     pass), and the same pass unpacks the arrays;
+//  4. R, its per-(alpha+1, sigma) offsets and a bit set of the images;
 //  5. first-index array from the sorted sources;
 //  6. point-to-point send lists: regenerate alpha = -1 draws per target host,
 //     bit rows of the local sources they use, their compaction (S) and the
@@ -29,7 +33,9 @@ struct CallD {
     uint64_t gen_begin;
     const SegD* S;
     uint32_t nS;
-    uint32_t a;   // alpha + 1
+    uint32_t a;      // alpha + 1
+    uint32_t order;  // position of the call in call order
+    uint32_t flag;   // 1: only the sources its local connections use get images
 };
 
 struct Lookup {
@@ -49,15 +55,8 @@ __device__ __forceinline__ uint32_t find_call(const CallD* calls, uint32_t n, ui
     return a;
 }
 
-// source of connection i: host, local id and the bit index (a G + global id)
-__device__ __forceinline__ void source_of(const Lookup& L, const uint32_t* g_src, uint64_t i, uint32_t& host,
-                                          uint32_t& local, uint64_t& bit) {
-    const CallD c = L.calls[find_call(L.calls, L.ncalls, i)];
-    set_lookup(c.S, c.nS, g_src[i], host, local);
-    bit = (uint64_t)c.a * L.G + L.host_base[host] + local;
-}
-
-// The same with a per-thread cache of the current call and source segment:
+// Source of connection i (host, local id and bit index (alpha+1) G + global
+// id), with a per-thread cache of the current call and source segment:
 // a thread walks increasing positions, so the binary searches run only when
 // the position leaves the cached call or the ordinal leaves the cached segment.
 struct SourceCursor {
@@ -67,8 +66,7 @@ struct SourceCursor {
     uint32_t seg_host = 0, seg_first = 0;
     uint64_t bit_base = 0;               // a G + host_base[seg_host] + seg_first - seg_lo
 
-    __device__ __forceinline__ void at(const Lookup& L, uint64_t i, uint32_t ord, uint32_t& host, uint32_t& local,
-                                       uint64_t& bit) {
+    __device__ __forceinline__ const CallD& call_at(const Lookup& L, uint64_t i) {
         if (i < call_lo || i >= call_hi) {
             const uint32_t k = find_call(L.calls, L.ncalls, i);
             call = L.calls[k];
@@ -77,6 +75,12 @@ struct SourceCursor {
             seg_lo = 1;
             seg_hi = 0;
         }
+        return call;
+    }
+
+    __device__ __forceinline__ void at(const Lookup& L, uint64_t i, uint32_t ord, uint32_t& host, uint32_t& local,
+                                       uint64_t& bit) {
+        call_at(L, i);
         if (ord < seg_lo || ord >= seg_hi) {
             uint32_t a = 0, b = call.nS;
             while (b - a > 1) {
@@ -103,66 +107,17 @@ __device__ __forceinline__ void block_range(uint64_t n, uint64_t& lo, uint64_t& 
     hi = lo + per < n ? lo + per : n;
 }
 
-__global__ __launch_bounds__(PNT) void k_mark(Lookup L, const uint32_t* g_src, uint64_t first, uint64_t end,
-                                              uint32_t* bits) {
-    uint64_t lo, hi;
-    block_range(end - first, lo, hi);
-    SourceCursor cur;
-    for (uint64_t i = first + lo + threadIdx.x; i < first + hi; i += PNT) {
-        uint32_t h, l;
-        uint64_t bit;
-        cur.at(L, i, g_src[i], h, l, bit);
-        if (h != L.PL) atomicOr(bits + (bit >> 5), 1u << (bit & 31));
-    }
-}
-
 __device__ __forceinline__ uint64_t rank_of(const uint32_t* bits, const uint64_t* word_rank, uint64_t bit) {
     const uint64_t w = bit >> 5;
     return word_rank[w] + (uint64_t)__popc(bits[w] & ((1u << (bit & 31)) - 1u));
-}
-
-// R: the set bits, in order, as local ids of their host
-__global__ __launch_bounds__(PNT) void k_rvals(const uint32_t* bits, const uint64_t* word_rank, uint64_t n_words,
-                                               const uint64_t* host_base, uint32_t P, uint64_t G, int32_t* R) {
-    for (uint64_t w = (uint64_t)blockIdx.x * PNT + threadIdx.x; w < n_words; w += (uint64_t)gridDim.x * PNT) {
-        uint32_t word = bits[w];
-        uint64_t pos = word_rank[w];
-        while (word) {
-            const uint32_t b = __ffs(word) - 1;
-            word &= word - 1;
-            const uint64_t gid = (w * 32 + b) % G;
-            uint32_t lo = 0, hi = P;   // host: last with host_base <= gid
-            while (hi - lo > 1) {
-                const uint32_t m = (lo + hi) >> 1;
-                if (host_base[m] <= gid) lo = m; else hi = m;
-            }
-            R[pos++] = (int32_t)(gid - host_base[lo]);
-        }
-    }
-}
-
-// r_off[a P + sigma] = rank of the first bit of (a, sigma); r_off[n_a P] = n_img
-__global__ void k_bounds(const uint32_t* bits, const uint64_t* word_rank, const uint64_t* host_base, uint32_t P,
-                         uint32_t n_a, uint64_t G, uint32_t M_local, uint64_t* r_off, int64_t* img_base) {
-    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t nk = (uint64_t)n_a * P;
-    if (k > nk) return;
-    uint64_t r;
-    if (k == nk) {
-        r = rank_of(bits, word_rank, (uint64_t)n_a * G);
-    } else {
-        const uint64_t a = k / P, sigma = k % P;
-        r = rank_of(bits, word_rank, a * G + host_base[sigma]);
-        img_base[k] = (int64_t)M_local + (int64_t)r;
-    }
-    r_off[k] = r;
 }
 
 // source' and the sort key (source' << tgt_shift | target << 16 | delay),
 // with the digit histograms of all radix passes
 __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, const uint32_t* g_tgt,
                                               const uint16_t* g_delay, uint64_t n, const uint32_t* bits,
-                                              const uint64_t* word_rank, uint32_t M_local, uint32_t tgt_shift,
+                                              const uint64_t* word_rank, const int32_t* Lmap, uint32_t M_local,
+                                              uint32_t tgt_shift,
                                               uint32_t dbits, uint32_t passes, uint64_t* keys, uint64_t* hist) {
     __shared__ uint32_t h[8 * 256];
     for (uint32_t i = threadIdx.x; i < passes * 256; i += PNT) h[i] = 0;
@@ -179,7 +134,11 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
             uint32_t host, local;
             uint64_t bit;
             cur.at(L, i, g_src[i], host, local, bit);
-            const uint64_t src2 = host == L.PL ? local : (uint64_t)M_local + rank_of(bits, word_rank, bit);
+            // remote sources: the image index L when the images were numbered before the sort,
+            // else the global prefix M_local + bit (images are numbered after the sort)
+            const uint64_t src2 = host == L.PL ? local
+                                  : bits       ? (uint64_t)Lmap[rank_of(bits, word_rank, bit)]
+                                               : (uint64_t)M_local + bit;
             key = (src2 << tgt_shift) | ((uint64_t)g_tgt[i] << 16) | g_delay[i];
             keys[i] = key;
         }
@@ -189,6 +148,292 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < passes * 256; i += PNT)
         if (h[i]) atomicAdd((unsigned long long*)&hist[i], (unsigned long long)h[i]);
+}
+
+// ---- image numbering after the sort (networks with remote sources)
+// The keys were sorted with source prefix p = local id (local source) or
+// M_local + (alpha+1) G + global id (remote source); both orders agree with
+// (alpha+1, sigma, s).  One pass over the sorted keys numbers the images: the
+// first key of every distinct remote prefix starts a new image, and a scan of
+// these flags (decoupled look-back across tiles) gives each connection its
+// image index.  The same pass unpacks the connection arrays, records each
+// image's prefix and writes the first-index array.
+constexpr int XNT = 256;
+constexpr int XIPT = 16;
+constexpr uint64_t XTILE = XNT * XIPT;
+constexpr uint64_t XFLAG_AGG = 1ull << 62, XFLAG_INC = 2ull << 62, XVALUE = (1ull << 40) - 1;
+constexpr uint32_t XEPOCH_MAX = (1u << 22) - 1;
+
+__global__ __launch_bounds__(XNT) void k_number(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                                uint64_t n, uint32_t tgt_shift, uint64_t tgt_mask, uint32_t M_local,
+                                                uint64_t* lookback, uint32_t* tile_counter, uint32_t epoch,
+                                                uint32_t* status, int32_t* o_src, int32_t* o_tgt, uint16_t* o_delay,
+                                                float* o_weight, uint64_t* img_key, uint64_t* row_ptr,
+                                                uint64_t* n_img_out) {
+    __shared__ uint32_t s_tile;
+    __shared__ uint64_t wave_tot[XNT / 64];
+    __shared__ uint64_t s_excl;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    const uint64_t wbase = tile * XTILE + (uint64_t)wave * 64 * XIPT;
+    // element of item k on this lane: wbase + k*64 + lane (wave-striped, so loads and stores coalesce)
+    uint64_t p[XIPT];
+    uint32_t incl[XIPT];          // flags up to and including the item, within the wave
+    uint64_t last = wbase > 0 && wbase - 1 < n ? (keys[wbase - 1] >> tgt_shift) : ~0ull;   // prefix before the wave
+    uint32_t carry = 0;
+#pragma unroll
+    for (int k = 0; k < XIPT; ++k) {
+        const uint64_t i = wbase + (uint64_t)k * 64 + lane;
+        p[k] = i < n ? keys[i] >> tgt_shift : ~0ull;
+        uint64_t prev = __shfl_up(p[k], 1, 64);
+        const uint64_t last_lane = __shfl(p[k], 63, 64);
+        if (lane == 0) prev = last;
+        last = last_lane;
+        const uint32_t f = (i < n && p[k] >= M_local && (i == 0 || p[k] != prev)) ? 1u : 0u;
+        const uint32_t s = wave_incl_scan(f);
+        incl[k] = carry + s;
+        carry += __shfl(s, 63, 64);
+    }
+    if (lane == 63) wave_tot[wave] = carry;
+    __syncthreads();
+    uint64_t wave_excl = 0, tile_tot = 0;
+#pragma unroll
+    for (int w = 0; w < XNT / 64; ++w) {
+        if (w < (int)wave) wave_excl += wave_tot[w];
+        tile_tot += wave_tot[w];
+    }
+    if (threadIdx.x == 0) {
+        uint64_t* my = lookback + tile;
+        uint64_t excl = 0;
+        if (tile == 0) {
+            __hip_atomic_store(my, XFLAG_INC | ((uint64_t)epoch << 40) | tile_tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(my, XFLAG_AGG | ((uint64_t)epoch << 40) | tile_tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int64_t pred = (int64_t)tile - 1;
+            uint32_t spins = 0;
+            while (pred >= 0) {
+                const uint64_t st = __hip_atomic_load(lookback + pred, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t flag = st & (3ull << 62);
+                if (flag != 0 && (uint32_t)((st >> 40) & XEPOCH_MAX) == epoch) {
+                    excl += st & XVALUE;
+                    if (flag == XFLAG_INC) break;
+                    --pred;
+                    continue;
+                }
+                if (++spins > (1u << 22) || __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    atomicOr(status, 2u);   // bounded wait exceeded: flag the failure and finish the tile
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __hip_atomic_store(my, XFLAG_INC | ((uint64_t)epoch << 40) | (excl + tile_tot), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_excl = excl;
+    }
+    __syncthreads();
+    const uint64_t before = s_excl + wave_excl;   // images started before this wave
+#pragma unroll
+    for (int k = 0; k < XIPT; ++k) {
+        const uint64_t i = wbase + (uint64_t)k * 64 + lane;
+        if (i >= n) continue;
+        const uint64_t key = keys[i];
+        const uint64_t rank = before + incl[k];                 // images started up to and including i
+        const bool local = p[k] < M_local;
+        const int64_t src2 = local ? (int64_t)p[k] : (int64_t)(M_local + rank - 1);
+        o_src[i] = (int32_t)src2;
+        o_tgt[i] = (int32_t)((key >> 16) & tgt_mask);
+        o_delay[i] = (uint16_t)(key & 0xffffu);
+        o_weight[i] = __uint_as_float(vals[i]);
+        // previous connection's source' (its flag count is rank minus this item's flag)
+        int64_t prev2 = -1;
+        bool flag_here = false;
+        if (i > 0) {
+            const uint64_t pp = keys[i - 1] >> tgt_shift;
+            flag_here = !local && pp != p[k];
+            prev2 = pp < M_local ? (int64_t)pp : (int64_t)(M_local + rank - (flag_here ? 1 : 0) - 1);
+        } else {
+            flag_here = !local;
+        }
+        if (flag_here) img_key[rank - 1] = p[k] - M_local;
+        for (int64_t r = prev2 + 1; r <= src2; ++r) row_ptr[r] = i;
+        if (i + 1 == n) {
+            const int64_t n_rows = (int64_t)M_local + (int64_t)rank;
+            for (int64_t r = src2 + 1; r <= n_rows; ++r) row_ptr[r] = n;
+            *n_img_out = rank;
+        }
+    }
+}
+
+// R value and (alpha+1, sigma) boundaries from the image prefixes a G + gid
+__global__ void k_rvals_sorted(const uint64_t* img_key, uint64_t n_img, const uint64_t* host_base, uint32_t P,
+                               uint64_t G, int32_t* R) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_img) return;
+    const uint64_t gid = img_key[j] % G;
+    uint32_t lo = 0, hi = P;
+    while (hi - lo > 1) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (host_base[m] <= gid) lo = m; else hi = m;
+    }
+    R[j] = (int32_t)(gid - host_base[lo]);
+}
+
+__global__ void k_bounds_sorted(const uint64_t* img_key, uint64_t n_img, const uint64_t* host_base, uint32_t P,
+                                uint32_t n_a, uint64_t G, uint32_t M_local, uint64_t* r_off, int64_t* img_base) {
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nk = (uint64_t)n_a * P;
+    if (k > nk) return;
+    const uint64_t x = k == nk ? (uint64_t)n_a * G : (k / P) * G + host_base[k % P];
+    uint64_t a = 0, b = n_img;   // lower_bound of x
+    while (a < b) {
+        const uint64_t m = (a + b) >> 1;
+        if (img_key[m] < x) a = m + 1; else b = m;
+    }
+    r_off[k] = a;
+    if (k < nk) img_base[k] = (int64_t)M_local + (int64_t)a;
+}
+
+// bit set of the image prefixes (sorted, distinct): the first image of every
+// 32-bit word writes the whole word, so no atomics are needed
+__global__ void k_bits_sorted(const uint64_t* img_key, uint64_t n_img, uint32_t* bits) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_img) return;
+    const uint64_t w = img_key[j] >> 5;
+    if (j > 0 && (img_key[j - 1] >> 5) == w) return;
+    uint32_t word = 0;
+    for (uint64_t t = j; t < n_img && (img_key[t] >> 5) == w; ++t) word |= 1u << (img_key[t] & 31);
+    bits[w] = word;
+}
+
+// ---- images numbered before the sort (map policies other than the default)
+// fc[(alpha+1) G + gid] = first call (in call order) that gives the source an
+// image; ~0 = none.  Flagged calls: the sources their local connections use.
+__global__ __launch_bounds__(PNT) void k_first_use(Lookup L, const uint32_t* g_src, uint64_t n, uint32_t* fc) {
+    uint64_t lo, hi;
+    block_range(n, lo, hi);
+    SourceCursor cur;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += PNT) {
+        if (!cur.call_at(L, i).flag) continue;
+        uint32_t host, local;
+        uint64_t bit;
+        cur.at(L, i, g_src[i], host, local, bit);
+        if (host == L.PL) continue;
+        const uint32_t ord = cur.call.order;
+        if (fc[bit] > ord) atomicMin(&fc[bit], ord);   // fc only decreases: a stale read never skips wrongly
+    }
+}
+
+// Unflagged calls: every source passed to them (bit ranges, concatenated)
+struct FRange {
+    uint64_t begin;   // first position in the concatenation
+    uint64_t bit;     // bit of the range's first source
+    uint32_t order;   // call order
+    uint32_t pad;
+};
+
+__global__ __launch_bounds__(PNT) void k_first_pass(const FRange* rg, uint32_t n_rg, uint64_t total, uint32_t* fc) {
+    for (uint64_t j = (uint64_t)blockIdx.x * PNT + threadIdx.x; j < total; j += (uint64_t)gridDim.x * PNT) {
+        uint32_t a = 0, b = n_rg;
+        while (b - a > 1) {
+            const uint32_t m = (a + b) >> 1;
+            if (rg[m].begin <= j) a = m; else b = m;
+        }
+        const uint64_t bit = rg[a].bit + (j - rg[a].begin);
+        const uint32_t ord = rg[a].order;
+        if (fc[bit] > ord) atomicMin(&fc[bit], ord);
+    }
+}
+
+// bit set of the sources with an image: one ballot per wave covers 64 bits
+__global__ __launch_bounds__(PNT) void k_fc_bits(const uint32_t* fc, uint64_t n_bits, uint64_t n_words, uint32_t* bits) {
+    for (uint64_t base = (uint64_t)blockIdx.x * PNT; base < n_bits; base += (uint64_t)gridDim.x * PNT) {
+        const uint64_t b = base + threadIdx.x;   // the loop bound is uniform per workgroup: whole waves ballot
+        const uint64_t m = __ballot(b < n_bits && fc[b] != ~0u);
+        if ((threadIdx.x & 63) == 0) {
+            const uint64_t w = (b >> 6) * 2;
+            if (w < n_words) bits[w] = (uint32_t)m;
+            if (w + 1 < n_words) bits[w + 1] = (uint32_t)(m >> 32);
+        }
+    }
+}
+
+// images in canonical order: R value, and (first call << 16, canonical index)
+// pairs for the numbering in call order
+__global__ __launch_bounds__(PNT) void k_img_list(const uint32_t* bits, const uint64_t* word_rank, uint64_t n_words,
+                                                  const uint32_t* fc, const uint64_t* host_base, uint32_t P, uint64_t G,
+                                                  int32_t* R, uint64_t* okey, uint32_t* oval) {
+    for (uint64_t w = (uint64_t)blockIdx.x * PNT + threadIdx.x; w < n_words; w += (uint64_t)gridDim.x * PNT) {
+        uint32_t word = bits[w];
+        uint64_t pos = word_rank[w];
+        while (word) {
+            const uint32_t bb = __ffs(word) - 1;
+            word &= word - 1;
+            const uint64_t bit = w * 32 + bb;
+            const uint64_t gid = bit % G;
+            uint32_t lo = 0, hi = P;
+            while (hi - lo > 1) {
+                const uint32_t m = (lo + hi) >> 1;
+                if (host_base[m] <= gid) lo = m; else hi = m;
+            }
+            R[pos] = (int32_t)(gid - host_base[lo]);
+            if (okey) {
+                okey[pos] = (uint64_t)fc[bit] << 16;
+                oval[pos] = (uint32_t)pos;
+            }
+            ++pos;
+        }
+    }
+}
+
+// L[j] = M_local + j (canonical numbering)
+__global__ void k_iota_l(int32_t* Lv, uint64_t n, uint32_t M_local) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) Lv[j] = (int32_t)((uint64_t)M_local + j);
+}
+
+// L[canonical index] = M_local + position in call order
+__global__ void k_scatter_l(const uint32_t* canon, uint64_t n, uint32_t M_local, int32_t* Lv) {
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) Lv[canon[k]] = (int32_t)((uint64_t)M_local + k);
+}
+
+// R offsets per (alpha+1, sigma) from the bit set ranks
+__global__ void k_bounds_bits(const uint32_t* bits, const uint64_t* word_rank, const uint64_t* host_base, uint32_t P,
+                              uint32_t n_a, uint64_t G, uint32_t M_local, int canonical, uint64_t* r_off,
+                              int64_t* img_base) {
+    const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t nk = (uint64_t)n_a * P;
+    if (k > nk) return;
+    const uint64_t x = k == nk ? (uint64_t)n_a * G : (k / P) * G + host_base[k % P];
+    const uint64_t r = rank_of(bits, word_rank, x);
+    r_off[k] = r;
+    if (k < nk) img_base[k] = canonical ? (int64_t)M_local + (int64_t)r : -1;
+}
+
+// point-to-point rows: set the bits of local-id ranges (unflagged calls)
+struct WRange {
+    uint64_t begin;   // first position in the concatenation of word counts
+    uint64_t row;     // first word of the row
+    uint32_t lo, hi;  // local ids [lo, hi)
+};
+
+__global__ __launch_bounds__(PNT) void k_set_ranges(const WRange* rg, uint32_t n_rg, uint64_t total, uint32_t* rows) {
+    for (uint64_t j = (uint64_t)blockIdx.x * PNT + threadIdx.x; j < total; j += (uint64_t)gridDim.x * PNT) {
+        uint32_t a = 0, b = n_rg;
+        while (b - a > 1) {
+            const uint32_t m = (a + b) >> 1;
+            if (rg[m].begin <= j) a = m; else b = m;
+        }
+        const WRange r = rg[a];
+        const uint32_t w = (r.lo >> 5) + (uint32_t)(j - r.begin);
+        const uint32_t first = max(r.lo, w * 32), last = min(r.hi, w * 32 + 32);   // [first, last) in this word
+        const uint32_t nb = last - first;
+        const uint32_t mask = (nb == 32 ? ~0u : ((1u << nb) - 1u)) << (first & 31);
+        atomicOr(&rows[r.row + w], mask);
+    }
 }
 
 // first-index array: row_ptr[r] = first position with source >= r
@@ -271,8 +516,8 @@ struct HRange {
 };
 
 __global__ __launch_bounds__(PNT) void k_hi(const HRange* rg, uint32_t n_rg, uint64_t n_h, const uint32_t* bits,
-                                            const uint64_t* word_rank, const uint64_t* host_base, uint64_t G,
-                                            uint32_t PL, uint32_t M_local, int32_t* H, int32_t* I) {
+                                            const uint64_t* word_rank, const int32_t* Lmap, const uint64_t* host_base,
+                                            uint64_t G, uint32_t PL, int32_t* H, int32_t* I) {
     for (uint64_t j = (uint64_t)blockIdx.x * PNT + threadIdx.x; j < n_h; j += (uint64_t)gridDim.x * PNT) {
         uint32_t a = 0, b = n_rg;
         while (b - a > 1) {
@@ -285,7 +530,7 @@ __global__ __launch_bounds__(PNT) void k_hi(const HRange* rg, uint32_t n_rg, uin
         int32_t img = -1;
         if (r.sigma != PL) {
             const uint64_t bit = (uint64_t)r.a * G + host_base[r.sigma] + s;
-            if ((bits[bit >> 5] >> (bit & 31)) & 1u) img = (int32_t)((uint64_t)M_local + rank_of(bits, word_rank, bit));
+            if ((bits[bit >> 5] >> (bit & 31)) & 1u) img = Lmap[rank_of(bits, word_rank, bit)];
         }
         I[j] = img;
     }
@@ -322,6 +567,32 @@ __global__ __launch_bounds__(PNT) void k_gq(const LRange* lr, const uint32_t* g_
         }
     }
     if (!gq_ptr) cnt[s] = c;
+}
+
+uint64_t count_on(const HostSet& s, uint32_t host) {
+    uint64_t n = 0;
+    for (auto& g : s.seg)
+        if (g.host == host) n += g.n;
+    return n;
+}
+
+// Map policy: does call cl give images on host tau only to the sources its
+// connections there use (flagging)?  The threshold heuristic flags rules that
+// draw their sources at random when the estimated connections on tau per
+// source fall below xi; out-degree and one-to-one calls use every source.
+bool flag_sources(const Ctx& c, const Call& cl, uint32_t tau) {
+    if (c.img_sources == 0) return true;
+    if (c.img_sources == 2) return false;
+    if (cl.S.total == 0) return true;
+    const double n_s = (double)cl.S.total, n_t = (double)count_on(cl.T, tau);
+    double est;
+    switch (cl.rule) {
+        case SNNC_FIXED_INDEGREE: est = (double)cl.n * n_t; break;
+        case SNNC_FIXED_TOTAL_NUMBER: est = n_t > 0.0 ? (double)cl.n : 0.0; break;
+        case SNNC_PAIRWISE_BERNOULLI: est = cl.p * n_s * n_t; break;
+        default: return false;
+    }
+    return est / n_s < c.xi;
 }
 
 template <class T>
@@ -368,127 +639,284 @@ void prepare_all(Ctx& c) {
         int32_t amax = -1;
         for (auto& cl : c.calls) amax = std::max(amax, cl.alpha);
         const uint32_t n_a = (uint32_t)(amax + 2);
+        const uint32_t n_calls = (uint32_t)c.calls.size();
+        std::vector<uint8_t> flag_local(n_calls);
+        for (uint32_t k = 0; k < n_calls; ++k) flag_local[k] = flag_sources(c, c.calls[k], PL) ? 1 : 0;
         std::vector<CallD> calls;
-        for (auto& cl : c.calls)
-            if (cl.gen_count) calls.push_back(CallD{cl.gen_begin, cl.dS, (uint32_t)cl.S.seg.size(), (uint32_t)(cl.alpha + 1)});
-        if (calls.empty()) calls.push_back(CallD{0, nullptr, 0, 0});
+        for (uint32_t k = 0; k < n_calls; ++k) {
+            const Call& cl = c.calls[k];
+            if (cl.gen_count)
+                calls.push_back(CallD{cl.gen_begin, cl.dS, (uint32_t)cl.S.seg.size(), (uint32_t)(cl.alpha + 1), k,
+                                      flag_local[k]});
+        }
+        if (calls.empty()) calls.push_back(CallD{0, nullptr, 0, 0, 0, 0});
         CallD* d_calls = static_cast<CallD*>(tmp(calls.size() * sizeof(CallD)));
         upload(c, d_calls, calls.data(), calls.size() * sizeof(CallD));
         uint64_t* d_hb = static_cast<uint64_t*>(tmp((P + 1) * 8));
         upload(c, d_hb, host_base.data(), (P + 1) * 8);
         Lookup L{d_calls, (uint32_t)calls.size(), d_hb, P, PL, G};
 
-        // ---------------------------------------------------------- 1-2 image map
+        // ---------------------------------------------------------- 1-5 image map, keys, sort, first index
+        // Default policy: without remote sources the keys hold final sources and
+        // the last radix pass unpacks; with remote sources the keys hold global
+        // source ids and the images are numbered by a scan over the sorted keys.
+        // Other policies (or "map_path"): the images are numbered first (first
+        // call of every image source, its order), the keys hold image indices
+        // and the last pass unpacks.
+        bool remote_net = false;
+        for (auto& cl : c.calls)
+            for (auto& g : cl.S.seg) remote_net |= (g.host != PL && cl.gen_count > 0);
+        const bool mapped = c.numbering != 0 || c.img_sources != 0 || c.force_map_path;
         const uint64_t n_bits = (uint64_t)n_a * G;
         const uint64_t n_words = n_bits / 32 + 1;    // one spare word: rank of the end bit
         uint32_t* bits = static_cast<uint32_t*>(tmp(n_words * 4));
         HIPCHK(hipMemsetAsync(bits, 0, n_words * 4, c.stream));
-        // only the connections of calls with a source segment off P_local can need an image
-        std::vector<std::pair<uint64_t, uint64_t>> mark_ranges;
-        for (auto& cl : c.calls) {
-            bool remote = false;
-            for (auto& g : cl.S.seg) remote |= (g.host != PL);
-            if (!remote || !cl.gen_count) continue;
-            if (!mark_ranges.empty() && mark_ranges.back().second == cl.gen_begin)
-                mark_ranges.back().second += cl.gen_count;
-            else
-                mark_ranges.push_back({cl.gen_begin, cl.gen_begin + cl.gen_count});
-        }
-        for (auto& r : mark_ranges) {
-            tstart(c, "prep_mark");
-            hipLaunchKernelGGL(k_mark, dim3(grid_for(r.second - r.first, 8192)), dim3(PNT), 0, c.stream, L, c.g_src, r.first,
-                               r.second, bits);
-            tstop(c);
-            HIPCHK(hipGetLastError());
-        }
         uint64_t* word_rank = static_cast<uint64_t*>(tmp((n_words + 1) * 8));
-        const uint64_t n_img = scan_popc_u64(c, bits, word_rank, n_words, true);
-        c.n_img = n_img;
-        if ((uint64_t)M_local + n_img > 0x7fffffffull) raise(SNNC_EUNSUPPORTED, "more than 2^31-1 local and image neurons");
-        int32_t* R = result<int32_t>(c, SNNC_R_VAL, n_img);
-        if (n_img) {
-            tstart(c, "prep_rvals");
-            hipLaunchKernelGGL(k_rvals, dim3(grid_for(n_words)), dim3(PNT), 0, c.stream, bits, word_rank, n_words,
-                               d_hb, P, G, R);
-            tstop(c);
-            HIPCHK(hipGetLastError());
+        uint64_t n_img = 0;
+        int32_t* Lmap = nullptr;
+        if (mapped) {
+            uint32_t* fc = static_cast<uint32_t*>(dalloc(c, n_bits * 4));
+            try {
+                HIPCHK(hipMemsetAsync(fc, 0xff, n_bits * 4, c.stream));
+                bool any_flagged = false;
+                for (auto& cd : calls) any_flagged |= (cd.flag && cd.nS > 0);
+                if (N && remote_net && any_flagged) {
+                    tstart(c, "prep_first_use");
+                    hipLaunchKernelGGL(k_first_use, dim3(grid_for(N, 8192)), dim3(PNT), 0, c.stream, L, c.g_src, N, fc);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                }
+                std::vector<FRange> fr;
+                uint64_t f_total = 0;
+                for (uint32_t k = 0; k < n_calls; ++k) {
+                    const Call& cl = c.calls[k];
+                    if (flag_local[k] || count_on(cl.T, PL) == 0) continue;
+                    for (auto& g : cl.S.seg)
+                        if (g.host != PL && g.n) {
+                            fr.push_back(FRange{f_total, (uint64_t)(cl.alpha + 1) * G + host_base[g.host] + g.first, k, 0});
+                            f_total += g.n;
+                        }
+                }
+                if (f_total) {
+                    FRange* d_fr = static_cast<FRange*>(tmp(fr.size() * sizeof(FRange)));
+                    upload(c, d_fr, fr.data(), fr.size() * sizeof(FRange));
+                    tstart(c, "prep_first_pass");
+                    hipLaunchKernelGGL(k_first_pass, dim3(grid_for(f_total)), dim3(PNT), 0, c.stream, d_fr,
+                                       (uint32_t)fr.size(), f_total, fc);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                }
+                tstart(c, "prep_fc_bits");
+                hipLaunchKernelGGL(k_fc_bits, dim3(grid_for(n_bits)), dim3(PNT), 0, c.stream, fc, n_bits, n_words, bits);
+                tstop(c);
+                HIPCHK(hipGetLastError());
+                n_img = scan_popc_u64(c, bits, word_rank, n_words, true);
+                if ((uint64_t)M_local + n_img > 0x7fffffffull)
+                    raise(SNNC_EUNSUPPORTED, "more than 2^31-1 local and image neurons");
+                int32_t* R = result<int32_t>(c, SNNC_R_VAL, n_img);
+                Lmap = result<int32_t>(c, SNNC_L_VAL, n_img);
+                const uint32_t call_bits = bits_for(n_calls);
+                const bool by_call = c.numbering == 1 && call_bits > 0;
+                uint64_t* ik0 = nullptr;
+                uint32_t* iv0 = nullptr;
+                if (by_call && n_img) {
+                    ik0 = static_cast<uint64_t*>(tmp(n_img * 8));
+                    iv0 = static_cast<uint32_t*>(tmp(n_img * 4));
+                }
+                if (n_img) {
+                    tstart(c, "prep_img_list");
+                    hipLaunchKernelGGL(k_img_list, dim3(grid_for(n_words)), dim3(PNT), 0, c.stream, bits, word_rank,
+                                       n_words, fc, d_hb, P, G, R, ik0, iv0);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                }
+                dfree(c, fc);
+                fc = nullptr;
+                if (n_img && by_call) {
+                    // stable sort of the canonical indices by first call: the paper's order
+                    uint64_t* ik1 = static_cast<uint64_t*>(tmp(n_img * 8));
+                    uint32_t* iv1 = static_cast<uint32_t*>(tmp(n_img * 4));
+                    const int w = radix_sort(c, ik0, iv0, ik1, iv1, n_img, 16, 16 + call_bits, nullptr, nullptr);
+                    tstart(c, "prep_number_calls");
+                    hipLaunchKernelGGL(k_scatter_l, dim3((unsigned)((n_img + 255) / 256)), dim3(256), 0, c.stream,
+                                       w ? iv1 : iv0, n_img, M_local, Lmap);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                } else if (n_img) {
+                    hipLaunchKernelGGL(k_iota_l, dim3((unsigned)((n_img + 255) / 256)), dim3(256), 0, c.stream, Lmap,
+                                       n_img, M_local);
+                    HIPCHK(hipGetLastError());
+                }
+                uint64_t* r_off = result<uint64_t>(c, SNNC_R_OFF, (uint64_t)n_a * P + 1);
+                int64_t* img_base = result<int64_t>(c, SNNC_IMG_BASE, (uint64_t)n_a * P);
+                const uint64_t nk = (uint64_t)n_a * P + 1;
+                hipLaunchKernelGGL(k_bounds_bits, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, c.stream, bits,
+                                   word_rank, d_hb, P, n_a, G, M_local, c.numbering == 0 ? 1 : 0, r_off, img_base);
+                HIPCHK(hipGetLastError());
+            } catch (...) {
+                if (fc) dfree(c, fc);
+                throw;
+            }
         }
-        uint64_t* r_off = result<uint64_t>(c, SNNC_R_OFF, (uint64_t)n_a * P + 1);
-        int64_t* img_base = result<int64_t>(c, SNNC_IMG_BASE, (uint64_t)n_a * P);
-        {
-            const uint64_t nk = (uint64_t)n_a * P + 1;
-            tstart(c, "prep_bounds");
-            hipLaunchKernelGGL(k_bounds, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, c.stream, bits, word_rank,
-                               d_hb, P, n_a, G, M_local, r_off, img_base);
-            tstop(c);
-            HIPCHK(hipGetLastError());
-        }
-
-        // ---------------------------------------------------------- 3-4 keys and sort
-        const uint64_t n_rows = (uint64_t)M_local + n_img;
-        const uint32_t sbits = bits_for(n_rows), tbits = bits_for(M_local);
+        const uint32_t tbits = bits_for(M_local);
+        const uint64_t prefix_span = mapped       ? (uint64_t)M_local + n_img
+                                     : remote_net ? (uint64_t)M_local + n_bits
+                                                  : (uint64_t)M_local;
+        const uint32_t sbits = bits_for(prefix_span);
         c.key_bits = sbits + tbits;
         if (sbits + tbits > 48) raise(SNNC_EUNSUPPORTED, "source and target ids need more than 48 key bits");
         uint32_t passes, dbits;
         radix_plan(sbits + tbits, passes, dbits);
+        const bool unpack_in_sort = !remote_net || mapped;
         int32_t* o_src = nullptr;
+        uint64_t* row_ptr = nullptr;
+        uint64_t* keys0 = nullptr;
+        uint64_t* keys1 = nullptr;
+        uint32_t* vals1 = nullptr;
         if (N) {
-            uint64_t* keys0 = static_cast<uint64_t*>(tmp(N * 8));
+            keys0 = static_cast<uint64_t*>(tmp(N * 8));
             uint64_t* hist = static_cast<uint64_t*>(tmp(8 * 256 * 8));
             HIPCHK(hipMemsetAsync(hist, 0, 8 * 256 * 8, c.stream));
             tstart(c, "prep_keys");
             hipLaunchKernelGGL(k_keys, dim3(grid_for(N, 8192)), dim3(PNT), 0, c.stream, L, c.g_src, c.g_tgt, c.g_delay,
-                               N, bits, word_rank, M_local, 16 + tbits, dbits, passes, keys0, hist);
+                               N, mapped ? bits : (const uint32_t*)nullptr, mapped ? word_rank : (const uint64_t*)nullptr,
+                               Lmap, M_local, 16 + tbits, dbits, passes, keys0, hist);
             tstop(c);
             HIPCHK(hipGetLastError());
             // the source ordinals, targets and delays now live in the keys (released in stream order)
             dfree(c, c.g_src); c.g_src = nullptr;
             dfree(c, c.g_tgt); c.g_tgt = nullptr;
             dfree(c, c.g_delay); c.g_delay = nullptr;
-            uint64_t* keys1 = static_cast<uint64_t*>(tmp(N * 8));
-            uint32_t* vals1 = static_cast<uint32_t*>(tmp(N * 4));
+            keys1 = static_cast<uint64_t*>(tmp(N * 8));
+            vals1 = static_cast<uint32_t*>(tmp(N * 4));
             // outputs allocated only now, so they reuse the memory just released
             o_src = result<int32_t>(c, SNNC_SRC, N);
             int32_t* o_tgt = result<int32_t>(c, SNNC_TGT, N);
             uint16_t* o_delay = result<uint16_t>(c, SNNC_DELAY, N);
             float* o_weight = result<float>(c, SNNC_WEIGHT, N);
-            FinalOut fo{o_src, o_tgt, o_delay, o_weight, 16 + tbits, (1ull << tbits) - 1};
-            if (tbits == 0) fo.tgt_mask = 0;
-            radix_sort(c, keys0, reinterpret_cast<uint32_t*>(c.g_weight), keys1, vals1, N, 16, 16 + sbits + tbits,
-                       hist, &fo);
+            FinalOut fo{o_src, o_tgt, o_delay, o_weight, 16 + tbits, tbits ? (1ull << tbits) - 1 : 0};
+            if (unpack_in_sort) {
+                radix_sort(c, keys0, reinterpret_cast<uint32_t*>(c.g_weight), keys1, vals1, N, 16, 16 + sbits + tbits,
+                           hist, &fo);
+                const uint64_t n_rows = (uint64_t)M_local + n_img;
+                row_ptr = result<uint64_t>(c, SNNC_ROW_PTR, n_rows + 1);
+                tstart(c, "prep_csr");
+                hipLaunchKernelGGL(k_csr, dim3(grid_for(N / 4 + 1, 16384)), dim3(PNT), 0, c.stream, o_src, N, n_rows,
+                                   row_ptr);
+                tstop(c);
+                HIPCHK(hipGetLastError());
+            } else {
+                const int which = radix_sort(c, keys0, reinterpret_cast<uint32_t*>(c.g_weight), keys1, vals1, N, 16,
+                                             16 + sbits + tbits, hist, nullptr);
+                const uint64_t max_img = std::min<uint64_t>(N, n_bits);
+                uint64_t* img_key = static_cast<uint64_t*>(tmp(max_img * 8 + 8));
+                row_ptr = result<uint64_t>(c, SNNC_ROW_PTR, (uint64_t)M_local + max_img + 1);
+                uint64_t* d_nimg = static_cast<uint64_t*>(tmp(8));
+                const uint64_t tiles = (N + XTILE - 1) / XTILE;
+                if (c.lookback_bytes < tiles * 8) raise(SNNC_EDEVICE, "look-back table too small");
+                if (++c.sort_epoch > XEPOCH_MAX) {
+                    HIPCHK(hipMemsetAsync(c.lookback, 0, c.lookback_bytes, c.stream));
+                    c.sort_epoch = 1;
+                }
+                uint32_t* counter = static_cast<uint32_t*>(tmp(4));
+                HIPCHK(hipMemsetAsync(counter, 0, 4, c.stream));
+                const uint32_t* vsorted = which ? vals1 : reinterpret_cast<uint32_t*>(c.g_weight);
+                tstart(c, "prep_number");
+                hipLaunchKernelGGL(k_number, dim3((unsigned)tiles), dim3(XNT), 0, c.stream, which ? keys1 : keys0,
+                                   vsorted, N, 16 + tbits, fo.tgt_mask, M_local, (uint64_t*)c.lookback, counter,
+                                   c.sort_epoch, c.d_status, o_src, o_tgt, o_delay, o_weight, img_key, row_ptr, d_nimg);
+                tstop(c);
+                HIPCHK(hipGetLastError());
+                download(c, &n_img, d_nimg, 8);
+                c.counts[SNNC_ROW_PTR] = (uint64_t)M_local + n_img + 1;
+                if ((uint64_t)M_local + n_img > 0x7fffffffull)
+                    raise(SNNC_EUNSUPPORTED, "more than 2^31-1 local and image neurons");
+                int32_t* R = result<int32_t>(c, SNNC_R_VAL, n_img);
+                Lmap = result<int32_t>(c, SNNC_L_VAL, n_img);
+                uint64_t* r_off = result<uint64_t>(c, SNNC_R_OFF, (uint64_t)n_a * P + 1);
+                int64_t* img_base = result<int64_t>(c, SNNC_IMG_BASE, (uint64_t)n_a * P);
+                if (n_img) {
+                    tstart(c, "prep_rvals");
+                    hipLaunchKernelGGL(k_rvals_sorted, dim3((unsigned)((n_img + 255) / 256)), dim3(256), 0, c.stream,
+                                       img_key, n_img, d_hb, P, G, R);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                    tstart(c, "prep_bits");
+                    hipLaunchKernelGGL(k_bits_sorted, dim3((unsigned)((n_img + 255) / 256)), dim3(256), 0, c.stream,
+                                       img_key, n_img, bits);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                    hipLaunchKernelGGL(k_iota_l, dim3((unsigned)((n_img + 255) / 256)), dim3(256), 0, c.stream, Lmap,
+                                       n_img, M_local);
+                    HIPCHK(hipGetLastError());
+                }
+                const uint64_t nk = (uint64_t)n_a * P + 1;
+                tstart(c, "prep_bounds");
+                hipLaunchKernelGGL(k_bounds_sorted, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, c.stream, img_key,
+                                   n_img, d_hb, P, n_a, G, M_local, r_off, img_base);
+                tstop(c);
+                HIPCHK(hipGetLastError());
+            }
         } else {
             o_src = result<int32_t>(c, SNNC_SRC, 0);
             result<int32_t>(c, SNNC_TGT, 0);
             result<uint16_t>(c, SNNC_DELAY, 0);
             result<float>(c, SNNC_WEIGHT, 0);
+            const uint64_t n_rows = (uint64_t)M_local + n_img;
+            row_ptr = result<uint64_t>(c, SNNC_ROW_PTR, n_rows + 1);
+            hipLaunchKernelGGL(k_fill_u64, dim3((n_rows + 1 + 255) / 256), dim3(256), 0, c.stream, row_ptr, n_rows + 1,
+                               (uint64_t)0);
+            HIPCHK(hipGetLastError());
         }
-        dfree(c, c.g_src); c.g_src = nullptr;
-        dfree(c, c.g_tgt); c.g_tgt = nullptr;
-        dfree(c, c.g_delay); c.g_delay = nullptr;
+        if (!mapped && (!remote_net || !N)) {
+            result<int32_t>(c, SNNC_R_VAL, 0);
+            result<int32_t>(c, SNNC_L_VAL, 0);
+            uint64_t* r_off = result<uint64_t>(c, SNNC_R_OFF, (uint64_t)n_a * P + 1);
+            int64_t* img_base = result<int64_t>(c, SNNC_IMG_BASE, (uint64_t)n_a * P);
+            HIPCHK(hipMemsetAsync(r_off, 0, ((uint64_t)n_a * P + 1) * 8, c.stream));
+            std::vector<int64_t> ib((size_t)n_a * P, (int64_t)M_local);
+            upload(c, img_base, ib.data(), ib.size() * 8);
+        }
+        c.n_img = n_img;
+        // word ranks of the image bit set (the collective arrays look images up by bit)
+        if (!mapped) scan_popc_u64(c, bits, word_rank, n_words, false);
         dfree(c, c.g_weight); c.g_weight = nullptr;
         c.cap_gen = 0;
-
-        // ---------------------------------------------------------- 5 first-index array
-        uint64_t* row_ptr = result<uint64_t>(c, SNNC_ROW_PTR, n_rows + 1);
-        tstart(c, "prep_csr");
-        hipLaunchKernelGGL(k_csr, dim3(grid_for(N / 4 + 1, 16384)), dim3(PNT), 0, c.stream, o_src, N, n_rows, row_ptr);
-        tstop(c);
-        HIPCHK(hipGetLastError());
+        (void)row_ptr;
 
         // ---------------------------------------------------------- 6 point-to-point lists
         const uint32_t wpr = (M_local + 31) / 32 + 1;     // words per row (+1 spare)
         const uint64_t n_rw = (uint64_t)P * wpr;
         uint32_t* rows = static_cast<uint32_t*>(tmp(n_rw * 4));
         HIPCHK(hipMemsetAsync(rows, 0, n_rw * 4, c.stream));
+        std::vector<WRange> wr;
+        uint64_t w_total = 0;
         for (auto& cl : c.calls) {
             if (cl.alpha != -1) continue;
             bool has_local_source = false;
-            for (auto& g : cl.S.seg) has_local_source |= (g.host == PL);
+            for (auto& g : cl.S.seg) has_local_source |= (g.host == PL && g.n > 0);
             if (!has_local_source) continue;
-            std::vector<bool> tgt_host(P, false);
-            for (auto& g : cl.T.seg) tgt_host[g.host] = true;
-            for (uint32_t tau = 0; tau < P; ++tau)
-                if (tau != PL && tgt_host[tau]) gen_mark(c, cl, tau, rows + (uint64_t)tau * wpr);
+            for (uint32_t tau = 0; tau < P; ++tau) {
+                if (tau == PL || count_on(cl.T, tau) == 0) continue;
+                if (flag_sources(c, cl, tau)) {   // regenerate tau's draws, keep the local sources they use
+                    gen_mark(c, cl, tau, rows + (uint64_t)tau * wpr);
+                    continue;
+                }
+                for (auto& g : cl.S.seg)          // not flagged: every local source of the call
+                    if (g.host == PL && g.n) {
+                        wr.push_back(WRange{w_total, (uint64_t)tau * wpr, g.first, g.first + g.n});
+                        w_total += ((g.first + g.n - 1) >> 5) - (g.first >> 5) + 1;
+                    }
+            }
+        }
+        if (w_total) {
+            WRange* d_wr = static_cast<WRange*>(tmp(wr.size() * sizeof(WRange)));
+            upload(c, d_wr, wr.data(), wr.size() * sizeof(WRange));
+            tstart(c, "prep_s_ranges");
+            hipLaunchKernelGGL(k_set_ranges, dim3(grid_for(w_total)), dim3(PNT), 0, c.stream, d_wr, (uint32_t)wr.size(),
+                               w_total, rows);
+            tstop(c);
+            HIPCHK(hipGetLastError());
         }
         uint64_t* row_rank = static_cast<uint64_t*>(tmp((n_rw + 1) * 8));
         const uint64_t n_s = scan_popc_u64(c, rows, row_rank, n_rw, true);
@@ -576,7 +1004,7 @@ void prepare_all(Ctx& c) {
             upload(c, d_rg, ranges.data(), ranges.size() * sizeof(HRange));
             tstart(c, "prep_hi");
             hipLaunchKernelGGL(k_hi, dim3(grid_for(h_total)), dim3(PNT), 0, c.stream, d_rg, (uint32_t)ranges.size(),
-                               h_total, bits, word_rank, d_hb, G, PL, M_local, Hv, Iv);
+                               h_total, bits, word_rank, Lmap, d_hb, G, PL, Hv, Iv);
             tstop(c);
             HIPCHK(hipGetLastError());
         }

@@ -8,6 +8,7 @@
 // the key builder in the prepare pipeline).  Tile shapes (threads x keys per
 // thread) are template variants; the context picks one (tunable).
 #include <algorithm>
+#include <map>
 
 #include "device_common.h"
 #include "internal.h"
@@ -69,7 +70,11 @@ __global__ __launch_bounds__(RADIX) void k_hist_scan(const uint64_t* hist, uint6
     off[blockIdx.x * RADIX + threadIdx.x] = ex;
 }
 
-template <int NT, int IPT, bool FINAL>
+// LB = true: onesweep (dynamic tile order, decoupled look-back, digit_off =
+// exclusive digit totals).  LB = false: the scatter of a reduce-then-scan pass
+// (tile = block index, digit_off = exclusive scan of the per-tile counts laid
+// out digit-major, so entry d * tiles + t is the tile's global base for d).
+template <int NT, int IPT, bool FINAL, bool LB>
 __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                  uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n,
                                                  uint32_t shift, uint32_t dbits, const uint64_t* __restrict__ digit_off,
@@ -87,10 +92,10 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
     __shared__ uint32_t stage_v[TILE];
 
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
+    if (LB && threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
     for (uint32_t i = threadIdx.x; i < WAVES * RADIX; i += NT) (&wave_hist[0][0])[i] = 0;
     __syncthreads();
-    const uint64_t tile = s_tile;
+    const uint64_t tile = LB ? (uint64_t)s_tile : (uint64_t)blockIdx.x;
     const uint64_t base = tile * TILE;
     const uint32_t mask = (1u << dbits) - 1;
 
@@ -143,7 +148,9 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
             cnt += wave_hist[w][d];
         }
         uint64_t* my = lookback + tile * RADIX + d;
-        if (tile == 0) {
+        if (!LB) {
+            // offsets known from the reduce-then-scan counts
+        } else if (tile == 0) {
             __hip_atomic_store(my, pack_status(FLAG_INC, epoch, cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             __hip_atomic_store(my, pack_status(FLAG_AGG, epoch, cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -175,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
     const uint32_t start = (uint32_t)block_excl_scan<NT, uint64_t>((uint64_t)cnt, scan_scratch, &tot);
     if (digit_thread) {
         tile_start[d] = start;
-        glob_base[d] = digit_off[d] + excl;
+        glob_base[d] = LB ? digit_off[d] + excl : digit_off[(uint64_t)d * ((n + TILE - 1) / TILE) + tile];
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) wave_hist[w][d] = start + woff[w];
     }
@@ -237,16 +244,65 @@ struct PassArgs {
     FinalOut fo;
 };
 
+// Digit counts of every tile of a pass, digit-major (counts[d * tiles + t]),
+// for the reduce-then-scan form of a pass.
+template <int NT, int IPT>
+__global__ __launch_bounds__(NT) void k_tile_counts(const uint64_t* __restrict__ kin, uint64_t n, uint32_t shift,
+                                                    uint32_t dbits, uint32_t* counts) {
+    constexpr int TILE = NT * IPT;
+    __shared__ uint32_t h[RADIX];
+    for (uint32_t i = threadIdx.x; i < RADIX; i += NT) h[i] = 0;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint64_t tiles = (n + TILE - 1) / TILE;
+    const uint64_t wbase = (uint64_t)blockIdx.x * TILE + (uint64_t)wave * 64 * IPT + lane;
+    const uint32_t mask = (1u << dbits) - 1;
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const uint64_t i = wbase + (uint64_t)k * 64;
+        const bool valid = i < n;
+        const uint32_t d = valid ? (uint32_t)((kin[i] >> shift) & mask) : 0u;
+        wave_hist_add(h, d, valid);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < RADIX; d += NT) counts[(uint64_t)d * tiles + blockIdx.x] = h[d];
+}
+
 template <int NT, int IPT>
 void launch_pass(Ctx& c, const PassArgs& a, bool final) {
     constexpr int TILE = NT * IPT;
     const uint64_t tiles = (a.n + TILE - 1) / TILE;
-    if (final)
-        hipLaunchKernelGGL((k_onesweep<NT, IPT, true>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin, a.vin, a.kout,
-                           a.vout, a.n, a.shift, a.dbits, a.off, a.lookback, a.counter, a.epoch, a.status, a.fo);
-    else
-        hipLaunchKernelGGL((k_onesweep<NT, IPT, false>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin, a.vin,
-                           a.kout, a.vout, a.n, a.shift, a.dbits, a.off, a.lookback, a.counter, a.epoch, a.status, a.fo);
+    const uint64_t* off = a.off;
+    std::vector<void*> temps;
+    if (c.sort_mode == 1) {
+        // reduce-then-scan: per-tile counts, one scan, scatter with known bases
+        uint32_t* counts = dalloc_n<uint32_t>(c, tiles * RADIX);
+        temps.push_back(counts);
+        uint64_t* scanned = dalloc_n<uint64_t>(c, tiles * RADIX + 1);
+        temps.push_back(scanned);
+        hipLaunchKernelGGL((k_tile_counts<NT, IPT>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin, a.n, a.shift,
+                           a.dbits, counts);
+        HIPCHK(hipGetLastError());
+        scan_u32_u64(c, counts, scanned, tiles * RADIX, false);
+        off = scanned;
+        if (final)
+            hipLaunchKernelGGL((k_onesweep<NT, IPT, true, false>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin,
+                               a.vin, a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch,
+                               a.status, a.fo);
+        else
+            hipLaunchKernelGGL((k_onesweep<NT, IPT, false, false>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin,
+                               a.vin, a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch,
+                               a.status, a.fo);
+    } else if (final) {
+        hipLaunchKernelGGL((k_onesweep<NT, IPT, true, true>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin, a.vin,
+                           a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch, a.status, a.fo);
+    } else {
+        hipLaunchKernelGGL((k_onesweep<NT, IPT, false, true>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin,
+                           a.vin, a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch, a.status,
+                           a.fo);
+    }
+    HIPCHK(hipGetLastError());
+    for (void* p : temps) dfree(c, p);   // stream-ordered release
 }
 
 struct Variant {
@@ -376,6 +432,131 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
 }
 
 }  // namespace snnc
+
+// ------------------------------------------------------------------ autotuner
+namespace snnc {
+namespace {
+
+__global__ void k_random_keys(uint64_t* keys, uint32_t* vals, uint64_t n, uint32_t bit_lo, uint32_t bits,
+                              uint32_t seed) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 b = draw(seed, 0x7ea5u, i, PURPOSE_IDX);
+    const uint64_t r = ((uint64_t)b.y << 32) | b.x;
+    keys[i] = bits >= 64 ? r : ((r & ((1ull << bits) - 1)) << bit_lo);
+    vals[i] = (uint32_t)i;
+}
+
+struct TuneKey {
+    int size_class;   // floor(log2 n)
+    uint32_t bits;
+    bool operator<(const TuneKey& o) const { return size_class != o.size_class ? size_class < o.size_class : bits < o.bits; }
+};
+
+std::map<TuneKey, std::pair<int, int>>& tune_cache() {
+    static std::map<TuneKey, std::pair<int, int>> m;
+    return m;
+}
+
+int log2_floor(uint64_t n) {
+    int l = 0;
+    while (n >>= 1) ++l;
+    return l;
+}
+
+}  // namespace
+
+// Time every (pass algorithm, tile shape) on n synthetic keys with `bits`
+// sorted bits; keep the fastest in the context and in the process cache.
+void autotune_sort(Ctx& c, uint64_t n, uint32_t bits, int* mode_out, int* variant_out, float* ms_out) {
+    const TuneKey key{log2_floor(std::max<uint64_t>(n, 1)), bits};
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+        c.sort_mode = it->second.first;
+        c.sort_variant = it->second.second;
+        *mode_out = c.sort_mode;
+        *variant_out = c.sort_variant;
+        *ms_out = -1.f;
+        return;
+    }
+    uint64_t* k0 = dalloc_n<uint64_t>(c, n);
+    uint64_t* k1 = dalloc_n<uint64_t>(c, n);
+    uint32_t* v0 = dalloc_n<uint32_t>(c, n);
+    uint32_t* v1 = dalloc_n<uint32_t>(c, n);
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    int best_mode = 0, best_var = 0;
+    float best = 1e30f;
+    const int saved_mode = c.sort_mode, saved_var = c.sort_variant;
+    const bool saved_timing = c.timing;
+    c.timing = false;
+    try {
+        for (int mode = 0; mode < 2; ++mode) {
+            for (int v = 0; v < N_VARIANTS; ++v) {
+                c.sort_mode = mode;
+                c.sort_variant = v;
+                float t_best = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    hipLaunchKernelGGL(k_random_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, k0, v0,
+                                       n, 16, bits, 1234u);
+                    HIPCHK(hipGetLastError());
+                    HIPCHK(hipEventRecord(a, c.stream));
+                    radix_sort(c, k0, v0, k1, v1, n, 16, 16 + bits, nullptr, nullptr);
+                    HIPCHK(hipEventRecord(b, c.stream));
+                    HIPCHK(hipEventSynchronize(b));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, a, b));
+                    t_best = std::min(t_best, ms);
+                }
+                if (t_best < best) {
+                    best = t_best;
+                    best_mode = mode;
+                    best_var = v;
+                }
+            }
+        }
+    } catch (...) {
+        c.sort_mode = saved_mode;
+        c.sort_variant = saved_var;
+        c.timing = saved_timing;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        dfree(c, k0); dfree(c, k1); dfree(c, v0); dfree(c, v1);
+        throw;
+    }
+    c.timing = saved_timing;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    dfree(c, k0); dfree(c, k1); dfree(c, v0); dfree(c, v1);
+    c.sort_mode = best_mode;
+    c.sort_variant = best_var;
+    tune_cache()[key] = {best_mode, best_var};
+    *mode_out = best_mode;
+    *variant_out = best_var;
+    *ms_out = best;
+}
+
+}  // namespace snnc
+
+extern "C" snnc_status snnc_autotune_sort(snnc_ctx* ctx, uint64_t n, uint32_t bits, int32_t* mode_out,
+                                          int32_t* variant_out, float* ms_out) {
+    using namespace snnc;
+    if (!ctx || !mode_out || !variant_out || !ms_out || bits == 0 || bits > 48) return SNNC_EINVAL;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        int m = 0, v = 0;
+        float ms = 0.f;
+        autotune_sort(*ctx, std::max<uint64_t>(n, 1), bits, &m, &v, &ms);
+        *mode_out = m;
+        *variant_out = v;
+        *ms_out = ms;
+        return SNNC_OK;
+    } catch (const Error& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+}
 
 extern "C" snnc_status snnc_sort_pairs(snnc_ctx* ctx, uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
                                        uint32_t* vals_tmp, uint64_t n, uint32_t bit_lo, uint32_t bit_hi,

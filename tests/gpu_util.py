@@ -8,7 +8,7 @@ import oracle
 import paper_2512_09502_amd as snnc
 
 GEN_ARRAYS = ["gen_src", "gen_tgt", "gen_delay", "gen_weight"]
-PREP_ARRAYS = ["src", "tgt", "delay", "weight", "row_ptr", "r_off", "r_val", "img_base", "s_off", "s_val",
+PREP_ARRAYS = ["src", "tgt", "delay", "weight", "row_ptr", "r_off", "r_val", "l_val", "img_base", "s_off", "s_val",
                "tp_ptr", "t_val", "p_val", "groups", "h_off", "h_val", "i_val", "gq_ptr", "g_val", "q_val"]
 WEIGHT_ULP = 2
 

@@ -17,11 +17,13 @@ def net():
     n.close()
 
 
+@pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("variant", range(6))
 @pytest.mark.parametrize("n,lo,hi", [(1, 0, 8), (4095, 16, 50), (100003, 16, 50), (333333, 0, 64), (77777, 3, 9),
                                      (250000, 16, 20)])
-def test_sort_pairs_matches_stable_argsort(net, variant, n, lo, hi):
+def test_sort_pairs_matches_stable_argsort(net, mode, variant, n, lo, hi):
     import torch
+    net.tune("sort_mode", mode)
     rng = np.random.default_rng(n + variant + 31 * lo)
     keys = rng.integers(0, 2**63, size=n, dtype=np.int64).view(np.uint64)
     if hi - lo <= 8:
@@ -33,3 +35,17 @@ def test_sort_pairs_matches_stable_argsort(net, variant, n, lo, hi):
     order = np.argsort(keys & mask, kind="stable")
     np.testing.assert_array_equal(v.cpu().numpy(), order.astype(np.int32))
     np.testing.assert_array_equal(k.cpu().numpy().view(np.uint64), keys[order])
+
+
+def test_autotune_picks_a_valid_setting_and_caches_it(net):
+    import torch
+    r = net.autotune_sort(200003, 30)
+    assert r["sort_mode"] in (0, 1) and 0 <= r["sort_variant"] < 6 and r["ms"] > 0
+    again = net.autotune_sort(200003 + 5, 30)        # same size class: served from the cache
+    assert (again["sort_mode"], again["sort_variant"]) == (r["sort_mode"], r["sort_variant"]) and again["ms"] == -1
+    rng = np.random.default_rng(5)
+    keys = rng.integers(0, 2**46, size=200003, dtype=np.int64).view(np.uint64)
+    vals = np.arange(keys.size, dtype=np.int32)
+    k, v = net.sort_pairs(torch.from_numpy(keys.view(np.int64)).cuda(), torch.from_numpy(vals).cuda(), 16, 46)
+    order = np.argsort(keys >> np.uint64(16), kind="stable")
+    np.testing.assert_array_equal(v.cpu().numpy(), order.astype(np.int32))
