@@ -45,6 +45,8 @@ def expected_conns(script) -> int:
 def build_once(script, P_local: int, timing: bool):
     import paper_2512_09502_amd as snnc
     net = snnc.Network(script["P"], P_local, script["seed"], script["dt"])
+    if script.get("map_policy") is not None:
+        net.set_map_policy(*script["map_policy"])
     if timing:
         net.set_timing(True)
     hint = expected_conns(script)
@@ -233,6 +235,13 @@ def main():
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--map-policy", default=None,
+                    help="numbering,sources,xi: numbering 0 canonical / 1 call order; sources 0 used / "
+                         "1 threshold / 2 all passed")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the sort autotuner in the first (untimed) warmup step")
+    ap.add_argument("--pmc-calibrate", action="store_true",
+                    help="after the timed steps, one plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the construction of one host's share needs no second GPU "
@@ -243,12 +252,28 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    import paper_2512_09502_amd as snnc
     if args.workload == "served":
         return served(args)
     script = workload(args.workload, args.scale)
+    if args.map_policy:
+        n_, s_, x_ = args.map_policy.split(",")
+        script["map_policy"] = (int(n_), int(s_), float(x_))
 
-    for _ in range(args.warmup):
+    tuning = None
+    for w in range(args.warmup):
         net = build_once(script, 0, timing=False)
+        if w == 0 and args.autotune:
+            # sort autotuner (untimed): picks the pass algorithm and tile shape for
+            # this size class; later contexts in the process use its choice
+            st = net.stats()
+            n_w = net.count("src")
+            net.close()
+            tuner = snnc.Network(1, 0, 1, 0.1)
+            tuning = tuner.autotune_sort(n_w, st["key_bits"])
+            tuning.update({"n": n_w, "bits": st["key_bits"]})
+            tuner.close()
+            continue
         net.close()
     torch.cuda.synchronize()
 
@@ -270,6 +295,11 @@ def main():
         net.close()
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
+    if args.pmc_calibrate:   # outside the timed region: a copy of known size for the HBM counters
+        x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        torch.empty_like(x).copy_(x)
+        torch.cuda.synchronize()
+        del x
     ms_per_step = 1e3 * total / args.steps
     value = n_conn * args.steps / total / 1e9
 
@@ -301,7 +331,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": script["name"], "connections": n_conn, "calls": stats["n_calls"],
                    "neurons": stats["M_local"], "images": stats["n_images"], "key_bits": stats["key_bits"],
-                   "sort_passes": stats["sort_passes"], "scale": args.scale},
+                   "sort_passes": stats["sort_passes"], "scale": args.scale,
+                   "map_policy": script.get("map_policy")},
+        "sort_tuning": tuning,
         "step_ms": {"min": round(1e3 * min(times), 3), "median": round(1e3 * sorted(times)[len(times) // 2], 3)},
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in sorted(kt_total.items(), key=lambda kv: -kv[1][1])},
         "dominant_kernel": dom[0],

@@ -330,8 +330,9 @@ typedef enum { SNNC_IMAGES_USED = 0, SNNC_IMAGES_THRESHOLD = 1, SNNC_IMAGES_ALL 
 snnc_status snnc_set_map_policy(snnc_ctx* ctx, int32_t numbering, int32_t image_sources, double xi);
 
 /* Tuning knobs of the context, by name.  "sort_variant": tile shape of the
- * radix-sort passes, 0 .. 5 (threads x keys per thread: 256x16, 256x8,
- * 512x8, 512x16, 1024x8, 256x12).  SNNC_EINVAL for an unknown key or value. */
+ * radix-sort passes, 0 .. 5 (threads x keys per thread: 1024x8 (default),
+ * 256x8, 512x8, 512x16, 256x16, 256x12).  SNNC_EINVAL for an unknown key or
+ * value. */
 snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
 /* "sort_mode": 0 = single-pass onesweep passes (decoupled look-back), 1 =
  * reduce-then-scan passes (per-tile digit counts, one scan, scatter).
@@ -343,9 +344,11 @@ snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
 /* Autotuner of the source-major sort: times every pass algorithm and tile
  * shape (sort_mode x sort_variant) on n synthetic keys with `bits` sorted
  * bits (1 .. 48), on the context's device, and sets the fastest on the
- * context.  Results are cached per (floor(log2 n), bits) for the process: a
- * cached size class returns at once with *ms_out = -1.  Allocates scratch of
- * about 24 n bytes.  Errors: SNNC_EINVAL, SNNC_ENOMEM, SNNC_EDEVICE. */
+ * context.  Results are cached per (floor(log2 n), bits) for the process and
+ * used by every later sort of that size class on any context whose sort
+ * settings were not set with snnc_tune; a cached size class returns at once
+ * with *ms_out = -1.  Allocates scratch of about 24 n bytes.
+ * Errors: SNNC_EINVAL, SNNC_ENOMEM, SNNC_EDEVICE. */
 snnc_status snnc_autotune_sort(snnc_ctx* ctx, uint64_t n, uint32_t bits, int32_t* mode_out, int32_t* variant_out,
                                float* ms_out);
 

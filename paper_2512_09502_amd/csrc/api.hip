@@ -719,9 +719,11 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
         if (!strcmp(key, "sort_variant")) {
             if (value < 0 || value >= sort_variant_count()) raise(SNNC_EINVAL, "sort_variant out of range");
             c->sort_variant = (int)value;
+            c->sort_pinned = true;
         } else if (!strcmp(key, "sort_mode")) {
             if (value < 0 || value > 1) raise(SNNC_EINVAL, "sort_mode out of range");
             c->sort_mode = (int)value;
+            c->sort_pinned = true;
         } else if (!strcmp(key, "map_path")) {
             if (value < 0 || value > 1) raise(SNNC_EINVAL, "map_path out of range");
             c->force_map_path = value == 1;

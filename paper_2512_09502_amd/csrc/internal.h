@@ -147,6 +147,7 @@ struct Ctx {
     size_t lookback_bytes = 0;
     int sort_variant = 0;                // tile shape of the radix passes (tunable)
     int sort_mode = 0;                   // 0: onesweep (look-back), 1: reduce-then-scan (tunable)
+    bool sort_pinned = false;            // set by hand: the autotuner's process-wide choice is not used
     // map policy: image numbering (0 canonical, 1 call order), image sources
     // (0 used, 1 threshold heuristic, 2 all passed), threshold xi
     int numbering = 0, img_sources = 0;

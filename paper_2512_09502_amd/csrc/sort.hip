@@ -242,6 +242,7 @@ struct PassArgs {
     uint32_t epoch;
     uint32_t* status;
     FinalOut fo;
+    int mode;   // 0: onesweep, 1: reduce-then-scan
 };
 
 // Digit counts of every tile of a pass, digit-major (counts[d * tiles + t]),
@@ -274,7 +275,7 @@ void launch_pass(Ctx& c, const PassArgs& a, bool final) {
     const uint64_t tiles = (a.n + TILE - 1) / TILE;
     const uint64_t* off = a.off;
     std::vector<void*> temps;
-    if (c.sort_mode == 1) {
+    if (a.mode == 1) {
         // reduce-then-scan: per-tile counts, one scan, scatter with known bases
         uint32_t* counts = dalloc_n<uint32_t>(c, tiles * RADIX);
         temps.push_back(counts);
@@ -308,18 +309,39 @@ void launch_pass(Ctx& c, const PassArgs& a, bool final) {
 struct Variant {
     int nt, ipt;
 };
-// tile shapes available to the tuner; index 0 is the default
-constexpr Variant VARIANTS[] = {{256, 16}, {256, 8}, {512, 8}, {512, 16}, {1024, 8}, {256, 12}};
+// tile shapes available to the tuner; index 0 is the default (the fastest
+// measured for sorts of 1e8 .. 2e9 pairs: 8192-pair tiles give digit runs of
+// 32 pairs on average, so the scattered writes cover whole cache lines)
+constexpr Variant VARIANTS[] = {{1024, 8}, {256, 8}, {512, 8}, {512, 16}, {256, 16}, {256, 12}};
 constexpr int N_VARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
+
+// autotuner results for the process: (pass algorithm, tile shape) per size
+// class; used by every context whose sort settings were not set by hand
+struct TuneKey {
+    int size_class;   // floor(log2 n)
+    uint32_t bits;
+    bool operator<(const TuneKey& o) const { return size_class != o.size_class ? size_class < o.size_class : bits < o.bits; }
+};
+
+std::map<TuneKey, std::pair<int, int>>& tune_cache() {
+    static std::map<TuneKey, std::pair<int, int>> m;
+    return m;
+}
+
+int log2_floor(uint64_t n) {
+    int l = 0;
+    while (n >>= 1) ++l;
+    return l;
+}
 
 void launch_variant(Ctx& c, int v, const PassArgs& a, bool final) {
     switch (v) {
     case 1: launch_pass<256, 8>(c, a, final); break;
     case 2: launch_pass<512, 8>(c, a, final); break;
     case 3: launch_pass<512, 16>(c, a, final); break;
-    case 4: launch_pass<1024, 8>(c, a, final); break;
+    case 4: launch_pass<256, 16>(c, a, final); break;
     case 5: launch_pass<256, 12>(c, a, final); break;
-    default: launch_pass<256, 16>(c, a, final); break;
+    default: launch_pass<1024, 8>(c, a, final); break;
     }
 }
 
@@ -348,7 +370,15 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
     uint32_t passes, dbits;
     radix_plan(bit_hi > bit_lo ? bit_hi - bit_lo : 0, passes, dbits);
     if (passes > 8) raise(SNNC_EUNSUPPORTED, "radix sort over more than 64 bits");
-    const int variant = (c.sort_variant >= 0 && c.sort_variant < N_VARIANTS) ? c.sort_variant : 0;
+    int variant = (c.sort_variant >= 0 && c.sort_variant < N_VARIANTS) ? c.sort_variant : 0;
+    int mode = c.sort_mode;
+    if (!c.sort_pinned) {
+        auto it = tune_cache().find(TuneKey{log2_floor(std::max<uint64_t>(n, 1)), bit_hi > bit_lo ? bit_hi - bit_lo : 0});
+        if (it != tune_cache().end()) {
+            mode = it->second.first;
+            variant = it->second.second;
+        }
+    }
     const uint64_t tile = (uint64_t)VARIANTS[variant].nt * VARIANTS[variant].ipt;
     std::vector<void*> temps;
     auto cleanup = [&] {
@@ -409,7 +439,7 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
             PassArgs a{kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, bit_lo + p * dbits,
                        pass_width(bit_lo, bit_hi, dbits, p),
                        off + (size_t)p * RADIX, (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status,
-                       final_out ? *final_out : FinalOut{}};
+                       final_out ? *final_out : FinalOut{}, mode};
             tstart(c, last ? "sort_pass_final" : "sort_pass");
             launch_variant(c, variant, a, last);
             tstop(c);
@@ -447,23 +477,6 @@ __global__ void k_random_keys(uint64_t* keys, uint32_t* vals, uint64_t n, uint32
     vals[i] = (uint32_t)i;
 }
 
-struct TuneKey {
-    int size_class;   // floor(log2 n)
-    uint32_t bits;
-    bool operator<(const TuneKey& o) const { return size_class != o.size_class ? size_class < o.size_class : bits < o.bits; }
-};
-
-std::map<TuneKey, std::pair<int, int>>& tune_cache() {
-    static std::map<TuneKey, std::pair<int, int>> m;
-    return m;
-}
-
-int log2_floor(uint64_t n) {
-    int l = 0;
-    while (n >>= 1) ++l;
-    return l;
-}
-
 }  // namespace
 
 // Time every (pass algorithm, tile shape) on n synthetic keys with `bits`
@@ -489,8 +502,9 @@ void autotune_sort(Ctx& c, uint64_t n, uint32_t bits, int* mode_out, int* varian
     int best_mode = 0, best_var = 0;
     float best = 1e30f;
     const int saved_mode = c.sort_mode, saved_var = c.sort_variant;
-    const bool saved_timing = c.timing;
+    const bool saved_timing = c.timing, saved_pinned = c.sort_pinned;
     c.timing = false;
+    c.sort_pinned = true;   // each candidate runs as set
     try {
         for (int mode = 0; mode < 2; ++mode) {
             for (int v = 0; v < N_VARIANTS; ++v) {
@@ -520,12 +534,14 @@ void autotune_sort(Ctx& c, uint64_t n, uint32_t bits, int* mode_out, int* varian
         c.sort_mode = saved_mode;
         c.sort_variant = saved_var;
         c.timing = saved_timing;
+        c.sort_pinned = saved_pinned;
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
         dfree(c, k0); dfree(c, k1); dfree(c, v0); dfree(c, v1);
         throw;
     }
     c.timing = saved_timing;
+    c.sort_pinned = saved_pinned;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     dfree(c, k0); dfree(c, k1); dfree(c, v0); dfree(c, v1);
