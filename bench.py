@@ -47,6 +47,8 @@ def build_once(script, P_local: int, timing: bool):
     net = snnc.Network(script["P"], P_local, script["seed"], script["dt"])
     if script.get("map_policy") is not None:
         net.set_map_policy(*script["map_policy"])
+    if script.get("sort_variant") is not None:
+        net.tune("sort_variant", script["sort_variant"])
     if timing:
         net.set_timing(True)
     hint = expected_conns(script)
@@ -238,6 +240,7 @@ def main():
     ap.add_argument("--map-policy", default=None,
                     help="numbering,sources,xi: numbering 0 canonical / 1 call order; sources 0 used / "
                          "1 threshold / 2 all passed")
+    ap.add_argument("--sort-variant", type=int, default=None, help="radix-pass tile shape (snnc_tune)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the sort autotuner in the first (untimed) warmup step")
     ap.add_argument("--pmc-calibrate", action="store_true",
@@ -256,6 +259,8 @@ def main():
     if args.workload == "served":
         return served(args)
     script = workload(args.workload, args.scale)
+    if args.sort_variant is not None:
+        script["sort_variant"] = args.sort_variant
     if args.map_policy:
         n_, s_, x_ = args.map_policy.split(",")
         script["map_policy"] = (int(n_), int(s_), float(x_))

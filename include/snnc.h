@@ -330,16 +330,21 @@ typedef enum { SNNC_IMAGES_USED = 0, SNNC_IMAGES_THRESHOLD = 1, SNNC_IMAGES_ALL 
 snnc_status snnc_set_map_policy(snnc_ctx* ctx, int32_t numbering, int32_t image_sources, double xi);
 
 /* Tuning knobs of the context, by name.  "sort_variant": tile shape of the
- * radix-sort passes, 0 .. 5 (threads x keys per thread: 1024x8 (default),
- * 256x8, 512x8, 512x16, 256x16, 256x12).  SNNC_EINVAL for an unknown key or
- * value. */
+ * radix-sort passes, 0 .. 10, as threads x keys per thread: 0 = 512x16 with
+ * keys and payloads staged through LDS one after the other (70 KB, two
+ * workgroups per compute unit; default), 1 = 256x8, 2 = 512x8, 3 = 512x16,
+ * 4 = 256x16, 5 = 256x12, 6 = 1024x8, and staged in two phases like 0:
+ * 7 = 1024x8, 8 = 512x8, 9 = 512x12, 10 = 256x16.  SNNC_EINVAL for an unknown
+ * key or value. */
 snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
 /* "sort_mode": 0 = single-pass onesweep passes (decoupled look-back), 1 =
  * reduce-then-scan passes (per-tile digit counts, one scan, scatter).
  * Further keys: "fuse_batches" (0/1, default 1), "fused_wgs_per_cu"
  * (workgroups per compute unit of the persistent batch launch, 1 .. 64) and
  * "map_path" (0: automatic, 1: number images before the sort even under the
- * default map policy, the path the other policies take). */
+ * default map policy, the path the other policies take) and "digit_bits"
+ * (0: 9-bit digits, 512 buckets, when they save a pass and the tile has at
+ * least 512 threads; 8 or 9: forced where the tile allows). */
 
 /* Autotuner of the source-major sort: times every pass algorithm and tile
  * shape (sort_mode x sort_variant) on n synthetic keys with `bits` sorted

@@ -724,6 +724,9 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
             if (value < 0 || value > 1) raise(SNNC_EINVAL, "sort_mode out of range");
             c->sort_mode = (int)value;
             c->sort_pinned = true;
+        } else if (!strcmp(key, "digit_bits")) {
+            if (value != 0 && value != 8 && value != 9) raise(SNNC_EINVAL, "digit_bits must be 0, 8 or 9");
+            c->digit_bits = (int)value;
         } else if (!strcmp(key, "map_path")) {
             if (value < 0 || value > 1) raise(SNNC_EINVAL, "map_path out of range");
             c->force_map_path = value == 1;

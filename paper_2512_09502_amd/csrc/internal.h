@@ -148,6 +148,7 @@ struct Ctx {
     int sort_variant = 0;                // tile shape of the radix passes (tunable)
     int sort_mode = 0;                   // 0: onesweep (look-back), 1: reduce-then-scan (tunable)
     bool sort_pinned = false;            // set by hand: the autotuner's process-wide choice is not used
+    int digit_bits = 0;                  // 0: 9-bit digits when they save a pass; 8 or 9: forced
     // map policy: image numbering (0 canonical, 1 call order), image sources
     // (0 used, 1 threshold heuristic, 2 all passed), threshold xi
     int numbering = 0, img_sources = 0;
@@ -246,7 +247,14 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
                uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist /* may be null */,
                const FinalOut* final_out);
 // digit histograms for all passes of a sort (radix 256, D bits per pass)
-void radix_plan(uint32_t bits, uint32_t& passes, uint32_t& digit_bits);
+// digit histograms: entries per pass (buckets of digits up to 9 bits)
+constexpr int HIST_STRIDE = 512;
+struct SortPlan {
+    int mode = 0, variant = 0;
+    uint32_t passes = 0, dbits = 0;
+    bool wide = false;   // 9-bit digits
+};
+SortPlan plan_sort(const Ctx& c, uint64_t n, uint32_t bits);
 int sort_variant_count();
 
 // prepare pipeline (prepare.hip)

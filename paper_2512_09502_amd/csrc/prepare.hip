@@ -36,7 +36,22 @@ struct CallD {
     uint32_t a;      // alpha + 1
     uint32_t order;  // position of the call in call order
     uint32_t flag;   // 1: only the sources its local connections use get images
+    uint32_t uniform;   // 1: all source segments have the same length (segment = ordinal / length)
+    FastDiv seg_div;
 };
+
+// segment lookup by division when every source segment of the call has the same length
+CallD make_calld(const Call& cl, uint32_t order, uint32_t flag) {
+    CallD d{cl.gen_begin, cl.dS, (uint32_t)cl.S.seg.size(), (uint32_t)(cl.alpha + 1), order, flag, 0, FastDiv{}};
+    const auto& seg = cl.S.seg;
+    bool uniform = seg.size() > 1 && seg[0].n > 0 && cl.S.total < (1ull << 31);
+    for (const auto& g : seg) uniform = uniform && g.n == seg[0].n;
+    if (uniform) {
+        d.uniform = 1;
+        d.seg_div = make_fastdiv(seg[0].n);
+    }
+    return d;
+}
 
 struct Lookup {
     const CallD* calls;
@@ -83,9 +98,13 @@ struct SourceCursor {
         call_at(L, i);
         if (ord < seg_lo || ord >= seg_hi) {
             uint32_t a = 0, b = call.nS;
-            while (b - a > 1) {
-                const uint32_t m = (a + b) >> 1;
-                if (call.S[m].ord_begin <= ord) a = m; else b = m;
+            if (call.uniform) {
+                a = fastdiv(ord, call.seg_div);
+            } else {
+                while (b - a > 1) {
+                    const uint32_t m = (a + b) >> 1;
+                    if (call.S[m].ord_begin <= ord) a = m; else b = m;
+                }
             }
             const SegD s = call.S[a];
             seg_lo = s.ord_begin;
@@ -119,8 +138,8 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
                                               const uint64_t* word_rank, const int32_t* Lmap, uint32_t M_local,
                                               uint32_t tgt_shift,
                                               uint32_t dbits, uint32_t passes, uint64_t* keys, uint64_t* hist) {
-    __shared__ uint32_t h[8 * 256];
-    for (uint32_t i = threadIdx.x; i < passes * 256; i += PNT) h[i] = 0;
+    __shared__ uint32_t h[8 * HIST_STRIDE];
+    for (uint32_t i = threadIdx.x; i < passes * HIST_STRIDE; i += PNT) h[i] = 0;
     __syncthreads();
     const uint32_t dmask = (1u << dbits) - 1;
     uint64_t lo, hi;
@@ -143,10 +162,10 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
             keys[i] = key;
         }
         for (uint32_t p = 0; p < passes; ++p)
-            wave_hist_add(&h[p * 256], (uint32_t)((key >> (16 + p * dbits)) & dmask), valid);
+            wave_hist_add(&h[p * HIST_STRIDE], (uint32_t)((key >> (16 + p * dbits)) & dmask), valid);
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < passes * 256; i += PNT)
+    for (uint32_t i = threadIdx.x; i < passes * HIST_STRIDE; i += PNT)
         if (h[i]) atomicAdd((unsigned long long*)&hist[i], (unsigned long long)h[i]);
 }
 
@@ -645,11 +664,9 @@ void prepare_all(Ctx& c) {
         std::vector<CallD> calls;
         for (uint32_t k = 0; k < n_calls; ++k) {
             const Call& cl = c.calls[k];
-            if (cl.gen_count)
-                calls.push_back(CallD{cl.gen_begin, cl.dS, (uint32_t)cl.S.seg.size(), (uint32_t)(cl.alpha + 1), k,
-                                      flag_local[k]});
+            if (cl.gen_count) calls.push_back(make_calld(cl, k, flag_local[k]));
         }
-        if (calls.empty()) calls.push_back(CallD{0, nullptr, 0, 0, 0, 0});
+        if (calls.empty()) calls.push_back(CallD{0, nullptr, 0, 0, 0, 0, 0, FastDiv{}});
         CallD* d_calls = static_cast<CallD*>(tmp(calls.size() * sizeof(CallD)));
         upload(c, d_calls, calls.data(), calls.size() * sizeof(CallD));
         uint64_t* d_hb = static_cast<uint64_t*>(tmp((P + 1) * 8));
@@ -765,8 +782,8 @@ void prepare_all(Ctx& c) {
         const uint32_t sbits = bits_for(prefix_span);
         c.key_bits = sbits + tbits;
         if (sbits + tbits > 48) raise(SNNC_EUNSUPPORTED, "source and target ids need more than 48 key bits");
-        uint32_t passes, dbits;
-        radix_plan(sbits + tbits, passes, dbits);
+        const SortPlan plan = plan_sort(c, N, sbits + tbits);   // the sort below takes the same plan
+        const uint32_t passes = plan.passes, dbits = plan.dbits;
         const bool unpack_in_sort = !remote_net || mapped;
         int32_t* o_src = nullptr;
         uint64_t* row_ptr = nullptr;
@@ -775,8 +792,8 @@ void prepare_all(Ctx& c) {
         uint32_t* vals1 = nullptr;
         if (N) {
             keys0 = static_cast<uint64_t*>(tmp(N * 8));
-            uint64_t* hist = static_cast<uint64_t*>(tmp(8 * 256 * 8));
-            HIPCHK(hipMemsetAsync(hist, 0, 8 * 256 * 8, c.stream));
+            uint64_t* hist = static_cast<uint64_t*>(tmp(8 * HIST_STRIDE * 8));
+            HIPCHK(hipMemsetAsync(hist, 0, 8 * HIST_STRIDE * 8, c.stream));
             tstart(c, "prep_keys");
             hipLaunchKernelGGL(k_keys, dim3(grid_for(N, 8192)), dim3(PNT), 0, c.stream, L, c.g_src, c.g_tgt, c.g_delay,
                                N, mapped ? bits : (const uint32_t*)nullptr, mapped ? word_rank : (const uint64_t*)nullptr,

@@ -17,7 +17,8 @@ namespace snnc {
 
 namespace {
 
-constexpr int RADIX = 256;
+constexpr int RADIX = 256;          // buckets of an 8-bit digit
+constexpr int HSTRIDE = HIST_STRIDE; // histogram entries per pass (up to 9-bit digits)
 
 // look-back status word: [63:62] flag, [61:40] epoch, [39:0] count
 constexpr uint64_t FLAG_AGG = 1ull << 62;
@@ -44,8 +45,8 @@ __host__ __device__ __forceinline__ uint32_t pass_width(uint32_t bit_lo, uint32_
 
 __global__ __launch_bounds__(HNT) void k_hist(const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t bit_hi,
                                               uint32_t dbits, uint32_t passes, uint64_t* hist) {
-    __shared__ uint32_t h[8 * RADIX];
-    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += HNT) h[i] = 0;
+    __shared__ uint32_t h[8 * HSTRIDE];
+    for (uint32_t i = threadIdx.x; i < passes * HSTRIDE; i += HNT) h[i] = 0;
     __syncthreads();
     for (uint64_t base = (uint64_t)blockIdx.x * HNT; base < n; base += (uint64_t)gridDim.x * HNT) {
         const uint64_t i = base + threadIdx.x;
@@ -53,28 +54,33 @@ __global__ __launch_bounds__(HNT) void k_hist(const uint64_t* keys, uint64_t n, 
         const uint64_t k = valid ? keys[i] : 0;
         for (uint32_t p = 0; p < passes; ++p) {
             const uint32_t mask = (1u << pass_width(bit_lo, bit_hi, dbits, p)) - 1;
-            wave_hist_add(&h[p * RADIX], (uint32_t)((k >> (bit_lo + p * dbits)) & mask), valid);
+            wave_hist_add(&h[p * HSTRIDE], (uint32_t)((k >> (bit_lo + p * dbits)) & mask), valid);
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += HNT)
+    for (uint32_t i = threadIdx.x; i < passes * HSTRIDE; i += HNT)
         if (h[i]) atomicAdd((unsigned long long*)&hist[i], (unsigned long long)h[i]);
 }
 
-// exclusive scan over the RADIX buckets of each pass (one workgroup per pass)
-__global__ __launch_bounds__(RADIX) void k_hist_scan(const uint64_t* hist, uint64_t* off) {
-    __shared__ uint64_t scratch[RADIX / 64];
-    const uint64_t v = hist[blockIdx.x * RADIX + threadIdx.x];
+// exclusive scan over the buckets of each pass (one workgroup per pass)
+__global__ __launch_bounds__(HSTRIDE) void k_hist_scan(const uint64_t* hist, uint64_t* off) {
+    __shared__ uint64_t scratch[HSTRIDE / 64];
+    const uint64_t v = hist[blockIdx.x * HSTRIDE + threadIdx.x];
     uint64_t tot;
-    const uint64_t ex = block_excl_scan<RADIX, uint64_t>(v, scratch, &tot);
-    off[blockIdx.x * RADIX + threadIdx.x] = ex;
+    const uint64_t ex = block_excl_scan<HSTRIDE, uint64_t>(v, scratch, &tot);
+    off[blockIdx.x * HSTRIDE + threadIdx.x] = ex;
 }
 
 // LB = true: onesweep (dynamic tile order, decoupled look-back, digit_off =
 // exclusive digit totals).  LB = false: the scatter of a reduce-then-scan pass
 // (tile = block index, digit_off = exclusive scan of the per-tile counts laid
 // out digit-major, so entry d * tiles + t is the tile's global base for d).
-template <int NT, int IPT, bool FINAL, bool LB>
+// RB: buckets of the digit (256, or 512 for 9-bit digits).  SPLIT: stage the
+// keys, then the payloads (with their digits), through one LDS buffer of
+// 8 B per pair that also holds the per-wave digit counts while the tile is
+// ranked: about 70 KB for an 8192-pair tile, so two workgroups share a compute
+// unit and one's ranking and look-back overlap the other's memory traffic.
+template <int NT, int IPT, bool FINAL, bool LB, int RB, bool SPLIT>
 __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                  uint64_t* __restrict__ kout, uint32_t* __restrict__ vout, uint64_t n,
                                                  uint32_t shift, uint32_t dbits, const uint64_t* __restrict__ digit_off,
@@ -82,18 +88,23 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
                                                  uint32_t* status, FinalOut fo) {
     constexpr int TILE = NT * IPT;
     constexpr int WAVES = NT / 64;
-    static_assert(NT >= RADIX, "one thread per digit");
+    static_assert(NT >= RB, "one thread per digit");
+    constexpr int STAGE_K = TILE * 8;            // bytes of the staged keys
+    constexpr int WH = WAVES * RB * 4;           // bytes of the per-wave digit counts
+    static_assert(!SPLIT || (WH <= STAGE_K && TILE * 6 <= STAGE_K), "split staging layout");
     __shared__ uint32_t s_tile;
-    __shared__ uint32_t wave_hist[WAVES][RADIX];
-    __shared__ uint32_t tile_start[RADIX];       // first LDS slot of each digit in the tile
-    __shared__ uint64_t glob_base[RADIX];        // global position of the tile's first key of each digit
+    __shared__ uint32_t tile_start[RB];          // first LDS slot of each digit in the tile
+    __shared__ uint64_t glob_base[RB];           // global position of the tile's first key of each digit
     __shared__ uint64_t scan_scratch[NT / 64];
-    __shared__ uint64_t stage_k[TILE];
-    __shared__ uint32_t stage_v[TILE];
+    __shared__ __align__(16) unsigned char pool[SPLIT ? STAGE_K : STAGE_K + TILE * 4 + WH];
+    auto wave_hist = reinterpret_cast<uint32_t (*)[RB]>(SPLIT ? pool : pool + STAGE_K + TILE * 4);
+    uint64_t* stage_k = reinterpret_cast<uint64_t*>(pool);
+    uint32_t* stage_v = reinterpret_cast<uint32_t*>(SPLIT ? pool : pool + STAGE_K);
+    uint16_t* stage_d = reinterpret_cast<uint16_t*>(pool + TILE * 4);   // SPLIT: digit of each staged payload
 
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (LB && threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
-    for (uint32_t i = threadIdx.x; i < WAVES * RADIX; i += NT) (&wave_hist[0][0])[i] = 0;
+    for (uint32_t i = threadIdx.x; i < WAVES * RB; i += NT) (&wave_hist[0][0])[i] = 0;
     __syncthreads();
     const uint64_t tile = LB ? (uint64_t)s_tile : (uint64_t)blockIdx.x;
     const uint64_t base = tile * TILE;
@@ -107,10 +118,8 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
         const uint64_t i = wbase + (uint64_t)k * 64;
-        if (i < n) {
-            key[k] = kin[i];
-            val[k] = vin[i];
-        }
+        key[k] = i < n ? kin[i] : 0ull;
+        val[k] = i < n ? vin[i] : 0u;
     }
     const uint64_t lt_mask = (1ull << lane) - 1;
 #pragma unroll
@@ -137,7 +146,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
 
     // per digit: tile count, per-wave offsets, look-back over earlier tiles
     const uint32_t d = threadIdx.x;
-    const bool digit_thread = d < RADIX;
+    const bool digit_thread = d < RB;
     uint32_t cnt = 0;
     uint32_t woff[WAVES];
     uint64_t excl = 0;
@@ -147,7 +156,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
             woff[w] = cnt;
             cnt += wave_hist[w][d];
         }
-        uint64_t* my = lookback + tile * RADIX + d;
+        uint64_t* my = lookback + tile * RB + d;
         if (!LB) {
             // offsets known from the reduce-then-scan counts
         } else if (tile == 0) {
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
             int64_t pred = (int64_t)tile - 1;
             uint32_t spins = 0;
             while (pred >= 0) {
-                const uint64_t st = __hip_atomic_load(lookback + (uint64_t)pred * RADIX + d, __ATOMIC_RELAXED,
+                const uint64_t st = __hip_atomic_load(lookback + (uint64_t)pred * RB + d, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
                 const uint64_t flag = st & (3ull << 62);
                 const uint32_t ep = (uint32_t)((st >> 40) & EPOCH_MAX);
@@ -188,6 +197,50 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
     }
     __syncthreads();
 
+    const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, n - base);
+    if constexpr (SPLIT) {
+        // slots first: the counts share the staging buffer
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const uint32_t dd = (uint32_t)((key[k] >> shift) & mask);
+            rank[k] += wave_hist[wave][dd];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < IPT; ++k)
+            if (wbase + (uint64_t)k * 64 < n) stage_k[rank[k]] = key[k];
+        __syncthreads();
+#pragma unroll 4
+        for (uint32_t s = threadIdx.x; s < tile_n; s += NT) {
+            const uint64_t k = stage_k[s];
+            const uint32_t dd = (uint32_t)((k >> shift) & mask);
+            const uint64_t g = glob_base[dd] + (s - tile_start[dd]);
+            if constexpr (FINAL) {
+                fo.src[g] = (int32_t)(k >> fo.tgt_shift);
+                fo.tgt[g] = (int32_t)((k >> 16) & fo.tgt_mask);
+                fo.delay[g] = (uint16_t)(k & 0xffffu);
+            } else {
+                kout[g] = k;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < IPT; ++k)
+            if (wbase + (uint64_t)k * 64 < n) {
+                stage_v[rank[k]] = val[k];
+                stage_d[rank[k]] = (uint16_t)((key[k] >> shift) & mask);
+            }
+        __syncthreads();
+#pragma unroll 4
+        for (uint32_t s = threadIdx.x; s < tile_n; s += NT) {
+            const uint32_t dd = stage_d[s];
+            const uint64_t g = glob_base[dd] + (s - tile_start[dd]);
+            if constexpr (FINAL) fo.weight[g] = __uint_as_float(stage_v[s]);
+            else vout[g] = stage_v[s];
+        }
+        return;
+    }
+
     // stage in digit order
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
@@ -201,7 +254,6 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
     }
     __syncthreads();
 
-    const uint32_t tile_n = (uint32_t)min((uint64_t)TILE, n - base);
 #pragma unroll 4
     for (uint32_t s = threadIdx.x; s < tile_n; s += NT) {
         const uint64_t k = stage_k[s];
@@ -247,12 +299,12 @@ struct PassArgs {
 
 // Digit counts of every tile of a pass, digit-major (counts[d * tiles + t]),
 // for the reduce-then-scan form of a pass.
-template <int NT, int IPT>
+template <int NT, int IPT, int RB>
 __global__ __launch_bounds__(NT) void k_tile_counts(const uint64_t* __restrict__ kin, uint64_t n, uint32_t shift,
                                                     uint32_t dbits, uint32_t* counts) {
     constexpr int TILE = NT * IPT;
-    __shared__ uint32_t h[RADIX];
-    for (uint32_t i = threadIdx.x; i < RADIX; i += NT) h[i] = 0;
+    __shared__ uint32_t h[RB];
+    for (uint32_t i = threadIdx.x; i < RB; i += NT) h[i] = 0;
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t tiles = (n + TILE - 1) / TILE;
@@ -266,10 +318,10 @@ __global__ __launch_bounds__(NT) void k_tile_counts(const uint64_t* __restrict__
         wave_hist_add(h, d, valid);
     }
     __syncthreads();
-    for (uint32_t d = threadIdx.x; d < RADIX; d += NT) counts[(uint64_t)d * tiles + blockIdx.x] = h[d];
+    for (uint32_t d = threadIdx.x; d < RB; d += NT) counts[(uint64_t)d * tiles + blockIdx.x] = h[d];
 }
 
-template <int NT, int IPT>
+template <int NT, int IPT, int RB, bool SPLIT = false>
 void launch_pass(Ctx& c, const PassArgs& a, bool final) {
     constexpr int TILE = NT * IPT;
     const uint64_t tiles = (a.n + TILE - 1) / TILE;
@@ -277,28 +329,29 @@ void launch_pass(Ctx& c, const PassArgs& a, bool final) {
     std::vector<void*> temps;
     if (a.mode == 1) {
         // reduce-then-scan: per-tile counts, one scan, scatter with known bases
-        uint32_t* counts = dalloc_n<uint32_t>(c, tiles * RADIX);
+        uint32_t* counts = dalloc_n<uint32_t>(c, tiles * RB);
         temps.push_back(counts);
-        uint64_t* scanned = dalloc_n<uint64_t>(c, tiles * RADIX + 1);
+        uint64_t* scanned = dalloc_n<uint64_t>(c, tiles * RB + 1);
         temps.push_back(scanned);
-        hipLaunchKernelGGL((k_tile_counts<NT, IPT>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin, a.n, a.shift,
-                           a.dbits, counts);
+        hipLaunchKernelGGL((k_tile_counts<NT, IPT, RB>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin, a.n,
+                           a.shift, a.dbits, counts);
         HIPCHK(hipGetLastError());
-        scan_u32_u64(c, counts, scanned, tiles * RADIX, false);
+        scan_u32_u64(c, counts, scanned, tiles * RB, false);
         off = scanned;
         if (final)
-            hipLaunchKernelGGL((k_onesweep<NT, IPT, true, false>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin,
-                               a.vin, a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch,
+            hipLaunchKernelGGL((k_onesweep<NT, IPT, true, false, RB, SPLIT>), dim3((unsigned)tiles), dim3(NT), 0, c.stream,
+                               a.kin, a.vin, a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch,
                                a.status, a.fo);
         else
-            hipLaunchKernelGGL((k_onesweep<NT, IPT, false, false>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin,
-                               a.vin, a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch,
+            hipLaunchKernelGGL((k_onesweep<NT, IPT, false, false, RB, SPLIT>), dim3((unsigned)tiles), dim3(NT), 0, c.stream,
+                               a.kin, a.vin, a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch,
                                a.status, a.fo);
     } else if (final) {
-        hipLaunchKernelGGL((k_onesweep<NT, IPT, true, true>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin, a.vin,
-                           a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch, a.status, a.fo);
+        hipLaunchKernelGGL((k_onesweep<NT, IPT, true, true, RB, SPLIT>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin,
+                           a.vin, a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch, a.status,
+                           a.fo);
     } else {
-        hipLaunchKernelGGL((k_onesweep<NT, IPT, false, true>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin,
+        hipLaunchKernelGGL((k_onesweep<NT, IPT, false, true, RB, SPLIT>), dim3((unsigned)tiles), dim3(NT), 0, c.stream, a.kin,
                            a.vin, a.kout, a.vout, a.n, a.shift, a.dbits, off, a.lookback, a.counter, a.epoch, a.status,
                            a.fo);
     }
@@ -308,11 +361,15 @@ void launch_pass(Ctx& c, const PassArgs& a, bool final) {
 
 struct Variant {
     int nt, ipt;
+    bool split;   // keys and payloads staged through LDS one after the other
 };
-// tile shapes available to the tuner; index 0 is the default (the fastest
-// measured for sorts of 1e8 .. 2e9 pairs: 8192-pair tiles give digit runs of
-// 32 pairs on average, so the scattered writes cover whole cache lines)
-constexpr Variant VARIANTS[] = {{1024, 8}, {256, 8}, {512, 8}, {512, 16}, {256, 16}, {256, 12}};
+// tile shapes available to the tuner; index 0 is the default, the fastest
+// measured for sorts of 4e8 .. 2e9 pairs: 8192-pair tiles (digit runs long
+// enough for whole-line writes) staged in two phases, so that two workgroups
+// share each compute unit
+constexpr Variant VARIANTS[] = {{512, 16, true},  {256, 8, false},  {512, 8, false}, {512, 16, false},
+                                {256, 16, false}, {256, 12, false}, {1024, 8, false}, {1024, 8, true},
+                                {512, 8, true},   {512, 12, true},  {256, 16, true}};
 constexpr int N_VARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 
 // autotuner results for the process: (pass algorithm, tile shape) per size
@@ -334,14 +391,32 @@ int log2_floor(uint64_t n) {
     return l;
 }
 
-void launch_variant(Ctx& c, int v, const PassArgs& a, bool final) {
+void launch_variant(Ctx& c, int v, const PassArgs& a, bool final, bool wide) {
+    if (wide) {   // 9-bit digits: tile shapes with at least 512 threads
+        switch (v) {
+        case 2: launch_pass<512, 8, 512>(c, a, final); break;
+        case 3: launch_pass<512, 16, 512>(c, a, final); break;
+        case 0: launch_pass<512, 16, 512, true>(c, a, final); break;
+        case 6: launch_pass<1024, 8, 512>(c, a, final); break;
+        case 7: launch_pass<1024, 8, 512, true>(c, a, final); break;
+        case 8: launch_pass<512, 8, 512, true>(c, a, final); break;
+        case 9: launch_pass<512, 12, 512, true>(c, a, final); break;
+        default: raise(SNNC_EINVAL, "9-bit digits need a tile of at least 512 threads");
+        }
+        return;
+    }
     switch (v) {
-    case 1: launch_pass<256, 8>(c, a, final); break;
-    case 2: launch_pass<512, 8>(c, a, final); break;
-    case 3: launch_pass<512, 16>(c, a, final); break;
-    case 4: launch_pass<256, 16>(c, a, final); break;
-    case 5: launch_pass<256, 12>(c, a, final); break;
-    default: launch_pass<1024, 8>(c, a, final); break;
+    case 1: launch_pass<256, 8, RADIX>(c, a, final); break;
+    case 2: launch_pass<512, 8, RADIX>(c, a, final); break;
+    case 3: launch_pass<512, 16, RADIX>(c, a, final); break;
+    case 4: launch_pass<256, 16, RADIX>(c, a, final); break;
+    case 5: launch_pass<256, 12, RADIX>(c, a, final); break;
+    case 6: launch_pass<1024, 8, RADIX>(c, a, final); break;
+    case 7: launch_pass<1024, 8, RADIX, true>(c, a, final); break;
+    case 8: launch_pass<512, 8, RADIX, true>(c, a, final); break;
+    case 9: launch_pass<512, 12, RADIX, true>(c, a, final); break;
+    case 10: launch_pass<256, 16, RADIX, true>(c, a, final); break;
+    default: launch_pass<512, 16, RADIX, true>(c, a, final); break;
     }
 }
 
@@ -349,14 +424,32 @@ void launch_variant(Ctx& c, int v, const PassArgs& a, bool final) {
 
 int sort_variant_count() { return N_VARIANTS; }
 
-void radix_plan(uint32_t bits, uint32_t& passes, uint32_t& digit_bits) {
-    passes = (bits + 7) / 8;
-    digit_bits = passes ? (bits + passes - 1) / passes : 0;
+// Pass algorithm, tile shape and digit plan of a sort of n keys over `bits`
+// bits.  9-bit digits (512 buckets) are taken when the tile has at least 512
+// threads and they save a pass over 8-bit digits (or when forced).
+SortPlan plan_sort(const Ctx& c, uint64_t n, uint32_t bits) {
+    SortPlan p;
+    p.variant = (c.sort_variant >= 0 && c.sort_variant < N_VARIANTS) ? c.sort_variant : 0;
+    p.mode = c.sort_mode;
+    if (!c.sort_pinned) {
+        auto it = tune_cache().find(TuneKey{log2_floor(std::max<uint64_t>(n, 1)), bits});
+        if (it != tune_cache().end()) {
+            p.mode = it->second.first;
+            p.variant = it->second.second;
+        }
+    }
+    const uint32_t p8 = (bits + 7) / 8, p9 = (bits + 8) / 9;
+    const bool can9 = VARIANTS[p.variant].nt >= 512;
+    const bool use9 = can9 && (c.digit_bits == 9 || (c.digit_bits == 0 && p9 < p8));
+    p.passes = use9 ? p9 : p8;
+    p.dbits = p.passes ? (bits + p.passes - 1) / p.passes : 0;
+    p.wide = p.dbits > 8;
+    return p;
 }
 
 void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t bit_hi, uint32_t dbits,
                  uint32_t passes, uint64_t* hist) {
-    HIPCHK(hipMemsetAsync(hist, 0, (size_t)passes * RADIX * 8, c.stream));
+    HIPCHK(hipMemsetAsync(hist, 0, (size_t)passes * HSTRIDE * 8, c.stream));
     if (!n || !passes) return;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((n + HNT - 1) / HNT, 4096);
     tstart(c, "sort_hist");
@@ -367,18 +460,11 @@ void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint
 
 int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, uint64_t n,
                uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist, const FinalOut* final_out) {
-    uint32_t passes, dbits;
-    radix_plan(bit_hi > bit_lo ? bit_hi - bit_lo : 0, passes, dbits);
+    const SortPlan plan = plan_sort(c, n, bit_hi > bit_lo ? bit_hi - bit_lo : 0);
+    const uint32_t passes = plan.passes, dbits = plan.dbits;
+    const int variant = plan.variant, mode = plan.mode;
+    const uint32_t rb = plan.wide ? 512 : RADIX;
     if (passes > 8) raise(SNNC_EUNSUPPORTED, "radix sort over more than 64 bits");
-    int variant = (c.sort_variant >= 0 && c.sort_variant < N_VARIANTS) ? c.sort_variant : 0;
-    int mode = c.sort_mode;
-    if (!c.sort_pinned) {
-        auto it = tune_cache().find(TuneKey{log2_floor(std::max<uint64_t>(n, 1)), bit_hi > bit_lo ? bit_hi - bit_lo : 0});
-        if (it != tune_cache().end()) {
-            mode = it->second.first;
-            variant = it->second.second;
-        }
-    }
     const uint64_t tile = (uint64_t)VARIANTS[variant].nt * VARIANTS[variant].ipt;
     std::vector<void*> temps;
     auto cleanup = [&] {
@@ -387,24 +473,24 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
     int cur = 0;
     try {
         const uint64_t tiles = (n + tile - 1) / tile;
-        std::vector<uint64_t> hh((size_t)passes * RADIX, 0);
+        std::vector<uint64_t> hh((size_t)passes * HSTRIDE, 0);
         uint64_t* off = nullptr;
         if (passes && n) {
             uint64_t* hist = const_cast<uint64_t*>(digit_hist);
             if (!hist) {
-                hist = dalloc_n<uint64_t>(c, (uint64_t)passes * RADIX);
+                hist = dalloc_n<uint64_t>(c, (uint64_t)passes * HSTRIDE);
                 temps.push_back(hist);
                 launch_hist(c, keys0, n, bit_lo, bit_hi, dbits, passes, hist);
             }
-            off = dalloc_n<uint64_t>(c, (uint64_t)passes * RADIX);
+            off = dalloc_n<uint64_t>(c, (uint64_t)passes * HSTRIDE);
             temps.push_back(off);
             tstart(c, "sort_hist_scan");
-            hipLaunchKernelGGL(k_hist_scan, dim3(passes), dim3(RADIX), 0, c.stream, hist, off);
+            hipLaunchKernelGGL(k_hist_scan, dim3(passes), dim3(HSTRIDE), 0, c.stream, hist, off);
             tstop(c);
             HIPCHK(hipGetLastError());
             download(c, hh.data(), hist, hh.size() * 8);
-            // look-back table: tiles x RADIX status words, zeroed once when (re)allocated
-            const size_t need = (size_t)tiles * RADIX * 8;
+            // look-back table: tiles x buckets status words, zeroed once when (re)allocated
+            const size_t need = (size_t)tiles * rb * 8;
             if (c.lookback_bytes < need) {
                 dfree(c, c.lookback);
                 c.lookback = nullptr;
@@ -422,8 +508,8 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
         std::vector<uint32_t> live;
         for (uint32_t p = 0; p < passes; ++p) {
             bool trivial = false;
-            for (int b = 0; b < RADIX; ++b)
-                if (hh[(size_t)p * RADIX + b] == n) trivial = true;
+            for (int b = 0; b < HSTRIDE; ++b)
+                if (hh[(size_t)p * HSTRIDE + b] == n) trivial = true;
             if (!trivial) live.push_back(p);
         }
         c.sort_passes = (uint32_t)live.size();
@@ -438,10 +524,10 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
             const bool last = (li + 1 == live.size()) && final_out;
             PassArgs a{kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, bit_lo + p * dbits,
                        pass_width(bit_lo, bit_hi, dbits, p),
-                       off + (size_t)p * RADIX, (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status,
+                       off + (size_t)p * HSTRIDE, (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status,
                        final_out ? *final_out : FinalOut{}, mode};
             tstart(c, last ? "sort_pass_final" : "sort_pass");
-            launch_variant(c, variant, a, last);
+            launch_variant(c, variant, a, last, plan.wide);
             tstop(c);
             HIPCHK(hipGetLastError());
             cur ^= 1;
