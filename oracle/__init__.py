@@ -79,6 +79,14 @@ def lib():
         L.orc_declare.argtypes = conn_args
         L.orc_prepare.argtypes = [vp]
         L.orc_set_map_policy.argtypes = [vp, ctypes.c_int, ctypes.c_int, dbl]
+        L.orc_packets_from_lists.restype = ctypes.c_int64
+        L.orc_packets_from_lists.argtypes = [vp, vp, vp, u32, u32, vp, vp, u64, vp, vp, vp, u64]
+        L.orc_spike_packets.restype = ctypes.c_int64
+        L.orc_spike_packets.argtypes = [vp, ctypes.c_int, vp, vp, u64, vp, vp, vp, u64]
+        L.orc_deliver_from_maps.restype = ctypes.c_int64
+        L.orc_deliver_from_maps.argtypes = [vp, vp, u64, vp, vp, vp, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp, vp, u64]
+        L.orc_deliver.restype = ctypes.c_int64
+        L.orc_deliver.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp, vp, u64]
         L.orc_len.argtypes = [vp, ctypes.c_int]
         L.orc_len.restype = i64
         L.orc_copy.argtypes = [vp, ctypes.c_int, vp, u64]
@@ -155,6 +163,57 @@ def transpose_lists(lists, M: int):
     pos = np.zeros(cap, np.uint32)
     n = lib().orc_transpose_lists(len(lists), _ptr(off), _ptr(val), M, _ptr(ptr), _ptr(which), _ptr(pos))
     return ptr, which[:n], pos[:n]
+
+
+def _u32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+
+
+def _packets_result(r, off, pos, mult):
+    if r < 0:
+        raise OracleError(-1, "spike id out of range")
+    return {"off": off, "pos": pos[:r], "mult": mult[:r]}
+
+
+def packets_from_lists(ptr, dest, where, M: int, n_dest: int, spikes, mult=None) -> dict:
+    """Packets of one step from explicit per-source lists (Appendix E)."""
+    ptr = np.ascontiguousarray(np.asarray(ptr, dtype=np.uint64))
+    dest, where, spikes = _u32(dest), _u32(where), _u32(spikes)
+    mult = None if mult is None else _u32(mult)
+    cap = int(ptr[-1]) * max(1, len(spikes))
+    off = np.zeros(n_dest + 1, np.uint64)
+    pos, mo = np.zeros(max(cap, 1), np.uint32), np.zeros(max(cap, 1), np.uint32)
+    r = lib().orc_packets_from_lists(_ptr(ptr), _ptr(dest), _ptr(where), M, n_dest, _ptr(spikes),
+                                     None if mult is None else _ptr(mult), len(spikes), _ptr(off), _ptr(pos),
+                                     _ptr(mo), cap)
+    return _packets_result(r, off, pos, mo)
+
+
+def _deliver_result(r, image, rb, re, et, ed, ew):
+    if r == -1:
+        raise OracleError(-1, "entry outside its map")
+    return {"image": image, "row_begin": rb, "row_end": re, "tgt": et[:r], "delay": ed[:r], "weight": ew[:r]}
+
+
+def deliver_from_maps(map_off, map_img, row_ptr, tgt, delay, weight, key, pos, mult=None) -> dict:
+    """Delivery through explicit maps and sorted connection arrays (Appendix E)."""
+    map_off = np.ascontiguousarray(np.asarray(map_off, dtype=np.uint64))
+    map_img = np.ascontiguousarray(np.asarray(map_img, dtype=np.int32))
+    row_ptr = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.uint64))
+    tgt = np.ascontiguousarray(np.asarray(tgt, dtype=np.int32))
+    delay = np.ascontiguousarray(np.asarray(delay, dtype=np.uint16))
+    weight = np.ascontiguousarray(np.asarray(weight, dtype=np.float32))
+    key, pos = _u32(key), _u32(pos)
+    mult = None if mult is None else _u32(mult)
+    n = len(key)
+    cap = max(1, int(tgt.size) * max(1, n))
+    image, rb, re = np.zeros(max(n, 1), np.int32), np.zeros(max(n, 1), np.uint64), np.zeros(max(n, 1), np.uint64)
+    et, ed, ew = np.zeros(cap, np.int32), np.zeros(cap, np.uint16), np.zeros(cap, np.float32)
+    r = lib().orc_deliver_from_maps(_ptr(map_off), _ptr(map_img), map_off.size - 1, _ptr(row_ptr), _ptr(tgt),
+                                    _ptr(delay), _ptr(weight), _ptr(key), _ptr(pos),
+                                    None if mult is None else _ptr(mult), n, _ptr(image), _ptr(rb), _ptr(re),
+                                    _ptr(et), _ptr(ed), _ptr(ew), cap)
+    return _deliver_result(r, image[:n], rb[:n], re[:n], et, ed, ew)
 
 
 class OracleError(RuntimeError):
@@ -250,6 +309,33 @@ class OracleNet:
         if r == 0:
             return None
         return {"src": so.value, "tgt_host": th.value, "tgt": tl.value, "weight": w.value, "delay": d.value}
+
+    def spike_packets(self, kind: int, spikes, mult=None) -> dict:
+        """Packets of one step: kind 0 per target host (T/P), kind 1 per group (G/Q)."""
+        spikes = _u32(spikes)
+        mult = None if mult is None else _u32(mult)
+        n_dest = self.P if kind == 0 else len(self.array("groups"))
+        cap = max(1, int(self.array("tp_ptr" if kind == 0 else "gq_ptr")[-1]) * max(1, len(spikes)))
+        off = np.zeros(n_dest + 1, np.uint64)
+        pos, mo = np.zeros(cap, np.uint32), np.zeros(cap, np.uint32)
+        r = lib().orc_spike_packets(self._h, kind, _ptr(spikes), None if mult is None else _ptr(mult), len(spikes),
+                                    _ptr(off), _ptr(pos), _ptr(mo), cap)
+        return _packets_result(r, off, pos, mo)
+
+    def deliver(self, kind: int, host, pos, mult=None, grp=None) -> dict:
+        """Delivery of received entries: kind 0 (sigma, i) through L, kind 1
+        (group rank, sigma, j) through I; per entry image and row, and events."""
+        host, pos = _u32(host), _u32(pos)
+        grp = None if grp is None else _u32(grp)
+        mult = None if mult is None else _u32(mult)
+        n = len(host)
+        cap = max(1, len(self.array("tgt")) * max(1, n))
+        image, rb, re = np.zeros(max(n, 1), np.int32), np.zeros(max(n, 1), np.uint64), np.zeros(max(n, 1), np.uint64)
+        et, ed, ew = np.zeros(cap, np.int32), np.zeros(cap, np.uint16), np.zeros(cap, np.float32)
+        r = lib().orc_deliver(self._h, kind, None if grp is None else _ptr(grp), _ptr(host), _ptr(pos),
+                              None if mult is None else _ptr(mult), n, _ptr(image), _ptr(rb), _ptr(re),
+                              _ptr(et), _ptr(ed), _ptr(ew), cap)
+        return _deliver_result(r, image[:n], rb[:n], re[:n], et, ed, ew)
 
     def call_range(self, call_id: int, host: int, lo: int, hi: int, cap: int) -> dict:
         """Draws of one call on one host's share, primary ordinal in [lo, hi)."""

@@ -1099,6 +1099,134 @@ int orc_prepare(orc_net* net)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Spike exchange with the built maps (Appendix E: packet and delivery        */
+/* figures; collective subsection for groups).                               */
+/* ------------------------------------------------------------------------ */
+
+/* Packets of one time step from per-source lists (ptr over M sources;
+ * dest[j], where[j]): spike k of source spikes[k] (multiplicity mult[k], or 1
+ * when mult is NULL) appends (where[j], mult) to packet dest[j] for each of its
+ * list entries j; packets keep the spike order.  off has n_dest + 1 entries.
+ * Returns the number of packet entries, or -1 for a spike id >= M or a
+ * capacity below the count (nothing written then). */
+int64_t orc_packets_from_lists(const uint64_t* ptr, const uint32_t* dest, const uint32_t* where, uint32_t M,
+                               uint32_t n_dest, const uint32_t* spikes, const uint32_t* mult, uint64_t n,
+                               uint64_t* off, uint32_t* pos_out, uint32_t* mult_out, uint64_t cap)
+{
+    uint64_t total = 0;
+    for (uint64_t k = 0; k < n; k++) {
+        if (spikes[k] >= M) return -1;
+        total += ptr[spikes[k] + 1] - ptr[spikes[k]];
+    }
+    if (total > cap) return -1;
+    for (uint32_t d = 0; d <= n_dest; d++) off[d] = 0;
+    for (uint64_t k = 0; k < n; k++)          /* packet sizes */
+        for (uint64_t j = ptr[spikes[k]]; j < ptr[spikes[k] + 1]; j++) off[dest[j] + 1]++;
+    for (uint32_t d = 0; d < n_dest; d++) off[d + 1] += off[d];
+    uint64_t* fill = (uint64_t*)malloc(((size_t)n_dest + 1) * sizeof(uint64_t));
+    for (uint32_t d = 0; d <= n_dest; d++) fill[d] = off[d];
+    for (uint64_t k = 0; k < n; k++)          /* append in spike order */
+        for (uint64_t j = ptr[spikes[k]]; j < ptr[spikes[k] + 1]; j++) {
+            uint64_t o = fill[dest[j]]++;
+            pos_out[o] = where[j];
+            mult_out[o] = mult ? mult[k] : 1u;
+        }
+    free(fill);
+    return (int64_t)total;
+}
+
+/* Packets of the local host: kind 0 point-to-point (destinations = hosts,
+ * lists T/P), kind 1 collective (destinations = the groups in ascending
+ * order, lists G/Q with the group replaced by its rank). */
+int64_t orc_spike_packets(const orc_net* net, int kind, const uint32_t* spikes, const uint32_t* mult, uint64_t n,
+                          uint64_t* off, uint32_t* pos_out, uint32_t* mult_out, uint64_t cap)
+{
+    if (!net->prepared) return -1;
+    const uint32_t M = net->M[net->P_local];
+    if (kind == 0)
+        return orc_packets_from_lists(net->TP_ptr, net->T_val, net->P_val, M, net->P, spikes, mult, n,
+                                      off, pos_out, mult_out, cap);
+    if (kind != 1) return -1;
+    const uint64_t m = net->GQ_ptr[M];
+    uint32_t* grank = (uint32_t*)malloc((m ? m : 1) * sizeof(uint32_t));
+    for (uint64_t j = 0; j < m; j++) {
+        uint32_t g = 0;
+        while (g < net->n_groups && net->groups[g] != net->G_val[j]) g++;
+        grank[j] = g;
+    }
+    int64_t r = orc_packets_from_lists(net->GQ_ptr, grank, net->Q_val, M, net->n_groups, spikes, mult, n,
+                                       off, pos_out, mult_out, cap);
+    free(grank);
+    return r;
+}
+
+/* Delivery from explicit maps: entry e names a received position pos[e] in
+ * map key[e] (map_off over n_maps maps, map_img the local image index or -1
+ * for none); the image's outgoing connections are its row of the sorted
+ * arrays.  Per entry: image (or -1), row [begin, end).  Events, for entries
+ * in order and their connections in row order: (target, delay,
+ * weight * multiplicity in fp32).  Returns the event count, -1 for an entry
+ * outside its map, -2 when the events exceed ev_cap (the per-entry outputs
+ * are written, the events are not). */
+int64_t orc_deliver_from_maps(const uint64_t* map_off, const int32_t* map_img, uint64_t n_maps,
+                              const uint64_t* row_ptr, const int32_t* tgt, const uint16_t* delay, const float* weight,
+                              const uint32_t* key, const uint32_t* pos, const uint32_t* mult, uint64_t n,
+                              int32_t* image, uint64_t* rb, uint64_t* re,
+                              int32_t* ev_tgt, uint16_t* ev_delay, float* ev_weight, uint64_t ev_cap)
+{
+    uint64_t total = 0;
+    for (uint64_t e = 0; e < n; e++) {
+        if (key[e] >= n_maps || pos[e] >= map_off[key[e] + 1] - map_off[key[e]]) return -1;
+        int32_t img = map_img[map_off[key[e]] + pos[e]];
+        image[e] = img;
+        rb[e] = img >= 0 ? row_ptr[img] : 0;
+        re[e] = img >= 0 ? row_ptr[img + 1] : 0;
+        total += re[e] - rb[e];
+    }
+    if (!ev_tgt) return (int64_t)total;
+    if (total > ev_cap) return -2;
+    uint64_t o = 0;
+    for (uint64_t e = 0; e < n; e++) {
+        const float m = mult ? (float)mult[e] : 1.0f;
+        for (uint64_t c = rb[e]; c < re[e]; c++, o++) {
+            ev_tgt[o] = tgt[c];
+            ev_delay[o] = delay[c];
+            ev_weight[o] = weight[c] * m;
+        }
+    }
+    return (int64_t)total;
+}
+
+/* Delivery on the local host.  kind 0: entry = (source host sigma, position
+ * i in the point-to-point map R_{P_local,sigma}) -> L; kind 1: entry = (group
+ * rank g, source host sigma, position j in H_{alpha_g,sigma}) -> I (-1: the
+ * source has no image here).  grp is ignored for kind 0. */
+int64_t orc_deliver(const orc_net* net, int kind, const uint32_t* grp, const uint32_t* host, const uint32_t* pos,
+                    const uint32_t* mult, uint64_t n, int32_t* image, uint64_t* rb, uint64_t* re,
+                    int32_t* ev_tgt, uint16_t* ev_delay, float* ev_weight, uint64_t ev_cap)
+{
+    if (!net->prepared || (kind != 0 && kind != 1)) return -1;
+    const uint32_t P = net->P;
+    uint32_t* key = (uint32_t*)malloc((n ? n : 1) * sizeof(uint32_t));
+    for (uint64_t e = 0; e < n; e++) {
+        if (host[e] >= P || (kind == 0 && host[e] == net->P_local) || (kind == 1 && grp[e] >= net->n_groups)) {
+            free(key);
+            return -1;
+        }
+        key[e] = kind == 0 ? host[e] : grp[e] * P + host[e];   /* map (alpha+1 = 0, sigma) / (g, sigma) */
+    }
+    int64_t r = kind == 0
+        ? orc_deliver_from_maps(net->r_off, net->l_val, P, net->row_ptr, net->s_tgt,
+                                net->s_delay, net->s_weight, key, pos, mult, n, image, rb, re,
+                                ev_tgt, ev_delay, ev_weight, ev_cap)
+        : orc_deliver_from_maps(net->H_off, net->I_val, (uint64_t)net->n_groups * P, net->row_ptr, net->s_tgt,
+                                net->s_delay, net->s_weight, key, pos, mult, n, image, rb, re,
+                                ev_tgt, ev_delay, ev_weight, ev_cap);
+    free(key);
+    return r;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Access                                                                    */
 /* ------------------------------------------------------------------------ */
 enum {
