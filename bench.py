@@ -34,6 +34,8 @@ def workload(name: str, scale: float):
         return W.multiarea_p2p()
     if name == "collective":
         return W.balanced_collective()
+    if name.startswith("indegree"):        # indegree or indegreeS: in-degree scale S (default 2)
+        return W.balanced_indegree(int(name[len("indegree"):] or 2))
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -117,6 +119,75 @@ def cpu_baseline(script, budget_conns: float = 1.2e7):
     return {"value": round(n / dt / 1e9, 6), "unit": "Gconn/s", "cores": 1, "kind": "oracle",
             "sample": f"{kept} of the {total_calls} Connect calls of the same workload, in script order while they "
                       f"fit {budget_conns:.0e} connections ({n} connections), then Prepare; {dt:.1f} s on one core"}
+
+
+def exchange(args):
+    """Spike exchange through the built maps of the multi-area network (one
+    host's share of 32): per step, packets for the spikes of 1% of the local
+    neurons (point-to-point, T/P) and delivery of received entries naming 1% of
+    the images (through L into their connection rows, expanded to events)."""
+    import numpy as np
+    import torch
+    import paper_2512_09502_amd as snnc
+    script = workload("multiarea", args.scale)
+    net = build_once(script, 0, timing=False)
+    st = net.stats()
+    M, n_img = st["M_local"], st["n_images"]
+    r_off = net.array("r_off").astype(np.int64)
+    rng = np.random.default_rng(7)
+    P = script["P"]
+    sizes = np.diff(r_off[: P + 1])
+
+    def step_inputs():
+        spikes = rng.choice(M, size=max(1, M // 100), replace=False).astype(np.uint32)
+        k = max(1, n_img // 100)
+        which = rng.choice(n_img, size=k, replace=False)
+        sigma = np.searchsorted(r_off[: P + 1], which, side="right") - 1
+        pos = which - r_off[sigma]
+        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint32).view(np.int32)).cuda()
+        return dev(spikes), dev(sigma), dev(pos), dev(rng.integers(1, 4, size=k))
+
+    inputs = [step_inputs() for _ in range(args.steps + args.warmup)]
+    for sp, sg, ps, mu in inputs[: args.warmup]:
+        net.spike_packets(0, sp)
+        net.deliver(0, sg, ps, mu)
+    torch.cuda.synchronize()
+    net.set_timing(True)
+    t_pk = t_dl = 0.0
+    n_pk = n_ev = 0
+    for sp, sg, ps, mu in inputs[args.warmup:]:
+        t0 = time.perf_counter()
+        pk = net.spike_packets(0, sp)
+        t1 = time.perf_counter()
+        d = net.deliver(0, sg, ps, mu)
+        t2 = time.perf_counter()
+        t_pk += t1 - t0
+        t_dl += t2 - t1
+        n_pk += int(pk["pos"].numel())
+        n_ev += int(d["n_events"])
+    kt = net.kernel_times()
+    ev_ms = kt.get("deliver_events", (1, 0.0))
+    roof = None
+    if ev_ms[1] > 0:
+        per_launch = 20.0 * n_ev / args.steps          # read 10 B (target, delay, weight) + write 10 B per event
+        achieved = per_launch / (ev_ms[1] / ev_ms[0] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None, "kernel": "deliver_events",
+                "avg_launch_ms": round(ev_ms[1] / ev_ms[0], 4), "algorithmic_bytes_per_launch": per_launch}
+    out = {"metric": "delivered events/sec (Gevents/s) on 1 MI355X; packet entries/sec",
+           "value": round(n_ev / t_dl / 1e9, 4), "unit": "Gevents/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(1e3 * (t_pk + t_dl) / args.steps, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32 ids, f32 weights",
+           "data": "synthetic",
+           "config": {"workload": "multiarea_p2p spike exchange", "neurons": M, "images": n_img,
+                      "spikes_per_step": int(inputs[0][0].numel()), "entries_per_step": int(inputs[0][1].numel())},
+           "packets": {"entries_per_step": n_pk // args.steps, "ms_per_step": round(1e3 * t_pk / args.steps, 3),
+                       "Mentries_s": round(n_pk / t_pk / 1e6, 2)},
+           "delivery": {"events_per_step": n_ev // args.steps, "ms_per_step": round(1e3 * t_dl / args.steps, 3)},
+           "kernels_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in sorted(kt.items(), key=lambda kv: -kv[1][1])},
+           "roofline": roof}
+    net.close()
+    print(json.dumps(out), flush=True)
 
 
 def served(args):
@@ -258,6 +329,8 @@ def main():
     import paper_2512_09502_amd as snnc
     if args.workload == "served":
         return served(args)
+    if args.workload == "exchange":
+        return exchange(args)
     script = workload(args.workload, args.scale)
     if args.sort_variant is not None:
         script["sort_variant"] = args.sort_variant

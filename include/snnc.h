@@ -357,6 +357,44 @@ snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
 snnc_status snnc_autotune_sort(snnc_ctx* ctx, uint64_t n, uint32_t bits, int32_t* mode_out, int32_t* variant_out,
                                float* ms_out);
 
+/* ---------------------------------------------------------- spike exchange */
+
+/* Spike packets of one time step on this host (Appendix E, packet figure;
+ * collective subsection).  kind 0 (point-to-point): spike k of local neuron
+ * spikes[k] appends (P_{s,j}, mult[k]) to the packet of target host T_{s,j}
+ * for each of its (T, P) pairs; kind 1 (collective): appends (Q_{s,j},
+ * mult[k]) to the packet of group G_{s,j}, groups numbered by their rank in
+ * SNNC_GROUPS.  Packets keep the spike order.  All pointers are the caller's
+ * device memory: spikes, mult (NULL: multiplicity 1) [n]; off [n_dest + 1],
+ * n_dest = P (kind 0) or the number of groups (kind 1), packet d is
+ * [off[d], off[d+1]); pos_out, mult_out [cap].  *n_out receives the number
+ * of entries; when it exceeds cap nothing is written and SNNC_EINVAL is
+ * returned.  Runs on the context stream and waits for completion.
+ * Errors: SNNC_ESTATE before snnc_prepare; SNNC_EINVAL for an unknown kind,
+ * a spike id >= M_local or a small cap. */
+snnc_status snnc_spike_packets(snnc_ctx* ctx, int32_t kind, const uint32_t* spikes, const uint32_t* mult,
+                               uint64_t n, uint64_t* off, uint32_t* pos_out, uint32_t* mult_out, uint64_t cap,
+                               uint64_t* n_out);
+
+/* Delivery of received packet entries on this host (Appendix E, delivery
+ * figure).  kind 0: entry e = (source host host[e] != P_local, position
+ * pos[e] in the point-to-point map R_{P_local,host[e]}) -> its image L; kind
+ * 1: entry e = (group rank grp[e], source host host[e], position pos[e] in
+ * H_{group,host}) -> its image I, or -1 when the source has no image here.
+ * Per entry (caller device arrays of n): image[e] and the image's row
+ * [row_begin[e], row_end[e]) in the sorted connection arrays (empty for -1).
+ * Events (skipped when ev_tgt is NULL): for the entries in order and their
+ * connections in row order, (target, delay steps, weight x multiplicity in
+ * fp32) into ev_tgt, ev_delay, ev_weight of ev_cap; mult NULL means 1.
+ * *n_events receives the number of events.  Runs on the context stream and
+ * waits for completion.  Errors: SNNC_ESTATE before snnc_prepare;
+ * SNNC_EINVAL for an unknown kind, an entry outside its map, or more events
+ * than ev_cap (per-entry outputs written, events not). */
+snnc_status snnc_deliver(snnc_ctx* ctx, int32_t kind, const uint32_t* grp, const uint32_t* host,
+                         const uint32_t* pos, const uint32_t* mult, uint64_t n, int32_t* image,
+                         uint64_t* row_begin, uint64_t* row_end, int32_t* ev_tgt, uint16_t* ev_delay,
+                         float* ev_weight, uint64_t ev_cap, uint64_t* n_events);
+
 /* ---------------------------------------------------------------- helpers */
 
 /* The source-major sort of Prepare on its own: stable LSD radix sort of n

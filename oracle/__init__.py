@@ -180,7 +180,8 @@ def packets_from_lists(ptr, dest, where, M: int, n_dest: int, spikes, mult=None)
     ptr = np.ascontiguousarray(np.asarray(ptr, dtype=np.uint64))
     dest, where, spikes = _u32(dest), _u32(where), _u32(spikes)
     mult = None if mult is None else _u32(mult)
-    cap = int(ptr[-1]) * max(1, len(spikes))
+    ok = spikes[spikes < ptr.size - 1].astype(np.int64)
+    cap = int((ptr[ok + 1].astype(np.int64) - ptr[ok].astype(np.int64)).sum())
     off = np.zeros(n_dest + 1, np.uint64)
     pos, mo = np.zeros(max(cap, 1), np.uint32), np.zeros(max(cap, 1), np.uint32)
     r = lib().orc_packets_from_lists(_ptr(ptr), _ptr(dest), _ptr(where), M, n_dest, _ptr(spikes),
@@ -206,13 +207,14 @@ def deliver_from_maps(map_off, map_img, row_ptr, tgt, delay, weight, key, pos, m
     key, pos = _u32(key), _u32(pos)
     mult = None if mult is None else _u32(mult)
     n = len(key)
-    cap = max(1, int(tgt.size) * max(1, n))
     image, rb, re = np.zeros(max(n, 1), np.int32), np.zeros(max(n, 1), np.uint64), np.zeros(max(n, 1), np.uint64)
-    et, ed, ew = np.zeros(cap, np.int32), np.zeros(cap, np.uint16), np.zeros(cap, np.float32)
-    r = lib().orc_deliver_from_maps(_ptr(map_off), _ptr(map_img), map_off.size - 1, _ptr(row_ptr), _ptr(tgt),
-                                    _ptr(delay), _ptr(weight), _ptr(key), _ptr(pos),
-                                    None if mult is None else _ptr(mult), n, _ptr(image), _ptr(rb), _ptr(re),
-                                    _ptr(et), _ptr(ed), _ptr(ew), cap)
+    args = (_ptr(map_off), _ptr(map_img), map_off.size - 1, _ptr(row_ptr), _ptr(tgt), _ptr(delay), _ptr(weight),
+            _ptr(key), _ptr(pos), None if mult is None else _ptr(mult), n, _ptr(image), _ptr(rb), _ptr(re))
+    cap = lib().orc_deliver_from_maps(*args, None, None, None, 0)   # event count first
+    if cap < 0:
+        return _deliver_result(cap, image, rb, re, None, None, None)
+    et, ed, ew = np.zeros(max(cap, 1), np.int32), np.zeros(max(cap, 1), np.uint16), np.zeros(max(cap, 1), np.float32)
+    r = lib().orc_deliver_from_maps(*args, _ptr(et), _ptr(ed), _ptr(ew), cap)
     return _deliver_result(r, image[:n], rb[:n], re[:n], et, ed, ew)
 
 
@@ -315,7 +317,9 @@ class OracleNet:
         spikes = _u32(spikes)
         mult = None if mult is None else _u32(mult)
         n_dest = self.P if kind == 0 else len(self.array("groups"))
-        cap = max(1, int(self.array("tp_ptr" if kind == 0 else "gq_ptr")[-1]) * max(1, len(spikes)))
+        ptr = self.array("tp_ptr" if kind == 0 else "gq_ptr").astype(np.int64)
+        ok = spikes[spikes < ptr.size - 1].astype(np.int64)
+        cap = max(1, int((ptr[ok + 1] - ptr[ok]).sum()))
         off = np.zeros(n_dest + 1, np.uint64)
         pos, mo = np.zeros(cap, np.uint32), np.zeros(cap, np.uint32)
         r = lib().orc_spike_packets(self._h, kind, _ptr(spikes), None if mult is None else _ptr(mult), len(spikes),
@@ -329,12 +333,14 @@ class OracleNet:
         grp = None if grp is None else _u32(grp)
         mult = None if mult is None else _u32(mult)
         n = len(host)
-        cap = max(1, len(self.array("tgt")) * max(1, n))
         image, rb, re = np.zeros(max(n, 1), np.int32), np.zeros(max(n, 1), np.uint64), np.zeros(max(n, 1), np.uint64)
-        et, ed, ew = np.zeros(cap, np.int32), np.zeros(cap, np.uint16), np.zeros(cap, np.float32)
-        r = lib().orc_deliver(self._h, kind, None if grp is None else _ptr(grp), _ptr(host), _ptr(pos),
-                              None if mult is None else _ptr(mult), n, _ptr(image), _ptr(rb), _ptr(re),
-                              _ptr(et), _ptr(ed), _ptr(ew), cap)
+        args = (self._h, kind, None if grp is None else _ptr(grp), _ptr(host), _ptr(pos),
+                None if mult is None else _ptr(mult), n, _ptr(image), _ptr(rb), _ptr(re))
+        cap = lib().orc_deliver(*args, None, None, None, 0)          # event count first
+        if cap < 0:
+            return _deliver_result(cap, image, rb, re, None, None, None)
+        et, ed, ew = np.zeros(max(cap, 1), np.int32), np.zeros(max(cap, 1), np.uint16), np.zeros(max(cap, 1), np.float32)
+        r = lib().orc_deliver(*args, _ptr(et), _ptr(ed), _ptr(ew), cap)
         return _deliver_result(r, image[:n], rb[:n], re[:n], et, ed, ew)
 
     def call_range(self, call_id: int, host: int, lo: int, hi: int, cap: int) -> dict:

@@ -83,7 +83,7 @@ EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_cr
            "snnc_reserve", "snnc_prepare", "snnc_get_array", "snnc_copy_array", "snnc_copy_range",
            "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks",
            "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_flush", "snnc_poll",
-           "snnc_autotune_sort", "snnc_set_map_policy"]
+           "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver"]
 
 _lib = None
 
@@ -108,6 +108,9 @@ def lib():
         L.snnc_reserve.argtypes = [vp, u64]
         L.snnc_prepare.argtypes = [vp]
         L.snnc_set_map_policy.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
+        L.snnc_spike_packets.argtypes = [vp, ctypes.c_int32, vp, vp, u64, vp, vp, vp, u64, ctypes.POINTER(u64)]
+        L.snnc_deliver.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp, vp, u64,
+                                   ctypes.POINTER(u64)]
         L.snnc_get_array.argtypes = [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(u64)]
         L.snnc_copy_array.argtypes = [vp, i32, vp, u64]
         L.snnc_copy_range.argtypes = [vp, i32, u64, u64, vp]
@@ -305,6 +308,61 @@ class Network:
 
     def tune(self, key: str, value: int):
         self._check(lib().snnc_tune(self._h, key.encode(), int(value)))
+
+    @staticmethod
+    def _dptr(t):
+        return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+    def spike_packets(self, kind: int, spikes, mult=None) -> dict:
+        """Packets of one time step from device tensors spikes / mult (int32
+        holding unsigned ids and counts): kind 0 per target host (T/P), kind 1
+        per group (G/Q).  Returns tensors off, pos, mult."""
+        torch = self._torch
+        dev = spikes.device
+        n_dest = self.P if kind == 0 else int(self.count("groups"))
+        off = torch.empty(n_dest + 1, dtype=torch.int64, device=dev)
+        cap = max(1, int(self.count("t_val" if kind == 0 else "q_val")))
+        for _ in range(2):
+            pos = torch.empty(cap, dtype=torch.int32, device=dev)
+            mo = torch.empty(cap, dtype=torch.int32, device=dev)
+            n_out = ctypes.c_uint64()
+            st = lib().snnc_spike_packets(self._h, kind, self._dptr(spikes), self._dptr(mult), spikes.numel(),
+                                          self._dptr(off), self._dptr(pos), self._dptr(mo), cap, ctypes.byref(n_out))
+            if st != 0 and n_out.value > cap:
+                cap = n_out.value
+                continue
+            self._check(st)
+            return {"off": off, "pos": pos[:n_out.value], "mult": mo[:n_out.value]}
+        raise SnncError(-1, "packet capacity")
+
+    def deliver(self, kind: int, host, pos, mult=None, grp=None, events: bool = True) -> dict:
+        """Delivery of received entries (device int32 tensors): image and row
+        per entry, and the (target, delay, weight x multiplicity) events."""
+        torch = self._torch
+        dev = host.device
+        n = host.numel()
+        image = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        rb = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        re = torch.empty(max(n, 1), dtype=torch.int64, device=dev)
+        cap = max(1, n * 64)
+        for _ in range(2):
+            et = torch.empty(cap, dtype=torch.int32, device=dev) if events else None
+            ed = torch.empty(cap, dtype=torch.int16, device=dev) if events else None
+            ew = torch.empty(cap, dtype=torch.float32, device=dev) if events else None
+            n_ev = ctypes.c_uint64()
+            st = lib().snnc_deliver(self._h, kind, self._dptr(grp), self._dptr(host), self._dptr(pos),
+                                    self._dptr(mult), n, self._dptr(image), self._dptr(rb), self._dptr(re),
+                                    self._dptr(et), self._dptr(ed), self._dptr(ew), cap if events else 0,
+                                    ctypes.byref(n_ev))
+            if st != 0 and events and n_ev.value > cap:
+                cap = n_ev.value
+                continue
+            self._check(st)
+            out = {"image": image[:n], "row_begin": rb[:n], "row_end": re[:n], "n_events": n_ev.value}
+            if events:
+                out.update(tgt=et[:n_ev.value], delay=ed[:n_ev.value], weight=ew[:n_ev.value])
+            return out
+        raise SnncError(-1, "event capacity")
 
     def autotune_sort(self, n: int, bits: int) -> dict:
         """Pick the fastest radix-pass algorithm and tile shape for n keys of

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsnnc.so")
-SOURCES = ["api.hip", "gen.hip", "scan.hip", "sort.hip", "prepare.hip"]
+SOURCES = ["api.hip", "gen.hip", "scan.hip", "sort.hip", "prepare.hip", "spikes.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -148,6 +148,31 @@ def balanced_collective(P: int = 1024, n_e: int = 160000, n_i: int = 40000, k_e:
     return b.script("balanced_collective", conns_per_host=(n_e + n_i) * (k_e + k_i))
 
 
+def balanced_indegree(in_scale: int = 2, P: int = 1024, n_e: int = 160000, n_i: int = 40000, k_e: int = 9000,
+                      k_i: int = 2250, group: int = 0) -> dict:
+    """The balanced network with an in-degree scale (the paper's in-degree
+    appendix): each host holds n_e / s excitatory and n_i / s inhibitory
+    neurons, every neuron receives s * k_e excitatory and s * k_i inhibitory
+    connections, and the weights are divided by s, so the connections per
+    host stay (n_e + n_i) (k_e + k_i) while the sources (and images) shrink
+    by s."""
+    s = int(in_scale)
+    ne, ni = max(1, n_e // s), max(1, n_i // s)
+    b = _Builder(P)
+    E, I = [], []
+    for h in range(P):
+        E.append(b.create(h, ne))
+        I.append(b.create(h, ni))
+    allset = [seg for h in range(P) for seg in (E[h], I[h])]
+    w_e = {"kind": "normal", "mean": W_E["mean"] / s, "sd": W_E["sd"] / s}
+    w_i = {"kind": "normal", "mean": W_I["mean"] / s, "sd": W_I["sd"] / s}
+    b.connect(E, allset, {"rule": "fixed_indegree", "n": k_e * s, "autapses": True, "multapses": True},
+              {"weight": w_e, "delay": D_CONST_15}, group)
+    b.connect(I, allset, {"rule": "fixed_indegree", "n": k_i * s, "autapses": True, "multapses": True},
+              {"weight": w_i, "delay": D_CONST_15}, group)
+    return b.script(f"balanced_indegree_x{s}", conns=(ne + ni) * (k_e + k_i) * s, in_scale=s)
+
+
 def served_requests(n_requests: int = 10000, n_pops: int = 64, pop_min: int = 1000, pop_max: int = 200000,
                     size_min: float = 1e2, size_max: float = 1e7, seed: int = 1005) -> dict:
     """A stream of Connect requests of uneven size on one host: 64

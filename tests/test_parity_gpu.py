@@ -56,6 +56,15 @@ def test_balanced_collective_scaled():
         compare_all(s, pl)
 
 
+@pytest.mark.parametrize("in_scale", [1, 4, 10])
+def test_balanced_indegree_scaled(in_scale):
+    """In-degree sweep at a fixed connection count (fewer sources, larger K)."""
+    s = W.balanced_indegree(in_scale, P=6, n_e=400, n_i=100, k_e=30, k_i=8)
+    for pl in (0, 5):
+        n = compare_all(s, pl)
+        log(f"indegree x{in_scale} P_local={pl}: {n} connections")
+
+
 @pytest.mark.parametrize("seed", range(16))
 def test_random_tiny(seed):
     s = W.random_tiny(seed)
