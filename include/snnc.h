@@ -159,18 +159,21 @@ snnc_status snnc_create(snnc_ctx* ctx, uint32_t host, uint32_t n, snnc_segment* 
  *                        K draws of a target, then sorted ascending;
  *                        without autapses the draw skips the target itself;
  *   fixed out-degree K:  mirror image with sources and targets swapped;
- *   fixed total number:  candidate c draws (source, target) from IDX(c); the
- *                        first n candidates that are valid (no autapse if
- *                        excluded, no repeated pair if multapses excluded)
- *                        are the connections, e = c; targets on one host only;
+ *   fixed total number:  candidate c draws (source, target) from IDX(c) over
+ *                        the whole sets; the first n candidates that are valid
+ *                        (no autapse if excluded, no repeated pair if
+ *                        multapses excluded) are the connections, e = c; with
+ *                        targets on several hosts every host evaluates every
+ *                        candidate and keeps those whose target it holds;
  *   pairwise Bernoulli:  pair q = t_ord * n_s + s_ord connects iff word q%4 of
  *                        block BERN(q/4) is below floor(p 2^32); e = q;
  *   one-to-one:          e = i.
  * Synapse values of element e come from block SYN(e) of the same call.
  * Errors: SNNC_EINVAL (bad segment, overlapping segments within a set, rule
  * parameters impossible for the sets, port != 0, delay below one step or
- * beyond 65535 steps, sd < 0), SNNC_EUNSUPPORTED (fixed total number with
- * targets on several hosts; more than 2^32-1 neurons in a set),
+ * beyond 65535 steps, sd < 0), SNNC_EUNSUPPORTED (more than 2^32-1 neurons
+ * in a set, total number or degree above 2^32-1, degree above 8192 without
+ * multapses),
  * SNNC_ESTATE after prepare, SNNC_ENOMEM / SNNC_EBUDGET, SNNC_EDEVICE. */
 snnc_status snnc_connect(snnc_ctx* ctx, const snnc_nodeset* src, const snnc_nodeset* tgt,
                          const snnc_conn_spec* conn, const snnc_syn_spec* syn, int32_t alpha,

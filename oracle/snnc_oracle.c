@@ -348,18 +348,6 @@ static int copy_set(orc_net* net, const uint32_t* triples, uint32_t nseg, orc_se
     return ORC_OK;
 }
 
-static int all_on_one_host(const orc_set* s, uint32_t* host)
-{
-    int found = 0;
-    for (uint32_t i = 0; i < s->nseg; i++) {
-        if (s->seg[i].n == 0) continue;
-        if (!found) { *host = s->seg[i].host; found = 1; }
-        else if (s->seg[i].host != *host) return 0;
-    }
-    if (!found) *host = 0xffffffffu;
-    return 1;
-}
-
 /* ------------------------------------------------------------------------ */
 /* Rule draws.  gen_call walks the draws of one call that land on a given    */
 /* host's share and hands each accepted connection (source position in S,   */
@@ -486,9 +474,10 @@ static void gen_call(const orc_net* net, const orc_call* c, uint32_t host, uint6
         break;
     }
     case R_TOTAL: {
-        uint32_t thost;
-        all_on_one_host(&c->T, &thost);
-        if (thost != host) break;
+        /* The rule over the whole target set (reading for targets on several
+         * hosts): candidates c = 0, 1, ... draw a pair over S x T, the first
+         * N valid ones are the connections, and each host keeps those whose
+         * target it holds.  Every host evaluates every candidate. */
         pairset seen = { NULL, 0, 0 };
         uint64_t accepted = 0;
         for (uint64_t cand = 0; accepted < c->n && cand < hi; cand++) {
@@ -501,7 +490,7 @@ static void gen_call(const orc_net* net, const orc_call* c, uint32_t host, uint6
             if (!c->autapses && h == h2 && l == l2) continue;
             if (!c->multapses && !pairset_insert(&seen, s, t)) continue;
             accepted++;
-            if (cand >= lo) sink.emit(sink.ctx, s, l2, cand);
+            if (cand >= lo && h2 == host) sink.emit(sink.ctx, s, l2, cand);
         }
         free(seen.key);
         break;
@@ -610,8 +599,6 @@ static int validate_and_fill(orc_net* net, orc_call* c)
         }
         break;
     case R_TOTAL: {
-        uint32_t thost;
-        if (!all_on_one_host(&c->T, &thost)) return fail(net, ORC_EUNSUPPORTED, "total number over targets on several hosts");
         if (c->n > 0) {
             if (ns == 0 || nt == 0) return fail(net, ORC_EINVAL, "empty set");
             unsigned __int128 pairs = (unsigned __int128)ns * nt - ov;
@@ -852,10 +839,10 @@ static uint64_t set_count_on(const orc_set* s, uint32_t host)
  * is the threshold heuristic of the point-to-point creation subsection:
  * flag when the rule draws its source indices at random and the estimated
  * number of new connections on tau divided by the number of sources is below
- * xi.  Estimates (reading): fixed in-degree K N_t, fixed total number N (its
- * targets live on tau), pairwise Bernoulli p N_s N_t, with N_t the call's
- * targets on tau and N_s all its sources; one-to-one and fixed out-degree use
- * every source and are never flagged. */
+ * xi.  Estimates (reading): fixed in-degree K N_t, fixed total number
+ * N N_t / (all targets of the call), pairwise Bernoulli p N_s N_t, with N_t
+ * the call's targets on tau and N_s all its sources; one-to-one and fixed
+ * out-degree use every source and are never flagged. */
 static int flag_sources(const orc_net* net, const orc_call* c, uint32_t tau)
 {
     if (net->img_sources == 0) return 1;
@@ -865,7 +852,7 @@ static int flag_sources(const orc_net* net, const orc_call* c, uint32_t tau)
     double est;
     switch (c->rule) {
     case R_INDEGREE: est = (double)c->n * n_t; break;
-    case R_TOTAL: est = n_t > 0.0 ? (double)c->n : 0.0; break;
+    case R_TOTAL: est = (double)c->n * n_t / (double)c->T.total; break;
     case R_BERNOULLI: est = c->p * n_s * n_t; break;
     default: return 0;
     }

@@ -179,15 +179,6 @@ static uint64_t set_overlap(const HostSet& a, const HostSet& b) {
     return total;
 }
 
-static bool one_host(const HostSet& s, uint32_t& host) {
-    host = 0xffffffffu;
-    for (auto& g : s.seg) {
-        if (host == 0xffffffffu) host = g.host;
-        else if (g.host != host) return false;
-    }
-    return true;
-}
-
 // Standard normal CDF via the complementary error function.
 static double phi(double x) { return 0.5 * std::erfc(-x / 1.41421356237309504880168872420969808); }
 
@@ -228,8 +219,6 @@ static void validate(const Ctx& c, Call& cl, const snnc_syn_spec* syn) {
         break;
     }
     case SNNC_FIXED_TOTAL_NUMBER: {
-        uint32_t th;
-        if (!one_host(cl.T, th)) raise(SNNC_EUNSUPPORTED, "fixed total number over targets on several hosts");
         if (cl.n > 0) {
             if (ns == 0 || nt == 0) raise(SNNC_EINVAL, "empty node set");
             const unsigned __int128 pairs = (unsigned __int128)ns * nt - ov;

@@ -146,12 +146,13 @@ struct Total {
     uint32_t autapses;
     const uint8_t* first;   // null when multapses are allowed
     uint32_t seed, call;
-    __device__ __forceinline__ int eval(uint64_t cand, Res* r) const {
+    __device__ __forceinline__ int eval(uint64_t cand, Res* r, uint32_t* th_out = nullptr) const {
         const uint4 b = draw(seed, call, cand, PURPOSE_IDX);
         const uint32_t s = uniform_index(b.x, b.y, n_s);
         const uint32_t t = uniform_index(b.z, b.w, n_t);
         uint32_t th, tl;
         set_lookup(T, nT, t, th, tl);
+        if (th_out) *th_out = th;
         if (!autapses) {
             uint32_t sh, sl;
             set_lookup(S, nS, s, sh, sl);
@@ -268,6 +269,75 @@ void launch_gen(Ctx& c, const char* name, const Rule& rule, const Sink& sink, ui
         tstart(c, name);
         hipLaunchKernelGGL((k_gen<Rule, Sink, MODE>), dim3(nb), dim3(NT), 0, c.stream, rule, sink, n_items, t0,
                            tile_counts, tile_offsets, limit);
+        tstop(c);
+        HIPCHK(hipGetLastError());
+    }
+}
+
+// ------------------------------------------------------------------ fixed total number
+// Candidates of a fixed-total-number call in order; the first `limit` valid
+// ones (global rank over all targets) are the connections, and a host keeps
+// those whose target it holds.  CNT_VALID counts valid candidates per tile;
+// CNT_KEEP counts the kept ones (ranks from the scanned valid counts);
+// WRITE_KEEP writes them at the scanned kept counts (ALL_LOCAL: every target
+// is on the host, the position is the rank itself); MARK_KEEP marks them.
+enum DistMode { CNT_VALID = 0, CNT_KEEP = 1, WRITE_KEEP = 2, MARK_KEEP = 3 };
+
+template <class Sink, int MODE, bool ALL_LOCAL>
+__global__ __launch_bounds__(NT) void k_total_dist(Total rule, uint32_t host, Sink sink, uint64_t n_items,
+                                                   uint64_t tile0, uint32_t* tile_counts, const uint64_t* valid_off,
+                                                   const uint64_t* keep_off, uint64_t limit) {
+    __shared__ uint32_t scratch[NT / 64];
+    const uint64_t tile = tile0 + blockIdx.x;
+    const uint64_t base = tile * TILE;
+    uint64_t vrun = 0, krun = 0;
+    if constexpr (MODE != CNT_VALID) vrun = valid_off[tile];
+    if constexpr (MODE == WRITE_KEEP && !ALL_LOCAL) krun = keep_off[tile];
+    uint32_t counted = 0;
+#pragma unroll 1
+    for (int it = 0; it < IPT; ++it) {
+        const uint64_t item = base + (uint64_t)it * NT + threadIdx.x;
+        Res r{};
+        uint32_t th = 0;
+        const uint32_t v = item < n_items ? (uint32_t)rule.eval(item, &r, &th) : 0u;
+        if constexpr (MODE == CNT_VALID) {
+            counted += v;
+        } else {
+            uint32_t vtot;
+            const uint32_t vpre = block_excl_scan<NT>(v, scratch, &vtot);
+            const uint64_t rank = vrun + vpre;
+            const bool keep = v && (ALL_LOCAL || th == host) && rank < limit;
+            vrun += vtot;
+            if constexpr (MODE == CNT_KEEP) {
+                counted += keep ? 1u : 0u;
+            } else if constexpr (MODE == MARK_KEEP) {
+                if (keep) sink.mark(r);
+            } else if constexpr (ALL_LOCAL) {
+                if (keep) sink.put(rank, r);
+            } else {
+                uint32_t ktot;
+                const uint32_t kpre = block_excl_scan<NT>(keep ? 1u : 0u, scratch, &ktot);
+                if (keep) sink.put(krun + kpre, r);
+                krun += ktot;
+            }
+        }
+    }
+    if constexpr (MODE == CNT_VALID || MODE == CNT_KEEP) {
+        uint32_t tot;
+        block_excl_scan<NT>(counted, scratch, &tot);
+        if (threadIdx.x == 0) tile_counts[tile] = tot;
+    }
+}
+
+template <class Sink, int MODE, bool ALL_LOCAL>
+void launch_total_dist(Ctx& c, const Total& rule, uint32_t host, const Sink& sink, uint64_t n_items,
+                       uint32_t* tile_counts, const uint64_t* valid_off, const uint64_t* keep_off, uint64_t limit) {
+    const uint64_t tiles = (n_items + TILE - 1) / TILE;
+    for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
+        const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
+        tstart(c, "gen_total");
+        hipLaunchKernelGGL((k_total_dist<Sink, MODE, ALL_LOCAL>), dim3(nb), dim3(NT), 0, c.stream, rule, host, sink,
+                           n_items, t0, tile_counts, valid_off, keep_off, limit);
         tstop(c);
         HIPCHK(hipGetLastError());
     }
@@ -673,21 +743,26 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             break;
         }
         case SNNC_FIXED_TOTAL_NUMBER: {
-            uint32_t th = 0xffffffffu;
-            for (auto& g : cl.T.seg) { th = g.host; break; }
-            if (th != host || !cl.n) break;
+            // targets on several hosts: every host evaluates every candidate and
+            // keeps the first N valid ones whose target it holds
+            const uint64_t on_host = [&] {
+                uint64_t k = 0;
+                for (auto& g : cl.T.seg) if (g.host == host) k += g.n;
+                return k;
+            }();
+            if (!cl.n || !on_host) break;
+            const bool all_local = on_host == nt;
             const uint64_t N = cl.n;
             Total r{cl.dS, nS, cl.dT, nT, (uint32_t)ns, (uint32_t)nt, cl.autapses ? 1u : 0u, nullptr, c.seed, cl.id};
-            if (cl.autapses && cl.multapses) {
+            if (cl.autapses && cl.multapses && all_local) {
                 result = N;
                 if (mark) launch_gen<Total, MarkSink, MARK>(c, "gen_total", r, ms, N, nullptr, nullptr, 0);
                 else launch_gen<Total, WriteSink, DIRECT>(c, "gen_total", r, *reserve(N), N, nullptr, nullptr, 0);
                 break;
             }
-            result = N;
             // candidate window: enough draws for N valid ones (expected), grown until it is
             const double V = (double)ns * (double)nt;
-            double est = (double)N * 1.05 + 1024.0;
+            double est = cl.autapses && cl.multapses ? (double)N : (double)N * 1.05 + 1024.0;
             if (!cl.multapses) {
                 const double frac = std::min(0.999999, (double)N / V);
                 est = std::max(est, -V * std::log1p(-frac) * 1.05 + 1024.0);
@@ -721,13 +796,40 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 }
                 Total rr = r;
                 rr.first = first;
-                auto no_sink = [](uint64_t) -> WriteSink* { return nullptr; };
-                const uint64_t valid = count_and_write<Total>(c, "gen_total", rr, no_sink, C, UINT64_MAX);
+                const uint64_t tiles = (C + TILE - 1) / TILE;
+                uint32_t* cnt = dalloc_n<uint32_t>(c, tiles);
+                temps.push_back(cnt);
+                uint64_t* voff = dalloc_n<uint64_t>(c, tiles + 1);
+                temps.push_back(voff);
+                launch_total_dist<WriteSink, CNT_VALID, true>(c, rr, host, ws, C, cnt, nullptr, nullptr, 0);
+                const uint64_t valid = scan_u32_u64(c, cnt, voff, tiles, true);
                 if (valid >= N) {
-                    if (mark) count_and_write<Total>(c, "gen_total", rr, [&](uint64_t) { return &ms; }, C, N);
-                    else count_and_write<Total>(c, "gen_total", rr, reserve, C, N);
+                    uint64_t kept = N;
+                    uint64_t* koff = nullptr;
+                    if (!all_local) {
+                        koff = dalloc_n<uint64_t>(c, tiles + 1);
+                        temps.push_back(koff);
+                        launch_total_dist<WriteSink, CNT_KEEP, false>(c, rr, host, ws, C, cnt, voff, nullptr, N);
+                        kept = scan_u32_u64(c, cnt, koff, tiles, true);
+                    }
+                    result = kept;
+                    if (mark) {
+                        if (all_local) launch_total_dist<MarkSink, MARK_KEEP, true>(c, rr, host, ms, C, nullptr, voff, nullptr, N);
+                        else launch_total_dist<MarkSink, MARK_KEEP, false>(c, rr, host, ms, C, nullptr, voff, nullptr, N);
+                    } else {
+                        WriteSink* sink = reserve(kept);
+                        if (kept) {
+                            if (all_local)
+                                launch_total_dist<WriteSink, WRITE_KEEP, true>(c, rr, host, *sink, C, nullptr, voff, koff, N);
+                            else
+                                launch_total_dist<WriteSink, WRITE_KEEP, false>(c, rr, host, *sink, C, nullptr, voff, koff, N);
+                        }
+                    }
                     break;
                 }
+                dfree(c, cnt);
+                dfree(c, voff);
+                temps.resize(temps.size() - 2);
                 if (first) {
                     dfree(c, first);
                     temps.pop_back();
@@ -872,11 +974,15 @@ bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<void*>& owned) {
         q.outd = OutDegree{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt, cl.dT, nT, host, c.seed, cl.id};
         return true;
     }
-    case SNNC_FIXED_TOTAL_NUMBER:
+    case SNNC_FIXED_TOTAL_NUMBER: {
         if (!cl.autapses || !cl.multapses) return false;
+        uint64_t on_host = 0;
+        for (auto& g : cl.T.seg) if (g.host == host) on_host += g.n;
+        if (on_host != nt) return false;   // targets on several hosts: candidates are filtered
         q.kind = F_TOTAL;
         q.tot = Total{cl.dS, nS, cl.dT, nT, (uint32_t)ns, (uint32_t)nt, 1u, nullptr, c.seed, cl.id};
         return true;
+    }
     case SNNC_ONE_TO_ONE: {
         auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, 1, MAX_RUN_ELEMS);
         if (runs_elems(runs, 1) != cl.gen_count) return false;   // some autapses are skipped

@@ -607,7 +607,7 @@ bool flag_sources(const Ctx& c, const Call& cl, uint32_t tau) {
     double est;
     switch (cl.rule) {
         case SNNC_FIXED_INDEGREE: est = (double)cl.n * n_t; break;
-        case SNNC_FIXED_TOTAL_NUMBER: est = n_t > 0.0 ? (double)cl.n : 0.0; break;
+        case SNNC_FIXED_TOTAL_NUMBER: est = (double)cl.n * n_t / (double)cl.T.total; break;
         case SNNC_PAIRWISE_BERNOULLI: est = cl.p * n_s * n_t; break;
         default: return false;
     }

@@ -272,9 +272,6 @@ def random_tiny(seed: int, P: int | None = None) -> dict:
         elif rule == "fixed_outdegree":
             conn["n"] = int(rng.integers(0, max(1, nt - 1) + 1)) if not mult else int(rng.integers(0, 12))
         elif rule == "fixed_total_number":
-            th = tgt[0][0]
-            tgt = [t for t in tgt if t[0] == th]
-            nt = sum(t[2] for t in tgt)
             conn["n"] = int(rng.integers(0, max(1, ns * nt // 2) + 1))
         else:
             conn["p"] = float(rng.choice([0.0, 0.05, 0.3, 0.7, 1.0]))

@@ -126,13 +126,32 @@ def test_total_number_exact_and_uniform():
     assert (net.array("gen_e") == np.arange(N)).all()
 
 
-def test_total_number_targets_on_several_hosts_unsupported():
-    net = oracle.OracleNet(2, 0, 1, 0.1)
-    a = net.create(0, 5)
-    b = net.create(1, 5)
-    with pytest.raises(oracle.OracleError) as e:
-        net.connect([a], [a, b], {"rule": "fixed_total_number", "n": 3}, SYN)
-    assert e.value.code == -5
+@pytest.mark.parametrize("aut,mult", [(True, True), (False, True), (True, False), (False, False)])
+def test_total_number_over_several_hosts(aut, mult):
+    """Targets on three hosts: the hosts' shares together are exactly the first
+    N valid candidates of the same rule on one host holding all neurons (same
+    ordinals, same draws), and each host keeps the ones it holds."""
+    N, sizes = 700, [30, 45, 25]
+    conn = {"rule": "fixed_total_number", "n": N, "autapses": aut, "multapses": mult}
+    shares = []
+    for pl in range(3):
+        net = oracle.OracleNet(3, pl, 17, 0.1)
+        pops = [net.create(h, n) for h, n in enumerate(sizes)]
+        net.connect(pops, pops, conn, SYN)
+        shares.append((net.array("gen_e"), net.array("gen_src"), net.array("gen_tgt")))
+    one = oracle.OracleNet(1, 0, 17, 0.1)
+    pop = one.create(0, sum(sizes))
+    one.connect([pop], [pop], conn, SYN)
+    e1, s1, t1 = one.array("gen_e"), one.array("gen_src"), one.array("gen_tgt")
+    assert e1.size == N
+    e_all = np.concatenate([sh[0] for sh in shares])
+    assert np.array_equal(np.sort(e_all), e1)
+    first = np.cumsum([0] + sizes)
+    for pl, (e, s, t) in enumerate(shares):
+        idx = np.searchsorted(e1, e)
+        assert (s == s1[idx]).all()
+        assert (t + first[pl] == t1[idx]).all()           # same target, as a local id of host pl
+        assert ((t1 >= first[pl]) & (t1 < first[pl + 1])).sum() == e.size
 
 
 @pytest.mark.parametrize("p", [0.0, 0.03, 0.5, 1.0])

@@ -56,6 +56,22 @@ def test_balanced_collective_scaled():
         compare_all(s, pl)
 
 
+@pytest.mark.parametrize("aut,mult", [(True, True), (False, True), (True, False), (False, False)])
+def test_total_number_over_several_hosts(aut, mult):
+    """Fixed total number with targets on four hosts: every host keeps its
+    part of the first N valid candidates."""
+    b = W._Builder(4, seed=99)
+    pops = [b.create(h, 300 + 50 * h) for h in range(4)]
+    b.connect(pops, pops[1:], {"rule": "fixed_total_number", "n": 60000, "autapses": aut, "multapses": mult},
+              SYN_N, -1)
+    b.connect([pops[2]], pops, {"rule": "fixed_total_number", "n": 9000, "autapses": aut, "multapses": mult},
+              SYN_N, 0)
+    s = b.script(f"total_dist_{int(aut)}{int(mult)}")
+    for pl in range(4):
+        n = compare_all(s, pl)
+        log(f"total number over hosts, P_local={pl}: {n} connections")
+
+
 @pytest.mark.parametrize("in_scale", [1, 4, 10])
 def test_balanced_indegree_scaled(in_scale):
     """In-degree sweep at a fixed connection count (fewer sources, larger K)."""
