@@ -217,11 +217,14 @@ def served(args):
 
     def run(mode):
         net = fresh()
+        net.set_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        t_host = 0.0
         admitted = 0
         for k, op in enumerate(reqs):
             _, src, tgt, conn, syn, alpha = op
+            th = time.perf_counter()
             try:
                 if mode == "per_call":
                     net.connect(src, tgt, conn, syn, alpha)
@@ -231,6 +234,7 @@ def served(args):
             except snnc.SnncError as e:
                 if e.code != -3:
                     raise
+            t_host += time.perf_counter() - th
             if mode == "batched" and (k + 1) % args.batch == 0:
                 net.flush()
         net.flush() if mode == "batched" else None
@@ -241,10 +245,14 @@ def served(args):
         t_all = time.perf_counter() - t0
         n = net.count("src")
         st = net.stats()
+        kt = net.kernel_times()
         net.close()
+        gen_kernels = {k: round(v[1], 2) for k, v in sorted(kt.items(), key=lambda kv: -kv[1][1])
+                       if k.startswith("gen") or k.startswith("fused")}
         return {"connections": n, "admitted": admitted, "rejected": len(reqs) - admitted, "gen_s": round(t_gen, 4),
                 "total_s": round(t_all, 4), "Gconn_s": round(n / t_all / 1e9, 4),
-                "gen_Gconn_s": round(n / t_gen / 1e9, 4), "sort_passes": st["sort_passes"]}
+                "gen_Gconn_s": round(n / t_gen / 1e9, 4), "sort_passes": st["sort_passes"],
+                "submit_host_s": round(t_host, 4), "gen_kernel_ms": gen_kernels}
 
     res_b = run("batched")
     res_p = run("per_call")

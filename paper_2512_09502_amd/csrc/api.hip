@@ -230,6 +230,8 @@ static void validate(const Ctx& c, Call& cl, const snnc_syn_spec* syn) {
     }
     case SNNC_PAIRWISE_BERNOULLI:
         if (!(cl.p >= 0.0 && cl.p <= 1.0)) raise(SNNC_EINVAL, "probability outside [0, 1]");
+        cl.btab.resize(64);
+        build_bern_table(cl.p, cl.btab.data());
         break;
     default:
         raise(SNNC_EINVAL, "unknown rule");
@@ -256,22 +258,45 @@ static void validate(const Ctx& c, Call& cl, const snnc_syn_spec* syn) {
     } else raise(SNNC_EINVAL, "unknown delay distribution");
 }
 
-// device copies of a call's sets and delay table (one allocation)
+// Gap thresholds of a Bernoulli(p) sequence: the failures before the next
+// success are #{k < 64 : w >= thr[k]} for a uniform 32-bit word w, with
+// thr[k] = ceil((1 - (1 - p)^(k+1)) 2^32); the powers come from repeated
+// products (correctly rounded operations only, so the table does not depend
+// on a math library).
+void build_bern_table(double p, uint64_t* thr) {
+#pragma clang fp contract(off)
+    const double q = 1.0 - p;
+    double pw = 1.0;
+    for (int k = 0; k < 64; ++k) {
+        pw = pw * q;
+        double v = std::ceil((1.0 - pw) * 4294967296.0);
+        if (v < 0.0) v = 0.0;
+        if (v > 4294967296.0) v = 4294967296.0;
+        thr[k] = (uint64_t)v;
+    }
+}
+
+// device copies of a call's sets, Bernoulli gap table and delay table (one allocation)
 static void upload_meta(Ctx& c, Call& cl) {
     const size_t nS = std::max<size_t>(cl.S.seg.size(), 1), nT = std::max<size_t>(cl.T.seg.size(), 1);
-    const size_t bytes = (nS + nT) * sizeof(SegD) + std::max<size_t>(cl.dtab.size(), 1) * sizeof(uint32_t);
+    const size_t nB = cl.btab.size();
+    const size_t bytes = (nS + nT) * sizeof(SegD) + nB * sizeof(uint64_t) +
+                         std::max<size_t>(cl.dtab.size(), 1) * sizeof(uint32_t);
     std::vector<char> host(bytes, 0);
     SegD* hS = reinterpret_cast<SegD*>(host.data());
     SegD* hT = hS + nS;
     for (size_t i = 0; i < cl.S.seg.size(); ++i) hS[i] = SegD{cl.S.ord_begin[i], cl.S.seg[i].host, cl.S.seg[i].first};
     for (size_t i = 0; i < cl.T.seg.size(); ++i) hT[i] = SegD{cl.T.ord_begin[i], cl.T.seg[i].host, cl.T.seg[i].first};
-    if (!cl.dtab.empty()) memcpy(hT + nT, cl.dtab.data(), cl.dtab.size() * sizeof(uint32_t));
+    uint64_t* hB = reinterpret_cast<uint64_t*>(hT + nT);
+    if (nB) memcpy(hB, cl.btab.data(), nB * sizeof(uint64_t));
+    if (!cl.dtab.empty()) memcpy(hB + nB, cl.dtab.data(), cl.dtab.size() * sizeof(uint32_t));
     cl.meta = dalloc(c, bytes);
     cl.meta_bytes = bytes;
     upload(c, cl.meta, host.data(), bytes);
     cl.dS = static_cast<SegD*>(cl.meta);
     cl.dT = cl.dS + nS;
-    cl.dtab_dev = reinterpret_cast<uint32_t*>(cl.dT + nT);
+    cl.btab_dev = nB ? reinterpret_cast<uint64_t*>(cl.dT + nT) : nullptr;
+    cl.dtab_dev = reinterpret_cast<uint32_t*>(reinterpret_cast<uint64_t*>(cl.dT + nT) + nB);
 }
 
 void grow_gen(Ctx& c, uint64_t need) {
@@ -730,6 +755,12 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
             raise(SNNC_EINVAL, std::string("unknown tuning key ") + key);
         }
     });
+}
+
+snnc_status snnc_bern_table(double p, uint64_t* thr) {
+    if (!thr || !(p >= 0.0 && p <= 1.0)) return SNNC_EINVAL;
+    snnc::build_bern_table(p, thr);
+    return SNNC_OK;
 }
 
 snnc_status snnc_set_map_policy(snnc_ctx* c, int32_t numbering, int32_t image_sources, double xi) {

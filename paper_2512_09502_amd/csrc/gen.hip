@@ -164,45 +164,111 @@ struct Total {
     }
 };
 
-// Pairwise Bernoulli: pair q = t_ord n_s + s_ord connects iff word (q mod 4)
-// of BERN(q / 4) is below floor(p 2^32).  Item = (target, block of that
-// target's pair range); a block shared by two targets is drawn by both and
-// each keeps its own pairs.
-struct Bernoulli {
-    static constexpr int R = 4;
+// Pairwise Bernoulli: the pairs of a target are taken in blocks of 64 source
+// ordinals; item = (target, block j), element eb = t_ord nb + j.  Inside a
+// block the successes follow from geometric gaps: step m reads word m % 4 of
+// BERN(eb, sub = m / 4), the gap is the number of thresholds at or below the
+// word, a success lands at pos + gap while inside the block.  A connection's
+// element index is its pair index q = t_ord n_s + s_ord.
+struct BernGap {
     const TChunk* ch;
     uint32_t nch;
-    uint32_t nb;      // blocks per target item range
+    uint32_t nb;      // blocks per target
     FastDiv fnb;
     uint32_t n_s;
-    uint64_t thr;     // floor(p 2^32), 2^32 for p = 1
+    const uint64_t* thr;   // 64 gap thresholds
     uint32_t autapses;
     uint32_t seed, call;
-    __device__ __forceinline__ int eval(uint64_t g, Res* r) const {
-        const TChunk c = ch[find_chunk(ch, nch, g)];
-        const uint32_t rel = (uint32_t)(g - c.out_begin);
-        const uint32_t t_rel = fastdiv(rel, fnb);
-        const uint32_t k = rel - t_rel * nb;
-        const uint64_t t_ord = c.t_ord + t_rel;
-        const uint64_t q0 = t_ord * n_s, q1 = q0 + n_s;
-        const uint64_t blk = (q0 >> 2) + k;
-        if (blk * 4 >= q1) return 0;
-        const uint4 b = draw(seed, call, blk, PURPOSE_BERN);
-        const uint32_t w[4] = {b.x, b.y, b.z, b.w};
-        const int64_t self = c.self_base >= 0 ? c.self_base + t_rel : -1;
-        int n = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint64_t q = blk * 4 + i;
-            if (q < q0 || q >= q1) continue;
-            if ((uint64_t)w[i] >= thr) continue;
-            const uint64_t s = q - q0;
-            if (!autapses && (int64_t)s == self) continue;
-            r[n++] = Res{(uint32_t)s, c.local_first + t_rel, q};
-        }
-        return n;
-    }
 };
+
+__device__ __forceinline__ uint4 draw_sub(uint32_t seed, uint32_t call, uint64_t e, uint32_t purpose, uint32_t sub) {
+    return philox10(make_uint4((uint32_t)e, (uint32_t)(e >> 32), purpose, sub), seed, call);
+}
+
+// visit the connections of item g in source order; thr is the LDS copy of the table
+template <class F>
+__device__ __forceinline__ void bern_visit(const BernGap& r, const uint64_t* thr, uint64_t g, F&& f) {
+    const TChunk c = r.ch[find_chunk(r.ch, r.nch, g)];
+    const uint32_t rel = (uint32_t)(g - c.out_begin);
+    const uint32_t t_rel = fastdiv(rel, r.fnb);
+    const uint32_t j = rel - t_rel * r.nb;
+    const uint64_t t_ord = c.t_ord + t_rel;
+    const uint64_t eb = t_ord * r.nb + j;
+    const uint32_t s0 = j * 64;
+    const uint32_t len = r.n_s - s0 < 64 ? r.n_s - s0 : 64;
+    const int64_t self = c.self_base >= 0 ? c.self_base + t_rel : -1;
+    const uint32_t tgt = c.local_first + t_rel;
+    uint32_t pos = 0;
+    uint4 b = make_uint4(0, 0, 0, 0);
+    for (uint32_t m = 0;; ++m) {
+        if ((m & 3u) == 0) b = draw_sub(r.seed, r.call, eb, PURPOSE_BERN, m >> 2);
+        const uint32_t w = (m & 3u) == 0 ? b.x : (m & 3u) == 1 ? b.y : (m & 3u) == 2 ? b.z : b.w;
+        uint32_t lo = 0, hi = 64;   // gap = #{k : thr[k] <= w} (thresholds non-decreasing)
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (thr[mid] <= (uint64_t)w) lo = mid + 1; else hi = mid;
+        }
+        if (pos + lo >= len) break;
+        const uint32_t s = s0 + pos + lo;
+        pos += lo + 1;
+        if (!r.autapses && (int64_t)s == self) continue;
+        f(Res{s, tgt, t_ord * r.n_s + s});
+    }
+}
+
+template <class Sink, int MODE>
+__global__ __launch_bounds__(NT) void k_bern(BernGap r, Sink sink, uint64_t n_items, uint64_t tile0,
+                                             uint32_t* tile_counts, const uint64_t* tile_offsets) {
+    __shared__ uint64_t thr[64];
+    __shared__ uint32_t scratch[NT / 64];
+    if (threadIdx.x < 64) thr[threadIdx.x] = r.thr[threadIdx.x];
+    __syncthreads();
+    const uint64_t tile = tile0 + blockIdx.x;
+    const uint64_t base = tile * TILE;
+    uint64_t running = 0;
+    if constexpr (MODE == WRITE) running = tile_offsets[tile];
+    uint32_t counted = 0;
+#pragma unroll 1
+    for (int it = 0; it < IPT; ++it) {
+        const uint64_t item = base + (uint64_t)it * NT + threadIdx.x;
+        if constexpr (MODE == MARK) {
+            if (item < n_items) bern_visit(r, thr, item, [&](const Res& x) { sink.mark(x); });
+            continue;
+        }
+        uint32_t n = 0;
+        if (item < n_items) bern_visit(r, thr, item, [&](const Res&) { ++n; });
+        if constexpr (MODE == COUNT) {
+            counted += n;
+        } else {
+            uint32_t tot;
+            const uint32_t pre = block_excl_scan<NT>(n, scratch, &tot);
+            if (n) {
+                uint64_t pos = running + pre;
+                bern_visit(r, thr, item, [&](const Res& x) { sink.put(pos++, x); });
+            }
+            running += tot;
+        }
+    }
+    if constexpr (MODE == COUNT) {
+        uint32_t tot;
+        block_excl_scan<NT>(counted, scratch, &tot);
+        if (threadIdx.x == 0) tile_counts[tile] = tot;
+    }
+}
+
+template <class Sink, int MODE>
+void launch_bern(Ctx& c, const BernGap& r, const Sink& sink, uint64_t n_items, uint32_t* tile_counts,
+                 const uint64_t* tile_offsets) {
+    const uint64_t tiles = (n_items + TILE - 1) / TILE;
+    for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
+        const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
+        tstart(c, "gen_bernoulli");
+        hipLaunchKernelGGL((k_bern<Sink, MODE>), dim3(nb), dim3(NT), 0, c.stream, r, sink, n_items, t0, tile_counts,
+                           tile_offsets);
+        tstop(c);
+        HIPCHK(hipGetLastError());
+    }
+}
 
 // One-to-one: element i connects source ordinal i to target ordinal i; it is
 // an autapse exactly when the target's own source ordinal equals i.
@@ -841,16 +907,26 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
         }
         case SNNC_PAIRWISE_BERNOULLI: {
             if (!ns || !nt) break;
-            const uint32_t nb = (uint32_t)((ns + 3) / 4 + 1);
+            const uint32_t nb = (uint32_t)((ns + 63) / 64);
             auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, nb, MAX_RUN_ELEMS);
             const uint64_t items = runs_elems(runs, nb);
             if (!items) break;
             DeviceChunks dc = upload_chunks(c, runs, items);
             temps.push_back(dc.d);
-            const uint64_t thr = cl.p >= 1.0 ? (1ull << 32) : (uint64_t)std::floor(cl.p * 4294967296.0);
-            Bernoulli r{dc.d, dc.n, nb, make_fastdiv(nb), (uint32_t)ns, thr, cl.autapses ? 1u : 0u, c.seed, cl.id};
-            if (mark) launch_gen<Bernoulli, MarkSink, MARK>(c, "gen_bernoulli", r, ms, items, nullptr, nullptr, 0);
-            else result = count_and_write<Bernoulli>(c, "gen_bernoulli", r, reserve, items, UINT64_MAX);
+            BernGap r{dc.d, dc.n, nb, make_fastdiv(nb), (uint32_t)ns, cl.btab_dev, cl.autapses ? 1u : 0u, c.seed, cl.id};
+            if (mark) {
+                launch_bern<MarkSink, MARK>(c, r, ms, items, nullptr, nullptr);
+                break;
+            }
+            const uint64_t tiles = (items + TILE - 1) / TILE;
+            uint32_t* cnt = dalloc_n<uint32_t>(c, tiles);
+            temps.push_back(cnt);
+            uint64_t* off = dalloc_n<uint64_t>(c, tiles + 1);
+            temps.push_back(off);
+            launch_bern<WriteSink, COUNT>(c, r, ws, items, cnt, nullptr);
+            result = scan_u32_u64(c, cnt, off, tiles, true);
+            WriteSink* sink = reserve(result);
+            if (result) launch_bern<WriteSink, WRITE>(c, r, *sink, items, nullptr, off);
             break;
         }
         case SNNC_ONE_TO_ONE: {

@@ -38,11 +38,14 @@ struct CallD {
     uint32_t flag;   // 1: only the sources its local connections use get images
     uint32_t uniform;   // 1: all source segments have the same length (segment = ordinal / length)
     FastDiv seg_div;
+    const int64_t* seg_base;   // per segment: bit of its first neuron minus its first ordinal
+    uint64_t local_lo;         // bit of P_local's neuron 0 in this call's map index
 };
 
 // segment lookup by division when every source segment of the call has the same length
 CallD make_calld(const Call& cl, uint32_t order, uint32_t flag) {
-    CallD d{cl.gen_begin, cl.dS, (uint32_t)cl.S.seg.size(), (uint32_t)(cl.alpha + 1), order, flag, 0, FastDiv{}};
+    CallD d{cl.gen_begin, cl.dS, (uint32_t)cl.S.seg.size(), (uint32_t)(cl.alpha + 1), order, flag, 0, FastDiv{},
+            nullptr, 0};
     const auto& seg = cl.S.seg;
     bool uniform = seg.size() > 1 && seg[0].n > 0 && cl.S.total < (1ull << 31);
     for (const auto& g : seg) uniform = uniform && g.n == seg[0].n;
@@ -144,25 +147,68 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
     const uint32_t dmask = (1u << dbits) - 1;
     uint64_t lo, hi;
     block_range(n, lo, hi);
-    SourceCursor cur;
-    for (uint64_t base = lo; base < hi; base += PNT) {
-        const uint64_t i = base + threadIdx.x;
-        const bool valid = i < hi;
-        uint64_t key = 0;
-        if (valid) {
-            uint32_t host, local;
-            uint64_t bit;
-            cur.at(L, i, g_src[i], host, local, bit);
+    // call of the current window (a workgroup's range crosses few calls)
+    uint64_t call_lo = 1, call_hi = 0;
+    CallD cd{};
+    uint32_t last_sidx = ~0u;   // segment whose base is cached (single-segment calls load it once)
+    int64_t last_base = 0;
+    constexpr int KU = 4;   // independent elements per thread per step: their table loads overlap
+    for (uint64_t base = lo; base < hi; base += (uint64_t)PNT * KU) {
+        uint32_t ord[KU], tg[KU];
+        uint16_t dl[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const uint64_t i = base + (uint64_t)u * PNT + threadIdx.x;
+            if (i < hi) {
+                ord[u] = g_src[i];
+                tg[u] = g_tgt[i];
+                dl[u] = g_delay[i];
+            }
+        }
+        uint64_t key[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const uint64_t i = base + (uint64_t)u * PNT + threadIdx.x;
+            key[u] = 0;
+            if (i >= hi) continue;
+            if (i < call_lo || i >= call_hi) {
+                const uint32_t k = find_call(L.calls, L.ncalls, i);
+                cd = L.calls[k];
+                call_lo = cd.gen_begin;
+                call_hi = k + 1 < L.ncalls ? L.calls[k + 1].gen_begin : ~0ull;
+                last_sidx = ~0u;
+            }
+            uint32_t sidx;
+            if (cd.uniform) {
+                sidx = fastdiv(ord[u], cd.seg_div);
+            } else {
+                uint32_t a = 0, b = cd.nS;
+                while (b - a > 1) {
+                    const uint32_t m = (a + b) >> 1;
+                    if (cd.S[m].ord_begin <= ord[u]) a = m; else b = m;
+                }
+                sidx = a;
+            }
+            if (sidx != last_sidx) {
+                last_base = cd.seg_base[sidx];
+                last_sidx = sidx;
+            }
+            const uint64_t bit = (uint64_t)(last_base + (int64_t)ord[u]);
+            const uint64_t rel = bit - cd.local_lo;   // the local neuron, when below M_local
             // remote sources: the image index L when the images were numbered before the sort,
             // else the global prefix M_local + bit (images are numbered after the sort)
-            const uint64_t src2 = host == L.PL ? local
-                                  : bits       ? (uint64_t)Lmap[rank_of(bits, word_rank, bit)]
-                                               : (uint64_t)M_local + bit;
-            key = (src2 << tgt_shift) | ((uint64_t)g_tgt[i] << 16) | g_delay[i];
-            keys[i] = key;
+            const uint64_t src2 = rel < M_local ? rel
+                                  : bits        ? (uint64_t)Lmap[rank_of(bits, word_rank, bit)]
+                                                : (uint64_t)M_local + bit;
+            key[u] = (src2 << tgt_shift) | ((uint64_t)tg[u] << 16) | dl[u];
+            keys[i] = key[u];
         }
-        for (uint32_t p = 0; p < passes; ++p)
-            wave_hist_add(&h[p * HIST_STRIDE], (uint32_t)((key >> (16 + p * dbits)) & dmask), valid);
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const bool valid = base + (uint64_t)u * PNT + threadIdx.x < hi;
+            for (uint32_t p = 0; p < passes; ++p)
+                wave_hist_add(&h[p * HIST_STRIDE], (uint32_t)((key[u] >> (16 + p * dbits)) & dmask), valid);
+        }
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < passes * HIST_STRIDE; i += PNT)
@@ -178,7 +224,7 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
 // image index.  The same pass unpacks the connection arrays, records each
 // image's prefix and writes the first-index array.
 constexpr int XNT = 256;
-constexpr int XIPT = 16;
+constexpr int XIPT = 12;
 constexpr uint64_t XTILE = XNT * XIPT;
 constexpr uint64_t XFLAG_AGG = 1ull << 62, XFLAG_INC = 2ull << 62, XVALUE = (1ull << 40) - 1;
 constexpr uint32_t XEPOCH_MAX = (1u << 22) - 1;
@@ -197,20 +243,25 @@ __global__ __launch_bounds__(XNT) void k_number(const uint64_t* __restrict__ key
     __syncthreads();
     const uint64_t tile = s_tile;
     const uint64_t wbase = tile * XTILE + (uint64_t)wave * 64 * XIPT;
-    // element of item k on this lane: wbase + k*64 + lane (wave-striped, so loads and stores coalesce)
-    uint64_t p[XIPT];
+    // element of item k on this lane: wbase + k*64 + lane (wave-striped, so loads and stores coalesce);
+    // the keys stay in registers for the second half (a reload would come from HBM again)
+    uint64_t key[XIPT];
     uint32_t incl[XIPT];          // flags up to and including the item, within the wave
-    uint64_t last = wbase > 0 && wbase - 1 < n ? (keys[wbase - 1] >> tgt_shift) : ~0ull;   // prefix before the wave
+    uint32_t fl = 0;              // bit k: item k starts a new image
+    const uint64_t before_wave = wbase > 0 && wbase - 1 < n ? (keys[wbase - 1] >> tgt_shift) : ~0ull;
+    uint64_t last = before_wave;  // prefix before the wave
     uint32_t carry = 0;
 #pragma unroll
     for (int k = 0; k < XIPT; ++k) {
         const uint64_t i = wbase + (uint64_t)k * 64 + lane;
-        p[k] = i < n ? keys[i] >> tgt_shift : ~0ull;
-        uint64_t prev = __shfl_up(p[k], 1, 64);
-        const uint64_t last_lane = __shfl(p[k], 63, 64);
+        key[k] = i < n ? keys[i] : ~0ull;
+        const uint64_t pk = i < n ? key[k] >> tgt_shift : ~0ull;
+        uint64_t prev = __shfl_up(pk, 1, 64);
+        const uint64_t last_lane = __shfl(pk, 63, 64);
         if (lane == 0) prev = last;
         last = last_lane;
-        const uint32_t f = (i < n && p[k] >= M_local && (i == 0 || p[k] != prev)) ? 1u : 0u;
+        const uint32_t f = (i < n && pk >= M_local && (i == 0 || pk != prev)) ? 1u : 0u;
+        fl |= f << k;
         const uint32_t s = wave_incl_scan(f);
         incl[k] = carry + s;
         carry += __shfl(s, 63, 64);
@@ -254,29 +305,29 @@ __global__ __launch_bounds__(XNT) void k_number(const uint64_t* __restrict__ key
     }
     __syncthreads();
     const uint64_t before = s_excl + wave_excl;   // images started before this wave
+    last = before_wave;
 #pragma unroll
     for (int k = 0; k < XIPT; ++k) {
         const uint64_t i = wbase + (uint64_t)k * 64 + lane;
+        const uint64_t pk = key[k] >> tgt_shift;
+        // prefix of the previous connection, again from the neighbouring lane
+        uint64_t pp = __shfl_up(pk, 1, 64);
+        const uint64_t last_lane = __shfl(pk, 63, 64);
+        if (lane == 0) pp = last;
+        last = last_lane;
         if (i >= n) continue;
-        const uint64_t key = keys[i];
         const uint64_t rank = before + incl[k];                 // images started up to and including i
-        const bool local = p[k] < M_local;
-        const int64_t src2 = local ? (int64_t)p[k] : (int64_t)(M_local + rank - 1);
+        const bool local = pk < M_local;
+        const int64_t src2 = local ? (int64_t)pk : (int64_t)(M_local + rank - 1);
         o_src[i] = (int32_t)src2;
-        o_tgt[i] = (int32_t)((key >> 16) & tgt_mask);
-        o_delay[i] = (uint16_t)(key & 0xffffu);
+        o_tgt[i] = (int32_t)((key[k] >> 16) & tgt_mask);
+        o_delay[i] = (uint16_t)(key[k] & 0xffffu);
         o_weight[i] = __uint_as_float(vals[i]);
         // previous connection's source' (its flag count is rank minus this item's flag)
+        const bool flag_here = (fl >> k) & 1u;
         int64_t prev2 = -1;
-        bool flag_here = false;
-        if (i > 0) {
-            const uint64_t pp = keys[i - 1] >> tgt_shift;
-            flag_here = !local && pp != p[k];
-            prev2 = pp < M_local ? (int64_t)pp : (int64_t)(M_local + rank - (flag_here ? 1 : 0) - 1);
-        } else {
-            flag_here = !local;
-        }
-        if (flag_here) img_key[rank - 1] = p[k] - M_local;
+        if (i > 0) prev2 = pp < M_local ? (int64_t)pp : (int64_t)(M_local + rank - (flag_here ? 1 : 0) - 1);
+        if (flag_here) img_key[rank - 1] = pk - M_local;
         for (int64_t r = prev2 + 1; r <= src2; ++r) row_ptr[r] = i;
         if (i + 1 == n) {
             const int64_t n_rows = (int64_t)M_local + (int64_t)rank;
@@ -662,11 +713,24 @@ void prepare_all(Ctx& c) {
         std::vector<uint8_t> flag_local(n_calls);
         for (uint32_t k = 0; k < n_calls; ++k) flag_local[k] = flag_sources(c, c.calls[k], PL) ? 1 : 0;
         std::vector<CallD> calls;
+        std::vector<int64_t> seg_base;   // all calls' segment tables, concatenated
+        std::vector<size_t> seg_at;
         for (uint32_t k = 0; k < n_calls; ++k) {
             const Call& cl = c.calls[k];
-            if (cl.gen_count) calls.push_back(make_calld(cl, k, flag_local[k]));
+            if (!cl.gen_count) continue;
+            CallD d = make_calld(cl, k, flag_local[k]);
+            const uint64_t a = (uint64_t)(cl.alpha + 1);
+            seg_at.push_back(seg_base.size());
+            for (size_t j = 0; j < cl.S.seg.size(); ++j)
+                seg_base.push_back((int64_t)(a * G + host_base[cl.S.seg[j].host] + cl.S.seg[j].first) -
+                                   (int64_t)cl.S.ord_begin[j]);
+            d.local_lo = a * G + host_base[PL];
+            calls.push_back(d);
         }
-        if (calls.empty()) calls.push_back(CallD{0, nullptr, 0, 0, 0, 0, 0, FastDiv{}});
+        int64_t* d_seg_base = static_cast<int64_t*>(tmp(std::max<size_t>(seg_base.size(), 1) * 8));
+        upload(c, d_seg_base, seg_base.data(), seg_base.size() * 8);
+        for (size_t k = 0; k < calls.size(); ++k) calls[k].seg_base = d_seg_base + seg_at[k];
+        if (calls.empty()) calls.push_back(CallD{0, nullptr, 0, 0, 0, 0, 0, FastDiv{}, nullptr, 0});
         CallD* d_calls = static_cast<CallD*>(tmp(calls.size() * sizeof(CallD)));
         upload(c, d_calls, calls.data(), calls.size() * sizeof(CallD));
         uint64_t* d_hb = static_cast<uint64_t*>(tmp((P + 1) * 8));

@@ -228,3 +228,63 @@ def test_invalid_specs_rejected():
     with pytest.raises(oracle.OracleError):       # p outside [0, 1]
         net.connect([a], [a], {"rule": "pairwise_bernoulli", "p": 1.5}, SYN)
     net.connect([a], [a], {"rule": "fixed_indegree", "n": 4, "autapses": False, "multapses": False}, SYN)
+
+
+@pytest.mark.parametrize("p", [0.0, 1e-6, 0.001, 0.03, 0.2, 0.5, 0.97, 1.0])
+def test_bernoulli_gap_table_closed_form(p):
+    """thr[k] = ceil((1 - (1-p)^(k+1)) 2^32) against exact rational arithmetic on
+    the double p (the table's repeated products may differ by a rounding)."""
+    from fractions import Fraction
+    thr = oracle.bern_table(p).astype(object)
+    q = 1 - Fraction(p)
+    prev = 0
+    for k in range(64):
+        exact = math.ceil((1 - q ** (k + 1)) * 2**32)
+        assert abs(int(thr[k]) - exact) <= 1, (k, thr[k], exact)
+        assert int(thr[k]) >= prev
+        prev = int(thr[k])
+        # the gap pmf the table implies is p (1-p)^k
+        lo = int(thr[k - 1]) if k else 0
+        pmf = (int(thr[k]) - lo) / 2**32
+        assert abs(pmf - float(Fraction(p) * q ** k)) <= 2.0 / 2**32
+
+
+def test_bernoulli_block_positions_and_pairs():
+    """Every source position inside the 64-pair blocks connects with
+    probability p, and neighbouring pairs independently (p^2)."""
+    p, n_s, reps = 0.05, 64 * 8 + 17, 300
+    net = oracle.OracleNet(1, 0, 9, 0.1)
+    a = net.create(0, n_s)
+    t = net.create(0, 4)
+    for _ in range(reps):
+        net.connect([a], [t], {"rule": "pairwise_bernoulli", "p": p}, SYN)
+    s = net.array("gen_src").astype(np.int64)
+    tg = net.array("gen_tgt").astype(np.int64) - n_s
+    n_trials = reps * 4
+    pos = np.bincount(s % 64, minlength=64)
+    per_pos = np.array([(np.arange(n_s) % 64 == k).sum() for k in range(64)]) * n_trials
+    assert stats.chisquare(pos, per_pos * p * pos.sum() / (per_pos * p).sum()).pvalue > 1e-4
+    assert abs(pos.sum() - n_trials * n_s * p) <= 5 * math.sqrt(n_trials * n_s * p * (1 - p))
+    # pairs (s, s+1) inside one block connected together
+    e = net.array("gen_e").astype(np.int64)
+    off = np.r_[0, np.nonzero(np.diff(e) <= 0)[0] + 1, e.size]     # element indices restart with each call
+    assert off.size == reps + 1
+    both = 0
+    for c in range(reps):
+        for tt in range(4):
+            sel = s[off[c]:off[c + 1]][tg[off[c]:off[c + 1]] == tt]
+            ss = set(sel.tolist())
+            both += sum(1 for x in ss if (x + 1) in ss and (x + 1) % 64 != 0)
+    n_adj = n_trials * sum(1 for x in range(n_s - 1) if (x + 1) % 64 != 0)
+    assert abs(both - n_adj * p * p) <= 5 * math.sqrt(n_adj * p * p)
+
+
+def test_bernoulli_element_replay_matches_generation():
+    net = oracle.OracleNet(1, 0, 3, 0.1)
+    a = net.create(0, 150)
+    net.connect([a], [a], {"rule": "pairwise_bernoulli", "p": 0.1, "autapses": False}, SYN)
+    e = set(net.array("gen_e").tolist())
+    rng = np.random.default_rng(0)
+    for q in rng.integers(0, 150 * 150, size=400).tolist() + sorted(e)[:100]:
+        r = net.element(0, q)
+        assert (r is not None) == (q in e)
