@@ -16,8 +16,40 @@ void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) raise(SNNC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+static void* dalloc_big(Ctx& c, size_t bytes);
+
+constexpr size_t SMALL_MAX = 1u << 20;   // blocks up to this size come from the slabs
+constexpr size_t SLAB_BYTES = 8u << 20;
+
+// Blocks up to SMALL_MAX: a free list per power-of-two class, refilled from 8 MB
+// slabs.  All device work runs on the context stream, so a block freed after
+// the work that uses it was enqueued is reused only by later work (the same
+// stream-ordered rule as the outer allocator).
 void* dalloc(Ctx& c, size_t bytes) {
     if (bytes == 0) bytes = 1;
+    if (bytes > SMALL_MAX) return dalloc_big(c, bytes);
+    size_t cls = 256;
+    while (cls < bytes) cls <<= 1;
+    auto& fl = c.small_free[cls];
+    void* p = nullptr;
+    if (!fl.empty()) {
+        p = fl.back();
+        fl.pop_back();
+    } else {
+        if (c.slab_left < cls) {
+            c.slab_cur = static_cast<char*>(dalloc_big(c, SLAB_BYTES));
+            c.slabs.push_back(c.slab_cur);
+            c.slab_left = SLAB_BYTES;
+        }
+        p = c.slab_cur;
+        c.slab_cur += cls;
+        c.slab_left -= cls;
+    }
+    c.small_live[p] = cls;
+    return p;
+}
+
+static void* dalloc_big(Ctx& c, size_t bytes) {
     bytes = (bytes + 255) & ~(size_t)255;
     if (c.budget && c.bytes_live + bytes > c.budget)
         raise(SNNC_EBUDGET, "device-memory budget exceeded (" + std::to_string(c.bytes_live + bytes) + " > " +
@@ -42,6 +74,12 @@ void* dalloc(Ctx& c, size_t bytes) {
 
 void dfree(Ctx& c, void* p) {
     if (!p) return;
+    auto sm = c.small_live.find(p);
+    if (sm != c.small_live.end()) {
+        c.small_free[sm->second].push_back(p);
+        c.small_live.erase(sm);
+        return;
+    }
     auto it = c.live.find(p);
     if (it == c.live.end()) return;
     c.bytes_live -= it->second;
@@ -373,6 +411,7 @@ static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
         HIPCHK(hipGetLastError());
     } catch (...) {
         dfree(c, cl.meta);
+        release_pre(c, cl);
         throw;
     }
     c.n_gen += cl.gen_count;
@@ -398,6 +437,7 @@ static void submit_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt
         cl.gen_count = n;
     } catch (...) {
         dfree(c, cl.meta);
+        release_pre(c, cl);
         throw;
     }
     c.n_gen += cl.gen_count;

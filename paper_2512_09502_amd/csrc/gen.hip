@@ -569,9 +569,86 @@ __global__ __launch_bounds__(64) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
     }
 }
 
+// Small degrees (K <= FLOYD_SMALL): one lane per unit, the same draws and
+// insertions as k_floyd (membership by a scan of the K chosen values), the
+// chosen values sorted ascending and emitted with j = rank.  LDS slot j of
+// lane t is [j * FNT + t], so the lanes of a wave hit distinct banks.
+constexpr uint32_t FLOYD_SMALL = 32;
+constexpr int FNT = 256;
+
+template <class Sink, int MODE>
+__global__ __launch_bounds__(FNT) void k_floyd_small(FloydArgs a, Sink sink, uint32_t* unit_counts,
+                                                     const uint64_t* unit_offsets) {
+    __shared__ uint32_t x[FLOYD_SMALL * FNT];
+    const uint32_t t = threadIdx.x;
+    for (uint64_t u = (uint64_t)blockIdx.x * FNT + t; u < a.n_units; u += (uint64_t)gridDim.x * FNT) {
+        uint32_t lo = 0, hi = a.nch;
+        const uint64_t g = u * a.K;
+        while (hi - lo > 1) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (a.ch[m].out_begin <= g) lo = m; else hi = m;
+        }
+        const TChunk c = a.ch[lo];
+        const uint32_t rel = (uint32_t)((g - c.out_begin) / a.K);
+        const uint64_t ord = c.t_ord + rel;
+        const int64_t self = c.self_base >= 0 ? c.self_base + rel : -1;
+        const uint32_t n_eff = a.n_set - (self >= 0 ? 1u : 0u);
+        const uint64_t e0 = ord * a.K;
+        for (uint32_t j = 0; j < a.K; ++j) {
+            const uint4 b = draw(a.seed, a.call, e0 + j, PURPOSE_IDX);
+            const uint32_t r = uniform_index(b.x, b.y, n_eff - a.K + j + 1);
+            bool found = false;
+            for (uint32_t i = 0; i < j; ++i) found |= x[i * FNT + t] == r;
+            x[j * FNT + t] = found ? n_eff - a.K + j : r;   // the fallback was never chosen before step j
+        }
+        for (uint32_t j = 1; j < a.K; ++j) {   // insertion sort, ascending
+            const uint32_t v = x[j * FNT + t];
+            uint32_t i = j;
+            while (i > 0 && x[(i - 1) * FNT + t] > v) {
+                x[i * FNT + t] = x[(i - 1) * FNT + t];
+                --i;
+            }
+            x[i * FNT + t] = v;
+        }
+        uint64_t running = 0;
+        if constexpr (MODE == WRITE) running = unit_offsets[u];
+        uint32_t counted = 0;
+        for (uint32_t j = 0; j < a.K; ++j) {
+            uint32_t v = x[j * FNT + t];
+            if (self >= 0 && v >= (uint64_t)self) ++v;
+            Res r{};
+            bool ok;
+            if (a.in_degree) {
+                r = Res{v, c.local_first + rel, e0 + j};
+                ok = true;
+            } else {
+                uint32_t h, l;
+                set_lookup(a.T, a.nT, v, h, l);
+                r = Res{(uint32_t)ord, l, e0 + j};
+                ok = (h == a.host);
+            }
+            if (!ok) continue;
+            if constexpr (MODE == DIRECT) sink.put(c.out_begin + (uint64_t)rel * a.K + j, r);
+            else if constexpr (MODE == MARK) sink.mark(r);
+            else if constexpr (MODE == COUNT) ++counted;
+            else sink.put(running++, r);
+        }
+        if constexpr (MODE == COUNT) unit_counts[u] = counted;
+    }
+}
+
 template <class Sink, int MODE>
 void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
     if (!a.n_units) return;
+    if (a.K <= FLOYD_SMALL) {
+        const uint32_t grid = (uint32_t)std::min<uint64_t>((a.n_units + FNT - 1) / FNT, 65536);
+        tstart(c, "gen_floyd");
+        hipLaunchKernelGGL((k_floyd_small<Sink, MODE>), dim3(grid), dim3(FNT), 0, c.stream, a, sink, unit_counts,
+                           unit_offsets);
+        tstop(c);
+        HIPCHK(hipGetLastError());
+        return;
+    }
     const uint32_t grid = (uint32_t)std::min<uint64_t>(a.n_units, 65536);
     const size_t shmem = (size_t)(a.cap + a.kpad) * 4;
     if (shmem > 160 * 1024) raise(SNNC_EUNSUPPORTED, "degree too large for the LDS sampler");
@@ -834,6 +911,26 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 est = std::max(est, -V * std::log1p(-frac) * 1.05 + 1024.0);
             }
             uint64_t C = (uint64_t)std::min(est, 4.0e9);
+            if (cl.pre_off && mode != Out::COUNT && !mark) {
+                // counted at admission: window, flags and offsets are kept with the call
+                C = cl.pre_window;
+                Total rr = r;
+                rr.first = cl.pre_first;
+                uint64_t* voff = cl.pre_off;
+                uint64_t* koff = cl.pre_koff;
+                result = cl.pre_count;
+                temps.insert(temps.end(), {(void*)voff, (void*)koff, (void*)cl.pre_first});
+                cl.pre_off = cl.pre_koff = nullptr;
+                cl.pre_first = nullptr;
+                WriteSink* sink = reserve(result);
+                if (result) {
+                    if (all_local)
+                        launch_total_dist<WriteSink, WRITE_KEEP, true>(c, rr, host, *sink, C, nullptr, voff, koff, N);
+                    else
+                        launch_total_dist<WriteSink, WRITE_KEEP, false>(c, rr, host, *sink, C, nullptr, voff, koff, N);
+                }
+                break;
+            }
             for (;;) {
                 uint8_t* first = nullptr;
                 if (!cl.multapses) {
@@ -879,6 +976,18 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                         kept = scan_u32_u64(c, cnt, koff, tiles, true);
                     }
                     result = kept;
+                    if (mode == Out::COUNT) {
+                        // keep the window, flags and offsets for the generation
+                        release_pre(c, cl);
+                        cl.pre_off = voff;
+                        cl.pre_koff = koff;
+                        cl.pre_first = first;
+                        cl.pre_window = C;
+                        cl.pre_count = kept;
+                        temps.erase(std::remove_if(temps.begin(), temps.end(),
+                                                   [&](void* q) { return q == voff || q == koff || q == first; }),
+                                    temps.end());
+                    }
                     if (mark) {
                         if (all_local) launch_total_dist<MarkSink, MARK_KEEP, true>(c, rr, host, ms, C, nullptr, voff, nullptr, N);
                         else launch_total_dist<MarkSink, MARK_KEEP, false>(c, rr, host, ms, C, nullptr, voff, nullptr, N);
@@ -919,25 +1028,55 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 break;
             }
             const uint64_t tiles = (items + TILE - 1) / TILE;
-            uint32_t* cnt = dalloc_n<uint32_t>(c, tiles);
-            temps.push_back(cnt);
-            uint64_t* off = dalloc_n<uint64_t>(c, tiles + 1);
-            temps.push_back(off);
-            launch_bern<WriteSink, COUNT>(c, r, ws, items, cnt, nullptr);
-            result = scan_u32_u64(c, cnt, off, tiles, true);
+            uint64_t* off = nullptr;
+            if (cl.pre_off && mode != Out::COUNT) {
+                // counted at admission: the tile offsets are kept with the call
+                off = cl.pre_off;
+                result = cl.pre_count;
+                cl.pre_off = nullptr;
+                temps.push_back(off);
+            } else {
+                uint32_t* cnt = dalloc_n<uint32_t>(c, tiles);
+                temps.push_back(cnt);
+                off = dalloc_n<uint64_t>(c, tiles + 1);
+                launch_bern<WriteSink, COUNT>(c, r, ws, items, cnt, nullptr);
+                result = scan_u32_u64(c, cnt, off, tiles, true);
+                if (mode == Out::COUNT) {
+                    dfree(c, cl.pre_off);
+                    cl.pre_off = off;
+                    cl.pre_count = result;
+                } else {
+                    temps.push_back(off);
+                }
+            }
             WriteSink* sink = reserve(result);
             if (result) launch_bern<WriteSink, WRITE>(c, r, *sink, items, nullptr, off);
             break;
         }
         case SNNC_ONE_TO_ONE: {
             auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, 1, MAX_RUN_ELEMS);
-            const uint64_t items = runs_elems(runs, 1);
-            if (!items) break;
-            DeviceChunks dc = upload_chunks(c, runs, items);
+            // a run is all autapses (its self position is its target ordinal) or none:
+            // drop those runs on the host, so the count is known and one launch writes
+            // element g of the kept runs at position g
+            std::vector<TChunk> kept;
+            uint64_t items = 0;
+            for (const TChunk& ch : runs) {
+                if (!cl.autapses && ch.self_base >= 0 && (uint64_t)ch.self_base == ch.t_ord) continue;
+                TChunk k = ch;
+                k.out_begin = items;
+                items += ch.n;
+                kept.push_back(k);
+            }
+            result = items;
+            if (!items) {
+                if (!mark) reserve(0);
+                break;
+            }
+            DeviceChunks dc = upload_chunks(c, kept, items);
             temps.push_back(dc.d);
-            OneToOne r{dc.d, dc.n, cl.autapses ? 1u : 0u};
+            OneToOne r{dc.d, dc.n, 1u};   // autapse runs are gone
             if (mark) launch_gen<OneToOne, MarkSink, MARK>(c, "gen_one_to_one", r, ms, items, nullptr, nullptr, 0);
-            else result = count_and_write<OneToOne>(c, "gen_one_to_one", r, reserve, items, UINT64_MAX);
+            else launch_gen<OneToOne, WriteSink, DIRECT>(c, "gen_one_to_one", r, *reserve(items), items, nullptr, nullptr, 0);
             break;
         }
         default:
@@ -1061,11 +1200,20 @@ bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<void*>& owned) {
     }
     case SNNC_ONE_TO_ONE: {
         auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, 1, MAX_RUN_ELEMS);
-        if (runs_elems(runs, 1) != cl.gen_count) return false;   // some autapses are skipped
-        DeviceChunks dc = upload_chunks(c, runs, cl.gen_count);
+        std::vector<TChunk> kept;   // runs that are all autapses are dropped (as in run_call)
+        uint64_t items = 0;
+        for (const TChunk& ch : runs) {
+            if (!cl.autapses && ch.self_base >= 0 && (uint64_t)ch.self_base == ch.t_ord) continue;
+            TChunk k = ch;
+            k.out_begin = items;
+            items += ch.n;
+            kept.push_back(k);
+        }
+        if (items != cl.gen_count) return false;
+        DeviceChunks dc = upload_chunks(c, kept, items);
         owned.push_back(dc.d);
         q.kind = F_ONE_TO_ONE;
-        q.o2o = OneToOne{dc.d, dc.n, cl.autapses ? 1u : 0u};
+        q.o2o = OneToOne{dc.d, dc.n, 1u};   // autapse runs are gone
         return true;
     }
     default:
@@ -1083,6 +1231,14 @@ __global__ void k_philox_blocks(uint32_t seed, uint32_t call, uint64_t e0, uint3
 uint64_t gen_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, Out::APPEND, nullptr); }
 
 uint64_t gen_count_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, Out::COUNT, nullptr); }
+
+void release_pre(Ctx& c, Call& cl) {
+    dfree(c, cl.pre_off);
+    dfree(c, cl.pre_koff);
+    dfree(c, cl.pre_first);
+    cl.pre_off = cl.pre_koff = nullptr;
+    cl.pre_first = nullptr;
+}
 
 void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits) { run_call(c, cl, host, Out::MARK, bits); }
 

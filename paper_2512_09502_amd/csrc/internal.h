@@ -86,6 +86,13 @@ struct Call {
     uint64_t gen_begin = 0, gen_count = 0;
     std::vector<void*> owned;   // device tables kept until the call's batch has run
     int32_t batch = -1;         // served mode: batch that generates the call (-1: not yet flushed)
+    // results of the admission count, reused by the generation: tile offsets
+    // (Bernoulli; valid-candidate offsets for fixed total number), and for fixed
+    // total number the kept-candidate offsets, first-occurrence flags and window
+    uint64_t* pre_off = nullptr;
+    uint64_t* pre_koff = nullptr;
+    uint8_t* pre_first = nullptr;
+    uint64_t pre_count = 0, pre_window = 0;
 };
 
 // ------------------------------------------------------------------ context
@@ -109,6 +116,13 @@ struct Ctx {
     uint64_t budget = 0;
     uint64_t bytes_live = 0, bytes_peak = 0;
     std::map<void*, size_t> live;
+    // small blocks (metadata, tables, tile counts) carved from slabs, so that
+    // requests do not call the outer allocator: free lists per power-of-two class
+    std::vector<void*> slabs;
+    char* slab_cur = nullptr;
+    size_t slab_left = 0;
+    std::map<size_t, std::vector<void*>> small_free;
+    std::map<void*, size_t> small_live;
     std::string last_error;
 
     std::vector<uint32_t> M;          // neurons per host
@@ -210,6 +224,8 @@ void sync(Ctx& c);
 //   lives on P_local (point-to-point send lists).
 uint64_t gen_local(Ctx& c, Call& cl);
 void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits);
+// frees what the admission count kept with a call
+void release_pre(Ctx& c, Call& cl);
 // exact number of connections the call has on P_local's share (may launch a
 // counting pass)
 uint64_t gen_count_local(Ctx& c, Call& cl);

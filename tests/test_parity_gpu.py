@@ -105,6 +105,11 @@ def _one(rule_conn, n_src=3000, n_tgt=2500, P=1, src_host=0, tgt_host=0, alpha=-
 
 @pytest.mark.parametrize("conn", [
     {"rule": "fixed_indegree", "n": 37, "autapses": False, "multapses": False},
+    {"rule": "fixed_indegree", "n": 1, "autapses": False, "multapses": False},
+    {"rule": "fixed_indegree", "n": 32, "autapses": True, "multapses": False},
+    {"rule": "fixed_indegree", "n": 33, "autapses": False, "multapses": False},
+    {"rule": "fixed_outdegree", "n": 7, "autapses": True, "multapses": False},
+    {"rule": "fixed_outdegree", "n": 32, "autapses": False, "multapses": False},
     {"rule": "fixed_indegree", "n": 300, "autapses": True, "multapses": False},
     {"rule": "fixed_outdegree", "n": 41, "autapses": False, "multapses": True},
     {"rule": "fixed_outdegree", "n": 23, "autapses": False, "multapses": False},
@@ -137,6 +142,18 @@ def test_remote_rules_all_hosts(rule):
     b.connect(src, tgt, conn, SYN_N, -1)
     b.connect(src, tgt, conn, SYN_N, 0)
     s = b.script("remote_" + rule)
+    for pl in range(3):
+        compare_all(s, pl)
+
+
+@pytest.mark.parametrize("k", [9, 50])
+def test_remote_outdegree_without_multapses(k):
+    # counting, writing and point-to-point marking through both samplers (small and large K)
+    b = W._Builder(3, seed=8)
+    p = [b.create(h, 400) for h in range(3)]
+    conn = {"rule": "fixed_outdegree", "n": k, "autapses": False, "multapses": False}
+    b.connect([(1, 0, 400), (2, 0, 100)], [(0, 0, 400), (2, 0, 400), (1, 0, 400)], conn, SYN_N, -1)
+    s = b.script(f"remote_outdegree_k{k}")
     for pl in range(3):
         compare_all(s, pl)
 
