@@ -16,18 +16,57 @@ void hip_check(hipError_t e, const char* what) {
     if (e != hipSuccess) raise(SNNC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-static void* dalloc_big(Ctx& c, size_t bytes);
-
 constexpr size_t SMALL_MAX = 1u << 20;   // blocks up to this size come from the slabs
 constexpr size_t SLAB_BYTES = 8u << 20;
 
-// Blocks up to SMALL_MAX: a free list per power-of-two class, refilled from 8 MB
-// slabs.  All device work runs on the context stream, so a block freed after
-// the work that uses it was enqueued is reused only by later work (the same
-// stream-ordered rule as the outer allocator).
+// Memory from the outer allocator.  `live` keeps the size with the lane in
+// bit 0: lane 0 uses the caller's allocator (else stream-ordered allocation
+// on the caller's stream), lane 1 stream-ordered allocation on the counting
+// stream.
+static void* raw_alloc(Ctx& c, size_t bytes, int lane) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (c.budget && c.bytes_live + bytes > c.budget)
+        raise(SNNC_EBUDGET, "device-memory budget exceeded (" + std::to_string(c.bytes_live + bytes) + " > " +
+                                std::to_string(c.budget) + " bytes)");
+    void* p = nullptr;
+    if (lane == 0 && c.has_alloc) {
+        p = c.alloc.alloc(bytes, (void*)c.main_stream, c.alloc.user);
+        if (!p) raise(SNNC_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        // stream-ordered: a buffer freed after enqueued work is reused only by later work
+        hipError_t e = hipMallocAsync(&p, bytes, lane == 0 ? c.main_stream : c.count_stream);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            raise(SNNC_ENOMEM, "hipMallocAsync failed for " + std::to_string(bytes) + " bytes");
+        }
+    }
+    c.live[p] = bytes | (size_t)lane;
+    c.bytes_live += bytes;
+    c.bytes_peak = std::max(c.bytes_peak, c.bytes_live);
+    return p;
+}
+
+static void raw_free(Ctx& c, void* p) {
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;
+    const size_t bytes = it->second & ~(size_t)255;
+    const int lane = (int)(it->second & 1);
+    c.bytes_live -= bytes;
+    c.live.erase(it);
+    if (lane == 0 && c.has_alloc) c.alloc.free(p, c.alloc.user);
+    else (void)hipFreeAsync(p, lane == 0 ? c.main_stream : c.count_stream);
+}
+
+// Blocks up to SMALL_MAX come from a free list per power-of-two class,
+// refilled from 8 MB slabs; larger blocks of the caller's lane go to the outer
+// allocator.  A block freed after the work that uses it was enqueued is
+// reused only by later work of the same stream.  The counting lane keeps every
+// block it allocates (large ones too) in its own class lists; its blocks freed
+// while the caller's stream may still use them wait for a fence (see
+// CountScope).
 void* dalloc(Ctx& c, size_t bytes) {
     if (bytes == 0) bytes = 1;
-    if (bytes > SMALL_MAX) return dalloc_big(c, bytes);
+    if (c.lane == 0 && bytes > SMALL_MAX) return raw_alloc(c, bytes, 0);
     size_t cls = 256;
     while (cls < bytes) cls <<= 1;
     auto& fl = c.small_free[cls];
@@ -35,9 +74,11 @@ void* dalloc(Ctx& c, size_t bytes) {
     if (!fl.empty()) {
         p = fl.back();
         fl.pop_back();
+    } else if (cls > SMALL_MAX) {
+        p = raw_alloc(c, cls, c.lane);
     } else {
         if (c.slab_left < cls) {
-            c.slab_cur = static_cast<char*>(dalloc_big(c, SLAB_BYTES));
+            c.slab_cur = static_cast<char*>(raw_alloc(c, SLAB_BYTES, c.lane));
             c.slabs.push_back(c.slab_cur);
             c.slab_left = SLAB_BYTES;
         }
@@ -45,30 +86,7 @@ void* dalloc(Ctx& c, size_t bytes) {
         c.slab_cur += cls;
         c.slab_left -= cls;
     }
-    c.small_live[p] = cls;
-    return p;
-}
-
-static void* dalloc_big(Ctx& c, size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    if (c.budget && c.bytes_live + bytes > c.budget)
-        raise(SNNC_EBUDGET, "device-memory budget exceeded (" + std::to_string(c.bytes_live + bytes) + " > " +
-                                std::to_string(c.budget) + " bytes)");
-    void* p = nullptr;
-    if (c.has_alloc) {
-        p = c.alloc.alloc(bytes, (void*)c.stream, c.alloc.user);
-        if (!p) raise(SNNC_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
-    } else {
-        // stream-ordered: a buffer freed after enqueued work is reused only by later work
-        hipError_t e = hipMallocAsync(&p, bytes, c.stream);
-        if (e != hipSuccess || !p) {
-            (void)hipGetLastError();
-            raise(SNNC_ENOMEM, "hipMallocAsync failed for " + std::to_string(bytes) + " bytes");
-        }
-    }
-    c.live[p] = bytes;
-    c.bytes_live += bytes;
-    c.bytes_peak = std::max(c.bytes_peak, c.bytes_live);
+    c.small_live[p] = cls | (size_t)c.lane;
     return p;
 }
 
@@ -76,19 +94,79 @@ void dfree(Ctx& c, void* p) {
     if (!p) return;
     auto sm = c.small_live.find(p);
     if (sm != c.small_live.end()) {
-        c.small_free[sm->second].push_back(p);
+        const size_t cls = sm->second & ~(size_t)1;
+        const int lane = (int)(sm->second & 1);
         c.small_live.erase(sm);
+        if (lane == c.lane) c.small_free[cls].push_back(p);
+        else if (lane == 1) c.deferred.push_back(Ctx::Deferred{c.fence_seq, p, cls});
+        else c.parked.small_free[cls].push_back(p);     // the caller's stream orders its later use
         return;
     }
-    auto it = c.live.find(p);
-    if (it == c.live.end()) return;
-    c.bytes_live -= it->second;
-    c.live.erase(it);
-    if (c.has_alloc) {
-        c.alloc.free(p, c.alloc.user);
-    } else {
-        (void)hipFreeAsync(p, c.stream);
+    raw_free(c, p);
+}
+
+static void swap_lane(Ctx& c) {
+    LaneState& o = c.parked;
+    std::swap(c.stream, o.stream);
+    std::swap(c.stage, o.stage);
+    std::swap(c.stage_bytes, o.stage_bytes);
+    std::swap(c.stage_used, o.stage_used);
+    std::swap(c.stage_done, o.stage_done);
+    std::swap(c.lookback, o.lookback);
+    std::swap(c.lookback_bytes, o.lookback_bytes);
+    std::swap(c.sort_epoch, o.sort_epoch);
+    std::swap(c.slab_cur, o.slab_cur);
+    std::swap(c.slab_left, o.slab_left);
+    std::swap(c.small_free, o.small_free);
+    c.lane ^= 1;
+}
+
+CountScope::CountScope(Ctx& ctx) : c(ctx) {
+    if (c.lane != 0) raise(SNNC_ESTATE, "nested counting section");
+    if (!c.count_stream) {
+        HIPCHK(hipStreamCreateWithFlags(&c.count_stream, hipStreamNonBlocking));
+        c.parked.stream = c.count_stream;
+        HIPCHK(hipEventCreateWithFlags(&c.count_done, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c.parked.stage_done, hipEventDisableTiming));
+        c.parked.stage_bytes = 1u << 20;
+        HIPCHK(hipHostMalloc((void**)&c.parked.stage, c.parked.stage_bytes, hipHostMallocDefault));
     }
+    // fence the blocks freed since the last fence, then take back those whose
+    // fence the caller's stream has passed
+    if (!c.deferred.empty() && c.deferred.back().seq == c.fence_seq) {
+        hipEvent_t e = nullptr;
+        if (!c.fence_pool.empty()) {
+            e = c.fence_pool.back();
+            c.fence_pool.pop_back();
+        } else {
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(e, c.main_stream));
+        c.fences.emplace_back(c.fence_seq, e);
+        ++c.fence_seq;
+    }
+    bool any = false;
+    uint64_t done = 0;
+    while (!c.fences.empty()) {
+        const hipError_t q = hipEventQuery(c.fences.front().second);
+        if (q == hipErrorNotReady) break;
+        HIPCHK(q);
+        done = c.fences.front().first;
+        any = true;
+        c.fence_pool.push_back(c.fences.front().second);
+        c.fences.pop_front();
+    }
+    while (any && !c.deferred.empty() && c.deferred.front().seq <= done) {
+        c.parked.small_free[c.deferred.front().cls].push_back(c.deferred.front().p);
+        c.deferred.pop_front();
+    }
+    swap_lane(c);
+}
+
+CountScope::~CountScope() {
+    (void)hipEventRecord(c.count_done, c.stream);
+    swap_lane(c);
+    (void)hipStreamWaitEvent(c.stream, c.count_done, 0);
 }
 
 static hipEvent_t get_event(Ctx& c) {
@@ -125,7 +203,8 @@ void resolve_times(Ctx& c) {
     if (c.pending.empty()) return;
     for (size_t k : c.open_timers) HIPCHK(hipEventRecord(c.pending[k].b, c.stream));   // left open by an error
     c.open_timers.clear();
-    HIPCHK(hipStreamSynchronize(c.stream));
+    HIPCHK(hipStreamSynchronize(c.main_stream));
+    if (c.count_stream) HIPCHK(hipStreamSynchronize(c.count_stream));
     for (auto& p : c.pending) {
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
@@ -160,6 +239,14 @@ void upload(Ctx& c, void* dst, const void* src, size_t bytes) {
 
 void download(Ctx& c, void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
+    if (c.dl_pin && bytes <= c.dl_pin_bytes) {
+        // small read-backs (counts, histograms) land in pinned memory: a direct DMA
+        // instead of the runtime's staged copy into pageable memory
+        HIPCHK(hipMemcpyAsync(c.dl_pin, src, bytes, hipMemcpyDeviceToHost, c.stream));
+        HIPCHK(hipStreamSynchronize(c.stream));
+        memcpy(dst, c.dl_pin, bytes);
+        return;
+    }
     HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, c.stream));
     HIPCHK(hipStreamSynchronize(c.stream));
 }
@@ -366,9 +453,9 @@ void grow_gen(Ctx& c, uint64_t need) {
     c.cap_gen = cap;
 }
 
-// A validated call record with its device metadata (not yet admitted).
-static Call make_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
-                      const snnc_syn_spec* syn, int32_t alpha) {
+// A validated call record without its device metadata (not yet admitted).
+static Call make_call_host(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
+                           const snnc_syn_spec* syn, int32_t alpha) {
     if (c.prepared) raise(SNNC_ESTATE, "connect after prepare");
     if (!conn) raise(SNNC_EINVAL, "null argument");
     Call cl;
@@ -382,6 +469,13 @@ static Call make_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, 
     cl.S = make_set(c, src);
     cl.T = make_set(c, tgt);
     validate(c, cl, syn);
+    return cl;
+}
+
+// ... with its device metadata.
+static Call make_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
+                      const snnc_syn_spec* syn, int32_t alpha) {
+    Call cl = make_call_host(c, src, tgt, conn, syn, alpha);
     upload_meta(c, cl);
     return cl;
 }
@@ -395,12 +489,43 @@ static void admit(Ctx& c, Call& cl, uint64_t n) {
         raise(SNNC_EBUDGET, "request of " + std::to_string(n) + " connections exceeds the resident budget");
 }
 
+// Builds the call record and counts its local connections (served mode).  A
+// count that needs device work runs on the counting lane, so that the host
+// reads it back without waiting for generation already queued on the
+// caller's stream.
+static Call counted_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
+                         const snnc_syn_spec* syn, int32_t alpha, uint64_t* n_out) {
+    Call cl = make_call_host(c, src, tgt, conn, syn, alpha);
+    if (!count_on_device(c, cl)) {     // counted on the host: no second stream needed
+        upload_meta(c, cl);
+        try {
+            *n_out = gen_count_local(c, cl);
+        } catch (...) {
+            dfree(c, cl.meta);
+            throw;
+        }
+        return cl;
+    }
+    CountScope lane(c);
+    upload_meta(c, cl);
+    try {
+        *n_out = gen_count_local(c, cl);
+    } catch (...) {
+        dfree(c, cl.meta);
+        release_pre(c, cl);
+        throw;
+    }
+    return cl;
+}
+
 static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
                          const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
     if (!call_id_out) raise(SNNC_EINVAL, "null argument");
-    Call cl = make_call(c, src, tgt, conn, syn, alpha);
+    uint64_t n = 0;
+    Call cl = c.resident_budget ? counted_call(c, src, tgt, conn, syn, alpha, &n)
+                                : make_call(c, src, tgt, conn, syn, alpha);
     try {
-        if (c.resident_budget) admit(c, cl, gen_count_local(c, cl));
+        if (c.resident_budget) admit(c, cl, n);
         if (!c.conn_started) {
             HIPCHK(hipEventRecord(c.conn_first, c.stream));
             c.conn_started = true;
@@ -420,13 +545,12 @@ static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
     *call_id_out = c.calls.back().id;
 }
 
-// Served mode: count, admit and reserve now; generate at the next flush.
 static void submit_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
                         const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
     if (!call_id_out) raise(SNNC_EINVAL, "null argument");
-    Call cl = make_call(c, src, tgt, conn, syn, alpha);
+    uint64_t n = 0;
+    Call cl = counted_call(c, src, tgt, conn, syn, alpha, &n);
     try {
-        const uint64_t n = gen_count_local(c, cl);
         admit(c, cl, n);
         grow_gen(c, c.n_gen + n);
         if (!c.conn_started) {
@@ -504,6 +628,7 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
     c->seed = seed;
     c->dt = dt_ms;
     c->stream = (hipStream_t)hip_stream;
+    c->main_stream = c->stream;
     c->budget = budget_bytes;
     if (alloc) {
         c->alloc = *alloc;
@@ -519,6 +644,8 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
         HIPCHK(hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming));
         c->stage_bytes = 4u << 20;
         HIPCHK(hipHostMalloc((void**)&c->stage, c->stage_bytes, hipHostMallocDefault));
+        c->dl_pin_bytes = 64u << 10;
+        HIPCHK(hipHostMalloc((void**)&c->dl_pin, c->dl_pin_bytes, hipHostMallocDefault));
         c->d_status = dalloc_n<uint32_t>(*c, 1);
         HIPCHK(hipMemsetAsync(c->d_status, 0, 4, c->stream));
         sync(*c);
@@ -534,10 +661,13 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
 snnc_status snnc_destroy(snnc_ctx* c) {
     if (!c) return SNNC_OK;
     (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(c->main_stream);
+    if (c->count_stream) (void)hipStreamSynchronize(c->count_stream);
     std::vector<void*> ptrs;
     for (auto& kv : c->live) ptrs.push_back(kv.first);
-    for (void* p : ptrs) dfree(*c, p);
+    for (void* p : ptrs) raw_free(*c, p);
+    if (c->count_stream) (void)hipStreamSynchronize(c->count_stream);
+    (void)hipStreamSynchronize(c->main_stream);
     for (auto& p : c->pending) {
         (void)hipEventDestroy(p.a);
         (void)hipEventDestroy(p.b);
@@ -549,9 +679,16 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     if (c->conn_last) (void)hipEventDestroy(c->conn_last);
     if (c->stage_done) (void)hipEventDestroy(c->stage_done);
     if (c->stage) (void)hipHostFree(c->stage);
+    if (c->dl_pin) (void)hipHostFree(c->dl_pin);
     for (auto e : c->batch_done) (void)hipEventDestroy(e);
     if (c->fused_exec) (void)hipGraphExecDestroy(c->fused_exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+    for (auto& f : c->fences) (void)hipEventDestroy(f.second);
+    for (auto e : c->fence_pool) (void)hipEventDestroy(e);
+    if (c->count_done) (void)hipEventDestroy(c->count_done);
+    if (c->parked.stage_done) (void)hipEventDestroy(c->parked.stage_done);
+    if (c->parked.stage) (void)hipHostFree(c->parked.stage);
+    if (c->count_stream) (void)hipStreamDestroy(c->count_stream);
     delete c;
     return SNNC_OK;
 }

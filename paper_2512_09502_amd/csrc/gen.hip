@@ -441,12 +441,11 @@ uint64_t count_and_write(Ctx& c, const char* name, const Rule& rule, Provider pr
 }
 
 // ------------------------------------------------------------------ Floyd's sampling
-// One workgroup (one wave) per unit draws K distinct values in [0, n_eff):
-// lanes draw r_j = index(IDX(base + j), n_eff - K + j + 1) in parallel, lane
-// 0 runs Floyd's insertions sequentially with an LDS hash set, the wave
-// sorts the K chosen values (bitonic network in LDS) and emits them in
-// ascending order (j = rank).  In-degree: unit = target, all K kept.
-// Out-degree: unit = source, a value is kept when its target is on `host`.
+// One workgroup per unit draws K distinct values in [0, n_eff) with the
+// draws r_j = index(IDX(base + j), n_eff - K + j + 1) of Floyd's sampling and
+// emits them in ascending order (j = rank).  In-degree: unit = target, all K
+// kept.  Out-degree: unit = source, a value is kept when its target is on
+// `host`.
 struct FloydArgs {
     const TChunk* ch;
     uint32_t nch;
@@ -456,19 +455,34 @@ struct FloydArgs {
     const SegD* T;         // out-degree: target set
     uint32_t nT;
     uint32_t host;
-    uint32_t cap;          // hash capacity (power of two >= 2K)
     uint32_t kpad;         // power of two >= K
     uint32_t seed, call;
 };
 
+// Floyd's sampling without the sequential loop.  Step j draws r_j in
+// [0, m_j], m_j = n - K + j, and takes m_j instead exactly when r_j is already
+// chosen.  A low value (< n - K) is chosen at its first draw, so a repeat is
+// detected by an earlier occurrence (A_j).  A high value m_i (i < j) is chosen
+// at step i when step i took its fallback or drew m_i itself, else at its
+// first later draw; so dup_j = A_j or dup_i.  These links point to earlier
+// steps and are resolved by pointer jumping.  Then the chosen values are
+// sorted ascending -- the same set as inserting one by one.  K <= 8192, so a
+// step index fits 13 bits of the sort key.
+constexpr int FLNT = 256;
+
 template <class Sink, int MODE>
-__global__ __launch_bounds__(64) void k_floyd(FloydArgs a, Sink sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
-    extern __shared__ uint32_t lds[];
-    uint32_t* table = lds;               // cap entries
-    uint32_t* vals = lds + a.cap;        // kpad entries
-    const uint32_t lane = threadIdx.x;
+__global__ __launch_bounds__(FLNT) void k_floyd(FloydArgs a, Sink sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const uint32_t kp = a.kpad;
+    uint64_t* key = reinterpret_cast<uint64_t*>(lds_raw);          // (value << 13 | step), later the chosen values
+    uint32_t* rv = reinterpret_cast<uint32_t*>(key + kp);           // draw of step j
+    uint16_t* par0 = reinterpret_cast<uint16_t*>(rv + kp);
+    uint16_t* par1 = par0 + kp;
+    uint8_t* dup0 = reinterpret_cast<uint8_t*>(par1 + kp);
+    uint8_t* dup1 = dup0 + kp;
+    uint32_t* vals = reinterpret_cast<uint32_t*>(lds_raw);           // aliases key once it is no longer needed
+    const uint32_t tid = threadIdx.x;
     for (uint64_t u = blockIdx.x; u < a.n_units; u += gridDim.x) {
-        // unit -> chunk (units are laid out as chunk.out_begin / K)
         uint32_t lo = 0, hi = a.nch;
         const uint64_t g = u * a.K;
         while (hi - lo > 1) {
@@ -480,42 +494,70 @@ __global__ __launch_bounds__(64) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
         const uint64_t ord = c.t_ord + rel;
         const int64_t self = c.self_base >= 0 ? c.self_base + rel : -1;
         const uint32_t n_eff = a.n_set - (self >= 0 ? 1u : 0u);
+        const uint32_t base_m = n_eff - a.K;                    // m_j = base_m + j
         const uint64_t e0 = ord * a.K;
-        for (uint32_t i = lane; i < a.cap; i += 64) table[i] = 0xffffffffu;
-        for (uint32_t j = lane; j < a.kpad; j += 64) {
+        for (uint32_t j = tid; j < kp; j += FLNT) {
             if (j < a.K) {
                 const uint4 b = draw(a.seed, a.call, e0 + j, PURPOSE_IDX);
-                vals[j] = uniform_index(b.x, b.y, n_eff - a.K + j + 1);
+                const uint32_t r = uniform_index(b.x, b.y, base_m + j + 1);
+                rv[j] = r;
+                key[j] = ((uint64_t)r << 13) | j;
             } else {
-                vals[j] = 0xffffffffu;
+                key[j] = ~0ull;
             }
         }
         __syncthreads();
-        if (lane == 0) {
-            const uint32_t mask = a.cap - 1;
-            for (uint32_t j = 0; j < a.K; ++j) {
-                const uint32_t r = vals[j];
-                uint32_t h = (r * 2654435761u) & mask;
-                bool found = false;
-                while (table[h] != 0xffffffffu) {
-                    if (table[h] == r) { found = true; break; }
-                    h = (h + 1) & mask;
-                }
-                uint32_t x = r;
-                if (found) {
-                    x = n_eff - a.K + j;           // never chosen before step j
-                    h = (x * 2654435761u) & mask;
-                    while (table[h] != 0xffffffffu) h = (h + 1) & mask;
-                }
-                table[h] = x;
-                vals[j] = x;
-            }
-        }
-        __syncthreads();
-        // bitonic sort of vals[0..kpad)
-        for (uint32_t size = 2; size <= a.kpad; size <<= 1) {
+        for (uint32_t size = 2; size <= kp; size <<= 1) {      // bitonic sort of (value, step)
             for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t i = lane; i < a.kpad / 2; i += 64) {
+                for (uint32_t i = tid; i < kp / 2; i += FLNT) {
+                    const uint32_t lo_i = 2 * i - (i & (stride - 1));
+                    const uint32_t hi_i = lo_i + stride;
+                    const bool up = ((lo_i & size) == 0);
+                    const uint64_t x = key[lo_i], y = key[hi_i];
+                    if ((x > y) == up) {
+                        key[lo_i] = y;
+                        key[hi_i] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // A_j: an earlier step drew the same value (first occurrence by binary search)
+        for (uint32_t p = tid; p < a.K; p += FLNT) {
+            const uint64_t k = key[p];
+            const uint32_t j = (uint32_t)(k & 0x1fffu);
+            const uint64_t v0 = (k >> 13) << 13;
+            uint32_t l = 0, h = p;                              // first position with value == v
+            while (l < h) {
+                const uint32_t m = (l + h) >> 1;
+                if (key[m] < v0) l = m + 1; else h = m;
+            }
+            const uint32_t first = (uint32_t)(key[l] & 0x1fffu);
+            dup0[j] = first < j ? 1 : 0;
+            const uint32_t r = rv[j];
+            par0[j] = (uint16_t)(r >= base_m ? r - base_m : j);   // link to the step whose fallback is r
+        }
+        __syncthreads();
+        uint16_t* pa = par0;
+        uint16_t* pb = par1;
+        uint8_t* da = dup0;
+        uint8_t* db = dup1;
+        for (uint32_t span = 1; span < a.K; span <<= 1) {     // pointer jumping
+            for (uint32_t j = tid; j < a.K; j += FLNT) {
+                const uint32_t q = pa[j];
+                db[j] = da[j] | da[q];
+                pb[j] = pa[q];
+            }
+            __syncthreads();
+            uint16_t* tp = pa; pa = pb; pb = tp;
+            uint8_t* td = da; da = db; db = td;
+        }
+        for (uint32_t j = tid; j < kp; j += FLNT)
+            vals[j] = j < a.K ? (da[j] ? base_m + j : rv[j]) : 0xffffffffu;
+        __syncthreads();
+        for (uint32_t size = 2; size <= kp; size <<= 1) {      // bitonic sort of the chosen values
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                for (uint32_t i = tid; i < kp / 2; i += FLNT) {
                     const uint32_t lo_i = 2 * i - (i & (stride - 1));
                     const uint32_t hi_i = lo_i + stride;
                     const bool up = ((lo_i & size) == 0);
@@ -528,12 +570,13 @@ __global__ __launch_bounds__(64) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
                 __syncthreads();
             }
         }
-        // emit in ascending order
+        // emit in ascending order (j = rank)
+        __shared__ uint32_t wsum[FLNT / 64];
         uint64_t running = 0;
         if constexpr (MODE == WRITE) running = unit_offsets[u];
         uint32_t counted = 0;
-        for (uint32_t j0 = 0; j0 < a.K; j0 += 64) {
-            const uint32_t j = j0 + lane;
+        for (uint32_t j0 = 0; j0 < a.K; j0 += FLNT) {
+            const uint32_t j = j0 + tid;
             Res r{};
             bool ok = false;
             if (j < a.K) {
@@ -549,28 +592,29 @@ __global__ __launch_bounds__(64) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
                     ok = (h == a.host);
                 }
             }
-            const uint64_t ballot = __ballot(ok);
             if constexpr (MODE == DIRECT) {
                 if (ok) sink.put(c.out_begin + (uint64_t)rel * a.K + j, r);
             } else if constexpr (MODE == MARK) {
                 if (ok) sink.mark(r);
-            } else if constexpr (MODE == COUNT) {
-                counted += (uint32_t)__popcll(ballot);
             } else {
-                const uint32_t before = (uint32_t)__popcll(ballot & ((1ull << lane) - 1));
-                if (ok) sink.put(running + before, r);
-                running += (uint32_t)__popcll(ballot);
+                uint32_t tot;
+                const uint32_t before = block_excl_scan<FLNT>(ok ? 1u : 0u, wsum, &tot);
+                if constexpr (MODE == COUNT) counted += tot;
+                else {
+                    if (ok) sink.put(running + before, r);
+                    running += tot;
+                }
             }
         }
         if constexpr (MODE == COUNT) {
-            if (lane == 0) unit_counts[u] = counted;
+            if (tid == 0) unit_counts[u] = counted;
         }
         __syncthreads();
     }
 }
 
 // Small degrees (K <= FLOYD_SMALL): one lane per unit, the same draws and
-// insertions as k_floyd (membership by a scan of the K chosen values), the
+// Floyd's insertions one by one (membership by a scan of the K chosen values), the
 // chosen values sorted ascending and emitted with j = rank.  LDS slot j of
 // lane t is [j * FNT + t], so the lanes of a wave hit distinct banks.
 constexpr uint32_t FLOYD_SMALL = 32;
@@ -650,13 +694,14 @@ void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_c
         return;
     }
     const uint32_t grid = (uint32_t)std::min<uint64_t>(a.n_units, 65536);
-    const size_t shmem = (size_t)(a.cap + a.kpad) * 4;
-    if (shmem > 160 * 1024) raise(SNNC_EUNSUPPORTED, "degree too large for the LDS sampler");
+    if (a.kpad > 8192) raise(SNNC_EUNSUPPORTED, "degree above 8192 without multapses");
+    const size_t shmem = (size_t)a.kpad * (8 + 4 + 2 * 2 + 2 * 1);
     if (shmem > 64 * 1024)
         HIPCHK(hipFuncSetAttribute((const void*)k_floyd<Sink, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)shmem));
     tstart(c, "gen_floyd");
-    hipLaunchKernelGGL((k_floyd<Sink, MODE>), dim3(grid), dim3(64), shmem, c.stream, a, sink, unit_counts, unit_offsets);
+    hipLaunchKernelGGL((k_floyd<Sink, MODE>), dim3(grid), dim3(FLNT), shmem, c.stream, a, sink, unit_counts,
+                       unit_offsets);
     tstop(c);
     HIPCHK(hipGetLastError());
 }
@@ -825,7 +870,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, K, MAX_RUN_ELEMS);
             const uint64_t items = runs_elems(runs, K);
             result = items;
-            if (!items) break;
+            if (!items || mode == Out::COUNT) break;     // every target keeps its K draws
             DeviceChunks dc = upload_chunks(c, runs, items);
             temps.push_back(dc.d);
             if (cl.multapses) {
@@ -834,7 +879,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 else launch_gen<InDegree, WriteSink, DIRECT>(c, "gen_indegree", r, *reserve(items), items, nullptr, nullptr, 0);
             } else {
                 FloydArgs a{dc.d, dc.n, items / K, (uint32_t)K, (uint32_t)ns, 1, cl.dT, nT, host,
-                            next_pow2((uint32_t)(2 * K)), next_pow2((uint32_t)K), c.seed, cl.id};
+                            next_pow2((uint32_t)K), c.seed, cl.id};
                 if (mark) launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
                 else launch_floyd<WriteSink, DIRECT>(c, a, *reserve(items), nullptr, nullptr);
             }
@@ -848,11 +893,15 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             auto runs = unit_runs(cl.S, cl.autapses ? nullptr : &cl.T, unit_host, K, MAX_RUN_ELEMS);
             const uint64_t items = runs_elems(runs, K);
             if (!items) break;
-            DeviceChunks dc = upload_chunks(c, runs, items);
-            temps.push_back(dc.d);
             uint64_t on_host = 0;
             for (auto& g : cl.T.seg) if (g.host == host) on_host += g.n;
             const bool all_local = on_host == nt;
+            if (all_local && mode == Out::COUNT) {   // every draw is kept
+                result = items;
+                break;
+            }
+            DeviceChunks dc = upload_chunks(c, runs, items);
+            temps.push_back(dc.d);
             if (cl.multapses) {
                 OutDegree r{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt, cl.dT, nT, host,
                             c.seed, cl.id};
@@ -867,7 +916,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             } else {
                 const uint64_t units = items / K;
                 FloydArgs a{dc.d, dc.n, units, (uint32_t)K, (uint32_t)nt, 0, cl.dT, nT, host,
-                            next_pow2((uint32_t)(2 * K)), next_pow2((uint32_t)K), c.seed, cl.id};
+                            next_pow2((uint32_t)K), c.seed, cl.id};
                 if (mark) {
                     launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
                 } else if (all_local) {
@@ -1072,6 +1121,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 if (!mark) reserve(0);
                 break;
             }
+            if (mode == Out::COUNT) break;
             DeviceChunks dc = upload_chunks(c, kept, items);
             temps.push_back(dc.d);
             OneToOne r{dc.d, dc.n, 1u};   // autapse runs are gone
@@ -1231,6 +1281,21 @@ __global__ void k_philox_blocks(uint32_t seed, uint32_t call, uint64_t e0, uint3
 uint64_t gen_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, Out::APPEND, nullptr); }
 
 uint64_t gen_count_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, Out::COUNT, nullptr); }
+
+// Whether counting the call's local connections launches device work (the
+// counting branches of run_call): Bernoulli draws, total number unless every
+// candidate is kept, out-degree with targets on other hosts.
+bool count_on_device(const Ctx& c, const Call& cl) {
+    uint64_t on_host = 0;
+    for (auto& g : cl.T.seg) if (g.host == c.P_local) on_host += g.n;
+    const bool all_local = on_host == cl.T.total;
+    switch (cl.rule) {
+    case SNNC_PAIRWISE_BERNOULLI: return cl.S.total && cl.T.total;
+    case SNNC_FIXED_TOTAL_NUMBER: return cl.n && on_host && !(cl.autapses && cl.multapses && all_local);
+    case SNNC_FIXED_OUTDEGREE: return cl.n && cl.T.total && !all_local;
+    default: return false;
+    }
+}
 
 void release_pre(Ctx& c, Call& cl) {
     dfree(c, cl.pre_off);

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <string>
 #include <vector>
@@ -106,10 +107,26 @@ struct KernelTime {
     double ms = 0.0;
 };
 
+// Per-stream state that changes hands when admission counting runs on its own
+// stream: the stream, the pinned staging area, the radix-sort look-back table
+// and the free lists of the small-block pool.
+struct LaneState {
+    hipStream_t stream = nullptr;
+    char* stage = nullptr;
+    size_t stage_bytes = 0, stage_used = 0;
+    hipEvent_t stage_done = nullptr;
+    void* lookback = nullptr;
+    size_t lookback_bytes = 0;
+    uint32_t sort_epoch = 0;
+    char* slab_cur = nullptr;
+    size_t slab_left = 0;
+    std::map<size_t, std::vector<void*>> small_free;
+};
+
 struct Ctx {
     uint32_t P = 1, P_local = 0, seed = 0;
     double dt = 0.1;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;        // stream of the active lane (the caller's stream outside counting)
     int device = 0;
     snnc_allocator alloc{};
     bool has_alloc = false;
@@ -119,10 +136,10 @@ struct Ctx {
     // small blocks (metadata, tables, tile counts) carved from slabs, so that
     // requests do not call the outer allocator: free lists per power-of-two class
     std::vector<void*> slabs;
-    char* slab_cur = nullptr;
-    size_t slab_left = 0;
-    std::map<size_t, std::vector<void*>> small_free;
-    std::map<void*, size_t> small_live;
+    char* slab_cur = nullptr;                        // per lane
+    size_t slab_left = 0;                            // per lane
+    std::map<size_t, std::vector<void*>> small_free; // per lane
+    std::map<void*, size_t> small_live;              // class | lane of each block in use
     std::string last_error;
 
     std::vector<uint32_t> M;          // neurons per host
@@ -158,9 +175,9 @@ struct Ctx {
     // device status word for bounded waits (0 = fine)
     uint32_t* d_status = nullptr;
     // radix-sort look-back epoch (never reset, so status tables need no clearing)
-    uint32_t sort_epoch = 0;
-    void* lookback = nullptr;
-    size_t lookback_bytes = 0;
+    uint32_t sort_epoch = 0;             // per lane
+    void* lookback = nullptr;            // per lane
+    size_t lookback_bytes = 0;           // per lane
     int sort_variant = 0;                // tile shape of the radix passes (tunable)
     int sort_mode = 0;                   // 0: onesweep (look-back), 1: reduce-then-scan (tunable)
     bool sort_pinned = false;            // set by hand: the autotuner's process-wide choice is not used
@@ -172,9 +189,12 @@ struct Ctx {
     bool force_map_path = false;         // number images before the sort under the default policy
 
     // pinned staging for host-to-device uploads (no synchronisation per upload)
-    char* stage = nullptr;
+    char* stage = nullptr;               // per lane
     size_t stage_bytes = 0, stage_used = 0;
     hipEvent_t stage_done = nullptr;     // last copy out of the staging area
+    // pinned landing area of small device-to-host reads (each read waits for its copy)
+    char* dl_pin = nullptr;
+    size_t dl_pin_bytes = 0;
     // connect timing: first connect start, last connect end
     hipEvent_t conn_first = nullptr, conn_last = nullptr;
     bool conn_started = false;
@@ -193,6 +213,37 @@ struct Ctx {
     void* fused_hdr = nullptr;
     hipGraphExec_t fused_exec = nullptr;
     hipStream_t capture_stream = nullptr;
+
+    // admission counting lane: counts of served requests run on their own
+    // stream, so that reading a count back does not wait for queued
+    // generation.  The fields above marked per lane (stream, staging,
+    // look-back, small-block free lists) belong to the active lane; the
+    // other lane's are parked here.
+    int lane = 0;                        // 0: caller's stream, 1: counting stream
+    hipStream_t main_stream = nullptr, count_stream = nullptr;
+    LaneState parked;
+    hipEvent_t count_done = nullptr;     // end of the last counting section
+    // blocks of the counting lane freed while the caller's stream may still
+    // use them: reusable once the fence event recorded after that use completes
+    struct Deferred {
+        uint64_t seq;
+        void* p;
+        size_t cls;
+    };
+    std::deque<Deferred> deferred;
+    std::deque<std::pair<uint64_t, hipEvent_t>> fences;
+    std::vector<hipEvent_t> fence_pool;
+    uint64_t fence_seq = 0;
+};
+
+// Runs its scope on the counting lane: swaps the per-lane state, and on exit
+// makes the caller's stream wait for everything the scope enqueued.
+struct CountScope {
+    Ctx& c;
+    explicit CountScope(Ctx& ctx);
+    ~CountScope();
+    CountScope(const CountScope&) = delete;
+    CountScope& operator=(const CountScope&) = delete;
 };
 
 // allocation through the context (budget-checked); throws on failure
@@ -226,6 +277,7 @@ uint64_t gen_local(Ctx& c, Call& cl);
 void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits);
 // frees what the admission count kept with a call
 void release_pre(Ctx& c, Call& cl);
+bool count_on_device(const Ctx& c, const Call& cl);
 // exact number of connections the call has on P_local's share (may launch a
 // counting pass)
 uint64_t gen_count_local(Ctx& c, Call& cl);

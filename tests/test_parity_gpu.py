@@ -130,6 +130,18 @@ def test_rules_with_flags(conn):
     compare_all(s, 0)
 
 
+@pytest.mark.parametrize("rule,k,n_src,n_tgt,aut", [
+    ("fixed_indegree", 2990, 3000, 400, False),    # K close to the candidate count: long fallback chains
+    ("fixed_indegree", 8192, 9000, 300, False),    # largest degree of the workgroup sampler
+    ("fixed_indegree", 64, 64, 400, False),        # K = all candidates
+    ("fixed_outdegree", 8000, 200, 8300, False),
+    ("fixed_outdegree", 33, 500, 133, True),       # K = all targets
+])
+def test_large_degree_without_multapses(rule, k, n_src, n_tgt, aut):
+    conn = {"rule": rule, "n": k, "autapses": aut, "multapses": False}
+    compare_all(_one(conn, n_src=n_src, n_tgt=n_tgt), 0)
+
+
 @pytest.mark.parametrize("rule", ["fixed_outdegree", "pairwise_bernoulli", "fixed_indegree", "one_to_one"])
 def test_remote_rules_all_hosts(rule):
     # sources on host 1, targets spread over hosts 0..2: every host's share,

@@ -18,13 +18,15 @@ def _served_script(n=120, size_max=3e4, seed=7):
                              seed=seed)
 
 
-def _build(script, mode, budget, batch=17, fuse=True):
+def _build(script, mode, budget, batch=17, fuse=True, reserve=0):
     import torch
     torch.cuda.set_device(0)
     net = snnc.Network(1, 0, script["seed"], script["dt"])
     net.tune("fuse_batches", int(fuse))
     if budget:
         net.set_resident_budget(budget)
+    if reserve:
+        net.reserve(reserve)
     rejected, submitted = [], 0
     for k, op in enumerate(script["ops"]):
         if op[0] == "create":
@@ -72,6 +74,25 @@ def test_batched_equals_per_call_under_budget(fuse):
     ref = oracle.run_script(kept, 0)
     for k in GEN_ARRAYS + PREP_ARRAYS:
         compare(k, b[k], ref.array(k), "served")
+
+
+def test_counting_lane_with_large_requests():
+    """Admission counts run on their own stream while earlier batches generate;
+    requests up to 1e6 connections make the counting lane reuse its large
+    blocks (sort buffers of total number without multapses, tile counts)
+    while generation that reads their predecessors may still be queued.  The
+    build equals the one-stream build (per call, no budget), which the other
+    parity tests check against the oracle."""
+    script = W.served_requests(n_requests=150, n_pops=12, pop_min=2000, pop_max=50000, size_min=1e3, size_max=1e6,
+                               seed=11)
+    a, rej_a = _build(script, "per_call", 0)
+    b, rej_b = _build(script, "batched", 1 << 40, batch=7, reserve=30_000_000)
+    c, rej_c = _build(script, "per_call", 1 << 40)
+    log(f"counting lane: {a['src'].size} connections")
+    assert rej_a == rej_b == rej_c == []
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+        np.testing.assert_array_equal(a[k], c[k], err_msg=k)
 
 
 def test_served_poll_and_flush_order():
