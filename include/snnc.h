@@ -78,7 +78,9 @@ typedef enum {
     SNNC_FIXED_INDEGREE = 1,      /* n sources drawn for every target               */
     SNNC_FIXED_OUTDEGREE = 2,     /* n targets drawn for every source               */
     SNNC_FIXED_TOTAL_NUMBER = 3,  /* n connections drawn over all pairs             */
-    SNNC_PAIRWISE_BERNOULLI = 4   /* every pair connected with probability p        */
+    SNNC_PAIRWISE_BERNOULLI = 4,  /* every pair connected with probability p        */
+    SNNC_ASSIGNED_NODES = 5       /* explicit (source, target) pairs: only through
+                                     snnc_connect_assigned                          */
 } snnc_rule_kind;
 
 typedef struct {
@@ -169,7 +171,8 @@ snnc_status snnc_create(snnc_ctx* ctx, uint32_t host, uint32_t n, snnc_segment* 
  *                        ordinals, successes by geometric gaps from the
  *                        threshold table of snnc_bern_table; e = q = t_ord * n_s
  *                        + s_ord;
- *   one-to-one:          e = i.
+ *   one-to-one:          e = i;
+ *   assigned nodes:      see snnc_connect_assigned (snnc_connect rejects it).
  * Synapse values of element e come from block SYN(e) of the same call.
  * Errors: SNNC_EINVAL (bad segment, overlapping segments within a set, rule
  * parameters impossible for the sets, port != 0, delay below one step or
@@ -180,6 +183,27 @@ snnc_status snnc_create(snnc_ctx* ctx, uint32_t host, uint32_t n, snnc_segment* 
 snnc_status snnc_connect(snnc_ctx* ctx, const snnc_nodeset* src, const snnc_nodeset* tgt,
                          const snnc_conn_spec* conn, const snnc_syn_spec* syn, int32_t alpha,
                          uint32_t* call_id_out);
+
+/* Connect with the assigned-nodes rule (Methods, distributed fixed in-degree
+ * subsection: after the source draws of a target host are sorted by source
+ * host and position, each source host's part is connected with a rule that
+ * takes the source and target of every connection as given).  Pair i
+ * connects source position src_pos[i] of `src` to target position
+ * tgt_pos[i] of `tgt` (positions = ordinals in the concatenated segments);
+ * element index e = i, synapse values from block SYN(i).  The connection
+ * belongs to the share of the target's host, so every host passes the same
+ * pairs (as for every Connect).  src_pos, tgt_pos: host arrays of n uint32,
+ * read during the call and copied to the device (the library keeps the copy
+ * until snnc_destroy, since Prepare regenerates the point-to-point lists from
+ * it).  Autapse and multapse flags do not apply.  Under the threshold map
+ * policy the estimate is the number of pairs with a target on the host.
+ * Errors: SNNC_EINVAL (null arrays with n > 0, a position outside its set,
+ * bad segments or synapse spec as snnc_connect), SNNC_ESTATE after prepare,
+ * SNNC_ENOMEM / SNNC_EBUDGET, SNNC_EDEVICE.  Per call only: snnc_submit
+ * rejects SNNC_ASSIGNED_NODES (SNNC_EINVAL). */
+snnc_status snnc_connect_assigned(snnc_ctx* ctx, const snnc_nodeset* src, const snnc_nodeset* tgt,
+                                  const uint32_t* src_pos, const uint32_t* tgt_pos, uint64_t n,
+                                  const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out);
 
 /* Reserve room for n generated connections (optional; avoids regrowth). */
 snnc_status snnc_reserve(snnc_ctx* ctx, uint64_t n_connections);

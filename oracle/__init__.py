@@ -19,7 +19,7 @@ _SRC = os.path.join(_HERE, "snnc_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
 RULES = {"one_to_one": 0, "fixed_indegree": 1, "fixed_outdegree": 2,
-         "fixed_total_number": 3, "pairwise_bernoulli": 4}
+         "fixed_total_number": 3, "pairwise_bernoulli": 4, "assigned_nodes": 5}
 DISTS = {"const": 0, "normal": 1}
 
 # array ids and dtypes (same numbering as the C file's accessor enum)
@@ -77,6 +77,8 @@ def lib():
                      ctypes.c_int, dbl, dbl, ctypes.c_int, dbl, dbl, dbl, i32, vp]
         L.orc_connect.argtypes = conn_args
         L.orc_declare.argtypes = conn_args
+        L.orc_connect_assigned.argtypes = [vp, vp, u32, vp, u32, vp, vp, u64,
+                                           ctypes.c_int, dbl, dbl, ctypes.c_int, dbl, dbl, dbl, i32, vp]
         L.orc_prepare.argtypes = [vp]
         L.orc_set_map_policy.argtypes = [vp, ctypes.c_int, ctypes.c_int, dbl]
         L.orc_bern_table.argtypes = [dbl, vp]
@@ -282,7 +284,24 @@ class OracleNet:
         return int(cid[0])
 
     def connect(self, src, tgt, conn, syn, alpha=-1) -> int:
+        if conn["rule"] == "assigned_nodes":
+            return self._assigned(src, tgt, conn, syn, alpha)
         return self._conn(lib().orc_connect, src, tgt, conn, syn, alpha)
+
+    def _assigned(self, src, tgt, conn, syn, alpha):
+        """Assigned nodes: conn["pairs"] = (source positions, target positions)."""
+        s, t = _triples(src), _triples(tgt)
+        ps = np.ascontiguousarray(conn["pairs"][0], dtype=np.uint32)
+        pt = np.ascontiguousarray(conn["pairs"][1], dtype=np.uint32)
+        if ps.shape != pt.shape:
+            raise OracleError(-1, "pair arrays differ in length")
+        wk, wm, wsd, _ = _dist(syn.get("weight"))
+        dk, dm, dsd, dlo = _dist(syn.get("delay"))
+        cid = np.zeros(1, np.uint32)
+        st = lib().orc_connect_assigned(self._h, _ptr(s), s.shape[0], _ptr(t), t.shape[0], _ptr(ps), _ptr(pt),
+                                        ps.size, wk, wm, wsd, dk, dm, dsd, dlo, int(alpha), _ptr(cid))
+        self._check(st)
+        return int(cid[0])
 
     def declare(self, src, tgt, conn, syn, alpha=-1) -> int:
         return self._conn(lib().orc_declare, src, tgt, conn, syn, alpha)

@@ -41,7 +41,7 @@
 #define ORC_ESTATE (-4)
 #define ORC_EUNSUPPORTED (-5)
 
-enum { R_ONE_TO_ONE = 0, R_INDEGREE = 1, R_OUTDEGREE = 2, R_TOTAL = 3, R_BERNOULLI = 4 };
+enum { R_ONE_TO_ONE = 0, R_INDEGREE = 1, R_OUTDEGREE = 2, R_TOTAL = 3, R_BERNOULLI = 4, R_ASSIGNED = 5 };
 enum { D_CONST = 0, D_NORMAL = 1 };
 enum { PURPOSE_IDX = 0, PURPOSE_SYN = 1, PURPOSE_BERN = 2 };
 
@@ -200,6 +200,8 @@ typedef struct {
     uint32_t* dtab;
     uint32_t dtab_len;
     uint32_t d_klo;
+    uint32_t* pair_s;     /* assigned nodes: source and target ordinal of pair i (n pairs) */
+    uint32_t* pair_t;
     uint64_t gen_begin, gen_count;
 } orc_call;
 
@@ -295,6 +297,7 @@ void orc_free(orc_net* net)
     if (!net) return;
     for (uint32_t c = 0; c < net->ncalls; c++) {
         free(net->calls[c].S.seg); free(net->calls[c].T.seg); free(net->calls[c].dtab);
+        free(net->calls[c].pair_s); free(net->calls[c].pair_t);
     }
     free(net->calls); free(net->M);
     free(net->g_src); free(net->g_tgt); free(net->g_delay); free(net->g_weight); free(net->g_e);
@@ -572,6 +575,16 @@ static void gen_call(const orc_net* net, const orc_call* c, uint32_t host, uint6
         }
         break;
     }
+    case R_ASSIGNED: {
+        /* assigned nodes (distributed fixed in-degree subsection): pair i
+         * gives the source and target positions itself; the host of the
+         * target keeps it.  Element index i. */
+        for (uint64_t i = lo; i < hi && i < c->n; i++) {
+            set_at(&c->T, c->pair_t[i], &h2, &l2);
+            if (h2 == host) sink.emit(sink.ctx, c->pair_s[i], l2, i);
+        }
+        break;
+    }
     }
 }
 
@@ -653,6 +666,11 @@ static int validate_and_fill(orc_net* net, orc_call* c)
     case R_BERNOULLI:
         if (!(c->p >= 0.0 && c->p <= 1.0)) return fail(net, ORC_EINVAL, "probability outside [0,1]");
         break;
+    case R_ASSIGNED:
+        if (c->n > 0 && (!c->pair_s || !c->pair_t)) return fail(net, ORC_EINVAL, "assigned nodes without pairs");
+        for (uint64_t i = 0; i < c->n; i++)
+            if (c->pair_s[i] >= ns || c->pair_t[i] >= nt) return fail(net, ORC_EINVAL, "assigned pair outside the sets");
+        break;
     default:
         return fail(net, ORC_EINVAL, "unknown rule");
     }
@@ -680,6 +698,48 @@ static int validate_and_fill(orc_net* net, orc_call* c)
     return ORC_OK;
 }
 
+/* Validates a call record, appends it and generates P_local's share. */
+static int add_call(orc_net* net, orc_call* c, uint32_t* call_id_out)
+{
+    int st = validate_and_fill(net, c);
+    if (st != ORC_OK) {
+        free(c->S.seg); free(c->T.seg); free(c->dtab); free(c->pair_s); free(c->pair_t);
+        return st;
+    }
+    if (net->ncalls == net->capcalls) {
+        net->capcalls = net->capcalls ? 2 * net->capcalls : 16;
+        net->calls = (orc_call*)realloc(net->calls, net->capcalls * sizeof(orc_call));
+    }
+    net->calls[net->ncalls] = *c;
+    orc_call* cp = &net->calls[net->ncalls];
+    net->ncalls++;
+    cp->gen_begin = net->n_gen;
+    local_sink_ctx ctx = { net, cp };
+    sink_t sink = { emit_local, &ctx };
+    gen_call(net, cp, net->P_local, 0, UINT64_MAX, sink);
+    cp->gen_count = net->n_gen - cp->gen_begin;
+    *call_id_out = cp->id;
+    return ORC_OK;
+}
+
+static int init_call(orc_net* net, orc_call* c, const uint32_t* src_triples, uint32_t n_src_seg,
+                     const uint32_t* tgt_triples, uint32_t n_tgt_seg,
+                     int rule, uint64_t n, double p, int autapses, int multapses,
+                     int w_kind, double w_mean, double w_sd,
+                     int d_kind, double d_mean, double d_sd, double d_lo, int32_t alpha)
+{
+    memset(c, 0, sizeof *c);
+    c->id = net->ncalls;
+    c->rule = rule; c->n = n; c->p = p; c->autapses = autapses != 0; c->multapses = multapses != 0;
+    c->alpha = alpha;
+    c->w.kind = w_kind; c->w.mean = w_mean; c->w.sd = w_sd; c->w.lo = 0.0;
+    c->d.kind = d_kind; c->d.mean = d_mean; c->d.sd = d_sd; c->d.lo = d_lo;
+    int st = copy_set(net, src_triples, n_src_seg, &c->S);
+    if (st == ORC_OK) st = copy_set(net, tgt_triples, n_tgt_seg, &c->T);
+    if (st != ORC_OK) { free(c->S.seg); free(c->T.seg); }
+    return st;
+}
+
 /* Connect(src, tgt, rule, syn_spec) with group alpha (-1: point-to-point).
  * Sets are lists of (host, first, n) triples; the position of a neuron in a
  * set is its rank in the concatenation of the segments. */
@@ -691,31 +751,35 @@ int orc_connect(orc_net* net, const uint32_t* src_triples, uint32_t n_src_seg,
                 int32_t alpha, uint32_t* call_id_out)
 {
     if (net->prepared) return fail(net, ORC_ESTATE, "connect after prepare");
+    if (rule == R_ASSIGNED) return fail(net, ORC_EINVAL, "assigned nodes take their pairs (orc_connect_assigned)");
     orc_call c;
-    memset(&c, 0, sizeof c);
-    c.id = net->ncalls;
-    c.rule = rule; c.n = n; c.p = p; c.autapses = autapses != 0; c.multapses = multapses != 0;
-    c.alpha = alpha;
-    c.w.kind = w_kind; c.w.mean = w_mean; c.w.sd = w_sd; c.w.lo = 0.0;
-    c.d.kind = d_kind; c.d.mean = d_mean; c.d.sd = d_sd; c.d.lo = d_lo;
-    int st = copy_set(net, src_triples, n_src_seg, &c.S);
-    if (st == ORC_OK) st = copy_set(net, tgt_triples, n_tgt_seg, &c.T);
-    if (st == ORC_OK) st = validate_and_fill(net, &c);
-    if (st != ORC_OK) { free(c.S.seg); free(c.T.seg); free(c.dtab); return st; }
-    if (net->ncalls == net->capcalls) {
-        net->capcalls = net->capcalls ? 2 * net->capcalls : 16;
-        net->calls = (orc_call*)realloc(net->calls, net->capcalls * sizeof(orc_call));
+    int st = init_call(net, &c, src_triples, n_src_seg, tgt_triples, n_tgt_seg, rule, n, p, autapses, multapses,
+                       w_kind, w_mean, w_sd, d_kind, d_mean, d_sd, d_lo, alpha);
+    if (st != ORC_OK) return st;
+    return add_call(net, &c, call_id_out);
+}
+
+/* Connect with the assigned-nodes rule: n pairs (pair_s[i], pair_t[i]) of
+ * source and target positions in the two sets (copied). */
+int orc_connect_assigned(orc_net* net, const uint32_t* src_triples, uint32_t n_src_seg,
+                         const uint32_t* tgt_triples, uint32_t n_tgt_seg,
+                         const uint32_t* pair_s, const uint32_t* pair_t, uint64_t n,
+                         int w_kind, double w_mean, double w_sd,
+                         int d_kind, double d_mean, double d_sd, double d_lo,
+                         int32_t alpha, uint32_t* call_id_out)
+{
+    if (net->prepared) return fail(net, ORC_ESTATE, "connect after prepare");
+    orc_call c;
+    int st = init_call(net, &c, src_triples, n_src_seg, tgt_triples, n_tgt_seg, R_ASSIGNED, n, 0.0, 1, 1,
+                       w_kind, w_mean, w_sd, d_kind, d_mean, d_sd, d_lo, alpha);
+    if (st != ORC_OK) return st;
+    if (n > 0 && pair_s && pair_t) {
+        c.pair_s = (uint32_t*)malloc(n * sizeof(uint32_t));
+        c.pair_t = (uint32_t*)malloc(n * sizeof(uint32_t));
+        memcpy(c.pair_s, pair_s, n * sizeof(uint32_t));
+        memcpy(c.pair_t, pair_t, n * sizeof(uint32_t));
     }
-    net->calls[net->ncalls] = c;
-    orc_call* cp = &net->calls[net->ncalls];
-    net->ncalls++;
-    cp->gen_begin = net->n_gen;
-    local_sink_ctx ctx = { net, cp };
-    sink_t sink = { emit_local, &ctx };
-    gen_call(net, cp, net->P_local, 0, UINT64_MAX, sink);
-    cp->gen_count = net->n_gen - cp->gen_begin;
-    *call_id_out = cp->id;
-    return ORC_OK;
+    return add_call(net, &c, call_id_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -883,9 +947,10 @@ static uint64_t set_count_on(const orc_set* s, uint32_t host)
  * flag when the rule draws its source indices at random and the estimated
  * number of new connections on tau divided by the number of sources is below
  * xi.  Estimates (reading): fixed in-degree K N_t, fixed total number
- * N N_t / (all targets of the call), pairwise Bernoulli p N_s N_t, with N_t
- * the call's targets on tau and N_s all its sources; one-to-one and fixed
- * out-degree use every source and are never flagged. */
+ * N N_t / (all targets of the call), pairwise Bernoulli p N_s N_t, assigned
+ * nodes the number of its pairs with the target on tau, with N_t the call's
+ * targets on tau and N_s all its sources; one-to-one and fixed out-degree use
+ * every source and are never flagged. */
 static int flag_sources(const orc_net* net, const orc_call* c, uint32_t tau)
 {
     if (net->img_sources == 0) return 1;
@@ -897,6 +962,15 @@ static int flag_sources(const orc_net* net, const orc_call* c, uint32_t tau)
     case R_INDEGREE: est = (double)c->n * n_t; break;
     case R_TOTAL: est = (double)c->n * n_t / (double)c->T.total; break;
     case R_BERNOULLI: est = c->p * n_s * n_t; break;
+    case R_ASSIGNED: {     /* the pairs whose target is on tau */
+        uint32_t h, l;
+        est = 0.0;
+        for (uint64_t i = 0; i < c->n; i++) {
+            set_at(&c->T, c->pair_t[i], &h, &l);
+            if (h == tau) est += 1.0;
+        }
+        break;
+    }
     default: return 0;
     }
     return est / n_s < net->xi;
@@ -1457,6 +1531,13 @@ int orc_call_element(const orc_net* net, uint32_t call_id, uint64_t e, uint32_t*
         }
         break;
     }
+    case R_ASSIGNED: {
+        if (e >= c->n) return -1;
+        s = c->pair_s[e];
+        t = c->pair_t[e];
+        set_at(&c->T, t, &h2, &l2);
+        break;
+    }
     case R_ONE_TO_ONE: {
         if (e >= nt) return -1;
         s = t = e;
@@ -1496,6 +1577,7 @@ int orc_declare(orc_net* net, const uint32_t* src_triples, uint32_t n_src_seg,
                 int32_t alpha, uint32_t* call_id_out)
 {
     if (net->prepared) return fail(net, ORC_ESTATE, "declare after prepare");
+    if (rule == R_ASSIGNED) return fail(net, ORC_EINVAL, "assigned nodes cannot be declared");
     orc_call c;
     memset(&c, 0, sizeof c);
     c.id = net->ncalls;

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsnnc.so")
 
 RULES = {"one_to_one": 0, "fixed_indegree": 1, "fixed_outdegree": 2,
-         "fixed_total_number": 3, "pairwise_bernoulli": 4}
+         "fixed_total_number": 3, "pairwise_bernoulli": 4, "assigned_nodes": 5}
 DISTS = {"const": 0, "normal": 1}
 STATUS = {0: "SNNC_OK", -1: "SNNC_EINVAL", -2: "SNNC_ENOMEM", -3: "SNNC_EBUDGET",
           -4: "SNNC_ESTATE", -5: "SNNC_EUNSUPPORTED", -6: "SNNC_EDEVICE"}
@@ -83,7 +83,8 @@ EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_cr
            "snnc_reserve", "snnc_prepare", "snnc_get_array", "snnc_copy_array", "snnc_copy_range",
            "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks",
            "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_flush", "snnc_poll",
-           "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver", "snnc_bern_table"]
+           "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver", "snnc_bern_table",
+           "snnc_connect_assigned"]
 
 _lib = None
 
@@ -124,6 +125,8 @@ def lib():
         L.snnc_sort_pairs.argtypes = [vp, vp, vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int32)]
         L.snnc_set_resident_budget.argtypes = [vp, u64]
         L.snnc_submit.argtypes = L.snnc_connect.argtypes
+        L.snnc_connect_assigned.argtypes = [vp, ctypes.POINTER(NodeSet), ctypes.POINTER(NodeSet), vp, vp, u64,
+                                            ctypes.POINTER(SynSpec), i32, ctypes.POINTER(u32)]
         L.snnc_flush.argtypes = [vp]
         L.snnc_poll.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_int32)]
         L.snnc_autotune_sort.argtypes = [vp, u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -237,7 +240,25 @@ class Network:
         return int(cid.value)
 
     def connect(self, src, tgt, conn, syn, alpha: int = -1) -> int:
+        if conn["rule"] == "assigned_nodes":
+            return self.connect_assigned(src, tgt, conn["pairs"][0], conn["pairs"][1], syn, alpha)
         return self._connect_like(lib().snnc_connect, src, tgt, conn, syn, alpha)
+
+    def connect_assigned(self, src, tgt, src_pos, tgt_pos, syn, alpha: int = -1) -> int:
+        """Assigned nodes: pair i connects position src_pos[i] of src to
+        position tgt_pos[i] of tgt (host arrays, copied by the call)."""
+        s, s_keep = _nodeset(src)
+        t, t_keep = _nodeset(tgt)
+        sp = np.ascontiguousarray(src_pos, dtype=np.uint32)
+        tp = np.ascontiguousarray(tgt_pos, dtype=np.uint32)
+        if sp.shape != tp.shape or sp.ndim != 1:
+            raise SnncError(-1, "pair arrays differ in shape")
+        ss = SynSpec(_dist(syn.get("weight")), _dist(syn.get("delay")), int(syn.get("port", 0)), 0)
+        cid = ctypes.c_uint32()
+        self._check(lib().snnc_connect_assigned(self._h, ctypes.byref(s), ctypes.byref(t), sp.ctypes.data,
+                                                tp.ctypes.data, int(sp.size), ctypes.byref(ss), int(alpha),
+                                                ctypes.byref(cid)))
+        return int(cid.value)
 
     def submit(self, src, tgt, conn, syn, alpha: int = -1) -> int:
         """Served mode: admit and reserve now, generate at the next flush()."""

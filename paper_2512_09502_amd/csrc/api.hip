@@ -358,6 +358,29 @@ static void validate(const Ctx& c, Call& cl, const snnc_syn_spec* syn) {
         cl.btab.resize(64);
         build_bern_table(cl.p, cl.btab.data());
         break;
+    case SNNC_ASSIGNED_NODES: {
+        if (cl.n && (!cl.in_src_pos || !cl.in_tgt_pos))
+            raise(SNNC_EINVAL, "assigned nodes take their pairs through snnc_connect_assigned");
+        uint32_t smax = 0, tmax = 0;
+        for (uint64_t i = 0; i < cl.n; ++i) {
+            smax = std::max(smax, cl.in_src_pos[i]);
+            tmax = std::max(tmax, cl.in_tgt_pos[i]);
+        }
+        if (cl.n && (smax >= ns || tmax >= nt)) raise(SNNC_EINVAL, "assigned pair outside the node sets");
+        // pairs per target host (the threshold map policy's estimate)
+        bool one_host = true;
+        for (auto& g : cl.T.seg) one_host = one_host && g.host == cl.T.seg[0].host;
+        if (cl.n && one_host) {
+            cl.pairs_on[cl.T.seg[0].host] = cl.n;
+        } else {
+            for (uint64_t i = 0; i < cl.n; ++i) {
+                uint32_t h, l;
+                set_lookup_host(cl.T, cl.in_tgt_pos[i], h, l);
+                cl.pairs_on[h] += 1;
+            }
+        }
+        break;
+    }
     default:
         raise(SNNC_EINVAL, "unknown rule");
     }
@@ -420,6 +443,13 @@ static void upload_meta(Ctx& c, Call& cl) {
     upload(c, cl.meta, host.data(), bytes);
     cl.dS = static_cast<SegD*>(cl.meta);
     cl.dT = cl.dS + nS;
+    if (cl.rule == SNNC_ASSIGNED_NODES && cl.n) {
+        cl.pairs = dalloc_n<uint32_t>(c, 2 * cl.n);
+        upload(c, cl.pairs, cl.in_src_pos, cl.n * 4);
+        upload(c, cl.pairs + cl.n, cl.in_tgt_pos, cl.n * 4);
+        cl.meta_bytes += 8 * cl.n;
+    }
+    cl.in_src_pos = cl.in_tgt_pos = nullptr;
     cl.btab_dev = nB ? reinterpret_cast<uint64_t*>(cl.dT + nT) : nullptr;
     cl.dtab_dev = reinterpret_cast<uint32_t*>(reinterpret_cast<uint64_t*>(cl.dT + nT) + nB);
 }
@@ -454,11 +484,18 @@ void grow_gen(Ctx& c, uint64_t need) {
 }
 
 // A validated call record without its device metadata (not yet admitted).
+// Assigned nodes come only through snnc_connect_assigned, which passes the
+// pair arrays (`pairs` true, arrays may be null when n is 0).
 static Call make_call_host(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
-                           const snnc_syn_spec* syn, int32_t alpha) {
+                           const snnc_syn_spec* syn, int32_t alpha, bool pairs = false,
+                           const uint32_t* src_pos = nullptr, const uint32_t* tgt_pos = nullptr) {
     if (c.prepared) raise(SNNC_ESTATE, "connect after prepare");
     if (!conn) raise(SNNC_EINVAL, "null argument");
+    if ((conn->kind == SNNC_ASSIGNED_NODES) != pairs)
+        raise(SNNC_EINVAL, "assigned nodes take their pairs through snnc_connect_assigned");
     Call cl;
+    cl.in_src_pos = src_pos;
+    cl.in_tgt_pos = tgt_pos;
     cl.id = (uint32_t)c.calls.size();
     cl.rule = conn->kind;
     cl.n = conn->n;
@@ -474,8 +511,9 @@ static Call make_call_host(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* 
 
 // ... with its device metadata.
 static Call make_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
-                      const snnc_syn_spec* syn, int32_t alpha) {
-    Call cl = make_call_host(c, src, tgt, conn, syn, alpha);
+                      const snnc_syn_spec* syn, int32_t alpha, bool pairs = false,
+                      const uint32_t* src_pos = nullptr, const uint32_t* tgt_pos = nullptr) {
+    Call cl = make_call_host(c, src, tgt, conn, syn, alpha, pairs, src_pos, tgt_pos);
     upload_meta(c, cl);
     return cl;
 }
@@ -494,14 +532,16 @@ static void admit(Ctx& c, Call& cl, uint64_t n) {
 // reads it back without waiting for generation already queued on the
 // caller's stream.
 static Call counted_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
-                         const snnc_syn_spec* syn, int32_t alpha, uint64_t* n_out) {
-    Call cl = make_call_host(c, src, tgt, conn, syn, alpha);
+                         const snnc_syn_spec* syn, int32_t alpha, uint64_t* n_out, bool pairs = false,
+                         const uint32_t* src_pos = nullptr, const uint32_t* tgt_pos = nullptr) {
+    Call cl = make_call_host(c, src, tgt, conn, syn, alpha, pairs, src_pos, tgt_pos);
     if (!count_on_device(c, cl)) {     // counted on the host: no second stream needed
         upload_meta(c, cl);
         try {
             *n_out = gen_count_local(c, cl);
         } catch (...) {
             dfree(c, cl.meta);
+            dfree(c, cl.pairs);
             throw;
         }
         return cl;
@@ -512,6 +552,7 @@ static Call counted_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
         *n_out = gen_count_local(c, cl);
     } catch (...) {
         dfree(c, cl.meta);
+        dfree(c, cl.pairs);
         release_pre(c, cl);
         throw;
     }
@@ -519,11 +560,12 @@ static Call counted_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
 }
 
 static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
-                         const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
+                         const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out, bool pairs = false,
+                         const uint32_t* src_pos = nullptr, const uint32_t* tgt_pos = nullptr) {
     if (!call_id_out) raise(SNNC_EINVAL, "null argument");
     uint64_t n = 0;
-    Call cl = c.resident_budget ? counted_call(c, src, tgt, conn, syn, alpha, &n)
-                                : make_call(c, src, tgt, conn, syn, alpha);
+    Call cl = c.resident_budget ? counted_call(c, src, tgt, conn, syn, alpha, &n, pairs, src_pos, tgt_pos)
+                                : make_call(c, src, tgt, conn, syn, alpha, pairs, src_pos, tgt_pos);
     try {
         if (c.resident_budget) admit(c, cl, n);
         if (!c.conn_started) {
@@ -536,6 +578,7 @@ static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
         HIPCHK(hipGetLastError());
     } catch (...) {
         dfree(c, cl.meta);
+        dfree(c, cl.pairs);
         release_pre(c, cl);
         throw;
     }
@@ -561,6 +604,7 @@ static void submit_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt
         cl.gen_count = n;
     } catch (...) {
         dfree(c, cl.meta);
+        dfree(c, cl.pairs);
         release_pre(c, cl);
         throw;
     }
@@ -718,6 +762,20 @@ snnc_status snnc_connect(snnc_ctx* c, const snnc_nodeset* src, const snnc_nodese
                          uint32_t* call_id_out) {
     if (!c) return SNNC_EINVAL;
     return guarded(c, [&] { connect_impl(*c, src, tgt, conn, syn, alpha, call_id_out); });
+}
+
+snnc_status snnc_connect_assigned(snnc_ctx* c, const snnc_nodeset* src, const snnc_nodeset* tgt,
+                                  const uint32_t* src_pos, const uint32_t* tgt_pos, uint64_t n,
+                                  const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        snnc_conn_spec conn{};
+        conn.kind = SNNC_ASSIGNED_NODES;
+        conn.allow_autapses = 1;
+        conn.allow_multapses = 1;
+        conn.n = n;
+        connect_impl(*c, src, tgt, &conn, syn, alpha, call_id_out, true, src_pos, tgt_pos);
+    });
 }
 
 snnc_status snnc_set_resident_budget(snnc_ctx* c, uint64_t bytes) {

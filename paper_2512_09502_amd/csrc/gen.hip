@@ -164,6 +164,24 @@ struct Total {
     }
 };
 
+// Assigned nodes: pair i names its source and target positions; the
+// connection belongs to the share of the target's host.  Element index i.
+struct Assigned {
+    static constexpr int R = 1;
+    const uint32_t* src_pos;
+    const uint32_t* tgt_pos;
+    const SegD* T;
+    uint32_t nT;
+    uint32_t host;
+    __device__ __forceinline__ int eval(uint64_t i, Res* r) const {
+        uint32_t h, l;
+        set_lookup(T, nT, tgt_pos[i], h, l);
+        if (h != host) return 0;
+        r[0] = Res{src_pos[i], l, i};
+        return 1;
+    }
+};
+
 // Pairwise Bernoulli: the pairs of a target are taken in blocks of 64 source
 // ordinals; item = (target, block j), element eb = t_ord nb + j.  Inside a
 // block the successes follow from geometric gaps: step m reads word m % 4 of
@@ -1129,6 +1147,24 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             else launch_gen<OneToOne, WriteSink, DIRECT>(c, "gen_one_to_one", r, *reserve(items), items, nullptr, nullptr, 0);
             break;
         }
+        case SNNC_ASSIGNED_NODES: {
+            const uint64_t n = cl.n;
+            if (!n) break;
+            uint64_t on_host = 0;
+            for (auto& g : cl.T.seg) if (g.host == host) on_host += g.n;
+            if (!on_host && !mark) break;
+            Assigned r{cl.pairs, cl.pairs + n, cl.dT, nT, host};
+            if (mark) {
+                launch_gen<Assigned, MarkSink, MARK>(c, "gen_assigned", r, ms, n, nullptr, nullptr, 0);
+            } else if (on_host == nt) {      // every target here: every pair is kept
+                result = n;
+                if (mode == Out::COUNT) break;
+                launch_gen<Assigned, WriteSink, DIRECT>(c, "gen_assigned", r, *reserve(n), n, nullptr, nullptr, 0);
+            } else {
+                result = count_and_write<Assigned>(c, "gen_assigned", r, reserve, n, UINT64_MAX);
+            }
+            break;
+        }
         default:
             raise(SNNC_EINVAL, "unknown rule");
         }
@@ -1284,7 +1320,7 @@ uint64_t gen_count_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, O
 
 // Whether counting the call's local connections launches device work (the
 // counting branches of run_call): Bernoulli draws, total number unless every
-// candidate is kept, out-degree with targets on other hosts.
+// candidate is kept, out-degree and assigned pairs with targets on other hosts.
 bool count_on_device(const Ctx& c, const Call& cl) {
     uint64_t on_host = 0;
     for (auto& g : cl.T.seg) if (g.host == c.P_local) on_host += g.n;
@@ -1293,6 +1329,7 @@ bool count_on_device(const Ctx& c, const Call& cl) {
     case SNNC_PAIRWISE_BERNOULLI: return cl.S.total && cl.T.total;
     case SNNC_FIXED_TOTAL_NUMBER: return cl.n && on_host && !(cl.autapses && cl.multapses && all_local);
     case SNNC_FIXED_OUTDEGREE: return cl.n && cl.T.total && !all_local;
+    case SNNC_ASSIGNED_NODES: return cl.n && on_host && !all_local;
     default: return false;
     }
 }

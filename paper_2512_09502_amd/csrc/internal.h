@@ -94,6 +94,13 @@ struct Call {
     uint64_t* pre_koff = nullptr;
     uint8_t* pre_first = nullptr;
     uint64_t pre_count = 0, pre_window = 0;
+    // assigned nodes: the caller's pair arrays during the call, then the
+    // device copy (n source positions, then n target positions) and the
+    // number of pairs per target host
+    const uint32_t* in_src_pos = nullptr;
+    const uint32_t* in_tgt_pos = nullptr;
+    uint32_t* pairs = nullptr;
+    std::map<uint32_t, uint64_t> pairs_on;
 };
 
 // ------------------------------------------------------------------ context

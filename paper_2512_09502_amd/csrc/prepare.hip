@@ -648,8 +648,9 @@ uint64_t count_on(const HostSet& s, uint32_t host) {
 
 // Map policy: does call cl give images on host tau only to the sources its
 // connections there use (flagging)?  The threshold heuristic flags rules that
-// draw their sources at random when the estimated connections on tau per
-// source fall below xi; out-degree and one-to-one calls use every source.
+// draw their sources at random (and assigned pairs) when the estimated
+// connections on tau per source fall below xi; out-degree and one-to-one calls
+// use every source.
 bool flag_sources(const Ctx& c, const Call& cl, uint32_t tau) {
     if (c.img_sources == 0) return true;
     if (c.img_sources == 2) return false;
@@ -660,6 +661,11 @@ bool flag_sources(const Ctx& c, const Call& cl, uint32_t tau) {
         case SNNC_FIXED_INDEGREE: est = (double)cl.n * n_t; break;
         case SNNC_FIXED_TOTAL_NUMBER: est = (double)cl.n * n_t / (double)cl.T.total; break;
         case SNNC_PAIRWISE_BERNOULLI: est = cl.p * n_s * n_t; break;
+        case SNNC_ASSIGNED_NODES: {
+            auto it = cl.pairs_on.find(tau);
+            est = it == cl.pairs_on.end() ? 0.0 : (double)it->second;
+            break;
+        }
         default: return false;
     }
     return est / n_s < c.xi;

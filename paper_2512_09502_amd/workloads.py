@@ -287,6 +287,71 @@ def random_tiny(seed: int, P: int | None = None) -> dict:
     return b.script(f"random_tiny_{seed}")
 
 
+def distributed_indegree_assigned(P: int = 4, n_per_host: int = 500, K: int = 20, seed: int = 1006) -> dict:
+    """Fixed in-degree over populations distributed across hosts, built the
+    way of the paper's distributed fixed in-degree subsection: every target
+    host tau draws, for each of its targets, K sources uniformly from the
+    whole distributed source population (triplets (sigma~, s~, t)), sorts the
+    triplets by sigma~ and then s~, splits them by source host and connects
+    each part with the assigned-nodes rule (one call per (tau, sigma)).  The
+    structural draws come from numpy (seeded); the pairs are the calls'
+    inputs.  E populations on every host are the sources, all neurons the
+    targets; weights N(0.1, 0.01), delays N(1.5, 0.75) ms clipped at 0.1."""
+    rng = np.random.default_rng(seed)
+    b = _Builder(P, seed=1)
+    pops = [b.create(h, n_per_host) for h in range(P)]
+    delay = {"kind": "normal", "mean": 1.5, "sd": 0.75, "lo": 0.1}
+    n_src = P * n_per_host
+    for tau in range(P):
+        t = np.repeat(np.arange(n_per_host, dtype=np.int64), K)
+        g = rng.integers(0, n_src, size=t.size)            # global source index over the population
+        sig, s = g // n_per_host, g % n_per_host
+        order = np.lexsort((s, sig))                        # by sigma~, then s~ (stable)
+        sig, s, t = sig[order], s[order], t[order]
+        for sigma in range(P):
+            m = sig == sigma
+            if not m.any():
+                continue
+            conn = {"rule": "assigned_nodes", "pairs": (s[m].tolist(), t[m].tolist())}
+            b.connect([pops[sigma]], [pops[tau]], conn, {"weight": W_E, "delay": delay})
+    return b.script("distributed_indegree_assigned", K=K)
+
+
+def random_assigned(seed: int, P: int | None = None) -> dict:
+    """Random scripts with assigned-nodes calls (random pairs over random
+    multi-host segment sets, groups -1..1) mixed with fixed in-degree calls,
+    for property and parity tests."""
+    rng = np.random.default_rng(20_000 + seed)
+    if P is None:
+        P = int(rng.integers(1, 5))
+    b = _Builder(P, seed=int(rng.integers(0, 2**32)), dt=0.1)
+    pops = [b.create(int(rng.integers(0, P)), int(rng.integers(1, 60))) for _ in range(int(rng.integers(2, 6)))]
+
+    def pick_set():
+        k = int(rng.integers(1, min(3, len(pops)) + 1))
+        segs = []
+        for i in rng.choice(len(pops), size=k, replace=False):
+            h, f, n = pops[i]
+            a = int(rng.integers(0, n))
+            c = int(rng.integers(a + 1, n + 1))
+            segs.append((h, f + a, c - a))
+        return segs
+
+    delay = {"kind": "normal", "mean": 1.5, "sd": 0.5, "lo": 0.1}
+    for _ in range(int(rng.integers(1, 7))):
+        src, tgt = pick_set(), pick_set()
+        ns, nt = sum(x[2] for x in src), sum(x[2] for x in tgt)
+        alpha = int(rng.integers(-1, 2))
+        if rng.integers(0, 4) == 0:
+            b.connect(src, tgt, {"rule": "fixed_indegree", "n": int(rng.integers(1, 6))}, {"weight": W_I, "delay": delay},
+                      alpha)
+            continue
+        n = int(rng.integers(0, 300))
+        pairs = (rng.integers(0, ns, size=n).tolist(), rng.integers(0, nt, size=n).tolist())
+        b.connect(src, tgt, {"rule": "assigned_nodes", "pairs": pairs}, {"weight": W_E, "delay": delay}, alpha)
+    return b.script(f"random_assigned_{seed}")
+
+
 def _truncate(segs, m):
     out = []
     for h, f, n in segs:

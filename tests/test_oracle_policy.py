@@ -194,6 +194,13 @@ THRESHOLD_CASES = [
     ({"rule": "fixed_total_number", "n": 150}, [(1, 0, 10)], False),       # 1.5
     ({"rule": "fixed_outdegree", "n": 1}, [(1, 0, 10), (0, 0, 90)], False),   # uses all sources
     ({"rule": "one_to_one"}, [(1, 0, 10), (0, 0, 90)], False),                # uses all sources
+    # assigned nodes: the pairs with a target on host 1, per source
+    ({"rule": "assigned_nodes", "pairs": (list(range(50)), [i % 10 for i in range(50)])}, [(1, 0, 10)], True),
+    ({"rule": "assigned_nodes", "pairs": ([i % 90 for i in range(150)], [i % 10 for i in range(150)])},
+     [(1, 0, 10)], False),                                                      # 1.5
+    ({"rule": "assigned_nodes", "pairs": ([i % 60 for i in range(230)], [i % 10 if i < 30 else 10 + i % 90
+                                                                          for i in range(230)])},
+     [(1, 0, 10), (0, 0, 90)], True),                                           # 30 of 230 on host 1: 0.3
 ]
 
 

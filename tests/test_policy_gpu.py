@@ -60,6 +60,10 @@ THRESHOLD_CASES = [
     ({"rule": "fixed_total_number", "n": 150}, [(1, 0, 10)]),
     ({"rule": "fixed_outdegree", "n": 1}, [(1, 0, 10), (0, 0, 90)]),
     ({"rule": "one_to_one"}, [(1, 0, 10), (0, 0, 90)]),
+    ({"rule": "assigned_nodes", "pairs": (list(range(50)), [i % 10 for i in range(50)])}, [(1, 0, 10)]),
+    ({"rule": "assigned_nodes", "pairs": ([i % 60 for i in range(230)], [i % 10 if i < 30 else 10 + i % 90
+                                                                          for i in range(230)])},
+     [(1, 0, 10), (0, 0, 90)]),
 ]
 
 
