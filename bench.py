@@ -44,9 +44,21 @@ def expected_conns(script) -> int:
     return int(info.get("conns", info.get("conns_per_host", 0)))
 
 
+def _kept(net, name) -> bool:
+    """whether the prepared network holds this array (some exist at certain memory levels only)"""
+    import paper_2512_09502_amd as snnc
+    try:
+        net.count(name)
+        return True
+    except snnc.SnncError:
+        return False
+
+
 def build_once(script, P_local: int, timing: bool):
     import paper_2512_09502_amd as snnc
     net = snnc.Network(script["P"], P_local, script["seed"], script["dt"])
+    if script.get("memory_level") is not None:
+        net.set_memory_level(script["memory_level"])
     if script.get("map_policy") is not None:
         net.set_map_policy(*script["map_policy"])
     if script.get("sort_variant") is not None:
@@ -321,6 +333,8 @@ def main():
                     help="numbering,sources,xi: numbering 0 canonical / 1 call order; sources 0 used / "
                          "1 threshold / 2 all passed")
     ap.add_argument("--sort-variant", type=int, default=None, help="radix-pass tile shape (snnc_tune)")
+    ap.add_argument("--memory-level", type=int, default=None, choices=[0, 1, 2, 3],
+                    help="GPU memory level: maps and image rows in host (0, 1) or device memory (2, 3)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the sort autotuner in the first (untimed) warmup step")
     ap.add_argument("--pmc-calibrate", action="store_true",
@@ -335,6 +349,7 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    import numpy as np
     import paper_2512_09502_amd as snnc
     if args.workload == "served":
         return served(args)
@@ -346,6 +361,8 @@ def main():
     if args.map_policy:
         n_, s_, x_ = args.map_policy.split(",")
         script["map_policy"] = (int(n_), int(s_), float(x_))
+    if args.memory_level is not None:
+        script["memory_level"] = args.memory_level
 
     tuning = None
     for w in range(args.warmup):
@@ -366,22 +383,29 @@ def main():
 
     # timed steps (kernel timing by HIP events on the library stream)
     times, n_conn, kt_total, stats = [], 0, {}, None
+    untimed = 0.0          # reporting work inside the loop that is not part of a step
+    host_bytes = 0
     torch.cuda.synchronize()
     t_all = time.perf_counter()
-    for _ in range(args.steps):
+    for step in range(args.steps):
         t0 = time.perf_counter()
         net = build_once(script, 0, timing=True)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         n_conn = net.count("src")
         stats = net.stats()
+        if step == args.steps - 1:
+            tq = time.perf_counter()
+            host_bytes = sum(net.count(k) * np.dtype(snnc.ARRAYS[k][1]).itemsize for k in snnc.ARRAYS
+                             if not k.startswith("gen_") and k != "call_off" and _kept(net, k) and net.on_host(k))
+            untimed += time.perf_counter() - tq
         for k, (l, ms) in net.kernel_times().items():
             a = kt_total.setdefault(k, [0, 0.0])
             a[0] += l
             a[1] += ms
         net.close()
     torch.cuda.synchronize()
-    total = time.perf_counter() - t_all
+    total = time.perf_counter() - t_all - untimed
     if args.pmc_calibrate:   # outside the timed region: a copy of known size for the HBM counters
         x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
         torch.empty_like(x).copy_(x)
@@ -419,13 +443,15 @@ def main():
         "config": {"workload": script["name"], "connections": n_conn, "calls": stats["n_calls"],
                    "neurons": stats["M_local"], "images": stats["n_images"], "key_bits": stats["key_bits"],
                    "sort_passes": stats["sort_passes"], "scale": args.scale,
-                   "map_policy": script.get("map_policy")},
+                   "map_policy": script.get("map_policy"), "memory_level": script.get("memory_level")},
         "sort_tuning": tuning,
         "step_ms": {"min": round(1e3 * min(times), 3), "median": round(1e3 * sorted(times)[len(times) // 2], 3)},
         "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in sorted(kt_total.items(), key=lambda kv: -kv[1][1])},
         "dominant_kernel": dom[0],
         "roofline": roof,
         "peak_hbm_bytes": stats["bytes_peak"],
+        "hbm_bytes_after_prepare": stats["bytes_live"],
+        "host_bytes_after_prepare": host_bytes,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(script)

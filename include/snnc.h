@@ -279,7 +279,12 @@ typedef enum {
     SNNC_TGT = 11,         /* int32 target local id                            */
     SNNC_DELAY = 12,       /* uint16                                           */
     SNNC_WEIGHT = 13,      /* float                                            */
-    SNNC_ROW_PTR = 14,     /* uint64 [M_local + n_img + 1]                     */
+    SNNC_ROW_PTR = 14,     /* uint64 [M_local + n_img + 1]; [M_local + 1] at   */
+                           /* GPU memory levels 0 and 1 (image rows apart)     */
+    SNNC_IMG_FIRST = 15,   /* uint64 [n_img] first connection of each image    */
+                           /* row (levels 0 and 1, host memory)                */
+    SNNC_IMG_COUNT = 16,   /* uint32 [n_img] connections of each image row     */
+                           /* (levels 0 and 1 host memory, level 3 device)     */
     SNNC_R_OFF = 20,       /* uint64 [n_a * P + 1] offsets of R per (a, sigma) */
     SNNC_R_VAL = 21,       /* int32 remote source ids                          */
     SNNC_IMG_BASE = 22,    /* int64 [n_a * P] first image index per (a, sigma); */
@@ -299,9 +304,16 @@ typedef enum {
     SNNC_Q_VAL = 46        /* uint32 position in H_{group, P_local}            */
 } snnc_array_id;
 
-/* Device pointer and element count of an array (count 0 and ptr NULL for an
- * empty array).  SNNC_ESTATE if the array does not exist in this state. */
+/* Pointer and element count of an array (count 0 and ptr NULL for an empty
+ * array): device memory, except the arrays that GPU memory levels 0 and 1
+ * keep in pinned host memory (snnc_array_on_host).  SNNC_ESTATE if the array
+ * does not exist in this state. */
 snnc_status snnc_get_array(const snnc_ctx* ctx, int32_t id, const void** dev_ptr, uint64_t* count);
+
+/* *on_host = 1 when the array lives in pinned host memory (readable by
+ * kernels through the mapping), 0 for device memory.  SNNC_ESTATE as
+ * snnc_get_array. */
+snnc_status snnc_array_on_host(const snnc_ctx* ctx, int32_t id, int32_t* on_host);
 
 /* Copy an array to dst (host or device memory, hipMemcpyDefault), waiting
  * for completion.  SNNC_EINVAL if cap_bytes is too small. */
@@ -354,6 +366,21 @@ snnc_status snnc_kernel_times(snnc_ctx* ctx, uint32_t cap, char (*names)[48], ui
  * host, so S_{tau,sigma} stays equal to R_{tau,sigma}.  Default: CANONICAL,
  * USED, xi = 1.  Errors: SNNC_EINVAL for unknown values or xi < 0 / not
  * finite, SNNC_ESTATE after snnc_prepare. */
+/* GPU memory level 0 .. 3 (Methods, GPU memory levels subsection), set before
+ * snnc_prepare.  Levels 0 and 1 keep the maps of the remote sources to their
+ * images (R_OFF, R_VAL, IMG_BASE, L_VAL; H_OFF, H_VAL, I_VAL) and the first
+ * index and count of every image row (IMG_FIRST, IMG_COUNT) in pinned host
+ * memory; the device keeps ROW_PTR over the local rows only.  Level 2 keeps
+ * everything in device memory and a row's count is the difference of two
+ * ROW_PTR entries; level 3 adds IMG_COUNT in device memory.  Level 0 gives
+ * images to the used remote sources only, levels 1 to 3 to every source
+ * passed to a call with targets on this host: the level sets the map
+ * policy's image sources (SNNC_IMAGES_USED, SNNC_IMAGES_ALL), which a later
+ * snnc_set_map_policy overrides.  Without a level the placement is level 2's
+ * and the image sources are the map policy's.  Errors: SNNC_EINVAL outside
+ * 0 .. 3, SNNC_ESTATE after snnc_prepare. */
+snnc_status snnc_set_memory_level(snnc_ctx* ctx, int32_t level);
+
 typedef enum { SNNC_NUMBER_CANONICAL = 0, SNNC_NUMBER_CALL_ORDER = 1 } snnc_numbering;
 typedef enum { SNNC_IMAGES_USED = 0, SNNC_IMAGES_THRESHOLD = 1, SNNC_IMAGES_ALL = 2 } snnc_image_sources;
 snnc_status snnc_set_map_policy(snnc_ctx* ctx, int32_t numbering, int32_t image_sources, double xi);

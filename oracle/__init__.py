@@ -28,6 +28,7 @@ ARRAYS = {
     "gen_weight": (3, np.float32), "gen_e": (4, np.uint64), "call_off": (5, np.uint64),
     "src": (10, np.int32), "tgt": (11, np.int32), "delay": (12, np.uint16),
     "weight": (13, np.float32), "row_ptr": (14, np.uint64),
+    "img_first": (15, np.uint64), "img_count": (16, np.uint32),
     "r_off": (20, np.uint64), "r_val": (21, np.int32), "img_base": (22, np.int64),
     "l_val": (23, np.int32),
     "s_off": (30, np.uint64), "s_val": (31, np.int32), "tp_ptr": (32, np.uint64),
@@ -81,6 +82,7 @@ def lib():
                                            ctypes.c_int, dbl, dbl, ctypes.c_int, dbl, dbl, dbl, i32, vp]
         L.orc_prepare.argtypes = [vp]
         L.orc_set_map_policy.argtypes = [vp, ctypes.c_int, ctypes.c_int, dbl]
+        L.orc_set_memory_level.argtypes = [vp, ctypes.c_int]
         L.orc_bern_table.argtypes = [dbl, vp]
         L.orc_packets_from_lists.restype = ctypes.c_int64
         L.orc_packets_from_lists.argtypes = [vp, vp, vp, u32, u32, vp, vp, u64, vp, vp, vp, u64]
@@ -311,6 +313,11 @@ class OracleNet:
         1 threshold heuristic with xi, 2 all passed sources."""
         self._check(lib().orc_set_map_policy(self._h, int(numbering), int(sources), float(xi)))
 
+    def set_memory_level(self, level: int):
+        """GPU memory level 0..3: images of used (0) or all passed sources
+        (1..3), and which image-row arrays exist."""
+        self._check(lib().orc_set_memory_level(self._h, int(level)))
+
     def prepare(self):
         self._check(lib().orc_prepare(self._h))
 
@@ -389,6 +396,8 @@ def run_script(script, P_local: int, declare_only: bool = False, skip_invalid: b
     P_local.  With ``skip_invalid`` a rejected connect is recorded in
     ``net.rejected`` as (op index, status) and the replay goes on."""
     net = OracleNet(script["P"], P_local, script["seed"], script["dt"])
+    if script.get("memory_level") is not None:
+        net.set_memory_level(script["memory_level"])
     if script.get("map_policy") is not None:
         net.set_map_policy(*script["map_policy"])
     net.rejected = []

@@ -224,6 +224,12 @@ typedef struct orc_net {
      * sources get images (0 used, 1 threshold heuristic, 2 all passed) */
     int numbering, img_sources;
     double xi;
+    /* GPU memory level (Methods, GPU memory levels subsection), -1 when not
+     * set; decides which of the first-index and count arrays of the image
+     * rows exist (placement in host or device memory has no counterpart here) */
+    int mem_level;
+    uint64_t* img_first;
+    uint32_t* img_count;
     /* image map */
     uint32_t n_a;
     uint64_t* r_off;
@@ -271,6 +277,7 @@ orc_net* orc_new(uint32_t P, uint32_t P_local, uint32_t seed, double dt)
     net->P = P; net->P_local = P_local; net->seed = seed; net->dt = dt;
     net->M = (uint32_t*)calloc(P, sizeof(uint32_t));
     net->xi = 1.0;
+    net->mem_level = -1;
     return net;
 }
 
@@ -283,6 +290,20 @@ int orc_set_map_policy(orc_net* net, int numbering, int img_sources, double xi)
     return ORC_OK;
 }
 
+/* GPU memory level 0..3 (Methods, GPU memory levels subsection), before
+ * prepare: level 0 gives images to the used sources only, levels 1 to 3 to
+ * every source passed to a call (the image-source choice of the map policy,
+ * which a later orc_set_map_policy overrides); the level also decides which
+ * first-index and count arrays of the image rows exist. */
+int orc_set_memory_level(orc_net* net, int level)
+{
+    if (net->prepared) return fail(net, ORC_ESTATE, "memory level after prepare");
+    if (level < 0 || level > 3) return fail(net, ORC_EINVAL, "memory level out of range");
+    net->mem_level = level;
+    net->img_sources = level == 0 ? 0 : 2;
+    return ORC_OK;
+}
+
 static void free_prepared(orc_net* net)
 {
     free(net->r_off); free(net->r_val); free(net->l_val); free(net->img_base);
@@ -290,6 +311,7 @@ static void free_prepared(orc_net* net)
     free(net->S_off); free(net->S_val); free(net->TP_ptr); free(net->T_val); free(net->P_val);
     free(net->groups); free(net->H_off); free(net->H_val); free(net->I_val);
     free(net->GQ_ptr); free(net->G_val); free(net->Q_val);
+    free(net->img_first); free(net->img_count);
 }
 
 void orc_free(orc_net* net)
@@ -1198,6 +1220,20 @@ int orc_prepare(orc_net* net)
     for (uint64_t k = 0; k < (uint64_t)G * P; k++) free(H[k].v);
     free(H);
 
+    /* first index and count of the image rows, as the memory level keeps
+     * them: levels 0 and 1 both (in host memory in the library), level 3 the
+     * count beside the first-index array; level 2 derives the count from it */
+    const uint64_t n_img_rows = net->n_rows - M_local;
+    if (net->mem_level == 0 || net->mem_level == 1) {
+        net->img_first = (uint64_t*)malloc((n_img_rows ? n_img_rows : 1) * sizeof(uint64_t));
+        for (uint64_t i = 0; i < n_img_rows; i++) net->img_first[i] = net->row_ptr[M_local + i];
+    }
+    if (net->mem_level == 0 || net->mem_level == 1 || net->mem_level == 3) {
+        net->img_count = (uint32_t*)malloc((n_img_rows ? n_img_rows : 1) * sizeof(uint32_t));
+        for (uint64_t i = 0; i < n_img_rows; i++)
+            net->img_count[i] = (uint32_t)(net->row_ptr[M_local + i + 1] - net->row_ptr[M_local + i]);
+    }
+
     net->prepared = 1;
     return ORC_OK;
 }
@@ -1335,7 +1371,7 @@ int64_t orc_deliver(const orc_net* net, int kind, const uint32_t* grp, const uin
 /* ------------------------------------------------------------------------ */
 enum {
     A_GEN_SRC = 0, A_GEN_TGT = 1, A_GEN_DELAY = 2, A_GEN_WEIGHT = 3, A_GEN_E = 4, A_CALL_OFF = 5,
-    A_SRC = 10, A_TGT = 11, A_DELAY = 12, A_WEIGHT = 13, A_ROW_PTR = 14,
+    A_SRC = 10, A_TGT = 11, A_DELAY = 12, A_WEIGHT = 13, A_ROW_PTR = 14, A_IMG_FIRST = 15, A_IMG_COUNT = 16,
     A_R_OFF = 20, A_R_VAL = 21, A_IMG_BASE = 22, A_L_VAL = 23,
     A_S_OFF = 30, A_S_VAL = 31, A_TP_PTR = 32, A_T_VAL = 33, A_P_VAL = 34,
     A_GROUPS = 40, A_H_OFF = 41, A_H_VAL = 42, A_I_VAL = 43, A_GQ_PTR = 44, A_G_VAL = 45, A_Q_VAL = 46
@@ -1353,7 +1389,10 @@ int64_t orc_len(const orc_net* net, int which)
     switch (which) {
     case A_CALL_OFF: return net->ncalls + 1;
     case A_SRC: case A_TGT: case A_DELAY: case A_WEIGHT: return (int64_t)net->n_gen;
-    case A_ROW_PTR: return (int64_t)net->n_rows + 1;
+    case A_ROW_PTR:     /* levels 0 and 1 keep the image rows apart */
+        return (net->mem_level == 0 || net->mem_level == 1) ? (int64_t)net->M[PL] + 1 : (int64_t)net->n_rows + 1;
+    case A_IMG_FIRST: return net->img_first ? (int64_t)(net->n_rows - net->M[PL]) : -1;
+    case A_IMG_COUNT: return net->img_count ? (int64_t)(net->n_rows - net->M[PL]) : -1;
     case A_R_OFF: return (int64_t)net->n_a * net->P + 1;
     case A_R_VAL: case A_L_VAL: return (int64_t)net->n_img;
     case A_IMG_BASE: return (int64_t)net->n_a * net->P;
@@ -1382,6 +1421,8 @@ static const void* array_ptr(const orc_net* net, int which, size_t* elem)
     case A_DELAY: *elem = 2; return net->s_delay;
     case A_WEIGHT: *elem = 4; return net->s_weight;
     case A_ROW_PTR: *elem = 8; return net->row_ptr;
+    case A_IMG_FIRST: *elem = 8; return net->img_first;
+    case A_IMG_COUNT: *elem = 4; return net->img_count;
     case A_R_OFF: *elem = 8; return net->r_off;
     case A_R_VAL: *elem = 4; return net->r_val;
     case A_IMG_BASE: *elem = 8; return net->img_base;

@@ -30,6 +30,7 @@ ARRAYS = {
     "gen_weight": (3, np.float32), "call_off": (5, np.uint64),
     "src": (10, np.int32), "tgt": (11, np.int32), "delay": (12, np.uint16),
     "weight": (13, np.float32), "row_ptr": (14, np.uint64),
+    "img_first": (15, np.uint64), "img_count": (16, np.uint32),
     "r_off": (20, np.uint64), "r_val": (21, np.int32), "img_base": (22, np.int64),
     "l_val": (23, np.int32),
     "s_off": (30, np.uint64), "s_val": (31, np.int32), "tp_ptr": (32, np.uint64),
@@ -84,7 +85,7 @@ EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_cr
            "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks",
            "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_flush", "snnc_poll",
            "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver", "snnc_bern_table",
-           "snnc_connect_assigned"]
+           "snnc_connect_assigned", "snnc_set_memory_level", "snnc_array_on_host"]
 
 _lib = None
 
@@ -109,6 +110,8 @@ def lib():
         L.snnc_reserve.argtypes = [vp, u64]
         L.snnc_prepare.argtypes = [vp]
         L.snnc_set_map_policy.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
+        L.snnc_set_memory_level.argtypes = [vp, ctypes.c_int32]
+        L.snnc_array_on_host.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32)]
         L.snnc_bern_table.argtypes = [ctypes.c_double, vp]
         L.snnc_spike_packets.argtypes = [vp, ctypes.c_int32, vp, vp, u64, vp, vp, vp, u64, ctypes.POINTER(u64)]
         L.snnc_deliver.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp, vp, u64,
@@ -278,6 +281,17 @@ class Network:
     def reserve(self, n: int):
         self._check(lib().snnc_reserve(self._h, int(n)))
 
+    def set_memory_level(self, level: int):
+        """GPU memory level 0..3 (placement of the maps and image rows, and
+        images of used (0) or all passed sources (1..3))."""
+        self._check(lib().snnc_set_memory_level(self._h, int(level)))
+
+    def on_host(self, name: str) -> bool:
+        which, _ = ARRAYS[name]
+        flag = ctypes.c_int32()
+        self._check(lib().snnc_array_on_host(self._h, which, ctypes.byref(flag)))
+        return bool(flag.value)
+
     def set_map_policy(self, numbering: int, sources: int, xi: float = 1.0):
         """numbering: 0 canonical, 1 in call order; sources: 0 used, 1
         threshold heuristic with xi, 2 all passed sources."""
@@ -424,6 +438,8 @@ class Network:
 def run_script(script: dict, P_local: int, prepare: bool = True, skip_invalid: bool = False, **kw) -> Network:
     """Replay a workload script on the GPU for host P_local."""
     net = Network(script["P"], P_local, script["seed"], script["dt"], **kw)
+    if script.get("memory_level") is not None:
+        net.set_memory_level(script["memory_level"])
     if script.get("map_policy") is not None:
         net.set_map_policy(*script["map_policy"])
     net.rejected = []

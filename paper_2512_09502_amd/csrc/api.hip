@@ -629,7 +629,7 @@ void flush_pending(Ctx& c) {
 }
 
 static void free_results(Ctx& c) {
-    for (auto& kv : c.arrays) dfree(c, kv.second.p);
+    for (auto& kv : c.arrays) free_array(c, kv.second);
     c.arrays.clear();
     c.counts.clear();
 }
@@ -707,6 +707,9 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->main_stream);
     if (c->count_stream) (void)hipStreamSynchronize(c->count_stream);
+    for (auto& kv : c->arrays)
+        if (kv.second.host) (void)hipHostFree(kv.second.p);
+    c->arrays.clear();
     std::vector<void*> ptrs;
     for (auto& kv : c->live) ptrs.push_back(kv.first);
     for (void* p : ptrs) raw_free(*c, p);
@@ -911,7 +914,7 @@ static size_t elem_size(int32_t id) {
     switch (id) {
     case SNNC_GEN_DELAY: case SNNC_DELAY: return 2;
     case SNNC_CALL_OFF: case SNNC_ROW_PTR: case SNNC_R_OFF: case SNNC_IMG_BASE: case SNNC_S_OFF:
-    case SNNC_TP_PTR: case SNNC_H_OFF: case SNNC_GQ_PTR: return 8;
+    case SNNC_TP_PTR: case SNNC_H_OFF: case SNNC_GQ_PTR: case SNNC_IMG_FIRST: return 8;
     default: return 4;
     }
 }
@@ -995,6 +998,28 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
 snnc_status snnc_bern_table(double p, uint64_t* thr) {
     if (!thr || !(p >= 0.0 && p <= 1.0)) return SNNC_EINVAL;
     snnc::build_bern_table(p, thr);
+    return SNNC_OK;
+}
+
+snnc_status snnc_set_memory_level(snnc_ctx* c, int32_t level) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (c->prepared) raise(SNNC_ESTATE, "memory level after prepare");
+        if (level < 0 || level > 3) raise(SNNC_EINVAL, "memory level out of range");
+        c->mem_level = level;
+        c->img_sources = level == 0 ? SNNC_IMAGES_USED : SNNC_IMAGES_ALL;
+    });
+}
+
+snnc_status snnc_array_on_host(const snnc_ctx* cc, int32_t id, int32_t* on_host) {
+    snnc_ctx* c = const_cast<snnc_ctx*>(cc);
+    if (!c || !on_host) return SNNC_EINVAL;
+    const void* p = nullptr;
+    uint64_t n = 0;
+    snnc_status st = snnc_get_array(c, id, &p, &n);
+    if (st != SNNC_OK) return st;
+    auto it = c->arrays.find(id);
+    *on_host = (it != c->arrays.end() && it->second.host) ? 1 : 0;
     return SNNC_OK;
 }
 

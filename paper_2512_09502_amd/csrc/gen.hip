@@ -280,7 +280,7 @@ void launch_bern(Ctx& c, const BernGap& r, const Sink& sink, uint64_t n_items, u
     const uint64_t tiles = (n_items + TILE - 1) / TILE;
     for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
         const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
-        tstart(c, "gen_bernoulli");
+        tstart(c, MODE == MARK ? "prep_mark" : "gen_bernoulli");
         hipLaunchKernelGGL((k_bern<Sink, MODE>), dim3(nb), dim3(NT), 0, c.stream, r, sink, n_items, t0, tile_counts,
                            tile_offsets);
         tstop(c);
@@ -350,7 +350,7 @@ void launch_gen(Ctx& c, const char* name, const Rule& rule, const Sink& sink, ui
     const uint64_t tiles = (n_items + TILE - 1) / TILE;
     for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
         const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
-        tstart(c, name);
+        tstart(c, MODE == MARK ? "prep_mark" : name);   // regeneration for the send lists
         hipLaunchKernelGGL((k_gen<Rule, Sink, MODE>), dim3(nb), dim3(NT), 0, c.stream, rule, sink, n_items, t0,
                            tile_counts, tile_offsets, limit);
         tstop(c);
@@ -419,7 +419,7 @@ void launch_total_dist(Ctx& c, const Total& rule, uint32_t host, const Sink& sin
     const uint64_t tiles = (n_items + TILE - 1) / TILE;
     for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
         const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
-        tstart(c, "gen_total");
+        tstart(c, MODE == MARK_KEEP ? "prep_mark" : "gen_total");
         hipLaunchKernelGGL((k_total_dist<Sink, MODE, ALL_LOCAL>), dim3(nb), dim3(NT), 0, c.stream, rule, host, sink,
                            n_items, t0, tile_counts, valid_off, keep_off, limit);
         tstop(c);
@@ -704,7 +704,7 @@ void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_c
     if (!a.n_units) return;
     if (a.K <= FLOYD_SMALL) {
         const uint32_t grid = (uint32_t)std::min<uint64_t>((a.n_units + FNT - 1) / FNT, 65536);
-        tstart(c, "gen_floyd");
+        tstart(c, MODE == MARK ? "prep_mark" : "gen_floyd");
         hipLaunchKernelGGL((k_floyd_small<Sink, MODE>), dim3(grid), dim3(FNT), 0, c.stream, a, sink, unit_counts,
                            unit_offsets);
         tstop(c);
@@ -717,7 +717,7 @@ void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_c
     if (shmem > 64 * 1024)
         HIPCHK(hipFuncSetAttribute((const void*)k_floyd<Sink, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)shmem));
-    tstart(c, "gen_floyd");
+    tstart(c, MODE == MARK ? "prep_mark" : "gen_floyd");
     hipLaunchKernelGGL((k_floyd<Sink, MODE>), dim3(grid), dim3(FLNT), shmem, c.stream, a, sink, unit_counts,
                        unit_offsets);
     tstop(c);

@@ -107,6 +107,8 @@ struct Call {
 struct DevArray {
     void* p = nullptr;
     size_t bytes = 0;
+    bool host = false;       // pinned host memory (GPU memory levels 0 and 1)
+    void* dev = nullptr;     // its address for kernels when host
 };
 
 struct KernelTime {
@@ -194,6 +196,9 @@ struct Ctx {
     int numbering = 0, img_sources = 0;
     double xi = 1.0;
     bool force_map_path = false;         // number images before the sort under the default policy
+    // GPU memory level 0..3, -1 when not set (then: maps and first-index array
+    // in device memory, counts from the first-index array, as level 2)
+    int mem_level = -1;
 
     // pinned staging for host-to-device uploads (no synchronisation per upload)
     char* stage = nullptr;               // per lane
@@ -338,6 +343,7 @@ int sort_variant_count();
 
 // prepare pipeline (prepare.hip)
 void prepare_all(Ctx& c);
+void free_array(Ctx& c, DevArray& a);
 
 }  // namespace snnc
 

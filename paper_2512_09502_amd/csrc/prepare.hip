@@ -693,6 +693,75 @@ uint32_t bits_for(uint64_t n_values) {   // bits to hold 0 .. n_values - 1
 
 }  // namespace
 
+namespace {
+
+// first index and count of the image rows [M_local, M_local + n_img)
+__global__ void k_img_rows(const uint64_t* row_ptr, uint32_t M_local, uint64_t n_img, uint64_t* first,
+                           uint32_t* count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_img; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = row_ptr[(uint64_t)M_local + i], b = row_ptr[(uint64_t)M_local + i + 1];
+        if (first) first[i] = a;
+        if (count) count[i] = (uint32_t)(b - a);
+    }
+}
+
+// Moves a result array into pinned host memory that kernels can read.
+void to_host(Ctx& c, int32_t id) {
+    auto it = c.arrays.find(id);
+    if (it == c.arrays.end() || it->second.host) return;
+    DevArray& a = it->second;
+    void* h = nullptr;
+    HIPCHK(hipHostMalloc(&h, std::max<size_t>(a.bytes, 1), hipHostMallocMapped));
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(h);
+        raise(SNNC_EDEVICE, "pinned host memory without a device address");
+    }
+    if (a.bytes) HIPCHK(hipMemcpyAsync(h, a.p, a.bytes, hipMemcpyDeviceToHost, c.stream));
+    HIPCHK(hipStreamSynchronize(c.stream));
+    dfree(c, a.p);
+    a.p = h;
+    a.dev = d;
+    a.host = true;
+}
+
+// GPU memory levels (Methods, GPU memory levels subsection).  Levels 0 and 1:
+// the maps of the remote sources to their images (R, L, img_base and their
+// offsets; H and I of the collective layout) and the first index and count
+// of every image row live in pinned host memory, the device keeps the
+// first-index array of the local rows only.  Level 2: everything in device
+// memory, the count of a row from two first-index entries.  Level 3: level 2
+// plus the counts of the image rows as an array.  (Images of every passed
+// source from level 1 on: set with the level.)
+void place_memory_level(Ctx& c, uint32_t M_local) {
+    const int L = c.mem_level;
+    if (L != 0 && L != 1 && L != 3) return;
+    const uint64_t n_img = c.n_img;
+    const uint64_t* rp = static_cast<const uint64_t*>(c.arrays[SNNC_ROW_PTR].p);
+    uint64_t* first = (L <= 1) ? result<uint64_t>(c, SNNC_IMG_FIRST, n_img) : nullptr;
+    uint32_t* count = result<uint32_t>(c, SNNC_IMG_COUNT, n_img);
+    if (n_img) {
+        tstart(c, "prep_img_rows");
+        hipLaunchKernelGGL(k_img_rows, dim3(grid_for(n_img)), dim3(PNT), 0, c.stream, rp, M_local, n_img, first, count);
+        tstop(c);
+        HIPCHK(hipGetLastError());
+    }
+    if (L == 3) return;
+    // the device keeps the local rows of the first-index array
+    const uint64_t keep = (uint64_t)M_local + 1;
+    DevArray old = c.arrays[SNNC_ROW_PTR];
+    c.arrays[SNNC_ROW_PTR] = DevArray{};
+    uint64_t* nrp = result<uint64_t>(c, SNNC_ROW_PTR, keep);
+    HIPCHK(hipMemcpyAsync(nrp, old.p, keep * 8, hipMemcpyDeviceToDevice, c.stream));
+    free_array(c, old);
+    for (int32_t id : {SNNC_IMG_FIRST, SNNC_IMG_COUNT, SNNC_R_OFF, SNNC_R_VAL, SNNC_IMG_BASE, SNNC_L_VAL, SNNC_H_OFF,
+                       SNNC_H_VAL, SNNC_I_VAL})
+        to_host(c, id);
+}
+
+}  // namespace
+
 void prepare_all(Ctx& c) {
     const uint32_t P = c.P, PL = c.P_local;
     const uint64_t N = c.n_gen;
@@ -1128,11 +1197,18 @@ void prepare_all(Ctx& c) {
             result<uint32_t>(c, SNNC_Q_VAL, 0);
         }
         sync(c);
+        place_memory_level(c, M_local);
     } catch (...) {
         cleanup();
         throw;
     }
     cleanup();
+}
+
+void free_array(Ctx& c, DevArray& a) {
+    if (a.host) (void)hipHostFree(a.p);
+    else dfree(c, a.p);
+    a = DevArray{};
 }
 
 }  // namespace snnc

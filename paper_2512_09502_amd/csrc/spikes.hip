@@ -85,8 +85,9 @@ __global__ __launch_bounds__(SNT) void k_packet_bounds(const uint64_t* keys, uin
 __global__ __launch_bounds__(SNT) void k_deliver_lookup(const uint32_t* grp, const uint32_t* host, const uint32_t* pos,
                                                         uint64_t n, uint32_t P, uint32_t PL, uint32_t n_maps_grp,
                                                         int kind, const uint64_t* map_off, const int32_t* map_img,
-                                                        const uint64_t* row_ptr, int32_t* image, uint64_t* rb,
-                                                        uint64_t* re, uint64_t* cnt, uint32_t* err) {
+                                                        const uint64_t* row_ptr, const uint64_t* img_first,
+                                                        const uint32_t* img_count, uint32_t M_local, int32_t* image,
+                                                        uint64_t* rb, uint64_t* re, uint64_t* cnt, uint32_t* err) {
     for (uint64_t e = (uint64_t)blockIdx.x * SNT + threadIdx.x; e < n; e += (uint64_t)gridDim.x * SNT) {
         const uint32_t h = host[e];
         bool ok = h < P && (kind == 1 || h != PL);
@@ -103,7 +104,14 @@ __global__ __launch_bounds__(SNT) void k_deliver_lookup(const uint32_t* grp, con
             else ok = false;
         }
         if (!ok) atomicOr(err, 1u);
-        const uint64_t lo = img >= 0 ? row_ptr[img] : 0, hi = img >= 0 ? row_ptr[img + 1] : 0;
+        uint64_t lo = 0, hi = 0;
+        if (img >= 0 && img_first) {     // image rows kept apart (GPU memory levels 0 and 1)
+            lo = img_first[(uint32_t)img - M_local];
+            hi = lo + img_count[(uint32_t)img - M_local];
+        } else if (img >= 0) {
+            lo = row_ptr[img];
+            hi = row_ptr[img + 1];
+        }
         image[e] = img;
         rb[e] = lo;
         re[e] = hi;
@@ -130,11 +138,17 @@ __global__ __launch_bounds__(SNT) void k_deliver_events(const uint64_t* ev_off, 
     }
 }
 
+// address of a result array for kernels (host-resident arrays through their mapping)
 template <class T>
 const T* arr(Ctx& c, int32_t id) {
     auto it = c.arrays.find(id);
     if (it == c.arrays.end()) raise(SNNC_ESTATE, "array not available");
-    return static_cast<const T*>(it->second.p);
+    return static_cast<const T*>(it->second.host ? it->second.dev : it->second.p);
+}
+
+template <class T>
+const T* arr_or_null(Ctx& c, int32_t id) {
+    return c.arrays.count(id) ? arr<T>(c, id) : nullptr;
 }
 
 uint32_t bits_for_values(uint64_t n_values) {
@@ -239,8 +253,9 @@ uint64_t deliver(Ctx& c, int kind, const uint32_t* grp, const uint32_t* host, co
         if (n) {
             tstart(c, "deliver_lookup");
             hipLaunchKernelGGL(k_deliver_lookup, dim3(sgrid(n)), dim3(SNT), 0, c.stream, grp, host, pos, n, c.P,
-                               c.P_local, (uint32_t)c.counts[SNNC_GROUPS], kind, map_off, map_img, row_ptr, image, rb,
-                               re, cnt, err);
+                               c.P_local, (uint32_t)c.counts[SNNC_GROUPS], kind, map_off, map_img, row_ptr,
+                               arr_or_null<uint64_t>(c, SNNC_IMG_FIRST), arr_or_null<uint32_t>(c, SNNC_IMG_COUNT),
+                               c.M[c.P_local], image, rb, re, cnt, err);
             tstop(c);
             HIPCHK(hipGetLastError());
         }

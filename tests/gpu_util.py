@@ -10,6 +10,7 @@ import paper_2512_09502_amd as snnc
 GEN_ARRAYS = ["gen_src", "gen_tgt", "gen_delay", "gen_weight"]
 PREP_ARRAYS = ["src", "tgt", "delay", "weight", "row_ptr", "r_off", "r_val", "l_val", "img_base", "s_off", "s_val",
                "tp_ptr", "t_val", "p_val", "groups", "h_off", "h_val", "i_val", "gq_ptr", "g_val", "q_val"]
+LEVEL_ARRAYS = ["img_first", "img_count"]      # exist at some GPU memory levels only
 WEIGHT_ULP = 2
 
 
@@ -64,6 +65,14 @@ def compare_all(script, P_local, skip_invalid=True):
     compare("call_off", gen["call_off"], ref.array("call_off"), what)
     for k in PREP_ARRAYS:
         compare(k, net.array(k), ref.array(k), what)
+    for k in LEVEL_ARRAYS:
+        try:
+            want = ref.array(k)
+        except oracle.OracleError:
+            with np.testing.assert_raises(snnc.SnncError):
+                net.array(k)
+            continue
+        compare(k, net.array(k), want, what)
     n = net.count("src")
     net.close()
     return n
