@@ -142,6 +142,8 @@ def exchange(args):
     import torch
     import paper_2512_09502_amd as snnc
     script = workload("multiarea", args.scale)
+    if args.memory_level is not None:
+        script["memory_level"] = args.memory_level
     net = build_once(script, 0, timing=False)
     st = net.stats()
     M, n_img = st["M_local"], st["n_images"]
@@ -192,7 +194,8 @@ def exchange(args):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32 ids, f32 weights",
            "data": "synthetic",
            "config": {"workload": "multiarea_p2p spike exchange", "neurons": M, "images": n_img,
-                      "spikes_per_step": int(inputs[0][0].numel()), "entries_per_step": int(inputs[0][1].numel())},
+                      "spikes_per_step": int(inputs[0][0].numel()), "entries_per_step": int(inputs[0][1].numel()),
+                      "memory_level": script.get("memory_level")},
            "packets": {"entries_per_step": n_pk // args.steps, "ms_per_step": round(1e3 * t_pk / args.steps, 3),
                        "Mentries_s": round(n_pk / t_pk / 1e6, 2)},
            "delivery": {"events_per_step": n_ev // args.steps, "ms_per_step": round(1e3 * t_dl / args.steps, 3)},
