@@ -331,10 +331,24 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
 // digit histograms for all passes of a sort (radix 256, D bits per pass)
 // digit histograms: entries per pass (buckets of digits up to 9 bits)
 constexpr int HIST_STRIDE = 512;
+// Digits of radix pass p over bits [bit_lo, bit_hi): the first n9 passes take
+// 9 bits, the others dbits; the last pass ends at bit_hi.
+__host__ __device__ inline uint32_t pass_shift(uint32_t bit_lo, uint32_t n9, uint32_t dbits, uint32_t p) {
+    const uint32_t a = p < n9 ? p : n9;
+    return bit_lo + 9 * a + dbits * (p - a);
+}
+__host__ __device__ inline uint32_t pass_bits(uint32_t bit_lo, uint32_t bit_hi, uint32_t n9, uint32_t dbits,
+                                              uint32_t p) {
+    const uint32_t s = pass_shift(bit_lo, n9, dbits, p);
+    const uint32_t w = p < n9 ? 9u : dbits;
+    return bit_hi - s < w ? bit_hi - s : w;
+}
+
 struct SortPlan {
     int mode = 0, variant = 0;
     uint32_t passes = 0, dbits = 0;
-    bool wide = false;   // 9-bit digits
+    uint32_t n9 = 0;     // leading passes with 9-bit digits
+    bool wide = false;   // some pass has 9-bit digits
 };
 SortPlan plan_sort(const Ctx& c, uint64_t n, uint32_t bits);
 // 64 geometric-gap thresholds of a Bernoulli(p) sequence (pairwise Bernoulli rule)

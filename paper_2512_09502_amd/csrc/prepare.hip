@@ -139,12 +139,11 @@ __device__ __forceinline__ uint64_t rank_of(const uint32_t* bits, const uint64_t
 __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, const uint32_t* g_tgt,
                                               const uint16_t* g_delay, uint64_t n, const uint32_t* bits,
                                               const uint64_t* word_rank, const int32_t* Lmap, uint32_t M_local,
-                                              uint32_t tgt_shift,
+                                              uint32_t tgt_shift, uint32_t n9,
                                               uint32_t dbits, uint32_t passes, uint64_t* keys, uint64_t* hist) {
     __shared__ uint32_t h[8 * HIST_STRIDE];
     for (uint32_t i = threadIdx.x; i < passes * HIST_STRIDE; i += PNT) h[i] = 0;
     __syncthreads();
-    const uint32_t dmask = (1u << dbits) - 1;
     uint64_t lo, hi;
     block_range(n, lo, hi);
     // call of the current window (a workgroup's range crosses few calls)
@@ -206,8 +205,10 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
             const bool valid = base + (uint64_t)u * PNT + threadIdx.x < hi;
-            for (uint32_t p = 0; p < passes; ++p)
-                wave_hist_add(&h[p * HIST_STRIDE], (uint32_t)((key[u] >> (16 + p * dbits)) & dmask), valid);
+            for (uint32_t p = 0; p < passes; ++p)   // bits above the key's top are zero
+                wave_hist_add(&h[p * HIST_STRIDE],
+                              (uint32_t)((key[u] >> pass_shift(16, n9, dbits, p)) & ((p < n9 ? 0x1ffu : (1u << dbits) - 1))),
+                              valid);
         }
     }
     __syncthreads();
@@ -936,7 +937,7 @@ void prepare_all(Ctx& c) {
             tstart(c, "prep_keys");
             hipLaunchKernelGGL(k_keys, dim3(grid_for(N, 8192)), dim3(PNT), 0, c.stream, L, c.g_src, c.g_tgt, c.g_delay,
                                N, mapped ? bits : (const uint32_t*)nullptr, mapped ? word_rank : (const uint64_t*)nullptr,
-                               Lmap, M_local, 16 + tbits, dbits, passes, keys0, hist);
+                               Lmap, M_local, 16 + tbits, plan.n9, dbits, passes, keys0, hist);
             tstop(c);
             HIPCHK(hipGetLastError());
             // the source ordinals, targets and delays now live in the keys (released in stream order)

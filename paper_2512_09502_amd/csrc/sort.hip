@@ -37,14 +37,8 @@ namespace {
 
 constexpr int HNT = 256;
 
-// digit width of pass p: dbits, narrowed for the last pass to end at bit_hi
-__host__ __device__ __forceinline__ uint32_t pass_width(uint32_t bit_lo, uint32_t bit_hi, uint32_t dbits, uint32_t p) {
-    const uint32_t shift = bit_lo + p * dbits;
-    return bit_hi - shift < dbits ? bit_hi - shift : dbits;
-}
-
 __global__ __launch_bounds__(HNT) void k_hist(const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t bit_hi,
-                                              uint32_t dbits, uint32_t passes, uint64_t* hist) {
+                                              uint32_t n9, uint32_t dbits, uint32_t passes, uint64_t* hist) {
     __shared__ uint32_t h[8 * HSTRIDE];
     for (uint32_t i = threadIdx.x; i < passes * HSTRIDE; i += HNT) h[i] = 0;
     __syncthreads();
@@ -53,8 +47,8 @@ __global__ __launch_bounds__(HNT) void k_hist(const uint64_t* keys, uint64_t n, 
         const bool valid = i < n;
         const uint64_t k = valid ? keys[i] : 0;
         for (uint32_t p = 0; p < passes; ++p) {
-            const uint32_t mask = (1u << pass_width(bit_lo, bit_hi, dbits, p)) - 1;
-            wave_hist_add(&h[p * HSTRIDE], (uint32_t)((k >> (bit_lo + p * dbits)) & mask), valid);
+            const uint32_t mask = (1u << pass_bits(bit_lo, bit_hi, n9, dbits, p)) - 1;
+            wave_hist_add(&h[p * HSTRIDE], (uint32_t)((k >> pass_shift(bit_lo, n9, dbits, p)) & mask), valid);
         }
     }
     __syncthreads();
@@ -115,22 +109,35 @@ __global__ __launch_bounds__(NT) void k_onesweep(const uint64_t* __restrict__ ki
     uint32_t val[IPT];
     uint32_t rank[IPT];
     const uint64_t wbase = base + (uint64_t)wave * 64 * IPT + lane;
+    if (base + TILE <= n) {      // full tile: no per-element guards
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-        const uint64_t i = wbase + (uint64_t)k * 64;
-        key[k] = i < n ? kin[i] : 0ull;
-        val[k] = i < n ? vin[i] : 0u;
+        for (int k = 0; k < IPT; ++k) {
+            key[k] = kin[wbase + (uint64_t)k * 64];
+            val[k] = vin[wbase + (uint64_t)k * 64];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const uint64_t i = wbase + (uint64_t)k * 64;
+            key[k] = i < n ? kin[i] : 0ull;
+            val[k] = i < n ? vin[i] : 0u;
+        }
     }
     const uint64_t lt_mask = (1ull << lane) - 1;
+    constexpr int MAXBITS = RB == 512 ? 9 : 8;   // digits of a pass have at most this many bits
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
         const uint64_t i = wbase + (uint64_t)k * 64;
         const bool valid = i < n;
         const uint32_t d = valid ? (uint32_t)((key[k] >> shift) & mask) : 0u;
+        // lanes holding the same digit: one ballot per digit bit (bits above
+        // dbits are zero in every lane and leave the set unchanged)
         uint64_t peers = __ballot(valid);
-        for (uint32_t b = 0; b < dbits; ++b) {
-            const uint64_t bb = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bb : ~bb;
+#pragma unroll
+        for (int b = 0; b < MAXBITS; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
         }
         uint32_t r = 0;
         if (valid) {
@@ -369,7 +376,8 @@ struct Variant {
 // share each compute unit
 constexpr Variant VARIANTS[] = {{512, 16, true},  {256, 8, false},  {512, 8, false}, {512, 16, false},
                                 {256, 16, false}, {256, 12, false}, {1024, 8, false}, {1024, 8, true},
-                                {512, 8, true},   {512, 12, true},  {256, 16, true}};
+                                {512, 8, true},   {512, 12, true},  {256, 16, true},  {512, 11, true},
+                                {1024, 16, true}, {768, 12, true}};
 constexpr int N_VARIANTS = sizeof(VARIANTS) / sizeof(VARIANTS[0]);
 
 // autotuner results for the process: (pass algorithm, tile shape) per size
@@ -401,6 +409,9 @@ void launch_variant(Ctx& c, int v, const PassArgs& a, bool final, bool wide) {
         case 7: launch_pass<1024, 8, 512, true>(c, a, final); break;
         case 8: launch_pass<512, 8, 512, true>(c, a, final); break;
         case 9: launch_pass<512, 12, 512, true>(c, a, final); break;
+        case 11: launch_pass<512, 11, 512, true>(c, a, final); break;
+        case 12: launch_pass<1024, 16, 512, true>(c, a, final); break;
+        case 13: launch_pass<768, 12, 512, true>(c, a, final); break;
         default: raise(SNNC_EINVAL, "9-bit digits need a tile of at least 512 threads");
         }
         return;
@@ -416,6 +427,9 @@ void launch_variant(Ctx& c, int v, const PassArgs& a, bool final, bool wide) {
     case 8: launch_pass<512, 8, RADIX, true>(c, a, final); break;
     case 9: launch_pass<512, 12, RADIX, true>(c, a, final); break;
     case 10: launch_pass<256, 16, RADIX, true>(c, a, final); break;
+    case 11: launch_pass<512, 11, RADIX, true>(c, a, final); break;
+    case 12: launch_pass<1024, 16, RADIX, true>(c, a, final); break;
+    case 13: launch_pass<768, 12, RADIX, true>(c, a, final); break;
     default: launch_pass<512, 16, RADIX, true>(c, a, final); break;
     }
 }
@@ -442,18 +456,27 @@ SortPlan plan_sort(const Ctx& c, uint64_t n, uint32_t bits) {
     const bool can9 = VARIANTS[p.variant].nt >= 512;
     const bool use9 = can9 && (c.digit_bits == 9 || (c.digit_bits == 0 && p9 < p8));
     p.passes = use9 ? p9 : p8;
-    p.dbits = p.passes ? (bits + p.passes - 1) / p.passes : 0;
-    p.wide = p.dbits > 8;
+    if (use9 && c.digit_bits == 9) {          // forced: every pass 9 bits
+        p.n9 = p.passes;
+        p.dbits = 9;
+    } else if (use9) {                         // as few 9-bit passes as the pass count allows
+        p.n9 = bits - 8 * p.passes;           // (a 9-bit pass costs more than an 8-bit one)
+        p.dbits = 8;
+    } else {
+        p.n9 = 0;
+        p.dbits = p.passes ? (bits + p.passes - 1) / p.passes : 0;
+    }
+    p.wide = p.n9 > 0;
     return p;
 }
 
-void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t bit_hi, uint32_t dbits,
-                 uint32_t passes, uint64_t* hist) {
+void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t bit_hi, uint32_t n9,
+                 uint32_t dbits, uint32_t passes, uint64_t* hist) {
     HIPCHK(hipMemsetAsync(hist, 0, (size_t)passes * HSTRIDE * 8, c.stream));
     if (!n || !passes) return;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((n + HNT - 1) / HNT, 4096);
     tstart(c, "sort_hist");
-    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(HNT), 0, c.stream, keys, n, bit_lo, bit_hi, dbits, passes, hist);
+    hipLaunchKernelGGL(k_hist, dim3(grid), dim3(HNT), 0, c.stream, keys, n, bit_lo, bit_hi, n9, dbits, passes, hist);
     tstop(c);
     HIPCHK(hipGetLastError());
 }
@@ -480,7 +503,7 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
             if (!hist) {
                 hist = dalloc_n<uint64_t>(c, (uint64_t)passes * HSTRIDE);
                 temps.push_back(hist);
-                launch_hist(c, keys0, n, bit_lo, bit_hi, dbits, passes, hist);
+                launch_hist(c, keys0, n, bit_lo, bit_hi, plan.n9, dbits, passes, hist);
             }
             off = dalloc_n<uint64_t>(c, (uint64_t)passes * HSTRIDE);
             temps.push_back(off);
@@ -522,12 +545,12 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
                 c.sort_epoch = 1;
             }
             const bool last = (li + 1 == live.size()) && final_out;
-            PassArgs a{kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, bit_lo + p * dbits,
-                       pass_width(bit_lo, bit_hi, dbits, p),
+            const uint32_t width = pass_bits(bit_lo, bit_hi, plan.n9, dbits, p);
+            PassArgs a{kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, pass_shift(bit_lo, plan.n9, dbits, p), width,
                        off + (size_t)p * HSTRIDE, (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status,
                        final_out ? *final_out : FinalOut{}, mode};
             tstart(c, last ? "sort_pass_final" : "sort_pass");
-            launch_variant(c, variant, a, last, plan.wide);
+            launch_variant(c, variant, a, last, width > 8);
             tstop(c);
             HIPCHK(hipGetLastError());
             cur ^= 1;
