@@ -197,48 +197,78 @@ struct BernGap {
     const uint64_t* thr;   // 64 gap thresholds
     uint32_t autapses;
     uint32_t seed, call;
+    float inv_l2q;    // 1 / log2(1 - p): first guess of a gap (checked against the table)
 };
 
 __device__ __forceinline__ uint4 draw_sub(uint32_t seed, uint32_t call, uint64_t e, uint32_t purpose, uint32_t sub) {
     return philox10(make_uint4((uint32_t)e, (uint32_t)(e >> 32), purpose, sub), seed, call);
 }
 
-// visit the connections of item g in source order; thr is the LDS copy of the table
-template <class F>
-__device__ __forceinline__ void bern_visit(const BernGap& r, const uint64_t* thr, uint64_t g, F&& f) {
+// gap = #{k : thr[k] <= w} over the non-decreasing table (thr in LDS).  The
+// geometric law gives a first guess, log2(1 - w/2^32) / log2(1 - p); the
+// two walks over the table make the count exact whatever the guess.
+__device__ __forceinline__ uint32_t bern_gap(const uint64_t* thr, uint32_t w, float inv_l2q) {
+    const float l = __log2f((float)(0x100000000ull - (uint64_t)w)) - 32.0f;   // log2(1 - u) <= 0
+    const float est = l * inv_l2q;
+    uint32_t g = est >= 64.0f ? 64u : (est > 0.0f ? (uint32_t)est : 0u);
+    while (g < 64 && thr[g] <= (uint64_t)w) ++g;
+    while (g > 0 && thr[g - 1] > (uint64_t)w) --g;
+    return g;
+}
+
+// one item: target t_rel of its chunk, source block j
+struct BernItem {
+    uint64_t t_ord, eb;
+    int64_t self;
+    uint32_t s0, len, tgt;
+};
+
+__device__ __forceinline__ BernItem bern_item(const BernGap& r, uint64_t g) {
     const TChunk c = r.ch[find_chunk(r.ch, r.nch, g)];
     const uint32_t rel = (uint32_t)(g - c.out_begin);
     const uint32_t t_rel = fastdiv(rel, r.fnb);
     const uint32_t j = rel - t_rel * r.nb;
-    const uint64_t t_ord = c.t_ord + t_rel;
-    const uint64_t eb = t_ord * r.nb + j;
-    const uint32_t s0 = j * 64;
-    const uint32_t len = r.n_s - s0 < 64 ? r.n_s - s0 : 64;
-    const int64_t self = c.self_base >= 0 ? c.self_base + t_rel : -1;
-    const uint32_t tgt = c.local_first + t_rel;
+    BernItem it;
+    it.t_ord = c.t_ord + t_rel;
+    it.eb = it.t_ord * r.nb + j;
+    it.s0 = j * 64;
+    it.len = r.n_s - it.s0 < 64 ? r.n_s - it.s0 : 64;
+    it.self = c.self_base >= 0 ? c.self_base + t_rel : -1;
+    it.tgt = c.local_first + t_rel;
+    return it;
+}
+
+// the connected positions of an item's block, in source order: f(offset in the block)
+template <class F>
+__device__ __forceinline__ void bern_successes(const BernGap& r, const uint64_t* thr, const BernItem& it, F&& f) {
     uint32_t pos = 0;
     uint4 b = make_uint4(0, 0, 0, 0);
     for (uint32_t m = 0;; ++m) {
-        if ((m & 3u) == 0) b = draw_sub(r.seed, r.call, eb, PURPOSE_BERN, m >> 2);
+        if ((m & 3u) == 0) b = draw_sub(r.seed, r.call, it.eb, PURPOSE_BERN, m >> 2);
         const uint32_t w = (m & 3u) == 0 ? b.x : (m & 3u) == 1 ? b.y : (m & 3u) == 2 ? b.z : b.w;
-        uint32_t lo = 0, hi = 64;   // gap = #{k : thr[k] <= w} (thresholds non-decreasing)
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (thr[mid] <= (uint64_t)w) lo = mid + 1; else hi = mid;
-        }
-        if (pos + lo >= len) break;
-        const uint32_t s = s0 + pos + lo;
-        pos += lo + 1;
-        if (!r.autapses && (int64_t)s == self) continue;
-        f(Res{s, tgt, t_ord * r.n_s + s});
+        const uint32_t gap = bern_gap(thr, w, r.inv_l2q);
+        if (pos + gap >= it.len) break;
+        const uint32_t off = pos + gap;
+        pos = off + 1;
+        if (!r.autapses && (int64_t)(it.s0 + off) == it.self) continue;
+        f(off);
     }
 }
 
+__device__ __forceinline__ Res bern_res(const BernGap& r, const BernItem& it, uint32_t off) {
+    const uint32_t s = it.s0 + off;
+    return Res{s, it.tgt, it.t_ord * r.n_s + s};
+}
+
+// COUNT: connections per tile.  WRITE: each thread records the block offsets
+// of its connections in LDS (slot k of thread t at [k * NT + t]) in one visit,
+// a workgroup scan places them, then they are written in item order.
 template <class Sink, int MODE>
 __global__ __launch_bounds__(NT) void k_bern(BernGap r, Sink sink, uint64_t n_items, uint64_t tile0,
                                              uint32_t* tile_counts, const uint64_t* tile_offsets) {
     __shared__ uint64_t thr[64];
     __shared__ uint32_t scratch[NT / 64];
+    __shared__ uint8_t offs[MODE == WRITE ? 64 * NT : 1];
     if (threadIdx.x < 64) thr[threadIdx.x] = r.thr[threadIdx.x];
     __syncthreads();
     const uint64_t tile = tile0 + blockIdx.x;
@@ -247,23 +277,25 @@ __global__ __launch_bounds__(NT) void k_bern(BernGap r, Sink sink, uint64_t n_it
     if constexpr (MODE == WRITE) running = tile_offsets[tile];
     uint32_t counted = 0;
 #pragma unroll 1
-    for (int it = 0; it < IPT; ++it) {
-        const uint64_t item = base + (uint64_t)it * NT + threadIdx.x;
+    for (int k = 0; k < IPT; ++k) {
+        const uint64_t item = base + (uint64_t)k * NT + threadIdx.x;
+        const bool live = item < n_items;
+        BernItem it{};
+        if (live) it = bern_item(r, item);
         if constexpr (MODE == MARK) {
-            if (item < n_items) bern_visit(r, thr, item, [&](const Res& x) { sink.mark(x); });
+            if (live) bern_successes(r, thr, it, [&](uint32_t off) { sink.mark(bern_res(r, it, off)); });
             continue;
         }
         uint32_t n = 0;
-        if (item < n_items) bern_visit(r, thr, item, [&](const Res&) { ++n; });
         if constexpr (MODE == COUNT) {
+            if (live) bern_successes(r, thr, it, [&](uint32_t) { ++n; });
             counted += n;
         } else {
+            if (live) bern_successes(r, thr, it, [&](uint32_t off) { offs[n++ * NT + threadIdx.x] = (uint8_t)off; });
             uint32_t tot;
             const uint32_t pre = block_excl_scan<NT>(n, scratch, &tot);
-            if (n) {
-                uint64_t pos = running + pre;
-                bern_visit(r, thr, item, [&](const Res& x) { sink.put(pos++, x); });
-            }
+            for (uint32_t i = 0; i < n; ++i)   // each thread reads back only its own slots
+                sink.put(running + pre + i, bern_res(r, it, offs[i * NT + threadIdx.x]));
             running += tot;
         }
     }
@@ -1089,7 +1121,11 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             if (!items) break;
             DeviceChunks dc = upload_chunks(c, runs, items);
             temps.push_back(dc.d);
-            BernGap r{dc.d, dc.n, nb, make_fastdiv(nb), (uint32_t)ns, cl.btab_dev, cl.autapses ? 1u : 0u, c.seed, cl.id};
+            // first guess of a gap: 1 / log2(1 - p) (-inf when 1 - p rounds to 1, -0 for p = 1; the table decides)
+            const double l2q = std::log2(1.0 - cl.p);
+            const float inv_l2q = l2q < 0.0 ? (float)(1.0 / l2q) : -INFINITY;
+            BernGap r{dc.d, dc.n, nb, make_fastdiv(nb), (uint32_t)ns, cl.btab_dev, cl.autapses ? 1u : 0u, c.seed, cl.id,
+                      inv_l2q};
             if (mark) {
                 launch_bern<MarkSink, MARK>(c, r, ms, items, nullptr, nullptr);
                 break;
