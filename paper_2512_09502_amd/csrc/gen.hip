@@ -782,6 +782,60 @@ __global__ void k_first_flags(const uint64_t* keys, const uint32_t* vals, uint64
     first[vals[i]] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
 }
 
+// First occurrences by hashing (small candidate windows: fewer launches and no
+// read-back in the middle).  Open addressing over a power-of-two table of at
+// least 1.5 slots per candidate: each candidate claims the slot of its pair
+// (compare-and-swap) and lowers the slot's smallest candidate index; a second
+// pass finds the slot again and flags the candidate that holds the minimum.
+// The result does not depend on the order of the atomics.
+constexpr uint64_t HASH_EMPTY = ~0ull;
+constexpr uint64_t HASH_MAX_WINDOW = 1u << 20;
+
+__device__ __forceinline__ uint64_t pair_hash(uint64_t x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+__global__ void k_first_insert(const Total t, uint64_t n, uint32_t n_t, uint64_t* tab, uint32_t* minidx,
+                               uint64_t mask) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 b = draw(t.seed, t.call, i, PURPOSE_IDX);
+    const uint64_t key = (uint64_t)uniform_index(b.x, b.y, t.n_s) * n_t + uniform_index(b.z, b.w, t.n_t);
+    uint64_t h = pair_hash(key) & mask;
+    for (uint64_t probe = 0; probe <= mask; ++probe) {   // the table is never full
+        const uint64_t prev = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)HASH_EMPTY,
+                                        (unsigned long long)key);
+        if (prev == HASH_EMPTY || prev == key) {
+            atomicMin(&minidx[h], (uint32_t)i);
+            return;
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+__global__ void k_first_mark(const Total t, uint64_t n, uint32_t n_t, const uint64_t* tab, const uint32_t* minidx,
+                             uint64_t mask, uint8_t* first) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 b = draw(t.seed, t.call, i, PURPOSE_IDX);
+    const uint64_t key = (uint64_t)uniform_index(b.x, b.y, t.n_s) * n_t + uniform_index(b.z, b.w, t.n_t);
+    uint64_t h = pair_hash(key) & mask;
+    uint8_t f = 0;
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+        if (tab[h] == key) {
+            f = minidx[h] == (uint32_t)i ? 1 : 0;
+            break;
+        }
+        h = (h + 1) & mask;
+    }
+    first[i] = f;
+}
+
 struct DeviceChunks {
     TChunk* d = nullptr;
     uint32_t n = 0;
@@ -1032,7 +1086,27 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             }
             for (;;) {
                 uint8_t* first = nullptr;
-                if (!cl.multapses) {
+                if (!cl.multapses && C <= HASH_MAX_WINDOW) {
+                    uint64_t H = 1024;
+                    while (H < C + C / 2) H <<= 1;
+                    uint64_t* tab = dalloc_n<uint64_t>(c, H);
+                    uint32_t* minidx = dalloc_n<uint32_t>(c, H);
+                    first = dalloc_n<uint8_t>(c, C);
+                    temps.insert(temps.end(), {tab, minidx, first});
+                    HIPCHK(hipMemsetAsync(tab, 0xff, H * 8, c.stream));        // HASH_EMPTY
+                    HIPCHK(hipMemsetAsync(minidx, 0xff, H * 4, c.stream));     // no candidate yet
+                    tstart(c, "gen_total_first");
+                    hipLaunchKernelGGL(k_first_insert, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream, r, C,
+                                       (uint32_t)nt, tab, minidx, H - 1);
+                    hipLaunchKernelGGL(k_first_mark, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream, r, C,
+                                       (uint32_t)nt, (const uint64_t*)tab, (const uint32_t*)minidx, H - 1, first);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                    dfree(c, tab);
+                    dfree(c, minidx);
+                    temps.resize(temps.size() - 3);
+                    temps.push_back(first);
+                } else if (!cl.multapses) {
                     uint64_t* k0 = dalloc_n<uint64_t>(c, C);
                     uint64_t* k1 = dalloc_n<uint64_t>(c, C);
                     uint32_t* v0 = dalloc_n<uint32_t>(c, C);

@@ -116,6 +116,7 @@ def _one(rule_conn, n_src=3000, n_tgt=2500, P=1, src_host=0, tgt_host=0, alpha=-
     {"rule": "fixed_total_number", "n": 200000, "autapses": False, "multapses": True},
     {"rule": "fixed_total_number", "n": 150000, "autapses": True, "multapses": False},
     {"rule": "fixed_total_number", "n": 120000, "autapses": False, "multapses": False},
+    {"rule": "fixed_total_number", "n": 1100000, "autapses": True, "multapses": False},   # window above 2^20: sort path
     {"rule": "pairwise_bernoulli", "p": 0.013, "autapses": False},
     {"rule": "pairwise_bernoulli", "p": 1.0, "autapses": True},
     {"rule": "one_to_one", "autapses": False},
