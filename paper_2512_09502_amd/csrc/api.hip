@@ -108,10 +108,7 @@ void dfree(Ctx& c, void* p) {
 static void swap_lane(Ctx& c) {
     LaneState& o = c.parked;
     std::swap(c.stream, o.stream);
-    std::swap(c.stage, o.stage);
-    std::swap(c.stage_bytes, o.stage_bytes);
-    std::swap(c.stage_used, o.stage_used);
-    std::swap(c.stage_done, o.stage_done);
+    std::swap(c.ring, o.ring);
     std::swap(c.lookback, o.lookback);
     std::swap(c.lookback_bytes, o.lookback_bytes);
     std::swap(c.sort_epoch, o.sort_epoch);
@@ -127,9 +124,7 @@ CountScope::CountScope(Ctx& ctx) : c(ctx) {
         HIPCHK(hipStreamCreateWithFlags(&c.count_stream, hipStreamNonBlocking));
         c.parked.stream = c.count_stream;
         HIPCHK(hipEventCreateWithFlags(&c.count_done, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&c.parked.stage_done, hipEventDisableTiming));
-        c.parked.stage_bytes = 1u << 20;
-        HIPCHK(hipHostMalloc((void**)&c.parked.stage, c.parked.stage_bytes, hipHostMallocDefault));
+        init_ring(c.parked.ring, 4u << 20);
     }
     // fence the blocks freed since the last fence, then take back those whose
     // fence the caller's stream has passed
@@ -217,24 +212,46 @@ void resolve_times(Ctx& c) {
     c.pending.clear();
 }
 
+void init_ring(StageRing& r, size_t bytes) {
+    for (auto& e : r.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipHostMalloc((void**)&r.buf, bytes, hipHostMallocDefault));
+    r.bytes = bytes;
+}
+
+void free_ring(StageRing& r) {
+    for (auto& e : r.ev)
+        if (e) (void)hipEventDestroy(e);
+    if (r.buf) (void)hipHostFree(r.buf);
+    r = StageRing{};
+}
+
+// the writer moves into quarter nq: close the quarter it leaves, and wait
+// for the copies out of nq's previous contents
+static void enter_quarter(Ctx& c, StageRing& r, int nq) {
+    if (nq == r.q) return;
+    HIPCHK(hipEventRecord(r.ev[r.q], c.stream));
+    r.pending[r.q] = true;
+    if (r.pending[nq]) HIPCHK(hipEventSynchronize(r.ev[nq]));
+    r.pending[nq] = false;
+    r.q = nq;
+}
+
 void upload(Ctx& c, void* dst, const void* src, size_t bytes) {
     if (!bytes) return;
-    if (!c.stage || bytes > c.stage_bytes) {
+    StageRing& r = c.ring;
+    const size_t quarter = r.bytes / 4;
+    if (!r.buf || bytes > quarter) {
         HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c.stream));
         HIPCHK(hipStreamSynchronize(c.stream));
         return;
     }
-    const size_t at = (c.stage_used + 255) & ~(size_t)255;
-    if (at + bytes > c.stage_bytes) {
-        // every earlier copy out of the staging area must have run before reuse
-        HIPCHK(hipEventSynchronize(c.stage_done));
-        c.stage_used = 0;
-        return upload(c, dst, src, bytes);
-    }
-    memcpy(c.stage + at, src, bytes);
-    HIPCHK(hipMemcpyAsync(dst, c.stage + at, bytes, hipMemcpyHostToDevice, c.stream));
-    HIPCHK(hipEventRecord(c.stage_done, c.stream));
-    c.stage_used = at + bytes;
+    size_t at = (r.used + 255) & ~(size_t)255;
+    if (at + bytes > r.bytes) at = 0;                      // wrap
+    enter_quarter(c, r, (int)(at / quarter));
+    enter_quarter(c, r, (int)((at + bytes - 1) / quarter));   // a copy spans at most two quarters
+    memcpy(r.buf + at, src, bytes);
+    HIPCHK(hipMemcpyAsync(dst, r.buf + at, bytes, hipMemcpyHostToDevice, c.stream));
+    r.used = at + bytes;
 }
 
 void download(Ctx& c, void* dst, const void* src, size_t bytes) {
@@ -685,9 +702,7 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
         HIPCHK(hipEventCreate(&c->phase_b));
         HIPCHK(hipEventCreate(&c->conn_first));
         HIPCHK(hipEventCreate(&c->conn_last));
-        HIPCHK(hipEventCreateWithFlags(&c->stage_done, hipEventDisableTiming));
-        c->stage_bytes = 4u << 20;
-        HIPCHK(hipHostMalloc((void**)&c->stage, c->stage_bytes, hipHostMallocDefault));
+        init_ring(c->ring, 16u << 20);
         c->dl_pin_bytes = 64u << 10;
         HIPCHK(hipHostMalloc((void**)&c->dl_pin, c->dl_pin_bytes, hipHostMallocDefault));
         c->d_status = dalloc_n<uint32_t>(*c, 1);
@@ -724,8 +739,7 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     if (c->phase_b) (void)hipEventDestroy(c->phase_b);
     if (c->conn_first) (void)hipEventDestroy(c->conn_first);
     if (c->conn_last) (void)hipEventDestroy(c->conn_last);
-    if (c->stage_done) (void)hipEventDestroy(c->stage_done);
-    if (c->stage) (void)hipHostFree(c->stage);
+    free_ring(c->ring);
     if (c->dl_pin) (void)hipHostFree(c->dl_pin);
     for (auto e : c->batch_done) (void)hipEventDestroy(e);
     if (c->fused_exec) (void)hipGraphExecDestroy(c->fused_exec);
@@ -733,8 +747,7 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     for (auto& f : c->fences) (void)hipEventDestroy(f.second);
     for (auto e : c->fence_pool) (void)hipEventDestroy(e);
     if (c->count_done) (void)hipEventDestroy(c->count_done);
-    if (c->parked.stage_done) (void)hipEventDestroy(c->parked.stage_done);
-    if (c->parked.stage) (void)hipHostFree(c->parked.stage);
+    free_ring(c->parked.ring);
     if (c->count_stream) (void)hipStreamDestroy(c->count_stream);
     delete c;
     return SNNC_OK;

@@ -119,11 +119,20 @@ struct KernelTime {
 // Per-stream state that changes hands when admission counting runs on its own
 // stream: the stream, the pinned staging area, the radix-sort look-back table
 // and the free lists of the small-block pool.
+// Pinned staging ring for host-to-device uploads, in four quarters: an event
+// recorded when the writer leaves a quarter covers every copy out of it, and
+// the writer waits for that event only when it comes back to the quarter.
+struct StageRing {
+    char* buf = nullptr;
+    size_t bytes = 0, used = 0;
+    int q = 0;                           // quarter being filled
+    hipEvent_t ev[4] = {};
+    bool pending[4] = {};
+};
+
 struct LaneState {
     hipStream_t stream = nullptr;
-    char* stage = nullptr;
-    size_t stage_bytes = 0, stage_used = 0;
-    hipEvent_t stage_done = nullptr;
+    StageRing ring;
     void* lookback = nullptr;
     size_t lookback_bytes = 0;
     uint32_t sort_epoch = 0;
@@ -201,9 +210,7 @@ struct Ctx {
     int mem_level = -1;
 
     // pinned staging for host-to-device uploads (no synchronisation per upload)
-    char* stage = nullptr;               // per lane
-    size_t stage_bytes = 0, stage_used = 0;
-    hipEvent_t stage_done = nullptr;     // last copy out of the staging area
+    StageRing ring;                      // per lane
     // pinned landing area of small device-to-host reads (each read waits for its copy)
     char* dl_pin = nullptr;
     size_t dl_pin_bytes = 0;
@@ -357,6 +364,8 @@ int sort_variant_count();
 
 // prepare pipeline (prepare.hip)
 void prepare_all(Ctx& c);
+void init_ring(StageRing& r, size_t bytes);
+void free_ring(StageRing& r);
 void free_array(Ctx& c, DevArray& a);
 
 }  // namespace snnc
