@@ -59,7 +59,11 @@ struct MarkSink {
     __device__ __forceinline__ void mark(const Res& r) const {
         uint32_t h, l;
         set_lookup(S, nS, r.src, h, l);
-        if (h == host) atomicOr(bits + (l >> 5), 1u << (l & 31));
+        if (h != host) return;
+        // most draws hit sources already marked: a plain read skips their atomics
+        // (a stale read only costs a redundant atomic)
+        const uint32_t m = 1u << (l & 31);
+        if (!(bits[l >> 5] & m)) atomicOr(bits + (l >> 5), m);
     }
     __device__ __forceinline__ void put(uint64_t, const Res& r) const { mark(r); }
 };
