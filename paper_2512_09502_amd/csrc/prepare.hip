@@ -224,7 +224,7 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
 // these flags (decoupled look-back across tiles) gives each connection its
 // image index.  The same pass unpacks the connection arrays, records each
 // image's prefix and writes the first-index array.
-constexpr int XNT = 256;
+constexpr int XNT = 1024;
 constexpr int XIPT = 12;
 constexpr uint64_t XTILE = XNT * XIPT;
 constexpr uint64_t XFLAG_AGG = 1ull << 62, XFLAG_INC = 2ull << 62, XVALUE = (1ull << 40) - 1;
