@@ -91,9 +91,10 @@ def kernel_roofline(name: str, launches: int, ms: float, n_conn: int, n_passes: 
     return per_launch
 
 
-def measured_traffic(kernel: str, n_elem: int):
+def measured_traffic(kernel: str, n_elem: int, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter table, or
-    None when the kernel's source changed since the counters were taken."""
+    None when the counters were taken on another workload or the kernel's
+    source changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -102,7 +103,7 @@ def measured_traffic(kernel: str, n_elem: int):
         src = open(os.path.join(ROOT, entry["source"]), "rb").read()
     except (OSError, KeyError, ValueError):
         return None
-    if hashlib.sha1(src).hexdigest() != entry["sha1"]:
+    if entry.get("workload") != workload or hashlib.sha1(src).hexdigest() != entry["sha1"]:
         return None
     return round(n_elem * (entry["read_bytes_per_elem"] + entry["write_bytes_per_elem"]))
 
@@ -427,7 +428,7 @@ def main():
         avg_ms = ms / launches
         achieved = per / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, n_conn),
+                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, n_conn, script["name"]),
                 "kernel": name, "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": per}
 
     out = {
