@@ -6,6 +6,7 @@
 
 #include <cstdint>
 
+#include "bm_math.h"
 #include "internal.h"
 
 namespace snnc {
@@ -42,16 +43,15 @@ __device__ __forceinline__ uint32_t uniform_index(uint32_t lo, uint32_t hi, uint
     return (uint32_t)(p_hi >> 32);
 }
 
-// fp32 weight N(mean, sd): Box-Muller, cosine branch, IEEE double, one
-// rounding to fp32.  Contraction is off so that the products and sums round
-// exactly as written.
+// fp32 weight N(mean, sd): Box-Muller, cosine branch, in double precision,
+// u1 = (w0 + 1) / 2^32, u2 = w1 / 2^32, one rounding to fp32.  ln u1 and
+// cos(2pi_d u2) come from the argument-exact helpers of bm_math.h (within two
+// double ulp of the library functions).  Contraction is off so that the
+// final product and sum round as written.
 __device__ __forceinline__ float normal_weight(uint32_t w0, uint32_t w1, double mean, double sd) {
 #pragma clang fp contract(off)
-    const double two_pi = 6.283185307179586476925286766559;
-    const double u1 = ((double)w0 + 1.0) * (1.0 / 4294967296.0);
-    const double u2 = (double)w1 * (1.0 / 4294967296.0);
-    const double radius = sqrt(-2.0 * log(u1));
-    const double z = radius * cos(two_pi * u2);
+    const double radius = sqrt(-2.0 * log_u32_frac((uint64_t)w0 + 1));
+    const double z = radius * cos_2pi_u32(w1);
     const double scaled = sd * z;
     return (float)(mean + scaled);
 }
