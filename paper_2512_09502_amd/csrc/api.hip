@@ -445,8 +445,9 @@ void build_bern_table(double p, uint64_t* thr) {
 static void upload_meta(Ctx& c, Call& cl) {
     const size_t nS = std::max<size_t>(cl.S.seg.size(), 1), nT = std::max<size_t>(cl.T.seg.size(), 1);
     const size_t nB = cl.btab.size();
-    const size_t bytes = (nS + nT) * sizeof(SegD) + nB * sizeof(uint64_t) +
-                         std::max<size_t>(cl.dtab.size(), 1) * sizeof(uint32_t);
+    const size_t nD = std::max<size_t>(cl.dtab.size(), 1);
+    const size_t nG = cl.dtab.empty() ? 0 : 257;   // guide of the delay table
+    const size_t bytes = (nS + nT) * sizeof(SegD) + nB * sizeof(uint64_t) + (nD + nG) * sizeof(uint32_t);
     std::vector<char> host(bytes, 0);
     SegD* hS = reinterpret_cast<SegD*>(host.data());
     SegD* hT = hS + nS;
@@ -454,7 +455,19 @@ static void upload_meta(Ctx& c, Call& cl) {
     for (size_t i = 0; i < cl.T.seg.size(); ++i) hT[i] = SegD{cl.T.ord_begin[i], cl.T.seg[i].host, cl.T.seg[i].first};
     uint64_t* hB = reinterpret_cast<uint64_t*>(hT + nT);
     if (nB) memcpy(hB, cl.btab.data(), nB * sizeof(uint64_t));
-    if (!cl.dtab.empty()) memcpy(hB + nB, cl.dtab.data(), cl.dtab.size() * sizeof(uint32_t));
+    if (!cl.dtab.empty()) {
+        uint32_t* hD = reinterpret_cast<uint32_t*>(hB + nB);
+        memcpy(hD, cl.dtab.data(), cl.dtab.size() * sizeof(uint32_t));
+        // guide[j] = number of thresholds below j * 2^24: a word in [j 2^24, (j+1) 2^24)
+        // has its delay step between guide[j] and guide[j + 1]
+        uint32_t* hG = hD + nD;
+        for (uint32_t j = 0; j <= 256; ++j) {
+            const uint64_t edge = (uint64_t)j << 24;
+            hG[j] = (uint32_t)(std::lower_bound(cl.dtab.begin(), cl.dtab.end(), edge,
+                                                [](uint32_t t, uint64_t e) { return (uint64_t)t < e; }) -
+                               cl.dtab.begin());
+        }
+    }
     cl.meta = dalloc(c, bytes);
     cl.meta_bytes = bytes;
     upload(c, cl.meta, host.data(), bytes);
@@ -469,6 +482,7 @@ static void upload_meta(Ctx& c, Call& cl) {
     cl.in_src_pos = cl.in_tgt_pos = nullptr;
     cl.btab_dev = nB ? reinterpret_cast<uint64_t*>(cl.dT + nT) : nullptr;
     cl.dtab_dev = reinterpret_cast<uint32_t*>(reinterpret_cast<uint64_t*>(cl.dT + nT) + nB);
+    cl.dguide_dev = nG ? cl.dtab_dev + nD : nullptr;
 }
 
 void grow_gen(Ctx& c, uint64_t need) {

@@ -56,9 +56,12 @@ __device__ __forceinline__ float normal_weight(uint32_t w0, uint32_t w1, double 
     return (float)(mean + scaled);
 }
 
-// Delay step from the threshold table: k_lo + #{k : w >= t_k}.
-__device__ __forceinline__ uint16_t delay_step(const uint32_t* tab, uint32_t len, uint32_t klo, uint32_t w) {
-    uint32_t a = 0, b = len;
+// Delay step from the threshold table: k_lo + #{k : w >= t_k}.  The guide
+// bounds the search to the thresholds inside w's 2^24-wide slice (usually
+// none or one).
+__device__ __forceinline__ uint16_t delay_step(const uint32_t* tab, const uint32_t* guide, uint32_t klo,
+                                               uint32_t w) {
+    uint32_t a = guide[w >> 24], b = guide[(w >> 24) + 1];
     while (a < b) {
         const uint32_t m = (a + b) >> 1;
         if (tab[m] <= w) a = m + 1; else b = m;
@@ -71,7 +74,7 @@ __device__ __forceinline__ void syn_values(const SynD& s, uint32_t seed, uint32_
     if (s.w_normal | s.d_normal) {
         const uint4 b = draw(seed, call, e, PURPOSE_SYN);
         w = s.w_normal ? normal_weight(b.x, b.y, s.w_mean, s.w_sd) : s.w_const;
-        d = s.d_normal ? delay_step(s.dtab, s.dtab_len, s.d_klo, b.z) : (uint16_t)s.d_const;
+        d = s.d_normal ? delay_step(s.dtab, s.dguide, s.d_klo, b.z) : (uint16_t)s.d_const;
     } else {
         w = s.w_const;
         d = (uint16_t)s.d_const;

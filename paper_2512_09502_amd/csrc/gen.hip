@@ -925,6 +925,7 @@ SynD syn_of(const Call& cl) {
     s.d_normal = cl.d.kind == SNNC_NORMAL;
     s.d_const = cl.d_const;
     s.dtab = cl.dtab_dev;
+    s.dguide = cl.dguide_dev;
     s.dtab_len = (uint32_t)cl.dtab.size();
     s.d_klo = cl.d_klo;
     return s;

@@ -48,6 +48,7 @@ struct TChunk {
 struct SynD {
     double w_mean, w_sd;
     const uint32_t* dtab;  // delay thresholds (device)
+    const uint32_t* dguide;   // 257 entries: thresholds below j * 2^24 (device)
     uint32_t dtab_len;
     uint32_t d_klo;
     float w_const;
@@ -83,6 +84,7 @@ struct Call {
     SegD* dS = nullptr;
     SegD* dT = nullptr;
     uint32_t* dtab_dev = nullptr;
+    uint32_t* dguide_dev = nullptr;
     uint64_t* btab_dev = nullptr;
     uint64_t gen_begin = 0, gen_count = 0;
     std::vector<void*> owned;   // device tables kept until the call's batch has run
