@@ -340,10 +340,12 @@ typedef struct {
 
 snnc_status snnc_stats(snnc_ctx* ctx, snnc_stats_t* out);
 
-/* Per-kernel GPU timing with HIP events on the context stream.  While
- * enabled, every kernel launch is bracketed by an event pair; snnc_kernel_times
+/* Per-kernel GPU timing with HIP events on the context stream.  enable = 1:
+ * every kernel launch is bracketed by an event pair; 2: only the radix-sort
+ * passes (the brackets cost host time per launch); 0: off.  snnc_kernel_times
  * reports, per kernel name, the launch count and the summed milliseconds
- * (names as NUL-terminated strings of at most 47 characters). */
+ * (names as NUL-terminated strings of at most 47 characters).  SNNC_EINVAL
+ * for other values of enable. */
 snnc_status snnc_set_timing(snnc_ctx* ctx, int enable);
 snnc_status snnc_kernel_times(snnc_ctx* ctx, uint32_t cap, char (*names)[48], uint64_t* launches,
                               double* ms, uint32_t* n_out);

@@ -338,7 +338,8 @@ class Network:
         self._check(lib().snnc_stats(self._h, ctypes.byref(s)))
         return {f: getattr(s, f) for f, _ in Stats._fields_}
 
-    def set_timing(self, on: bool):
+    def set_timing(self, on):
+        """False/True (0/1): off / every launch; 2: the radix-sort passes only."""
         self._check(lib().snnc_set_timing(self._h, int(on)))
 
     def kernel_times(self) -> dict:

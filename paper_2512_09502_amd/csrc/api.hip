@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <stdexcept>
 
 #include "device_common.h"
@@ -177,6 +178,10 @@ static hipEvent_t get_event(Ctx& c) {
 
 void tstart(Ctx& c, const char* name) {
     if (!c.timing) return;
+    if (c.timing == 2 && strncmp(name, "sort_pass", 9) != 0) {
+        c.open_timers.push_back(SIZE_MAX);   // bracket not timed
+        return;
+    }
     Ctx::Pending p;
     p.name = name;
     p.a = get_event(c);
@@ -191,12 +196,14 @@ void tstop(Ctx& c) {
     if (!c.timing || c.open_timers.empty()) return;
     const size_t k = c.open_timers.back();
     c.open_timers.pop_back();
+    if (k == SIZE_MAX) return;
     HIPCHK(hipEventRecord(c.pending[k].b, c.stream));
 }
 
 void resolve_times(Ctx& c) {
     if (c.pending.empty()) return;
-    for (size_t k : c.open_timers) HIPCHK(hipEventRecord(c.pending[k].b, c.stream));   // left open by an error
+    for (size_t k : c.open_timers)   // left open by an error
+        if (k != SIZE_MAX) HIPCHK(hipEventRecord(c.pending[k].b, c.stream));
     c.open_timers.clear();
     HIPCHK(hipStreamSynchronize(c.main_stream));
     if (c.count_stream) HIPCHK(hipStreamSynchronize(c.count_stream));
@@ -1066,8 +1073,9 @@ snnc_status snnc_set_map_policy(snnc_ctx* c, int32_t numbering, int32_t image_so
 snnc_status snnc_set_timing(snnc_ctx* c, int enable) {
     if (!c) return SNNC_EINVAL;
     return guarded(c, [&] {
+        if (enable < 0 || enable > 2) raise(SNNC_EINVAL, "timing must be 0, 1 or 2");
         resolve_times(*c);
-        c->timing = enable != 0;
+        c->timing = enable;
         if (enable) c->ktimes.clear();
     });
 }

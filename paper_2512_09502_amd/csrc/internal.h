@@ -180,7 +180,7 @@ struct Ctx {
     uint32_t sort_passes = 0, key_bits = 0;
 
     // timing
-    bool timing = false;
+    int timing = 0;                      // 0 off, 1 every launch, 2 radix passes only
     struct Pending {
         std::string name;
         hipEvent_t a, b;
