@@ -218,3 +218,91 @@ def test_multiarea_p2p_full_size():
         R = net.tensor("r_val")
         assert torch.equal(S[s_off[tau]:s_off[tau + 1]], R[r_off[0]:r_off[1]]), f"S on 0 != R on {tau}"
         net.close()
+
+
+def _served_build(script, budget, batched):
+    reqs = [op for op in script["ops"] if op[0] == "connect"]
+    net = snnc.Network(1, 0, script["seed"], script["dt"])
+    net.set_resident_budget(budget)
+    net.reserve(budget // 14)
+    for op in script["ops"]:
+        if op[0] == "create":
+            net.create(op[1], op[2])
+    admitted = []
+    for k, op in enumerate(reqs):
+        _, src, tgt, conn, syn, alpha = op
+        try:
+            (net.submit if batched else net.connect)(src, tgt, conn, syn, alpha)
+            admitted.append(k)
+        except snnc.SnncError as e:
+            assert e.code == -3, e
+        if batched and admitted and len(admitted) % 256 == 0:
+            net.flush()
+    if batched:
+        net.flush()
+    net.sync()
+    return net, admitted
+
+
+def test_served_full_size():
+    """10,000 uneven requests against a 64 GiB resident budget, built in fused
+    batches as the bench builds them: the admitted requests and their
+    connection counts equal the per-call build's; sampled connections of the
+    rules whose elements are independent equal the oracle's replay of their
+    element (element = position for fixed in/out-degree and total number
+    with multapses and autapses, the source ordinal for one-to-one, the pair
+    index for Bernoulli); calls of up to 20,000 connections of every rule
+    (Floyd's sampling, first-N-valid candidates) equal the oracle's generation
+    of the whole call."""
+    _torch()
+    script = W.served_requests()
+    budget = 64 << 30
+    reqs = [op for op in script["ops"] if op[0] == "connect"]
+    net, adm = _served_build(script, budget, batched=True)
+    off = net.array("call_off").astype(np.int64)
+    per_call, adm_p = _served_build(script, budget, batched=False)
+    off_p = per_call.array("call_off").astype(np.int64)
+    per_call.close()
+    assert adm == adm_p
+    np.testing.assert_array_equal(off, off_p)
+    log(f"served full: {len(adm)} admitted, {off[-1]} connections")
+    kept = dict(script)
+    kept["ops"] = [op for op in script["ops"] if op[0] == "create"] + [reqs[k] for k in adm]
+    ref = oracle.run_script(kept, 0, declare_only=True)
+    rng = np.random.default_rng(3)
+    n_elem = n_full = 0
+    for c, k in enumerate(adm):
+        _, src, tgt, conn, syn, alpha = reqs[k]
+        a, b = int(off[c]), int(off[c + 1])
+        if b == a:
+            continue
+        rule = conn["rule"]
+        aut, mult = conn.get("autapses", True), conn.get("multapses", True)
+        independent = (rule in ("fixed_indegree", "fixed_outdegree") and mult) or \
+                      (rule == "fixed_total_number" and mult and aut) or rule in ("one_to_one", "pairwise_bernoulli")
+        if independent and c % 3 == 0:
+            for p in np.unique(rng.integers(a, b, size=4)):
+                p = int(p)
+                got = {n: net.array_range("gen_" + n, p, 1)[0] for n in ("src", "tgt", "delay", "weight")}
+                if rule == "one_to_one":
+                    e = int(got["src"])
+                elif rule == "pairwise_bernoulli":
+                    n_s = sum(s[2] for s in src)
+                    e = (int(got["tgt"]) - tgt[0][1]) * n_s + int(got["src"])
+                else:
+                    e = p - a
+                r = ref.element(c, e)
+                assert r is not None, (c, rule, e)
+                assert (got["src"], got["tgt"], got["delay"]) == (r["src"], r["tgt"], r["delay"]), (c, rule, p)
+                assert ulp_diff(np.array([got["weight"]], np.float32), np.array([r["weight"]], np.float32)) <= 2
+                n_elem += 1
+        if b - a <= 20000 and (not independent or c % 7 == 0):
+            want = ref.call_range(c, 0, 0, 2**63, b - a + 1)
+            assert want["src"].size == b - a, (c, rule, want["src"].size, b - a)
+            np.testing.assert_array_equal(net.array_range("gen_src", a, b - a), want["src"])
+            np.testing.assert_array_equal(net.array_range("gen_tgt", a, b - a), want["tgt"])
+            np.testing.assert_array_equal(net.array_range("gen_delay", a, b - a), want["delay"])
+            assert ulp_diff(net.array_range("gen_weight", a, b - a), want["weight"]) <= 2
+            n_full += 1
+    log(f"served full: {n_elem} sampled elements, {n_full} whole calls equal the oracle")
+    net.close()
