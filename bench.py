@@ -44,6 +44,35 @@ def expected_conns(script) -> int:
     return int(info.get("conns", info.get("conns_per_host", 0)))
 
 
+PHASES = (
+    ("generation", ("gen_",)),
+    ("keys_unique_remap", ("prep_keys", "prep_number", "prep_bits", "prep_first", "prep_fc_bits", "prep_img_list",
+                           "prep_rvals", "prep_bounds", "prep_img_rows")),
+    ("sort", ("sort_",)),
+    ("csr", ("prep_csr",)),
+    ("send_lists", ("prep_mark", "prep_tp", "prep_s_", "prep_hi", "prep_gq")),
+)
+
+
+def phase_times(kernels: dict, stats: dict) -> dict:
+    """Kernel milliseconds of one build grouped by the path's steps (generation;
+    key build, image unique/number/remap; sort; first-index array; send lists),
+    and the connect and prepare phases timed by HIP events on the library stream."""
+    out = {name: 0.0 for name, _ in PHASES}
+    out["other"] = 0.0
+    for k, (_, ms) in kernels.items():
+        for name, prefixes in PHASES:
+            if any(k.startswith(p) for p in prefixes):
+                out[name] += ms
+                break
+        else:
+            out["other"] += ms
+    out = {k: round(v, 3) for k, v in out.items()}
+    out["connect_events_ms"] = round(stats["ms_connect"], 3)
+    out["prepare_events_ms"] = round(stats["ms_prepare"], 3)
+    return out
+
+
 def _kept(net, name) -> bool:
     """whether the prepared network holds this array (some exist at certain memory levels only)"""
     import paper_2512_09502_amd as snnc
@@ -459,6 +488,8 @@ def main():
                    "map_policy": script.get("map_policy"), "memory_level": script.get("memory_level")},
         "sort_tuning": tuning,
         "step_ms": {"min": round(1e3 * min(times), 3), "median": round(1e3 * sorted(times)[len(times) // 2], 3)},
+        # per-phase times of the scope table's steps, from the same breakdown
+        "phase_ms": phase_times(per_build, stats),
         # per-kernel breakdown of one build after the timed steps (every launch bracketed)
         "kernels_ms_per_step": {k: round(v[1], 3) for k, v in sorted(per_build.items(), key=lambda kv: -kv[1][1])},
         "dominant_kernel": dom[0],
