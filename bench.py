@@ -39,8 +39,12 @@ def workload(name: str, scale: float):
     raise SystemExit(f"unknown workload {name}")
 
 
-def expected_conns(script) -> int:
+def expected_conns(script, P_local: int = 0) -> int:
+    """Connections the host will hold, where the workload states it (passed to
+    snnc_reserve so that the generation arrays are allocated once)."""
     info = script.get("info", {})
+    if "conns_by_host" in info:
+        return int(info["conns_by_host"][P_local])
     return int(info.get("conns", info.get("conns_per_host", 0)))
 
 
@@ -94,7 +98,7 @@ def build_once(script, P_local: int, timing):
         net.tune("sort_variant", script["sort_variant"])
     if timing:
         net.set_timing(timing)   # 1: every launch, 2: the radix passes only
-    hint = expected_conns(script)
+    hint = expected_conns(script, P_local)
     if hint:
         net.reserve(hint)
     for op in script["ops"]:

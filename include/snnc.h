@@ -334,7 +334,7 @@ typedef struct {
     uint64_t bytes_peak;      /* high-water mark                          */
     uint32_t sort_passes;     /* radix passes of the last prepare         */
     uint32_t key_bits;        /* bits(sources) + bits(targets)            */
-    double ms_connect;        /* GPU time of all connect calls (events)   */
+    double ms_connect;        /* stream time from the first connect call to the start of prepare (events) */
     double ms_prepare;        /* GPU time of prepare                      */
 } snnc_stats_t;
 

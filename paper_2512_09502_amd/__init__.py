@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import struct
 
 import numpy as np
 
@@ -136,6 +137,11 @@ def lib():
                                          ctypes.POINTER(ctypes.c_float)]
         for name in EXPORTS:
             getattr(L, name).restype = st if name != "snnc_last_error" else ctypes.c_char_p
+        # connect and submit with their structs passed as plain addresses into
+        # one packed buffer (see Network._connect_like)
+        proto = ctypes.CFUNCTYPE(st, vp, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_size_t, i32,
+                                 ctypes.c_size_t)
+        L.packed = {name: proto((name, L)) for name in ("snnc_connect", "snnc_submit")}
         _lib = L
     return _lib
 
@@ -150,6 +156,23 @@ def _dist(d) -> Dist:
     d = d or {"kind": "const", "mean": 0.0}
     return Dist(DISTS[d.get("kind", "const")], 0, float(d.get("mean", 0.0)), float(d.get("sd", 0.0)),
                 float(d.get("lo", 0.0)))
+
+
+# Packed connect arguments, C layout without padding: snnc_conn_spec (32 B),
+# snnc_syn_spec (72 B), source and target snnc_nodeset (16 B each), the call
+# id (4 B, then 4 B pad), then the segments (12 B each).
+_SPEC = struct.Struct("<IIIIQdIIdddIIdddII")
+_NODESETS = struct.Struct("<QI4xQI4x")
+_OFF_SYN, _OFF_NS, _OFF_CID, _OFF_SEG = 32, 104, 136, 144
+_SEGS = {}
+_CONST0 = {"kind": "const", "mean": 0.0}
+
+
+def _seg_struct(n):
+    f = _SEGS.get(n)
+    if f is None:
+        f = _SEGS[n] = struct.Struct("<" + "III" * n)
+    return f
 
 
 def _nodeset(segs):
@@ -231,21 +254,38 @@ class Network:
         self._check(lib().snnc_create(self._h, host, n, ctypes.byref(seg)))
         return (seg.host, seg.first, seg.n)
 
-    def _connect_like(self, fn, src, tgt, conn, syn, alpha):
-        s, s_keep = _nodeset(src)
-        t, t_keep = _nodeset(tgt)
-        cs = ConnSpec(RULES[conn["rule"]], int(conn.get("autapses", True)), int(conn.get("multapses", True)), 0,
-                      int(conn.get("n", 0)), float(conn.get("p", 0.0)))
-        ss = SynSpec(_dist(syn.get("weight")), _dist(syn.get("delay")), int(syn.get("port", 0)), 0)
-        cid = ctypes.c_uint32()
-        self._check(fn(self._h, ctypes.byref(s), ctypes.byref(t), ctypes.byref(cs), ctypes.byref(ss), int(alpha),
-                       ctypes.byref(cid)))
-        return int(cid.value)
+    def _connect_like(self, name, src, tgt, conn, syn, alpha):
+        # one struct.pack per argument group into a buffer reused across calls
+        ns, nt = len(src), len(tgt)
+        need = _OFF_SEG + 12 * (ns + nt)
+        if need > len(getattr(self, "_mb", b"")):
+            self._mb = ctypes.create_string_buffer(max(need, 1024))
+            self._mb_cid = ctypes.c_uint32.from_buffer(self._mb, _OFF_CID)
+        mb = self._mb
+        base = ctypes.addressof(mb)
+        w = syn.get("weight") or _CONST0
+        d = syn.get("delay") or _CONST0
+        try:
+            _SPEC.pack_into(mb, 0, RULES[conn["rule"]], int(conn.get("autapses", True)),
+                            int(conn.get("multapses", True)), 0, int(conn.get("n", 0)), float(conn.get("p", 0.0)),
+                            DISTS[w.get("kind", "const")], 0, float(w.get("mean", 0.0)), float(w.get("sd", 0.0)),
+                            float(w.get("lo", 0.0)),
+                            DISTS[d.get("kind", "const")], 0, float(d.get("mean", 0.0)), float(d.get("sd", 0.0)),
+                            float(d.get("lo", 0.0)), int(syn.get("port", 0)), 0)
+            seg0 = base + _OFF_SEG
+            _NODESETS.pack_into(mb, _OFF_NS, seg0, ns, seg0 + 12 * ns, nt)
+            _seg_struct(ns + nt).pack_into(mb, _OFF_SEG, *[int(v) for g in src for v in g],
+                                           *[int(v) for g in tgt for v in g])
+        except struct.error as err:
+            raise SnncError(-1, f"connection argument out of range: {err}") from None
+        self._check(lib().packed[name](self._h, base + _OFF_NS, base + _OFF_NS + 16, base, base + _OFF_SYN,
+                                       int(alpha), base + _OFF_CID))
+        return int(self._mb_cid.value)
 
     def connect(self, src, tgt, conn, syn, alpha: int = -1) -> int:
         if conn["rule"] == "assigned_nodes":
             return self.connect_assigned(src, tgt, conn["pairs"][0], conn["pairs"][1], syn, alpha)
-        return self._connect_like(lib().snnc_connect, src, tgt, conn, syn, alpha)
+        return self._connect_like("snnc_connect", src, tgt, conn, syn, alpha)
 
     def connect_assigned(self, src, tgt, src_pos, tgt_pos, syn, alpha: int = -1) -> int:
         """Assigned nodes: pair i connects position src_pos[i] of src to
@@ -265,7 +305,7 @@ class Network:
 
     def submit(self, src, tgt, conn, syn, alpha: int = -1) -> int:
         """Served mode: admit and reserve now, generate at the next flush()."""
-        return self._connect_like(lib().snnc_submit, src, tgt, conn, syn, alpha)
+        return self._connect_like("snnc_submit", src, tgt, conn, syn, alpha)
 
     def flush(self):
         self._check(lib().snnc_flush(self._h))

@@ -347,7 +347,32 @@ static bool build_delay_table(double mean, double sd, double lo, double dt, std:
     return true;
 }
 
-static void validate(const Ctx& c, Call& cl, const snnc_syn_spec* syn) {
+// The context's table of a normal delay distribution, built on first use
+// (null when the distribution does not fit uint16 steps).
+static std::shared_ptr<const DelayTable> delay_table_for(Ctx& c, const snnc_dist& d) {
+    std::array<uint64_t, 3> key;
+    memcpy(&key[0], &d.mean, 8);
+    memcpy(&key[1], &d.sd, 8);
+    memcpy(&key[2], &d.lo, 8);
+    auto it = c.delay_tables.find(key);
+    if (it != c.delay_tables.end()) return it->second;
+    auto t = std::make_shared<DelayTable>();
+    if (!build_delay_table(d.mean, d.sd, d.lo, c.dt, t->tab, t->klo, 65536)) return nullptr;
+    if (!t->tab.empty()) {   // the thresholds do not decrease: one merge against the slice edges
+        t->guide.resize(257);
+        size_t i = 0;
+        for (uint32_t j = 0; j <= 256; ++j) {
+            const uint64_t edge = (uint64_t)j << 24;
+            while (i < t->tab.size() && t->tab[i] < edge) ++i;
+            t->guide[j] = (uint32_t)i;
+        }
+    }
+    if (c.delay_tables.size() >= 4096) c.delay_tables.clear();   // bound the cache
+    c.delay_tables.emplace(key, t);
+    return t;
+}
+
+static void validate(Ctx& c, Call& cl, const snnc_syn_spec* syn) {
     const uint64_t ns = cl.S.total, nt = cl.T.total;
     const uint64_t ov = cl.autapses ? 0 : set_overlap(cl.S, cl.T);
     switch (cl.rule) {
@@ -425,8 +450,9 @@ static void validate(const Ctx& c, Call& cl, const snnc_syn_spec* syn) {
     } else if (cl.d.kind == SNNC_NORMAL) {
         if (!(cl.d.sd > 0.0)) raise(SNNC_EINVAL, "delay sd must be > 0");
         if (!(cl.d.lo >= c.dt)) raise(SNNC_EINVAL, "delay clip below one time step");
-        if (!build_delay_table(cl.d.mean, cl.d.sd, cl.d.lo, c.dt, cl.dtab, cl.d_klo, 65536))
-            raise(SNNC_EINVAL, "delay distribution does not fit uint16 steps");
+        cl.dtab = delay_table_for(c, cl.d);
+        if (!cl.dtab) raise(SNNC_EINVAL, "delay distribution does not fit uint16 steps");
+        cl.d_klo = cl.dtab->klo;
     } else raise(SNNC_EINVAL, "unknown delay distribution");
 }
 
@@ -449,11 +475,12 @@ void build_bern_table(double p, uint64_t* thr) {
 }
 
 // device copies of a call's sets, Bernoulli gap table and delay table (one allocation)
-static void upload_meta(Ctx& c, Call& cl) {
+void upload_meta(Ctx& c, Call& cl) {
     const size_t nS = std::max<size_t>(cl.S.seg.size(), 1), nT = std::max<size_t>(cl.T.seg.size(), 1);
     const size_t nB = cl.btab.size();
-    const size_t nD = std::max<size_t>(cl.dtab.size(), 1);
-    const size_t nG = cl.dtab.empty() ? 0 : 257;   // guide of the delay table
+    const std::vector<uint32_t>* tab = cl.dtab && !cl.dtab->tab.empty() ? &cl.dtab->tab : nullptr;
+    const size_t nD = tab ? tab->size() : 1;
+    const size_t nG = tab ? 257 : 0;   // guide of the delay table
     const size_t bytes = (nS + nT) * sizeof(SegD) + nB * sizeof(uint64_t) + (nD + nG) * sizeof(uint32_t);
     std::vector<char> host(bytes, 0);
     SegD* hS = reinterpret_cast<SegD*>(host.data());
@@ -462,18 +489,10 @@ static void upload_meta(Ctx& c, Call& cl) {
     for (size_t i = 0; i < cl.T.seg.size(); ++i) hT[i] = SegD{cl.T.ord_begin[i], cl.T.seg[i].host, cl.T.seg[i].first};
     uint64_t* hB = reinterpret_cast<uint64_t*>(hT + nT);
     if (nB) memcpy(hB, cl.btab.data(), nB * sizeof(uint64_t));
-    if (!cl.dtab.empty()) {
+    if (tab) {
         uint32_t* hD = reinterpret_cast<uint32_t*>(hB + nB);
-        memcpy(hD, cl.dtab.data(), cl.dtab.size() * sizeof(uint32_t));
-        // guide[j] = number of thresholds below j * 2^24: a word in [j 2^24, (j+1) 2^24)
-        // has its delay step between guide[j] and guide[j + 1]
-        uint32_t* hG = hD + nD;
-        for (uint32_t j = 0; j <= 256; ++j) {
-            const uint64_t edge = (uint64_t)j << 24;
-            hG[j] = (uint32_t)(std::lower_bound(cl.dtab.begin(), cl.dtab.end(), edge,
-                                                [](uint32_t t, uint64_t e) { return (uint64_t)t < e; }) -
-                               cl.dtab.begin());
-        }
+        memcpy(hD, tab->data(), nD * sizeof(uint32_t));
+        memcpy(hD + nD, cl.dtab->guide.data(), 257 * sizeof(uint32_t));
     }
     cl.meta = dalloc(c, bytes);
     cl.meta_bytes = bytes;
@@ -547,12 +566,24 @@ static Call make_call_host(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* 
     return cl;
 }
 
-// ... with its device metadata.
+// Whether the call's device tables are needed on this host: it has local
+// sources or targets (a call with neither adds no local connection and no
+// entry to the local send lists), or it takes assigned pairs (the caller's
+// pair arrays are copied during the call).  Other calls keep host records only;
+// run_call uploads the tables if it is ever asked to run one.
+static bool needs_meta(const Ctx& c, const Call& cl) {
+    if (cl.rule == SNNC_ASSIGNED_NODES) return true;
+    for (auto& g : cl.S.seg) if (g.host == c.P_local && g.n) return true;
+    for (auto& g : cl.T.seg) if (g.host == c.P_local && g.n) return true;
+    return false;
+}
+
+// ... with its device metadata where this host needs it.
 static Call make_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, const snnc_conn_spec* conn,
                       const snnc_syn_spec* syn, int32_t alpha, bool pairs = false,
                       const uint32_t* src_pos = nullptr, const uint32_t* tgt_pos = nullptr) {
     Call cl = make_call_host(c, src, tgt, conn, syn, alpha, pairs, src_pos, tgt_pos);
-    upload_meta(c, cl);
+    if (needs_meta(c, cl)) upload_meta(c, cl);
     return cl;
 }
 
@@ -573,6 +604,10 @@ static Call counted_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
                          const snnc_syn_spec* syn, int32_t alpha, uint64_t* n_out, bool pairs = false,
                          const uint32_t* src_pos = nullptr, const uint32_t* tgt_pos = nullptr) {
     Call cl = make_call_host(c, src, tgt, conn, syn, alpha, pairs, src_pos, tgt_pos);
+    if (!needs_meta(c, cl)) {          // no local target: nothing to count or generate here
+        *n_out = 0;
+        return cl;
+    }
     if (!count_on_device(c, cl)) {     // counted on the host: no second stream needed
         upload_meta(c, cl);
         try {
@@ -611,8 +646,7 @@ static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
             c.conn_started = true;
         }
         cl.gen_begin = c.n_gen;
-        cl.gen_count = gen_local(c, cl);
-        HIPCHK(hipEventRecord(c.conn_last, c.stream));
+        cl.gen_count = cl.meta ? gen_local(c, cl) : 0;   // no tables: no local target
         HIPCHK(hipGetLastError());
     } catch (...) {
         dfree(c, cl.meta);
@@ -663,7 +697,6 @@ void flush_pending(Ctx& c) {
     ids.swap(c.queued);
     for (uint32_t id : ids) c.calls[id].batch = b;
     flush_batch(c, ids, ev);
-    HIPCHK(hipEventRecord(c.conn_last, c.stream));
 }
 
 static void free_results(Ctx& c) {
@@ -872,7 +905,8 @@ snnc_status snnc_prepare(snnc_ctx* c) {
     return guarded(c, [&] {
         if (c->prepared) raise(SNNC_ESTATE, "prepare called twice");
         flush_pending(*c);
-        if (c->conn_started) {
+        if (c->conn_started) {   // the connect phase ends where prepare's work begins
+            HIPCHK(hipEventRecord(c->conn_last, c->stream));
             HIPCHK(hipEventSynchronize(c->conn_last));
             float cms = 0.f;
             HIPCHK(hipEventElapsedTime(&cms, c->conn_first, c->conn_last));

@@ -926,7 +926,7 @@ SynD syn_of(const Call& cl) {
     s.d_const = cl.d_const;
     s.dtab = cl.dtab_dev;
     s.dguide = cl.dguide_dev;
-    s.dtab_len = (uint32_t)cl.dtab.size();
+    s.dtab_len = cl.dtab ? (uint32_t)cl.dtab->tab.size() : 0u;
     s.d_klo = cl.d_klo;
     return s;
 }
@@ -946,6 +946,7 @@ enum class Out { APPEND, AT_BASE, COUNT, MARK };
 //            depends on the draws);
 //   MARK:    mark the sources on P_local (point-to-point regeneration).
 uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits) {
+    if (!cl.meta) upload_meta(c, cl);
     const bool mark = mode == Out::MARK;
     WriteSink ws{};
     MarkSink ms{};
@@ -1469,6 +1470,10 @@ void flush_batch(Ctx& c, const std::vector<uint32_t>& ids, hipEvent_t done) {
     for (uint32_t id : ids) {
         Call& cl = c.calls[id];
         FusedReq q;
+        if (!cl.gen_count) {           // nothing to generate on this host
+            release_pre(c, cl);
+            continue;
+        }
         if (c.fuse_batches && fused_desc(c, cl, q, cl.owned)) {
             q.item_begin = total;
             total += cl.gen_count;

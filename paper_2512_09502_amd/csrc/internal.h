@@ -6,7 +6,9 @@
 #include <cstdint>
 #include <cstring>
 #include <deque>
+#include <array>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -64,6 +66,15 @@ struct HostSet {
     uint64_t total = 0;
 };
 
+// Threshold table of a normal delay distribution (delay step klo + i while the
+// word is at or above tab[i]) and its guide: guide[j] counts the thresholds
+// below j 2^24, so a word in [j 2^24, (j + 1) 2^24) has its step between
+// guide[j] and guide[j + 1].  Built once per distribution and context.
+struct DelayTable {
+    uint32_t klo = 0;
+    std::vector<uint32_t> tab, guide;
+};
+
 struct Call {
     uint32_t id = 0;
     uint32_t rule = 0;
@@ -76,7 +87,7 @@ struct Call {
     float w_const = 0.f;
     uint16_t d_const = 0;
     uint32_t d_klo = 0;
-    std::vector<uint32_t> dtab;
+    std::shared_ptr<const DelayTable> dtab;   // normal delays only
     std::vector<uint64_t> btab;         // Bernoulli gap thresholds (64), pairwise Bernoulli only
     // device copies
     void* meta = nullptr;       // one allocation: S segs, T segs, delay table
@@ -216,7 +227,9 @@ struct Ctx {
     // pinned landing area of small device-to-host reads (each read waits for its copy)
     char* dl_pin = nullptr;
     size_t dl_pin_bytes = 0;
-    // connect timing: first connect start, last connect end
+    // delay tables by distribution (bit patterns of mean, sd, lo)
+    std::map<std::array<uint64_t, 3>, std::shared_ptr<const DelayTable>> delay_tables;
+    // connect timing: first connect start, prepare entry
     hipEvent_t conn_first = nullptr, conn_last = nullptr;
     bool conn_started = false;
 
@@ -299,6 +312,8 @@ void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits);
 // frees what the admission count kept with a call
 void release_pre(Ctx& c, Call& cl);
 bool count_on_device(const Ctx& c, const Call& cl);
+// device copies of a call's sets and tables (cl.meta), once
+void upload_meta(Ctx& c, Call& cl);
 // exact number of connections the call has on P_local's share (may launch a
 // counting pass)
 uint64_t gen_count_local(Ctx& c, Call& cl);

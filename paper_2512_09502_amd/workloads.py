@@ -126,7 +126,9 @@ def multiarea_p2p(P: int = 32, n_e: int = 104000, n_i: int = 26000, k_e: int = 2
             b.connect([E[sigma]], tgt, {"rule": "fixed_indegree", "n": int(kr[sigma, tau]),
                                         "autapses": True, "multapses": True},
                       {"weight": W_E, "delay": d_remote}, alpha=-1)
-    return b.script("multiarea_p2p", k_remote=kr.tolist())
+    # connections held by each host: every target draws k_e + k_i local and sum_sigma K[sigma, tau] remote sources
+    by_host = [(n_e + n_i) * (k_e + k_i + int(kr[:, tau].sum() - kr[tau, tau])) for tau in range(P)]
+    return b.script("multiarea_p2p", k_remote=kr.tolist(), conns_by_host=by_host)
 
 
 def balanced_collective(P: int = 1024, n_e: int = 160000, n_i: int = 40000, k_e: int = 9000,

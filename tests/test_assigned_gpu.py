@@ -75,8 +75,7 @@ def test_assigned_argument_checks():
     with pytest.raises(snnc.SnncError) as e:
         net.connect([(0, 0, 5)], [(0, 0, 10)], {"rule": "assigned_nodes", "pairs": ([0, 1], [0])}, syn)
     assert e.value.code == -1
-    from paper_2512_09502_amd import lib
-    for entry in (lib().snnc_connect, lib().snnc_submit):
+    for entry in ("snnc_connect", "snnc_submit"):
         with pytest.raises(snnc.SnncError) as e:
             net._connect_like(entry, [(0, 0, 5)], [(0, 0, 10)], {"rule": "assigned_nodes", "n": 0}, syn, -1)
         assert e.value.code == -1
