@@ -96,6 +96,8 @@ def build_once(script, P_local: int, timing):
         net.set_map_policy(*script["map_policy"])
     if script.get("sort_variant") is not None:
         net.tune("sort_variant", script["sort_variant"])
+    for key, value in script.get("tune", {}).items():
+        net.tune(key, value)
     if timing:
         net.set_timing(timing)   # 1: every launch, 2: the radix passes only
     hint = expected_conns(script, P_local)

@@ -483,6 +483,8 @@ def run_script(script: dict, P_local: int, prepare: bool = True, skip_invalid: b
         net.set_memory_level(script["memory_level"])
     if script.get("map_policy") is not None:
         net.set_map_policy(*script["map_policy"])
+    for key, value in script.get("tune", {}).items():
+        net.tune(key, value)
     net.rejected = []
     for k, op in enumerate(script["ops"]):
         if op[0] == "create":

@@ -210,6 +210,7 @@ struct Ctx {
     void* lookback = nullptr;            // per lane
     size_t lookback_bytes = 0;           // per lane
     int sort_variant = 0;                // tile shape of the radix passes (tunable)
+    int number_variant = 10;             // tile shape of the image-numbering pass (tunable; 1024 x 10, payload early)
     int sort_mode = 0;                   // 0: onesweep (look-back), 1: reduce-then-scan (tunable)
     bool sort_pinned = false;            // set by hand: the autotuner's process-wide choice is not used
     int digit_bits = 0;                  // 0: 9-bit digits when they save a pass; 8 or 9: forced
@@ -311,6 +312,8 @@ uint64_t gen_local(Ctx& c, Call& cl);
 void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits);
 // frees what the admission count kept with a call
 void release_pre(Ctx& c, Call& cl);
+// number of tile shapes of the image-numbering pass
+int number_variant_count();
 bool count_on_device(const Ctx& c, const Call& cl);
 // device copies of a call's sets and tables (cl.meta), once
 void upload_meta(Ctx& c, Call& cl);

@@ -224,12 +224,25 @@ __global__ __launch_bounds__(PNT) void k_keys(Lookup L, const uint32_t* g_src, c
 // these flags (decoupled look-back across tiles) gives each connection its
 // image index.  The same pass unpacks the connection arrays, records each
 // image's prefix and writes the first-index array.
-constexpr int XNT = 1024;
-constexpr int XIPT = 12;
-constexpr uint64_t XTILE = XNT * XIPT;
+// Tile shapes (threads, items per thread; whether the payload is loaded with
+// the keys, before the look-back).  Measured on the 6.4e8- and 2.25e9-connection
+// remote-source networks: larger tiles win (fewer look-back steps per element)
+// and loading the payload early hides its latency behind the look-back; 1024
+// threads x 10 items with the early payload is the fastest shape that does
+// not spill (variant 10, the default).
+struct NumberShape {
+    int nt, ipt;
+    bool early_vals;
+};
+constexpr NumberShape NUMBER_SHAPES[] = {{1024, 12, false}, {512, 12, false}, {256, 12, false},
+                                         {512, 12, true},   {256, 12, true},  {256, 16, true},
+                                         {256, 8, true},    {256, 6, true},   {512, 8, true},
+                                         {1024, 12, true},  {1024, 10, true}, {1024, 8, true}};
+constexpr int NUMBER_VARIANTS = (int)(sizeof(NUMBER_SHAPES) / sizeof(NUMBER_SHAPES[0]));
 constexpr uint64_t XFLAG_AGG = 1ull << 62, XFLAG_INC = 2ull << 62, XVALUE = (1ull << 40) - 1;
 constexpr uint32_t XEPOCH_MAX = (1u << 22) - 1;
 
+template <int XNT, int XIPT, bool EARLY_VALS>
 __global__ __launch_bounds__(XNT) void k_number(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                 uint64_t n, uint32_t tgt_shift, uint64_t tgt_mask, uint32_t M_local,
                                                 uint64_t* lookback, uint32_t* tile_counter, uint32_t epoch,
@@ -243,10 +256,12 @@ __global__ __launch_bounds__(XNT) void k_number(const uint64_t* __restrict__ key
     if (threadIdx.x == 0) s_tile = atomicAdd(tile_counter, 1u);
     __syncthreads();
     const uint64_t tile = s_tile;
+    constexpr uint64_t XTILE = (uint64_t)XNT * XIPT;
     const uint64_t wbase = tile * XTILE + (uint64_t)wave * 64 * XIPT;
     // element of item k on this lane: wbase + k*64 + lane (wave-striped, so loads and stores coalesce);
     // the keys stay in registers for the second half (a reload would come from HBM again)
     uint64_t key[XIPT];
+    uint32_t val[EARLY_VALS ? XIPT : 1];
     uint32_t incl[XIPT];          // flags up to and including the item, within the wave
     uint32_t fl = 0;              // bit k: item k starts a new image
     const uint64_t before_wave = wbase > 0 && wbase - 1 < n ? (keys[wbase - 1] >> tgt_shift) : ~0ull;
@@ -256,6 +271,7 @@ __global__ __launch_bounds__(XNT) void k_number(const uint64_t* __restrict__ key
     for (int k = 0; k < XIPT; ++k) {
         const uint64_t i = wbase + (uint64_t)k * 64 + lane;
         key[k] = i < n ? keys[i] : ~0ull;
+        if constexpr (EARLY_VALS) val[k] = i < n ? vals[i] : 0u;
         const uint64_t pk = i < n ? key[k] >> tgt_shift : ~0ull;
         uint64_t prev = __shfl_up(pk, 1, 64);
         const uint64_t last_lane = __shfl(pk, 63, 64);
@@ -323,7 +339,8 @@ __global__ __launch_bounds__(XNT) void k_number(const uint64_t* __restrict__ key
         o_src[i] = (int32_t)src2;
         o_tgt[i] = (int32_t)((key[k] >> 16) & tgt_mask);
         o_delay[i] = (uint16_t)(key[k] & 0xffffu);
-        o_weight[i] = __uint_as_float(vals[i]);
+        if constexpr (EARLY_VALS) o_weight[i] = __uint_as_float(val[k]);
+        else o_weight[i] = __uint_as_float(vals[i]);
         // previous connection's source' (its flag count is rank minus this item's flag)
         const bool flag_here = (fl >> k) & 1u;
         int64_t prev2 = -1;
@@ -763,6 +780,8 @@ void place_memory_level(Ctx& c, uint32_t M_local) {
 
 }  // namespace
 
+int number_variant_count() { return NUMBER_VARIANTS; }
+
 void prepare_all(Ctx& c) {
     const uint32_t P = c.P, PL = c.P_local;
     const uint64_t N = c.n_gen;
@@ -969,7 +988,9 @@ void prepare_all(Ctx& c) {
                 uint64_t* img_key = static_cast<uint64_t*>(tmp(max_img * 8 + 8));
                 row_ptr = result<uint64_t>(c, SNNC_ROW_PTR, (uint64_t)M_local + max_img + 1);
                 uint64_t* d_nimg = static_cast<uint64_t*>(tmp(8));
-                const uint64_t tiles = (N + XTILE - 1) / XTILE;
+                const NumberShape shape = NUMBER_SHAPES[c.number_variant];
+                const uint64_t xtile = (uint64_t)shape.nt * shape.ipt;
+                const uint64_t tiles = (N + xtile - 1) / xtile;
                 if (c.lookback_bytes < tiles * 8) raise(SNNC_EDEVICE, "look-back table too small");
                 if (++c.sort_epoch > XEPOCH_MAX) {
                     HIPCHK(hipMemsetAsync(c.lookback, 0, c.lookback_bytes, c.stream));
@@ -979,9 +1000,25 @@ void prepare_all(Ctx& c) {
                 HIPCHK(hipMemsetAsync(counter, 0, 4, c.stream));
                 const uint32_t* vsorted = which ? vals1 : reinterpret_cast<uint32_t*>(c.g_weight);
                 tstart(c, "prep_number");
-                hipLaunchKernelGGL(k_number, dim3((unsigned)tiles), dim3(XNT), 0, c.stream, which ? keys1 : keys0,
+                auto number = [&](auto kern, int nt) {
+                    hipLaunchKernelGGL(kern, dim3((unsigned)tiles), dim3(nt), 0, c.stream, which ? keys1 : keys0,
                                    vsorted, N, 16 + tbits, fo.tgt_mask, M_local, (uint64_t*)c.lookback, counter,
                                    c.sort_epoch, c.d_status, o_src, o_tgt, o_delay, o_weight, img_key, row_ptr, d_nimg);
+                };
+                switch (c.number_variant) {
+                case 0: number(k_number<1024, 12, false>, 1024); break;
+                case 1: number(k_number<512, 12, false>, 512); break;
+                case 2: number(k_number<256, 12, false>, 256); break;
+                case 3: number(k_number<512, 12, true>, 512); break;
+                case 4: number(k_number<256, 12, true>, 256); break;
+                case 5: number(k_number<256, 16, true>, 256); break;
+                case 6: number(k_number<256, 8, true>, 256); break;
+                case 7: number(k_number<256, 6, true>, 256); break;
+                case 8: number(k_number<512, 8, true>, 512); break;
+                case 9: number(k_number<1024, 12, true>, 1024); break;
+                case 10: number(k_number<1024, 10, true>, 1024); break;
+                default: number(k_number<1024, 8, true>, 1024); break;
+                }
                 tstop(c);
                 HIPCHK(hipGetLastError());
                 download(c, &n_img, d_nimg, 8);

@@ -50,6 +50,17 @@ def test_multiarea_p2p_scaled():
         compare_all(s, pl)
 
 
+@pytest.mark.parametrize("variant", range(12))
+def test_number_variants(variant):
+    """Every tile shape of the image-numbering pass (block size, items per
+    thread, payload loaded before or after the look-back) gives the oracle's
+    arrays, on networks with remote sources over many tiles."""
+    for s in (W.multiarea_p2p(P=6, n_e=2000, n_i=500, k_e=40, k_i=10, k_remote_max=12),
+              W.balanced_collective(P=12, n_e=400, n_i=100, k_e=90, k_i=22)):
+        s["tune"] = {"number_variant": variant}
+        compare_all(s, 1)
+
+
 def test_balanced_collective_scaled():
     s = W.balanced_collective(P=12, n_e=400, n_i=100, k_e=90, k_i=22)
     for pl in (0, 11):
