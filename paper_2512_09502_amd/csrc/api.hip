@@ -1043,6 +1043,9 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
         } else if (!strcmp(key, "number_variant")) {
             if (value < 0 || value >= number_variant_count()) raise(SNNC_EINVAL, "number_variant out of range");
             c->number_variant = (int)value;
+        } else if (!strcmp(key, "mark_in_lds")) {
+            if (value < 0 || value > 1) raise(SNNC_EINVAL, "mark_in_lds must be 0 or 1");
+            c->mark_in_lds = value == 1;
         } else if (!strcmp(key, "sort_mode")) {
             if (value < 0 || value > 1) raise(SNNC_EINVAL, "sort_mode out of range");
             c->sort_mode = (int)value;

@@ -56,6 +56,7 @@ struct MarkSink {
     uint32_t nS;
     uint32_t host;
     uint32_t* bits;
+    uint32_t words;   // words of the row: (neurons on `host` + 31) / 32
     __device__ __forceinline__ void mark(const Res& r) const {
         uint32_t h, l;
         set_lookup(S, nS, r.src, h, l);
@@ -380,9 +381,52 @@ __global__ __launch_bounds__(NT) void k_gen(Rule rule, Sink sink, uint64_t n_ite
     }
 }
 
+// Regeneration for the point-to-point lists with the bit row in LDS: every
+// workgroup marks the draws of a long item range in its own copy of the row
+// and ORs the words it set into the global row once, so the global atomics
+// scale with workgroups x row words instead of with draws (most draws hit
+// sources already marked).
+constexpr uint32_t MARK_LDS_WORDS = 16384;   // rows up to 2^19 neurons (64 KB of LDS)
+
+template <class Rule>
+__global__ __launch_bounds__(NT) void k_gen_mark_lds(Rule rule, MarkSink sink, uint64_t n_items,
+                                                     uint64_t per_block) {
+    extern __shared__ uint32_t row[];
+    for (uint32_t w = threadIdx.x; w < sink.words; w += NT) row[w] = 0;
+    __syncthreads();
+    const uint64_t lo = (uint64_t)blockIdx.x * per_block;
+    const uint64_t hi = lo + per_block < n_items ? lo + per_block : n_items;
+#pragma unroll 1
+    for (uint64_t item = lo + threadIdx.x; item < hi; item += NT) {
+        Res r[Rule::R];
+        const int n = rule.eval(item, r);
+        for (int k = 0; k < n; ++k) {
+            uint32_t h, l;
+            set_lookup(sink.S, sink.nS, r[k].src, h, l);
+            if (h == sink.host) atomicOr(&row[l >> 5], 1u << (l & 31));
+        }
+    }
+    __syncthreads();
+    for (uint32_t w = threadIdx.x; w < sink.words; w += NT)
+        if (row[w]) atomicOr(sink.bits + w, row[w]);
+}
+
 template <class Rule, class Sink, int MODE>
 void launch_gen(Ctx& c, const char* name, const Rule& rule, const Sink& sink, uint64_t n_items,
                 uint32_t* tile_counts, const uint64_t* tile_offsets, uint64_t limit) {
+    if constexpr (MODE == MARK) {
+        if (c.mark_in_lds && sink.words <= MARK_LDS_WORDS && n_items) {
+            // about 2048 workgroups, each over at least 8192 items
+            const uint64_t per_block = std::max<uint64_t>(8192, (n_items + 2047) / 2048);
+            const uint64_t blocks = (n_items + per_block - 1) / per_block;
+            tstart(c, "prep_mark");
+            hipLaunchKernelGGL(k_gen_mark_lds<Rule>, dim3((unsigned)blocks), dim3(NT), sink.words * 4, c.stream, rule,
+                               sink, n_items, per_block);
+            tstop(c);
+            HIPCHK(hipGetLastError());
+            return;
+        }
+    }
     const uint64_t tiles = (n_items + TILE - 1) / TILE;
     for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
         const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
@@ -950,7 +994,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
     const bool mark = mode == Out::MARK;
     WriteSink ws{};
     MarkSink ms{};
-    if (mark) ms = MarkSink{cl.dS, (uint32_t)cl.S.seg.size(), c.P_local, mark_bits};
+    if (mark) ms = MarkSink{cl.dS, (uint32_t)cl.S.seg.size(), c.P_local, mark_bits, (c.M[c.P_local] + 31) / 32};
     // room for the n connections; returns the sink writing them
     auto reserve = [&](uint64_t n) -> WriteSink* {
         uint64_t base = c.n_gen;

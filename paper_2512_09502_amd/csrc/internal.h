@@ -210,6 +210,7 @@ struct Ctx {
     void* lookback = nullptr;            // per lane
     size_t lookback_bytes = 0;           // per lane
     int sort_variant = 0;                // tile shape of the radix passes (tunable)
+    bool mark_in_lds = true;             // regeneration marks bit rows in LDS when they fit (tunable)
     int number_variant = 10;             // tile shape of the image-numbering pass (tunable; 1024 x 10, payload early)
     int sort_mode = 0;                   // 0: onesweep (look-back), 1: reduce-then-scan (tunable)
     bool sort_pinned = false;            // set by hand: the autotuner's process-wide choice is not used

@@ -170,6 +170,24 @@ def test_remote_rules_all_hosts(rule):
         compare_all(s, pl)
 
 
+@pytest.mark.parametrize("in_lds", [1, 0])
+def test_mark_rows(in_lds):
+    # point-to-point regeneration on the source host, with the bit rows marked
+    # in LDS (one OR per word and workgroup) or with a global atomic per draw
+    b = W._Builder(3, seed=9)
+    src = b.create(0, 20000)
+    tgt = b.create(1, 3000)
+    other = b.create(2, 500)
+    for rule in ("fixed_indegree", "fixed_outdegree", "fixed_total_number"):
+        n = {"fixed_indegree": 40, "fixed_outdegree": 7, "fixed_total_number": 150000}[rule]
+        conn = {"rule": rule, "n": n, "autapses": True, "multapses": True}
+        b.connect([src], [tgt] if rule != "fixed_outdegree" else [tgt, other], conn, SYN_N, -1)
+    s = b.script(f"mark_rows_{in_lds}")
+    s["tune"] = {"mark_in_lds": in_lds}
+    for pl in (0, 1, 2):
+        compare_all(s, pl)
+
+
 @pytest.mark.parametrize("k", [9, 50])
 def test_remote_outdegree_without_multapses(k):
     # counting, writing and point-to-point marking through both samplers (small and large K)
