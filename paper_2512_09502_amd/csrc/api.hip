@@ -759,6 +759,8 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
         init_ring(c->ring, 16u << 20);
         c->dl_pin_bytes = 64u << 10;
         HIPCHK(hipHostMalloc((void**)&c->dl_pin, c->dl_pin_bytes, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&c->tot_pin, 2 * sizeof(uint64_t), hipHostMallocMapped));
+        HIPCHK(hipHostGetDevicePointer((void**)&c->tot_pin_dev, c->tot_pin, 0));
         c->d_status = dalloc_n<uint32_t>(*c, 1);
         HIPCHK(hipMemsetAsync(c->d_status, 0, 4, c->stream));
         sync(*c);
@@ -795,6 +797,7 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     if (c->conn_last) (void)hipEventDestroy(c->conn_last);
     free_ring(c->ring);
     if (c->dl_pin) (void)hipHostFree(c->dl_pin);
+    if (c->tot_pin) (void)hipHostFree(c->tot_pin);
     for (auto e : c->batch_done) (void)hipEventDestroy(e);
     if (c->fused_exec) (void)hipGraphExecDestroy(c->fused_exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);

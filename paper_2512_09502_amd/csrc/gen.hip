@@ -1139,12 +1139,12 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 if (!cl.multapses && C <= HASH_MAX_WINDOW) {
                     uint64_t H = 1024;
                     while (H < C + C / 2) H <<= 1;
-                    uint64_t* tab = dalloc_n<uint64_t>(c, H);
-                    uint32_t* minidx = dalloc_n<uint32_t>(c, H);
+                    // keys (HASH_EMPTY) and earliest candidates (none yet) in one block, cleared by one fill
+                    uint64_t* tab = dalloc_n<uint64_t>(c, H + H / 2);
+                    uint32_t* minidx = reinterpret_cast<uint32_t*>(tab + H);
                     first = dalloc_n<uint8_t>(c, C);
-                    temps.insert(temps.end(), {tab, minidx, first});
-                    HIPCHK(hipMemsetAsync(tab, 0xff, H * 8, c.stream));        // HASH_EMPTY
-                    HIPCHK(hipMemsetAsync(minidx, 0xff, H * 4, c.stream));     // no candidate yet
+                    temps.insert(temps.end(), {tab, first});
+                    HIPCHK(hipMemsetAsync(tab, 0xff, H * 12, c.stream));
                     tstart(c, "gen_total_first");
                     hipLaunchKernelGGL(k_first_insert, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream, r, C,
                                        (uint32_t)nt, tab, minidx, H - 1);
@@ -1153,8 +1153,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                     tstop(c);
                     HIPCHK(hipGetLastError());
                     dfree(c, tab);
-                    dfree(c, minidx);
-                    temps.resize(temps.size() - 3);
+                    temps.resize(temps.size() - 2);
                     temps.push_back(first);
                 } else if (!cl.multapses) {
                     uint64_t* k0 = dalloc_n<uint64_t>(c, C);

@@ -228,6 +228,10 @@ struct Ctx {
     StageRing ring;                      // per lane
     // pinned landing area of small device-to-host reads (each read waits for its copy)
     char* dl_pin = nullptr;
+    // scan totals read back without a copy: two mapped pinned words (main
+    // stream, counting stream), written by the scan's last kernel
+    uint64_t* tot_pin = nullptr;
+    uint64_t* tot_pin_dev = nullptr;
     size_t dl_pin_bytes = 0;
     // delay tables by distribution (bit patterns of mean, sd, lo)
     std::map<std::array<uint64_t, 3>, std::shared_ptr<const DelayTable>> delay_tables;

@@ -41,9 +41,11 @@ __global__ __launch_bounds__(SNT) void k_reduce(L load, uint64_t n, uint64_t* pa
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// Each thread owns SIPT consecutive elements; out[n] receives the total.
+// Each thread owns SIPT consecutive elements; out[n] receives the total (and
+// *total_out, when given: a mapped host word the caller reads after a sync).
 template <class L>
-__global__ __launch_bounds__(SNT) void k_scan(L load, uint64_t n, const uint64_t* block_off, uint64_t* out) {
+__global__ __launch_bounds__(SNT) void k_scan(L load, uint64_t n, const uint64_t* block_off, uint64_t* out,
+                                              uint64_t* total_out) {
     __shared__ uint64_t scratch[SNT / 64];
     const uint64_t base = (uint64_t)blockIdx.x * STILE + (uint64_t)threadIdx.x * SIPT;
     uint64_t v[SIPT];
@@ -61,16 +63,20 @@ __global__ __launch_bounds__(SNT) void k_scan(L load, uint64_t n, const uint64_t
         const uint64_t i = base + k;
         if (i < n) out[i] = run;
         run += v[k];
-        if (i + 1 == n) out[n] = run;
+        if (i + 1 == n) {
+            out[n] = run;
+            if (total_out) *total_out = run;
+        }
     }
 }
 
 template <class L>
-void scan_impl(Ctx& c, L load, uint64_t n, uint64_t* out) {
+void scan_impl(Ctx& c, L load, uint64_t n, uint64_t* out, uint64_t* total_out = nullptr) {
     const uint64_t nb = (n + STILE - 1) / STILE;
     if (nb <= 1) {
         tstart(c, "scan");
-        hipLaunchKernelGGL(k_scan<L>, dim3(1), dim3(SNT), 0, c.stream, load, n, (const uint64_t*)nullptr, out);
+        hipLaunchKernelGGL(k_scan<L>, dim3(1), dim3(SNT), 0, c.stream, load, n, (const uint64_t*)nullptr, out,
+                           total_out);
         tstop(c);
         HIPCHK(hipGetLastError());
         return;
@@ -85,7 +91,8 @@ void scan_impl(Ctx& c, L load, uint64_t n, uint64_t* out) {
         HIPCHK(hipGetLastError());
         scan_impl(c, LoadU64{partial}, nb, off);
         tstart(c, "scan");
-        hipLaunchKernelGGL(k_scan<L>, dim3((unsigned)nb), dim3(SNT), 0, c.stream, load, n, (const uint64_t*)off, out);
+        hipLaunchKernelGGL(k_scan<L>, dim3((unsigned)nb), dim3(SNT), 0, c.stream, load, n, (const uint64_t*)off, out,
+                           total_out);
         tstop(c);
         HIPCHK(hipGetLastError());
     } catch (...) {
@@ -105,10 +112,17 @@ uint64_t scan_any(Ctx& c, L load, uint64_t* out, uint64_t n, bool want_total) {
         if (want_total) sync(c);
         return 0;
     }
-    scan_impl(c, load, n, out);
-    uint64_t total = 0;
-    if (want_total) download(c, &total, out + n, 8);
-    return total;
+    if (!want_total || !c.tot_pin) {
+        scan_impl(c, load, n, out);
+        uint64_t total = 0;
+        if (want_total) download(c, &total, out + n, 8);
+        return total;
+    }
+    // the total lands in mapped host memory: no copy between the scan and the read
+    const int slot = c.stream == c.count_stream ? 1 : 0;
+    scan_impl(c, load, n, out, c.tot_pin_dev + slot);
+    sync(c);
+    return *reinterpret_cast<volatile uint64_t*>(c.tot_pin + slot);
 }
 
 }  // namespace
