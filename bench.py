@@ -244,7 +244,9 @@ def exchange(args):
 def served(args):
     """Served construction of a stream of uneven Connect requests against a
     resident budget: throughput with all requests arriving at once, per call
-    and in fused batches, then per-request latency under open-loop Poisson
+    and in batches (submitted together, one device wait per batch for the
+    admission counts, generated in fused launches), then per-request latency
+    under open-loop Poisson
     arrivals at half the measured batched capacity; each run ends with the
     final sort and first-index array (Prepare)."""
     import numpy as np
@@ -273,22 +275,27 @@ def served(args):
         t0 = time.perf_counter()
         t_host = 0.0
         admitted = 0
-        for k, op in enumerate(reqs):
+        if mode == "batched":
+            # batches of requests submitted together (one device wait for their counts), then flushed
+            for k0 in range(0, len(reqs), args.batch):
+                th = time.perf_counter()
+                res = net.submit_many([op[1:] for op in reqs[k0:k0 + args.batch]])
+                t_host += time.perf_counter() - th
+                for status, _ in res:
+                    if status not in (0, -3):
+                        raise snnc.SnncError(status, "request failed")
+                    admitted += status == 0
+                net.flush()
+        for k, op in enumerate(reqs if mode == "per_call" else []):
             _, src, tgt, conn, syn, alpha = op
             th = time.perf_counter()
             try:
-                if mode == "per_call":
-                    net.connect(src, tgt, conn, syn, alpha)
-                else:
-                    net.submit(src, tgt, conn, syn, alpha)
+                net.connect(src, tgt, conn, syn, alpha)
                 admitted += 1
             except snnc.SnncError as e:
                 if e.code != -3:
                     raise
             t_host += time.perf_counter() - th
-            if mode == "batched" and (k + 1) % args.batch == 0:
-                net.flush()
-        net.flush() if mode == "batched" else None
         net.sync()
         t_gen = time.perf_counter() - t0
         net.prepare()

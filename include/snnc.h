@@ -232,6 +232,24 @@ snnc_status snnc_set_resident_budget(snnc_ctx* ctx, uint64_t bytes);
 snnc_status snnc_submit(snnc_ctx* ctx, const snnc_nodeset* src, const snnc_nodeset* tgt,
                         const snnc_conn_spec* conn, const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out);
 
+/* Submit n requests at once (array i of each argument is request i): the
+ * same as n snnc_submit calls in order -- same admissions, call ids and
+ * network -- except that the host waits for the device once for all counts
+ * that need it instead of once per such request.  Those counts are queued
+ * assuming every earlier request of the batch is admitted (consecutive call
+ * ids); a request whose id moves because an earlier one was rejected, or
+ * whose fixed-total-number window held too few valid candidates, is counted
+ * again at its admission.  status_out[i] receives request i's status
+ * (SNNC_OK, SNNC_EBUDGET, or the SNNC_EINVAL / SNNC_EUNSUPPORTED of an
+ * invalid request, which then gets no call id) and call_ids_out[i] its call
+ * id (UINT32_MAX when not admitted); both are caller arrays of n entries.
+ * The call itself returns SNNC_EINVAL for null arrays with n > 0,
+ * SNNC_ESTATE after prepare, and SNNC_ENOMEM / SNNC_EDEVICE, after which the
+ * requests not yet admitted are dropped. */
+snnc_status snnc_submit_many(snnc_ctx* ctx, uint32_t n, const snnc_nodeset* src, const snnc_nodeset* tgt,
+                             const snnc_conn_spec* conn, const snnc_syn_spec* syn, const int32_t* alpha,
+                             snnc_status* status_out, uint32_t* call_ids_out);
+
 /* Launch every submitted, not yet generated request as one batch: requests
  * whose connections are one per element (fixed in-degree and out-degree with
  * multapses, fixed total number with autapses and multapses, one-to-one

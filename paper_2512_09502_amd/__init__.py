@@ -84,7 +84,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_create", "snnc_connect",
            "snnc_reserve", "snnc_prepare", "snnc_get_array", "snnc_copy_array", "snnc_copy_range",
            "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks",
-           "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_flush", "snnc_poll",
+           "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_submit_many", "snnc_flush", "snnc_poll",
            "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver", "snnc_bern_table",
            "snnc_connect_assigned", "snnc_set_memory_level", "snnc_array_on_host"]
 
@@ -131,6 +131,7 @@ def lib():
         L.snnc_submit.argtypes = L.snnc_connect.argtypes
         L.snnc_connect_assigned.argtypes = [vp, ctypes.POINTER(NodeSet), ctypes.POINTER(NodeSet), vp, vp, u64,
                                             ctypes.POINTER(SynSpec), i32, ctypes.POINTER(u32)]
+        L.snnc_submit_many.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp, vp]
         L.snnc_flush.argtypes = [vp]
         L.snnc_poll.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_int32)]
         L.snnc_autotune_sort.argtypes = [vp, u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -306,6 +307,42 @@ class Network:
     def submit(self, src, tgt, conn, syn, alpha: int = -1) -> int:
         """Served mode: admit and reserve now, generate at the next flush()."""
         return self._connect_like("snnc_submit", src, tgt, conn, syn, alpha)
+
+    def submit_many(self, requests, alpha: int | None = None):
+        """Served mode, several requests with one device wait for their counts:
+        requests is a list of (src, tgt, conn, syn) or (src, tgt, conn, syn,
+        alpha).  Returns one (status, call_id) per request: status 0 when
+        admitted, else the request's error code (-3 over budget), call_id
+        None when not admitted."""
+        n = len(requests)
+        nseg = sum(len(r[0]) + len(r[1]) for r in requests)
+        segs = (Segment * max(1, nseg))()
+        S = (NodeSet * max(1, n))()
+        T = (NodeSet * max(1, n))()
+        C = (ConnSpec * max(1, n))()
+        Y = (SynSpec * max(1, n))()
+        A = (ctypes.c_int32 * max(1, n))()
+        base = ctypes.addressof(segs)
+        k = 0
+        try:
+            for i, r in enumerate(requests):
+                src, tgt, conn, syn = r[:4]
+                for dst, group in ((S, src), (T, tgt)):
+                    dst[i].seg = ctypes.cast(base + 12 * k, ctypes.POINTER(Segment))
+                    dst[i].n_seg = len(group)
+                    for h, f, m in group:
+                        segs[k].host, segs[k].first, segs[k].n = int(h), int(f), int(m)
+                        k += 1
+                C[i] = ConnSpec(RULES[conn["rule"]], int(conn.get("autapses", True)), int(conn.get("multapses", True)),
+                                0, int(conn.get("n", 0)), float(conn.get("p", 0.0)))
+                Y[i] = SynSpec(_dist(syn.get("weight")), _dist(syn.get("delay")), int(syn.get("port", 0)), 0)
+                A[i] = int(r[4] if len(r) > 4 else (-1 if alpha is None else alpha))
+        except (OverflowError, TypeError, ValueError) as err:
+            raise SnncError(-1, f"request argument out of range: {err}") from None
+        st = (ctypes.c_int32 * max(1, n))()
+        ids = (ctypes.c_uint32 * max(1, n))()
+        self._check(lib().snnc_submit_many(self._h, n, S, T, C, Y, A, st, ids))
+        return [(int(st[i]), int(ids[i]) if st[i] == 0 else None) for i in range(n)]
 
     def flush(self):
         self._check(lib().snnc_flush(self._h))

@@ -687,6 +687,190 @@ static void submit_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt
     *call_id_out = c.calls.back().id;
 }
 
+// Several requests with one wait for the device counts: as submit_impl for
+// each request in order, but the counts that need the device are queued on
+// the counting lane for all requests first, their totals read after one
+// wait, and then the requests are admitted in order.  The counts depend on
+// the call id, so they are drawn with the ids the requests get if the
+// predicted admissions hold (exact host counts, expected device counts
+// against the budget); where an id turns out different, the rest of the
+// batch is counted again from there with the ids now known.
+static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const snnc_nodeset* tgt,
+                             const snnc_conn_spec* conn, const snnc_syn_spec* syn, const int32_t* alpha,
+                             snnc_status* status, uint32_t* ids) {
+    if (c.prepared) raise(SNNC_ESTATE, "submit after prepare");
+    if (n && (!src || !tgt || !conn || !syn || !alpha || !status || !ids)) raise(SNNC_EINVAL, "null argument");
+    if (c.defer_cap < n) {
+        if (c.defer_pin) {
+            if (c.count_stream) HIPCHK(hipStreamSynchronize(c.count_stream));   // no count still writes to it
+            HIPCHK(hipHostFree(c.defer_pin));
+        }
+        c.defer_pin = c.defer_pin_dev = nullptr;
+        c.defer_cap = 0;
+        const size_t cap = std::max<size_t>(n, 256);
+        HIPCHK(hipHostMalloc((void**)&c.defer_pin, cap * 2 * sizeof(uint64_t), hipHostMallocMapped));
+        HIPCHK(hipHostGetDevicePointer((void**)&c.defer_pin_dev, c.defer_pin, 0));
+        c.defer_cap = cap;
+    }
+    std::vector<Call> cls(n);
+    std::vector<uint64_t> count(n, 0);
+    std::vector<char> ok(n, 0), on_device(n, 0);
+    auto drop = [&](Call& cl) {
+        dfree(c, cl.meta);
+        dfree(c, cl.pairs);
+        release_pre(c, cl);
+        cl.meta = nullptr;
+        cl.pairs = nullptr;
+    };
+    auto fatal = [](const Error& e) {
+        return e.code == SNNC_EDEVICE || e.code == SNNC_ENOMEM || e.code == SNNC_ESTATE;
+    };
+    auto expected = [&](const Call& cl) -> uint64_t {   // expected local count of a device-counted request
+        uint64_t on_host = 0;
+        for (auto& g : cl.T.seg) if (g.host == c.P_local) on_host += g.n;
+        const double share = cl.T.total ? (double)on_host / (double)cl.T.total : 0.0;
+        switch (cl.rule) {
+        case SNNC_PAIRWISE_BERNOULLI: return (uint64_t)(cl.p * (double)cl.S.total * (double)on_host);
+        case SNNC_FIXED_TOTAL_NUMBER: return (uint64_t)((double)cl.n * share);
+        case SNNC_FIXED_OUTDEGREE: return (uint64_t)((double)cl.S.total * (double)cl.n * share);
+        case SNNC_ASSIGNED_NODES: {
+            const auto it = cl.pairs_on.find(c.P_local);
+            return it == cl.pairs_on.end() ? 0 : it->second;
+        }
+        default: return 0;
+        }
+    };
+    // 1. records, tables and host counts (on the counting lane; the caller's
+    // stream waits for it at the end of each counting section)
+    {
+        CountScope lane(c);
+        for (uint32_t i = 0; i < n; ++i) {
+            status[i] = SNNC_OK;
+            ids[i] = UINT32_MAX;
+            Call& cl = cls[i];
+            try {
+                cl = make_call_host(c, &src[i], &tgt[i], &conn[i], &syn[i], alpha[i]);
+                if (needs_meta(c, cl)) {
+                    upload_meta(c, cl);
+                    if (count_on_device(c, cl)) on_device[i] = 1;
+                    else count[i] = gen_count_local(c, cl);   // no draws: independent of the call id
+                }
+                ok[i] = 1;
+            } catch (const Error& e) {
+                drop(cl);
+                if (fatal(e)) {
+                    for (uint32_t k = 0; k < i; ++k) drop(cls[k]);
+                    throw;
+                }
+                status[i] = e.code;
+            }
+        }
+    }
+    uint32_t start = 0;
+    try {
+        while (start < n) {
+            // 2. device counts of requests start.. with their predicted ids, then one wait
+            bool queued = false;
+            {
+                CountScope lane(c);
+                uint32_t next = (uint32_t)c.calls.size();
+                uint64_t predicted = c.resident_bytes;
+                for (uint32_t i = start; i < n; ++i) {
+                    if (!ok[i]) continue;
+                    Call& cl = cls[i];
+                    cl.id = next;
+                    uint64_t est = count[i];
+                    if (on_device[i]) {
+                        release_pre(c, cl);
+                        cl.deferred = 0;
+                        c.defer_slot = c.defer_pin_dev + 2 * i;
+                        try {
+                            count[i] = gen_count_local(c, cl);
+                        } catch (const Error& e) {
+                            c.defer_slot = nullptr;
+                            if (fatal(e)) throw;
+                            drop(cl);
+                            ok[i] = 0;
+                            status[i] = e.code;
+                            continue;
+                        }
+                        c.defer_slot = nullptr;
+                        if (cl.deferred) {
+                            queued = true;
+                            est = expected(cl);
+                        } else {
+                            est = count[i];
+                        }
+                    }
+                    const uint64_t cost = resident_cost(cl, est);
+                    if (!c.resident_budget || predicted + cost <= c.resident_budget) {
+                        predicted += cost;
+                        ++next;
+                    }
+                }
+            }
+            if (queued) HIPCHK(hipStreamSynchronize(c.count_stream));
+            // 3. admission in order, up to the first request whose id moved
+            uint32_t restart = n;
+            for (uint32_t i = start; i < n; ++i) {
+                if (!ok[i]) continue;
+                Call& cl = cls[i];
+                const uint32_t id = (uint32_t)c.calls.size();
+                if (cl.id != id) {
+                    if (on_device[i]) {   // its draws used another id: count again from here
+                        restart = i;
+                        break;
+                    }
+                    cl.id = id;
+                }
+                try {
+                    if (cl.deferred) {
+                        const volatile uint64_t* w = c.defer_pin + 2 * i;
+                        bool again = false;
+                        if (cl.deferred == 1) count[i] = w[0];
+                        else if (w[0] >= cl.n) count[i] = cl.deferred == 2 ? cl.n : w[1];
+                        else again = true;   // too few valid candidates in the window
+                        cl.deferred = 0;
+                        if (again) {
+                            release_pre(c, cl);
+                            CountScope lane(c);
+                            count[i] = gen_count_local(c, cl);
+                        } else {
+                            cl.pre_count = count[i];
+                        }
+                    }
+                    admit(c, cl, count[i]);
+                    grow_gen(c, c.n_gen + count[i]);
+                } catch (const Error& e) {
+                    if (fatal(e)) throw;
+                    drop(cl);
+                    ok[i] = 0;
+                    status[i] = e.code;
+                    continue;
+                }
+                if (!c.conn_started) {
+                    HIPCHK(hipEventRecord(c.conn_first, c.stream));
+                    c.conn_started = true;
+                }
+                cl.gen_begin = c.n_gen;
+                cl.gen_count = count[i];
+                c.n_gen += cl.gen_count;
+                c.resident_bytes += resident_cost(cl, cl.gen_count);
+                c.queued.push_back(cl.id);
+                ids[i] = cl.id;
+                ok[i] = 0;   // moved into the context
+                c.calls.push_back(std::move(cl));
+            }
+            start = restart;
+        }
+    } catch (...) {
+        for (uint32_t k = 0; k < n; ++k)
+            if (ok[k]) drop(cls[k]);
+        c.defer_slot = nullptr;
+        throw;
+    }
+}
+
 void flush_pending(Ctx& c) {
     if (c.queued.empty()) return;
     hipEvent_t ev;
@@ -798,6 +982,7 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     free_ring(c->ring);
     if (c->dl_pin) (void)hipHostFree(c->dl_pin);
     if (c->tot_pin) (void)hipHostFree(c->tot_pin);
+    if (c->defer_pin) (void)hipHostFree(c->defer_pin);
     for (auto e : c->batch_done) (void)hipEventDestroy(e);
     if (c->fused_exec) (void)hipGraphExecDestroy(c->fused_exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
@@ -863,6 +1048,13 @@ snnc_status snnc_submit(snnc_ctx* c, const snnc_nodeset* src, const snnc_nodeset
                         const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out) {
     if (!c) return SNNC_EINVAL;
     return guarded(c, [&] { submit_impl(*c, src, tgt, conn, syn, alpha, call_id_out); });
+}
+
+snnc_status snnc_submit_many(snnc_ctx* c, uint32_t n, const snnc_nodeset* src, const snnc_nodeset* tgt,
+                             const snnc_conn_spec* conn, const snnc_syn_spec* syn, const int32_t* alpha,
+                             snnc_status* status_out, uint32_t* call_ids_out) {
+    if (!c) return SNNC_EINVAL;
+    return guarded(c, [&] { submit_many_impl(*c, n, src, tgt, conn, syn, alpha, status_out, call_ids_out); });
 }
 
 snnc_status snnc_flush(snnc_ctx* c) {

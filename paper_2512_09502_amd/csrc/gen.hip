@@ -1187,6 +1187,28 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 uint64_t* voff = dalloc_n<uint64_t>(c, tiles + 1);
                 temps.push_back(voff);
                 launch_total_dist<WriteSink, CNT_VALID, true>(c, rr, host, ws, C, cnt, nullptr, nullptr, 0);
+                if (mode == Out::COUNT && c.defer_slot) {
+                    // batched admission: valid candidates of this window (and the kept ones) go to
+                    // the caller's mapped words; a window with fewer than N valid candidates is
+                    // counted again, without deferral, when the batch is admitted
+                    scan_u32_u64_to(c, cnt, voff, tiles, c.defer_slot);
+                    uint64_t* koff = nullptr;
+                    if (!all_local) {
+                        koff = dalloc_n<uint64_t>(c, tiles + 1);
+                        launch_total_dist<WriteSink, CNT_KEEP, false>(c, rr, host, ws, C, cnt, voff, nullptr, N);
+                        scan_u32_u64_to(c, cnt, koff, tiles, c.defer_slot + 1);
+                    }
+                    release_pre(c, cl);
+                    cl.pre_off = voff;
+                    cl.pre_koff = koff;
+                    cl.pre_first = first;
+                    cl.pre_window = C;
+                    cl.deferred = all_local ? 2 : 3;
+                    temps.erase(std::remove_if(temps.begin(), temps.end(),
+                                               [&](void* q) { return q == voff || q == first; }),
+                                temps.end());
+                    break;
+                }
                 const uint64_t valid = scan_u32_u64(c, cnt, voff, tiles, true);
                 if (valid >= N) {
                     uint64_t kept = N;
@@ -1266,6 +1288,15 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 temps.push_back(cnt);
                 off = dalloc_n<uint64_t>(c, tiles + 1);
                 launch_bern<WriteSink, COUNT>(c, r, ws, items, cnt, nullptr);
+                if (mode == Out::COUNT && c.defer_slot) {
+                    // batched admission: the total goes to the caller's mapped word, read after one
+                    // wait for the whole batch; the tile offsets stay with the call
+                    scan_u32_u64_to(c, cnt, off, tiles, c.defer_slot);
+                    dfree(c, cl.pre_off);
+                    cl.pre_off = off;
+                    cl.deferred = 1;
+                    break;
+                }
                 result = scan_u32_u64(c, cnt, off, tiles, true);
                 if (mode == Out::COUNT) {
                     dfree(c, cl.pre_off);

@@ -107,6 +107,10 @@ struct Call {
     uint64_t* pre_koff = nullptr;
     uint8_t* pre_first = nullptr;
     uint64_t pre_count = 0, pre_window = 0;
+    // batched admission: the count was queued and its total is read later
+    // (1 Bernoulli; 2 fixed total number, all targets local; 3 the same with
+    // targets elsewhere, kept count in the second word)
+    uint8_t deferred = 0;
     // assigned nodes: the caller's pair arrays during the call, then the
     // device copy (n source positions, then n target positions) and the
     // number of pairs per target host
@@ -232,6 +236,12 @@ struct Ctx {
     // stream, counting stream), written by the scan's last kernel
     uint64_t* tot_pin = nullptr;
     uint64_t* tot_pin_dev = nullptr;
+    // batched admission: where the counting sections write their totals
+    // (null: counts are read back at once); mapped pinned words, two per request
+    uint64_t* defer_slot = nullptr;
+    uint64_t* defer_pin = nullptr;
+    uint64_t* defer_pin_dev = nullptr;
+    size_t defer_cap = 0;                // requests the pinned words hold
     size_t dl_pin_bytes = 0;
     // delay tables by distribution (bit patterns of mean, sd, lo)
     std::map<std::array<uint64_t, 3>, std::shared_ptr<const DelayTable>> delay_tables;
@@ -340,6 +350,8 @@ bool set_lookup_host(const HostSet& s, uint64_t ord, uint32_t& host, uint32_t& l
 // out[i] = sum_{k<i} in[i] for i <= n (out has n + 1 entries); returns total
 // after synchronising when want_total.
 uint64_t scan_u32_u64(Ctx& c, const uint32_t* in, uint64_t* out, uint64_t n, bool want_total);
+// the same without a wait: the total is written to total_dev (a mapped host word)
+void scan_u32_u64_to(Ctx& c, const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* total_dev);
 // the same over popcounts of 32-bit words
 uint64_t scan_popc_u64(Ctx& c, const uint32_t* words, uint64_t* out, uint64_t n_words, bool want_total);
 uint64_t scan_u64_u64(Ctx& c, const uint64_t* in, uint64_t* out, uint64_t n, bool want_total);

@@ -70,6 +70,12 @@ __global__ __launch_bounds__(SNT) void k_scan(L load, uint64_t n, const uint64_t
     }
 }
 
+// the total of an empty scan: out[0] and the caller's word are zero
+__global__ void k_put_u64(uint64_t* out, uint64_t* total_out) {
+    out[0] = 0;
+    *total_out = 0;
+}
+
 template <class L>
 void scan_impl(Ctx& c, L load, uint64_t n, uint64_t* out, uint64_t* total_out = nullptr) {
     const uint64_t nb = (n + STILE - 1) / STILE;
@@ -129,6 +135,15 @@ uint64_t scan_any(Ctx& c, L load, uint64_t* out, uint64_t n, bool want_total) {
 
 uint64_t scan_u32_u64(Ctx& c, const uint32_t* in, uint64_t* out, uint64_t n, bool want_total) {
     return scan_any(c, LoadU32{in}, out, n, want_total);
+}
+
+void scan_u32_u64_to(Ctx& c, const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* total_dev) {
+    if (n == 0) {
+        hipLaunchKernelGGL(k_put_u64, dim3(1), dim3(1), 0, c.stream, out, total_dev);
+        HIPCHK(hipGetLastError());
+        return;
+    }
+    scan_impl(c, LoadU32{in}, n, out, total_dev);
 }
 
 uint64_t scan_popc_u64(Ctx& c, const uint32_t* words, uint64_t* out, uint64_t n_words, bool want_total) {

@@ -28,6 +28,33 @@ def _build(script, mode, budget, batch=17, fuse=True, reserve=0):
     if reserve:
         net.reserve(reserve)
     rejected, submitted = [], 0
+    if mode.startswith("many"):   # "many<chunk>": snnc_submit_many over chunks of the request stream
+        chunk = int(mode[4:])
+        pending = []
+
+        def submit_chunk():
+            res = net.submit_many([req for _, req in pending])
+            for (k, _), (status, cid) in zip(pending, res):
+                if status != 0:
+                    rejected.append((k, status))
+                    assert cid is None
+            pending.clear()
+            net.flush()
+        for k, op in enumerate(script["ops"]):
+            if op[0] == "create":
+                net.create(op[1], op[2])
+                continue
+            pending.append((k, op[1:]))
+            if len(pending) == chunk:
+                submit_chunk()
+        submit_chunk()
+        net.sync()
+        gen = {k: net.array(k) for k in GEN_ARRAYS}
+        net.prepare()
+        out = {k: net.array(k) for k in PREP_ARRAYS}
+        out.update(gen)
+        net.close()
+        return out, rejected
     for k, op in enumerate(script["ops"]):
         if op[0] == "create":
             net.create(op[1], op[2])
@@ -74,6 +101,31 @@ def test_batched_equals_per_call_under_budget(fuse):
     ref = oracle.run_script(kept, 0)
     for k in GEN_ARRAYS + PREP_ARRAYS:
         compare(k, b[k], ref.array(k), "served")
+
+
+@pytest.mark.parametrize("chunk", [1, 13, 200])
+def test_submit_many_equals_submit(chunk):
+    """Batched submission (one device wait per chunk for the counts) admits
+    the same requests, assigns the same call ids and builds the same network
+    as one submit per request, with requests rejected by the budget and
+    invalid ones inside the chunks (so later requests' assumed ids move)."""
+    script = _served_script(n=160, seed=11)
+    # two invalid requests: a receptor port, and a degree above the candidates without multapses
+    ops = script["ops"]
+    firsts = [k for k, op in enumerate(ops) if op[0] == "connect"]
+    bad = dict(ops[firsts[5]][4]); bad["port"] = 1
+    ops.insert(firsts[5] + 1, ("connect", ops[firsts[5]][1], ops[firsts[5]][2], ops[firsts[5]][3], bad, -1))
+    src = ops[firsts[9]][1]
+    ops.insert(firsts[9] + 1, ("connect", src, src, {"rule": "fixed_indegree", "n": 10**6, "multapses": False},
+                               ops[firsts[9]][4], -1))
+    budget = 14 * 200000 + 50000
+    a, rej_a = _build(script, "batched", budget)
+    b, rej_b = _build(script, f"many{chunk}", budget)
+    log(f"submit_many chunk {chunk}: {len(rej_a)} rejected, {a['src'].size} connections")
+    assert rej_a == rej_b
+    assert any(code == -3 for _, code in rej_a) and any(code == -1 for _, code in rej_a)
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
 
 
 def test_counting_lane_with_large_requests():
