@@ -382,6 +382,8 @@ def main():
                     help="numbering,sources,xi: numbering 0 canonical / 1 call order; sources 0 used / "
                          "1 threshold / 2 all passed")
     ap.add_argument("--sort-variant", type=int, default=None, help="radix-pass tile shape (snnc_tune)")
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="snnc_tune setting for the build (repeatable), e.g. number_variant=10")
     ap.add_argument("--memory-level", type=int, default=None, choices=[0, 1, 2, 3],
                     help="GPU memory level: maps and image rows in host (0, 1) or device memory (2, 3)")
     ap.add_argument("--autotune", action="store_true",
@@ -407,6 +409,8 @@ def main():
     script = workload(args.workload, args.scale)
     if args.sort_variant is not None:
         script["sort_variant"] = args.sort_variant
+    if args.tune:
+        script["tune"] = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.tune}
     if args.map_policy:
         n_, s_, x_ = args.map_policy.split(",")
         script["map_policy"] = (int(n_), int(s_), float(x_))
@@ -498,7 +502,8 @@ def main():
         "config": {"workload": script["name"], "connections": n_conn, "calls": stats["n_calls"],
                    "neurons": stats["M_local"], "images": stats["n_images"], "key_bits": stats["key_bits"],
                    "sort_passes": stats["sort_passes"], "scale": args.scale,
-                   "map_policy": script.get("map_policy"), "memory_level": script.get("memory_level")},
+                   "map_policy": script.get("map_policy"), "memory_level": script.get("memory_level"),
+                   "tune": script.get("tune")},
         "sort_tuning": tuning,
         "step_ms": {"min": round(1e3 * min(times), 3), "median": round(1e3 * sorted(times)[len(times) // 2], 3)},
         # per-phase times of the scope table's steps, from the same breakdown
