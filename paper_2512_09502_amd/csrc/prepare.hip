@@ -384,16 +384,25 @@ __global__ void k_bounds_sorted(const uint64_t* img_key, uint64_t n_img, const u
     if (k < nk) img_base[k] = (int64_t)M_local + (int64_t)a;
 }
 
-// bit set of the image prefixes (sorted, distinct): the first image of every
-// 32-bit word writes the whole word, so no atomics are needed
+// Bit of every image prefix (bits is zero before).  The prefixes are sorted,
+// so the lanes of one word are contiguous in a wave: a segmented OR across
+// them leaves the word's bits in its last lane, which sets them with one
+// atomic (a word can continue in the next wave).
 __global__ void k_bits_sorted(const uint64_t* img_key, uint64_t n_img, uint32_t* bits) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_img) return;
-    const uint64_t w = img_key[j] >> 5;
-    if (j > 0 && (img_key[j - 1] >> 5) == w) return;
-    uint32_t word = 0;
-    for (uint64_t t = j; t < n_img && (img_key[t] >> 5) == w; ++t) word |= 1u << (img_key[t] & 31);
-    bits[w] = word;
+    const int lane = threadIdx.x & 63;
+    const bool valid = j < n_img;
+    const uint64_t key = valid ? img_key[j] : ~0ull;
+    const uint64_t w = key >> 5;
+    uint32_t acc = valid ? 1u << (key & 31) : 0u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t a = __shfl_up(acc, o, 64);
+        const uint64_t wo = __shfl_up(w, o, 64);
+        if (lane >= o && wo == w) acc |= a;
+    }
+    const uint64_t wn = __shfl_down(w, 1, 64);
+    if (valid && (lane == 63 || wn != w)) atomicOr(bits + w, acc);
 }
 
 // ---- images numbered before the sort (map policies other than the default)
