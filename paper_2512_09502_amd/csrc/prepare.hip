@@ -557,6 +557,19 @@ __global__ __launch_bounds__(PNT) void k_csr(const int32_t* src, uint64_t n, uin
     }
 }
 
+// The same by a binary search per row, for few rows against many connections:
+// a search reads about log2(n) positions where the pass above reads all n.
+__global__ void k_csr_search(const int32_t* src, uint64_t n, uint64_t n_rows, uint64_t* row_ptr) {
+    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n_rows) return;
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if ((int64_t)src[mid] < (int64_t)r) lo = mid + 1; else hi = mid;
+    }
+    row_ptr[r] = lo;
+}
+
 __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -986,8 +999,12 @@ void prepare_all(Ctx& c) {
                 const uint64_t n_rows = (uint64_t)M_local + n_img;
                 row_ptr = result<uint64_t>(c, SNNC_ROW_PTR, n_rows + 1);
                 tstart(c, "prep_csr");
-                hipLaunchKernelGGL(k_csr, dim3(grid_for(N / 4 + 1, 16384)), dim3(PNT), 0, c.stream, o_src, N, n_rows,
-                                   row_ptr);
+                if (n_rows * 64 < N)   // rows few against connections: search instead of reading every source
+                    hipLaunchKernelGGL(k_csr_search, dim3((unsigned)((n_rows + 1 + 255) / 256)), dim3(256), 0,
+                                       c.stream, o_src, N, n_rows, row_ptr);
+                else
+                    hipLaunchKernelGGL(k_csr, dim3(grid_for(N / 4 + 1, 16384)), dim3(PNT), 0, c.stream, o_src, N,
+                                       n_rows, row_ptr);
                 tstop(c);
                 HIPCHK(hipGetLastError());
             } else {
