@@ -1169,7 +1169,8 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                     HIPCHK(hipGetLastError());
                     uint32_t bits = 0;
                     while (bits < 64 && (ns * nt - 1) >> bits) ++bits;
-                    const int which = radix_sort(c, k0, v0, k1, v1, C, 0, bits, nullptr, nullptr);
+                    // every pass runs (no wait for the digit histograms): the pair keys are random
+                    const int which = radix_sort(c, k0, v0, k1, v1, C, 0, bits, nullptr, nullptr, false);
                     tstart(c, "gen_total_first");
                     hipLaunchKernelGGL(k_first_flags, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream,
                                        which ? k1 : k0, which ? v1 : v0, C, first);

@@ -369,9 +369,12 @@ struct FinalOut {
     uint32_t tgt_shift;   // key = src << tgt_shift | tgt << 16 | delay
     uint64_t tgt_mask;
 };
+// wait_for_plan: read the digit histograms back to skip passes whose digit is
+// the same for every key (a wait on the stream); false runs every pass
+// without waiting (the result is the same: such a pass keeps the order).
 int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, uint64_t n,
                uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist /* may be null */,
-               const FinalOut* final_out);
+               const FinalOut* final_out, bool wait_for_plan = true);
 // digit histograms for all passes of a sort (radix 256, D bits per pass)
 // digit histograms: entries per pass (buckets of digits up to 9 bits)
 constexpr int HIST_STRIDE = 512;

@@ -482,7 +482,8 @@ void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint
 }
 
 int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, uint64_t n,
-               uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist, const FinalOut* final_out) {
+               uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist, const FinalOut* final_out,
+               bool wait_for_plan) {
     const SortPlan plan = plan_sort(c, n, bit_hi > bit_lo ? bit_hi - bit_lo : 0);
     const uint32_t passes = plan.passes, dbits = plan.dbits;
     const int variant = plan.variant, mode = plan.mode;
@@ -511,7 +512,7 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
             hipLaunchKernelGGL(k_hist_scan, dim3(passes), dim3(HSTRIDE), 0, c.stream, hist, off);
             tstop(c);
             HIPCHK(hipGetLastError());
-            download(c, hh.data(), hist, hh.size() * 8);
+            if (wait_for_plan) download(c, hh.data(), hist, hh.size() * 8);
             // look-back table: tiles x buckets status words, zeroed once when (re)allocated
             const size_t need = (size_t)tiles * rb * 8;
             if (c.lookback_bytes < need) {
