@@ -406,12 +406,12 @@ typedef enum { SNNC_IMAGES_USED = 0, SNNC_IMAGES_THRESHOLD = 1, SNNC_IMAGES_ALL 
 snnc_status snnc_set_map_policy(snnc_ctx* ctx, int32_t numbering, int32_t image_sources, double xi);
 
 /* Tuning knobs of the context, by name.  "sort_variant": tile shape of the
- * radix-sort passes, 0 .. 10, as threads x keys per thread: 0 = 512x16 with
+ * radix-sort passes, 0 .. 13, as threads x keys per thread: 0 = 512x16 with
  * keys and payloads staged through LDS one after the other (70 KB, two
  * workgroups per compute unit; default), 1 = 256x8, 2 = 512x8, 3 = 512x16,
  * 4 = 256x16, 5 = 256x12, 6 = 1024x8, and staged in two phases like 0:
- * 7 = 1024x8, 8 = 512x8, 9 = 512x12, 10 = 256x16.  SNNC_EINVAL for an unknown
- * key or value. */
+ * 7 = 1024x8, 8 = 512x8, 9 = 512x12, 10 = 256x16, 11 = 512x11, 12 = 1024x16,
+ * 13 = 768x12.  SNNC_EINVAL for an unknown key or value. */
 snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
 /* "sort_mode": 0 = single-pass onesweep passes (decoupled look-back), 1 =
  * reduce-then-scan passes (per-tile digit counts, one scan, scatter).
@@ -420,7 +420,12 @@ snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
  * "map_path" (0: automatic, 1: number images before the sort even under the
  * default map policy, the path the other policies take) and "digit_bits"
  * (0: 9-bit digits, 512 buckets, when they save a pass and the tile has at
- * least 512 threads; 8 or 9: forced where the tile allows). */
+ * least 512 threads; 8 or 9: forced where the tile allows), "number_variant"
+ * (tile shape of the image-numbering pass after the sort, 0 .. 11; default 10 =
+ * 1024 threads x 10 items with the payload loaded before the look-back) and
+ * "mark_in_lds" (1, default: regeneration for the point-to-point lists marks
+ * its bit row in LDS when the row has at most 2^19 neurons; 0: a global
+ * atomic per draw).  Every setting gives the same arrays. */
 
 /* Autotuner of the source-major sort: times every pass algorithm and tile
  * shape (sort_mode x sort_variant) on n synthetic keys with `bits` sorted
