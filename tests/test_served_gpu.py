@@ -128,6 +128,32 @@ def test_submit_many_equals_submit(chunk):
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
 
 
+def test_submit_many_edges():
+    """An empty list, a list of only invalid requests, a request past the
+    budget between admitted ones, and the state check after prepare."""
+    import torch
+    torch.cuda.set_device(0)
+    net = snnc.Network(1, 0, 3, 0.1)
+    a = net.create(0, 1000)
+    syn = {"weight": {"kind": "const", "mean": 0.5}, "delay": {"kind": "const", "mean": 1.0}}
+    assert net.submit_many([]) == []
+    bad = ([a], [a], {"rule": "one_to_one"}, dict(syn, port=2))
+    assert net.submit_many([bad, bad]) == [(-1, None), (-1, None)]
+    net.set_resident_budget(14 * 60000 + 4096)
+    small = ([a], [a], {"rule": "pairwise_bernoulli", "p": 0.02}, syn)
+    big = ([a], [a], {"rule": "fixed_total_number", "n": 100000, "autapses": False}, syn)
+    res = net.submit_many([small, big, small])
+    assert [st for st, _ in res] == [0, -3, 0] and [cid for _, cid in res] == [0, None, 1]
+    net.flush()
+    net.prepare()
+    n = net.count("src")
+    assert 30000 < n < 50000, n
+    with pytest.raises(snnc.SnncError) as e:
+        net.submit_many([small])
+    assert e.value.code == -4
+    net.close()
+
+
 def test_counting_lane_with_large_requests():
     """Admission counts run on their own stream while earlier batches generate;
     requests up to 1e6 connections make the counting lane reuse its large
