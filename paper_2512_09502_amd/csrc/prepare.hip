@@ -355,18 +355,33 @@ __global__ __launch_bounds__(XNT) void k_number(const uint64_t* __restrict__ key
     }
 }
 
-// R value and (alpha+1, sigma) boundaries from the image prefixes a G + gid
+// R value and (alpha+1, sigma) boundaries from the image prefixes a G + gid.
+// Each thread takes RV_RUN consecutive images (sorted): the map slot a and the
+// host are found for the first and kept while the next ones stay inside them.
+constexpr int RV_RUN = 8;
+
 __global__ void k_rvals_sorted(const uint64_t* img_key, uint64_t n_img, const uint64_t* host_base, uint32_t P,
                                uint64_t G, int32_t* R) {
-    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n_img) return;
-    const uint64_t gid = img_key[j] % G;
-    uint32_t lo = 0, hi = P;
-    while (hi - lo > 1) {
-        const uint32_t m = (lo + hi) >> 1;
-        if (host_base[m] <= gid) lo = m; else hi = m;
+    const uint64_t j0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * RV_RUN;
+    if (j0 >= n_img) return;
+    const uint64_t j1 = j0 + RV_RUN < n_img ? j0 + RV_RUN : n_img;
+    uint64_t base = 0;             // a G of the current slot
+    uint64_t hlo = 1, hhi = 0;     // [host_base[h], host_base[h + 1]) of the current host (empty: none yet)
+    for (uint64_t j = j0; j < j1; ++j) {
+        const uint64_t key = img_key[j];
+        if (key < base || key - base >= G) base = key / G * G;
+        const uint64_t gid = key - base;
+        if (gid < hlo || gid >= hhi) {
+            uint32_t lo = 0, hi = P;
+            while (hi - lo > 1) {
+                const uint32_t m = (lo + hi) >> 1;
+                if (host_base[m] <= gid) lo = m; else hi = m;
+            }
+            hlo = host_base[lo];
+            hhi = host_base[lo + 1];
+        }
+        R[j] = (int32_t)(gid - hlo);
     }
-    R[j] = (int32_t)(gid - host_base[lo]);
 }
 
 __global__ void k_bounds_sorted(const uint64_t* img_key, uint64_t n_img, const uint64_t* host_base, uint32_t P,
@@ -1057,7 +1072,8 @@ void prepare_all(Ctx& c) {
                 int64_t* img_base = result<int64_t>(c, SNNC_IMG_BASE, (uint64_t)n_a * P);
                 if (n_img) {
                     tstart(c, "prep_rvals");
-                    hipLaunchKernelGGL(k_rvals_sorted, dim3((unsigned)((n_img + 255) / 256)), dim3(256), 0, c.stream,
+                    hipLaunchKernelGGL(k_rvals_sorted, dim3((unsigned)((n_img + 256 * RV_RUN - 1) / (256 * RV_RUN))),
+                                       dim3(256), 0, c.stream,
                                        img_key, n_img, d_hb, P, G, R);
                     tstop(c);
                     HIPCHK(hipGetLastError());
