@@ -188,6 +188,27 @@ def test_mark_rows(in_lds):
         compare_all(s, pl)
 
 
+def test_mark_row_of_the_largest_lds_size():
+    # a bit row of 2^19 neurons fills the 64 KB of LDS the marking kernel may
+    # use: its send lists equal those of the global-atomic path (which the
+    # oracle pins at smaller sizes)
+    import paper_2512_09502_amd as snnc
+    b = W._Builder(2, seed=13)
+    src = b.create(0, 1 << 19)
+    tgt = b.create(1, 2000)
+    b.connect([src], [tgt], {"rule": "fixed_indegree", "n": 30, "autapses": True, "multapses": True}, SYN_N, -1)
+    s = b.script("mark_row_max")
+    out = []
+    for in_lds in (1, 0):
+        s["tune"] = {"mark_in_lds": in_lds}
+        net = snnc.run_script(s, 0)
+        out.append({k: net.array(k) for k in ("s_off", "s_val", "tp_ptr", "t_val", "p_val")})
+        net.close()
+    for k in out[0]:
+        np.testing.assert_array_equal(out[0][k], out[1][k], err_msg=k)
+    assert out[0]["s_val"].size > 50000
+
+
 @pytest.mark.parametrize("k", [9, 50])
 def test_remote_outdegree_without_multapses(k):
     # counting, writing and point-to-point marking through both samplers (small and large K)
