@@ -943,7 +943,7 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
         init_ring(c->ring, 16u << 20);
         c->dl_pin_bytes = 64u << 10;
         HIPCHK(hipHostMalloc((void**)&c->dl_pin, c->dl_pin_bytes, hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&c->tot_pin, 2 * sizeof(uint64_t), hipHostMallocMapped));
+        HIPCHK(hipHostMalloc((void**)&c->tot_pin, 4 * sizeof(uint64_t), hipHostMallocMapped));
         HIPCHK(hipHostGetDevicePointer((void**)&c->tot_pin_dev, c->tot_pin, 0));
         c->d_status = dalloc_n<uint32_t>(*c, 1);
         HIPCHK(hipMemsetAsync(c->d_status, 0, 4, c->stream));

@@ -232,8 +232,9 @@ struct Ctx {
     StageRing ring;                      // per lane
     // pinned landing area of small device-to-host reads (each read waits for its copy)
     char* dl_pin = nullptr;
-    // scan totals read back without a copy: two mapped pinned words (main
-    // stream, counting stream), written by the scan's last kernel
+    // scan totals read back without a copy: mapped pinned words (main stream,
+    // counting stream), written by the scan's last kernel; word 2 is the
+    // spike exchange's error word, word 3 spare
     uint64_t* tot_pin = nullptr;
     uint64_t* tot_pin_dev = nullptr;
     // batched admission: where the counting sections write their totals

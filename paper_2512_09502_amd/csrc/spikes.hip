@@ -21,13 +21,21 @@ constexpr int SNT = 256;
 
 unsigned sgrid(uint64_t n) { return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + SNT - 1) / SNT, 1u << 20)); }
 
+// The exchange's error word: a mapped pinned word that the kernels set with a
+// plain store (any lane, same value) and the host reads after the stream's
+// wait; cleared by the host before the launches (the previous call waited).
+static uint32_t* err_word(Ctx& c) {
+    *reinterpret_cast<volatile uint32_t*>(c.tot_pin + 2) = 0u;
+    return reinterpret_cast<uint32_t*>(c.tot_pin_dev + 2);
+}
+
 // records per spike; spike ids beyond M set the error word
 __global__ __launch_bounds__(SNT) void k_spike_deg(const uint32_t* spikes, uint64_t n, uint32_t M, const uint64_t* ptr,
                                                    uint32_t* deg, uint32_t* err) {
     for (uint64_t k = (uint64_t)blockIdx.x * SNT + threadIdx.x; k < n; k += (uint64_t)gridDim.x * SNT) {
         const uint32_t s = spikes[k];
         uint32_t d = 0;
-        if (s >= M) atomicOr(err, 1u);
+        if (s >= M) *err = 1u;   // any lane may set it
         else d = (uint32_t)(ptr[s + 1] - ptr[s]);
         deg[k] = d;
     }
@@ -103,7 +111,7 @@ __global__ __launch_bounds__(SNT) void k_deliver_lookup(const uint32_t* grp, con
             if ((uint64_t)pos[e] < b - a) img = map_img[a + pos[e]];
             else ok = false;
         }
-        if (!ok) atomicOr(err, 1u);
+        if (!ok) *err = 1u;   // any lane may set it
         uint64_t lo = 0, hi = 0;
         if (img >= 0 && img_first) {     // image rows kept apart (GPU memory levels 0 and 1)
             lo = img_first[(uint32_t)img - M_local];
@@ -179,18 +187,16 @@ uint64_t spike_packets(Ctx& c, int kind, const uint32_t* spikes, const uint32_t*
     };
     uint64_t total = 0;
     try {
-        uint32_t* err = static_cast<uint32_t*>(tmp(4));
-        HIPCHK(hipMemsetAsync(err, 0, 4, c.stream));
+        // the error word lives in mapped pinned memory: read after the scan's wait, no copy
+        uint32_t* err = err_word(c);
         uint32_t* deg = static_cast<uint32_t*>(tmp(std::max<uint64_t>(n, 1) * 4));
         uint64_t* rec_off = static_cast<uint64_t*>(tmp((n + 1) * 8));
         if (n) {
             hipLaunchKernelGGL(k_spike_deg, dim3(sgrid(n)), dim3(SNT), 0, c.stream, spikes, n, M, ptr, deg, err);
             HIPCHK(hipGetLastError());
         }
-        total = n ? scan_u32_u64(c, deg, rec_off, n, true) : 0;
-        uint32_t err_h = 0;
-        download(c, &err_h, err, 4);
-        if (err_h) raise(SNNC_EINVAL, "spike id is not a local neuron");
+        total = n ? scan_u32_u64(c, deg, rec_off, n, true) : 0;   // waits for the stream
+        if (*reinterpret_cast<volatile uint32_t*>(c.tot_pin + 2)) raise(SNNC_EINVAL, "spike id is not a local neuron");
         if (total > cap) {
             for (void* p : temps) dfree(c, p);
             temps.clear();
@@ -206,7 +212,8 @@ uint64_t spike_packets(Ctx& c, int kind, const uint32_t* spikes, const uint32_t*
                                groups, n_groups, rec_off, k0, v0);
             tstop(c);
             HIPCHK(hipGetLastError());
-            const int w = radix_sort(c, k0, v0, k1, v1, total, 32, 32 + bits_for_values(n_dest), nullptr, nullptr);
+            const int w = radix_sort(c, k0, v0, k1, v1, total, 32, 32 + bits_for_values(n_dest), nullptr, nullptr,
+                                     false);   // every pass runs: no wait for the digit histograms
             const uint64_t* ks = w ? k1 : k0;
             const uint32_t* vs = w ? v1 : v0;
             tstart(c, "spike_packets");
@@ -246,8 +253,7 @@ uint64_t deliver(Ctx& c, int kind, const uint32_t* grp, const uint32_t* host, co
     };
     uint64_t total = 0;
     try {
-        uint32_t* err = static_cast<uint32_t*>(tmp(4));
-        HIPCHK(hipMemsetAsync(err, 0, 4, c.stream));
+        uint32_t* err = err_word(c);   // mapped pinned memory, read after the scan's wait
         uint64_t* cnt = static_cast<uint64_t*>(tmp(std::max<uint64_t>(n, 1) * 8));
         uint64_t* ev_off = static_cast<uint64_t*>(tmp((n + 1) * 8));
         if (n) {
@@ -259,10 +265,8 @@ uint64_t deliver(Ctx& c, int kind, const uint32_t* grp, const uint32_t* host, co
             tstop(c);
             HIPCHK(hipGetLastError());
         }
-        total = n ? scan_u64_u64(c, cnt, ev_off, n, true) : 0;
-        uint32_t err_h = 0;
-        download(c, &err_h, err, 4);
-        if (err_h) raise(SNNC_EINVAL, "received entry outside its map");
+        total = n ? scan_u64_u64(c, cnt, ev_off, n, true) : 0;   // waits for the stream
+        if (*reinterpret_cast<volatile uint32_t*>(c.tot_pin + 2)) raise(SNNC_EINVAL, "received entry outside its map");
         if (ev_tgt && total > ev_cap) {
             *too_small = true;
         } else if (ev_tgt && total) {
