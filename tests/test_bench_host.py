@@ -1,0 +1,54 @@
+"""Host logic of bench.py (no GPU): the single-GPU guard, the reserve hint a
+workload states for the host, the phase grouping of kernel times, and the
+traffic table's source-hash check."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+from paper_2512_09502_amd import workloads as W  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr) or "1 GPU" in (r.stdout + r.stderr)
+
+
+def test_reserve_hint_per_host():
+    s = W.multiarea_p2p(P=4, n_e=100, n_i=25, k_e=10, k_i=3, k_remote_max=5, seed=3)
+    kr = s["info"]["k_remote"]
+    for tau in range(4):
+        remote = sum(kr[sigma][tau] for sigma in range(4) if sigma != tau)
+        assert bench.expected_conns(s, tau) == 125 * (13 + remote)
+    assert bench.expected_conns(W.column8(scale=0.01)) == W.column8(scale=0.01)["info"]["conns"]
+
+
+def test_phase_grouping():
+    kernels = {"gen_total": (4, 4.0), "prep_keys": (1, 2.0), "prep_number": (1, 1.5), "sort_pass": (3, 9.0),
+               "sort_pass_final": (1, 3.0), "prep_csr": (1, 0.5), "prep_mark": (2, 1.0), "scan": (5, 0.25)}
+    out = bench.phase_times(kernels, {"ms_connect": 5.0, "ms_prepare": 15.0})
+    assert out["generation"] == 4.0 and out["keys_unique_remap"] == 3.5 and out["sort"] == 12.0
+    assert out["csr"] == 0.5 and out["send_lists"] == 1.0 and out["other"] == 0.25
+    assert out["connect_events_ms"] == 5.0 and out["prepare_events_ms"] == 15.0
+
+
+def test_traffic_table_follows_the_sort_source():
+    # the committed counters are used only while the kernel source they were taken on is unchanged
+    import hashlib
+    t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
+    e = t["sort_pass"]
+    n = 408483244
+    got = bench.measured_traffic("sort_pass", n, e["workload"])
+    sha = hashlib.sha1(open(os.path.join(ROOT, e["source"]), "rb").read()).hexdigest()
+    if sha == e["sha1"]:
+        assert got == pytest.approx(n * (e["read_bytes_per_elem"] + e["write_bytes_per_elem"]), rel=1e-6)
+    else:
+        assert got is None
+    assert bench.measured_traffic("sort_pass", n, "some_other_workload") is None
