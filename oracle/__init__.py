@@ -83,7 +83,6 @@ def lib():
         L.orc_prepare.argtypes = [vp]
         L.orc_set_map_policy.argtypes = [vp, ctypes.c_int, ctypes.c_int, dbl]
         L.orc_set_memory_level.argtypes = [vp, ctypes.c_int]
-        L.orc_bern_table.argtypes = [dbl, vp]
         L.orc_packets_from_lists.restype = ctypes.c_int64
         L.orc_packets_from_lists.argtypes = [vp, vp, vp, u32, u32, vp, vp, u64, vp, vp, vp, u64]
         L.orc_spike_packets.restype = ctypes.c_int64
@@ -127,13 +126,6 @@ def uniform_index(lo: int, hi: int, n: int) -> int:
 
 def normal_weight(w0: int, w1: int, mean: float, sd: float) -> float:
     return float(lib().orc_normal_weight(w0, w1, mean, sd))
-
-
-def bern_table(p: float) -> np.ndarray:
-    """The 64 geometric-gap thresholds of a Bernoulli(p) sequence (uint64)."""
-    out = np.zeros(64, np.uint64)
-    lib().orc_bern_table(float(p), _ptr(out))
-    return out
 
 
 def delay_table(mean: float, sd: float, lo: float, dt: float):

@@ -83,34 +83,6 @@ static void draw_block(uint32_t seed, uint32_t call_id, uint64_t e, uint32_t pur
     orc_philox4x32_10(ctr, key, w);
 }
 
-/* Block `sub` of the stream of element e: counter word 3 carries sub. */
-static void draw_block_sub(uint32_t seed, uint32_t call_id, uint64_t e, uint32_t purpose, uint32_t sub, uint32_t w[4])
-{
-    uint32_t ctr[4] = { (uint32_t)(e & 0xffffffffu), (uint32_t)(e >> 32), purpose, sub };
-    uint32_t key[2] = { seed, call_id };
-    orc_philox4x32_10(ctr, key, w);
-}
-
-/* Gap thresholds of a Bernoulli(p) sequence (reading): the number of failures
- * before the next success is g = #{k < 64 : w >= thr[k]} for a uniform 32-bit
- * word w, with thr[k] = ceil((1 - (1 - p)^(k + 1)) 2^32), the powers taken by
- * repeated multiplication in double (only correctly rounded operations, so
- * every implementation gets the same table); g = 64 means no success within
- * the next 64 pairs. */
-void orc_bern_table(double p, uint64_t thr[64])
-{
-    const double q = 1.0 - p;
-    double pw = 1.0;
-    for (int k = 0; k < 64; k++) {
-        pw = pw * q;
-        double f = (1.0 - pw) * 4294967296.0;
-        double c = ceil(f);
-        if (c < 0.0) c = 0.0;
-        if (c > 4294967296.0) c = 4294967296.0;
-        thr[k] = (uint64_t)c;
-    }
-}
-
 /* Uniform index in [0, n) from two 32-bit words: the 64-bit fraction
  * u = (hi:lo) / 2^64 scaled by n and truncated, i.e. floor(u * n / 2^64). */
 uint64_t orc_uniform_index(uint32_t lo, uint32_t hi, uint64_t n)
@@ -118,6 +90,15 @@ uint64_t orc_uniform_index(uint32_t lo, uint32_t hi, uint64_t n)
     uint64_t u = ((uint64_t)hi << 32) | (uint64_t)lo;
     unsigned __int128 prod = (unsigned __int128)u * (unsigned __int128)n;
     return (uint64_t)(prod >> 64);
+}
+
+/* Acceptance threshold of a pairwise Bernoulli(p) test on a uniform 32-bit
+ * word w: the pair connects iff w < floor(p 2^32); p = 1 gives 2^32, so every
+ * word passes.  The probability is floor(p 2^32) / 2^32, within 2^-32 of p. */
+static uint64_t bern_threshold(double p)
+{
+    if (p >= 1.0) return 4294967296ull;
+    return (uint64_t)floor(p * 4294967296.0);
 }
 
 /* Normal weight by the Box-Muller transform, cosine branch, in double,
@@ -549,38 +530,26 @@ static void gen_call(const orc_net* net, const orc_call* c, uint32_t host, uint6
         break;
     }
     case R_BERNOULLI: {
-        /* Pairwise Bernoulli (reading): the pairs of target t are taken in
-         * blocks of 64 source ordinals, block j = [64 j, 64 j + 64) of
-         * element eb = t * nb + j (nb = blocks per target).  Within a block
-         * the successes are found by geometric gaps: step m uses word m % 4 of
-         * block BERN(eb, sub = m / 4); gap g from the threshold table; the
-         * success is at position pos + g when inside the block, then pos moves
-         * past it; a gap reaching the block end closes the block.  The
-         * connection's element index is the pair index q = t n_s + s. */
-        uint64_t thr[64];
-        orc_bern_table(c->p, thr);
-        const uint64_t nb = (ns + 63) / 64;
+        /* Pairwise Bernoulli (the rule dictionary C; realisation is a
+         * reading): every (source, target) pair is an independent test.  The
+         * pairs are numbered target-major, q = t n_s + s, and four pairs share
+         * one Philox block: pair q connects iff word (q mod 4) of BERN(q / 4)
+         * is below T_p = floor(p 2^32), with T_p = 2^32 for p = 1 (every pair
+         * connects).  The connection's element index is q. */
+        const uint64_t thr = bern_threshold(c->p);
         for (uint64_t t = lo; t < hi && t < nt; t++) {
             set_at(&c->T, t, &h2, &l2);
             if (h2 != host) continue;
-            for (uint64_t j = 0; j < nb; j++) {
-                const uint64_t eb = t * nb + j;
-                const uint64_t len = (j + 1) * 64 <= ns ? 64 : ns - j * 64;
-                uint64_t pos = 0;
+            for (uint64_t s = 0; s < ns; s++) {
+                const uint64_t q = t * ns + s;
                 uint32_t w[4];
-                for (uint32_t m = 0;; m++) {
-                    if (m % 4 == 0) draw_block_sub(net->seed, c->id, eb, PURPOSE_BERN, m / 4, w);
-                    uint64_t g = 0;
-                    while (g < 64 && (uint64_t)w[m % 4] >= thr[g]) g++;
-                    if (pos + g >= len) break;
-                    const uint64_t s = j * 64 + pos + g;
-                    pos += g + 1;
-                    if (!c->autapses) {
-                        set_at(&c->S, s, &h, &l);
-                        if (h == h2 && l == l2) continue;
-                    }
-                    sink.emit(sink.ctx, s, l2, t * ns + s);
+                draw_block(net->seed, c->id, q / 4, PURPOSE_BERN, w);
+                if ((uint64_t)w[q % 4] >= thr) continue;
+                if (!c->autapses) {
+                    set_at(&c->S, s, &h, &l);
+                    if (h == h2 && l == l2) continue;
                 }
+                sink.emit(sink.ctx, s, l2, q);
             }
         }
         break;
@@ -1548,23 +1517,9 @@ int orc_call_element(const orc_net* net, uint32_t call_id, uint64_t e, uint32_t*
         t = e / ns;
         s = e % ns;
         if (t >= nt) return -1;
-        /* replay the pair's block of 64 up to its position */
-        uint64_t thr[64];
-        orc_bern_table(c->p, thr);
-        const uint64_t nb = (ns + 63) / 64, j = s / 64, want = s % 64;
-        const uint64_t len = (j + 1) * 64 <= ns ? 64 : ns - j * 64;
-        uint64_t pos = 0;
-        int hit = 0;
         uint32_t w[4];
-        for (uint32_t m = 0;; m++) {
-            if (m % 4 == 0) draw_block_sub(net->seed, c->id, t * nb + j, PURPOSE_BERN, m / 4, w);
-            uint64_t g = 0;
-            while (g < 64 && (uint64_t)w[m % 4] >= thr[g]) g++;
-            if (pos + g >= len || pos + g > want) break;
-            if (pos + g == want) { hit = 1; break; }
-            pos += g + 1;
-        }
-        if (!hit) return 0;
+        draw_block(net->seed, c->id, e / 4, PURPOSE_BERN, w);
+        if ((uint64_t)w[e % 4] >= bern_threshold(c->p)) return 0;
         set_at(&c->T, t, &h2, &l2);
         if (!c->autapses) {
             set_at(&c->S, s, &h, &l);

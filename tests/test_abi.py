@@ -60,13 +60,3 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(snnc.Dist) == 32
     assert ctypes.sizeof(snnc.SynSpec) == 72
     assert ctypes.sizeof(snnc.Stats) == 64
-
-
-@pytest.mark.parametrize("p", [0.0, 1e-9, 1e-6, 0.001, 0.0123, 0.05, 0.2, 1 / 3, 0.5, 0.9, 0.999999, 1.0])
-def test_bernoulli_tables_identical_to_oracle(p):
-    np.testing.assert_array_equal(snnc.bern_table(p), oracle.bern_table(p))
-
-
-def test_bernoulli_table_rejections():
-    for p in (-0.1, 1.5, float("nan")):
-        assert snnc.bern_table(p) is None

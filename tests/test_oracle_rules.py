@@ -230,53 +230,84 @@ def test_invalid_specs_rejected():
     net.connect([a], [a], {"rule": "fixed_indegree", "n": 4, "autapses": False, "multapses": False}, SYN)
 
 
-@pytest.mark.parametrize("p", [0.0, 1e-6, 0.001, 0.03, 0.2, 0.5, 0.97, 1.0])
-def test_bernoulli_gap_table_closed_form(p):
-    """thr[k] = ceil((1 - (1-p)^(k+1)) 2^32) against exact rational arithmetic on
-    the double p (the table's repeated products may differ by a rounding)."""
-    from fractions import Fraction
-    thr = oracle.bern_table(p).astype(object)
-    q = 1 - Fraction(p)
-    prev = 0
-    for k in range(64):
-        exact = math.ceil((1 - q ** (k + 1)) * 2**32)
-        assert abs(int(thr[k]) - exact) <= 1, (k, thr[k], exact)
-        assert int(thr[k]) >= prev
-        prev = int(thr[k])
-        # the gap pmf the table implies is p (1-p)^k
-        lo = int(thr[k - 1]) if k else 0
-        pmf = (int(thr[k]) - lo) / 2**32
-        assert abs(pmf - float(Fraction(p) * q ** k)) <= 2.0 / 2**32
+def _bern_threshold(p):
+    return 2**32 if p >= 1 else math.floor(p * 2**32)
 
 
-def test_bernoulli_block_positions_and_pairs():
-    """Every source position inside the 64-pair blocks connects with
-    probability p, and neighbouring pairs independently (p^2)."""
-    p, n_s, reps = 0.05, 64 * 8 + 17, 300
-    net = oracle.OracleNet(1, 0, 9, 0.1)
-    a = net.create(0, n_s)
-    t = net.create(0, 4)
+@pytest.mark.parametrize("n_s,n_t,p,aut", [(5, 3, 0.3, True), (3, 4, 0.5, False), (7, 2, 0.1, True)])
+def test_bernoulli_pair_enumeration(n_s, n_t, p, aut):
+    """Brute force over many calls on tiny sets: every pair connects with
+    probability T_p / 2^32 (chi-square per pair), the outcomes of the four
+    pairs that share a Philox block are jointly independent (chi-square over
+    the 16 joint outcomes), and so are neighbouring pairs across block and
+    target boundaries (p^2).  n_s not a multiple of 4 puts pairs of two targets
+    in one block."""
+    reps = 3000
+    net = oracle.OracleNet(1, 0, 17, 0.1)
+    a = net.create(0, max(n_s, n_t))
     for _ in range(reps):
-        net.connect([a], [t], {"rule": "pairwise_bernoulli", "p": p}, SYN)
+        net.connect([(0, 0, n_s)], [(0, 0, n_t)], {"rule": "pairwise_bernoulli", "p": p, "autapses": aut}, SYN)
     s = net.array("gen_src").astype(np.int64)
-    tg = net.array("gen_tgt").astype(np.int64) - n_s
-    n_trials = reps * 4
-    pos = np.bincount(s % 64, minlength=64)
-    per_pos = np.array([(np.arange(n_s) % 64 == k).sum() for k in range(64)]) * n_trials
-    assert stats.chisquare(pos, per_pos * p * pos.sum() / (per_pos * p).sum()).pvalue > 1e-4
-    assert abs(pos.sum() - n_trials * n_s * p) <= 5 * math.sqrt(n_trials * n_s * p * (1 - p))
-    # pairs (s, s+1) inside one block connected together
+    t = net.array("gen_tgt").astype(np.int64)
     e = net.array("gen_e").astype(np.int64)
-    off = np.r_[0, np.nonzero(np.diff(e) <= 0)[0] + 1, e.size]     # element indices restart with each call
+    assert (e == t * n_s + s).all()                      # element index = target-major pair index
+    net.prepare()
+    off = net.array("call_off").astype(np.int64)         # first generated index of each call
     assert off.size == reps + 1
-    both = 0
-    for c in range(reps):
-        for tt in range(4):
-            sel = s[off[c]:off[c + 1]][tg[off[c]:off[c + 1]] == tt]
-            ss = set(sel.tolist())
-            both += sum(1 for x in ss if (x + 1) in ss and (x + 1) % 64 != 0)
-    n_adj = n_trials * sum(1 for x in range(n_s - 1) if (x + 1) % 64 != 0)
-    assert abs(both - n_adj * p * p) <= 5 * math.sqrt(n_adj * p * p)
+    call = np.repeat(np.arange(reps), np.diff(off))
+    hit = np.zeros((reps, n_t * n_s), bool)
+    hit[call, e] = True
+    pp = _bern_threshold(p) / 2**32
+    valid = np.array([aut or (q % n_s) != (q // n_s) for q in range(n_s * n_t)])
+    assert not hit[:, ~valid].any()                      # autapses skipped when excluded
+    freq = hit[:, valid].sum(0)
+    sd = math.sqrt(reps * pp * (1 - pp))
+    assert np.all(np.abs(freq - reps * pp) <= 5 * sd)
+    assert stats.chisquare(freq, np.full(freq.size, freq.sum() / freq.size)).pvalue > 1e-4
+    # joint outcomes of a whole block of four valid pairs
+    for b in range(n_s * n_t // 4):
+        qs = list(range(4 * b, 4 * b + 4))
+        if not valid[qs].all():
+            continue
+        code = (hit[:, qs] * (1 << np.arange(4))).sum(1)
+        obs = np.bincount(code, minlength=16)
+        k = np.array([bin(c).count("1") for c in range(16)])
+        exp = reps * pp ** k * (1 - pp) ** (4 - k)
+        assert stats.chisquare(obs, exp).pvalue > 1e-4
+    # neighbouring valid pairs q, q + 1 (inside a block, across blocks, across targets)
+    pairs = [q for q in range(n_s * n_t - 1) if valid[q] and valid[q + 1]]
+    both = sum(int((hit[:, q] & hit[:, q + 1]).sum()) for q in pairs)
+    n_adj = reps * len(pairs)
+    assert abs(both - n_adj * pp * pp) <= 5 * math.sqrt(n_adj * pp * pp * (1 - pp * pp))
+
+
+@pytest.mark.parametrize("p", [0.0, 0.001, 0.25, 0.7, 1.0])
+def test_bernoulli_pairs_recomputed_from_philox(p):
+    """Per-pair recomputation on a random sample: pair q connects iff word
+    (q mod 4) of the BERN block q / 4 (Philox4x32-10 pinned by its
+    known-answer vectors) is below floor(p 2^32)."""
+    n_s, n_t, seed = 123, 57, 29
+    net = oracle.OracleNet(1, 0, seed, 0.1)
+    a = net.create(0, n_s)
+    b = net.create(0, n_t)
+    net.connect([a], [a], {"rule": "fixed_indegree", "n": 1}, SYN)              # call 0 (other stream)
+    net.connect([a], [b], {"rule": "pairwise_bernoulli", "p": p}, SYN)           # call 1
+    e = net.array("gen_e").astype(np.int64)[n_s:]
+    s = net.array("gen_src").astype(np.int64)[n_s:]
+    t = net.array("gen_tgt").astype(np.int64)[n_s:] - n_s
+    assert (e == t * n_s + s).all() and (np.diff(e) > 0).all()
+    got = set(e.tolist())
+    thr = _bern_threshold(p)
+    rng = np.random.default_rng(4)
+    sample = rng.choice(n_s * n_t, size=600, replace=False).tolist() + sorted(got)[:50]
+    for q in sample:
+        blk = q // 4
+        w = oracle.philox([blk & 0xFFFFFFFF, blk >> 32, 2, 0], [seed, 1])
+        assert (int(w[q % 4]) < thr) == (q in got), q
+    if p == 1.0:
+        assert len(got) == n_s * n_t
+    if p == 0.0:
+        assert not got
 
 
 def test_bernoulli_element_replay_matches_generation():
