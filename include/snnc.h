@@ -167,10 +167,10 @@ snnc_status snnc_create(snnc_ctx* ctx, uint32_t host, uint32_t n, snnc_segment* 
  *                        multapses excluded) are the connections, e = c; with
  *                        targets on several hosts every host evaluates every
  *                        candidate and keeps those whose target it holds;
- *   pairwise Bernoulli:  the pairs of a target in blocks of 64 source
- *                        ordinals, successes by geometric gaps from the
- *                        threshold table of snnc_bern_table; e = q = t_ord * n_s
- *                        + s_ord;
+ *   pairwise Bernoulli:  pairs numbered target-major, q = t_ord * n_s +
+ *                        s_ord; pair q connects iff word q % 4 of block
+ *                        BERN(q / 4) is below floor(p * 2^32) (every pair
+ *                        for p = 1); e = q;
  *   one-to-one:          e = i;
  *   assigned nodes:      see snnc_connect_assigned (snnc_connect rejects it).
  * Synapse values of element e come from block SYN(e) of the same call.
@@ -475,15 +475,6 @@ snnc_status snnc_deliver(snnc_ctx* ctx, int32_t kind, const uint32_t* grp, const
                          const uint32_t* pos, const uint32_t* mult, uint64_t n, int32_t* image,
                          uint64_t* row_begin, uint64_t* row_end, int32_t* ev_tgt, uint16_t* ev_delay,
                          float* ev_weight, uint64_t ev_cap, uint64_t* n_events);
-
-/* Gap thresholds of the pairwise Bernoulli rule (host only; for checking):
- * thr[k] = ceil((1 - (1 - p)^(k+1)) 2^32), k = 0 .. 63, the powers by repeated
- * products in double.  Inside a block of 64 source ordinals of a target, the
- * failures before the next success are #{k : w >= thr[k]} for the next 32-bit
- * word w of the block's stream (step m: word m % 4 of BERN(t_ord nb + j,
- * counter word 3 = m / 4), nb = ceil(n_s / 64)).  SNNC_EINVAL for p outside
- * [0, 1] or a null pointer. */
-snnc_status snnc_bern_table(double p, uint64_t* thr);
 
 /* ---------------------------------------------------------------- helpers */
 

@@ -85,7 +85,7 @@ EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_cr
            "snnc_reserve", "snnc_prepare", "snnc_get_array", "snnc_copy_array", "snnc_copy_range",
            "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks",
            "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_submit_many", "snnc_flush", "snnc_poll",
-           "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver", "snnc_bern_table",
+           "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver",
            "snnc_connect_assigned", "snnc_set_memory_level", "snnc_array_on_host"]
 
 _lib = None
@@ -113,7 +113,6 @@ def lib():
         L.snnc_set_map_policy.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
         L.snnc_set_memory_level.argtypes = [vp, ctypes.c_int32]
         L.snnc_array_on_host.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int32)]
-        L.snnc_bern_table.argtypes = [ctypes.c_double, vp]
         L.snnc_spike_packets.argtypes = [vp, ctypes.c_int32, vp, vp, u64, vp, vp, vp, u64, ctypes.POINTER(u64)]
         L.snnc_deliver.argtypes = [vp, ctypes.c_int32, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp, vp, u64,
                                    ctypes.POINTER(u64)]
@@ -190,14 +189,6 @@ def delay_table(mean: float, sd: float, lo: float, dt: float):
     if st != 0:
         return None
     return int(klo.value), buf[: n.value].copy()
-
-
-def bern_table(p: float):
-    """The library's host-built Bernoulli gap thresholds (64 x uint64) or None."""
-    buf = np.zeros(64, np.uint64)
-    if lib().snnc_bern_table(float(p), buf.ctypes.data) != 0:
-        return None
-    return buf
 
 
 class Network:

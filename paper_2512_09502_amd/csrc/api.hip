@@ -404,8 +404,6 @@ static void validate(Ctx& c, Call& cl, const snnc_syn_spec* syn) {
     }
     case SNNC_PAIRWISE_BERNOULLI:
         if (!(cl.p >= 0.0 && cl.p <= 1.0)) raise(SNNC_EINVAL, "probability outside [0, 1]");
-        cl.btab.resize(64);
-        build_bern_table(cl.p, cl.btab.data());
         break;
     case SNNC_ASSIGNED_NODES: {
         if (cl.n && (!cl.in_src_pos || !cl.in_tgt_pos))
@@ -456,41 +454,20 @@ static void validate(Ctx& c, Call& cl, const snnc_syn_spec* syn) {
     } else raise(SNNC_EINVAL, "unknown delay distribution");
 }
 
-// Gap thresholds of a Bernoulli(p) sequence: the failures before the next
-// success are #{k < 64 : w >= thr[k]} for a uniform 32-bit word w, with
-// thr[k] = ceil((1 - (1 - p)^(k+1)) 2^32); the powers come from repeated
-// products (correctly rounded operations only, so the table does not depend
-// on a math library).
-void build_bern_table(double p, uint64_t* thr) {
-#pragma clang fp contract(off)
-    const double q = 1.0 - p;
-    double pw = 1.0;
-    for (int k = 0; k < 64; ++k) {
-        pw = pw * q;
-        double v = std::ceil((1.0 - pw) * 4294967296.0);
-        if (v < 0.0) v = 0.0;
-        if (v > 4294967296.0) v = 4294967296.0;
-        thr[k] = (uint64_t)v;
-    }
-}
-
-// device copies of a call's sets, Bernoulli gap table and delay table (one allocation)
+// device copies of a call's sets and delay table (one allocation)
 void upload_meta(Ctx& c, Call& cl) {
     const size_t nS = std::max<size_t>(cl.S.seg.size(), 1), nT = std::max<size_t>(cl.T.seg.size(), 1);
-    const size_t nB = cl.btab.size();
     const std::vector<uint32_t>* tab = cl.dtab && !cl.dtab->tab.empty() ? &cl.dtab->tab : nullptr;
     const size_t nD = tab ? tab->size() : 1;
     const size_t nG = tab ? 257 : 0;   // guide of the delay table
-    const size_t bytes = (nS + nT) * sizeof(SegD) + nB * sizeof(uint64_t) + (nD + nG) * sizeof(uint32_t);
+    const size_t bytes = (nS + nT) * sizeof(SegD) + (nD + nG) * sizeof(uint32_t);
     std::vector<char> host(bytes, 0);
     SegD* hS = reinterpret_cast<SegD*>(host.data());
     SegD* hT = hS + nS;
     for (size_t i = 0; i < cl.S.seg.size(); ++i) hS[i] = SegD{cl.S.ord_begin[i], cl.S.seg[i].host, cl.S.seg[i].first};
     for (size_t i = 0; i < cl.T.seg.size(); ++i) hT[i] = SegD{cl.T.ord_begin[i], cl.T.seg[i].host, cl.T.seg[i].first};
-    uint64_t* hB = reinterpret_cast<uint64_t*>(hT + nT);
-    if (nB) memcpy(hB, cl.btab.data(), nB * sizeof(uint64_t));
     if (tab) {
-        uint32_t* hD = reinterpret_cast<uint32_t*>(hB + nB);
+        uint32_t* hD = reinterpret_cast<uint32_t*>(hT + nT);
         memcpy(hD, tab->data(), nD * sizeof(uint32_t));
         memcpy(hD + nD, cl.dtab->guide.data(), 257 * sizeof(uint32_t));
     }
@@ -506,8 +483,7 @@ void upload_meta(Ctx& c, Call& cl) {
         cl.meta_bytes += 8 * cl.n;
     }
     cl.in_src_pos = cl.in_tgt_pos = nullptr;
-    cl.btab_dev = nB ? reinterpret_cast<uint64_t*>(cl.dT + nT) : nullptr;
-    cl.dtab_dev = reinterpret_cast<uint32_t*>(reinterpret_cast<uint64_t*>(cl.dT + nT) + nB);
+    cl.dtab_dev = reinterpret_cast<uint32_t*>(cl.dT + nT);
     cl.dguide_dev = nG ? cl.dtab_dev + nD : nullptr;
 }
 
@@ -1264,11 +1240,6 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
     });
 }
 
-snnc_status snnc_bern_table(double p, uint64_t* thr) {
-    if (!thr || !(p >= 0.0 && p <= 1.0)) return SNNC_EINVAL;
-    snnc::build_bern_table(p, thr);
-    return SNNC_OK;
-}
 
 snnc_status snnc_set_memory_level(snnc_ctx* c, int32_t level) {
     if (!c) return SNNC_EINVAL;

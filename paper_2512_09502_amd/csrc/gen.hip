@@ -187,95 +187,69 @@ struct Assigned {
     }
 };
 
-// Pairwise Bernoulli: the pairs of a target are taken in blocks of 64 source
-// ordinals; item = (target, block j), element eb = t_ord nb + j.  Inside a
-// block the successes follow from geometric gaps: step m reads word m % 4 of
-// BERN(eb, sub = m / 4), the gap is the number of thresholds at or below the
-// word, a success lands at pos + gap while inside the block.  A connection's
-// element index is its pair index q = t_ord n_s + s_ord.
-struct BernGap {
+// Pairwise Bernoulli: pair q = t_ord n_s + s_ord (target-major) connects iff
+// word q % 4 of BERN(q / 4) is below thr = floor(p 2^32) (2^32 for p = 1).
+// Item = (target, k-th Philox block of the blocks that hold its pairs): the
+// pairs of target t start at q0 = t_ord n_s, its blocks at q0 / 4; nb =
+// ceil(n_s / 4) + 1 items per target cover a pair range that may start and
+// end inside a block (a block shared by two targets is drawn by both, each
+// keeping its own pairs).  A connection's element index is q.
+struct BernPair {
     const TChunk* ch;
     uint32_t nch;
-    uint32_t nb;      // blocks per target
+    uint32_t nb;      // items per target
     FastDiv fnb;
     uint32_t n_s;
-    const uint64_t* thr;   // 64 gap thresholds
+    uint64_t thr;     // floor(p 2^32), 2^32 for p = 1
     uint32_t autapses;
     uint32_t seed, call;
-    float inv_l2q;    // 1 / log2(1 - p): first guess of a gap (checked against the table)
 };
 
-__device__ __forceinline__ uint4 draw_sub(uint32_t seed, uint32_t call, uint64_t e, uint32_t purpose, uint32_t sub) {
-    return philox10(make_uint4((uint32_t)e, (uint32_t)(e >> 32), purpose, sub), seed, call);
-}
-
-// gap = #{k : thr[k] <= w} over the non-decreasing table (thr in LDS).  The
-// geometric law gives a first guess, log2(1 - w/2^32) / log2(1 - p); the
-// two walks over the table make the count exact whatever the guess.
-__device__ __forceinline__ uint32_t bern_gap(const uint64_t* thr, uint32_t w, float inv_l2q) {
-    const float l = __log2f((float)(0x100000000ull - (uint64_t)w)) - 32.0f;   // log2(1 - u) <= 0
-    const float est = l * inv_l2q;
-    uint32_t g = est >= 64.0f ? 64u : (est > 0.0f ? (uint32_t)est : 0u);
-    while (g < 64 && thr[g] <= (uint64_t)w) ++g;
-    while (g > 0 && thr[g - 1] > (uint64_t)w) --g;
-    return g;
-}
-
-// one item: target t_rel of its chunk, source block j
 struct BernItem {
-    uint64_t t_ord, eb;
-    int64_t self;
-    uint32_t s0, len, tgt;
+    uint64_t q0;      // first pair of the target
+    uint64_t blk;     // Philox block of this item
+    uint32_t tgt;     // target local id
 };
 
-__device__ __forceinline__ BernItem bern_item(const BernGap& r, uint64_t g) {
+// bit i set = pair 4 blk + i connects (inside the target's range, autapse rule applied)
+__device__ __forceinline__ uint32_t bern_mask(const BernPair& r, uint64_t g, BernItem& it) {
     const TChunk c = r.ch[find_chunk(r.ch, r.nch, g)];
     const uint32_t rel = (uint32_t)(g - c.out_begin);
     const uint32_t t_rel = fastdiv(rel, r.fnb);
-    const uint32_t j = rel - t_rel * r.nb;
-    BernItem it;
-    it.t_ord = c.t_ord + t_rel;
-    it.eb = it.t_ord * r.nb + j;
-    it.s0 = j * 64;
-    it.len = r.n_s - it.s0 < 64 ? r.n_s - it.s0 : 64;
-    it.self = c.self_base >= 0 ? c.self_base + t_rel : -1;
+    const uint32_t k = rel - t_rel * r.nb;
+    it.q0 = (c.t_ord + t_rel) * (uint64_t)r.n_s;
+    it.blk = (it.q0 >> 2) + k;
     it.tgt = c.local_first + t_rel;
-    return it;
-}
-
-// the connected positions of an item's block, in source order: f(offset in the block)
-template <class F>
-__device__ __forceinline__ void bern_successes(const BernGap& r, const uint64_t* thr, const BernItem& it, F&& f) {
-    uint32_t pos = 0;
-    uint4 b = make_uint4(0, 0, 0, 0);
-    for (uint32_t m = 0;; ++m) {
-        if ((m & 3u) == 0) b = draw_sub(r.seed, r.call, it.eb, PURPOSE_BERN, m >> 2);
-        const uint32_t w = (m & 3u) == 0 ? b.x : (m & 3u) == 1 ? b.y : (m & 3u) == 2 ? b.z : b.w;
-        const uint32_t gap = bern_gap(thr, w, r.inv_l2q);
-        if (pos + gap >= it.len) break;
-        const uint32_t off = pos + gap;
-        pos = off + 1;
-        if (!r.autapses && (int64_t)(it.s0 + off) == it.self) continue;
-        f(off);
+    const uint64_t q1 = it.q0 + r.n_s;
+    if (it.blk * 4 >= q1) return 0;
+    const uint4 b = draw(r.seed, r.call, it.blk, PURPOSE_BERN);
+    const uint32_t w[4] = {b.x, b.y, b.z, b.w};
+    const int64_t self = c.self_base >= 0 ? c.self_base + t_rel : -1;
+    uint32_t mask = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint64_t q = it.blk * 4 + i;
+        if (q < it.q0 || q >= q1 || (uint64_t)w[i] >= r.thr) continue;
+        if (!r.autapses && (int64_t)(q - it.q0) == self) continue;
+        mask |= 1u << i;
     }
+    return mask;
 }
 
-__device__ __forceinline__ Res bern_res(const BernGap& r, const BernItem& it, uint32_t off) {
-    const uint32_t s = it.s0 + off;
-    return Res{s, it.tgt, it.t_ord * r.n_s + s};
+__device__ __forceinline__ Res bern_res(const BernItem& it, uint32_t i) {
+    const uint64_t q = it.blk * 4 + i;
+    return Res{(uint32_t)(q - it.q0), it.tgt, q};
 }
 
-// COUNT: connections per tile.  WRITE: each thread records the block offsets
-// of its connections in LDS (slot k of thread t at [k * NT + t]) in one visit,
-// a workgroup scan places them, then they are written in item order.
+// COUNT: connections per tile.  WRITE: per round of NT items, a workgroup scan
+// of the per-item counts places every connection in an LDS list in pair order;
+// then all lanes take list entries in turn for the synapse values and the
+// stores, so the sparse hits of a low p do not leave most lanes of a wave idle.
 template <class Sink, int MODE>
-__global__ __launch_bounds__(NT) void k_bern(BernGap r, Sink sink, uint64_t n_items, uint64_t tile0,
+__global__ __launch_bounds__(NT) void k_bern(BernPair r, Sink sink, uint64_t n_items, uint64_t tile0,
                                              uint32_t* tile_counts, const uint64_t* tile_offsets) {
-    __shared__ uint64_t thr[64];
     __shared__ uint32_t scratch[NT / 64];
-    __shared__ uint8_t offs[MODE == WRITE ? 64 * NT : 1];
-    if (threadIdx.x < 64) thr[threadIdx.x] = r.thr[threadIdx.x];
-    __syncthreads();
+    __shared__ Res list[MODE == WRITE ? 4 * NT : 1];
     const uint64_t tile = tile0 + blockIdx.x;
     const uint64_t base = tile * TILE;
     uint64_t running = 0;
@@ -284,23 +258,19 @@ __global__ __launch_bounds__(NT) void k_bern(BernGap r, Sink sink, uint64_t n_it
 #pragma unroll 1
     for (int k = 0; k < IPT; ++k) {
         const uint64_t item = base + (uint64_t)k * NT + threadIdx.x;
-        const bool live = item < n_items;
         BernItem it{};
-        if (live) it = bern_item(r, item);
+        const uint32_t mask = item < n_items ? bern_mask(r, item, it) : 0u;
         if constexpr (MODE == MARK) {
-            if (live) bern_successes(r, thr, it, [&](uint32_t off) { sink.mark(bern_res(r, it, off)); });
-            continue;
-        }
-        uint32_t n = 0;
-        if constexpr (MODE == COUNT) {
-            if (live) bern_successes(r, thr, it, [&](uint32_t) { ++n; });
-            counted += n;
+            for (uint32_t m = mask; m; m &= m - 1) sink.mark(bern_res(it, __builtin_ctz(m)));
+        } else if constexpr (MODE == COUNT) {
+            counted += __builtin_popcount(mask);
         } else {
-            if (live) bern_successes(r, thr, it, [&](uint32_t off) { offs[n++ * NT + threadIdx.x] = (uint8_t)off; });
             uint32_t tot;
-            const uint32_t pre = block_excl_scan<NT>(n, scratch, &tot);
-            for (uint32_t i = 0; i < n; ++i)   // each thread reads back only its own slots
-                sink.put(running + pre + i, bern_res(r, it, offs[i * NT + threadIdx.x]));
+            uint32_t pre = block_excl_scan<NT>((uint32_t)__builtin_popcount(mask), scratch, &tot);
+            for (uint32_t m = mask; m; m &= m - 1) list[pre++] = bern_res(it, __builtin_ctz(m));
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < tot; i += NT) sink.put(running + i, list[i]);
+            __syncthreads();
             running += tot;
         }
     }
@@ -312,7 +282,7 @@ __global__ __launch_bounds__(NT) void k_bern(BernGap r, Sink sink, uint64_t n_it
 }
 
 template <class Sink, int MODE>
-void launch_bern(Ctx& c, const BernGap& r, const Sink& sink, uint64_t n_items, uint32_t* tile_counts,
+void launch_bern(Ctx& c, const BernPair& r, const Sink& sink, uint64_t n_items, uint32_t* tile_counts,
                  const uint64_t* tile_offsets) {
     const uint64_t tiles = (n_items + TILE - 1) / TILE;
     for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
@@ -1261,17 +1231,14 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
         }
         case SNNC_PAIRWISE_BERNOULLI: {
             if (!ns || !nt) break;
-            const uint32_t nb = (uint32_t)((ns + 63) / 64);
+            const uint32_t nb = (uint32_t)((ns + 3) / 4 + 1);
             auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, nb, MAX_RUN_ELEMS);
             const uint64_t items = runs_elems(runs, nb);
             if (!items) break;
             DeviceChunks dc = upload_chunks(c, runs, items);
             temps.push_back(dc.d);
-            // first guess of a gap: 1 / log2(1 - p) (-inf when 1 - p rounds to 1, -0 for p = 1; the table decides)
-            const double l2q = std::log2(1.0 - cl.p);
-            const float inv_l2q = l2q < 0.0 ? (float)(1.0 / l2q) : -INFINITY;
-            BernGap r{dc.d, dc.n, nb, make_fastdiv(nb), (uint32_t)ns, cl.btab_dev, cl.autapses ? 1u : 0u, c.seed, cl.id,
-                      inv_l2q};
+            const uint64_t thr = cl.p >= 1.0 ? (1ull << 32) : (uint64_t)std::floor(cl.p * 4294967296.0);
+            BernPair r{dc.d, dc.n, nb, make_fastdiv(nb), (uint32_t)ns, thr, cl.autapses ? 1u : 0u, c.seed, cl.id};
             if (mark) {
                 launch_bern<MarkSink, MARK>(c, r, ms, items, nullptr, nullptr);
                 break;

@@ -88,7 +88,6 @@ struct Call {
     uint16_t d_const = 0;
     uint32_t d_klo = 0;
     std::shared_ptr<const DelayTable> dtab;   // normal delays only
-    std::vector<uint64_t> btab;         // Bernoulli gap thresholds (64), pairwise Bernoulli only
     // device copies
     void* meta = nullptr;       // one allocation: S segs, T segs, delay table
     size_t meta_bytes = 0;
@@ -96,7 +95,6 @@ struct Call {
     SegD* dT = nullptr;
     uint32_t* dtab_dev = nullptr;
     uint32_t* dguide_dev = nullptr;
-    uint64_t* btab_dev = nullptr;
     uint64_t gen_begin = 0, gen_count = 0;
     std::vector<void*> owned;   // device tables kept until the call's batch has run
     int32_t batch = -1;         // served mode: batch that generates the call (-1: not yet flushed)
@@ -400,7 +398,6 @@ struct SortPlan {
 };
 SortPlan plan_sort(const Ctx& c, uint64_t n, uint32_t bits);
 // 64 geometric-gap thresholds of a Bernoulli(p) sequence (pairwise Bernoulli rule)
-void build_bern_table(double p, uint64_t* thr);
 int sort_variant_count();
 
 // prepare pipeline (prepare.hip)
