@@ -1,14 +1,22 @@
 """Benchmark: connections built and indexed per second on one MI355X.
 
-One step is one whole construction of one host's share of a synthetic
-network on the GPU: a fresh context, Create for every population, every
-Connect call (generation), and Prepare (image map, remap, source-major sort,
-first-index array, point-to-point and collective send lists).  Inputs are the
-workload script (a few KB); everything else is built in HBM inside the timed
-region.  Prints one JSON line.
+Default workload (`--workload served`): the served construction of a stream
+of 10,000 uneven Connect requests (64 populations of 1e3..2e5 neurons,
+request sizes log-uniform in 1e2..1e7 connections, the five rules mixed)
+against a 64 GiB resident budget, then the final sort and first-index array.
+One step = one whole served build of the stream; the line also reports the
+per-call build of the same stream and p50/p99 per-request latency under
+open-loop arrivals.
 
-Default workload: the 8-population cortical-column-shaped network (about 77k
-neurons, 64 fixed-total-number calls, about 4.6e8 connections, one host).
+Other workloads (`--workload column8 | multiarea | collective | indegreeS |
+balanced`): one step is one whole construction of one host's share of a
+synthetic network: a fresh context, Create for every population, every
+Connect call (generation), and Prepare (image map, remap, source-major sort,
+first-index array, point-to-point and collective send lists).  Inputs are
+the workload script (a few KB); everything else is built in HBM inside the
+timed region.  `--workload exchange` times spike packets and delivery.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -113,34 +121,73 @@ def build_once(script, P_local: int, timing):
     return net
 
 
-# algorithmic bytes per element of the kernels whose roofline is reported
-def kernel_roofline(name: str, launches: int, ms: float, n_conn: int, n_passes: int):
-    if name == "sort_pass":
-        per_launch = n_conn * 24.0      # read and write one 8-byte key and one 4-byte payload
-    elif name == "sort_pass_final":
-        per_launch = n_conn * 26.0      # read key + payload (12 B), write src, tgt, delay, weight (14 B)
-    elif name.startswith("gen_"):
-        per_launch = None
-    else:
-        per_launch = None
-    return per_launch
+# Sort + index (image map, remap, sort, first-index array, send lists):
+# algorithmic bytes are one read and one write of the 14-byte connection
+# record (source, target, delay, weight) per connection, 8 bytes per entry of
+# the first-index array, 4 bytes per image (R), per I entry and per entry of
+# the send lists (S, T, P, G, Q) plus 8 bytes per entry of their pointer arrays.
+BYTES_PER_CONN = 28.0
+SORT_INDEX_GROUPS = ("keys_unique_remap", "sort", "csr", "send_lists")
+
+
+def index_bytes(counts: dict) -> float:
+    """Algorithmic bytes of the index structures besides the connection
+    records, from the element counts of the prepared arrays."""
+    b = 8.0 * counts.get("row_ptr", 0)
+    for k in ("r_val", "i_val", "s_val", "t_val", "p_val", "g_val", "q_val"):
+        b += 4.0 * counts.get(k, 0)
+    for k in ("tp_ptr", "gq_ptr"):
+        b += 8.0 * counts.get(k, 0)
+    return b
 
 
 def measured_traffic(kernel: str, n_elem: int, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter table, or
-    None when the counters were taken on another workload or the kernel's
-    source changed since."""
+    """HBM bytes per launch from the committed rocprofv3 counter table
+    (FETCH_SIZE and WRITE_SIZE per element, calibrated), or None when no
+    entry was taken on this workload or the kernel's source changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         table = json.load(open(path))
-        entry = table[kernel]
+        entry = next(e for e in table["entries"] if e["kernel"] == kernel and e["workload"] == workload)
         src = open(os.path.join(ROOT, entry["source"]), "rb").read()
-    except (OSError, KeyError, ValueError):
+    except (OSError, KeyError, ValueError, StopIteration):
         return None
-    if entry.get("workload") != workload or hashlib.sha1(src).hexdigest() != entry["sha1"]:
+    if hashlib.sha1(src).hexdigest() != entry["sha1"]:
         return None
     return round(n_elem * (entry["read_bytes_per_elem"] + entry["write_bytes_per_elem"]))
+
+
+def sort_roofline(kt_timed: dict, breakdown: dict, n_conn: int, counts: dict, workload: str):
+    """Roofline of the dominant radix pass (average launch time from the HIP
+    events of the timed steps) at the sort+index figure of 28 B per
+    connection, and of the whole sort+index phase (every Prepare kernel of
+    the bracketed build: algorithmic bytes over their summed time)."""
+    sort_like = {k: v for k, v in kt_timed.items() if k in ("sort_pass", "sort_pass_final")}
+    if not sort_like or not n_conn:
+        return None
+    name, (launches, ms) = max(sort_like.items(), key=lambda kv: kv[1][1])
+    avg_ms = ms / launches
+    per_launch = BYTES_PER_CONN * n_conn
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    phase_ms = 0.0
+    for k, (_, kms) in breakdown.items():
+        for group, prefixes in PHASES:
+            if group in SORT_INDEX_GROUPS and any(k.startswith(p) for p in prefixes):
+                phase_ms += kms
+                break
+    phase_bytes = BYTES_PER_CONN * n_conn + index_bytes(counts)
+    phase = None
+    if phase_ms > 0:
+        ph = phase_bytes / (phase_ms * 1e-3) / 1e9
+        phase = {"kernels_ms": round(phase_ms, 3), "algorithmic_bytes": phase_bytes, "achieved": round(ph, 1),
+                 "frac": round(ph / PEAK_HBM_GBS, 4),
+                 "bytes_per_conn_algorithmic": round(phase_bytes / n_conn, 3)}
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, n_conn, workload),
+            "kernel": name, "launches_timed": launches, "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_bytes_per_launch": per_launch, "bytes_per_conn": BYTES_PER_CONN,
+            "phase_sort_index": phase}
 
 
 def cpu_baseline(script, budget_conns: float = 1.2e7):
@@ -241,14 +288,88 @@ def exchange(args):
     print(json.dumps(out), flush=True)
 
 
+def _cpu_info() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def _on_one_core(fn):
+    """Run fn() with the calling thread pinned to one CPU (the first one the
+    process may use); returns (result, cpu)."""
+    old = os.sched_getaffinity(0)
+    cpu = min(old)
+    os.sched_setaffinity(0, {cpu})
+    try:
+        return fn(), cpu
+    finally:
+        os.sched_setaffinity(0, old)
+
+
+def served_cpu_baseline(script, work_budget: float = 1.5e8):
+    """The oracle (single-threaded C, one pinned core) on a bounded sample of
+    the served stream: its first requests in submission order while their
+    work (connections, plus a quarter Philox block per tested pair of the
+    Bernoulli requests) fits work_budget, generated and then prepared (sort
+    and first-index array).  No budget binds on this sample."""
+    import oracle
+    creates = [op for op in script["ops"] if op[0] == "create"]
+    reqs = [op for op in script["ops"] if op[0] == "connect"]
+    kept, work = [], 0.0
+    for op in reqs:
+        conn = op[3]
+        ns, nt = sum(g[2] for g in op[1]), sum(g[2] for g in op[2])
+        if conn["rule"] == "pairwise_bernoulli":
+            w = conn["p"] * ns * nt + ns * nt / 4.0
+        elif conn["rule"] == "fixed_indegree":
+            w = nt * conn["n"]
+        elif conn["rule"] == "fixed_outdegree":
+            w = ns * conn["n"]
+        elif conn["rule"] == "fixed_total_number":
+            w = conn["n"]
+        else:
+            w = min(ns, nt)
+        if work + w > work_budget:
+            break
+        work += w
+        kept.append(op)
+    sub = dict(script)
+    sub["ops"] = creates + kept
+
+    def run():
+        t0 = time.perf_counter()
+        net = oracle.run_script(sub, 0, skip_invalid=True)
+        return net, time.perf_counter() - t0
+
+    (net, dt), cpu = _on_one_core(run)
+    n = int(net.array("row_ptr")[-1])
+    info = _cpu_info()
+    return {"value": round(n / dt / 1e9, 6), "unit": "Gconn/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {len(kept)} of the {len(reqs)} requests in submission order ({n} connections, "
+                      f"{len(net.rejected)} rejected as invalid), generated and prepared (sort, first-index array) "
+                      f"in {dt:.1f} s on one core (CPU {cpu} pinned)",
+            **info}
+
+
 def served(args):
     """Served construction of a stream of uneven Connect requests against a
-    resident budget: throughput with all requests arriving at once, per call
-    and in batches (submitted together, one device wait per batch for the
-    admission counts, generated in fused launches), then per-request latency
-    under open-loop Poisson
-    arrivals at half the measured batched capacity; each run ends with the
-    final sort and first-index array (Prepare)."""
+    resident budget.  One step = a fresh context, Create of the 64
+    populations, every request of the stream submitted in batches
+    (snnc_submit_many over `batch` requests, one device wait per batch for
+    the admission counts, then snnc_flush: fused generation launches), and
+    the final Prepare (source-major sort and first-index array) of the
+    admitted network.  The requests are marshalled into the ABI's C structs
+    once, before the timed steps (they are the input).  After the timed
+    steps: one per-call build of the same stream (snnc_connect per request)
+    for comparison, one build with every kernel bracketed for the phase
+    breakdown, and per-request latency under open-loop Poisson arrivals at
+    half the measured batched capacity (one snnc_submit per arrival)."""
     import numpy as np
     import torch
 
@@ -259,111 +380,140 @@ def served(args):
     budget = int(args.budget_gib * 2**30)
     creates = [op for op in script["ops"] if op[0] == "create"]
     reqs = [op for op in script["ops"] if op[0] == "connect"]
+    batch = snnc.RequestBatch([op[1:] for op in reqs])
 
     def fresh():
         net = snnc.Network(1, 0, script["seed"], script["dt"])
         net.set_resident_budget(budget)
-        net.reserve(budget // 14)
+        if args.reserve:
+            net.reserve(budget // 14)
         for op in creates:
             net.create(op[1], op[2])
         return net
 
-    def run(mode, timing=False):
+    def count_status(tally, status):
+        if status not in (0, -1, -3, -5):
+            raise snnc.SnncError(status, "request failed")
+        key = {0: "admitted", -1: "invalid", -3: "over_budget", -5: "unsupported"}[status]
+        tally[key] = tally.get(key, 0) + 1
+
+    def run(mode, timing=0):
+        """one build of the whole stream; timing 1 brackets every kernel
+        launch, 2 the radix passes of Prepare only"""
+        tally = {}
         net = fresh()
-        net.set_timing(timing)   # kernel brackets cost host time per launch: off for the timed runs
+        if timing == 1:
+            net.set_timing(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        t_host = 0.0
-        admitted = 0
         if mode == "batched":
-            # batches of requests submitted together (one device wait for their counts), then flushed
             for k0 in range(0, len(reqs), args.batch):
-                th = time.perf_counter()
-                res = net.submit_many([op[1:] for op in reqs[k0:k0 + args.batch]])
-                t_host += time.perf_counter() - th
-                for status, _ in res:
-                    if status not in (0, -3):
-                        raise snnc.SnncError(status, "request failed")
-                    admitted += status == 0
+                for status, _ in net.submit_batch(batch, k0, k0 + args.batch):
+                    count_status(tally, status)
                 net.flush()
-        for k, op in enumerate(reqs if mode == "per_call" else []):
-            _, src, tgt, conn, syn, alpha = op
-            th = time.perf_counter()
-            try:
-                net.connect(src, tgt, conn, syn, alpha)
-                admitted += 1
-            except snnc.SnncError as e:
-                if e.code != -3:
-                    raise
-            t_host += time.perf_counter() - th
-        net.sync()
-        t_gen = time.perf_counter() - t0
+        else:
+            for i in range(len(reqs)):
+                try:
+                    net.connect_packed(batch, i)
+                    count_status(tally, 0)
+                except snnc.SnncError as e:
+                    count_status(tally, e.code)
+        if timing == 2:
+            net.set_timing(2)
         net.prepare()
         net.sync()
-        t_all = time.perf_counter() - t0
+        dt = time.perf_counter() - t0
         n = net.count("src")
         st = net.stats()
         kt = net.kernel_times() if timing else {}
         net.close()
-        gen_kernels = {k: round(v[1], 2) for k, v in sorted(kt.items(), key=lambda kv: -kv[1][1])
-                       if k.startswith("gen") or k.startswith("fused")}
-        return {"connections": n, "admitted": admitted, "rejected": len(reqs) - admitted, "gen_s": round(t_gen, 4),
-                "total_s": round(t_all, 4), "Gconn_s": round(n / t_all / 1e9, 4),
-                "gen_Gconn_s": round(n / t_gen / 1e9, 4), "sort_passes": st["sort_passes"],
-                "submit_host_s": round(t_host, 4), "gen_kernel_ms": gen_kernels}
+        return dt, n, tally, st, kt
 
-    # warm-up (untimed, with kernel brackets for the breakdown): the first full-size build
-    # also grows the allocator's pool
-    breakdown = run("batched", timing=True)["gen_kernel_ms"]
-    res_b = run("batched")
-    res_p = run("per_call")
-    res_b["gen_kernel_ms"] = breakdown
+    # warm-up (untimed): the first full-size builds also grow the allocator's pool
+    for _ in range(args.warmup):
+        run("batched")
+    torch.cuda.synchronize()
+    times, kt_total = [], {}
+    n_conn, tally, stats = 0, {}, None
+    t_all = time.perf_counter()
+    for _ in range(args.steps):
+        dt, n_conn, tally, stats, kt = run("batched", timing=2)
+        times.append(dt)
+        for k, (l, ms) in kt.items():
+            acc = kt_total.setdefault(k, [0, 0.0])
+            acc[0] += l
+            acc[1] += ms
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    value = n_conn * args.steps / total / 1e9
 
-    # open-loop latency at half the batched capacity (requests per second of generation)
-    cap = res_b["admitted"] / res_b["gen_s"]
+    t_pc, n_pc, tally_pc, _, _ = run("per_call")
+    assert n_pc == n_conn and tally_pc == tally, "per-call and batched builds admitted different requests"
+    _, _, _, _, breakdown = run("batched", timing=1)
+
+    # latency: open-loop arrivals at half the batched capacity
+    cap = len(reqs) * args.steps / total
     lam = 0.5 * cap
     arrival = np.asarray(script["info"]["arrival"]) / lam
     net = fresh()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lat, outstanding, k, last_batch = [], [], 0, None
+    sojourn, service, outstanding, k, last_batch = [], [], [], 0, None
     while k < len(reqs) or outstanding:
         now = time.perf_counter() - t0
         while k < len(reqs) and arrival[k] <= now:
-            _, src, tgt, conn, syn, alpha = reqs[k]
+            ts = time.perf_counter() - t0
             try:
-                cid = net.submit(src, tgt, conn, syn, alpha)
-                outstanding.append((cid, arrival[k]))
+                cid = net.connect_packed(batch, k, submit=True)
+                outstanding.append((cid, arrival[k], ts))
             except snnc.SnncError as e:
-                if e.code != -3:
+                if e.code not in (-1, -3, -5):
                     raise
             k += 1
         if outstanding and (last_batch is None or net.poll(last_batch)):
             net.flush()
             last_batch = outstanding[-1][0]
         still = []
-        for cid, arr in outstanding:
+        for cid, arr, ts in outstanding:
             if net.poll(cid):
-                lat.append(time.perf_counter() - t0 - arr)
+                done = time.perf_counter() - t0
+                sojourn.append(done - arr)
+                service.append(done - ts)
             else:
-                still.append((cid, arr))
+                still.append((cid, arr, ts))
         outstanding = still
         if k < len(reqs) and not outstanding:
             time.sleep(max(0.0, min(arrival[k] - (time.perf_counter() - t0), 0.001)))
     net.prepare()
     net.close()
-    lat_ms = np.asarray(lat) * 1e3
+    soj_ms, svc_ms = np.asarray(sojourn) * 1e3, np.asarray(service) * 1e3
+
+    roof = sort_roofline(kt_total, breakdown, n_conn, {"row_ptr": stats["M_local"] + 1}, "served_requests")
     out = {
         "metric": "connections built+indexed/sec (Gconn/s) on 1 MI355X; p50/p99 Connect latency",
-        "value": res_b["Gconn_s"], "unit": "Gconn/s", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": round(1e3 * res_b["total_s"], 3), "higher_is_better": True, "scaling": "weak",
+        "value": round(value, 4), "unit": "Gconn/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * total / args.steps, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32/u64 int + f64->f32 weights", "data": "synthetic",
-        "config": {"workload": script["name"], "requests": len(reqs), "budget_gib": args.budget_gib,
-                   "offered_connections": script["info"]["offered"], "batch": args.batch},
-        "batched": res_b, "per_call": res_p,
-        "latency": {"lambda_req_per_s": round(lam, 1), "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
-                    "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "n": int(lat_ms.size)},
+        "config": {"workload": "served_requests", "requests": len(reqs), "budget_gib": args.budget_gib,
+                   "populations": len(creates), "neurons": stats["M_local"],
+                   "offered_connections": script["info"]["offered"], "connections": n_conn,
+                   "batch": args.batch, "key_bits": stats["key_bits"], "sort_passes": stats["sort_passes"]},
+        "requests": tally,
+        "step_ms": {"min": round(1e3 * min(times), 3), "median": round(1e3 * sorted(times)[len(times) // 2], 3)},
+        "per_call": {"Gconn_s": round(n_pc / t_pc / 1e9, 4), "ms": round(1e3 * t_pc, 3)},
+        "batched_over_per_call": round(value / (n_pc / t_pc / 1e9), 3),
+        "latency": {"lambda_req_per_s": round(lam, 1), "n": int(soj_ms.size),
+                    "p50_ms": round(float(np.percentile(soj_ms, 50)), 3),
+                    "p99_ms": round(float(np.percentile(soj_ms, 99)), 3),
+                    "service_p50_ms": round(float(np.percentile(svc_ms, 50)), 3),
+                    "service_p99_ms": round(float(np.percentile(svc_ms, 99)), 3)},
+        "phase_ms": phase_times(breakdown, stats),
+        "kernels_ms_per_step": {k: round(v[1], 3) for k, v in sorted(breakdown.items(), key=lambda kv: -kv[1][1])},
+        "roofline": roof,
+        "peak_hbm_bytes": stats["bytes_peak"],
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = served_cpu_baseline(script)
     print(json.dumps(out), flush=True)
 
 
@@ -372,12 +522,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="column8")
+    ap.add_argument("--workload", default="served",
+                    help="served (default: the served request stream), column8, multiarea, collective, indegreeS, "
+                         "balanced, exchange")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=10000)
     ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--reserve", type=int, default=1, choices=[0, 1],
+                    help="served: 1 reserves the generation arrays for the whole budget up front, 0 grows them "
+                         "as requests are admitted")
     ap.add_argument("--map-policy", default=None,
                     help="numbering,sources,xi: numbering 0 canonical / 1 call order; sources 0 used / "
                          "1 threshold / 2 all passed")
@@ -436,7 +591,7 @@ def main():
 
     # timed steps (HIP events on the library stream bracket the radix passes only:
     # a bracket costs host time per launch)
-    times, n_conn, kt_total, stats = [], 0, {}, None
+    times, n_conn, kt_total, stats, counts = [], 0, {}, None, {}
     untimed = 0.0          # reporting work inside the loop that is not part of a step
     host_bytes = 0
     torch.cuda.synchronize()
@@ -452,6 +607,7 @@ def main():
             tq = time.perf_counter()
             host_bytes = sum(net.count(k) * np.dtype(snnc.ARRAYS[k][1]).itemsize for k in snnc.ARRAYS
                              if not k.startswith("gen_") and k != "call_off" and _kept(net, k) and net.on_host(k))
+            counts = {k: net.count(k) for k in snnc.ARRAYS if not k.startswith("gen_") and _kept(net, k)}
             untimed += time.perf_counter() - tq
         for k, (l, ms) in net.kernel_times().items():
             a = kt_total.setdefault(k, [0, 0.0])
@@ -475,16 +631,7 @@ def main():
     # dominant kernel and its roofline
     per_build = breakdown or {k: (v[0] / args.steps, v[1] / args.steps) for k, v in kt_total.items()}
     dom = max(per_build.items(), key=lambda kv: kv[1][1])
-    roof = None
-    sort_like = {k: v for k, v in kt_total.items() if k in ("sort_pass", "sort_pass_final")}
-    if sort_like:
-        name, (launches, ms) = max(sort_like.items(), key=lambda kv: kv[1][1])
-        per = kernel_roofline(name, launches, ms, n_conn, stats["sort_passes"])
-        avg_ms = ms / launches
-        achieved = per / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, n_conn, script["name"]),
-                "kernel": name, "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": per}
+    roof = sort_roofline(kt_total, per_build, n_conn, counts, script["name"])
 
     out = {
         "metric": "connections built+indexed/sec (Gconn/s) on 1 MI355X",

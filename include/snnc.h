@@ -342,6 +342,108 @@ snnc_status snnc_copy_array(snnc_ctx* ctx, int32_t id, void* dst, uint64_t cap_b
  * array. */
 snnc_status snnc_copy_range(snnc_ctx* ctx, int32_t id, uint64_t first, uint64_t count, void* dst);
 
+/* ---------------------------------------------------------------- typed views
+ * Views gather the pointers and sizes of the prepared arrays (no copy, no
+ * device work).  Pointers are device memory except where a GPU memory level
+ * keeps an array in pinned host memory (flagged in the view); they stay
+ * valid until snnc_destroy (nothing mutates a prepared network).  Every view
+ * call returns SNNC_ESTATE before snnc_prepare. */
+
+/* The sorted connections and their first-index array (Methods, "GPU memory
+ * levels": connections stored in blocks sorted by source, with the first
+ * index and the number of outgoing connections of every source; Methods,
+ * point-to-point creation subsection, for the image indices of remote
+ * sources).  src[i] is a local id (< M_local) or an image index (M_local ..
+ * M_local + n_images - 1); connections of a source are contiguous, ordered by
+ * target, ties in generation order.  Row s is [row_ptr[s], row_ptr[s+1]) for
+ * s < n_rows: n_rows = M_local + n_images at levels 2 and 3, M_local at
+ * levels 0 and 1, where image row i is [img_first[i], img_first[i] +
+ * img_count[i]) (host memory, img_rows_on_host = 1); img_count is also
+ * present at level 3 (device).  Absent arrays are NULL. */
+typedef struct {
+    const int32_t* src;        /* [n] */
+    const int32_t* tgt;        /* [n] target local id */
+    const uint16_t* delay;     /* [n] steps of dt */
+    const float* weight;       /* [n] */
+    const uint64_t* row_ptr;   /* [n_rows + 1] */
+    const uint64_t* img_first; /* [n_images] or NULL */
+    const uint32_t* img_count; /* [n_images] or NULL */
+    uint64_t n;
+    uint64_t n_rows;
+    uint64_t n_images;
+    uint32_t M_local;
+    int32_t img_rows_on_host;
+} snnc_conn_view;
+
+snnc_status snnc_get_connections(const snnc_ctx* ctx, snnc_conn_view* out);
+
+/* The image map of remote host sigma for group alpha (map index alpha + 1;
+ * Methods, point-to-point creation subsection: the sorted array of the
+ * remote sources of sigma that have an image on this host, and the map of
+ * each to its image index; collective subsection for alpha >= 0).  *R gets
+ * the n sorted source local ids of sigma, *L (when L is not NULL) their
+ * image indices, *img_base the first image index when the images of the map
+ * are contiguous (canonical numbering: L[i] = img_base + i) and -1 under
+ * call-order numbering.  A map that does not exist (no image, a map index
+ * above the network's groups, sigma = P_local) gives n = 0 and NULL
+ * pointers.  Pointers are into SNNC_R_VAL / SNNC_L_VAL (host memory at GPU
+ * memory levels 0 and 1).  Errors: SNNC_EINVAL for alpha < -1 or sigma >= P,
+ * SNNC_ESTATE before prepare. */
+snnc_status snnc_get_image_map(const snnc_ctx* ctx, int32_t alpha, uint32_t sigma, const int32_t** R, uint64_t* n,
+                               int64_t* img_base, const int32_t** L);
+
+/* The point-to-point send lists (Methods, point-to-point creation
+ * subsection, source-process side; Eq. of the map alignment: S_{tau,P_local}
+ * equals the map R_{tau,P_local} that host tau builds; simulation
+ * preparation: the per-source lists of target hosts and positions).  S_tau =
+ * s_val[s_off[tau] .. s_off[tau+1]), sorted local ids; for local source s,
+ * entries tp_ptr[s] .. tp_ptr[s+1] give (t_val = target host tau, ascending,
+ * p_val = position of s in S_tau).  Device memory. */
+typedef struct {
+    const uint64_t* s_off;   /* [P + 1] */
+    const int32_t* s_val;    /* [n_s] */
+    const uint64_t* tp_ptr;  /* [M_local + 1] */
+    const uint32_t* t_val;   /* [n_tp] */
+    const uint32_t* p_val;   /* [n_tp] */
+    uint64_t n_s, n_tp;
+    uint32_t P, M_local;
+} snnc_p2p_view;
+
+snnc_status snnc_get_p2p_send(const snnc_ctx* ctx, snnc_p2p_view* out);
+
+/* The collective arrays of group alpha >= 0 (Methods, collective
+ * communication subsection): H_{alpha,sigma} = h_val[h_off[sigma] ..
+ * h_off[sigma+1]) for sigma < P (offsets index the whole h_val / i_val
+ * arrays: h_off points at this group's P + 1 entries of SNNC_H_OFF), the
+ * sorted union of the sigma-sources passed to the group's calls; i_val
+ * aligned with h_val: the image index of that source on this host or -1
+ * (always -1 for sigma = P_local); and, over all groups, for local source s
+ * the entries gq_ptr[s] .. gq_ptr[s+1] of (g_val = group id, q_val =
+ * position of s in H_{group,P_local}).  rank = the group's rank in
+ * SNNC_GROUPS; on_host = 1 when H and I live in pinned host memory (GPU
+ * memory levels 0 and 1).  Errors: SNNC_EINVAL for alpha < 0 or a group
+ * without calls, SNNC_ESTATE before prepare. */
+typedef struct {
+    const uint64_t* h_off;   /* [P + 1] */
+    const int32_t* h_val;    /* [n_h], all groups */
+    const int32_t* i_val;    /* [n_h], all groups */
+    const uint64_t* gq_ptr;  /* [M_local + 1] */
+    const int32_t* g_val;    /* [n_gq] */
+    const uint32_t* q_val;   /* [n_gq] */
+    uint64_t n_h, n_gq;
+    int32_t alpha;
+    uint32_t rank, P, M_local;
+    int32_t on_host;
+} snnc_coll_view;
+
+snnc_status snnc_get_collective(const snnc_ctx* ctx, int32_t alpha, snnc_coll_view* out);
+
+/* Copy a whole array into caller host memory of `bytes` (at least the
+ * array's size; snnc_get_array gives its element count), waiting for
+ * completion; the caller owns dst.  Errors: SNNC_EINVAL (dst NULL with bytes
+ * > 0, or bytes too small), SNNC_ESTATE as snnc_get_array. */
+snnc_status snnc_copy_to_host(const snnc_ctx* ctx, int32_t id, void* dst, uint64_t bytes);
+
 /* Counters of the context. */
 typedef struct {
     uint64_t n_connections;   /* local-share connections generated       */

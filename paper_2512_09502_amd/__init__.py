@@ -86,10 +86,31 @@ EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_cr
            "snnc_stats", "snnc_set_timing", "snnc_kernel_times", "snnc_delay_table", "snnc_philox_blocks",
            "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_submit_many", "snnc_flush", "snnc_poll",
            "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver",
-           "snnc_connect_assigned", "snnc_set_memory_level", "snnc_array_on_host"]
+           "snnc_connect_assigned", "snnc_set_memory_level", "snnc_array_on_host", "snnc_get_connections",
+           "snnc_get_image_map", "snnc_get_p2p_send", "snnc_get_collective", "snnc_copy_to_host"]
 
 _lib = None
 
+
+_P = ctypes.c_void_p
+_U64, _U32, _I32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+
+
+class ConnView(ctypes.Structure):
+    _fields_ = [("src", _P), ("tgt", _P), ("delay", _P), ("weight", _P), ("row_ptr", _P), ("img_first", _P),
+                ("img_count", _P), ("n", _U64), ("n_rows", _U64), ("n_images", _U64), ("M_local", _U32),
+                ("img_rows_on_host", _I32)]
+
+
+class P2PView(ctypes.Structure):
+    _fields_ = [("s_off", _P), ("s_val", _P), ("tp_ptr", _P), ("t_val", _P), ("p_val", _P), ("n_s", _U64),
+                ("n_tp", _U64), ("P", _U32), ("M_local", _U32)]
+
+
+class CollView(ctypes.Structure):
+    _fields_ = [("h_off", _P), ("h_val", _P), ("i_val", _P), ("gq_ptr", _P), ("g_val", _P), ("q_val", _P),
+                ("n_h", _U64), ("n_gq", _U64), ("alpha", _I32), ("rank", _U32), ("P", _U32), ("M_local", _U32),
+                ("on_host", _I32)]
 
 def lib():
     """Load libsnnc.so (raises if it has not been built)."""
@@ -135,6 +156,12 @@ def lib():
         L.snnc_poll.argtypes = [vp, u32, ctypes.POINTER(ctypes.c_int32)]
         L.snnc_autotune_sort.argtypes = [vp, u64, u32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                          ctypes.POINTER(ctypes.c_float)]
+        L.snnc_get_connections.argtypes = [vp, ctypes.POINTER(ConnView)]
+        L.snnc_get_image_map.argtypes = [vp, i32, u32, ctypes.POINTER(vp), ctypes.POINTER(u64),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(vp)]
+        L.snnc_get_p2p_send.argtypes = [vp, ctypes.POINTER(P2PView)]
+        L.snnc_get_collective.argtypes = [vp, i32, ctypes.POINTER(CollView)]
+        L.snnc_copy_to_host.argtypes = [vp, i32, vp, u64]
         for name in EXPORTS:
             getattr(L, name).restype = st if name != "snnc_last_error" else ctypes.c_char_p
         # connect and submit with their structs passed as plain addresses into
@@ -189,6 +216,53 @@ def delay_table(mean: float, sd: float, lo: float, dt: float):
     if st != 0:
         return None
     return int(klo.value), buf[: n.value].copy()
+
+
+class RequestBatch:
+    """Connect requests marshalled once into the C structs of the ABI
+    (snnc_nodeset, snnc_conn_spec, snnc_syn_spec and alpha arrays; segments
+    in one array), so that snnc_submit_many or snnc_connect can take any
+    range of them by pointer.  requests: (src, tgt, conn, syn) or (src, tgt,
+    conn, syn, alpha) tuples; alpha defaults to `alpha` (else -1)."""
+
+    def __init__(self, requests, alpha: int | None = None):
+        n = len(requests)
+        nseg = sum(len(r[0]) + len(r[1]) for r in requests)
+        self.n = n
+        self.segs = (Segment * max(1, nseg))()
+        self.S = (NodeSet * max(1, n))()
+        self.T = (NodeSet * max(1, n))()
+        self.C = (ConnSpec * max(1, n))()
+        self.Y = (SynSpec * max(1, n))()
+        self.A = (ctypes.c_int32 * max(1, n))()
+        base = ctypes.addressof(self.segs)
+        k = 0
+        try:
+            for i, r in enumerate(requests):
+                src, tgt, conn, syn = r[:4]
+                if conn["rule"] == "assigned_nodes":
+                    raise SnncError(-1, "assigned nodes take their pairs through connect_assigned")
+                for dst, group in ((self.S, src), (self.T, tgt)):
+                    dst[i].seg = ctypes.cast(base + 12 * k, ctypes.POINTER(Segment))
+                    dst[i].n_seg = len(group)
+                    for h, f, m in group:
+                        self.segs[k].host, self.segs[k].first, self.segs[k].n = int(h), int(f), int(m)
+                        k += 1
+                self.C[i] = ConnSpec(RULES[conn["rule"]], int(conn.get("autapses", True)),
+                                     int(conn.get("multapses", True)), 0, int(conn.get("n", 0)),
+                                     float(conn.get("p", 0.0)))
+                self.Y[i] = SynSpec(_dist(syn.get("weight")), _dist(syn.get("delay")), int(syn.get("port", 0)), 0)
+                self.A[i] = int(r[4] if len(r) > 4 else (-1 if alpha is None else alpha))
+        except (OverflowError, TypeError, ValueError) as err:
+            raise SnncError(-1, f"request argument out of range: {err}") from None
+
+    def __len__(self):
+        return self.n
+
+    def at(self, which: str, i: int):
+        """Address of element i of array S, T, C, Y or A."""
+        arr = getattr(self, which)
+        return ctypes.c_void_p(ctypes.addressof(arr) + i * ctypes.sizeof(arr._type_))
 
 
 class Network:
@@ -302,38 +376,29 @@ class Network:
     def submit_many(self, requests, alpha: int | None = None):
         """Served mode, several requests with one device wait for their counts:
         requests is a list of (src, tgt, conn, syn) or (src, tgt, conn, syn,
-        alpha).  Returns one (status, call_id) per request: status 0 when
-        admitted, else the request's error code (-3 over budget), call_id
-        None when not admitted."""
-        n = len(requests)
-        nseg = sum(len(r[0]) + len(r[1]) for r in requests)
-        segs = (Segment * max(1, nseg))()
-        S = (NodeSet * max(1, n))()
-        T = (NodeSet * max(1, n))()
-        C = (ConnSpec * max(1, n))()
-        Y = (SynSpec * max(1, n))()
-        A = (ctypes.c_int32 * max(1, n))()
-        base = ctypes.addressof(segs)
-        k = 0
-        try:
-            for i, r in enumerate(requests):
-                src, tgt, conn, syn = r[:4]
-                for dst, group in ((S, src), (T, tgt)):
-                    dst[i].seg = ctypes.cast(base + 12 * k, ctypes.POINTER(Segment))
-                    dst[i].n_seg = len(group)
-                    for h, f, m in group:
-                        segs[k].host, segs[k].first, segs[k].n = int(h), int(f), int(m)
-                        k += 1
-                C[i] = ConnSpec(RULES[conn["rule"]], int(conn.get("autapses", True)), int(conn.get("multapses", True)),
-                                0, int(conn.get("n", 0)), float(conn.get("p", 0.0)))
-                Y[i] = SynSpec(_dist(syn.get("weight")), _dist(syn.get("delay")), int(syn.get("port", 0)), 0)
-                A[i] = int(r[4] if len(r) > 4 else (-1 if alpha is None else alpha))
-        except (OverflowError, TypeError, ValueError) as err:
-            raise SnncError(-1, f"request argument out of range: {err}") from None
+        alpha), or a RequestBatch.  Returns one (status, call_id) per request:
+        status 0 when admitted, else the request's error code (-3 over
+        budget), call_id None when not admitted."""
+        batch = requests if isinstance(requests, RequestBatch) else RequestBatch(requests, alpha)
+        return self.submit_batch(batch, 0, len(batch))
+
+    def submit_batch(self, batch: "RequestBatch", lo: int, hi: int):
+        """snnc_submit_many over requests [lo, hi) of a packed RequestBatch."""
+        n = max(0, min(hi, len(batch)) - lo)
         st = (ctypes.c_int32 * max(1, n))()
         ids = (ctypes.c_uint32 * max(1, n))()
-        self._check(lib().snnc_submit_many(self._h, n, S, T, C, Y, A, st, ids))
+        self._check(lib().snnc_submit_many(self._h, n, batch.at("S", lo), batch.at("T", lo), batch.at("C", lo),
+                                           batch.at("Y", lo), batch.at("A", lo), st, ids))
         return [(int(st[i]), int(ids[i]) if st[i] == 0 else None) for i in range(n)]
+
+    def connect_packed(self, batch: "RequestBatch", i: int, submit: bool = False) -> int:
+        """snnc_connect (or, with submit, snnc_submit) of request i of a packed
+        RequestBatch."""
+        cid = ctypes.c_uint32()
+        self._check(lib().packed["snnc_submit" if submit else "snnc_connect"](self._h, batch.at("S", i).value, batch.at("T", i).value,
+                                                 batch.at("C", i).value, batch.at("Y", i).value, int(batch.A[i]),
+                                                 ctypes.addressof(cid)))
+        return int(cid.value)
 
     def flush(self):
         self._check(lib().snnc_flush(self._h))
@@ -371,6 +436,13 @@ class Network:
     def sync(self):
         self._check(lib().snnc_sync(self._h))
 
+    def array_ptr(self, name: str) -> tuple:
+        """(pointer, element count) that snnc_get_array hands out for an array."""
+        which, _ = ARRAYS[name]
+        p, n = ctypes.c_void_p(), ctypes.c_uint64()
+        self._check(lib().snnc_get_array(self._h, which, ctypes.byref(p), ctypes.byref(n)))
+        return p.value, int(n.value)
+
     def count(self, name: str) -> int:
         which, _ = ARRAYS[name]
         p, n = ctypes.c_void_p(), ctypes.c_uint64()
@@ -400,6 +472,52 @@ class Network:
         out = torch.empty(n, dtype=tdt, device=f"cuda:{self.device}")
         self._check(lib().snnc_copy_array(self._h, which, ctypes.c_void_p(out.data_ptr()), out.numel() * out.element_size()))
         return out
+
+    def connections_view(self) -> dict:
+        """snnc_get_connections: pointers (addresses) and sizes of the sorted
+        connections and their first-index array."""
+        v = ConnView()
+        self._check(lib().snnc_get_connections(self._h, ctypes.byref(v)))
+        return {f: getattr(v, f) for f, _ in ConnView._fields_}
+
+    def image_map(self, alpha: int, sigma: int) -> dict:
+        """snnc_get_image_map of (alpha, sigma): R, L as host copies (read
+        through the returned pointers), img_base and the pointers."""
+        R, L = ctypes.c_void_p(), ctypes.c_void_p()
+        n, base = ctypes.c_uint64(), ctypes.c_int64()
+        self._check(lib().snnc_get_image_map(self._h, int(alpha), int(sigma), ctypes.byref(R), ctypes.byref(n),
+                                             ctypes.byref(base), ctypes.byref(L)))
+        return {"R_ptr": R.value, "L_ptr": L.value, "n": int(n.value), "img_base": int(base.value),
+                "R": self._read(R.value, int(n.value), np.int32, "r_val"),
+                "L": self._read(L.value, int(n.value), np.int32, "l_val")}
+
+    def p2p_send(self) -> dict:
+        v = P2PView()
+        self._check(lib().snnc_get_p2p_send(self._h, ctypes.byref(v)))
+        return {f: getattr(v, f) for f, _ in P2PView._fields_}
+
+    def collective(self, alpha: int) -> dict:
+        v = CollView()
+        self._check(lib().snnc_get_collective(self._h, int(alpha), ctypes.byref(v)))
+        return {f: getattr(v, f) for f, _ in CollView._fields_}
+
+    def copy_to_host(self, name: str) -> np.ndarray:
+        """snnc_copy_to_host of a whole array into a new numpy array."""
+        which, dt = ARRAYS[name]
+        out = np.zeros(self.count(name), dt)
+        self._check(lib().snnc_copy_to_host(self._h, which, out.ctypes.data if out.size else None, out.nbytes))
+        return out
+
+    def _read(self, ptr, n: int, dtype, name: str) -> np.ndarray:
+        """Host copy of n elements at a pointer into array `name` that a view
+        handed out (through snnc_copy_range at the pointer's offset)."""
+        if not n or not ptr:
+            return np.zeros(0, dtype)
+        base = ctypes.c_void_p()
+        cnt = ctypes.c_uint64()
+        self._check(lib().snnc_get_array(self._h, ARRAYS[name][0], ctypes.byref(base), ctypes.byref(cnt)))
+        first = (ptr - base.value) // np.dtype(dtype).itemsize
+        return self.array_range(name, int(first), n)
 
     def stats(self) -> dict:
         s = Stats()

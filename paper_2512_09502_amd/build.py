@@ -13,7 +13,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsnnc.so")
-SOURCES = ["api.hip", "gen.hip", "scan.hip", "sort.hip", "prepare.hip", "spikes.hip"]
+SOURCES = ["api.hip", "gen.hip", "scan.hip", "sort.hip", "prepare.hip", "spikes.hip", "views.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -184,10 +184,12 @@ def served_requests(n_requests: int = 10000, n_pops: int = 64, pop_min: int = 10
     in-degree: n_t = min(N_t, S) targets, K = max(1, S // n_t); out-degree:
     the mirror; total number: N = S; one-to-one: n = min(S, N_s, N_t);
     Bernoulli: p ~ U(0.001, 0.2) on the first n_t = min(N_t, ceil(sqrt(S/p)))
-    targets and n_s = min(N_s, ceil(S / (p n_t))) sources.  Without
-    multapses the degree is capped at min(8192, candidates) and the total
-    number at half the pairs.  Poisson arrival times for an offered rate of
-    one request per unit time are in info['arrival']."""
+    targets and n_s = min(N_s, ceil(S / (p n_t))) sources.  No parameter
+    is trimmed to what the library accepts: a degree above the candidates or
+    a total number above the pairs without multapses is invalid, a degree
+    above the library's limit without multapses unsupported, and the library
+    rejects such requests (the stream goes on).  Poisson arrival times for
+    an offered rate of one request per unit time are in info['arrival']."""
     rng = np.random.default_rng(seed)
     sizes = np.exp(rng.uniform(math.log(pop_min), math.log(pop_max), size=n_pops)).astype(np.int64)
     b = _Builder(1)
@@ -206,19 +208,15 @@ def served_requests(n_requests: int = 10000, n_pops: int = 64, pop_min: int = 10
         if rule == "fixed_indegree":
             nt = min(Nj, S)
             K = max(1, S // nt)
-            if not mult:
-                K = min(K, 8192, Ni - 1)
             src, tgt, conn["n"] = [(h, fi, Ni)], [(h, fj, nt)], K
             offered += nt * K
         elif rule == "fixed_outdegree":
             ns = min(Ni, S)
             K = max(1, S // ns)
-            if not mult:
-                K = min(K, 8192, Nj - 1)
             src, tgt, conn["n"] = [(h, fi, ns)], [(h, fj, Nj)], K
             offered += ns * K
         elif rule == "fixed_total_number":
-            N = S if mult else min(S, Ni * Nj // 2)
+            N = S
             src, tgt, conn["n"] = [(h, fi, Ni)], [(h, fj, Nj)], N
             offered += N
         elif rule == "one_to_one":

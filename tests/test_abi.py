@@ -60,3 +60,37 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(snnc.Dist) == 32
     assert ctypes.sizeof(snnc.SynSpec) == 72
     assert ctypes.sizeof(snnc.Stats) == 64
+
+
+def test_view_struct_layouts_match_the_c_compiler(tmp_path):
+    # offsets and sizes of the view structs as gcc lays out include/snnc.h,
+    # against the binding's ctypes declarations
+    views = {"snnc_conn_view": snnc.ConnView, "snnc_p2p_view": snnc.P2PView, "snnc_coll_view": snnc.CollView,
+             "snnc_stats_t": snnc.Stats, "snnc_conn_spec": snnc.ConnSpec, "snnc_syn_spec": snnc.SynSpec}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{os.path.join(ROOT, "include", "snnc.h")}"',
+             "int main(void) {"]
+    for cname, cls in views.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c11", "-o", str(exe), str(src)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in views.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_views_reject_null_arguments_without_a_device():
+    L = snnc.lib()
+    assert L.snnc_get_connections(None, None) == -1
+    assert L.snnc_get_p2p_send(None, None) == -1
+    assert L.snnc_get_collective(None, 0, None) == -1
+    assert L.snnc_copy_to_host(None, 10, None, 0) == -1
+    assert L.snnc_get_image_map(None, 0, 0, None, None, None, None) == -1

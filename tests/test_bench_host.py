@@ -43,7 +43,7 @@ def test_traffic_table_follows_the_sort_source():
     # the committed counters are used only while the kernel source they were taken on is unchanged
     import hashlib
     t = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    e = t["sort_pass"]
+    e = next(x for x in t["entries"] if x["kernel"] == "sort_pass")
     n = 408483244
     got = bench.measured_traffic("sort_pass", n, e["workload"])
     sha = hashlib.sha1(open(os.path.join(ROOT, e["source"]), "rb").read()).hexdigest()
@@ -52,3 +52,21 @@ def test_traffic_table_follows_the_sort_source():
     else:
         assert got is None
     assert bench.measured_traffic("sort_pass", n, "some_other_workload") is None
+
+
+def test_sort_roofline_figures():
+    # dominant pass at 28 B per connection over its average launch time; the
+    # phase figure sums every Prepare kernel of the bracketed build
+    n = 10**9
+    timed = {"sort_pass": (8, 80.0), "sort_pass_final": (2, 24.0), "gen_fused": (5, 400.0)}
+    breakdown = {"prep_keys": (1, 5.0), "sort_pass": (4, 40.0), "sort_pass_final": (1, 12.0), "prep_csr": (1, 1.0),
+                 "gen_fused": (3, 100.0)}
+    r = bench.sort_roofline(timed, breakdown, n, {"row_ptr": 1001}, "no_such_workload")
+    assert r["kernel"] == "sort_pass" and r["avg_launch_ms"] == 10.0
+    assert r["achieved"] == pytest.approx(28 * n / 10e-3 / 1e9, rel=1e-6)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, abs=1e-4)
+    assert r["traffic"] is None
+    ph = r["phase_sort_index"]
+    assert ph["kernels_ms"] == 58.0
+    assert ph["algorithmic_bytes"] == 28 * n + 8 * 1001
+    assert bench.index_bytes({"row_ptr": 3, "r_val": 2, "i_val": 5, "tp_ptr": 4}) == 8 * 3 + 4 * 7 + 8 * 4
