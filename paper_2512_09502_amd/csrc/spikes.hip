@@ -29,6 +29,16 @@ static uint32_t* err_word(Ctx& c) {
     return reinterpret_cast<uint32_t*>(c.tot_pin_dev + 2);
 }
 
+// status word of the packet sort's look-back waits (mapped pinned memory,
+// cleared here while no kernel of the context runs)
+static uint32_t* sort_status_word(Ctx& c) {
+    *reinterpret_cast<volatile uint32_t*>(c.tot_pin + 3) = 0u;
+    return reinterpret_cast<uint32_t*>(c.tot_pin_dev + 3);
+}
+
+// after the stream's final wait: whether a look-back wait gave up
+bool sort_status_failed(Ctx& c) { return *reinterpret_cast<volatile uint32_t*>(c.tot_pin + 3) != 0u; }
+
 // records per spike; spike ids beyond M set the error word
 __global__ __launch_bounds__(SNT) void k_spike_deg(const uint32_t* spikes, uint64_t n, uint32_t M, const uint64_t* ptr,
                                                    uint32_t* deg, uint32_t* err) {
@@ -212,8 +222,19 @@ uint64_t spike_packets(Ctx& c, int kind, const uint32_t* spikes, const uint32_t*
                                groups, n_groups, rec_off, k0, v0);
             tstop(c);
             HIPCHK(hipGetLastError());
-            const int w = radix_sort(c, k0, v0, k1, v1, total, 32, 32 + bits_for_values(n_dest), nullptr, nullptr,
-                                     false);   // every pass runs: no wait for the digit histograms
+            // a look-back wait that gives up flags the sort's status word: here the
+            // fourth mapped pinned word, read after the final wait below
+            uint32_t* const saved_status = c.d_status;
+            c.d_status = sort_status_word(c);
+            int w = 0;
+            try {
+                w = radix_sort(c, k0, v0, k1, v1, total, 32, 32 + bits_for_values(n_dest), nullptr, nullptr,
+                               false);   // every pass runs: no wait for the digit histograms
+            } catch (...) {
+                c.d_status = saved_status;
+                throw;
+            }
+            c.d_status = saved_status;
             const uint64_t* ks = w ? k1 : k0;
             const uint32_t* vs = w ? v1 : v0;
             tstart(c, "spike_packets");
@@ -227,6 +248,7 @@ uint64_t spike_packets(Ctx& c, int kind, const uint32_t* spikes, const uint32_t*
             HIPCHK(hipMemsetAsync(off, 0, ((uint64_t)n_dest + 1) * 8, c.stream));
         }
         sync(c);
+        if (sort_status_failed(c)) raise(SNNC_EDEVICE, "a look-back wait of the packet sort exceeded its bound");
     } catch (...) {
         for (void* p : temps) dfree(c, p);
         throw;
