@@ -590,6 +590,27 @@ snnc_status snnc_deliver(snnc_ctx* ctx, int32_t kind, const uint32_t* grp, const
 snnc_status snnc_sort_pairs(snnc_ctx* ctx, uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp,
                             uint64_t n, uint32_t bit_lo, uint32_t bit_hi, int32_t* result_in_tmp);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * snnc_sort_pairs (same arguments, same result) without any allocation.  The
+ * digit histograms, tile counters, status word and look-back table live in
+ * one static device array of 16 MiB per GPU owned by the library (set up by
+ * the first snnc_init on that GPU and held until the process ends); the
+ * caller passes keys, vals and the keys_tmp/vals_tmp ping-pong buffers as
+ * for snnc_sort_pairs.  Limit: the look-back table (tiles x digit buckets x
+ * 8 B, tiles of the context's sort variant, 8192 pairs by default) must fit
+ * 16 MiB - 64.25 KiB: about 33 million pairs with 9-bit digits and 67 million
+ * with 8-bit digits at the default tile; larger n returns SNNC_EINVAL before
+ * any device work.  Every call on a GPU shares that GPU's array and keeps its
+ * contents between calls (the library clears what must start at zero);
+ * calls are serialised by a host lock and each waits for its sort, so calls
+ * from several contexts or threads do not overlap on the array.  No timing
+ * brackets are recorded.  Errors: as snnc_sort_pairs, SNNC_ESTATE if the
+ * device's scratch was not set up (no snnc_init on it). */
+snnc_status snnc_sort_pairs_noalloc(snnc_ctx* ctx, uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
+                                    uint32_t* vals_tmp, uint64_t n, uint32_t bit_lo, uint32_t bit_hi,
+                                    int32_t* result_in_tmp);
+
 /* The delay-step table of a NORMAL(mean, sd) delay clipped at lo (ms) for
  * time step dt (ms): k_lo = round(lo / dt) and thresholds
  * t_k = ceil(Phi(((k + 1/2) dt - mean) / sd) 2^32) for k = k_lo, k_lo+1, ...

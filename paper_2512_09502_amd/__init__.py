@@ -87,7 +87,8 @@ EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_cr
            "snnc_tune", "snnc_sort_pairs", "snnc_set_resident_budget", "snnc_submit", "snnc_submit_many", "snnc_flush", "snnc_poll",
            "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver",
            "snnc_connect_assigned", "snnc_set_memory_level", "snnc_array_on_host", "snnc_get_connections",
-           "snnc_get_image_map", "snnc_get_p2p_send", "snnc_get_collective", "snnc_copy_to_host"]
+           "snnc_get_image_map", "snnc_get_p2p_send", "snnc_get_collective", "snnc_copy_to_host",
+           "snnc_sort_pairs_noalloc"]
 
 _lib = None
 
@@ -147,6 +148,7 @@ def lib():
         L.snnc_philox_blocks.argtypes = [vp, u32, u32, u64, u32, u64, vp]
         L.snnc_tune.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
         L.snnc_sort_pairs.argtypes = [vp, vp, vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int32)]
+        L.snnc_sort_pairs_noalloc.argtypes = L.snnc_sort_pairs.argtypes
         L.snnc_set_resident_budget.argtypes = [vp, u64]
         L.snnc_submit.argtypes = L.snnc_connect.argtypes
         L.snnc_connect_assigned.argtypes = [vp, ctypes.POINTER(NodeSet), ctypes.POINTER(NodeSet), vp, vp, u64,
@@ -613,6 +615,17 @@ class Network:
                                           ctypes.c_void_p(kt.data_ptr()), ctypes.c_void_p(vt.data_ptr()),
                                           keys.numel(), bit_lo, bit_hi, ctypes.byref(where)))
         return (kt, vt) if where.value else (keys, vals)
+
+    def sort_pairs_noalloc(self, keys, vals, keys_tmp, vals_tmp, bit_lo: int, bit_hi: int):
+        """snnc_sort_pairs_noalloc on caller tensors (keys int64, vals int32,
+        and ping-pong buffers of the same sizes); the library allocates
+        nothing.  Returns the (keys, vals) pair that holds the result."""
+        where = ctypes.c_int32()
+        self._check(lib().snnc_sort_pairs_noalloc(
+            self._h, ctypes.c_void_p(keys.data_ptr()), ctypes.c_void_p(vals.data_ptr()),
+            ctypes.c_void_p(keys_tmp.data_ptr()), ctypes.c_void_p(vals_tmp.data_ptr()), keys.numel(), bit_lo, bit_hi,
+            ctypes.byref(where)))
+        return (keys_tmp, vals_tmp) if where.value else (keys, vals)
 
     def philox_blocks(self, seed: int, call_id: int, e_begin: int, purpose: int, n: int) -> np.ndarray:
         torch = self._torch

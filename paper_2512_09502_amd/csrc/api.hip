@@ -924,6 +924,7 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
         c->d_status = dalloc_n<uint32_t>(*c, 1);
         HIPCHK(hipMemsetAsync(c->d_status, 0, 4, c->stream));
         sync(*c);
+        noalloc_setup(*c);   // device address of the allocation-free sort's static scratch
     });
     if (st != SNNC_OK) {
         snnc_destroy(c);

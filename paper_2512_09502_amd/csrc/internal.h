@@ -371,6 +371,9 @@ struct FinalOut {
 // wait_for_plan: read the digit histograms back to skip passes whose digit is
 // the same for every key (a wait on the stream); false runs every pass
 // without waiting (the result is the same: such a pass keeps the order).
+// takes the device address of the allocation-free sort's static scratch
+// (once per device; called by snnc_init with the context's device current)
+void noalloc_setup(Ctx& c);
 int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, uint64_t n,
                uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist /* may be null */,
                const FinalOut* final_out, bool wait_for_plan = true);

@@ -9,6 +9,7 @@
 // thread) are template variants; the context picks one (tunable).
 #include <algorithm>
 #include <map>
+#include <mutex>
 
 #include "device_common.h"
 #include "internal.h"
@@ -481,41 +482,90 @@ void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint
     HIPCHK(hipGetLastError());
 }
 
-int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, uint64_t n,
-               uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist, const FinalOut* final_out,
-               bool wait_for_plan) {
+namespace {
+
+__global__ void k_fill_words(uint64_t* p, uint64_t n, uint64_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// clears n 64-bit words with a kernel (no memset node in a captured stream)
+void fill_words(Ctx& c, uint64_t* p, uint64_t n) {
+    if (!n) return;
+    const unsigned grid = (unsigned)std::min<uint64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_words, dim3(grid), dim3(256), 0, c.stream, p, n, 0ull);
+    HIPCHK(hipGetLastError());
+}
+
+// Scratch of a sort that allocates nothing: digit histograms and offsets,
+// tile counters, a status word and the look-back table, all at fixed
+// addresses; the look-back epoch persists with the table.
+struct FixedScratch {
+    uint64_t* hist;
+    uint64_t* off;
+    uint32_t* counter;
+    uint32_t* status;
+    void* lookback;
+    size_t lookback_bytes;
+    uint32_t* epoch;
+};
+
+int radix_sort_impl(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, uint64_t n,
+                    uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist, const FinalOut* final_out,
+                    bool wait_for_plan, const FixedScratch* fs) {
     const SortPlan plan = plan_sort(c, n, bit_hi > bit_lo ? bit_hi - bit_lo : 0);
     const uint32_t passes = plan.passes, dbits = plan.dbits;
-    const int variant = plan.variant, mode = plan.mode;
+    // the reduce-then-scan passes allocate per-tile counts: fixed scratch takes onesweep passes
+    const int variant = plan.variant, mode = fs ? 0 : plan.mode;
     const uint32_t rb = plan.wide ? 512 : RADIX;
     if (passes > 8) raise(SNNC_EUNSUPPORTED, "radix sort over more than 64 bits");
     const uint64_t tile = (uint64_t)VARIANTS[variant].nt * VARIANTS[variant].ipt;
-    std::vector<void*> temps;
+    const uint64_t tiles = (n + tile - 1) / tile;
+    if (fs && passes && n && (size_t)tiles * rb * 8 > fs->lookback_bytes)
+        raise(SNNC_EINVAL, "sort of " + std::to_string(n) + " keys needs a look-back table of " +
+                               std::to_string((size_t)tiles * rb * 8) + " bytes, above the " +
+                               std::to_string(fs->lookback_bytes) + " of the static scratch");
+    void* temps[3] = {nullptr, nullptr, nullptr};
     auto cleanup = [&] {
         for (void* p : temps) dfree(c, p);
     };
+    uint32_t* status = fs ? fs->status : c.d_status;
+    void* lookback = fs ? fs->lookback : c.lookback;
+    uint32_t& epoch = fs ? *fs->epoch : c.sort_epoch;
+    const size_t lookback_bytes = fs ? fs->lookback_bytes : 0;
     int cur = 0;
     try {
-        const uint64_t tiles = (n + tile - 1) / tile;
-        std::vector<uint64_t> hh((size_t)passes * HSTRIDE, 0);
+        uint64_t hh[8 * HSTRIDE];
+        memset(hh, 0, sizeof hh);
         uint64_t* off = nullptr;
         if (passes && n) {
             uint64_t* hist = const_cast<uint64_t*>(digit_hist);
-            if (!hist) {
+            if (!hist && fs) {
+                hist = fs->hist;
+                fill_words(c, hist, (uint64_t)passes * HSTRIDE);
+                const uint32_t grid = (uint32_t)std::min<uint64_t>((n + HNT - 1) / HNT, 4096);
+                hipLaunchKernelGGL(k_hist, dim3(grid), dim3(HNT), 0, c.stream, keys0, n, bit_lo, bit_hi, plan.n9, dbits,
+                                   passes, hist);
+                HIPCHK(hipGetLastError());
+            } else if (!hist) {
                 hist = dalloc_n<uint64_t>(c, (uint64_t)passes * HSTRIDE);
-                temps.push_back(hist);
+                temps[0] = hist;
                 launch_hist(c, keys0, n, bit_lo, bit_hi, plan.n9, dbits, passes, hist);
             }
-            off = dalloc_n<uint64_t>(c, (uint64_t)passes * HSTRIDE);
-            temps.push_back(off);
+            if (fs) {
+                off = fs->off;
+            } else {
+                off = dalloc_n<uint64_t>(c, (uint64_t)passes * HSTRIDE);
+                temps[1] = off;
+            }
             tstart(c, "sort_hist_scan");
             hipLaunchKernelGGL(k_hist_scan, dim3(passes), dim3(HSTRIDE), 0, c.stream, hist, off);
             tstop(c);
             HIPCHK(hipGetLastError());
-            if (wait_for_plan) download(c, hh.data(), hist, hh.size() * 8);
+            if (wait_for_plan) download(c, hh, hist, (size_t)passes * HSTRIDE * 8);
             // look-back table: tiles x buckets status words, zeroed once when (re)allocated
             const size_t need = (size_t)tiles * rb * 8;
-            if (c.lookback_bytes < need) {
+            if (!fs && c.lookback_bytes < need) {
                 dfree(c, c.lookback);
                 c.lookback = nullptr;
                 c.lookback_bytes = 0;
@@ -523,32 +573,41 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
                 c.lookback_bytes = need;
                 HIPCHK(hipMemsetAsync(c.lookback, 0, need, c.stream));
                 c.sort_epoch = 0;
+                lookback = c.lookback;
             }
         }
-        uint32_t* counter = dalloc_n<uint32_t>(c, std::max<uint32_t>(passes, 1));
-        temps.push_back(counter);
-        HIPCHK(hipMemsetAsync(counter, 0, std::max<uint32_t>(passes, 1) * 4, c.stream));
+        uint32_t* counter;
+        if (fs) {
+            counter = fs->counter;
+            fill_words(c, reinterpret_cast<uint64_t*>(counter), 4);   // 8 tile counters
+        } else {
+            counter = dalloc_n<uint32_t>(c, std::max<uint32_t>(passes, 1));
+            temps[2] = counter;
+            HIPCHK(hipMemsetAsync(counter, 0, std::max<uint32_t>(passes, 1) * 4, c.stream));
+        }
         // passes whose digit is the same for every key leave the order unchanged
-        std::vector<uint32_t> live;
+        uint32_t live[8];
+        uint32_t n_live = 0;
         for (uint32_t p = 0; p < passes; ++p) {
             bool trivial = false;
             for (int b = 0; b < HSTRIDE; ++b)
                 if (hh[(size_t)p * HSTRIDE + b] == n) trivial = true;
-            if (!trivial) live.push_back(p);
+            if (!trivial) live[n_live++] = p;
         }
-        c.sort_passes = (uint32_t)live.size();
+        c.sort_passes = n_live;
         uint64_t* kb[2] = {keys0, keys1};
         uint32_t* vb[2] = {vals0, vals1};
-        for (size_t li = 0; li < live.size(); ++li) {
+        for (uint32_t li = 0; li < n_live; ++li) {
             const uint32_t p = live[li];
-            if (++c.sort_epoch > EPOCH_MAX) {
-                HIPCHK(hipMemsetAsync(c.lookback, 0, c.lookback_bytes, c.stream));
-                c.sort_epoch = 1;
+            if (++epoch > EPOCH_MAX) {
+                if (fs) fill_words(c, static_cast<uint64_t*>(lookback), lookback_bytes / 8);
+                else HIPCHK(hipMemsetAsync(c.lookback, 0, c.lookback_bytes, c.stream));
+                epoch = 1;
             }
-            const bool last = (li + 1 == live.size()) && final_out;
+            const bool last = (li + 1 == n_live) && final_out;
             const uint32_t width = pass_bits(bit_lo, bit_hi, plan.n9, dbits, p);
             PassArgs a{kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, pass_shift(bit_lo, plan.n9, dbits, p), width,
-                       off + (size_t)p * HSTRIDE, (uint64_t*)c.lookback, counter + p, c.sort_epoch, c.d_status,
+                       off + (size_t)p * HSTRIDE, (uint64_t*)lookback, counter + p, epoch, status,
                        final_out ? *final_out : FinalOut{}, mode};
             tstart(c, last ? "sort_pass_final" : "sort_pass");
             launch_variant(c, variant, a, last, width > 8);
@@ -556,7 +615,7 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
             HIPCHK(hipGetLastError());
             cur ^= 1;
         }
-        if (final_out && live.empty() && n) {
+        if (final_out && !n_live && n) {
             tstart(c, "sort_unpack");
             hipLaunchKernelGGL(k_unpack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, kb[cur], vb[cur], n,
                                *final_out);
@@ -569,6 +628,15 @@ int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32
     }
     cleanup();
     return cur;
+}
+
+}  // namespace
+
+int radix_sort(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, uint32_t* vals1, uint64_t n,
+               uint32_t bit_lo, uint32_t bit_hi, const uint64_t* digit_hist, const FinalOut* final_out,
+               bool wait_for_plan) {
+    return radix_sort_impl(c, keys0, vals0, keys1, vals1, n, bit_lo, bit_hi, digit_hist, final_out, wait_for_plan,
+                           nullptr);
 }
 
 }  // namespace snnc
@@ -696,6 +764,103 @@ extern "C" snnc_status snnc_sort_pairs(snnc_ctx* ctx, uint64_t* keys, uint32_t* 
         uint32_t status = 0;
         download(*ctx, &status, ctx->d_status, 4);
         if (status) raise(SNNC_EDEVICE, "a device wait exceeded its bound");
+        return SNNC_OK;
+    } catch (const Error& e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    }
+}
+
+// ------------------------------------------------------------------ allocation-free sort
+// One static scratch array per GPU, for callers that cannot allocate device
+// memory.  Layout: digit histograms (8 passes x 512 u64), their offsets
+// (same), 8 tile counters and a status word (256 B), then the look-back
+// table.  Host code reaches it only through the address that
+// hipGetSymbolAddress gives for the current device.
+namespace snnc {
+namespace {
+
+constexpr size_t NA_BYTES = 16u << 20;
+constexpr size_t NA_HIST = 0;
+constexpr size_t NA_OFF = NA_HIST + 8 * HSTRIDE * 8;
+constexpr size_t NA_CNT = NA_OFF + 8 * HSTRIDE * 8;
+constexpr size_t NA_STATUS = NA_CNT + 8 * 4;
+constexpr size_t NA_LB = NA_CNT + 256;
+constexpr size_t NA_LB_BYTES = NA_BYTES - NA_LB;
+constexpr int NA_MAX_DEVICES = 64;
+
+struct NoallocDevice {
+    char* ptr = nullptr;    // device address of `scratch` on this GPU
+    uint32_t epoch = 0;     // look-back epoch of the last pass run on it
+};
+
+std::mutex& na_mutex() {
+    static std::mutex m;
+    return m;
+}
+
+NoallocDevice* na_devices() {
+    static NoallocDevice d[NA_MAX_DEVICES];
+    return d;
+}
+
+}  // namespace
+}  // namespace snnc
+
+static __device__ __align__(256) unsigned char scratch[snnc::NA_BYTES];
+
+namespace snnc {
+
+// Called by snnc_init with the context's device current: takes the device
+// address of the static scratch once per device and clears its look-back
+// table (a fill kernel on the context stream, waited for).
+void noalloc_setup(Ctx& c) {
+    if (c.device < 0 || c.device >= NA_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(na_mutex());
+    NoallocDevice& d = na_devices()[c.device];
+    if (d.ptr) return;
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    char* base = static_cast<char*>(p);
+    fill_words(c, reinterpret_cast<uint64_t*>(base + NA_LB), NA_LB_BYTES / 8);
+    HIPCHK(hipStreamSynchronize(c.stream));
+    d.ptr = base;
+    d.epoch = 0;
+}
+
+}  // namespace snnc
+
+extern "C" snnc_status snnc_sort_pairs_noalloc(snnc_ctx* ctx, uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp,
+                                               uint32_t* vals_tmp, uint64_t n, uint32_t bit_lo, uint32_t bit_hi,
+                                               int32_t* result_in_tmp) {
+    using namespace snnc;
+    if (!ctx || !result_in_tmp || (n && (!keys || !vals || !keys_tmp || !vals_tmp)) || bit_hi > 64 || bit_lo > bit_hi)
+        return SNNC_EINVAL;
+    try {
+        HIPCHK(hipSetDevice(ctx->device));
+        if (ctx->device < 0 || ctx->device >= NA_MAX_DEVICES) raise(SNNC_EUNSUPPORTED, "device ordinal above 63");
+        std::lock_guard<std::mutex> lock(na_mutex());
+        NoallocDevice& d = na_devices()[ctx->device];
+        if (!d.ptr) raise(SNNC_ESTATE, "static scratch not set up on this device");
+        FixedScratch fs{reinterpret_cast<uint64_t*>(d.ptr + NA_HIST), reinterpret_cast<uint64_t*>(d.ptr + NA_OFF),
+                        reinterpret_cast<uint32_t*>(d.ptr + NA_CNT), reinterpret_cast<uint32_t*>(d.ptr + NA_STATUS),
+                        d.ptr + NA_LB, NA_LB_BYTES, &d.epoch};
+        const int saved_timing = ctx->timing;
+        ctx->timing = 0;   // timing brackets would create events
+        fill_words(*ctx, reinterpret_cast<uint64_t*>(d.ptr + NA_CNT), 32);   // counters and status word
+        int which = 0;
+        try {
+            which = radix_sort_impl(*ctx, keys, vals, keys_tmp, vals_tmp, n, bit_lo, bit_hi, nullptr, nullptr, true,
+                                    &fs);
+        } catch (...) {
+            ctx->timing = saved_timing;
+            throw;
+        }
+        ctx->timing = saved_timing;
+        uint32_t status = 0;
+        download(*ctx, &status, d.ptr + NA_STATUS, 4);
+        if (status) raise(SNNC_EDEVICE, "a device wait exceeded its bound");
+        *result_in_tmp = which;
         return SNNC_OK;
     } catch (const Error& e) {
         ctx->last_error = e.msg;
