@@ -78,6 +78,8 @@ def lib():
                      ctypes.c_int, dbl, dbl, ctypes.c_int, dbl, dbl, dbl, i32, vp]
         L.orc_connect.argtypes = conn_args
         L.orc_declare.argtypes = conn_args
+        L.orc_call_count.argtypes = [vp, u32, u32, u64, u64]
+        L.orc_call_count.restype = i64
         L.orc_connect_assigned.argtypes = [vp, vp, u32, vp, u32, vp, vp, u64,
                                            ctypes.c_int, dbl, dbl, ctypes.c_int, dbl, dbl, dbl, i32, vp]
         L.orc_prepare.argtypes = [vp]
@@ -381,6 +383,14 @@ class OracleNet:
         if n < 0:
             raise OracleError(-1, "call_range: capacity too small or bad call id")
         return {"src": src[:n], "tgt": tgt[:n], "e": e[:n], "weight": w[:n], "delay": d[:n]}
+
+    def call_count(self, call_id: int, host: int, lo: int = 0, hi: int = 2**63) -> int:
+        """Connections of a call on one host's share (primary ordinal in [lo,
+        hi)), counted by the same walk of the draws as the generation."""
+        n = lib().orc_call_count(self._h, call_id, host, lo, hi)
+        if n < 0:
+            raise OracleError(-1, "call_count: bad call id")
+        return int(n)
 
 
 def run_script(script, P_local: int, declare_only: bool = False, skip_invalid: bool = False):

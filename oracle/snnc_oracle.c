@@ -1594,3 +1594,25 @@ int orc_declare(orc_net* net, const uint32_t* src_triples, uint32_t n_src_seg,
     *call_id_out = c.id;
     return ORC_OK;
 }
+
+/* Number of connections of one call on one host's share whose primary
+ * ordinal lies in [lo, hi): the same walk of the rule's draws as the
+ * generation (gen_call), counting each accepted connection instead of
+ * drawing its synapse values.  Used to decide admission against a resident
+ * budget without generating.  -1 for an unknown call. */
+typedef struct { uint64_t n; } count_ctx;
+
+static void emit_count(void* vctx, uint64_t src_ord, uint32_t tgt_local, uint64_t e)
+{
+    (void)src_ord; (void)tgt_local; (void)e;
+    ((count_ctx*)vctx)->n++;
+}
+
+int64_t orc_call_count(const orc_net* net, uint32_t call_id, uint32_t host, uint64_t lo, uint64_t hi)
+{
+    if (call_id >= net->ncalls) return -1;
+    count_ctx ctx = { 0 };
+    sink_t sink = { emit_count, &ctx };
+    gen_call(net, &net->calls[call_id], host, lo, hi, sink);
+    return (int64_t)ctx.n;
+}

@@ -7,6 +7,7 @@ import pytest
 
 import oracle
 import paper_2512_09502_amd as snnc
+from fullsize_oracle import served_admission
 from gpu_util import GEN_ARRAYS, PREP_ARRAYS, compare, log
 from paper_2512_09502_amd import workloads as W
 
@@ -94,10 +95,14 @@ def test_batched_equals_per_call_under_budget(fuse):
     assert any(code == -3 for _, code in rej_a), "the budget should reject some requests"
     for k in a:
         np.testing.assert_array_equal(a[k], b[k], err_msg=k)
-    # and the oracle on the admitted requests
+    # the oracle's own admission (its counts under the documented resident
+    # cost) rejects the same requests; its build of the admitted ones is the network
+    status, admitted, _ = served_admission(script, budget, workers=2)
+    conn_at = [k for k, op in enumerate(script["ops"]) if op[0] == "connect"]
+    assert [(conn_at[i], st) for i, st in enumerate(status) if st != 0] == rej_a
     kept = dict(script)
-    drop = {k for k, _ in rej_a}
-    kept["ops"] = [op for k, op in enumerate(script["ops"]) if k not in drop]
+    keep = {conn_at[i] for i in admitted}
+    kept["ops"] = [op for k, op in enumerate(script["ops"]) if op[0] == "create" or k in keep]
     ref = oracle.run_script(kept, 0)
     for k in GEN_ARRAYS + PREP_ARRAYS:
         compare(k, b[k], ref.array(k), "served")
