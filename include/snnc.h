@@ -211,7 +211,11 @@ snnc_status snnc_reserve(snnc_ctx* ctx, uint64_t n_connections);
 /* ---------------------------------------------------------------- served construction
  * A construction server keeps the growing network resident in HBM and admits
  * each Connect request against a budget on the resident network: 14 bytes
- * per connection (source, target, delay, weight) plus the request's metadata.
+ * per connection (source, target, delay, weight) plus the request's metadata
+ * (16 bytes per segment of each node set, at least one per set, and 4 bytes
+ * per delay-table threshold plus a 257-word guide for a normal delay, or 4
+ * bytes for a constant one; assigned nodes add 8 bytes per pair; a request
+ * with no source or target on P_local has no metadata and no connections).
  * Admission uses the exact connection count of the request on P_local's share
  * (a counting pass where the count depends on the draws), in submission
  * order, so it is deterministic; a rejected request changes nothing and gets
@@ -527,7 +531,10 @@ snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
  * 1024 threads x 10 items with the payload loaded before the look-back) and
  * "mark_in_lds" (1, default: regeneration for the point-to-point lists marks
  * its bit row in LDS when the row has at most 2^19 neurons; 0: a global
- * atomic per draw).  Every setting gives the same arrays. */
+ * atomic per draw) and "floyd_wave_max" (0 .. 8192, default 1024: Floyd's
+ * sampling of a unit runs in a one-wave workgroup when the degree rounded up
+ * to a power of two is at most this, else in 256 threads).  Every setting
+ * gives the same arrays. */
 
 /* Autotuner of the source-major sort: times every pass algorithm and tile
  * shape (sort_mode x sort_variant) on n synthetic keys with `bits` sorted

@@ -1228,6 +1228,9 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
         } else if (!strcmp(key, "map_path")) {
             if (value < 0 || value > 1) raise(SNNC_EINVAL, "map_path out of range");
             c->force_map_path = value == 1;
+        } else if (!strcmp(key, "floyd_wave_max")) {
+            if (value < 0 || value > 8192) raise(SNNC_EINVAL, "floyd_wave_max out of range");
+            c->floyd_wave_max = (uint32_t)value;
         } else if (!strcmp(key, "fuse_batches")) {
             c->fuse_batches = value != 0;
         } else if (!strcmp(key, "fused_wgs_per_cu")) {

@@ -536,10 +536,11 @@ struct FloydArgs {
 // steps and are resolved by pointer jumping.  Then the chosen values are
 // sorted ascending -- the same set as inserting one by one.  K <= 8192, so a
 // step index fits 13 bits of the sort key.
-constexpr int FLNT = 256;
-
-template <class Sink, int MODE>
-__global__ __launch_bounds__(FLNT) void k_floyd(FloydArgs a, Sink sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
+// NT threads per unit: 256, or one wave (64) for padded degrees up to the
+// context's floyd_wave_max, where the barriers of a one-wave workgroup cost
+// next to nothing and many units share a compute unit.
+template <int NT, class Sink, int MODE>
+__global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t kp = a.kpad;
     uint64_t* key = reinterpret_cast<uint64_t*>(lds_raw);          // (value << 13 | step), later the chosen values
@@ -564,7 +565,7 @@ __global__ __launch_bounds__(FLNT) void k_floyd(FloydArgs a, Sink sink, uint32_t
         const uint32_t n_eff = a.n_set - (self >= 0 ? 1u : 0u);
         const uint32_t base_m = n_eff - a.K;                    // m_j = base_m + j
         const uint64_t e0 = ord * a.K;
-        for (uint32_t j = tid; j < kp; j += FLNT) {
+        for (uint32_t j = tid; j < kp; j += NT) {
             if (j < a.K) {
                 const uint4 b = draw(a.seed, a.call, e0 + j, PURPOSE_IDX);
                 const uint32_t r = uniform_index(b.x, b.y, base_m + j + 1);
@@ -577,7 +578,7 @@ __global__ __launch_bounds__(FLNT) void k_floyd(FloydArgs a, Sink sink, uint32_t
         __syncthreads();
         for (uint32_t size = 2; size <= kp; size <<= 1) {      // bitonic sort of (value, step)
             for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t i = tid; i < kp / 2; i += FLNT) {
+                for (uint32_t i = tid; i < kp / 2; i += NT) {
                     const uint32_t lo_i = 2 * i - (i & (stride - 1));
                     const uint32_t hi_i = lo_i + stride;
                     const bool up = ((lo_i & size) == 0);
@@ -591,7 +592,7 @@ __global__ __launch_bounds__(FLNT) void k_floyd(FloydArgs a, Sink sink, uint32_t
             }
         }
         // A_j: an earlier step drew the same value (first occurrence by binary search)
-        for (uint32_t p = tid; p < a.K; p += FLNT) {
+        for (uint32_t p = tid; p < a.K; p += NT) {
             const uint64_t k = key[p];
             const uint32_t j = (uint32_t)(k & 0x1fffu);
             const uint64_t v0 = (k >> 13) << 13;
@@ -611,7 +612,7 @@ __global__ __launch_bounds__(FLNT) void k_floyd(FloydArgs a, Sink sink, uint32_t
         uint8_t* da = dup0;
         uint8_t* db = dup1;
         for (uint32_t span = 1; span < a.K; span <<= 1) {     // pointer jumping
-            for (uint32_t j = tid; j < a.K; j += FLNT) {
+            for (uint32_t j = tid; j < a.K; j += NT) {
                 const uint32_t q = pa[j];
                 db[j] = da[j] | da[q];
                 pb[j] = pa[q];
@@ -620,12 +621,12 @@ __global__ __launch_bounds__(FLNT) void k_floyd(FloydArgs a, Sink sink, uint32_t
             uint16_t* tp = pa; pa = pb; pb = tp;
             uint8_t* td = da; da = db; db = td;
         }
-        for (uint32_t j = tid; j < kp; j += FLNT)
+        for (uint32_t j = tid; j < kp; j += NT)
             vals[j] = j < a.K ? (da[j] ? base_m + j : rv[j]) : 0xffffffffu;
         __syncthreads();
         for (uint32_t size = 2; size <= kp; size <<= 1) {      // bitonic sort of the chosen values
             for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t i = tid; i < kp / 2; i += FLNT) {
+                for (uint32_t i = tid; i < kp / 2; i += NT) {
                     const uint32_t lo_i = 2 * i - (i & (stride - 1));
                     const uint32_t hi_i = lo_i + stride;
                     const bool up = ((lo_i & size) == 0);
@@ -639,11 +640,11 @@ __global__ __launch_bounds__(FLNT) void k_floyd(FloydArgs a, Sink sink, uint32_t
             }
         }
         // emit in ascending order (j = rank)
-        __shared__ uint32_t wsum[FLNT / 64];
+        __shared__ uint32_t wsum[NT / 64];
         uint64_t running = 0;
         if constexpr (MODE == WRITE) running = unit_offsets[u];
         uint32_t counted = 0;
-        for (uint32_t j0 = 0; j0 < a.K; j0 += FLNT) {
+        for (uint32_t j0 = 0; j0 < a.K; j0 += NT) {
             const uint32_t j = j0 + tid;
             Res r{};
             bool ok = false;
@@ -666,7 +667,7 @@ __global__ __launch_bounds__(FLNT) void k_floyd(FloydArgs a, Sink sink, uint32_t
                 if (ok) sink.mark(r);
             } else {
                 uint32_t tot;
-                const uint32_t before = block_excl_scan<FLNT>(ok ? 1u : 0u, wsum, &tot);
+                const uint32_t before = block_excl_scan<NT>(ok ? 1u : 0u, wsum, &tot);
                 if constexpr (MODE == COUNT) counted += tot;
                 else {
                     if (ok) sink.put(running + before, r);
@@ -764,12 +765,17 @@ void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_c
     const uint32_t grid = (uint32_t)std::min<uint64_t>(a.n_units, 65536);
     if (a.kpad > 8192) raise(SNNC_EUNSUPPORTED, "degree above 8192 without multapses");
     const size_t shmem = (size_t)a.kpad * (8 + 4 + 2 * 2 + 2 * 1);
-    if (shmem > 64 * 1024)
-        HIPCHK(hipFuncSetAttribute((const void*)k_floyd<Sink, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)shmem));
     tstart(c, MODE == MARK ? "prep_mark" : "gen_floyd");
-    hipLaunchKernelGGL((k_floyd<Sink, MODE>), dim3(grid), dim3(FLNT), shmem, c.stream, a, sink, unit_counts,
-                       unit_offsets);
+    if (a.kpad <= c.floyd_wave_max) {
+        hipLaunchKernelGGL((k_floyd<64, Sink, MODE>), dim3(grid), dim3(64), shmem, c.stream, a, sink, unit_counts,
+                           unit_offsets);
+    } else {
+        if (shmem > 64 * 1024)
+            HIPCHK(hipFuncSetAttribute((const void*)k_floyd<256, Sink, MODE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+        hipLaunchKernelGGL((k_floyd<256, Sink, MODE>), dim3(grid), dim3(256), shmem, c.stream, a, sink, unit_counts,
+                           unit_offsets);
+    }
     tstop(c);
     HIPCHK(hipGetLastError());
 }

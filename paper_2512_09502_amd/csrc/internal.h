@@ -257,6 +257,7 @@ struct Ctx {
     std::vector<hipEvent_t> batch_done;
     bool fuse_batches = true;
     int fused_wgs_per_cu = 8;
+    uint32_t floyd_wave_max = 1024;      // Floyd's sampling: one-wave workgroups up to this padded degree
     size_t fused_cap = 0;
     void* fused_reqs = nullptr;
     void* fused_hdr = nullptr;

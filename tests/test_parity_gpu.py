@@ -239,3 +239,18 @@ def test_edge_cases():
     b = W._Builder(1)
     b.create(0, 10)
     compare_all(b.script("empty"), 0)
+
+
+@pytest.mark.parametrize("wave_max", [0, 8192])
+@pytest.mark.parametrize("rule,k,n_src,n_tgt,aut", [
+    ("fixed_indegree", 37, 500, 300, False),
+    ("fixed_indegree", 1000, 1200, 200, True),
+    ("fixed_indegree", 2990, 3000, 100, False),
+    ("fixed_outdegree", 300, 100, 900, False),
+])
+def test_floyd_workgroup_shapes(rule, k, n_src, n_tgt, aut, wave_max):
+    # one-wave and 256-thread workgroups of the parallel Floyd sampler give the oracle's sets
+    conn = {"rule": rule, "n": k, "autapses": aut, "multapses": False}
+    s = _one(conn, n_src=n_src, n_tgt=n_tgt)
+    s["tune"] = {"floyd_wave_max": wave_max}
+    compare_all(s, 0)
