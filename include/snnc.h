@@ -547,6 +547,18 @@ snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
 snnc_status snnc_autotune_sort(snnc_ctx* ctx, uint64_t n, uint32_t bits, int32_t* mode_out, int32_t* variant_out,
                                float* ms_out);
 
+/* Autotuner of the persistent batch launch of snnc_flush: times the launch at
+ * 1, 2, 4, 8, 16 and 32 workgroups per compute unit on a synthetic batch of
+ * 48 fusable requests (fixed in-degree and out-degree with multapses, total
+ * number with autapses and multapses, one-to-one; sizes spread over three
+ * decades; about n connections) built in scratch contexts on this context's
+ * device, allocator and stream, and sets the fastest on the context.  The
+ * choice is cached for the device for the process: a later call returns at
+ * once with *ms_out = -1.  The grid changes no result.  Allocates about
+ * 2 x 14 n bytes while it runs.  Errors: SNNC_EINVAL (n = 0, null outputs),
+ * SNNC_ESTATE after prepare, SNNC_ENOMEM, SNNC_EDEVICE. */
+snnc_status snnc_autotune_fused(snnc_ctx* ctx, uint64_t n, int32_t* wgs_out, float* ms_out);
+
 /* ---------------------------------------------------------- spike exchange */
 
 /* Spike packets of one time step on this host (Appendix E, packet figure;

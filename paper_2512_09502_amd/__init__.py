@@ -88,7 +88,7 @@ EXPORTS = ["snnc_init", "snnc_destroy", "snnc_last_error", "snnc_sync", "snnc_cr
            "snnc_autotune_sort", "snnc_set_map_policy", "snnc_spike_packets", "snnc_deliver",
            "snnc_connect_assigned", "snnc_set_memory_level", "snnc_array_on_host", "snnc_get_connections",
            "snnc_get_image_map", "snnc_get_p2p_send", "snnc_get_collective", "snnc_copy_to_host",
-           "snnc_sort_pairs_noalloc"]
+           "snnc_sort_pairs_noalloc", "snnc_autotune_fused"]
 
 _lib = None
 
@@ -149,6 +149,7 @@ def lib():
         L.snnc_tune.argtypes = [vp, ctypes.c_char_p, ctypes.c_int64]
         L.snnc_sort_pairs.argtypes = [vp, vp, vp, vp, vp, u64, u32, u32, ctypes.POINTER(ctypes.c_int32)]
         L.snnc_sort_pairs_noalloc.argtypes = L.snnc_sort_pairs.argtypes
+        L.snnc_autotune_fused.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
         L.snnc_set_resident_budget.argtypes = [vp, u64]
         L.snnc_submit.argtypes = L.snnc_connect.argtypes
         L.snnc_connect_assigned.argtypes = [vp, ctypes.POINTER(NodeSet), ctypes.POINTER(NodeSet), vp, vp, u64,
@@ -604,6 +605,14 @@ class Network:
         self._check(lib().snnc_autotune_sort(self._h, int(n), int(bits), ctypes.byref(m), ctypes.byref(v),
                                              ctypes.byref(ms)))
         return {"sort_mode": m.value, "sort_variant": v.value, "ms": ms.value}
+
+    def autotune_fused(self, n: int) -> dict:
+        """Pick the grid of the persistent batch launch (workgroups per
+        compute unit) on a synthetic batch of about n connections (cached
+        per device for the process)."""
+        w, ms = ctypes.c_int32(), ctypes.c_float()
+        self._check(lib().snnc_autotune_fused(self._h, int(n), ctypes.byref(w), ctypes.byref(ms)))
+        return {"fused_wgs_per_cu": w.value, "ms": ms.value}
 
     def sort_pairs(self, keys, vals, bit_lo: int, bit_hi: int):
         """Stable radix sort of device tensors keys (int64) / vals (int32) by

@@ -1,9 +1,11 @@
 // C ABI and host planner: context state, allocation against the budget,
 // validation of Connect specs, kernel timing, array access.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 
 #include "device_common.h"
@@ -454,28 +456,50 @@ static void validate(Ctx& c, Call& cl, const snnc_syn_spec* syn) {
     } else raise(SNNC_EINVAL, "unknown delay distribution");
 }
 
-// device copies of a call's sets and delay table (one allocation)
-void upload_meta(Ctx& c, Call& cl) {
+// device copies of a call's sets and delay table (one allocation): layout
+// S segments, T segments, delay thresholds, their 257-entry guide
+static size_t meta_size(const Call& cl) {
     const size_t nS = std::max<size_t>(cl.S.seg.size(), 1), nT = std::max<size_t>(cl.T.seg.size(), 1);
-    const std::vector<uint32_t>* tab = cl.dtab && !cl.dtab->tab.empty() ? &cl.dtab->tab : nullptr;
-    const size_t nD = tab ? tab->size() : 1;
-    const size_t nG = tab ? 257 : 0;   // guide of the delay table
-    const size_t bytes = (nS + nT) * sizeof(SegD) + (nD + nG) * sizeof(uint32_t);
-    std::vector<char> host(bytes, 0);
-    SegD* hS = reinterpret_cast<SegD*>(host.data());
+    const bool tab = cl.dtab && !cl.dtab->tab.empty();
+    const size_t nD = tab ? cl.dtab->tab.size() : 1;
+    const size_t nG = tab ? 257 : 0;
+    return (nS + nT) * sizeof(SegD) + (nD + nG) * sizeof(uint32_t);
+}
+
+static void fill_meta(const Call& cl, char* host) {
+    const size_t nS = std::max<size_t>(cl.S.seg.size(), 1), nT = std::max<size_t>(cl.T.seg.size(), 1);
+    memset(host, 0, meta_size(cl));
+    SegD* hS = reinterpret_cast<SegD*>(host);
     SegD* hT = hS + nS;
     for (size_t i = 0; i < cl.S.seg.size(); ++i) hS[i] = SegD{cl.S.ord_begin[i], cl.S.seg[i].host, cl.S.seg[i].first};
     for (size_t i = 0; i < cl.T.seg.size(); ++i) hT[i] = SegD{cl.T.ord_begin[i], cl.T.seg[i].host, cl.T.seg[i].first};
-    if (tab) {
+    if (cl.dtab && !cl.dtab->tab.empty()) {
         uint32_t* hD = reinterpret_cast<uint32_t*>(hT + nT);
-        memcpy(hD, tab->data(), nD * sizeof(uint32_t));
+        const size_t nD = cl.dtab->tab.size();
+        memcpy(hD, cl.dtab->tab.data(), nD * sizeof(uint32_t));
         memcpy(hD + nD, cl.dtab->guide.data(), 257 * sizeof(uint32_t));
     }
-    cl.meta = dalloc(c, bytes);
-    cl.meta_bytes = bytes;
-    upload(c, cl.meta, host.data(), bytes);
-    cl.dS = static_cast<SegD*>(cl.meta);
+}
+
+static void bind_meta(Call& cl, void* dev) {
+    const size_t nS = std::max<size_t>(cl.S.seg.size(), 1), nT = std::max<size_t>(cl.T.seg.size(), 1);
+    const bool tab = cl.dtab && !cl.dtab->tab.empty();
+    const size_t nD = tab ? cl.dtab->tab.size() : 1;
+    cl.meta = dev;
+    cl.meta_bytes = meta_size(cl);
+    cl.dS = static_cast<SegD*>(dev);
     cl.dT = cl.dS + nS;
+    cl.dtab_dev = reinterpret_cast<uint32_t*>(cl.dT + nT);
+    cl.dguide_dev = tab ? cl.dtab_dev + nD : nullptr;
+}
+
+void upload_meta(Ctx& c, Call& cl) {
+    const size_t bytes = meta_size(cl);
+    std::vector<char> host(bytes);
+    fill_meta(cl, host.data());
+    void* dev = dalloc(c, bytes);
+    upload(c, dev, host.data(), bytes);
+    bind_meta(cl, dev);
     if (cl.rule == SNNC_ASSIGNED_NODES && cl.n) {
         cl.pairs = dalloc_n<uint32_t>(c, 2 * cl.n);
         upload(c, cl.pairs, cl.in_src_pos, cl.n * 4);
@@ -483,12 +507,212 @@ void upload_meta(Ctx& c, Call& cl) {
         cl.meta_bytes += 8 * cl.n;
     }
     cl.in_src_pos = cl.in_tgt_pos = nullptr;
-    cl.dtab_dev = reinterpret_cast<uint32_t*>(cl.dT + nT);
-    cl.dguide_dev = nG ? cl.dtab_dev + nD : nullptr;
+}
+
+// Metadata of several calls in one device block and one copy (batched
+// submission).  The calls share the block: it is released with the context.
+static void upload_meta_batch(Ctx& c, std::vector<Call*>& calls) {
+    if (calls.empty()) return;
+    std::vector<size_t> at(calls.size());
+    size_t total = 0;
+    for (size_t i = 0; i < calls.size(); ++i) {
+        at[i] = total;
+        total += (meta_size(*calls[i]) + 15) & ~(size_t)15;
+    }
+    std::vector<char> host(total);
+    for (size_t i = 0; i < calls.size(); ++i) fill_meta(*calls[i], host.data() + at[i]);
+    char* dev = static_cast<char*>(dalloc(c, total));
+    upload(c, dev, host.data(), total);
+    for (size_t i = 0; i < calls.size(); ++i) {
+        bind_meta(*calls[i], dev + at[i]);
+        calls[i]->meta_shared = true;
+        calls[i]->in_src_pos = calls[i]->in_tgt_pos = nullptr;
+    }
+}
+
+static void free_meta(Ctx& c, Call& cl) {
+    if (!cl.meta_shared) dfree(c, cl.meta);
+    cl.meta = nullptr;
+}
+
+// ------------------------------------------------------------------ generation store in blocks
+// The generation-order arrays (source ordinal, target, delay, weight) live in
+// fixed-size blocks of physical device memory (GEN_BLOCK connections each)
+// mapped on demand behind four reserved virtual ranges: kernels see
+// contiguous arrays and growth maps the next blocks (no copy, no wait for the
+// device).  After Prepare (or at destroy) a context hands its ranges, still
+// mapped, to a per-device store that the next context takes whole, so a
+// steady stream of contexts maps nothing; a context that finds the store in
+// use maps its own blocks and releases them at its end unless the store is
+// empty, which it then fills.
+namespace {
+constexpr uint64_t GEN_BLOCK = 1ull << 26;                 // connections per block
+constexpr uint64_t GEN_VA_CONNS = 1ull << 35;              // reserved connections per array
+constexpr size_t GEN_BPC[4] = {4, 4, 2, 4};                // bytes per connection of each array
+constexpr int GEN_MAX_DEVICES = 64;
+
+struct MappedStore {
+    std::mutex m;
+    bool in_use = false;
+    char* va[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<std::array<void*, 4>> blocks;
+    uint64_t mapped = 0;
+};
+
+MappedStore& mapped_store(int device) {
+    static MappedStore stores[GEN_MAX_DEVICES];
+    return stores[device];
+}
+
+void unmap_all(char* const va[4], const std::vector<std::array<void*, 4>>& blocks) {
+    for (int a = 0; a < 4; ++a) {
+        const size_t bytes = GEN_BPC[a] * GEN_BLOCK;
+        for (size_t b = 0; b < blocks.size(); ++b) {
+            (void)hipMemUnmap(va[a] + bytes * b, bytes);
+            (void)hipMemRelease(static_cast<hipMemGenericAllocationHandle_t>(blocks[b][a]));
+        }
+        (void)hipMemAddressFree(va[a], GEN_BPC[a] * GEN_VA_CONNS);
+    }
+}
+
+void gen_map(Ctx& c, uint64_t need) {
+    if (need > GEN_VA_CONNS) raise(SNNC_EUNSUPPORTED, "more than 2^35 generated connections");
+    if (!c.gen_va[0]) {
+        MappedStore& st = mapped_store(c.device);
+        std::lock_guard<std::mutex> lock(st.m);
+        if (st.va[0] && !st.in_use) {   // take the device's mapped store whole
+            st.in_use = true;
+            c.gen_pooled = true;
+            for (int a = 0; a < 4; ++a) c.gen_va[a] = st.va[a];
+            c.gen_handles = st.blocks;
+            c.gen_mapped = st.mapped;
+            c.bytes_live += 14 * GEN_BLOCK * c.gen_handles.size();
+            c.bytes_peak = std::max(c.bytes_peak, c.bytes_live);
+        }
+    }
+    if (!c.gen_va[0]) {
+        for (int a = 0; a < 4; ++a) {
+            void* p = nullptr;
+            if (hipMemAddressReserve(&p, GEN_BPC[a] * GEN_VA_CONNS, 0, nullptr, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                for (int b = 0; b < a; ++b) (void)hipMemAddressFree(c.gen_va[b], GEN_BPC[b] * GEN_VA_CONNS);
+                for (int b = 0; b < 4; ++b) c.gen_va[b] = nullptr;
+                raise(SNNC_ENOMEM, "virtual address range for the generation arrays");
+            }
+            c.gen_va[a] = static_cast<char*>(p);
+        }
+        c.gen_pooled = false;
+    }
+    hipMemAllocationProp prop{};
+    prop.type = hipMemAllocationTypePinned;
+    prop.location.type = hipMemLocationTypeDevice;
+    prop.location.id = c.device;
+    hipMemAccessDesc acc{};
+    acc.location = prop.location;
+    acc.flags = hipMemAccessFlagsProtReadWrite;
+    while (c.gen_mapped < need) {
+        const size_t block_bytes = 14 * GEN_BLOCK;
+        if (c.budget && c.bytes_live + block_bytes > c.budget)
+            raise(SNNC_EBUDGET, "device-memory budget exceeded by a generation block");
+        std::array<void*, 4> hs{};
+        int done = 0;
+        try {
+            for (; done < 4; ++done) {
+                const size_t bytes = GEN_BPC[done] * GEN_BLOCK;
+                hipMemGenericAllocationHandle_t h{};
+                if (hipMemCreate(&h, bytes, &prop, 0) != hipSuccess) {
+                    (void)hipGetLastError();
+                    raise(SNNC_ENOMEM, "no device memory for a generation block of " + std::to_string(bytes) + " bytes");
+                }
+                char* at = c.gen_va[done] + GEN_BPC[done] * c.gen_mapped;
+                if (hipMemMap(at, bytes, 0, h, 0) != hipSuccess) {
+                    (void)hipMemRelease(h);
+                    (void)hipGetLastError();
+                    raise(SNNC_EDEVICE, "mapping a generation block failed");
+                }
+                if (hipMemSetAccess(at, bytes, &acc, 1) != hipSuccess) {
+                    (void)hipMemUnmap(at, bytes);
+                    (void)hipMemRelease(h);
+                    (void)hipGetLastError();
+                    raise(SNNC_EDEVICE, "access to a generation block failed");
+                }
+                hs[done] = h;
+            }
+        } catch (...) {
+            for (int a = 0; a < done; ++a) {
+                (void)hipMemUnmap(c.gen_va[a] + GEN_BPC[a] * c.gen_mapped, GEN_BPC[a] * GEN_BLOCK);
+                (void)hipMemRelease(static_cast<hipMemGenericAllocationHandle_t>(hs[a]));
+            }
+            throw;
+        }
+        c.gen_handles.push_back(hs);
+        c.gen_mapped += GEN_BLOCK;
+        c.bytes_live += block_bytes;
+        c.bytes_peak = std::max(c.bytes_peak, c.bytes_live);
+    }
+    c.g_src = reinterpret_cast<uint32_t*>(c.gen_va[0]);
+    c.g_tgt = reinterpret_cast<uint32_t*>(c.gen_va[1]);
+    c.g_delay = reinterpret_cast<uint16_t*>(c.gen_va[2]);
+    c.g_weight = reinterpret_cast<float*>(c.gen_va[3]);
+    c.cap_gen = c.gen_mapped;
+}
+
+}  // namespace
+
+bool gen_blocks_supported(int device) {
+    if (device < 0 || device >= GEN_MAX_DEVICES) return false;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeVirtualMemoryManagementSupported, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    hipMemAllocationProp prop{};
+    prop.type = hipMemAllocationTypePinned;
+    prop.location.type = hipMemLocationTypeDevice;
+    prop.location.id = device;
+    size_t gran = 0;
+    if (hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityMinimum) != hipSuccess || !gran) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return v != 0 && (2 * GEN_BLOCK) % gran == 0;
+}
+
+// Hands the context's generation store back (the caller has waited for every
+// kernel that uses it): into the device's store, still mapped, when it came
+// from there or the store is empty; else unmapped and released.
+void gen_release(Ctx& c) {
+    if (!c.gen_vmm || !c.gen_va[0]) return;
+    bool kept = false;
+    {
+        MappedStore& st = mapped_store(c.device);
+        std::lock_guard<std::mutex> lock(st.m);
+        if (c.gen_pooled || !st.va[0]) {
+            for (int a = 0; a < 4; ++a) st.va[a] = c.gen_va[a];
+            st.blocks = c.gen_handles;
+            st.mapped = c.gen_mapped;
+            st.in_use = false;
+            kept = true;
+        }
+    }
+    if (!kept) unmap_all(c.gen_va, c.gen_handles);
+    c.bytes_live -= 14 * GEN_BLOCK * c.gen_handles.size();
+    for (int a = 0; a < 4; ++a) c.gen_va[a] = nullptr;
+    c.gen_handles.clear();
+    c.gen_mapped = 0;
+    c.gen_pooled = false;
+    c.g_src = c.g_tgt = nullptr;
+    c.g_delay = nullptr;
+    c.g_weight = nullptr;
+    c.cap_gen = 0;
 }
 
 void grow_gen(Ctx& c, uint64_t need) {
     if (need <= c.cap_gen) return;
+    if (c.gen_vmm) {
+        gen_map(c, need);
+        return;
+    }
     uint64_t cap = std::max<uint64_t>(c.cap_gen ? c.cap_gen : 1 << 16, 1 << 16);
     while (cap < need) cap *= 2;
     if (c.cap_gen && need <= c.cap_gen + (c.cap_gen >> 2)) cap = std::max(cap, need);
@@ -589,7 +813,7 @@ static Call counted_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
         try {
             *n_out = gen_count_local(c, cl);
         } catch (...) {
-            dfree(c, cl.meta);
+            free_meta(c, cl);
             dfree(c, cl.pairs);
             throw;
         }
@@ -600,7 +824,7 @@ static Call counted_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
     try {
         *n_out = gen_count_local(c, cl);
     } catch (...) {
-        dfree(c, cl.meta);
+        free_meta(c, cl);
         dfree(c, cl.pairs);
         release_pre(c, cl);
         throw;
@@ -625,7 +849,7 @@ static void connect_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
         cl.gen_count = cl.meta ? gen_local(c, cl) : 0;   // no tables: no local target
         HIPCHK(hipGetLastError());
     } catch (...) {
-        dfree(c, cl.meta);
+        free_meta(c, cl);
         dfree(c, cl.pairs);
         release_pre(c, cl);
         throw;
@@ -651,7 +875,7 @@ static void submit_impl(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt
         cl.gen_begin = c.n_gen;
         cl.gen_count = n;
     } catch (...) {
-        dfree(c, cl.meta);
+        free_meta(c, cl);
         dfree(c, cl.pairs);
         release_pre(c, cl);
         throw;
@@ -692,7 +916,7 @@ static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const 
     std::vector<uint64_t> count(n, 0);
     std::vector<char> ok(n, 0), on_device(n, 0);
     auto drop = [&](Call& cl) {
-        dfree(c, cl.meta);
+        free_meta(c, cl);
         dfree(c, cl.pairs);
         release_pre(c, cl);
         cl.meta = nullptr;
@@ -720,6 +944,8 @@ static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const 
     // stream waits for it at the end of each counting section)
     {
         CountScope lane(c);
+        std::vector<char> meta(n, 0);
+        std::vector<Call*> with_meta;
         for (uint32_t i = 0; i < n; ++i) {
             status[i] = SNNC_OK;
             ids[i] = UINT32_MAX;
@@ -727,9 +953,8 @@ static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const 
             try {
                 cl = make_call_host(c, &src[i], &tgt[i], &conn[i], &syn[i], alpha[i]);
                 if (needs_meta(c, cl)) {
-                    upload_meta(c, cl);
-                    if (count_on_device(c, cl)) on_device[i] = 1;
-                    else count[i] = gen_count_local(c, cl);   // no draws: independent of the call id
+                    meta[i] = 1;
+                    with_meta.push_back(&cl);
                 }
                 ok[i] = 1;
             } catch (const Error& e) {
@@ -738,6 +963,28 @@ static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const 
                     for (uint32_t k = 0; k < i; ++k) drop(cls[k]);
                     throw;
                 }
+                status[i] = e.code;
+            }
+        }
+        try {
+            upload_meta_batch(c, with_meta);   // the tables of the whole batch: one block, one copy
+        } catch (...) {
+            for (uint32_t k = 0; k < n; ++k) drop(cls[k]);
+            throw;
+        }
+        for (uint32_t i = 0; i < n; ++i) {
+            if (!meta[i]) continue;
+            Call& cl = cls[i];
+            try {
+                if (count_on_device(c, cl)) on_device[i] = 1;
+                else count[i] = gen_count_local(c, cl);   // no draws: independent of the call id
+            } catch (const Error& e) {
+                drop(cl);
+                if (fatal(e)) {
+                    for (uint32_t k = 0; k < n; ++k) drop(cls[k]);
+                    throw;
+                }
+                ok[i] = 0;
                 status[i] = e.code;
             }
         }
@@ -865,6 +1112,128 @@ static void free_results(Ctx& c) {
     c.counts.clear();
 }
 
+// ------------------------------------------------------------------ fused-launch autotuner
+// Times the persistent batch launch at 1 .. 32 workgroups per compute unit on
+// a synthetic batch of fusable requests (fixed in-degree and out-degree with
+// multapses, total number with autapses and multapses, one-to-one; sizes
+// spread over three decades) of about n connections, in scratch contexts on
+// the same device, allocator and stream, and keeps the fastest grid for the
+// process.  The grid changes no result: items are addressed by index.
+namespace {
+
+// serialises tuner runs (the scratch contexts of a run read the cache at init)
+std::mutex& fused_tune_mutex() {
+    static std::mutex m;
+    return m;
+}
+
+std::atomic<int>* fused_tune_cache() {
+    static std::atomic<int> best[64] = {};
+    return best;
+}
+
+float time_fused_grid(snnc_ctx* ctx, int wgs, uint64_t n) {
+    snnc_ctx* t = nullptr;
+    auto check = [&](snnc_status st) {
+        if (st != SNNC_OK) {
+            const std::string msg = t ? snnc_last_error(t) : "scratch context";
+            if (t) snnc_destroy(t);
+            raise(st, "fused autotuner: " + msg);
+        }
+    };
+    check(snnc_init(&t, 1, 0, 7, 0.1, ctx->has_alloc ? &ctx->alloc : nullptr, ctx->stream, 0));
+    check(snnc_tune(t, "fused_wgs_per_cu", wgs));
+    check(snnc_set_resident_budget(t, ~0ull >> 1));
+    snnc_segment a{}, b{};
+    check(snnc_create(t, 0, 100000, &a));
+    check(snnc_create(t, 0, 80000, &b));
+    // about n connections per batch in 48 requests, sizes log-spread over 1e3 .. 1e6 x scale
+    std::vector<snnc_conn_spec> cs;
+    std::vector<snnc_nodeset> S, T;
+    std::vector<snnc_segment> segs;
+    segs.reserve(2 * 48);
+    const double scale = std::max(1.0, (double)n / 48.0 / 3.0e5);
+    for (int i = 0; i < 48; ++i) {
+        const double size = 1.0e3 * std::pow(1.0e3, (double)i / 47.0) * scale;
+        snnc_conn_spec c{};
+        c.allow_autapses = c.allow_multapses = 1;
+        snnc_segment src = (i & 1) ? a : b, tgt = (i & 1) ? b : a;
+        switch (i % 4) {
+        case 0:   // in-degree over a prefix of the targets
+            tgt.n = (uint32_t)std::min<double>(tgt.n, std::max(1.0, size / 100.0));
+            c.kind = SNNC_FIXED_INDEGREE;
+            c.n = std::max<uint64_t>(1, (uint64_t)(size / tgt.n));
+            break;
+        case 1:
+            src.n = (uint32_t)std::min<double>(src.n, std::max(1.0, size / 50.0));
+            c.kind = SNNC_FIXED_OUTDEGREE;
+            c.n = std::max<uint64_t>(1, (uint64_t)(size / src.n));
+            break;
+        case 2:
+            c.kind = SNNC_FIXED_TOTAL_NUMBER;
+            c.n = (uint64_t)size;
+            break;
+        default:
+            src.n = tgt.n = (uint32_t)std::min<double>(std::min(src.n, tgt.n), size);
+            c.kind = SNNC_ONE_TO_ONE;
+            break;
+        }
+        segs.push_back(src);
+        segs.push_back(tgt);
+        cs.push_back(c);
+    }
+    for (int i = 0; i < 48; ++i) {
+        S.push_back(snnc_nodeset{&segs[2 * i], 1});
+        T.push_back(snnc_nodeset{&segs[2 * i + 1], 1});
+    }
+    snnc_syn_spec syn{};
+    syn.weight.kind = SNNC_NORMAL;
+    syn.weight.mean = 0.1;
+    syn.weight.sd = 0.01;
+    syn.delay_ms.kind = SNNC_NORMAL;
+    syn.delay_ms.mean = 1.5;
+    syn.delay_ms.sd = 0.75;
+    syn.delay_ms.lo = 0.1;
+    std::vector<snnc_syn_spec> Y(48, syn);
+    std::vector<int32_t> A(48, -1);
+    std::vector<snnc_status> st(48);
+    std::vector<uint32_t> ids(48);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best = 1e30f;
+    try {
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        for (int rep = 0; rep < 3; ++rep) {   // the first run captures the graph
+            check(snnc_submit_many(t, 48, S.data(), T.data(), cs.data(), Y.data(), A.data(), st.data(), ids.data()));
+            for (int i = 0; i < 48; ++i) check(st[i]);
+            check(snnc_sync(t));
+            HIPCHK(hipEventRecord(e0, t->stream));
+            check(snnc_flush(t));
+            HIPCHK(hipEventRecord(e1, t->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (rep) best = std::min(best, ms);
+        }
+    } catch (...) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        snnc_destroy(t);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    snnc_destroy(t);
+    return best;
+}
+
+}  // namespace
+
+int fused_grid_tuned(int device) {
+    if (device < 0 || device >= 64) return 0;
+    return fused_tune_cache()[device].load();
+}
+
 }  // namespace snnc
 
 using namespace snnc;
@@ -925,6 +1294,9 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
         HIPCHK(hipMemsetAsync(c->d_status, 0, 4, c->stream));
         sync(*c);
         noalloc_setup(*c);   // device address of the allocation-free sort's static scratch
+        c->gen_vmm = gen_blocks_supported(c->device);
+        const int tuned = fused_grid_tuned(c->device);   // the fused-launch autotuner's choice, if any
+        if (tuned) c->fused_wgs_per_cu = tuned;
     });
     if (st != SNNC_OK) {
         snnc_destroy(c);
@@ -942,6 +1314,7 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     for (auto& kv : c->arrays)
         if (kv.second.host) (void)hipHostFree(kv.second.p);
     c->arrays.clear();
+    gen_release(*c);
     std::vector<void*> ptrs;
     for (auto& kv : c->live) ptrs.push_back(kv.first);
     for (void* p : ptrs) raw_free(*c, p);
@@ -1102,6 +1475,7 @@ snnc_status snnc_prepare(snnc_ctx* c) {
         c->ms_prepare = ms;
         uint32_t status = 0;
         download(*c, &status, c->d_status, 4);
+        gen_release(*c);   // the stream has drained: the generation store goes back, still mapped
         if (status) raise(SNNC_EDEVICE, "a device wait exceeded its bound (status " + std::to_string(status) + ")");
         c->prepared = true;
     });
@@ -1228,6 +1602,12 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
         } else if (!strcmp(key, "map_path")) {
             if (value < 0 || value > 1) raise(SNNC_EINVAL, "map_path out of range");
             c->force_map_path = value == 1;
+        } else if (!strcmp(key, "gen_blocks")) {
+            if (value < 0 || value > 1) raise(SNNC_EINVAL, "gen_blocks must be 0 or 1");
+            if (c->cap_gen) raise(SNNC_ESTATE, "gen_blocks before the first connection");
+            if (value == 1 && !gen_blocks_supported(c->device))
+                raise(SNNC_EUNSUPPORTED, "the device has no virtual memory management");
+            c->gen_vmm = value == 1;
         } else if (!strcmp(key, "floyd_wave_max")) {
             if (value < 0 || value > 8192) raise(SNNC_EINVAL, "floyd_wave_max out of range");
             c->floyd_wave_max = (uint32_t)value;
@@ -1244,6 +1624,33 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
     });
 }
 
+
+snnc_status snnc_autotune_fused(snnc_ctx* c, uint64_t n, int32_t* wgs_out, float* ms_out) {
+    if (!c || !wgs_out || !ms_out || n == 0) return SNNC_EINVAL;
+    return guarded(c, [&] {
+        if (c->prepared) raise(SNNC_ESTATE, "autotune after prepare");
+        if (c->device < 0 || c->device >= 64) raise(SNNC_EUNSUPPORTED, "device ordinal above 63");
+        std::lock_guard<std::mutex> lock(fused_tune_mutex());
+        int best_w = fused_tune_cache()[c->device].load();
+        float best = -1.f;
+        if (!best_w) {
+            best = 1e30f;
+            for (int w : {1, 2, 4, 8, 16, 32}) {
+                const float ms = time_fused_grid(c, w, n);
+                if (ms < best) {
+                    best = ms;
+                    best_w = w;
+                }
+            }
+            fused_tune_cache()[c->device].store(best_w);
+        }
+        c->fused_wgs_per_cu = best_w;
+        if (c->fused_exec) HIPCHK(hipGraphExecDestroy(c->fused_exec));
+        c->fused_exec = nullptr;
+        *wgs_out = best_w;
+        *ms_out = best;
+    });
+}
 
 snnc_status snnc_set_memory_level(snnc_ctx* c, int32_t level) {
     if (!c) return SNNC_EINVAL;

@@ -533,9 +533,10 @@ struct FloydArgs {
 // detected by an earlier occurrence (A_j).  A high value m_i (i < j) is chosen
 // at step i when step i took its fallback or drew m_i itself, else at its
 // first later draw; so dup_j = A_j or dup_i.  These links point to earlier
-// steps and are resolved by pointer jumping.  Then the chosen values are
-// sorted ascending -- the same set as inserting one by one.  K <= 8192, so a
-// step index fits 13 bits of the sort key.
+// steps and are resolved by pointer jumping.  The chosen values -- the same
+// set as inserting one by one -- are then listed in ascending order from the
+// one sort of the draws and flags over the top window.  K <= 8192, so a step
+// index fits 13 bits of the sort key.
 // NT threads per unit: 256, or one wave (64) for padded degrees up to the
 // context's floyd_wave_max, where the barriers of a one-wave workgroup cost
 // next to nothing and many units share a compute unit.
@@ -549,7 +550,6 @@ __global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
     uint16_t* par1 = par0 + kp;
     uint8_t* dup0 = reinterpret_cast<uint8_t*>(par1 + kp);
     uint8_t* dup1 = dup0 + kp;
-    uint32_t* vals = reinterpret_cast<uint32_t*>(lds_raw);           // aliases key once it is no longer needed
     const uint32_t tid = threadIdx.x;
     for (uint64_t u = blockIdx.x; u < a.n_units; u += gridDim.x) {
         uint32_t lo = 0, hi = a.nch;
@@ -621,26 +621,42 @@ __global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
             uint16_t* tp = pa; pa = pb; pb = tp;
             uint8_t* td = da; da = db; db = td;
         }
-        for (uint32_t j = tid; j < kp; j += NT)
-            vals[j] = j < a.K ? (da[j] ? base_m + j : rv[j]) : 0xffffffffu;
-        __syncthreads();
-        for (uint32_t size = 2; size <= kp; size <<= 1) {      // bitonic sort of the chosen values
-            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t i = tid; i < kp / 2; i += NT) {
-                    const uint32_t lo_i = 2 * i - (i & (stride - 1));
-                    const uint32_t hi_i = lo_i + stride;
-                    const bool up = ((lo_i & size) == 0);
-                    const uint32_t x = vals[lo_i], y = vals[hi_i];
-                    if ((x > y) == up) {
-                        vals[lo_i] = y;
-                        vals[hi_i] = x;
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        // emit in ascending order (j = rank)
+        // The chosen values in ascending order, without sorting them again: a
+        // low value (< base_m) is chosen at its first draw, so the distinct low
+        // draws are the run starts of the sorted keys; every other chosen value
+        // lies in the window [base_m, base_m + K) and is flagged there (step
+        // j's fallback base_m + j, or a high draw kept as drawn).  Low values
+        // come first, then the flagged window positions; each thread takes a
+        // contiguous range of positions, one scan gives its output offsets.
         __shared__ uint32_t wsum[NT / 64];
+        for (uint32_t i = tid; i < a.K; i += NT) db[i] = 0;
+        __syncthreads();
+        for (uint32_t j = tid; j < a.K; j += NT) {
+            if (da[j]) db[j] = 1;
+            else if (rv[j] >= base_m) db[rv[j] - base_m] = 1;
+        }
+        __syncthreads();
+        uint32_t* vals = rv;   // the draws are no longer needed: chosen values in rank order
+        const uint32_t per = (a.K + NT - 1) / NT;
+        const uint32_t q0 = min(tid * per, a.K), q1 = min(q0 + per, a.K);
+        auto low_start = [&](uint32_t q) {
+            const uint64_t v = key[q] >> 13;
+            return v < base_m && (q == 0 || (key[q - 1] >> 13) != v);
+        };
+        uint32_t n_low = 0, n_high = 0;
+        for (uint32_t q = q0; q < q1; ++q) {
+            n_low += low_start(q) ? 1u : 0u;
+            n_high += db[q];
+        }
+        uint32_t tot_low, tot_high;
+        uint32_t at_low = block_excl_scan<NT>(n_low, wsum, &tot_low);
+        uint32_t at_high = tot_low + block_excl_scan<NT>(n_high, wsum, &tot_high);
+        for (uint32_t q = q0; q < q1; ++q) {
+            if (low_start(q)) vals[at_low++] = (uint32_t)(key[q] >> 13);
+            if (db[q]) vals[at_high++] = base_m + q;
+        }
+        __syncthreads();
+        // emit in ascending order (j = rank)
         uint64_t running = 0;
         if constexpr (MODE == WRITE) running = unit_offsets[u];
         uint32_t counted = 0;
@@ -1405,8 +1421,10 @@ __global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs,
 
 // Descriptor of a call for the fused launch, or false if the call needs its
 // own launches (counting passes, Floyd's sampling, restricted total number).
-// Chunk tables go to `owned` (kept until the batch has run).
-bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<void*>& owned) {
+// The call's chunk table is appended to `chunks` (all tables of a batch go to
+// the device in one block); the descriptor's table pointer is set by the
+// caller once that block exists (`*chunk_at` = first entry in `chunks`).
+bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<TChunk>& chunks, size_t* chunk_at) {
     const uint32_t host = c.P_local;
     const uint32_t nS = (uint32_t)cl.S.seg.size(), nT = (uint32_t)cl.T.seg.size();
     const uint64_t ns = cl.S.total, nt = cl.T.total;
@@ -1420,10 +1438,11 @@ bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<void*>& owned) {
         if (!cl.multapses) return false;
         const uint64_t K = cl.n;
         auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, K, MAX_RUN_ELEMS);
-        DeviceChunks dc = upload_chunks(c, runs, runs_elems(runs, K));
-        owned.push_back(dc.d);
+        *chunk_at = chunks.size();
+        chunks.insert(chunks.end(), runs.begin(), runs.end());
         q.kind = F_INDEGREE;
-        q.ind = InDegree{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)ns, c.seed, cl.id};
+        q.ind = InDegree{nullptr, (uint32_t)runs.size(), (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)ns, c.seed,
+                         cl.id};
         return true;
     }
     case SNNC_FIXED_OUTDEGREE: {
@@ -1433,10 +1452,11 @@ bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<void*>& owned) {
         if (on_host != nt) return false;
         const uint64_t K = cl.n;
         auto runs = unit_runs(cl.S, cl.autapses ? nullptr : &cl.T, -1, K, MAX_RUN_ELEMS);
-        DeviceChunks dc = upload_chunks(c, runs, runs_elems(runs, K));
-        owned.push_back(dc.d);
+        *chunk_at = chunks.size();
+        chunks.insert(chunks.end(), runs.begin(), runs.end());
         q.kind = F_OUTDEGREE;
-        q.outd = OutDegree{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt, cl.dT, nT, host, c.seed, cl.id};
+        q.outd = OutDegree{nullptr, (uint32_t)runs.size(), (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt, cl.dT,
+                           nT, host, c.seed, cl.id};
         return true;
     }
     case SNNC_FIXED_TOTAL_NUMBER: {
@@ -1460,10 +1480,10 @@ bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<void*>& owned) {
             kept.push_back(k);
         }
         if (items != cl.gen_count) return false;
-        DeviceChunks dc = upload_chunks(c, kept, items);
-        owned.push_back(dc.d);
+        *chunk_at = chunks.size();
+        chunks.insert(chunks.end(), kept.begin(), kept.end());
         q.kind = F_ONE_TO_ONE;
-        q.o2o = OneToOne{dc.d, dc.n, 1u};   // autapse runs are gone
+        q.o2o = OneToOne{nullptr, (uint32_t)kept.size(), 1u};   // autapse runs are gone
         return true;
     }
     default:
@@ -1513,21 +1533,43 @@ void gen_mark(Ctx& c, Call& cl, uint32_t host, uint32_t* bits) { run_call(c, cl,
 // writing at their admitted positions.  Records the batch's completion event.
 void flush_batch(Ctx& c, const std::vector<uint32_t>& ids, hipEvent_t done) {
     std::vector<FusedReq> reqs;
+    std::vector<size_t> chunk_at;
+    std::vector<TChunk> chunks;
     std::vector<uint32_t> rest;
     uint64_t total = 0;
+    uint32_t first_fused = UINT32_MAX;
     for (uint32_t id : ids) {
         Call& cl = c.calls[id];
         FusedReq q;
+        size_t at = SIZE_MAX;
         if (!cl.gen_count) {           // nothing to generate on this host
             release_pre(c, cl);
             continue;
         }
-        if (c.fuse_batches && fused_desc(c, cl, q, cl.owned)) {
+        if (c.fuse_batches && fused_desc(c, cl, q, chunks, &at)) {
             q.item_begin = total;
             total += cl.gen_count;
             reqs.push_back(q);
+            chunk_at.push_back(at);
+            if (first_fused == UINT32_MAX) first_fused = id;
         } else if (cl.gen_count) {
             rest.push_back(id);
+        }
+    }
+    if (!chunks.empty()) {
+        // the chunk tables of every fused call: one block, one copy (kept until Prepare)
+        TChunk* dev = dalloc_n<TChunk>(c, chunks.size());
+        c.calls[first_fused].owned.push_back(dev);
+        upload(c, dev, chunks.data(), chunks.size() * sizeof(TChunk));
+        for (size_t k = 0; k < reqs.size(); ++k) {
+            if (chunk_at[k] == SIZE_MAX) continue;
+            TChunk* t = dev + chunk_at[k];
+            switch (reqs[k].kind) {
+            case F_INDEGREE: reqs[k].ind.ch = t; break;
+            case F_OUTDEGREE: reqs[k].outd.ch = t; break;
+            case F_ONE_TO_ONE: reqs[k].o2o.ch = t; break;
+            default: break;
+            }
         }
     }
     if (!reqs.empty()) {

@@ -90,6 +90,7 @@ struct Call {
     std::shared_ptr<const DelayTable> dtab;   // normal delays only
     // device copies
     void* meta = nullptr;       // one allocation: S segs, T segs, delay table
+    bool meta_shared = false;   // meta lies in a block shared by a batch of calls (released with the context)
     size_t meta_bytes = 0;
     SegD* dS = nullptr;
     SegD* dT = nullptr;
@@ -185,6 +186,13 @@ struct Ctx {
     uint16_t* g_delay = nullptr;
     float* g_weight = nullptr;
     uint64_t n_gen = 0, cap_gen = 0;
+    // generation store in fixed-size blocks of physical memory mapped behind
+    // reserved virtual ranges (when the device supports it; tunable gen_blocks)
+    bool gen_vmm = false;
+    char* gen_va[4] = {nullptr, nullptr, nullptr, nullptr};   // src, tgt, delay, weight
+    bool gen_pooled = false;                                   // taken from the device's mapped store
+    uint64_t gen_mapped = 0;                                   // connections mapped
+    std::vector<std::array<void*, 4>> gen_handles;             // physical blocks (hipMemGenericAllocationHandle_t)
 
     // results of prepare
     std::map<int32_t, DevArray> arrays;    // by snnc_array_id
@@ -341,6 +349,13 @@ void flush_batch(Ctx& c, const std::vector<uint32_t>& ids, hipEvent_t done);
 void flush_pending(Ctx& c);
 // grow the generation-order arrays to hold `need` connections
 void grow_gen(Ctx& c, uint64_t need);
+// hands the generation block store back after the caller has waited for every
+// kernel that uses it (kept mapped for the next context on the device)
+void gen_release(Ctx& c);
+// workgroups per compute unit that the fused-launch autotuner chose for the
+// device in this process (0: not tuned)
+int fused_grid_tuned(int device);
+bool gen_blocks_supported(int device);
 
 // host-side helpers shared by the planner files
 std::vector<TChunk> target_chunks(const Call& cl, uint32_t host, uint64_t K, uint64_t max_elems);

@@ -997,9 +997,11 @@ void prepare_all(Ctx& c) {
             tstop(c);
             HIPCHK(hipGetLastError());
             // the source ordinals, targets and delays now live in the keys (released in stream order)
-            dfree(c, c.g_src); c.g_src = nullptr;
-            dfree(c, c.g_tgt); c.g_tgt = nullptr;
-            dfree(c, c.g_delay); c.g_delay = nullptr;
+            if (!c.gen_vmm) {   // block store: handed back after Prepare's final wait
+                dfree(c, c.g_src); c.g_src = nullptr;
+                dfree(c, c.g_tgt); c.g_tgt = nullptr;
+                dfree(c, c.g_delay); c.g_delay = nullptr;
+            }
             keys1 = static_cast<uint64_t*>(tmp(N * 8));
             vals1 = static_cast<uint32_t*>(tmp(N * 4));
             // outputs allocated only now, so they reuse the memory just released
@@ -1116,8 +1118,11 @@ void prepare_all(Ctx& c) {
         c.n_img = n_img;
         // word ranks of the image bit set (the collective arrays look images up by bit)
         if (!mapped) scan_popc_u64(c, bits, word_rank, n_words, false);
-        dfree(c, c.g_weight); c.g_weight = nullptr;
-        c.cap_gen = 0;
+        if (!c.gen_vmm) {   // block store: unmapped after the final wait of Prepare
+            dfree(c, c.g_weight);
+            c.g_weight = nullptr;
+            c.cap_gen = 0;
+        }
         (void)row_ptr;
 
         // ---------------------------------------------------------- 6 point-to-point lists

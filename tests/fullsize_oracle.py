@@ -187,7 +187,9 @@ def _slices(outdir, items_k, t0, t1, names):
         if a == b:
             continue
         for n in names:
-            out[n].append(np.load(os.path.join(outdir, f"a{k}_{n}.npy"), mmap_mode="r")[a:b])
+            mm = np.load(os.path.join(outdir, f"a{k}_{n}.npy"), mmap_mode="r")
+            out[n].append(np.array(mm[a:b]))      # a copy: the mapping (and its file) closes here
+            del mm
     return {n: (np.concatenate(v) if v else None) for n, v in out.items()}
 
 

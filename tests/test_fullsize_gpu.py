@@ -162,3 +162,9 @@ def test_served_full_size(scratch):
             f"oracle's ({time.time() - t0:.1f} s)")
     finally:
         h.close()
+
+
+def test_indegree_x10_full_size(scratch):
+    # the in-degree sweep's largest scale: K = 90,000 + 22,500 per target, 1.6e4 + 4e3 sources per host
+    _whole(W.balanced_indegree(10), 0, scratch, maps=("r_off", "r_val", "l_val", "img_base"),
+           extra=("groups", "h_off", "h_val", "i_val", "gq_ptr", "g_val", "q_val"))

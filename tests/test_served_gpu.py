@@ -201,3 +201,88 @@ def test_served_poll_and_flush_order():
     with pytest.raises(snnc.SnncError):
         net.flush()
     net.close()
+
+
+@pytest.mark.parametrize("reserve", [0, 40_000_000])
+def test_generation_blocks_equal_doubling(reserve):
+    """Generation arrays in mapped fixed-size blocks (grown as calls and
+    admitted requests need them; 2^26 connections per block, so these
+    8.2e7-connection builds cross block boundaries inside calls) equal the
+    doubling arrays, before and after Prepare, per call and in batches."""
+    import torch
+    torch.cuda.set_device(0)
+    b = W._Builder(1, seed=3)
+    a = b.create(0, 60000)
+    c = b.create(0, 50000)
+    syn = {"weight": {"kind": "normal", "mean": 0.1, "sd": 0.01},
+           "delay": {"kind": "normal", "mean": 1.5, "sd": 0.75, "lo": 0.1}}
+    b.connect([a], [c], {"rule": "fixed_indegree", "n": 700}, syn)
+    b.connect([c], [a], {"rule": "fixed_outdegree", "n": 520}, syn)
+    b.connect([a], [a], {"rule": "fixed_total_number", "n": 21_000_000, "autapses": False}, syn)
+    script = b.script("blocks")
+    out = []
+    for blocks, batched in ((0, False), (1, False), (1, True)):
+        net = snnc.Network(1, 0, script["seed"], script["dt"])
+        try:
+            net.tune("gen_blocks", blocks)
+        except snnc.SnncError as e:
+            pytest.skip(f"no virtual memory management: {e}")
+        if reserve:
+            net.reserve(reserve)
+        if batched:
+            net.set_resident_budget(1 << 40)
+        for op in script["ops"]:
+            if op[0] == "create":
+                net.create(op[1], op[2])
+        ops = [op[1:] for op in script["ops"] if op[0] == "connect"]
+        if batched:
+            assert [st for st, _ in net.submit_many(ops)] == [0, 0, 0]
+            net.flush()
+        else:
+            for op in ops:
+                net.connect(*op)
+        net.sync()
+        n = net.count("gen_src")
+        assert n == 50000 * 700 + 50000 * 520 + 21_000_000
+        got = {k: net.array_range(k, 0, n)[::997].copy() for k in GEN_ARRAYS}
+        net.prepare()
+        got.update({k: net.array(k) for k in ("src", "tgt", "delay", "weight", "row_ptr")})
+        net.close()
+        out.append(got)
+    for got in out[1:]:
+        for k in out[0]:
+            np.testing.assert_array_equal(out[0][k], got[k], err_msg=k)
+    log(f"generation blocks (reserve {reserve}): equal to the doubling arrays")
+
+
+def test_fused_grid_autotuner():
+    """The fused-launch autotuner picks one of its grids, caches it for the
+    device (a second call returns at once, new contexts take it), and the
+    grid changes nothing in the network."""
+    import torch
+    torch.cuda.set_device(0)
+    net = snnc.Network(1, 0, 1, 0.1)
+    r = net.autotune_fused(3_000_000)
+    assert r["fused_wgs_per_cu"] in (1, 2, 4, 8, 16, 32)
+    again = net.autotune_fused(3_000_000)
+    assert again["fused_wgs_per_cu"] == r["fused_wgs_per_cu"] and again["ms"] == -1.0
+    net.close()
+    script = _served_script(n=60, seed=21)
+    a, _ = _build(script, "batched", 1 << 40)                     # the tuned grid (taken at init)
+    outs = []
+    for w in (1, 32):
+        net = snnc.Network(1, 0, script["seed"], script["dt"])
+        net.tune("fused_wgs_per_cu", w)
+        net.set_resident_budget(1 << 40)
+        for op in script["ops"]:
+            if op[0] == "create":
+                net.create(op[1], op[2])
+        for k0 in range(0, 60, 17):
+            net.submit_many([op[1:] for op in script["ops"] if op[0] == "connect"][k0:k0 + 17])
+            net.flush()
+        net.prepare()
+        outs.append({k: net.array(k) for k in PREP_ARRAYS})
+        net.close()
+    for o in outs:
+        for k in PREP_ARRAYS:
+            np.testing.assert_array_equal(a[k], o[k], err_msg=k)
