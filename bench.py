@@ -382,8 +382,12 @@ def served(args):
     reqs = [op for op in script["ops"] if op[0] == "connect"]
     batch = snnc.RequestBatch([op[1:] for op in reqs])
 
+    tune = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.tune}
+
     def fresh():
         net = snnc.Network(1, 0, script["seed"], script["dt"])
+        for key, val in tune.items():
+            net.tune(key, val)
         net.set_resident_budget(budget)
         if args.reserve:
             net.reserve(budget // 14)
@@ -511,10 +515,12 @@ def served(args):
         "config": {"workload": "served_requests", "requests": len(reqs), "budget_gib": args.budget_gib,
                    "populations": len(creates), "neurons": stats["M_local"],
                    "offered_connections": script["info"]["offered"], "connections": n_conn,
-                   "batch": args.batch, "key_bits": stats["key_bits"], "sort_passes": stats["sort_passes"]},
+                   "batch": args.batch, "key_bits": stats["key_bits"], "sort_passes": stats["sort_passes"],
+                   "tune": tune or None},
         "requests": tally,
         "fused_tuning": fused_tuning,
-        "step_ms": {"min": round(1e3 * min(times), 3), "median": round(1e3 * sorted(times)[len(times) // 2], 3)},
+        "step_ms": {"min": round(1e3 * min(times), 3), "median": round(1e3 * sorted(times)[len(times) // 2], 3),
+                    "each": [round(1e3 * t, 1) for t in times]},
         "per_call": {"Gconn_s": round(n_pc / t_pc / 1e9, 4), "ms": round(1e3 * t_pc, 3)},
         "batched_over_per_call": round(value / (n_pc / t_pc / 1e9), 3),
         "latency": {"lambda_req_per_s": round(lam, 1), "n": int(soj_ms.size),

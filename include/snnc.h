@@ -533,8 +533,19 @@ snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
  * its bit row in LDS when the row has at most 2^19 neurons; 0: a global
  * atomic per draw) and "floyd_wave_max" (0 .. 8192, default 1024: Floyd's
  * sampling of a unit runs in a one-wave workgroup when the degree rounded up
- * to a power of two is at most this, else in 256 threads).  Every setting
- * gives the same arrays. */
+ * to a power of two is at most this, else in 256 threads up to 2048 and in
+ * 1024 threads above) and "total_hash_max" (0 .. 2^26: fixed
+ * total number without multapses finds each pair's first candidate with a
+ * hash table for candidate windows up to this size, by sorting the pair keys
+ * above it; default 2^20) and "bern_masks" (1, default: the counting pass of
+ * pairwise Bernoulli keeps each item's 4-bit pair mask for the writing pass;
+ * 0: the writing pass draws them again) and "gen_blocks" (1, default where
+ * the device supports virtual memory management: the generation-order arrays
+ * live in fixed-size blocks of 2^26 connections mapped as calls and admitted
+ * requests need them, kept mapped for the next context on the device after
+ * Prepare; 0: arrays grown by doubling; set before the first connection,
+ * SNNC_EUNSUPPORTED for 1 without support).  Every setting gives the same
+ * arrays. */
 
 /* Autotuner of the source-major sort: times every pass algorithm and tile
  * shape (sort_mode x sort_variant) on n synthetic keys with `bits` sorted

@@ -211,8 +211,8 @@ struct BernItem {
     uint32_t tgt;     // target local id
 };
 
-// bit i set = pair 4 blk + i connects (inside the target's range, autapse rule applied)
-__device__ __forceinline__ uint32_t bern_mask(const BernPair& r, uint64_t g, BernItem& it) {
+// the item's target and pair block, without the draw; false past the target's pairs
+__device__ __forceinline__ bool bern_item(const BernPair& r, uint64_t g, BernItem& it, int64_t* self) {
     const TChunk c = r.ch[find_chunk(r.ch, r.nch, g)];
     const uint32_t rel = (uint32_t)(g - c.out_begin);
     const uint32_t t_rel = fastdiv(rel, r.fnb);
@@ -220,11 +220,17 @@ __device__ __forceinline__ uint32_t bern_mask(const BernPair& r, uint64_t g, Ber
     it.q0 = (c.t_ord + t_rel) * (uint64_t)r.n_s;
     it.blk = (it.q0 >> 2) + k;
     it.tgt = c.local_first + t_rel;
+    *self = c.self_base >= 0 ? c.self_base + t_rel : -1;
+    return it.blk * 4 < it.q0 + r.n_s;
+}
+
+// bit i set = pair 4 blk + i connects (inside the target's range, autapse rule applied)
+__device__ __forceinline__ uint32_t bern_mask(const BernPair& r, uint64_t g, BernItem& it) {
+    int64_t self;
+    if (!bern_item(r, g, it, &self)) return 0;
     const uint64_t q1 = it.q0 + r.n_s;
-    if (it.blk * 4 >= q1) return 0;
     const uint4 b = draw(r.seed, r.call, it.blk, PURPOSE_BERN);
     const uint32_t w[4] = {b.x, b.y, b.z, b.w};
-    const int64_t self = c.self_base >= 0 ? c.self_base + t_rel : -1;
     uint32_t mask = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -241,13 +247,16 @@ __device__ __forceinline__ Res bern_res(const BernItem& it, uint32_t i) {
     return Res{(uint32_t)(q - it.q0), it.tgt, q};
 }
 
-// COUNT: connections per tile.  WRITE: per round of NT items, a workgroup scan
-// of the per-item counts places every connection in an LDS list in pair order;
-// then all lanes take list entries in turn for the synapse values and the
-// stores, so the sparse hits of a low p do not leave most lanes of a wave idle.
+// COUNT: connections per tile, and each item's 4-bit mask into `masks` (when
+// given).  WRITE: the item masks from `masks` when given (the counting pass
+// drew them; no second Philox draw), else drawn again; per round of NT items,
+// a workgroup scan of the per-item counts places every connection in an LDS
+// list in pair order; then all lanes take list entries in turn for the
+// synapse values and the stores, so the sparse hits of a low p do not leave
+// most lanes of a wave idle.
 template <class Sink, int MODE>
 __global__ __launch_bounds__(NT) void k_bern(BernPair r, Sink sink, uint64_t n_items, uint64_t tile0,
-                                             uint32_t* tile_counts, const uint64_t* tile_offsets) {
+                                             uint32_t* tile_counts, const uint64_t* tile_offsets, uint8_t* masks) {
     __shared__ uint32_t scratch[NT / 64];
     __shared__ Res list[MODE == WRITE ? 4 * NT : 1];
     const uint64_t tile = tile0 + blockIdx.x;
@@ -259,7 +268,17 @@ __global__ __launch_bounds__(NT) void k_bern(BernPair r, Sink sink, uint64_t n_i
     for (int k = 0; k < IPT; ++k) {
         const uint64_t item = base + (uint64_t)k * NT + threadIdx.x;
         BernItem it{};
-        const uint32_t mask = item < n_items ? bern_mask(r, item, it) : 0u;
+        uint32_t mask = 0;
+        if (item < n_items) {
+            if (MODE == WRITE && masks) {
+                int64_t self;
+                mask = masks[item];
+                if (mask) (void)bern_item(r, item, it, &self);
+            } else {
+                mask = bern_mask(r, item, it);
+                if (MODE == COUNT && masks) masks[item] = (uint8_t)mask;
+            }
+        }
         if constexpr (MODE == MARK) {
             for (uint32_t m = mask; m; m &= m - 1) sink.mark(bern_res(it, __builtin_ctz(m)));
         } else if constexpr (MODE == COUNT) {
@@ -283,13 +302,13 @@ __global__ __launch_bounds__(NT) void k_bern(BernPair r, Sink sink, uint64_t n_i
 
 template <class Sink, int MODE>
 void launch_bern(Ctx& c, const BernPair& r, const Sink& sink, uint64_t n_items, uint32_t* tile_counts,
-                 const uint64_t* tile_offsets) {
+                 const uint64_t* tile_offsets, uint8_t* masks = nullptr) {
     const uint64_t tiles = (n_items + TILE - 1) / TILE;
     for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
         const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
         tstart(c, MODE == MARK ? "prep_mark" : "gen_bernoulli");
         hipLaunchKernelGGL((k_bern<Sink, MODE>), dim3(nb), dim3(NT), 0, c.stream, r, sink, n_items, t0, tile_counts,
-                           tile_offsets);
+                           tile_offsets, masks);
         tstop(c);
         HIPCHK(hipGetLastError());
     }
@@ -537,9 +556,10 @@ struct FloydArgs {
 // set as inserting one by one -- are then listed in ascending order from the
 // one sort of the draws and flags over the top window.  K <= 8192, so a step
 // index fits 13 bits of the sort key.
-// NT threads per unit: 256, or one wave (64) for padded degrees up to the
-// context's floyd_wave_max, where the barriers of a one-wave workgroup cost
-// next to nothing and many units share a compute unit.
+// NT threads per unit: one wave (64) for padded degrees up to the context's
+// floyd_wave_max, where the barriers of a one-wave workgroup cost next to
+// nothing and many units share a compute unit; 256 up to 2048; 1024 above,
+// where the LDS of a unit leaves room for one or two units per compute unit.
 template <int NT, class Sink, int MODE>
 __global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -785,11 +805,14 @@ void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_c
     if (a.kpad <= c.floyd_wave_max) {
         hipLaunchKernelGGL((k_floyd<64, Sink, MODE>), dim3(grid), dim3(64), shmem, c.stream, a, sink, unit_counts,
                            unit_offsets);
-    } else {
-        if (shmem > 64 * 1024)
-            HIPCHK(hipFuncSetAttribute((const void*)k_floyd<256, Sink, MODE>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+    } else if (a.kpad <= 2048) {
         hipLaunchKernelGGL((k_floyd<256, Sink, MODE>), dim3(grid), dim3(256), shmem, c.stream, a, sink, unit_counts,
+                           unit_offsets);
+    } else {
+        // 74 .. 147 KB of LDS leave room for one or two units per compute unit: 16 waves each
+        HIPCHK(hipFuncSetAttribute((const void*)k_floyd<1024, Sink, MODE>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+        hipLaunchKernelGGL((k_floyd<1024, Sink, MODE>), dim3(grid), dim3(1024), shmem, c.stream, a, sink, unit_counts,
                            unit_offsets);
     }
     tstop(c);
@@ -829,7 +852,6 @@ __global__ void k_first_flags(const uint64_t* keys, const uint32_t* vals, uint64
 // pass finds the slot again and flags the candidate that holds the minimum.
 // The result does not depend on the order of the atomics.
 constexpr uint64_t HASH_EMPTY = ~0ull;
-constexpr uint64_t HASH_MAX_WINDOW = 1u << 20;
 
 __device__ __forceinline__ uint64_t pair_hash(uint64_t x) {
     x ^= x >> 33;
@@ -1128,7 +1150,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             }
             for (;;) {
                 uint8_t* first = nullptr;
-                if (!cl.multapses && C <= HASH_MAX_WINDOW) {
+                if (!cl.multapses && C <= c.total_hash_max) {
                     uint64_t H = 1024;
                     while (H < C + C / 2) H <<= 1;
                     // keys (HASH_EMPTY) and earliest candidates (none yet) in one block, cleared by one fill
@@ -1267,37 +1289,45 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             }
             const uint64_t tiles = (items + TILE - 1) / TILE;
             uint64_t* off = nullptr;
+            uint8_t* masks = nullptr;   // the counting pass's item masks, read by the writing pass
             if (cl.pre_off && mode != Out::COUNT) {
-                // counted at admission: the tile offsets are kept with the call
+                // counted at admission: the tile offsets and item masks are kept with the call
                 off = cl.pre_off;
+                masks = cl.pre_first;
                 result = cl.pre_count;
                 cl.pre_off = nullptr;
+                cl.pre_first = nullptr;
                 temps.push_back(off);
+                temps.push_back(masks);
             } else {
                 uint32_t* cnt = dalloc_n<uint32_t>(c, tiles);
                 temps.push_back(cnt);
                 off = dalloc_n<uint64_t>(c, tiles + 1);
-                launch_bern<WriteSink, COUNT>(c, r, ws, items, cnt, nullptr);
+                if (c.bern_masks) masks = dalloc_n<uint8_t>(c, items);
+                launch_bern<WriteSink, COUNT>(c, r, ws, items, cnt, nullptr, masks);
                 if (mode == Out::COUNT && c.defer_slot) {
                     // batched admission: the total goes to the caller's mapped word, read after one
-                    // wait for the whole batch; the tile offsets stay with the call
+                    // wait for the whole batch; the tile offsets and masks stay with the call
                     scan_u32_u64_to(c, cnt, off, tiles, c.defer_slot);
-                    dfree(c, cl.pre_off);
+                    release_pre(c, cl);
                     cl.pre_off = off;
+                    cl.pre_first = masks;
                     cl.deferred = 1;
                     break;
                 }
                 result = scan_u32_u64(c, cnt, off, tiles, true);
                 if (mode == Out::COUNT) {
-                    dfree(c, cl.pre_off);
+                    release_pre(c, cl);
                     cl.pre_off = off;
+                    cl.pre_first = masks;
                     cl.pre_count = result;
                 } else {
                     temps.push_back(off);
+                    temps.push_back(masks);
                 }
             }
             WriteSink* sink = reserve(result);
-            if (result) launch_bern<WriteSink, WRITE>(c, r, *sink, items, nullptr, off);
+            if (result) launch_bern<WriteSink, WRITE>(c, r, *sink, items, nullptr, off, masks);
             break;
         }
         case SNNC_ONE_TO_ONE: {

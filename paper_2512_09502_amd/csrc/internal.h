@@ -100,8 +100,10 @@ struct Call {
     std::vector<void*> owned;   // device tables kept until the call's batch has run
     int32_t batch = -1;         // served mode: batch that generates the call (-1: not yet flushed)
     // results of the admission count, reused by the generation: tile offsets
-    // (Bernoulli; valid-candidate offsets for fixed total number), and for fixed
-    // total number the kept-candidate offsets, first-occurrence flags and window
+    // (Bernoulli; valid-candidate offsets for fixed total number), per-item
+    // bytes (Bernoulli: the 4-bit pair masks of each item; fixed total number:
+    // first-occurrence flags), and for fixed total number the kept-candidate
+    // offsets and the window
     uint64_t* pre_off = nullptr;
     uint64_t* pre_koff = nullptr;
     uint8_t* pre_first = nullptr;
@@ -266,6 +268,8 @@ struct Ctx {
     bool fuse_batches = true;
     int fused_wgs_per_cu = 8;
     uint32_t floyd_wave_max = 1024;      // Floyd's sampling: one-wave workgroups up to this padded degree
+    uint64_t total_hash_max = 1u << 20;  // first occurrences by hashing up to this candidate window, else by sorting
+    bool bern_masks = true;              // Bernoulli: the counting pass keeps item masks for the writing pass
     size_t fused_cap = 0;
     void* fused_reqs = nullptr;
     void* fused_hdr = nullptr;

@@ -254,3 +254,13 @@ def test_floyd_workgroup_shapes(rule, k, n_src, n_tgt, aut, wave_max):
     s = _one(conn, n_src=n_src, n_tgt=n_tgt)
     s["tune"] = {"floyd_wave_max": wave_max}
     compare_all(s, 0)
+
+
+@pytest.mark.parametrize("hash_max", [0, 1 << 24])
+@pytest.mark.parametrize("n,aut", [(1_100_000, True), (150_000, False), (5_000_000, False)])
+def test_total_number_first_occurrence_paths(n, aut, hash_max):
+    # first candidates of each pair by sorting the pair keys (hash_max = 0) and by hashing
+    conn = {"rule": "fixed_total_number", "n": n, "autapses": aut, "multapses": False}
+    s = _one(conn)
+    s["tune"] = {"total_hash_max": hash_max}
+    compare_all(s, 0)
