@@ -150,10 +150,12 @@ def measured_traffic(kernel: str, n_elem: int, workload: str):
     try:
         table = json.load(open(path))
         entry = next(e for e in table["entries"] if e["kernel"] == kernel and e["workload"] == workload)
-        src = open(os.path.join(ROOT, entry["source"]), "rb").read()
+        sources = entry["source"] if isinstance(entry["source"], list) else [entry["source"]]
+        hashes = entry["sha1"] if isinstance(entry["sha1"], list) else [entry["sha1"]]
+        current = [hashlib.sha1(open(os.path.join(ROOT, s), "rb").read()).hexdigest() for s in sources]
     except (OSError, KeyError, ValueError, StopIteration):
         return None
-    if hashlib.sha1(src).hexdigest() != entry["sha1"]:
+    if current != hashes:
         return None
     return round(n_elem * (entry["read_bytes_per_elem"] + entry["write_bytes_per_elem"]))
 
@@ -180,9 +182,13 @@ def sort_roofline(kt_timed: dict, breakdown: dict, n_conn: int, counts: dict, wo
     phase = None
     if phase_ms > 0:
         ph = phase_bytes / (phase_ms * 1e-3) / 1e9
+        measured = measured_traffic("phase_sort_index", n_conn, workload)
         phase = {"kernels_ms": round(phase_ms, 3), "algorithmic_bytes": phase_bytes, "achieved": round(ph, 1),
                  "frac": round(ph / PEAK_HBM_GBS, 4),
-                 "bytes_per_conn_algorithmic": round(phase_bytes / n_conn, 3)}
+                 "bytes_per_conn_algorithmic": round(phase_bytes / n_conn, 3),
+                 "traffic": measured,
+                 "bytes_per_conn_measured": round(measured / n_conn, 2) if measured else None,
+                 "measured_GBs": round(measured / (phase_ms * 1e-3) / 1e9, 1) if measured else None}
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(name, n_conn, workload),
             "kernel": name, "launches_timed": launches, "avg_launch_ms": round(avg_ms, 4),
