@@ -49,6 +49,20 @@ struct WriteSink {
     __device__ __forceinline__ void mark(const Res&) const {}
 };
 
+// Source and target only, for Floyd's sampling (its synapse values are filled
+// afterwards by k_syn_fill: the sampling kernel then needs far fewer registers
+// than with the Box-Muller draw inline, and more of its waves fit a CU).
+struct IdSink {
+    uint32_t* src;
+    uint32_t* tgt;
+    uint64_t base;
+    __device__ __forceinline__ void put(uint64_t pos, const Res& r) const {
+        src[base + pos] = r.src;
+        tgt[base + pos] = r.tgt;
+    }
+    __device__ __forceinline__ void mark(const Res&) const {}
+};
+
 // Point-to-point regeneration: set the bit of every source that lives on
 // `host` (one bit row over that host's neurons).
 struct MarkSink {
@@ -527,6 +541,25 @@ uint64_t count_and_write(Ctx& c, const char* name, const Rule& rule, Provider pr
     return std::min(total, limit);
 }
 
+// Synapse values of a call written unit by unit (K elements per unit, in the
+// order of the unit runs): position p of the call holds element (t_ord + rel)
+// K + j of its run, rel = unit within the run, j = rank within the unit.
+__global__ __launch_bounds__(NT) void k_syn_fill(const TChunk* ch, uint32_t nch, uint32_t K, FastDiv fK,
+                                                 uint64_t items, SynD syn, uint32_t seed, uint32_t call,
+                                                 uint16_t* delay, float* weight, uint64_t base) {
+    for (uint64_t p = (uint64_t)blockIdx.x * NT + threadIdx.x; p < items; p += (uint64_t)gridDim.x * NT) {
+        const TChunk c = ch[find_chunk(ch, nch, p)];
+        const uint64_t off = p - c.out_begin;
+        const uint32_t rel = fastdiv((uint32_t)off, fK);   // a run holds fewer than 2^32 elements
+        const uint32_t j = (uint32_t)off - rel * K;
+        float w;
+        uint16_t d;
+        syn_values(syn, seed, call, (c.t_ord + rel) * (uint64_t)K + j, w, d);
+        delay[base + p] = d;
+        weight[base + p] = w;
+    }
+}
+
 // ------------------------------------------------------------------ Floyd's sampling
 // One workgroup per unit draws K distinct values in [0, n_eff) with the
 // draws r_j = index(IDX(base + j), n_eff - K + j + 1) of Floyd's sampling and
@@ -819,6 +852,20 @@ void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_c
     HIPCHK(hipGetLastError());
 }
 
+// Floyd's sampling written directly (one unit after another): sources and
+// targets by the sampler, then the synapse values by element index.
+void launch_floyd_direct(Ctx& c, const FloydArgs& a, const WriteSink& ws, uint64_t items) {
+    IdSink ids{ws.src, ws.tgt, ws.base};
+    launch_floyd<IdSink, DIRECT>(c, a, ids, nullptr, nullptr);
+    if (!items) return;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((items + NT - 1) / NT, 1u << 20);
+    tstart(c, "gen_floyd");
+    hipLaunchKernelGGL(k_syn_fill, dim3(grid), dim3(NT), 0, c.stream, a.ch, a.nch, a.K, make_fastdiv(a.K), items,
+                       ws.syn, ws.seed, ws.call, ws.delay, ws.weight, ws.base);
+    tstop(c);
+    HIPCHK(hipGetLastError());
+}
+
 uint32_t next_pow2(uint32_t x) {
     uint32_t p = 1;
     while (p < x) p <<= 1;
@@ -1049,7 +1096,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 FloydArgs a{dc.d, dc.n, items / K, (uint32_t)K, (uint32_t)ns, 1, cl.dT, nT, host,
                             next_pow2((uint32_t)K), c.seed, cl.id};
                 if (mark) launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
-                else launch_floyd<WriteSink, DIRECT>(c, a, *reserve(items), nullptr, nullptr);
+                else launch_floyd_direct(c, a, *reserve(items), items);
             }
             break;
         }
@@ -1089,7 +1136,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                     launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
                 } else if (all_local) {
                     result = items;
-                    launch_floyd<WriteSink, DIRECT>(c, a, *reserve(items), nullptr, nullptr);
+                    launch_floyd_direct(c, a, *reserve(items), items);
                 } else {
                     uint32_t* cnt = dalloc_n<uint32_t>(c, units);
                     temps.push_back(cnt);
