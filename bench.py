@@ -411,7 +411,9 @@ def served(args):
         """one build of the whole stream; timing 1 brackets every kernel
         launch, 2 the radix passes of Prepare only"""
         tally = {}
+        ti = time.perf_counter()
         net = fresh()
+        host_ms["init"] += 1e3 * (time.perf_counter() - ti)
         if timing == 1:
             net.set_timing(1)
         torch.cuda.synchronize()
@@ -436,7 +438,9 @@ def served(args):
         n = net.count("src")
         st = net.stats()
         kt = net.kernel_times() if timing else {}
+        tc = time.perf_counter()
         net.close()
+        host_ms["close"] += 1e3 * (time.perf_counter() - tc)
         return dt, n, tally, st, kt
 
     # grid of the persistent batch launch from the project autotuner (untimed;
@@ -444,9 +448,11 @@ def served(args):
     tuner = snnc.Network(1, 0, script["seed"], script["dt"])
     fused_tuning = tuner.autotune_fused(int(args.tune_conns))
     tuner.close()
+    host_ms = {"init": 0.0, "close": 0.0}   # context set-up (with Create) and destroy, summed
     # warm-up (untimed): the first full-size builds also grow the allocator's pool
     for _ in range(args.warmup):
         run("batched")
+    host_ms = {"init": 0.0, "close": 0.0}
     torch.cuda.synchronize()
     times, kt_total = [], {}
     n_conn, tally, stats = 0, {}, None
@@ -461,6 +467,7 @@ def served(args):
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
     value = n_conn * args.steps / total / 1e9
+    context_ms = {k: round(v / args.steps, 3) for k, v in host_ms.items()}
 
     if args.pmc_calibrate:   # outside the timed region: a copy of known size for the HBM counters
         x = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
@@ -526,7 +533,8 @@ def served(args):
         "requests": tally,
         "fused_tuning": fused_tuning,
         "step_ms": {"min": round(1e3 * min(times), 3), "median": round(1e3 * sorted(times)[len(times) // 2], 3),
-                    "each": [round(1e3 * t, 1) for t in times]},
+                    "each": [round(1e3 * t, 1) for t in times], "context_init": context_ms["init"],
+                    "context_close": context_ms["close"]},
         "per_call": {"Gconn_s": round(n_pc / t_pc / 1e9, 4), "ms": round(1e3 * t_pc, 3)},
         "batched_over_per_call": round(value / (n_pc / t_pc / 1e9), 3),
         "latency": {"lambda_req_per_s": round(lam, 1), "n": int(soj_ms.size),

@@ -23,7 +23,8 @@
  *    A failed call leaves the context as it was before the call.
  *  - Device memory: the context owns every device buffer.  It allocates
  *    through the caller's snnc_allocator (for instance a framework's caching
- *    allocator) or, if none is given, with hipMalloc.  Pointers handed out by
+ *    allocator) or, if none is given, stream-ordered from a memory pool the
+ *    library keeps per device.  Pointers handed out by
  *    snnc_get_array() are device pointers, valid until the next mutating call
  *    (connect, prepare, destroy) on the context.
  *  - Streams: all device work of a context is ordered on the HIP stream given
@@ -124,14 +125,19 @@ typedef struct {
 
 /* Create a context for host P_local of P virtual hosts.  seed keys every
  * Philox stream; dt_ms is the time step that delays are counted in.
- * `alloc` may be NULL (hipMalloc/hipFree).  budget_bytes > 0 caps the device
+ * `alloc` may be NULL (stream-ordered allocation from the library's pool).  budget_bytes > 0 caps the device
  * bytes the context may hold at once (SNNC_EBUDGET beyond).  The current HIP
  * device at the time of the call is the context's device.
  * Errors: SNNC_EINVAL for P == 0, P_local >= P, dt_ms <= 0. */
 snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t seed, double dt_ms,
                       const snnc_allocator* alloc, void* hip_stream, uint64_t budget_bytes);
 
-/* Free every device buffer of the context (after waiting for its stream). */
+/* Free every device buffer of the context (after waiting for its streams).
+ * Buffers the caller's allocator gave go back to it.  The library's own
+ * stream-ordered blocks are kept, up to 8 GiB per device, in a per-device
+ * cache that later contexts on that device draw exact-size blocks from
+ * (and pinned host staging buffers likewise); the rest return to the
+ * library's memory pool, which keeps its memory until the process ends. */
 snnc_status snnc_destroy(snnc_ctx* ctx);
 
 /* Message of the last failed call on this context ("" if none). */

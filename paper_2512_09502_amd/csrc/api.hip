@@ -22,6 +22,50 @@ void hip_check(hipError_t e, const char* what) {
 constexpr size_t SMALL_MAX = 1u << 20;   // blocks up to this size come from the slabs
 constexpr size_t SLAB_BYTES = 8u << 20;
 
+// Stream-ordered allocations come from one memory pool per device owned by
+// the library, which keeps freed memory (no release threshold): a served
+// stream makes a context per build, and memory returned to the driver at
+// every context's end would be mapped again by the next.
+static hipMemPool_t lib_pool(int device) {
+    static std::mutex m;
+    static hipMemPool_t pools[64] = {};
+    if (device < 0 || device >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(m);
+    if (!pools[device]) {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = device;
+        hipMemPool_t p = nullptr;
+        if (hipMemPoolCreate(&p, &props) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+        pools[device] = p;
+    }
+    return pools[device];
+}
+
+// Blocks of stream-ordered memory that a destroyed context held (after its
+// final wait) wait here for the next context on the device: freeing them
+// back to the pool costs milliseconds per block.  At most 8 GiB per device.
+namespace {
+constexpr size_t BLOCK_CACHE_MAX = 8ull << 30;
+
+struct BlockCache {
+    std::mutex m;
+    std::map<size_t, std::vector<void*>> free;
+    size_t bytes = 0;
+};
+
+BlockCache& block_cache(int device) {
+    static BlockCache caches[64];
+    return caches[device < 0 || device >= 64 ? 0 : device];
+}
+}  // namespace
+
 // Memory from the outer allocator.  `live` keeps the size with the lane in
 // bit 0: lane 0 uses the caller's allocator (else stream-ordered allocation
 // on the caller's stream), lane 1 stream-ordered allocation on the counting
@@ -37,7 +81,20 @@ static void* raw_alloc(Ctx& c, size_t bytes, int lane) {
         if (!p) raise(SNNC_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
     } else {
         // stream-ordered: a buffer freed after enqueued work is reused only by later work
-        hipError_t e = hipMallocAsync(&p, bytes, lane == 0 ? c.main_stream : c.count_stream);
+        hipStream_t strm = lane == 0 ? c.main_stream : c.count_stream;
+        {
+            BlockCache& bc = block_cache(c.device);
+            std::lock_guard<std::mutex> lock(bc.m);
+            auto it = bc.free.find(bytes);
+            if (it != bc.free.end() && !it->second.empty()) {
+                p = it->second.back();
+                it->second.pop_back();
+                bc.bytes -= bytes;
+            }
+        }
+        hipMemPool_t pool = p ? nullptr : lib_pool(c.device);
+        hipError_t e = p ? hipSuccess
+                         : pool ? hipMallocFromPoolAsync(&p, bytes, pool, strm) : hipMallocAsync(&p, bytes, strm);
         if (e != hipSuccess || !p) {
             (void)hipGetLastError();
             raise(SNNC_ENOMEM, "hipMallocAsync failed for " + std::to_string(bytes) + " bytes");
@@ -49,15 +106,29 @@ static void* raw_alloc(Ctx& c, size_t bytes, int lane) {
     return p;
 }
 
-static void raw_free(Ctx& c, void* p) {
+// to_cache: the context is being destroyed and its streams have drained, so a
+// stream-ordered block may go to the device's block cache instead.
+static void raw_free(Ctx& c, void* p, bool to_cache = false) {
     auto it = c.live.find(p);
     if (it == c.live.end()) return;
     const size_t bytes = it->second & ~(size_t)255;
     const int lane = (int)(it->second & 1);
     c.bytes_live -= bytes;
     c.live.erase(it);
-    if (lane == 0 && c.has_alloc) c.alloc.free(p, c.alloc.user);
-    else (void)hipFreeAsync(p, lane == 0 ? c.main_stream : c.count_stream);
+    if (lane == 0 && c.has_alloc) {
+        c.alloc.free(p, c.alloc.user);
+        return;
+    }
+    if (to_cache) {
+        BlockCache& bc = block_cache(c.device);
+        std::lock_guard<std::mutex> lock(bc.m);
+        if (bc.bytes + bytes <= BLOCK_CACHE_MAX) {
+            bc.free[bytes].push_back(p);
+            bc.bytes += bytes;
+            return;
+        }
+    }
+    (void)hipFreeAsync(p, lane == 0 ? c.main_stream : c.count_stream);
 }
 
 // Blocks up to SMALL_MAX come from a free list per power-of-two class,
@@ -221,16 +292,60 @@ void resolve_times(Ctx& c) {
     c.pending.clear();
 }
 
+// Pinned host buffers (staging rings, read-back and mapped words) outlive
+// their context in a process-wide cache keyed by size and flags: pinning and
+// unpinning pages costs milliseconds, and a served stream makes a context per
+// build.  The cache keeps a few buffers per key.
+namespace {
+std::mutex& pinned_mutex() {
+    static std::mutex m;
+    return m;
+}
+
+std::map<std::pair<size_t, unsigned>, std::vector<void*>>& pinned_cache() {
+    static std::map<std::pair<size_t, unsigned>, std::vector<void*>> m;
+    return m;
+}
+}  // namespace
+
+void* pinned_take(size_t bytes, unsigned flags) {
+    {
+        std::lock_guard<std::mutex> lock(pinned_mutex());
+        auto& v = pinned_cache()[{bytes, flags}];
+        if (!v.empty()) {
+            void* p = v.back();
+            v.pop_back();
+            return p;
+        }
+    }
+    void* p = nullptr;
+    HIPCHK(hipHostMalloc(&p, bytes, flags));
+    return p;
+}
+
+void pinned_give(void* p, size_t bytes, unsigned flags) {
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lock(pinned_mutex());
+        auto& v = pinned_cache()[{bytes, flags}];
+        if (v.size() < 4) {
+            v.push_back(p);
+            return;
+        }
+    }
+    (void)hipHostFree(p);
+}
+
 void init_ring(StageRing& r, size_t bytes) {
     for (auto& e : r.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    HIPCHK(hipHostMalloc((void**)&r.buf, bytes, hipHostMallocDefault));
+    r.buf = static_cast<char*>(pinned_take(bytes, hipHostMallocDefault));
     r.bytes = bytes;
 }
 
 void free_ring(StageRing& r) {
     for (auto& e : r.ev)
         if (e) (void)hipEventDestroy(e);
-    if (r.buf) (void)hipHostFree(r.buf);
+    pinned_give(r.buf, r.bytes, hipHostMallocDefault);
     r = StageRing{};
 }
 
@@ -903,12 +1018,12 @@ static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const 
     if (c.defer_cap < n) {
         if (c.defer_pin) {
             if (c.count_stream) HIPCHK(hipStreamSynchronize(c.count_stream));   // no count still writes to it
-            HIPCHK(hipHostFree(c.defer_pin));
+            pinned_give(c.defer_pin, c.defer_cap * 2 * sizeof(uint64_t), hipHostMallocMapped);
         }
         c.defer_pin = c.defer_pin_dev = nullptr;
         c.defer_cap = 0;
         const size_t cap = std::max<size_t>(n, 256);
-        HIPCHK(hipHostMalloc((void**)&c.defer_pin, cap * 2 * sizeof(uint64_t), hipHostMallocMapped));
+        c.defer_pin = static_cast<uint64_t*>(pinned_take(cap * 2 * sizeof(uint64_t), hipHostMallocMapped));
         HIPCHK(hipHostGetDevicePointer((void**)&c.defer_pin_dev, c.defer_pin, 0));
         c.defer_cap = cap;
     }
@@ -1287,8 +1402,8 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
         HIPCHK(hipEventCreate(&c->conn_last));
         init_ring(c->ring, 16u << 20);
         c->dl_pin_bytes = 64u << 10;
-        HIPCHK(hipHostMalloc((void**)&c->dl_pin, c->dl_pin_bytes, hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&c->tot_pin, 4 * sizeof(uint64_t), hipHostMallocMapped));
+        c->dl_pin = static_cast<char*>(pinned_take(c->dl_pin_bytes, hipHostMallocDefault));
+        c->tot_pin = static_cast<uint64_t*>(pinned_take(4 * sizeof(uint64_t), hipHostMallocMapped));
         HIPCHK(hipHostGetDevicePointer((void**)&c->tot_pin_dev, c->tot_pin, 0));
         c->d_status = dalloc_n<uint32_t>(*c, 1);
         HIPCHK(hipMemsetAsync(c->d_status, 0, 4, c->stream));
@@ -1317,7 +1432,7 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     gen_release(*c);
     std::vector<void*> ptrs;
     for (auto& kv : c->live) ptrs.push_back(kv.first);
-    for (void* p : ptrs) raw_free(*c, p);
+    for (void* p : ptrs) raw_free(*c, p, true);   // the streams have drained
     if (c->count_stream) (void)hipStreamSynchronize(c->count_stream);
     (void)hipStreamSynchronize(c->main_stream);
     for (auto& p : c->pending) {
@@ -1330,9 +1445,9 @@ snnc_status snnc_destroy(snnc_ctx* c) {
     if (c->conn_first) (void)hipEventDestroy(c->conn_first);
     if (c->conn_last) (void)hipEventDestroy(c->conn_last);
     free_ring(c->ring);
-    if (c->dl_pin) (void)hipHostFree(c->dl_pin);
-    if (c->tot_pin) (void)hipHostFree(c->tot_pin);
-    if (c->defer_pin) (void)hipHostFree(c->defer_pin);
+    pinned_give(c->dl_pin, c->dl_pin_bytes, hipHostMallocDefault);
+    pinned_give(c->tot_pin, 4 * sizeof(uint64_t), hipHostMallocMapped);
+    pinned_give(c->defer_pin, c->defer_cap * 2 * sizeof(uint64_t), hipHostMallocMapped);
     for (auto e : c->batch_done) (void)hipEventDestroy(e);
     if (c->fused_exec) (void)hipGraphExecDestroy(c->fused_exec);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
