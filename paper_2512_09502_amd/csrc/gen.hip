@@ -262,21 +262,55 @@ __device__ __forceinline__ Res bern_res(const BernItem& it, uint32_t i) {
 }
 
 // COUNT: connections per tile, and each item's 4-bit mask into `masks` (when
-// given).  WRITE: the item masks from `masks` when given (the counting pass
-// drew them; no second Philox draw), else drawn again; per round of NT items,
-// a workgroup scan of the per-item counts places every connection in an LDS
-// list in pair order; then all lanes take list entries in turn for the
-// synapse values and the stores, so the sparse hits of a low p do not leave
-// most lanes of a wave idle.
+// given).  WRITE: each thread takes IPT consecutive items of the tile, their
+// masks from `masks` when given (the counting pass drew them; no second
+// Philox draw), else drawn again; one workgroup scan of the per-thread counts
+// places every connection of the tile in an LDS list in pair order (its pair
+// within the tile, 2 bytes); then all lanes take list entries in turn for the
+// synapse values and the stores, so the sparse hits of a low p leave no lane
+// idle, with three barriers per tile.
 template <class Sink, int MODE>
 __global__ __launch_bounds__(NT) void k_bern(BernPair r, Sink sink, uint64_t n_items, uint64_t tile0,
                                              uint32_t* tile_counts, const uint64_t* tile_offsets, uint8_t* masks) {
     __shared__ uint32_t scratch[NT / 64];
-    __shared__ Res list[MODE == WRITE ? 4 * NT : 1];
     const uint64_t tile = tile0 + blockIdx.x;
     const uint64_t base = tile * TILE;
-    uint64_t running = 0;
-    if constexpr (MODE == WRITE) running = tile_offsets[tile];
+    if constexpr (MODE == WRITE) {
+        static_assert(4 * TILE <= 65536 && IPT <= 8, "pair index within a tile fits 16 bits, masks 32 bits");
+        __shared__ uint16_t hits[4 * TILE];
+        const uint64_t first = base + (uint64_t)threadIdx.x * IPT;
+        uint32_t mk = 0;   // 4 bits per item, item k at bits [4k, 4k + 4)
+        if (masks && first + IPT <= n_items && IPT == 4) {
+            const uint32_t w = *reinterpret_cast<const uint32_t*>(masks + first);   // 4-byte aligned: TILE, IPT multiples of 4
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) mk |= ((w >> (8 * k)) & 15u) << (4 * k);
+        } else {
+#pragma unroll
+            for (int k = 0; k < IPT; ++k) {
+                const uint64_t item = first + k;
+                if (item >= n_items) break;
+                BernItem it{};
+                const uint32_t m = masks ? (uint32_t)masks[item] : bern_mask(r, item, it);
+                mk |= (m & 15u) << (4 * k);
+            }
+        }
+        uint32_t tot;
+        uint32_t pre = block_excl_scan<NT>((uint32_t)__builtin_popcount(mk), scratch, &tot);
+        for (uint32_t m = mk; m; m &= m - 1) {
+            const uint32_t b = __builtin_ctz(m);   // = 4 k + pair within the item
+            hits[pre++] = (uint16_t)(threadIdx.x * IPT * 4 + b);
+        }
+        __syncthreads();
+        const uint64_t running = tile_offsets[tile];
+        for (uint32_t i = threadIdx.x; i < tot; i += NT) {
+            const uint32_t h = hits[i];
+            BernItem it{};
+            int64_t self;
+            (void)bern_item(r, base + (h >> 2), it, &self);
+            sink.put(running + i, bern_res(it, h & 3u));
+        }
+        return;
+    }
     uint32_t counted = 0;
 #pragma unroll 1
     for (int k = 0; k < IPT; ++k) {
@@ -284,27 +318,13 @@ __global__ __launch_bounds__(NT) void k_bern(BernPair r, Sink sink, uint64_t n_i
         BernItem it{};
         uint32_t mask = 0;
         if (item < n_items) {
-            if (MODE == WRITE && masks) {
-                int64_t self;
-                mask = masks[item];
-                if (mask) (void)bern_item(r, item, it, &self);
-            } else {
-                mask = bern_mask(r, item, it);
-                if (MODE == COUNT && masks) masks[item] = (uint8_t)mask;
-            }
+            mask = bern_mask(r, item, it);
+            if (MODE == COUNT && masks) masks[item] = (uint8_t)mask;
         }
         if constexpr (MODE == MARK) {
             for (uint32_t m = mask; m; m &= m - 1) sink.mark(bern_res(it, __builtin_ctz(m)));
-        } else if constexpr (MODE == COUNT) {
-            counted += __builtin_popcount(mask);
         } else {
-            uint32_t tot;
-            uint32_t pre = block_excl_scan<NT>((uint32_t)__builtin_popcount(mask), scratch, &tot);
-            for (uint32_t m = mask; m; m &= m - 1) list[pre++] = bern_res(it, __builtin_ctz(m));
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < tot; i += NT) sink.put(running + i, list[i]);
-            __syncthreads();
-            running += tot;
+            counted += __builtin_popcount(mask);
         }
     }
     if constexpr (MODE == COUNT) {
@@ -1231,7 +1251,15 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                     uint32_t bits = 0;
                     while (bits < 64 && (ns * nt - 1) >> bits) ++bits;
                     // every pass runs (no wait for the digit histograms): the pair keys are random
-                    const int which = radix_sort(c, k0, v0, k1, v1, C, 0, bits, nullptr, nullptr, false);
+                    c.sort_tag = "gen_total_sort";
+                    int which = 0;
+                    try {
+                        which = radix_sort(c, k0, v0, k1, v1, C, 0, bits, nullptr, nullptr, false);
+                    } catch (...) {
+                        c.sort_tag = nullptr;
+                        throw;
+                    }
+                    c.sort_tag = nullptr;
                     tstart(c, "gen_total_first");
                     hipLaunchKernelGGL(k_first_flags, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream,
                                        which ? k1 : k0, which ? v1 : v0, C, first);

@@ -204,6 +204,7 @@ struct Ctx {
 
     // timing
     int timing = 0;                      // 0 off, 1 every launch, 2 radix passes only
+    const char* sort_tag = nullptr;      // timer prefix of radix sorts outside Prepare (null: "sort")
     struct Pending {
         std::string name;
         hipEvent_t a, b;

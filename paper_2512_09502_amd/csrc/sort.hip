@@ -471,12 +471,18 @@ SortPlan plan_sort(const Ctx& c, uint64_t n, uint32_t bits) {
     return p;
 }
 
+// Timer name of a radix-sort step: "sort_<step>", or "<sort_tag>_<step>" for
+// the sorts that generation runs (kept out of the Prepare phase's figures).
+std::string sort_timer(const Ctx& c, const char* step) {
+    return std::string(c.sort_tag ? c.sort_tag : "sort") + "_" + step;
+}
+
 void launch_hist(Ctx& c, const uint64_t* keys, uint64_t n, uint32_t bit_lo, uint32_t bit_hi, uint32_t n9,
                  uint32_t dbits, uint32_t passes, uint64_t* hist) {
     HIPCHK(hipMemsetAsync(hist, 0, (size_t)passes * HSTRIDE * 8, c.stream));
     if (!n || !passes) return;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((n + HNT - 1) / HNT, 4096);
-    tstart(c, "sort_hist");
+    tstart(c, sort_timer(c, "hist").c_str());
     hipLaunchKernelGGL(k_hist, dim3(grid), dim3(HNT), 0, c.stream, keys, n, bit_lo, bit_hi, n9, dbits, passes, hist);
     tstop(c);
     HIPCHK(hipGetLastError());
@@ -558,7 +564,7 @@ int radix_sort_impl(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, u
                 off = dalloc_n<uint64_t>(c, (uint64_t)passes * HSTRIDE);
                 temps[1] = off;
             }
-            tstart(c, "sort_hist_scan");
+            tstart(c, sort_timer(c, "hist_scan").c_str());
             hipLaunchKernelGGL(k_hist_scan, dim3(passes), dim3(HSTRIDE), 0, c.stream, hist, off);
             tstop(c);
             HIPCHK(hipGetLastError());
@@ -609,14 +615,14 @@ int radix_sort_impl(Ctx& c, uint64_t* keys0, uint32_t* vals0, uint64_t* keys1, u
             PassArgs a{kb[cur], vb[cur], kb[cur ^ 1], vb[cur ^ 1], n, pass_shift(bit_lo, plan.n9, dbits, p), width,
                        off + (size_t)p * HSTRIDE, (uint64_t*)lookback, counter + p, epoch, status,
                        final_out ? *final_out : FinalOut{}, mode};
-            tstart(c, last ? "sort_pass_final" : "sort_pass");
+            tstart(c, sort_timer(c, last ? "pass_final" : "pass").c_str());
             launch_variant(c, variant, a, last, width > 8);
             tstop(c);
             HIPCHK(hipGetLastError());
             cur ^= 1;
         }
         if (final_out && !n_live && n) {
-            tstart(c, "sort_unpack");
+            tstart(c, sort_timer(c, "unpack").c_str());
             hipLaunchKernelGGL(k_unpack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c.stream, kb[cur], vb[cur], n,
                                *final_out);
             tstop(c);
