@@ -540,10 +540,12 @@ snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
  * atomic per draw) and "floyd_wave_max" (0 .. 8192, default 1024: Floyd's
  * sampling of a unit runs in a one-wave workgroup when the degree rounded up
  * to a power of two is at most this, else in 256 threads up to 2048 and in
- * 1024 threads above) and "total_hash_max" (0 .. 2^26: fixed
- * total number without multapses finds each pair's first candidate with a
- * hash table for candidate windows up to this size, by sorting the pair keys
- * above it; default 2^20) and "bern_masks" (1, default: the counting pass of
+ * 1024 threads above) and "total_hash_max" (0 .. 2^32: fixed
+ * total number without multapses finds each pair's first candidate by
+ * hashing for candidate windows up to this size -- a two-bit-per-slot filter
+ * of at least 16 slots per candidate settles the candidates alone in their
+ * slot, an exact table the rest -- and by sorting the pair keys above it;
+ * default 2^32, every window) and "bern_masks" (1, default: the counting pass of
  * pairwise Bernoulli keeps each item's 4-bit pair mask for the writing pass;
  * 0: the writing pass draws them again) and "gen_blocks" (1, default where
  * the device supports virtual memory management: the generation-order arrays

@@ -92,20 +92,41 @@ __device__ __forceinline__ uint32_t find_chunk(const TChunk* ch, uint32_t nch, u
     return a;
 }
 
+// A call's run table.  Up to CH_INLINE runs (a call over one source and one
+// target segment has one) travel inline with the kernel's arguments, so the
+// call needs no upload; longer tables live in device memory.
+constexpr uint32_t CH_INLINE = 4;
+
+struct ChunkTab {
+    const TChunk* d;            // device table when n > CH_INLINE, else null
+    uint32_t n;
+    TChunk in[CH_INLINE];
+    // the run holding element g (the last run starting at or before g)
+    __device__ __forceinline__ TChunk at(uint64_t g) const {
+        if (n <= CH_INLINE) {
+            TChunk c = in[0];
+#pragma unroll
+            for (uint32_t k = 1; k < CH_INLINE; ++k)
+                if (k < n && in[k].out_begin <= g) c = in[k];
+            return c;
+        }
+        return d[find_chunk(d, n, g)];
+    }
+};
+
 // ------------------------------------------------------------------ rules
 // Fixed in-degree with multapses: element e = t_ord K + j draws its source
 // ordinal from IDX(e) over the n_s candidates (n_s - 1 with the target itself
 // skipped when autapses are excluded).
 struct InDegree {
     static constexpr int R = 1;
-    const TChunk* ch;
-    uint32_t nch;
+    ChunkTab ch;
     uint32_t K;
     FastDiv fk;
     uint32_t n_s;
     uint32_t seed, call;
     __device__ __forceinline__ int eval(uint64_t g, Res* r) const {
-        const TChunk c = ch[find_chunk(ch, nch, g)];
+        const TChunk c = ch.at(g);
         const uint32_t rel = (uint32_t)(g - c.out_begin);
         const uint32_t t_rel = fastdiv(rel, fk);
         const uint32_t j = rel - t_rel * K;
@@ -124,8 +145,7 @@ struct InDegree {
 // ordinal; the connection belongs to the share of the target's host.
 struct OutDegree {
     static constexpr int R = 1;
-    const TChunk* ch;   // runs of source ordinals (local_first unused)
-    uint32_t nch;
+    ChunkTab ch;        // runs of source ordinals (local_first unused)
     uint32_t K;
     FastDiv fk;
     uint32_t n_t;
@@ -134,7 +154,7 @@ struct OutDegree {
     uint32_t host;
     uint32_t seed, call;
     __device__ __forceinline__ int eval(uint64_t g, Res* r) const {
-        const TChunk c = ch[find_chunk(ch, nch, g)];
+        const TChunk c = ch.at(g);
         const uint32_t rel = (uint32_t)(g - c.out_begin);
         const uint32_t s_rel = fastdiv(rel, fk);
         const uint32_t j = rel - s_rel * K;
@@ -209,8 +229,7 @@ struct Assigned {
 // end inside a block (a block shared by two targets is drawn by both, each
 // keeping its own pairs).  A connection's element index is q.
 struct BernPair {
-    const TChunk* ch;
-    uint32_t nch;
+    ChunkTab ch;
     uint32_t nb;      // items per target
     FastDiv fnb;
     uint32_t n_s;
@@ -227,7 +246,7 @@ struct BernItem {
 
 // the item's target and pair block, without the draw; false past the target's pairs
 __device__ __forceinline__ bool bern_item(const BernPair& r, uint64_t g, BernItem& it, int64_t* self) {
-    const TChunk c = r.ch[find_chunk(r.ch, r.nch, g)];
+    const TChunk c = r.ch.at(g);
     const uint32_t rel = (uint32_t)(g - c.out_begin);
     const uint32_t t_rel = fastdiv(rel, r.fnb);
     const uint32_t k = rel - t_rel * r.nb;
@@ -352,11 +371,10 @@ void launch_bern(Ctx& c, const BernPair& r, const Sink& sink, uint64_t n_items, 
 // an autapse exactly when the target's own source ordinal equals i.
 struct OneToOne {
     static constexpr int R = 1;
-    const TChunk* ch;
-    uint32_t nch;
+    ChunkTab ch;
     uint32_t autapses;
     __device__ __forceinline__ int eval(uint64_t g, Res* r) const {
-        const TChunk c = ch[find_chunk(ch, nch, g)];
+        const TChunk c = ch.at(g);
         const uint32_t rel = (uint32_t)(g - c.out_begin);
         const uint64_t i = c.t_ord + rel;
         if (!autapses && c.self_base >= 0 && (uint64_t)c.self_base + rel == i) return 0;
@@ -564,11 +582,11 @@ uint64_t count_and_write(Ctx& c, const char* name, const Rule& rule, Provider pr
 // Synapse values of a call written unit by unit (K elements per unit, in the
 // order of the unit runs): position p of the call holds element (t_ord + rel)
 // K + j of its run, rel = unit within the run, j = rank within the unit.
-__global__ __launch_bounds__(NT) void k_syn_fill(const TChunk* ch, uint32_t nch, uint32_t K, FastDiv fK,
+__global__ __launch_bounds__(NT) void k_syn_fill(ChunkTab ch, uint32_t K, FastDiv fK,
                                                  uint64_t items, SynD syn, uint32_t seed, uint32_t call,
                                                  uint16_t* delay, float* weight, uint64_t base) {
     for (uint64_t p = (uint64_t)blockIdx.x * NT + threadIdx.x; p < items; p += (uint64_t)gridDim.x * NT) {
-        const TChunk c = ch[find_chunk(ch, nch, p)];
+        const TChunk c = ch.at(p);
         const uint64_t off = p - c.out_begin;
         const uint32_t rel = fastdiv((uint32_t)off, fK);   // a run holds fewer than 2^32 elements
         const uint32_t j = (uint32_t)off - rel * K;
@@ -587,8 +605,7 @@ __global__ __launch_bounds__(NT) void k_syn_fill(const TChunk* ch, uint32_t nch,
 // kept.  Out-degree: unit = source, a value is kept when its target is on
 // `host`.
 struct FloydArgs {
-    const TChunk* ch;
-    uint32_t nch;
+    ChunkTab ch;
     uint64_t n_units;
     uint32_t K, n_set;     // draws per unit, candidate set size
     uint32_t in_degree;
@@ -625,13 +642,8 @@ __global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
     uint8_t* dup1 = dup0 + kp;
     const uint32_t tid = threadIdx.x;
     for (uint64_t u = blockIdx.x; u < a.n_units; u += gridDim.x) {
-        uint32_t lo = 0, hi = a.nch;
         const uint64_t g = u * a.K;
-        while (hi - lo > 1) {
-            const uint32_t m = (lo + hi) >> 1;
-            if (a.ch[m].out_begin <= g) lo = m; else hi = m;
-        }
-        const TChunk c = a.ch[lo];
+        const TChunk c = a.ch.at(g);
         const uint32_t rel = (uint32_t)((g - c.out_begin) / a.K);
         const uint64_t ord = c.t_ord + rel;
         const int64_t self = c.self_base >= 0 ? c.self_base + rel : -1;
@@ -784,13 +796,8 @@ __global__ __launch_bounds__(FNT) void k_floyd_small(FloydArgs a, Sink sink, uin
     __shared__ uint32_t x[FLOYD_SMALL * FNT];
     const uint32_t t = threadIdx.x;
     for (uint64_t u = (uint64_t)blockIdx.x * FNT + t; u < a.n_units; u += (uint64_t)gridDim.x * FNT) {
-        uint32_t lo = 0, hi = a.nch;
         const uint64_t g = u * a.K;
-        while (hi - lo > 1) {
-            const uint32_t m = (lo + hi) >> 1;
-            if (a.ch[m].out_begin <= g) lo = m; else hi = m;
-        }
-        const TChunk c = a.ch[lo];
+        const TChunk c = a.ch.at(g);
         const uint32_t rel = (uint32_t)((g - c.out_begin) / a.K);
         const uint64_t ord = c.t_ord + rel;
         const int64_t self = c.self_base >= 0 ? c.self_base + rel : -1;
@@ -880,7 +887,7 @@ void launch_floyd_direct(Ctx& c, const FloydArgs& a, const WriteSink& ws, uint64
     if (!items) return;
     const uint32_t grid = (uint32_t)std::min<uint64_t>((items + NT - 1) / NT, 1u << 20);
     tstart(c, "gen_floyd");
-    hipLaunchKernelGGL(k_syn_fill, dim3(grid), dim3(NT), 0, c.stream, a.ch, a.nch, a.K, make_fastdiv(a.K), items,
+    hipLaunchKernelGGL(k_syn_fill, dim3(grid), dim3(NT), 0, c.stream, a.ch, a.K, make_fastdiv(a.K), items,
                        ws.syn, ws.seed, ws.call, ws.delay, ws.weight, ws.base);
     tstop(c);
     HIPCHK(hipGetLastError());
@@ -912,13 +919,19 @@ __global__ void k_first_flags(const uint64_t* keys, const uint32_t* vals, uint64
     first[vals[i]] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
 }
 
-// First occurrences by hashing (small candidate windows: fewer launches and no
-// read-back in the middle).  Open addressing over a power-of-two table of at
-// least 1.5 slots per candidate: each candidate claims the slot of its pair
-// (compare-and-swap) and lowers the slot's smallest candidate index; a second
-// pass finds the slot again and flags the candidate that holds the minimum.
-// The result does not depend on the order of the atomics.
+// First occurrences by hashing behind a filter.  Every candidate clears the
+// "unseen" bit of its slot in a bitmap of at least 16 slots per candidate
+// (all bits start at one, so the table and the filter take one fill) and,
+// when that bit was clear already, the slot's "alone" bit.  A candidate alone
+// in its slot draws a pair that no other candidate draws, so it is the first
+// (and only) occurrence of that pair.  The others, about one in 16, resolve
+// exactly in an open-addressing table of at least 1.5 slots per distinct pair
+// they can hold: each claims the slot of its pair (compare-and-swap) and
+// lowers the slot's smallest candidate index; the candidate holding the
+// minimum is the first occurrence.  No result depends on the order of the
+// atomics.
 constexpr uint64_t HASH_EMPTY = ~0ull;
+constexpr uint8_t FIRST_PENDING = 2;   // shares its filter slot: resolved by the table
 
 __device__ __forceinline__ uint64_t pair_hash(uint64_t x) {
     x ^= x >> 33;
@@ -929,55 +942,100 @@ __device__ __forceinline__ uint64_t pair_hash(uint64_t x) {
     return x;
 }
 
-__global__ void k_first_insert(const Total t, uint64_t n, uint32_t n_t, uint64_t* tab, uint32_t* minidx,
-                               uint64_t mask) {
+__device__ __forceinline__ uint64_t total_pair_key(const Total& t, uint64_t i, uint32_t n_t) {
+    const uint4 b = draw(t.seed, t.call, i, PURPOSE_IDX);
+    return (uint64_t)uniform_index(b.x, b.y, t.n_s) * n_t + uniform_index(b.z, b.w, t.n_t);
+}
+
+// filter slot of a pair: two bits (seen, shared) in word slot / 16
+__device__ __forceinline__ uint64_t filter_slot(uint64_t key, uint64_t slot_mask) {
+    return pair_hash(key) & slot_mask;
+}
+
+// table slot of a pair: the other half of the hash, so that pairs sharing a
+// filter slot spread over the table
+__device__ __forceinline__ uint64_t table_slot(uint64_t key, uint64_t mask) {
+    const uint64_t h = pair_hash(key);
+    return ((h >> 32) | (h << 32)) & mask;
+}
+
+__global__ void k_first_filter(const Total t, uint64_t n, uint32_t n_t, uint32_t* bm, uint64_t slot_mask) {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint4 b = draw(t.seed, t.call, i, PURPOSE_IDX);
-    const uint64_t key = (uint64_t)uniform_index(b.x, b.y, t.n_s) * n_t + uniform_index(b.z, b.w, t.n_t);
-    uint64_t h = pair_hash(key) & mask;
-    for (uint64_t probe = 0; probe <= mask; ++probe) {   // the table is never full
-        const uint64_t prev = atomicCAS((unsigned long long*)&tab[h], (unsigned long long)HASH_EMPTY,
+    const uint64_t h = filter_slot(total_pair_key(t, i, n_t), slot_mask);
+    const uint32_t sh = (uint32_t)(h & 15) * 2;
+    const uint32_t old = atomicAnd(&bm[h >> 4], ~(1u << sh));
+    if (!((old >> sh) & 1u)) atomicAnd(&bm[h >> 4], ~(2u << sh));
+}
+
+__global__ void k_first_resolve(const Total t, uint64_t n, uint32_t n_t, const uint32_t* bm, uint64_t slot_mask,
+                                uint64_t* tab, uint32_t* minidx, uint64_t mask, uint8_t* first) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t key = total_pair_key(t, i, n_t);
+    const uint64_t h = filter_slot(key, slot_mask);
+    if ((bm[h >> 4] >> ((uint32_t)(h & 15) * 2 + 1)) & 1u) {   // still alone
+        first[i] = 1;
+        return;
+    }
+    first[i] = FIRST_PENDING;
+    uint64_t s = table_slot(key, mask);
+    for (uint64_t probe = 0; probe <= mask; ++probe) {   // never full: 1.5 slots per possible pair
+        const uint64_t prev = atomicCAS((unsigned long long*)&tab[s], (unsigned long long)HASH_EMPTY,
                                         (unsigned long long)key);
         if (prev == HASH_EMPTY || prev == key) {
-            atomicMin(&minidx[h], (uint32_t)i);
+            atomicMin(&minidx[s], (uint32_t)i);
             return;
         }
-        h = (h + 1) & mask;
+        s = (s + 1) & mask;
     }
 }
 
-__global__ void k_first_mark(const Total t, uint64_t n, uint32_t n_t, const uint64_t* tab, const uint32_t* minidx,
-                             uint64_t mask, uint8_t* first) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint4 b = draw(t.seed, t.call, i, PURPOSE_IDX);
-    const uint64_t key = (uint64_t)uniform_index(b.x, b.y, t.n_s) * n_t + uniform_index(b.z, b.w, t.n_t);
-    uint64_t h = pair_hash(key) & mask;
-    uint8_t f = 0;
-    for (uint64_t probe = 0; probe <= mask; ++probe) {
-        if (tab[h] == key) {
-            f = minidx[h] == (uint32_t)i ? 1 : 0;
-            break;
-        }
-        h = (h + 1) & mask;
+// eight candidates per thread: most flags are settled, one 8-byte read skips them
+__global__ void k_first_pending(const Total t, uint64_t n, uint32_t n_t, const uint64_t* tab, const uint32_t* minidx,
+                                uint64_t mask, uint8_t* first) {
+    const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+    if (i0 >= n) return;
+    uint64_t word = 0;
+    if (i0 + 8 <= n) {
+        word = *reinterpret_cast<const uint64_t*>(first + i0);   // 8-byte aligned: the flags start a device block
+    } else {
+        for (uint64_t i = i0; i < n; ++i) word |= (uint64_t)first[i] << (8 * (i - i0));
     }
-    first[i] = f;
+    // bytes equal to FIRST_PENDING (the flags are 0, 1 or 2: bit 1 set only there)
+    for (uint64_t m = word & 0x0202020202020202ull; m; m &= m - 1) {
+        const uint64_t i = i0 + (uint64_t)(__builtin_ctzll(m) >> 3);
+        const uint64_t key = total_pair_key(t, i, n_t);
+        uint64_t s = table_slot(key, mask);
+        uint8_t f = 0;
+        for (uint64_t probe = 0; probe <= mask; ++probe) {
+            if (tab[s] == key) {
+                f = minidx[s] == (uint32_t)i ? 1 : 0;
+                break;
+            }
+            s = (s + 1) & mask;
+        }
+        first[i] = f;
+    }
 }
 
 struct DeviceChunks {
-    TChunk* d = nullptr;
-    uint32_t n = 0;
+    ChunkTab tab{};
+    TChunk* d = nullptr;   // device copy of a table too long to go inline (owned)
     uint64_t items = 0;
 };
 
 DeviceChunks upload_chunks(Ctx& c, const std::vector<TChunk>& v, uint64_t items) {
     DeviceChunks dc;
-    dc.n = (uint32_t)v.size();
+    dc.tab.n = (uint32_t)v.size();
     dc.items = items;
-    if (v.empty()) return dc;
+    if (v.size() <= CH_INLINE) {
+        std::copy(v.begin(), v.end(), dc.tab.in);
+        return dc;
+    }
     dc.d = dalloc_n<TChunk>(c, v.size());
     upload(c, dc.d, v.data(), v.size() * sizeof(TChunk));
+    dc.tab.d = dc.d;
     return dc;
 }
 
@@ -1109,11 +1167,11 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             DeviceChunks dc = upload_chunks(c, runs, items);
             temps.push_back(dc.d);
             if (cl.multapses) {
-                InDegree r{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)ns, c.seed, cl.id};
+                InDegree r{dc.tab, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)ns, c.seed, cl.id};
                 if (mark) launch_gen<InDegree, MarkSink, MARK>(c, "gen_indegree", r, ms, items, nullptr, nullptr, 0);
                 else launch_gen<InDegree, WriteSink, DIRECT>(c, "gen_indegree", r, *reserve(items), items, nullptr, nullptr, 0);
             } else {
-                FloydArgs a{dc.d, dc.n, items / K, (uint32_t)K, (uint32_t)ns, 1, cl.dT, nT, host,
+                FloydArgs a{dc.tab, items / K, (uint32_t)K, (uint32_t)ns, 1, cl.dT, nT, host,
                             next_pow2((uint32_t)K), c.seed, cl.id};
                 if (mark) launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
                 else launch_floyd_direct(c, a, *reserve(items), items);
@@ -1138,7 +1196,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             DeviceChunks dc = upload_chunks(c, runs, items);
             temps.push_back(dc.d);
             if (cl.multapses) {
-                OutDegree r{dc.d, dc.n, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt, cl.dT, nT, host,
+                OutDegree r{dc.tab, (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt, cl.dT, nT, host,
                             c.seed, cl.id};
                 if (mark) {
                     launch_gen<OutDegree, MarkSink, MARK>(c, "gen_outdegree", r, ms, items, nullptr, nullptr, 0);
@@ -1150,7 +1208,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 }
             } else {
                 const uint64_t units = items / K;
-                FloydArgs a{dc.d, dc.n, units, (uint32_t)K, (uint32_t)nt, 0, cl.dT, nT, host,
+                FloydArgs a{dc.tab, units, (uint32_t)K, (uint32_t)nt, 0, cl.dT, nT, host,
                             next_pow2((uint32_t)K), c.seed, cl.id};
                 if (mark) {
                     launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
@@ -1218,19 +1276,29 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             for (;;) {
                 uint8_t* first = nullptr;
                 if (!cl.multapses && C <= c.total_hash_max) {
+                    // filter: 2 bits per slot, at least 16 slots per candidate
+                    uint64_t m = 1024;
+                    while (m < 16 * C) m <<= 1;
+                    // table: 1.5 slots per pair a pending candidate can hold (at most min(C, pairs))
+                    const uint64_t distinct = std::min<uint64_t>(C, ns * nt);
                     uint64_t H = 1024;
-                    while (H < C + C / 2) H <<= 1;
-                    // keys (HASH_EMPTY) and earliest candidates (none yet) in one block, cleared by one fill
-                    uint64_t* tab = dalloc_n<uint64_t>(c, H + H / 2);
+                    while (H < distinct + distinct / 2) H <<= 1;
+                    // keys (HASH_EMPTY), earliest candidates (none yet) and the filter (unseen, alone) in
+                    // one block, all bits one, cleared by one fill
+                    uint64_t* tab = dalloc_n<uint64_t>(c, H + H / 2 + m / 32);
                     uint32_t* minidx = reinterpret_cast<uint32_t*>(tab + H);
+                    uint32_t* bm = minidx + H;
                     first = dalloc_n<uint8_t>(c, C);
                     temps.insert(temps.end(), {tab, first});
-                    HIPCHK(hipMemsetAsync(tab, 0xff, H * 12, c.stream));
+                    HIPCHK(hipMemsetAsync(tab, 0xff, H * 12 + m / 4, c.stream));
+                    const dim3 grid((unsigned)((C + 255) / 256));
                     tstart(c, "gen_total_first");
-                    hipLaunchKernelGGL(k_first_insert, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream, r, C,
-                                       (uint32_t)nt, tab, minidx, H - 1);
-                    hipLaunchKernelGGL(k_first_mark, dim3((unsigned)((C + 255) / 256)), dim3(256), 0, c.stream, r, C,
-                                       (uint32_t)nt, (const uint64_t*)tab, (const uint32_t*)minidx, H - 1, first);
+                    hipLaunchKernelGGL(k_first_filter, grid, dim3(256), 0, c.stream, r, C, (uint32_t)nt, bm, m - 1);
+                    hipLaunchKernelGGL(k_first_resolve, grid, dim3(256), 0, c.stream, r, C, (uint32_t)nt,
+                                       (const uint32_t*)bm, m - 1, tab, minidx, H - 1, first);
+                    hipLaunchKernelGGL(k_first_pending, dim3((unsigned)((C + 8 * 256 - 1) / (8 * 256))), dim3(256), 0,
+                                       c.stream, r, C, (uint32_t)nt, (const uint64_t*)tab, (const uint32_t*)minidx,
+                                       H - 1, first);
                     tstop(c);
                     HIPCHK(hipGetLastError());
                     dfree(c, tab);
@@ -1357,7 +1425,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             DeviceChunks dc = upload_chunks(c, runs, items);
             temps.push_back(dc.d);
             const uint64_t thr = cl.p >= 1.0 ? (1ull << 32) : (uint64_t)std::floor(cl.p * 4294967296.0);
-            BernPair r{dc.d, dc.n, nb, make_fastdiv(nb), (uint32_t)ns, thr, cl.autapses ? 1u : 0u, c.seed, cl.id};
+            BernPair r{dc.tab, nb, make_fastdiv(nb), (uint32_t)ns, thr, cl.autapses ? 1u : 0u, c.seed, cl.id};
             if (mark) {
                 launch_bern<MarkSink, MARK>(c, r, ms, items, nullptr, nullptr);
                 break;
@@ -1427,7 +1495,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             if (mode == Out::COUNT) break;
             DeviceChunks dc = upload_chunks(c, kept, items);
             temps.push_back(dc.d);
-            OneToOne r{dc.d, dc.n, 1u};   // autapse runs are gone
+            OneToOne r{dc.tab, 1u};   // autapse runs are gone
             if (mark) launch_gen<OneToOne, MarkSink, MARK>(c, "gen_one_to_one", r, ms, items, nullptr, nullptr, 0);
             else launch_gen<OneToOne, WriteSink, DIRECT>(c, "gen_one_to_one", r, *reserve(items), items, nullptr, nullptr, 0);
             break;
@@ -1529,6 +1597,21 @@ __global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs,
 // The call's chunk table is appended to `chunks` (all tables of a batch go to
 // the device in one block); the descriptor's table pointer is set by the
 // caller once that block exists (`*chunk_at` = first entry in `chunks`).
+// A fused call's run table: inline when short, else appended to the batch's
+// table (*chunk_at = its first entry; the device address is set after the
+// batch's one upload).
+ChunkTab batch_tab(const std::vector<TChunk>& runs, std::vector<TChunk>& chunks, size_t* chunk_at) {
+    ChunkTab t{};
+    t.n = (uint32_t)runs.size();
+    if (runs.size() <= CH_INLINE) {
+        std::copy(runs.begin(), runs.end(), t.in);
+    } else {
+        *chunk_at = chunks.size();
+        chunks.insert(chunks.end(), runs.begin(), runs.end());
+    }
+    return t;
+}
+
 bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<TChunk>& chunks, size_t* chunk_at) {
     const uint32_t host = c.P_local;
     const uint32_t nS = (uint32_t)cl.S.seg.size(), nT = (uint32_t)cl.T.seg.size();
@@ -1543,11 +1626,9 @@ bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<TChunk>& chunks, size
         if (!cl.multapses) return false;
         const uint64_t K = cl.n;
         auto runs = unit_runs(cl.T, cl.autapses ? nullptr : &cl.S, host, K, MAX_RUN_ELEMS);
-        *chunk_at = chunks.size();
-        chunks.insert(chunks.end(), runs.begin(), runs.end());
         q.kind = F_INDEGREE;
-        q.ind = InDegree{nullptr, (uint32_t)runs.size(), (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)ns, c.seed,
-                         cl.id};
+        q.ind = InDegree{batch_tab(runs, chunks, chunk_at), (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)ns,
+                         c.seed, cl.id};
         return true;
     }
     case SNNC_FIXED_OUTDEGREE: {
@@ -1557,11 +1638,9 @@ bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<TChunk>& chunks, size
         if (on_host != nt) return false;
         const uint64_t K = cl.n;
         auto runs = unit_runs(cl.S, cl.autapses ? nullptr : &cl.T, -1, K, MAX_RUN_ELEMS);
-        *chunk_at = chunks.size();
-        chunks.insert(chunks.end(), runs.begin(), runs.end());
         q.kind = F_OUTDEGREE;
-        q.outd = OutDegree{nullptr, (uint32_t)runs.size(), (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt, cl.dT,
-                           nT, host, c.seed, cl.id};
+        q.outd = OutDegree{batch_tab(runs, chunks, chunk_at), (uint32_t)K, make_fastdiv((uint32_t)K), (uint32_t)nt,
+                           cl.dT, nT, host, c.seed, cl.id};
         return true;
     }
     case SNNC_FIXED_TOTAL_NUMBER: {
@@ -1585,10 +1664,8 @@ bool fused_desc(Ctx& c, Call& cl, FusedReq& q, std::vector<TChunk>& chunks, size
             kept.push_back(k);
         }
         if (items != cl.gen_count) return false;
-        *chunk_at = chunks.size();
-        chunks.insert(chunks.end(), kept.begin(), kept.end());
         q.kind = F_ONE_TO_ONE;
-        q.o2o = OneToOne{nullptr, (uint32_t)kept.size(), 1u};   // autapse runs are gone
+        q.o2o = OneToOne{batch_tab(kept, chunks, chunk_at), 1u};   // autapse runs are gone
         return true;
     }
     default:
@@ -1670,9 +1747,9 @@ void flush_batch(Ctx& c, const std::vector<uint32_t>& ids, hipEvent_t done) {
             if (chunk_at[k] == SIZE_MAX) continue;
             TChunk* t = dev + chunk_at[k];
             switch (reqs[k].kind) {
-            case F_INDEGREE: reqs[k].ind.ch = t; break;
-            case F_OUTDEGREE: reqs[k].outd.ch = t; break;
-            case F_ONE_TO_ONE: reqs[k].o2o.ch = t; break;
+            case F_INDEGREE: reqs[k].ind.ch.d = t; break;
+            case F_OUTDEGREE: reqs[k].outd.ch.d = t; break;
+            case F_ONE_TO_ONE: reqs[k].o2o.ch.d = t; break;
             default: break;
             }
         }
