@@ -881,10 +881,13 @@ void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_c
 
 // Floyd's sampling written directly (one unit after another): sources and
 // targets by the sampler, then the synapse values by element index.
+bool defer_syn_fill(Ctx& c, const FloydArgs& a, const WriteSink& ws, uint64_t items);
+
 void launch_floyd_direct(Ctx& c, const FloydArgs& a, const WriteSink& ws, uint64_t items) {
     IdSink ids{ws.src, ws.tgt, ws.base};
     launch_floyd<IdSink, DIRECT>(c, a, ids, nullptr, nullptr);
     if (!items) return;
+    if (defer_syn_fill(c, a, ws, items)) return;   // the batch's fused launch writes them
     const uint32_t grid = (uint32_t)std::min<uint64_t>((items + NT - 1) / NT, 1u << 20);
     tstart(c, "gen_floyd");
     hipLaunchKernelGGL(k_syn_fill, dim3(grid), dim3(NT), 0, c.stream, a.ch, a.K, make_fastdiv(a.K), items,
@@ -1540,7 +1543,10 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
 // gives its item range in the batch and its rule parameters; every item finds
 // its call by binary search and is generated exactly as in the per-call
 // kernel, at the position the call was admitted to.
-enum FusedKind : uint32_t { F_INDEGREE = 0, F_TOTAL = 1, F_OUTDEGREE = 2, F_ONE_TO_ONE = 3 };
+// F_SYN_FILL: the synapse values of a Floyd call (its sources and targets
+// written by its own launch), element index from the run table as in
+// k_syn_fill; `ind` holds the run table and K.
+enum FusedKind : uint32_t { F_INDEGREE = 0, F_TOTAL = 1, F_OUTDEGREE = 2, F_ONE_TO_ONE = 3, F_SYN_FILL = 4 };
 
 struct FusedReq {
     uint64_t item_begin;
@@ -1562,6 +1568,23 @@ struct FusedHdr {
     uint32_t seed;
 };
 
+// During a batch flush, a Floyd call whose run table travels inline leaves
+// its synapse values to the batch's fused launch (a descriptor whose
+// item_begin holds the element count until the flush places it).
+bool defer_syn_fill(Ctx& c, const FloydArgs& a, const WriteSink& ws, uint64_t items) {
+    if (!c.gen_defer || a.ch.d) return false;
+    FusedReq q;
+    memset(&q, 0, sizeof q);
+    q.kind = F_SYN_FILL;
+    q.item_begin = items;
+    q.out_base = ws.base;
+    q.call = ws.call;
+    q.syn = ws.syn;
+    q.ind = InDegree{a.ch, a.K, make_fastdiv(a.K), 0u, ws.seed, ws.call};
+    static_cast<std::vector<FusedReq>*>(c.gen_defer)->push_back(q);
+    return true;
+}
+
 __global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs, const FusedHdr* __restrict__ hdr) {
     const FusedHdr h = *hdr;
     for (uint64_t tile = blockIdx.x; tile * TILE < h.total; tile += gridDim.x) {
@@ -1576,6 +1599,18 @@ __global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs,
             }
             const FusedReq* q = reqs + a;
             const uint64_t local = item - q->item_begin;
+            if (q->kind == F_SYN_FILL) {
+                const TChunk ck = q->ind.ch.at(local);
+                const uint64_t off = local - ck.out_begin;
+                const uint32_t rel = fastdiv((uint32_t)off, q->ind.fk);   // a run holds fewer than 2^32 elements
+                const uint32_t j = (uint32_t)off - rel * q->ind.K;
+                float w;
+                uint16_t d;
+                syn_values(q->syn, h.seed, q->call, (ck.t_ord + rel) * (uint64_t)q->ind.K + j, w, d);
+                h.delay[q->out_base + local] = d;
+                h.weight[q->out_base + local] = w;
+                continue;
+            }
             Res r[1];
             int n = 0;
             switch (q->kind) {
@@ -1738,6 +1773,24 @@ void flush_batch(Ctx& c, const std::vector<uint32_t>& ids, hipEvent_t done) {
             rest.push_back(id);
         }
     }
+    // the other calls with their own launches; Floyd calls among them leave
+    // their synapse values to the fused launch below
+    std::vector<FusedReq> deferred;
+    c.gen_defer = &deferred;
+    try {
+        for (uint32_t id : rest) run_call(c, c.calls[id], c.P_local, Out::AT_BASE, nullptr);
+    } catch (...) {
+        c.gen_defer = nullptr;
+        throw;
+    }
+    c.gen_defer = nullptr;
+    for (FusedReq& q : deferred) {
+        const uint64_t items = q.item_begin;
+        q.item_begin = total;
+        total += items;
+        reqs.push_back(q);
+        chunk_at.push_back(SIZE_MAX);
+    }
     if (!chunks.empty()) {
         // the chunk tables of every fused call: one block, one copy (kept until Prepare)
         TChunk* dev = dalloc_n<TChunk>(c, chunks.size());
@@ -1784,7 +1837,6 @@ void flush_batch(Ctx& c, const std::vector<uint32_t>& ids, hipEvent_t done) {
         HIPCHK(hipGraphLaunch(c.fused_exec, c.stream));
         tstop(c);
     }
-    for (uint32_t id : rest) run_call(c, c.calls[id], c.P_local, Out::AT_BASE, nullptr);
     HIPCHK(hipEventRecord(done, c.stream));
 }
 

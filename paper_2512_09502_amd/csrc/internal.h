@@ -191,6 +191,7 @@ struct Ctx {
     // generation store in fixed-size blocks of physical memory mapped behind
     // reserved virtual ranges (when the device supports it; tunable gen_blocks)
     bool gen_vmm = false;
+    void* gen_defer = nullptr;           // during a batch flush: descriptors of work left to the fused launch
     char* gen_va[4] = {nullptr, nullptr, nullptr, nullptr};   // src, tgt, delay, weight
     bool gen_pooled = false;                                   // taken from the device's mapped store
     uint64_t gen_mapped = 0;                                   // connections mapped
