@@ -544,8 +544,9 @@ snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
  * total number without multapses finds each pair's first candidate by
  * hashing for candidate windows up to this size -- a two-bit-per-slot filter
  * of at least 16 slots per candidate settles the candidates alone in their
- * slot, an exact table the rest -- and by sorting the pair keys above it;
- * default 2^32, every window) and "bern_masks" (1, default: the counting pass of
+ * slot, an exact table the rest; 23 - 45 transient bytes per candidate --
+ * and by sorting the pair keys above it (25 bytes per candidate); default
+ * 2^28) and "bern_masks" (1, default: the counting pass of
  * pairwise Bernoulli keeps each item's 4-bit pair mask for the writing pass;
  * 0: the writing pass draws them again) and "gen_blocks" (1, default where
  * the device supports virtual memory management: the generation-order arrays
