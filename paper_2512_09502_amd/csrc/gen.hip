@@ -1585,18 +1585,35 @@ bool defer_syn_fill(Ctx& c, const FloydArgs& a, const WriteSink& ws, uint64_t it
     return true;
 }
 
+// the descriptor holding item g among reqs[lo, hi) (g at or after reqs[lo])
+__device__ __forceinline__ uint32_t find_req(const FusedReq* reqs, uint32_t lo, uint32_t hi, uint64_t g) {
+    while (hi - lo > 1) {
+        const uint32_t m = (lo + hi) >> 1;
+        if (reqs[m].item_begin <= g) lo = m; else hi = m;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs, const FusedHdr* __restrict__ hdr) {
+    __shared__ uint32_t s_range[2];
     const FusedHdr h = *hdr;
     for (uint64_t tile = blockIdx.x; tile * TILE < h.total; tile += gridDim.x) {
+        // the descriptors of the tile's first and last items, found once: the
+        // items' own searches then run over that range only (usually one entry)
+        if (threadIdx.x == 0) {
+            const uint64_t first = tile * TILE, last = min(first + TILE, h.total) - 1;
+            const uint32_t lo = find_req(reqs, 0, (uint32_t)h.n_req, first);
+            s_range[0] = lo;
+            s_range[1] = find_req(reqs, lo, (uint32_t)h.n_req, last) + 1;
+        }
+        __syncthreads();
+        const uint32_t r_lo = s_range[0], r_hi = s_range[1];
+        __syncthreads();   // read before thread 0 writes the next tile's range
 #pragma unroll 1
         for (int it = 0; it < IPT; ++it) {
             const uint64_t item = tile * TILE + (uint64_t)it * NT + threadIdx.x;
             if (item >= h.total) continue;
-            uint32_t a = 0, b = (uint32_t)h.n_req;
-            while (b - a > 1) {
-                const uint32_t m = (a + b) >> 1;
-                if (reqs[m].item_begin <= item) a = m; else b = m;
-            }
+            const uint32_t a = find_req(reqs, r_lo, r_hi, item);
             const FusedReq* q = reqs + a;
             const uint64_t local = item - q->item_begin;
             if (q->kind == F_SYN_FILL) {
