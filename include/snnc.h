@@ -546,7 +546,9 @@ snnc_status snnc_tune(snnc_ctx* ctx, const char* key, int64_t value);
  * of at least 16 slots per candidate settles the candidates alone in their
  * slot, an exact table the rest; 23 - 45 transient bytes per candidate --
  * and by sorting the pair keys above it (25 bytes per candidate); default
- * 2^28) and "bern_masks" (1, default: the counting pass of
+ * 2^28) and "total_small_max" (0 .. 2^15, default 8192: windows up to this
+ * size run the first occurrences, the valid counts and their scan in one
+ * launch of one workgroup instead of six launches) and "bern_masks" (1, default: the counting pass of
  * pairwise Bernoulli keeps each item's 4-bit pair mask for the writing pass;
  * 0: the writing pass draws them again) and "gen_blocks" (1, default where
  * the device supports virtual memory management: the generation-order arrays

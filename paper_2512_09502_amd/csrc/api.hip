@@ -1726,6 +1726,9 @@ snnc_status snnc_tune(snnc_ctx* c, const char* key, int64_t value) {
         } else if (!strcmp(key, "bern_masks")) {
             if (value < 0 || value > 1) raise(SNNC_EINVAL, "bern_masks must be 0 or 1");
             c->bern_masks = value == 1;
+        } else if (!strcmp(key, "total_small_max")) {
+            if (value < 0 || value > (1ll << 15)) raise(SNNC_EINVAL, "total_small_max out of range");
+            c->total_small_max = (uint64_t)value;
         } else if (!strcmp(key, "total_hash_max")) {
             if (value < 0 || value > (1ll << 32)) raise(SNNC_EINVAL, "total_hash_max out of range");
             c->total_hash_max = (uint64_t)value;

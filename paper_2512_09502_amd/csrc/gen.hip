@@ -1022,6 +1022,91 @@ __global__ void k_first_pending(const Total t, uint64_t n, uint32_t n_t, const u
     }
 }
 
+// Small candidate windows: the whole first-occurrence pipeline and the
+// valid counts with their scan in one launch of one workgroup, the phases
+// separated by barriers (fill the table and filter with ones; filter;
+// resolve; settle the pending candidates; valid candidates per tile of TILE
+// and the tiles' exclusive offsets, the total to out[tiles] and *total_out).
+// Every candidate stays with one thread through all phases (candidate
+// i = k FS_NT + thread, and TILE == FS_NT), so its flag is read back by the
+// thread that wrote it; the filter and table words other threads wrote are
+// read with device-scope atomic loads.  Same flags, offsets and total as the
+// filter, resolve, pending, counting and scan launches.
+constexpr uint32_t FS_NT = 1024;
+static_assert(TILE == FS_NT, "one tile per round of the workgroup");
+
+__global__ __launch_bounds__(FS_NT) void k_first_small(Total t, uint64_t n, uint32_t n_t, uint64_t* block,
+                                                       uint64_t words, uint64_t H, uint64_t slot_mask,
+                                                       uint8_t* first, uint64_t* voff, uint64_t* total_out) {
+    __shared__ uint32_t scratch[FS_NT / 64];
+    const uint32_t tid = threadIdx.x;
+    uint64_t* tab = block;
+    uint32_t* minidx = reinterpret_cast<uint32_t*>(block + H);
+    uint32_t* bm = minidx + H;
+    const uint64_t mask = H - 1;
+    for (uint64_t w = tid; w < words; w += FS_NT) block[w] = ~0ull;
+    __syncthreads();
+    for (uint64_t i = tid; i < n; i += FS_NT) {   // filter
+        const uint64_t h = filter_slot(total_pair_key(t, i, n_t), slot_mask);
+        const uint32_t sh = (uint32_t)(h & 15) * 2;
+        const uint32_t old = atomicAnd(&bm[h >> 4], ~(1u << sh));
+        if (!((old >> sh) & 1u)) atomicAnd(&bm[h >> 4], ~(2u << sh));
+    }
+    __syncthreads();
+    for (uint64_t i = tid; i < n; i += FS_NT) {   // resolve
+        const uint64_t key = total_pair_key(t, i, n_t);
+        const uint64_t h = filter_slot(key, slot_mask);
+        const uint32_t word = __hip_atomic_load(&bm[h >> 4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((word >> ((uint32_t)(h & 15) * 2 + 1)) & 1u) {
+            first[i] = 1;
+            continue;
+        }
+        first[i] = FIRST_PENDING;
+        uint64_t s = table_slot(key, mask);
+        for (uint64_t probe = 0; probe <= mask; ++probe) {   // never full: 1.5 slots per possible pair
+            const uint64_t prev = atomicCAS((unsigned long long*)&tab[s], (unsigned long long)HASH_EMPTY,
+                                            (unsigned long long)key);
+            if (prev == HASH_EMPTY || prev == key) {
+                atomicMin(&minidx[s], (uint32_t)i);
+                break;
+            }
+            s = (s + 1) & mask;
+        }
+    }
+    __syncthreads();
+    for (uint64_t i = tid; i < n; i += FS_NT) {   // pending
+        if (first[i] != FIRST_PENDING) continue;
+        const uint64_t key = total_pair_key(t, i, n_t);
+        uint64_t s = table_slot(key, mask);
+        uint8_t f = 0;
+        for (uint64_t probe = 0; probe <= mask; ++probe) {
+            if (__hip_atomic_load(&tab[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == key) {
+                f = __hip_atomic_load(&minidx[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)i ? 1 : 0;
+                break;
+            }
+            s = (s + 1) & mask;
+        }
+        first[i] = f;
+    }
+    Total tv = t;
+    tv.first = first;
+    const uint64_t tiles = (n + TILE - 1) / TILE;
+    uint64_t running = 0;
+    for (uint64_t tile = 0; tile < tiles; ++tile) {   // valid counts and their scan
+        const uint64_t i = tile * TILE + tid;
+        Res r{};
+        const uint32_t v = i < n ? (uint32_t)tv.eval(i, &r) : 0u;
+        uint32_t tot;
+        block_excl_scan<FS_NT, uint32_t>(v, scratch, &tot);
+        if (tid == 0) voff[tile] = running;
+        running += tot;
+    }
+    if (tid == 0) {
+        voff[tiles] = running;
+        *total_out = running;
+    }
+}
+
 struct DeviceChunks {
     ChunkTab tab{};
     TChunk* d = nullptr;   // device copy of a table too long to go inline (owned)
@@ -1278,7 +1363,28 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             }
             for (;;) {
                 uint8_t* first = nullptr;
-                if (!cl.multapses && C <= c.total_hash_max) {
+                const uint64_t tiles = (C + TILE - 1) / TILE;
+                const bool deferred = mode == Out::COUNT && c.defer_slot;
+                uint64_t* voff = nullptr;   // set here when the small-window launch counted and scanned
+                if (!cl.multapses && C <= c.total_small_max && C <= c.total_hash_max) {
+                    uint64_t m = 1024;
+                    while (m < 16 * C) m <<= 1;
+                    const uint64_t distinct = std::min<uint64_t>(C, ns * nt);
+                    uint64_t H = 1024;
+                    while (H < distinct + distinct / 2) H <<= 1;
+                    uint64_t* block = dalloc_n<uint64_t>(c, H + H / 2 + m / 32);
+                    first = dalloc_n<uint8_t>(c, C);
+                    voff = dalloc_n<uint64_t>(c, tiles + 1);
+                    temps.insert(temps.end(), {block, first, voff});
+                    uint64_t* total_out = deferred ? c.defer_slot : c.tot_pin_dev + (c.stream == c.count_stream ? 1 : 0);
+                    tstart(c, "gen_total_first");
+                    hipLaunchKernelGGL(k_first_small, dim3(1), dim3(FS_NT), 0, c.stream, r, C, (uint32_t)nt, block,
+                                       H + H / 2 + m / 32, H, m - 1, first, voff, total_out);
+                    tstop(c);
+                    HIPCHK(hipGetLastError());
+                    dfree(c, block);
+                    temps.erase(std::remove(temps.begin(), temps.end(), (void*)block), temps.end());
+                } else if (!cl.multapses && C <= c.total_hash_max) {
                     // filter: 2 bits per slot, at least 16 slots per candidate
                     uint64_t m = 1024;
                     while (m < 16 * C) m <<= 1;
@@ -1342,17 +1448,19 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 }
                 Total rr = r;
                 rr.first = first;
-                const uint64_t tiles = (C + TILE - 1) / TILE;
                 uint32_t* cnt = dalloc_n<uint32_t>(c, tiles);
                 temps.push_back(cnt);
-                uint64_t* voff = dalloc_n<uint64_t>(c, tiles + 1);
-                temps.push_back(voff);
-                launch_total_dist<WriteSink, CNT_VALID, true>(c, rr, host, ws, C, cnt, nullptr, nullptr, 0);
-                if (mode == Out::COUNT && c.defer_slot) {
+                const bool counted = voff != nullptr;
+                if (!counted) {
+                    voff = dalloc_n<uint64_t>(c, tiles + 1);
+                    temps.push_back(voff);
+                    launch_total_dist<WriteSink, CNT_VALID, true>(c, rr, host, ws, C, cnt, nullptr, nullptr, 0);
+                }
+                if (deferred) {
                     // batched admission: valid candidates of this window (and the kept ones) go to
                     // the caller's mapped words; a window with fewer than N valid candidates is
                     // counted again, without deferral, when the batch is admitted
-                    scan_u32_u64_to(c, cnt, voff, tiles, c.defer_slot);
+                    if (!counted) scan_u32_u64_to(c, cnt, voff, tiles, c.defer_slot);
                     uint64_t* koff = nullptr;
                     if (!all_local) {
                         koff = dalloc_n<uint64_t>(c, tiles + 1);
@@ -1370,7 +1478,13 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                                 temps.end());
                     break;
                 }
-                const uint64_t valid = scan_u32_u64(c, cnt, voff, tiles, true);
+                uint64_t valid;
+                if (counted) {   // the small-window launch wrote the total to the lane's mapped word
+                    sync(c);
+                    valid = *reinterpret_cast<volatile uint64_t*>(c.tot_pin + (c.stream == c.count_stream ? 1 : 0));
+                } else {
+                    valid = scan_u32_u64(c, cnt, voff, tiles, true);
+                }
                 if (valid >= N) {
                     uint64_t kept = N;
                     uint64_t* koff = nullptr;

@@ -270,6 +270,7 @@ struct Ctx {
     bool fuse_batches = true;
     int fused_wgs_per_cu = 8;
     uint32_t floyd_wave_max = 1024;      // Floyd's sampling: one-wave workgroups up to this padded degree
+    uint64_t total_small_max = 8192;      // first occurrences, counts and scan in one workgroup up to this window
     uint64_t total_hash_max = 1ull << 28;  // first occurrences by filtered hashing up to this candidate window, else by sorting
     bool bern_masks = true;              // Bernoulli: the counting pass keeps item masks for the writing pass
     size_t fused_cap = 0;

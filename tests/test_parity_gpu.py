@@ -256,14 +256,17 @@ def test_floyd_workgroup_shapes(rule, k, n_src, n_tgt, aut, wave_max):
     compare_all(s, 0)
 
 
-@pytest.mark.parametrize("hash_max", [0, 1 << 24])
+@pytest.mark.parametrize("tune", [{"total_hash_max": 0}, {"total_small_max": 0}, {"total_small_max": 1 << 15}],
+                         ids=["sorted", "filtered", "one_workgroup"])
 @pytest.mark.parametrize("n,aut,n_src,n_tgt", [(1_100_000, True, 3000, 2500), (150_000, False, 3000, 2500),
                                                (5_000_000, False, 3000, 2500), (990, False, 20, 150),
-                                               (40_000, True, 200, 300)])
-def test_total_number_first_occurrence_paths(n, aut, n_src, n_tgt, hash_max):
-    # first candidates of each pair by sorting the pair keys (hash_max = 0) and by filtered hashing;
-    # the dense cases (most candidates repeat a pair) send most candidates through the exact table
+                                               (40_000, True, 200, 300), (5_000, False, 3000, 2500),
+                                               (20_000, True, 3000, 2500), (1, False, 3000, 2500)])
+def test_total_number_first_occurrence_paths(n, aut, n_src, n_tgt, tune):
+    # first candidates of each pair by sorting the pair keys, by filtered hashing in separate launches,
+    # and (windows up to 2^15 candidates) in one workgroup; the dense cases (most candidates repeat a
+    # pair) send most candidates through the exact table
     conn = {"rule": "fixed_total_number", "n": n, "autapses": aut, "multapses": False}
     s = _one(conn, n_src=n_src, n_tgt=n_tgt)
-    s["tune"] = {"total_hash_max": hash_max}
+    s["tune"] = dict(tune)
     compare_all(s, 0)
