@@ -498,6 +498,31 @@ __global__ __launch_bounds__(NT) void k_total_dist(Total rule, uint32_t host, Si
     uint64_t vrun = 0, krun = 0;
     if constexpr (MODE != CNT_VALID) vrun = valid_off[tile];
     if constexpr (MODE == WRITE_KEEP && !ALL_LOCAL) krun = keep_off[tile];
+    if constexpr (MODE == WRITE_KEEP && ALL_LOCAL) {
+        // every target on the host: a valid candidate's position is its rank;
+        // each thread takes IPT consecutive candidates, one scan per tile
+        const uint64_t first_item = base + (uint64_t)threadIdx.x * IPT;
+        Res rr[IPT];
+        uint32_t vmask = 0, nv = 0;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const uint64_t item = first_item + k;
+            uint32_t th = 0;
+            rr[k] = Res{};
+            const bool v = item < n_items && rule.eval(item, &rr[k], &th) != 0;
+            vmask |= (v ? 1u : 0u) << k;
+            nv += v ? 1u : 0u;
+        }
+        uint32_t tot;
+        uint64_t rank = vrun + block_excl_scan<NT>(nv, scratch, &tot);
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            if (!((vmask >> k) & 1u)) continue;
+            if (rank < limit) sink.put(rank, rr[k]);
+            ++rank;
+        }
+        return;
+    }
     uint32_t counted = 0;
 #pragma unroll 1
     for (int it = 0; it < IPT; ++it) {
