@@ -488,10 +488,22 @@ void launch_gen(Ctx& c, const char* name, const Rule& rule, const Sink& sink, ui
 // is on the host, the position is the rank itself); MARK_KEEP marks them.
 enum DistMode { CNT_VALID = 0, CNT_KEEP = 1, WRITE_KEEP = 2, MARK_KEEP = 3 };
 
+constexpr uint8_t FIRST_PENDING = 2;   // shares its filter slot: resolved from the exact table
+
+// The exact table of the filtered first occurrences, read by the counting
+// pass (CNT_VALID) to settle the candidates still pending (tab null: none).
+struct PendingTab {
+    const uint64_t* tab;
+    const uint32_t* minidx;
+    uint64_t mask;
+    uint8_t* first;
+};
+__device__ uint8_t settle_pending(const Total& t, uint64_t i, const PendingTab& p);
+
 template <class Sink, int MODE, bool ALL_LOCAL>
 __global__ __launch_bounds__(NT) void k_total_dist(Total rule, uint32_t host, Sink sink, uint64_t n_items,
                                                    uint64_t tile0, uint32_t* tile_counts, const uint64_t* valid_off,
-                                                   const uint64_t* keep_off, uint64_t limit) {
+                                                   const uint64_t* keep_off, uint64_t limit, PendingTab pend) {
     __shared__ uint32_t scratch[NT / 64];
     const uint64_t tile = tile0 + blockIdx.x;
     const uint64_t base = tile * TILE;
@@ -527,6 +539,11 @@ __global__ __launch_bounds__(NT) void k_total_dist(Total rule, uint32_t host, Si
 #pragma unroll 1
     for (int it = 0; it < IPT; ++it) {
         const uint64_t item = base + (uint64_t)it * NT + threadIdx.x;
+        if constexpr (MODE == CNT_VALID) {
+            // a candidate sharing its filter slot: settled here, and its flag written back
+            if (pend.tab && item < n_items && pend.first[item] == FIRST_PENDING)
+                pend.first[item] = settle_pending(rule, item, pend);
+        }
         Res r{};
         uint32_t th = 0;
         const uint32_t v = item < n_items ? (uint32_t)rule.eval(item, &r, &th) : 0u;
@@ -561,13 +578,14 @@ __global__ __launch_bounds__(NT) void k_total_dist(Total rule, uint32_t host, Si
 
 template <class Sink, int MODE, bool ALL_LOCAL>
 void launch_total_dist(Ctx& c, const Total& rule, uint32_t host, const Sink& sink, uint64_t n_items,
-                       uint32_t* tile_counts, const uint64_t* valid_off, const uint64_t* keep_off, uint64_t limit) {
+                       uint32_t* tile_counts, const uint64_t* valid_off, const uint64_t* keep_off, uint64_t limit,
+                       const PendingTab& pend = PendingTab{}) {
     const uint64_t tiles = (n_items + TILE - 1) / TILE;
     for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
         const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
         tstart(c, MODE == MARK_KEEP ? "prep_mark" : "gen_total");
         hipLaunchKernelGGL((k_total_dist<Sink, MODE, ALL_LOCAL>), dim3(nb), dim3(NT), 0, c.stream, rule, host, sink,
-                           n_items, t0, tile_counts, valid_off, keep_off, limit);
+                           n_items, t0, tile_counts, valid_off, keep_off, limit, pend);
         tstop(c);
         HIPCHK(hipGetLastError());
     }
@@ -959,7 +977,6 @@ __global__ void k_first_flags(const uint64_t* keys, const uint32_t* vals, uint64
 // minimum is the first occurrence.  No result depends on the order of the
 // atomics.
 constexpr uint64_t HASH_EMPTY = ~0ull;
-constexpr uint8_t FIRST_PENDING = 2;   // shares its filter slot: resolved by the table
 
 __device__ __forceinline__ uint64_t pair_hash(uint64_t x) {
     x ^= x >> 33;
@@ -1019,32 +1036,16 @@ __global__ void k_first_resolve(const Total t, uint64_t n, uint32_t n_t, const u
     }
 }
 
-// eight candidates per thread: most flags are settled, one 8-byte read skips them
-__global__ void k_first_pending(const Total t, uint64_t n, uint32_t n_t, const uint64_t* tab, const uint32_t* minidx,
-                                uint64_t mask, uint8_t* first) {
-    const uint64_t i0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
-    if (i0 >= n) return;
-    uint64_t word = 0;
-    if (i0 + 8 <= n) {
-        word = *reinterpret_cast<const uint64_t*>(first + i0);   // 8-byte aligned: the flags start a device block
-    } else {
-        for (uint64_t i = i0; i < n; ++i) word |= (uint64_t)first[i] << (8 * (i - i0));
+// the first-occurrence flag of pending candidate i: whether it holds the
+// smallest index among the candidates of its pair
+__device__ uint8_t settle_pending(const Total& t, uint64_t i, const PendingTab& p) {
+    const uint64_t key = total_pair_key(t, i, t.n_t);
+    uint64_t s = table_slot(key, p.mask);
+    for (uint64_t probe = 0; probe <= p.mask; ++probe) {
+        if (p.tab[s] == key) return p.minidx[s] == (uint32_t)i ? 1 : 0;
+        s = (s + 1) & p.mask;
     }
-    // bytes equal to FIRST_PENDING (the flags are 0, 1 or 2: bit 1 set only there)
-    for (uint64_t m = word & 0x0202020202020202ull; m; m &= m - 1) {
-        const uint64_t i = i0 + (uint64_t)(__builtin_ctzll(m) >> 3);
-        const uint64_t key = total_pair_key(t, i, n_t);
-        uint64_t s = table_slot(key, mask);
-        uint8_t f = 0;
-        for (uint64_t probe = 0; probe <= mask; ++probe) {
-            if (tab[s] == key) {
-                f = minidx[s] == (uint32_t)i ? 1 : 0;
-                break;
-            }
-            s = (s + 1) & mask;
-        }
-        first[i] = f;
-    }
+    return 0;   // not reached: every pending candidate's pair is in the table
 }
 
 // Small candidate windows: the whole first-occurrence pipeline and the
@@ -1391,6 +1392,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 const uint64_t tiles = (C + TILE - 1) / TILE;
                 const bool deferred = mode == Out::COUNT && c.defer_slot;
                 uint64_t* voff = nullptr;   // set here when the small-window launch counted and scanned
+                PendingTab pend{};          // filtered windows: the exact table, read by the counting pass
                 if (!cl.multapses && C <= c.total_small_max && C <= c.total_hash_max) {
                     uint64_t m = 1024;
                     while (m < 16 * C) m <<= 1;
@@ -1430,14 +1432,11 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                     hipLaunchKernelGGL(k_first_filter, grid, dim3(256), 0, c.stream, r, C, (uint32_t)nt, bm, m - 1);
                     hipLaunchKernelGGL(k_first_resolve, grid, dim3(256), 0, c.stream, r, C, (uint32_t)nt,
                                        (const uint32_t*)bm, m - 1, tab, minidx, H - 1, first);
-                    hipLaunchKernelGGL(k_first_pending, dim3((unsigned)((C + 8 * 256 - 1) / (8 * 256))), dim3(256), 0,
-                                       c.stream, r, C, (uint32_t)nt, (const uint64_t*)tab, (const uint32_t*)minidx,
-                                       H - 1, first);
                     tstop(c);
                     HIPCHK(hipGetLastError());
-                    dfree(c, tab);
-                    temps.resize(temps.size() - 2);
-                    temps.push_back(first);
+                    // the pending candidates are settled by the counting pass below; the block
+                    // is released after it
+                    pend = PendingTab{tab, minidx, H - 1, first};
                 } else if (!cl.multapses) {
                     uint64_t* k0 = dalloc_n<uint64_t>(c, C);
                     uint64_t* k1 = dalloc_n<uint64_t>(c, C);
@@ -1479,7 +1478,13 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 if (!counted) {
                     voff = dalloc_n<uint64_t>(c, tiles + 1);
                     temps.push_back(voff);
-                    launch_total_dist<WriteSink, CNT_VALID, true>(c, rr, host, ws, C, cnt, nullptr, nullptr, 0);
+                    launch_total_dist<WriteSink, CNT_VALID, true>(c, rr, host, ws, C, cnt, nullptr, nullptr, 0, pend);
+                }
+                if (pend.tab) {   // released in stream order, after the counting pass
+                    void* blk = const_cast<uint64_t*>(pend.tab);
+                    dfree(c, blk);
+                    temps.erase(std::remove(temps.begin(), temps.end(), blk), temps.end());
+                    pend = PendingTab{};
                 }
                 if (deferred) {
                     // batched admission: valid candidates of this window (and the kept ones) go to
