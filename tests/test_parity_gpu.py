@@ -270,3 +270,61 @@ def test_total_number_first_occurrence_paths(n, aut, n_src, n_tgt, tune):
     s = _one(conn, n_src=n_src, n_tgt=n_tgt)
     s["tune"] = dict(tune)
     compare_all(s, 0)
+
+
+def _many_segments_script(conn):
+    # node sets of five and six segments from eight populations, sources and targets overlapping:
+    # the calls' run tables are longer than what travels inline with the kernel arguments
+    b = W._Builder(1, seed=91)
+    pops = [b.create(0, n) for n in (700, 300, 500, 900, 200, 600, 400, 800)]
+
+    def seg(p, a, n):
+        return (0, pops[p][1] + a, n)
+    tgt = [seg(0, 200, 400), seg(1, 0, 300), seg(3, 450, 400), seg(4, 0, 200), seg(5, 0, 600), seg(6, 50, 300)]
+    if conn["rule"] == "one_to_one":   # same size as the targets, shifted
+        src = [seg(0, 150, 400), seg(1, 0, 300), seg(3, 400, 400), seg(4, 0, 200), seg(5, 0, 600), seg(7, 0, 300)]
+    else:
+        src = [seg(0, 0, 500), seg(2, 100, 300), seg(3, 0, 900), seg(5, 200, 300), seg(7, 0, 600)]
+    b.connect(src, tgt, conn, SYN_N)
+    b.connect(tgt, src, conn, SYN_N)
+    return b.script("many_segments_" + conn["rule"])
+
+
+MANY_SEGMENT_RULES = [
+    {"rule": "fixed_indegree", "n": 40, "autapses": False, "multapses": False},
+    {"rule": "fixed_indegree", "n": 9, "autapses": False, "multapses": True},
+    {"rule": "fixed_outdegree", "n": 12, "autapses": False, "multapses": False},
+    {"rule": "fixed_outdegree", "n": 7, "autapses": True, "multapses": True},
+    {"rule": "pairwise_bernoulli", "p": 0.05, "autapses": False, "multapses": True},
+    {"rule": "one_to_one", "autapses": False, "multapses": True},
+    {"rule": "fixed_total_number", "n": 30000, "autapses": False, "multapses": False},
+    {"rule": "fixed_total_number", "n": 20000, "autapses": True, "multapses": True},
+]
+
+
+@pytest.mark.parametrize("conn", MANY_SEGMENT_RULES, ids=lambda c: f"{c['rule']}-{c.get('n', c.get('p'))}")
+def test_many_segment_sets(conn):
+    # per call: the run tables go to the device (more runs than travel inline)
+    compare_all(_many_segments_script(conn), 0)
+
+
+@pytest.mark.parametrize("conn", MANY_SEGMENT_RULES, ids=lambda c: f"{c['rule']}-{c.get('n', c.get('p'))}")
+def test_many_segment_sets_batched(conn):
+    # the same calls submitted as one batch: fused descriptors whose run tables are patched to the
+    # batch's one device copy, and Floyd calls that keep their own synapse-value pass
+    import paper_2512_09502_amd as snnc
+    s = _many_segments_script(conn)
+    net = snnc.Network(1, 0, s["seed"], s["dt"])
+    reqs = []
+    for op in s["ops"]:
+        if op[0] == "create":
+            net.create(op[1], op[2])
+        else:
+            reqs.append(op[1:])
+    assert all(status == 0 for status, _ in net.submit_many(reqs))
+    net.flush()
+    net.prepare()
+    ref = oracle.run_script(s, 0)
+    for k in ("src", "tgt", "delay", "weight", "row_ptr"):
+        compare(k, net.array(k), ref.array(k), s["name"] + " batched")
+    net.close()
