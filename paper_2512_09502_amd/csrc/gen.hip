@@ -1059,7 +1059,7 @@ __device__ uint8_t settle_pending(const Total& t, uint64_t i, const PendingTab& 
 // read with device-scope atomic loads.  Same flags, offsets and total as the
 // filter, resolve, pending, counting and scan launches.
 constexpr uint32_t FS_NT = 1024;
-static_assert(TILE == FS_NT, "one tile per round of the workgroup");
+static_assert(TILE == FS_NT, "one tile per iteration of the workgroup");
 
 __global__ __launch_bounds__(FS_NT) void k_first_small(Total t, uint64_t n, uint32_t n_t, uint64_t* block,
                                                        uint64_t words, uint64_t H, uint64_t slot_mask,
