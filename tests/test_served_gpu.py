@@ -108,6 +108,28 @@ def test_batched_equals_per_call_under_budget(fuse):
         compare(k, b[k], ref.array(k), "served")
 
 
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_submit_many_streams_equal_oracle(seed):
+    """Streams with requests up to 3e5 connections (candidate windows on the
+    filtered and the one-workgroup first-occurrence paths, Bernoulli counts
+    over several hundred tiles, Floyd degrees in every workgroup shape),
+    submitted in chunks of 64: admission equals the oracle's and the network
+    equals the oracle's build of the admitted requests."""
+    script = _served_script(n=150, size_max=3e5, seed=seed)
+    budget = 14 * 3_000_000
+    b, rej_b = _build(script, "many64", budget)
+    status, admitted, _ = served_admission(script, budget, workers=2)
+    conn_at = [k for k, op in enumerate(script["ops"]) if op[0] == "connect"]
+    assert [(conn_at[i], st) for i, st in enumerate(status) if st != 0] == rej_b
+    kept = dict(script)
+    keep = {conn_at[i] for i in admitted}
+    kept["ops"] = [op for k, op in enumerate(script["ops"]) if op[0] == "create" or k in keep]
+    ref = oracle.run_script(kept, 0)
+    log(f"served seed {seed}: {len(admitted)} admitted, {b['src'].size} connections, {len(rej_b)} rejected")
+    for k in GEN_ARRAYS + PREP_ARRAYS:
+        compare(k, b[k], ref.array(k), f"served seed {seed}")
+
+
 @pytest.mark.parametrize("chunk", [1, 13, 200])
 def test_submit_many_equals_submit(chunk):
     """Batched submission (one device wait per chunk for the counts) admits
