@@ -1111,6 +1111,17 @@ static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const 
             bool queued = false;
             {
                 CountScope lane(c);
+                // the counts' tile scans are queued and launched together before the wait
+                c.scan_batching = true;
+                struct ScanBatch {
+                    Ctx& c;
+                    ~ScanBatch() {   // on an error: drop the queued scans, release their inputs
+                        c.scan_batching = false;
+                        for (void* p : c.scan_owned) dfree(c, p);
+                        c.scan_jobs.clear();
+                        c.scan_owned.clear();
+                    }
+                } scan_batch{c};
                 uint32_t next = (uint32_t)c.calls.size();
                 uint64_t predicted = c.resident_bytes;
                 for (uint32_t i = start; i < n; ++i) {
@@ -1146,6 +1157,8 @@ static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const 
                         ++next;
                     }
                 }
+                c.scan_batching = false;
+                scan_batch_run(c);
             }
             if (queued) HIPCHK(hipStreamSynchronize(c.count_stream));
             // 3. admission in order, up to the first request whose id moved

@@ -1490,7 +1490,13 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                     // batched admission: valid candidates of this window (and the kept ones) go to
                     // the caller's mapped words; a window with fewer than N valid candidates is
                     // counted again, without deferral, when the batch is admitted
-                    if (!counted) scan_u32_u64_to(c, cnt, voff, tiles, c.defer_slot);
+                    if (!counted && all_local) {   // queued with the batch's scans
+                        temps.erase(std::remove(temps.begin(), temps.end(), (void*)cnt), temps.end());
+                        scan_u32_u64_later(c, cnt, voff, tiles, c.defer_slot);
+                        cnt = nullptr;
+                    } else if (!counted) {
+                        scan_u32_u64_to(c, cnt, voff, tiles, c.defer_slot);
+                    }
                     uint64_t* koff = nullptr;
                     if (!all_local) {
                         koff = dalloc_n<uint64_t>(c, tiles + 1);
@@ -1597,8 +1603,10 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 launch_bern<WriteSink, COUNT>(c, r, ws, items, cnt, nullptr, masks);
                 if (mode == Out::COUNT && c.defer_slot) {
                     // batched admission: the total goes to the caller's mapped word, read after one
-                    // wait for the whole batch; the tile offsets and masks stay with the call
-                    scan_u32_u64_to(c, cnt, off, tiles, c.defer_slot);
+                    // wait for the whole batch (the scan queued with the batch's others); the tile
+                    // offsets and masks stay with the call
+                    temps.erase(std::remove(temps.begin(), temps.end(), (void*)cnt), temps.end());
+                    scan_u32_u64_later(c, cnt, off, tiles, c.defer_slot);
                     release_pre(c, cl);
                     cl.pre_off = off;
                     cl.pre_first = masks;

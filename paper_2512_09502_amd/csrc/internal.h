@@ -148,6 +148,14 @@ struct StageRing {
     bool pending[4] = {};
 };
 
+// One queued exclusive scan of per-tile counts (out[n] and *total_out get the total).
+struct ScanJob {
+    const uint32_t* in;
+    uint64_t* out;
+    uint64_t* total_out;
+    uint64_t n;
+};
+
 struct LaneState {
     hipStream_t stream = nullptr;
     StageRing ring;
@@ -250,6 +258,11 @@ struct Ctx {
     // batched admission: where the counting sections write their totals
     // (null: counts are read back at once); mapped pinned words, two per request
     uint64_t* defer_slot = nullptr;
+    // batched admission: tile-count scans queued by scan_u32_u64_later and
+    // launched together by scan_batch_run (their count arrays owned here until then)
+    bool scan_batching = false;
+    std::vector<ScanJob> scan_jobs;
+    std::vector<void*> scan_owned;
     uint64_t* defer_pin = nullptr;
     uint64_t* defer_pin_dev = nullptr;
     size_t defer_cap = 0;                // requests the pinned words hold
@@ -374,6 +387,12 @@ bool set_lookup_host(const HostSet& s, uint64_t ord, uint32_t& host, uint32_t& l
 uint64_t scan_u32_u64(Ctx& c, const uint32_t* in, uint64_t* out, uint64_t n, bool want_total);
 // the same without a wait: the total is written to total_dev (a mapped host word)
 void scan_u32_u64_to(Ctx& c, const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* total_dev);
+// scan_u32_u64_to, queued while c.scan_batching is set (and n is at most
+// SCAN_BATCH_MAX); takes ownership of `in` (freed once the scan has been enqueued)
+constexpr uint64_t SCAN_BATCH_MAX = 1u << 16;
+void scan_u32_u64_later(Ctx& c, uint32_t* in, uint64_t* out, uint64_t n, uint64_t* total_dev);
+// launches every queued scan in one kernel on the active lane and frees their inputs
+void scan_batch_run(Ctx& c);
 // the same over popcounts of 32-bit words
 uint64_t scan_popc_u64(Ctx& c, const uint32_t* words, uint64_t* out, uint64_t n_words, bool want_total);
 uint64_t scan_u64_u64(Ctx& c, const uint64_t* in, uint64_t* out, uint64_t n, bool want_total);

@@ -131,7 +131,65 @@ uint64_t scan_any(Ctx& c, L load, uint64_t* out, uint64_t n, bool want_total) {
     return *reinterpret_cast<volatile uint64_t*>(c.tot_pin + slot);
 }
 
+// One workgroup per queued scan: chunks of STILE counts in order, the running
+// total carried from chunk to chunk.
+__global__ __launch_bounds__(SNT) void k_multi_scan(const ScanJob* jobs) {
+    __shared__ uint64_t scratch[SNT / 64];
+    const ScanJob j = jobs[blockIdx.x];
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < j.n; base += STILE) {
+        const uint64_t first = base + (uint64_t)threadIdx.x * SIPT;
+        uint64_t v[SIPT];
+        uint64_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < SIPT; ++k) {
+            v[k] = first + k < j.n ? j.in[first + k] : 0;
+            sum += v[k];
+        }
+        uint64_t tot;
+        uint64_t run = carry + block_excl_scan<SNT, uint64_t>(sum, scratch, &tot);
+#pragma unroll
+        for (int k = 0; k < SIPT; ++k) {
+            if (first + k < j.n) j.out[first + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        j.out[j.n] = carry;
+        if (j.total_out) *j.total_out = carry;
+    }
+}
+
 }  // namespace
+
+void scan_u32_u64_later(Ctx& c, uint32_t* in, uint64_t* out, uint64_t n, uint64_t* total_dev) {
+    if (!c.scan_batching || n > SCAN_BATCH_MAX) {
+        scan_u32_u64_to(c, in, out, n, total_dev);
+        dfree(c, in);   // in stream order: only later work reuses it
+        return;
+    }
+    c.scan_jobs.push_back(ScanJob{in, out, total_dev, n});
+    c.scan_owned.push_back(in);
+}
+
+void scan_batch_run(Ctx& c) {
+    if (!c.scan_jobs.empty()) {
+        const size_t bytes = c.scan_jobs.size() * sizeof(ScanJob);
+        ScanJob* dev = static_cast<ScanJob*>(dalloc(c, bytes));
+        upload(c, dev, c.scan_jobs.data(), bytes);
+        tstart(c, "scan");
+        hipLaunchKernelGGL(k_multi_scan, dim3((unsigned)c.scan_jobs.size()), dim3(SNT), 0, c.stream,
+                           (const ScanJob*)dev);
+        tstop(c);
+        const hipError_t e = hipGetLastError();
+        dfree(c, dev);
+        HIPCHK(e);
+    }
+    for (void* p : c.scan_owned) dfree(c, p);
+    c.scan_jobs.clear();
+    c.scan_owned.clear();
+}
 
 uint64_t scan_u32_u64(Ctx& c, const uint32_t* in, uint64_t* out, uint64_t n, bool want_total) {
     return scan_any(c, LoadU32{in}, out, n, want_total);
