@@ -328,3 +328,15 @@ def test_many_segment_sets_batched(conn):
     for k in ("src", "tgt", "delay", "weight", "row_ptr"):
         compare(k, net.array(k), ref.array(k), s["name"] + " batched")
     net.close()
+
+
+def test_first_occurrence_tuning_keys_reject_out_of_range():
+    import paper_2512_09502_amd as snnc
+    net = snnc.Network(1, 0, 1, 0.1)
+    for key, bad in [("total_small_max", (1 << 15) + 1), ("total_small_max", -1), ("total_hash_max", (1 << 32) + 1)]:
+        with pytest.raises(snnc.SnncError) as e:
+            net.tune(key, bad)
+        assert e.value.code == -1
+    net.tune("total_small_max", 0)
+    net.tune("total_hash_max", 1 << 32)
+    net.close()
