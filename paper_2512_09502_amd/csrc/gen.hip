@@ -656,8 +656,78 @@ struct FloydArgs {
     uint32_t nT;
     uint32_t host;
     uint32_t kpad;         // power of two >= K
+    uint32_t kshift;       // log2(kpad): step bits of a 32-bit sort key
     uint32_t seed, call;
 };
+
+// Bitonic sort of kp = NT * E keys by a workgroup of NT threads, E keys
+// per thread in registers (element tid * E + e in r[e]).  Strides below E
+// compare registers of the thread, strides below 64 * E exchange register e
+// with lane lane ^ (stride / E) of the same wave, and larger strides (several
+// waves) go through LDS.  The keys come from and go back to `key`; the caller
+// synchronises before and after.
+constexpr uint32_t FLOYD_REG_E = 16;   // at most 16 keys per thread in registers
+
+template <int NT, int E, class KeyT>
+__device__ __forceinline__ void reg_bitonic_sort(KeyT* key, uint32_t kp) {
+    constexpr uint32_t W = 64u * E;    // keys of one wave
+    const uint32_t tid = threadIdx.x;
+    const uint32_t base = tid * E;
+    KeyT r[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) r[e] = key[base + e];
+    for (uint32_t size = 2; size <= kp; size <<= 1) {
+        uint32_t stride = size >> 1;
+        if constexpr (NT > 64) {
+            if (stride >= W) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) key[base + e] = r[e];
+                __syncthreads();
+                for (; stride >= W; stride >>= 1) {
+                    for (uint32_t i = tid; i < kp / 2; i += NT) {
+                        const uint32_t lo_i = 2 * i - (i & (stride - 1));
+                        const uint32_t hi_i = lo_i + stride;
+                        const bool up = ((lo_i & size) == 0);
+                        const KeyT x = key[lo_i], y = key[hi_i];
+                        if ((x > y) == up) {
+                            key[lo_i] = y;
+                            key[hi_i] = x;
+                        }
+                    }
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int e = 0; e < E; ++e) r[e] = key[base + e];
+            }
+        }
+        for (; stride >= (uint32_t)E; stride >>= 1) {
+            const int m = (int)(stride / E);
+            const bool take_min = ((tid & (uint32_t)m) == 0) == ((base & size) == 0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const KeyT y = __shfl_xor(r[e], m, 64);
+                r[e] = take_min ? (y < r[e] ? y : r[e]) : (y < r[e] ? r[e] : y);
+            }
+        }
+#pragma unroll
+        for (int S = E / 2; S >= 1; S >>= 1) {
+            if ((uint32_t)S < size) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if ((e & S) == 0) {
+                        const bool up = ((base + (uint32_t)e) & size) == 0;
+                        const KeyT x = r[e], y = r[e + S];
+                        const KeyT lo = x < y ? x : y, hi = x < y ? y : x;
+                        r[e] = up ? lo : hi;
+                        r[e + S] = up ? hi : lo;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) key[base + e] = r[e];
+}
 
 // Floyd's sampling without the sequential loop.  Step j draws r_j in
 // [0, m_j], m_j = n - K + j, and takes m_j instead exactly when r_j is already
@@ -668,16 +738,23 @@ struct FloydArgs {
 // steps and are resolved by pointer jumping.  The chosen values -- the same
 // set as inserting one by one -- are then listed in ascending order from the
 // one sort of the draws and flags over the top window.  K <= 8192, so a step
-// index fits 13 bits of the sort key.
+// index fits 13 bits of the sort key.  The sort runs in registers where the
+// padded degree gives each thread 1 to 16 keys (8 for the larger workgroups),
+// in LDS otherwise.
 // NT threads per unit: one wave (64) for padded degrees up to the context's
 // floyd_wave_max, where the barriers of a one-wave workgroup cost next to
 // nothing and many units share a compute unit; 256 up to 2048; 1024 above,
 // where the LDS of a unit leaves room for one or two units per compute unit.
-template <int NT, class Sink, int MODE>
+// KeyT: the sort keys (value << SH | step) in 64 bits with SH = 13, or in 32
+// bits with SH = log2(kpad) when every value is below 2^(32 - SH) (half the
+// LDS bytes of the sort, and a smaller footprint per unit).
+template <int NT, class Sink, int MODE, class KeyT>
 __global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const uint32_t kp = a.kpad;
-    uint64_t* key = reinterpret_cast<uint64_t*>(lds_raw);          // (value << 13 | step), later the chosen values
+    const uint32_t SH = sizeof(KeyT) == 8 ? 13u : a.kshift;
+    const KeyT SM = (KeyT)((1u << SH) - 1u);
+    KeyT* key = reinterpret_cast<KeyT*>(lds_raw);                   // (value << SH | step), later the chosen values
     uint32_t* rv = reinterpret_cast<uint32_t*>(key + kp);           // draw of step j
     uint16_t* par0 = reinterpret_cast<uint16_t*>(rv + kp);
     uint16_t* par1 = par0 + kp;
@@ -698,39 +775,52 @@ __global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
                 const uint4 b = draw(a.seed, a.call, e0 + j, PURPOSE_IDX);
                 const uint32_t r = uniform_index(b.x, b.y, base_m + j + 1);
                 rv[j] = r;
-                key[j] = ((uint64_t)r << 13) | j;
+                key[j] = ((KeyT)r << SH) | (KeyT)j;
             } else {
-                key[j] = ~0ull;
+                key[j] = (KeyT)~(KeyT)0;
             }
         }
         __syncthreads();
-        for (uint32_t size = 2; size <= kp; size <<= 1) {      // bitonic sort of (value, step)
-            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t i = tid; i < kp / 2; i += NT) {
-                    const uint32_t lo_i = 2 * i - (i & (stride - 1));
-                    const uint32_t hi_i = lo_i + stride;
-                    const bool up = ((lo_i & size) == 0);
-                    const uint64_t x = key[lo_i], y = key[hi_i];
-                    if ((x > y) == up) {
-                        key[lo_i] = y;
-                        key[hi_i] = x;
+        bool sorted = false;
+        // keys per thread in registers: up to 16 for one wave, 8 for the
+        // larger workgroups (whose padded degrees stop at 8 per thread)
+        constexpr uint32_t EMAX = NT == 64 ? FLOYD_REG_E : FLOYD_REG_E / 2;
+        if (kp >= NT && kp <= NT * EMAX) {
+            switch (kp / NT) {
+            case 1: reg_bitonic_sort<NT, 1, KeyT>(key, kp); break;
+            case 2: reg_bitonic_sort<NT, 2, KeyT>(key, kp); break;
+            case 4: reg_bitonic_sort<NT, 4, KeyT>(key, kp); break;
+            case 8: reg_bitonic_sort<NT, 8, KeyT>(key, kp); break;
+            default:
+                if constexpr (EMAX == 16) reg_bitonic_sort<NT, 16, KeyT>(key, kp);
+                break;
+            }
+            __syncthreads();
+            sorted = true;
+        }
+        if (!sorted) {
+            for (uint32_t size = 2; size <= kp; size <<= 1) {  // bitonic sort of (value, step) in LDS
+                for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                    for (uint32_t i = tid; i < kp / 2; i += NT) {
+                        const uint32_t lo_i = 2 * i - (i & (stride - 1));
+                        const uint32_t hi_i = lo_i + stride;
+                        const bool up = ((lo_i & size) == 0);
+                        const KeyT x = key[lo_i], y = key[hi_i];
+                        if ((x > y) == up) {
+                            key[lo_i] = y;
+                            key[hi_i] = x;
+                        }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
         }
-        // A_j: an earlier step drew the same value (first occurrence by binary search)
+        // A_j: an earlier step drew the same value.  Equal values sort by
+        // step, so exactly the first key of each run of equal values has none.
         for (uint32_t p = tid; p < a.K; p += NT) {
-            const uint64_t k = key[p];
-            const uint32_t j = (uint32_t)(k & 0x1fffu);
-            const uint64_t v0 = (k >> 13) << 13;
-            uint32_t l = 0, h = p;                              // first position with value == v
-            while (l < h) {
-                const uint32_t m = (l + h) >> 1;
-                if (key[m] < v0) l = m + 1; else h = m;
-            }
-            const uint32_t first = (uint32_t)(key[l] & 0x1fffu);
-            dup0[j] = first < j ? 1 : 0;
+            const KeyT k = key[p];
+            const uint32_t j = (uint32_t)(k & SM);
+            dup0[j] = (p > 0 && (key[p - 1] >> SH) == (k >> SH)) ? 1 : 0;
             const uint32_t r = rv[j];
             par0[j] = (uint16_t)(r >= base_m ? r - base_m : j);   // link to the step whose fallback is r
         }
@@ -768,8 +858,8 @@ __global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
         const uint32_t per = (a.K + NT - 1) / NT;
         const uint32_t q0 = min(tid * per, a.K), q1 = min(q0 + per, a.K);
         auto low_start = [&](uint32_t q) {
-            const uint64_t v = key[q] >> 13;
-            return v < base_m && (q == 0 || (key[q - 1] >> 13) != v);
+            const uint64_t v = (uint64_t)(key[q] >> SH);
+            return v < base_m && (q == 0 || (uint64_t)(key[q - 1] >> SH) != v);
         };
         uint32_t n_low = 0, n_high = 0;
         for (uint32_t q = q0; q < q1; ++q) {
@@ -780,7 +870,7 @@ __global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
         uint32_t at_low = block_excl_scan<NT>(n_low, wsum, &tot_low);
         uint32_t at_high = tot_low + block_excl_scan<NT>(n_high, wsum, &tot_high);
         for (uint32_t q = q0; q < q1; ++q) {
-            if (low_start(q)) vals[at_low++] = (uint32_t)(key[q] >> 13);
+            if (low_start(q)) vals[at_low++] = (uint32_t)(key[q] >> SH);
             if (db[q]) vals[at_high++] = base_m + q;
         }
         __syncthreads();
@@ -889,6 +979,29 @@ __global__ __launch_bounds__(FNT) void k_floyd_small(FloydArgs a, Sink sink, uin
     }
 }
 
+template <class Sink, int MODE, class KeyT>
+void launch_floyd_keys(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_counts,
+                       const uint64_t* unit_offsets) {
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(a.n_units, 65536);
+    const size_t shmem = (size_t)a.kpad * (sizeof(KeyT) + 4 + 2 * 2 + 2 * 1);
+    tstart(c, MODE == MARK ? "prep_mark" : "gen_floyd");
+    if (a.kpad <= c.floyd_wave_max) {
+        hipLaunchKernelGGL((k_floyd<64, Sink, MODE, KeyT>), dim3(grid), dim3(64), shmem, c.stream, a, sink,
+                           unit_counts, unit_offsets);
+    } else if (a.kpad <= 2048) {
+        hipLaunchKernelGGL((k_floyd<256, Sink, MODE, KeyT>), dim3(grid), dim3(256), shmem, c.stream, a, sink,
+                           unit_counts, unit_offsets);
+    } else {
+        // 57 .. 147 KB of LDS leave room for one or two units per compute unit: 16 waves each
+        HIPCHK(hipFuncSetAttribute((const void*)k_floyd<1024, Sink, MODE, KeyT>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+        hipLaunchKernelGGL((k_floyd<1024, Sink, MODE, KeyT>), dim3(grid), dim3(1024), shmem, c.stream, a, sink,
+                           unit_counts, unit_offsets);
+    }
+    tstop(c);
+    HIPCHK(hipGetLastError());
+}
+
 template <class Sink, int MODE>
 void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_counts, const uint64_t* unit_offsets) {
     if (!a.n_units) return;
@@ -903,23 +1016,9 @@ void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_c
     }
     const uint32_t grid = (uint32_t)std::min<uint64_t>(a.n_units, 65536);
     if (a.kpad > 8192) raise(SNNC_EUNSUPPORTED, "degree above 8192 without multapses");
-    const size_t shmem = (size_t)a.kpad * (8 + 4 + 2 * 2 + 2 * 1);
-    tstart(c, MODE == MARK ? "prep_mark" : "gen_floyd");
-    if (a.kpad <= c.floyd_wave_max) {
-        hipLaunchKernelGGL((k_floyd<64, Sink, MODE>), dim3(grid), dim3(64), shmem, c.stream, a, sink, unit_counts,
-                           unit_offsets);
-    } else if (a.kpad <= 2048) {
-        hipLaunchKernelGGL((k_floyd<256, Sink, MODE>), dim3(grid), dim3(256), shmem, c.stream, a, sink, unit_counts,
-                           unit_offsets);
-    } else {
-        // 74 .. 147 KB of LDS leave room for one or two units per compute unit: 16 waves each
-        HIPCHK(hipFuncSetAttribute((const void*)k_floyd<1024, Sink, MODE>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-        hipLaunchKernelGGL((k_floyd<1024, Sink, MODE>), dim3(grid), dim3(1024), shmem, c.stream, a, sink, unit_counts,
-                           unit_offsets);
-    }
-    tstop(c);
-    HIPCHK(hipGetLastError());
+    // 32-bit sort keys when (value << log2(kpad) | step) stays below 2^32
+    if (((uint64_t)a.n_set << a.kshift) < (1ull << 32)) launch_floyd_keys<Sink, MODE, uint32_t>(c, a, sink, unit_counts, unit_offsets);
+    else launch_floyd_keys<Sink, MODE, uint64_t>(c, a, sink, unit_counts, unit_offsets);
 }
 
 // Floyd's sampling written directly (one unit after another): sources and
@@ -943,6 +1042,12 @@ uint32_t next_pow2(uint32_t x) {
     uint32_t p = 1;
     while (p < x) p <<= 1;
     return p;
+}
+
+uint32_t log2_pow2(uint32_t p) {
+    uint32_t l = 0;
+    while ((1u << l) < p) ++l;
+    return l;
 }
 
 // ------------------------------------------------------------------ total number, restricted
@@ -1286,7 +1391,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                 else launch_gen<InDegree, WriteSink, DIRECT>(c, "gen_indegree", r, *reserve(items), items, nullptr, nullptr, 0);
             } else {
                 FloydArgs a{dc.tab, items / K, (uint32_t)K, (uint32_t)ns, 1, cl.dT, nT, host,
-                            next_pow2((uint32_t)K), c.seed, cl.id};
+                            next_pow2((uint32_t)K), log2_pow2(next_pow2((uint32_t)K)), c.seed, cl.id};
                 if (mark) launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
                 else launch_floyd_direct(c, a, *reserve(items), items);
             }
@@ -1323,7 +1428,7 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
             } else {
                 const uint64_t units = items / K;
                 FloydArgs a{dc.tab, units, (uint32_t)K, (uint32_t)nt, 0, cl.dT, nT, host,
-                            next_pow2((uint32_t)K), c.seed, cl.id};
+                            next_pow2((uint32_t)K), log2_pow2(next_pow2((uint32_t)K)), c.seed, cl.id};
                 if (mark) {
                     launch_floyd<MarkSink, MARK>(c, a, ms, nullptr, nullptr);
                 } else if (all_local) {

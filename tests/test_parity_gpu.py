@@ -241,15 +241,35 @@ def test_edge_cases():
     compare_all(b.script("empty"), 0)
 
 
-@pytest.mark.parametrize("wave_max", [0, 8192])
+@pytest.mark.parametrize("wave_max", [0, 1024, 8192])
 @pytest.mark.parametrize("rule,k,n_src,n_tgt,aut", [
     ("fixed_indegree", 37, 500, 300, False),
+    ("fixed_indegree", 100, 400, 300, True),
+    ("fixed_indegree", 200, 600, 200, False),
     ("fixed_indegree", 1000, 1200, 200, True),
     ("fixed_indegree", 2990, 3000, 100, False),
     ("fixed_outdegree", 300, 100, 900, False),
+    ("fixed_outdegree", 1500, 50, 2000, True),
 ])
 def test_floyd_workgroup_shapes(rule, k, n_src, n_tgt, aut, wave_max):
-    # one-wave and 256-thread workgroups of the parallel Floyd sampler give the oracle's sets
+    # one-wave, 256- and 1024-thread workgroups of the parallel Floyd sampler give the oracle's
+    # sets: padded degrees of 1 to 16 keys per thread sorted in registers, the rest in LDS
+    conn = {"rule": rule, "n": k, "autapses": aut, "multapses": False}
+    s = _one(conn, n_src=n_src, n_tgt=n_tgt)
+    s["tune"] = {"floyd_wave_max": wave_max}
+    compare_all(s, 0)
+
+
+@pytest.mark.parametrize("wave_max", [0, 8192])
+@pytest.mark.parametrize("rule,k,n_src,n_tgt,aut", [
+    ("fixed_indegree", 5000, 524_287, 8, False),        # (value << 13 | step) just fits 32 bits
+    ("fixed_indegree", 5000, 524_288, 8, True),         # one more candidate: 64-bit keys
+    ("fixed_indegree", 2100, 1_048_577, 6, False),      # padded degree 4096, 64-bit keys
+    ("fixed_outdegree", 4100, 6, 524_388, False),       # 524,288 targets: 64-bit keys
+])
+def test_floyd_sort_key_widths(rule, k, n_src, n_tgt, aut, wave_max):
+    # the workgroup sampler sorts 32-bit keys while the candidate set times the padded degree
+    # stays below 2^32, 64-bit keys beyond; both widths give the oracle's sets
     conn = {"rule": rule, "n": k, "autapses": aut, "multapses": False}
     s = _one(conn, n_src=n_src, n_tgt=n_tgt)
     s["tune"] = {"floyd_wave_max": wave_max}
