@@ -1851,12 +1851,41 @@ __device__ __forceinline__ uint32_t find_req(const FusedReq* reqs, uint32_t lo, 
     return lo;
 }
 
+// one item of the fused launch, generated by its call's descriptor q
+__device__ __forceinline__ void fused_item(const FusedReq* __restrict__ q, const FusedHdr& h, uint64_t item) {
+    const uint64_t local = item - q->item_begin;
+    if (q->kind == F_SYN_FILL) {
+        const TChunk ck = q->ind.ch.at(local);
+        const uint64_t off = local - ck.out_begin;
+        const uint32_t rel = fastdiv((uint32_t)off, q->ind.fk);   // a run holds fewer than 2^32 elements
+        const uint32_t j = (uint32_t)off - rel * q->ind.K;
+        float w;
+        uint16_t d;
+        syn_values(q->syn, h.seed, q->call, (ck.t_ord + rel) * (uint64_t)q->ind.K + j, w, d);
+        h.delay[q->out_base + local] = d;
+        h.weight[q->out_base + local] = w;
+        return;
+    }
+    Res r[1];
+    int n = 0;
+    switch (q->kind) {
+    case F_INDEGREE: n = q->ind.eval(local, r); break;
+    case F_TOTAL: n = q->tot.eval(local, r); break;
+    case F_OUTDEGREE: n = q->outd.eval(local, r); break;
+    default: n = q->o2o.eval(local, r); break;
+    }
+    if (n) {
+        const WriteSink ws{h.src, h.tgt, h.delay, h.weight, q->out_base, q->syn, h.seed, q->call};
+        ws.put(local, r[0]);
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs, const FusedHdr* __restrict__ hdr) {
     __shared__ uint32_t s_range[2];
     const FusedHdr h = *hdr;
     for (uint64_t tile = blockIdx.x; tile * TILE < h.total; tile += gridDim.x) {
         // the descriptors of the tile's first and last items, found once: the
-        // items' own searches then run over that range only (usually one entry)
+        // items' own searches then run over that range only
         if (threadIdx.x == 0) {
             const uint64_t first = tile * TILE, last = min(first + TILE, h.total) - 1;
             const uint32_t lo = find_req(reqs, 0, (uint32_t)h.n_req, first);
@@ -1864,38 +1893,23 @@ __global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs,
             s_range[1] = find_req(reqs, lo, (uint32_t)h.n_req, last) + 1;
         }
         __syncthreads();
-        const uint32_t r_lo = s_range[0], r_hi = s_range[1];
+        const uint32_t r_lo = __builtin_amdgcn_readfirstlane(s_range[0]);
+        const uint32_t r_hi = __builtin_amdgcn_readfirstlane(s_range[1]);
         __syncthreads();   // read before thread 0 writes the next tile's range
+        if (r_hi - r_lo == 1) {
+            // the usual case, one call for the whole tile: its descriptor is
+            // the same for every lane (scalar loads, uniform branches)
+            const FusedReq* q = reqs + r_lo;
 #pragma unroll 1
-        for (int it = 0; it < IPT; ++it) {
-            const uint64_t item = tile * TILE + (uint64_t)it * NT + threadIdx.x;
-            if (item >= h.total) continue;
-            const uint32_t a = find_req(reqs, r_lo, r_hi, item);
-            const FusedReq* q = reqs + a;
-            const uint64_t local = item - q->item_begin;
-            if (q->kind == F_SYN_FILL) {
-                const TChunk ck = q->ind.ch.at(local);
-                const uint64_t off = local - ck.out_begin;
-                const uint32_t rel = fastdiv((uint32_t)off, q->ind.fk);   // a run holds fewer than 2^32 elements
-                const uint32_t j = (uint32_t)off - rel * q->ind.K;
-                float w;
-                uint16_t d;
-                syn_values(q->syn, h.seed, q->call, (ck.t_ord + rel) * (uint64_t)q->ind.K + j, w, d);
-                h.delay[q->out_base + local] = d;
-                h.weight[q->out_base + local] = w;
-                continue;
+            for (int it = 0; it < IPT; ++it) {
+                const uint64_t item = tile * TILE + (uint64_t)it * NT + threadIdx.x;
+                if (item < h.total) fused_item(q, h, item);
             }
-            Res r[1];
-            int n = 0;
-            switch (q->kind) {
-            case F_INDEGREE: n = q->ind.eval(local, r); break;
-            case F_TOTAL: n = q->tot.eval(local, r); break;
-            case F_OUTDEGREE: n = q->outd.eval(local, r); break;
-            default: n = q->o2o.eval(local, r); break;
-            }
-            if (n) {
-                const WriteSink ws{h.src, h.tgt, h.delay, h.weight, q->out_base, q->syn, h.seed, q->call};
-                ws.put(local, r[0]);
+        } else {
+#pragma unroll 1
+            for (int it = 0; it < IPT; ++it) {
+                const uint64_t item = tile * TILE + (uint64_t)it * NT + threadIdx.x;
+                if (item < h.total) fused_item(reqs + find_req(reqs, r_lo, r_hi, item), h, item);
             }
         }
     }
