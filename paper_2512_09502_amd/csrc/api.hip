@@ -1409,6 +1409,8 @@ snnc_status snnc_init(snnc_ctx** out, uint32_t P, uint32_t P_local, uint32_t see
     c->M.assign(P, 0);
     snnc_status st = guarded(nullptr, [&] {
         HIPCHK(hipGetDevice(&c->device));
+        (void)hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device);
+        if (c->n_cu < 1) c->n_cu = 256;
         HIPCHK(hipEventCreate(&c->phase_a));
         HIPCHK(hipEventCreate(&c->phase_b));
         HIPCHK(hipEventCreate(&c->conn_first));

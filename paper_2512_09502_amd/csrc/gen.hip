@@ -18,6 +18,7 @@ constexpr int NT = 256;          // threads per workgroup
 constexpr int IPT = 4;           // items per thread
 constexpr uint64_t TILE = NT * IPT;
 constexpr uint64_t MAX_TILES_PER_LAUNCH = 1u << 22;
+constexpr uint32_t BERN_WGS_PER_CU = 16;   // grid cap of the Bernoulli counting and marking passes
 
 enum Mode { DIRECT = 0, COUNT = 1, WRITE = 2, MARK = 3 };
 
@@ -242,37 +243,64 @@ struct BernItem {
     uint64_t q0;      // first pair of the target
     uint64_t blk;     // Philox block of this item
     uint32_t tgt;     // target local id
+    uint32_t k;       // the item's index among its target's nb items
+    int64_t self;     // the target's own source ordinal, or -1
 };
 
-// the item's target and pair block, without the draw; false past the target's pairs
-__device__ __forceinline__ bool bern_item(const BernPair& r, uint64_t g, BernItem& it, int64_t* self) {
-    const TChunk c = r.ch.at(g);
-    const uint32_t rel = (uint32_t)(g - c.out_begin);
-    const uint32_t t_rel = fastdiv(rel, r.fnb);
-    const uint32_t k = rel - t_rel * r.nb;
-    it.q0 = (c.t_ord + t_rel) * (uint64_t)r.n_s;
-    it.blk = (it.q0 >> 2) + k;
-    it.tgt = c.local_first + t_rel;
-    *self = c.self_base >= 0 ? c.self_base + t_rel : -1;
+// whether the item's block still holds pairs of its target
+__device__ __forceinline__ bool bern_valid(const BernPair& r, const BernItem& it) {
     return it.blk * 4 < it.q0 + r.n_s;
 }
 
-// bit i set = pair 4 blk + i connects (inside the target's range, autapse rule applied)
-__device__ __forceinline__ uint32_t bern_mask(const BernPair& r, uint64_t g, BernItem& it) {
-    int64_t self;
-    if (!bern_item(r, g, it, &self)) return 0;
-    const uint64_t q1 = it.q0 + r.n_s;
+// the item's target and pair block, without the draw; false past the target's pairs
+__device__ __forceinline__ bool bern_item(const BernPair& r, uint64_t g, BernItem& it) {
+    const TChunk c = r.ch.at(g);
+    const uint32_t rel = (uint32_t)(g - c.out_begin);
+    const uint32_t t_rel = fastdiv(rel, r.fnb);
+    it.k = rel - t_rel * r.nb;
+    it.q0 = (c.t_ord + t_rel) * (uint64_t)r.n_s;
+    it.blk = (it.q0 >> 2) + it.k;
+    it.tgt = c.local_first + t_rel;
+    it.self = c.self_base >= 0 ? c.self_base + t_rel : -1;
+    return bern_valid(r, it);
+}
+
+// the item after `it` (item g): the next block of the same target while the
+// target has items left (runs hold whole targets), else decoded afresh
+__device__ __forceinline__ bool bern_next(const BernPair& r, uint64_t g, BernItem& it) {
+    if (it.k + 1 < r.nb) {
+        ++it.k;
+        ++it.blk;
+        return bern_valid(r, it);
+    }
+    return bern_item(r, g, it);
+}
+
+// bit i set = pair 4 blk + i connects (inside the target's range, autapse
+// rule applied).  The block's pairs sit at positions d0 .. d1 - 1 of the
+// target's range (d0 = q0 - 4 blk), so the range and the autapse become two
+// shifts of the 4-bit mask.
+__device__ __forceinline__ uint32_t bern_draw_mask(const BernPair& r, const BernItem& it) {
     const uint4 b = draw(r.seed, r.call, it.blk, PURPOSE_BERN);
-    const uint32_t w[4] = {b.x, b.y, b.z, b.w};
-    uint32_t mask = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint64_t q = it.blk * 4 + i;
-        if (q < it.q0 || q >= q1 || (uint64_t)w[i] >= r.thr) continue;
-        if (!r.autapses && (int64_t)(q - it.q0) == self) continue;
-        mask |= 1u << i;
+    uint32_t mask = 15u;                                   // p = 1: every pair
+    if (!(r.thr >> 32)) {
+        const uint32_t t = (uint32_t)r.thr;
+        mask = (b.x < t ? 1u : 0u) | (b.y < t ? 2u : 0u) | (b.z < t ? 4u : 0u) | (b.w < t ? 8u : 0u);
+    }
+    const int64_t d0 = (int64_t)(it.q0 - it.blk * 4);
+    const int64_t d1 = d0 + r.n_s;
+    if (d0 > 0) mask &= d0 >= 4 ? 0u : (15u << d0) & 15u;
+    if (d1 < 4) mask &= d1 <= 0 ? 0u : (1u << d1) - 1u;
+    if (!r.autapses && it.self >= 0) {
+        const int64_t si = it.self + d0;                   // position of the pair (target, target)
+        if (si >= 0 && si < 4) mask &= ~(1u << si);
     }
     return mask;
+}
+
+__device__ __forceinline__ uint32_t bern_mask(const BernPair& r, uint64_t g, BernItem& it) {
+    if (!bern_item(r, g, it)) return 0;
+    return bern_draw_mask(r, it);
 }
 
 __device__ __forceinline__ Res bern_res(const BernItem& it, uint32_t i) {
@@ -281,7 +309,7 @@ __device__ __forceinline__ Res bern_res(const BernItem& it, uint32_t i) {
 }
 
 // COUNT: connections per tile, and each item's 4-bit mask into `masks` (when
-// given).  WRITE: each thread takes IPT consecutive items of the tile, their
+// given); MARK: the connections' marks.  WRITE: each thread takes IPT consecutive items of the tile, their
 // masks from `masks` when given (the counting pass drew them; no second
 // Philox draw), else drawn again; one workgroup scan of the per-thread counts
 // places every connection of the tile in an LDS list in pair order (its pair
@@ -289,13 +317,15 @@ __device__ __forceinline__ Res bern_res(const BernItem& it, uint32_t i) {
 // synapse values and the stores, so the sparse hits of a low p leave no lane
 // idle, with three barriers per tile.
 template <class Sink, int MODE>
-__global__ __launch_bounds__(NT) void k_bern(BernPair r, Sink sink, uint64_t n_items, uint64_t tile0,
+__global__ __launch_bounds__(NT) void k_bern(BernPair r, Sink sink, uint64_t n_items, uint64_t tile0, uint32_t n_tiles,
                                              uint32_t* tile_counts, const uint64_t* tile_offsets, uint8_t* masks) {
     __shared__ uint32_t scratch[NT / 64];
-    const uint64_t tile = tile0 + blockIdx.x;
-    const uint64_t base = tile * TILE;
     if constexpr (MODE == WRITE) {
         static_assert(4 * TILE <= 65536 && IPT <= 8, "pair index within a tile fits 16 bits, masks 32 bits");
+        const uint64_t tile = tile0 + blockIdx.x;
+        const uint64_t base = tile * TILE;
+        const uint64_t running = tile_offsets[tile];
+        if (tile_offsets[tile + 1] == running) return;     // no connection in the tile
         __shared__ uint16_t hits[4 * TILE];
         const uint64_t first = base + (uint64_t)threadIdx.x * IPT;
         uint32_t mk = 0;   // 4 bits per item, item k at bits [4k, 4k + 4)
@@ -320,36 +350,49 @@ __global__ __launch_bounds__(NT) void k_bern(BernPair r, Sink sink, uint64_t n_i
             hits[pre++] = (uint16_t)(threadIdx.x * IPT * 4 + b);
         }
         __syncthreads();
-        const uint64_t running = tile_offsets[tile];
         for (uint32_t i = threadIdx.x; i < tot; i += NT) {
             const uint32_t h = hits[i];
             BernItem it{};
-            int64_t self;
-            (void)bern_item(r, base + (h >> 2), it, &self);
+            (void)bern_item(r, base + (h >> 2), it);
             sink.put(running + i, bern_res(it, h & 3u));
         }
         return;
     }
-    uint32_t counted = 0;
-#pragma unroll 1
-    for (int k = 0; k < IPT; ++k) {
-        const uint64_t item = base + (uint64_t)k * NT + threadIdx.x;
+    // COUNT and MARK: the launch's tiles in turn (a capped grid); each
+    // thread takes IPT consecutive items, so it decodes its first item only
+    // and steps through the target's blocks, and stores its masks in one word
+    const uint64_t t_end = tile0 + n_tiles;
+    for (uint64_t tile = tile0 + blockIdx.x; tile < t_end; tile += gridDim.x) {
+        const uint64_t first = tile * TILE + (uint64_t)threadIdx.x * IPT;
+        uint32_t counted = 0, packed = 0;
         BernItem it{};
-        uint32_t mask = 0;
-        if (item < n_items) {
-            mask = bern_mask(r, item, it);
-            if (MODE == COUNT && masks) masks[item] = (uint8_t)mask;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const uint64_t item = first + k;
+            uint32_t mask = 0;
+            if (item < n_items && (k == 0 ? bern_item(r, item, it) : bern_next(r, item, it)))
+                mask = bern_draw_mask(r, it);
+            packed |= mask << (8 * k);
+            if constexpr (MODE == MARK) {
+                for (uint32_t m = mask; m; m &= m - 1) sink.mark(bern_res(it, __builtin_ctz(m)));
+            } else {
+                counted += __builtin_popcount(mask);
+            }
         }
-        if constexpr (MODE == MARK) {
-            for (uint32_t m = mask; m; m &= m - 1) sink.mark(bern_res(it, __builtin_ctz(m)));
-        } else {
-            counted += __builtin_popcount(mask);
+        if constexpr (MODE == COUNT) {
+            if (masks) {
+                if (first + IPT <= n_items) {
+                    *reinterpret_cast<uint32_t*>(masks + first) = packed;   // 4-byte aligned: TILE, IPT multiples of 4
+                } else {
+                    for (int k = 0; k < IPT; ++k)
+                        if (first + k < n_items) masks[first + k] = (uint8_t)(packed >> (8 * k));
+                }
+            }
+            uint32_t tot;
+            block_excl_scan<NT>(counted, scratch, &tot);
+            if (threadIdx.x == 0) tile_counts[tile] = tot;
+            __syncthreads();   // the scan's scratch is written again by the next tile
         }
-    }
-    if constexpr (MODE == COUNT) {
-        uint32_t tot;
-        block_excl_scan<NT>(counted, scratch, &tot);
-        if (threadIdx.x == 0) tile_counts[tile] = tot;
     }
 }
 
@@ -359,9 +402,12 @@ void launch_bern(Ctx& c, const BernPair& r, const Sink& sink, uint64_t n_items, 
     const uint64_t tiles = (n_items + TILE - 1) / TILE;
     for (uint64_t t0 = 0; t0 < tiles; t0 += MAX_TILES_PER_LAUNCH) {
         const uint32_t nb = (uint32_t)std::min<uint64_t>(MAX_TILES_PER_LAUNCH, tiles - t0);
+        // WRITE: one workgroup per tile; COUNT and MARK: at most BERN_WGS_PER_CU
+        // workgroups per compute unit, each taking tiles in turn
+        const uint32_t grid = MODE == WRITE ? nb : std::min<uint32_t>(nb, (uint32_t)c.n_cu * BERN_WGS_PER_CU);
         tstart(c, MODE == MARK ? "prep_mark" : "gen_bernoulli");
-        hipLaunchKernelGGL((k_bern<Sink, MODE>), dim3(nb), dim3(NT), 0, c.stream, r, sink, n_items, t0, tile_counts,
-                           tile_offsets, masks);
+        hipLaunchKernelGGL((k_bern<Sink, MODE>), dim3(grid), dim3(NT), 0, c.stream, r, sink, n_items, t0, nb,
+                           tile_counts, tile_offsets, masks);
         tstop(c);
         HIPCHK(hipGetLastError());
     }

@@ -172,6 +172,7 @@ struct Ctx {
     double dt = 0.1;
     hipStream_t stream = nullptr;        // stream of the active lane (the caller's stream outside counting)
     int device = 0;
+    int n_cu = 256;                      // compute units of the device
     snnc_allocator alloc{};
     bool has_alloc = false;
     uint64_t budget = 0;
