@@ -969,60 +969,68 @@ __global__ __launch_bounds__(NT) void k_floyd(FloydArgs a, Sink sink, uint32_t* 
 constexpr uint32_t FLOYD_SMALL = 32;
 constexpr int FNT = 256;
 
+// One unit of the small-degree sampler; x points at the unit's first value
+// slot, slot j at x[j * stride].
+template <class Sink, int MODE>
+__device__ __forceinline__ void floyd_small_unit(const FloydArgs& a, uint64_t u, uint32_t* x, uint32_t stride,
+                                                 const Sink& sink, uint32_t* unit_counts,
+                                                 const uint64_t* unit_offsets) {
+    const uint64_t g = u * a.K;
+    const TChunk c = a.ch.at(g);
+    const uint32_t rel = (uint32_t)((g - c.out_begin) / a.K);
+    const uint64_t ord = c.t_ord + rel;
+    const int64_t self = c.self_base >= 0 ? c.self_base + rel : -1;
+    const uint32_t n_eff = a.n_set - (self >= 0 ? 1u : 0u);
+    const uint64_t e0 = ord * a.K;
+    for (uint32_t j = 0; j < a.K; ++j) {
+        const uint4 b = draw(a.seed, a.call, e0 + j, PURPOSE_IDX);
+        const uint32_t r = uniform_index(b.x, b.y, n_eff - a.K + j + 1);
+        bool found = false;
+        for (uint32_t i = 0; i < j; ++i) found |= x[i * stride] == r;
+        x[j * stride] = found ? n_eff - a.K + j : r;   // the fallback was never chosen before step j
+    }
+    for (uint32_t j = 1; j < a.K; ++j) {   // insertion sort, ascending
+        const uint32_t v = x[j * stride];
+        uint32_t i = j;
+        while (i > 0 && x[(i - 1) * stride] > v) {
+            x[i * stride] = x[(i - 1) * stride];
+            --i;
+        }
+        x[i * stride] = v;
+    }
+    uint64_t running = 0;
+    if constexpr (MODE == WRITE) running = unit_offsets[u];
+    uint32_t counted = 0;
+    for (uint32_t j = 0; j < a.K; ++j) {
+        uint32_t v = x[j * stride];
+        if (self >= 0 && v >= (uint64_t)self) ++v;
+        Res r{};
+        bool ok;
+        if (a.in_degree) {
+            r = Res{v, c.local_first + rel, e0 + j};
+            ok = true;
+        } else {
+            uint32_t h, l;
+            set_lookup(a.T, a.nT, v, h, l);
+            r = Res{(uint32_t)ord, l, e0 + j};
+            ok = (h == a.host);
+        }
+        if (!ok) continue;
+        if constexpr (MODE == DIRECT) sink.put(c.out_begin + (uint64_t)rel * a.K + j, r);
+        else if constexpr (MODE == MARK) sink.mark(r);
+        else if constexpr (MODE == COUNT) ++counted;
+        else sink.put(running++, r);
+    }
+    if constexpr (MODE == COUNT) unit_counts[u] = counted;
+}
+
 template <class Sink, int MODE>
 __global__ __launch_bounds__(FNT) void k_floyd_small(FloydArgs a, Sink sink, uint32_t* unit_counts,
                                                      const uint64_t* unit_offsets) {
     __shared__ uint32_t x[FLOYD_SMALL * FNT];
     const uint32_t t = threadIdx.x;
-    for (uint64_t u = (uint64_t)blockIdx.x * FNT + t; u < a.n_units; u += (uint64_t)gridDim.x * FNT) {
-        const uint64_t g = u * a.K;
-        const TChunk c = a.ch.at(g);
-        const uint32_t rel = (uint32_t)((g - c.out_begin) / a.K);
-        const uint64_t ord = c.t_ord + rel;
-        const int64_t self = c.self_base >= 0 ? c.self_base + rel : -1;
-        const uint32_t n_eff = a.n_set - (self >= 0 ? 1u : 0u);
-        const uint64_t e0 = ord * a.K;
-        for (uint32_t j = 0; j < a.K; ++j) {
-            const uint4 b = draw(a.seed, a.call, e0 + j, PURPOSE_IDX);
-            const uint32_t r = uniform_index(b.x, b.y, n_eff - a.K + j + 1);
-            bool found = false;
-            for (uint32_t i = 0; i < j; ++i) found |= x[i * FNT + t] == r;
-            x[j * FNT + t] = found ? n_eff - a.K + j : r;   // the fallback was never chosen before step j
-        }
-        for (uint32_t j = 1; j < a.K; ++j) {   // insertion sort, ascending
-            const uint32_t v = x[j * FNT + t];
-            uint32_t i = j;
-            while (i > 0 && x[(i - 1) * FNT + t] > v) {
-                x[i * FNT + t] = x[(i - 1) * FNT + t];
-                --i;
-            }
-            x[i * FNT + t] = v;
-        }
-        uint64_t running = 0;
-        if constexpr (MODE == WRITE) running = unit_offsets[u];
-        uint32_t counted = 0;
-        for (uint32_t j = 0; j < a.K; ++j) {
-            uint32_t v = x[j * FNT + t];
-            if (self >= 0 && v >= (uint64_t)self) ++v;
-            Res r{};
-            bool ok;
-            if (a.in_degree) {
-                r = Res{v, c.local_first + rel, e0 + j};
-                ok = true;
-            } else {
-                uint32_t h, l;
-                set_lookup(a.T, a.nT, v, h, l);
-                r = Res{(uint32_t)ord, l, e0 + j};
-                ok = (h == a.host);
-            }
-            if (!ok) continue;
-            if constexpr (MODE == DIRECT) sink.put(c.out_begin + (uint64_t)rel * a.K + j, r);
-            else if constexpr (MODE == MARK) sink.mark(r);
-            else if constexpr (MODE == COUNT) ++counted;
-            else sink.put(running++, r);
-        }
-        if constexpr (MODE == COUNT) unit_counts[u] = counted;
-    }
+    for (uint64_t u = (uint64_t)blockIdx.x * FNT + t; u < a.n_units; u += (uint64_t)gridDim.x * FNT)
+        floyd_small_unit<Sink, MODE>(a, u, x + t, FNT, sink, unit_counts, unit_offsets);
 }
 
 template <class Sink, int MODE, class KeyT>
@@ -1070,10 +1078,11 @@ void launch_floyd(Ctx& c, const FloydArgs& a, const Sink& sink, uint32_t* unit_c
 // Floyd's sampling written directly (one unit after another): sources and
 // targets by the sampler, then the synapse values by element index.
 bool defer_syn_fill(Ctx& c, const FloydArgs& a, const WriteSink& ws, uint64_t items);
+bool defer_floyd_small(Ctx& c, const FloydArgs& a, const WriteSink& ws);
 
 void launch_floyd_direct(Ctx& c, const FloydArgs& a, const WriteSink& ws, uint64_t items) {
     IdSink ids{ws.src, ws.tgt, ws.base};
-    launch_floyd<IdSink, DIRECT>(c, a, ids, nullptr, nullptr);
+    if (!(a.K <= FLOYD_SMALL && defer_floyd_small(c, a, ws))) launch_floyd<IdSink, DIRECT>(c, a, ids, nullptr, nullptr);
     if (!items) return;
     if (defer_syn_fill(c, a, ws, items)) return;   // the batch's fused launch writes them
     const uint32_t grid = (uint32_t)std::min<uint64_t>((items + NT - 1) / NT, 1u << 20);
@@ -1849,7 +1858,11 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
 // F_SYN_FILL: the synapse values of a Floyd call (its sources and targets
 // written by its own launch), element index from the run table as in
 // k_syn_fill; `ind` holds the run table and K.
-enum FusedKind : uint32_t { F_INDEGREE = 0, F_TOTAL = 1, F_OUTDEGREE = 2, F_ONE_TO_ONE = 3, F_SYN_FILL = 4 };
+// F_FLOYD_SMALL: the sources and targets of a Floyd call of degree up to
+// FLOYD_SMALL, one item per unit (`fl` holds the sampler's arguments).
+enum FusedKind : uint32_t {
+    F_INDEGREE = 0, F_TOTAL = 1, F_OUTDEGREE = 2, F_ONE_TO_ONE = 3, F_SYN_FILL = 4, F_FLOYD_SMALL = 5
+};
 
 struct FusedReq {
     uint64_t item_begin;
@@ -1860,6 +1873,7 @@ struct FusedReq {
     OutDegree outd;
     Total tot;
     OneToOne o2o;
+    FloydArgs fl;
 };
 
 struct FusedHdr {
@@ -1888,6 +1902,22 @@ bool defer_syn_fill(Ctx& c, const FloydArgs& a, const WriteSink& ws, uint64_t it
     return true;
 }
 
+// During a batch flush, a Floyd call of degree up to FLOYD_SMALL whose run
+// table travels inline leaves its sampling to the batch's fused launch (one
+// item per unit; item_begin holds the unit count until the flush places it).
+bool defer_floyd_small(Ctx& c, const FloydArgs& a, const WriteSink& ws) {
+    if (!c.gen_defer || a.ch.d || !a.n_units) return false;
+    FusedReq q;
+    memset(&q, 0, sizeof q);
+    q.kind = F_FLOYD_SMALL;
+    q.item_begin = a.n_units;
+    q.out_base = ws.base;
+    q.call = ws.call;
+    q.fl = a;
+    static_cast<std::vector<FusedReq>*>(c.gen_defer)->push_back(q);
+    return true;
+}
+
 // the descriptor holding item g among reqs[lo, hi) (g at or after reqs[lo])
 __device__ __forceinline__ uint32_t find_req(const FusedReq* reqs, uint32_t lo, uint32_t hi, uint64_t g) {
     while (hi - lo > 1) {
@@ -1897,9 +1927,16 @@ __device__ __forceinline__ uint32_t find_req(const FusedReq* reqs, uint32_t lo, 
     return lo;
 }
 
-// one item of the fused launch, generated by its call's descriptor q
-__device__ __forceinline__ void fused_item(const FusedReq* __restrict__ q, const FusedHdr& h, uint64_t item) {
+// one item of the fused launch, generated by its call's descriptor q; fx is
+// the thread's first slot of the small Floyd sampler's LDS values
+__device__ __forceinline__ void fused_item(const FusedReq* __restrict__ q, const FusedHdr& h, uint64_t item,
+                                           uint32_t* fx) {
     const uint64_t local = item - q->item_begin;
+    if (q->kind == F_FLOYD_SMALL) {
+        const IdSink ids{h.src, h.tgt, q->out_base};
+        floyd_small_unit<IdSink, DIRECT>(q->fl, local, fx, NT, ids, nullptr, nullptr);
+        return;
+    }
     if (q->kind == F_SYN_FILL) {
         const TChunk ck = q->ind.ch.at(local);
         const uint64_t off = local - ck.out_begin;
@@ -1927,7 +1964,10 @@ __device__ __forceinline__ void fused_item(const FusedReq* __restrict__ q, const
 }
 
 __global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs, const FusedHdr* __restrict__ hdr) {
+    static_assert(NT == FNT, "the small Floyd sampler's LDS layout");
     __shared__ uint32_t s_range[2];
+    __shared__ uint32_t fx[FLOYD_SMALL * NT];
+    uint32_t* const my_fx = fx + threadIdx.x;
     const FusedHdr h = *hdr;
     for (uint64_t tile = blockIdx.x; tile * TILE < h.total; tile += gridDim.x) {
         // the descriptors of the tile's first and last items, found once: the
@@ -1949,13 +1989,13 @@ __global__ __launch_bounds__(NT) void k_fused(const FusedReq* __restrict__ reqs,
 #pragma unroll 1
             for (int it = 0; it < IPT; ++it) {
                 const uint64_t item = tile * TILE + (uint64_t)it * NT + threadIdx.x;
-                if (item < h.total) fused_item(q, h, item);
+                if (item < h.total) fused_item(q, h, item, my_fx);
             }
         } else {
 #pragma unroll 1
             for (int it = 0; it < IPT; ++it) {
                 const uint64_t item = tile * TILE + (uint64_t)it * NT + threadIdx.x;
-                if (item < h.total) fused_item(reqs + find_req(reqs, r_lo, r_hi, item), h, item);
+                if (item < h.total) fused_item(reqs + find_req(reqs, r_lo, r_hi, item), h, item, my_fx);
             }
         }
     }

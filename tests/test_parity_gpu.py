@@ -276,6 +276,16 @@ def test_floyd_sort_key_widths(rule, k, n_src, n_tgt, aut, wave_max):
     compare_all(s, 0)
 
 
+@pytest.mark.parametrize("aut", [False, True])
+@pytest.mark.parametrize("p", [1.0, 0.5])
+@pytest.mark.parametrize("n_src,n_tgt", [(1, 1), (2, 7), (3, 50), (5, 90), (7, 33), (1030, 300)])
+def test_bernoulli_block_edges(n_src, n_tgt, p, aut):
+    # source counts that leave a target's pairs starting and ending inside Philox blocks, with the
+    # targets among the sources so that the excluded autapse falls at every position of a block
+    conn = {"rule": "pairwise_bernoulli", "p": p, "autapses": aut}
+    compare_all(_one(conn, n_src=n_src, n_tgt=n_tgt), 0)
+
+
 @pytest.mark.parametrize("tune", [{"total_hash_max": 0}, {"total_small_max": 0}, {"total_small_max": 1 << 15}],
                          ids=["sorted", "filtered", "one_workgroup"])
 @pytest.mark.parametrize("n,aut,n_src,n_tgt", [(1_100_000, True, 3000, 2500), (150_000, False, 3000, 2500),
@@ -345,6 +355,48 @@ def test_many_segment_sets_batched(conn):
     net.flush()
     net.prepare()
     ref = oracle.run_script(s, 0)
+    for k in ("src", "tgt", "delay", "weight", "row_ptr"):
+        compare(k, net.array(k), ref.array(k), s["name"] + " batched")
+    net.close()
+
+
+def _floyd_degrees_script():
+    # Floyd calls (no multapses) of degrees on both sides of the small sampler's limit of 32,
+    # single-segment sets (run tables inline), among fusable calls, so that a batch's fused launch
+    # holds small-sampler units next to connection items of other calls
+    b = W._Builder(1, seed=57)
+    a = b.create(0, 900)
+    c = b.create(0, 700)
+    d = b.create(0, 40)
+    for k, (rule, aut) in enumerate([("fixed_indegree", False), ("fixed_outdegree", True),
+                                     ("fixed_indegree", True), ("fixed_outdegree", False)]):
+        for K in (1, 2, 7, 31, 32, 33, 100):
+            src, tgt = (a, c) if k % 2 == 0 else (c, a)
+            b.connect([src], [tgt], {"rule": rule, "n": K, "autapses": aut, "multapses": False}, SYN_N)
+        b.connect([d], [a], {"rule": "fixed_indegree", "n": 5, "autapses": True, "multapses": True}, SYN_N)
+    b.connect([a], [a], {"rule": "fixed_indegree", "n": 20, "autapses": False, "multapses": False}, SYN_N)
+    b.connect([d], [d], {"rule": "fixed_outdegree", "n": 39, "autapses": False, "multapses": False}, SYN_N)
+    return b.script("floyd_degrees")
+
+
+def test_batched_floyd_degrees():
+    # per call and as one batch (small-degree sampling inside the batch's fused launch): the oracle's sets
+    import paper_2512_09502_amd as snnc
+    s = _floyd_degrees_script()
+    compare_all(s, 0)
+    net = snnc.Network(1, 0, s["seed"], s["dt"])
+    reqs = []
+    for op in s["ops"]:
+        if op[0] == "create":
+            net.create(op[1], op[2])
+        else:
+            reqs.append(op[1:])
+    assert all(status == 0 for status, _ in net.submit_many(reqs))
+    net.flush()
+    ref = oracle.run_script(s, 0)
+    for k in ("gen_src", "gen_tgt", "gen_delay", "gen_weight", "call_off"):   # generation order, per call
+        compare(k, net.array(k), ref.array(k), s["name"] + " batched")
+    net.prepare()
     for k in ("src", "tgt", "delay", "weight", "row_ptr"):
         compare(k, net.array(k), ref.array(k), s["name"] + " batched")
     net.close()
