@@ -905,6 +905,23 @@ static Call make_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tgt, 
 // resident bytes of a call with n connections: 14 B per connection + metadata
 static uint64_t resident_cost(const Call& cl, uint64_t n) { return n * 14 + cl.meta_bytes; }
 
+// A lower bound of a call's local connection count, known without draws: a
+// fixed total number with every target on this host keeps exactly N, and the
+// other rules counted on the device may keep none.
+static uint64_t min_local_count(const Ctx& c, const Call& cl) {
+    if (cl.rule != SNNC_FIXED_TOTAL_NUMBER) return 0;
+    uint64_t on_host = 0;
+    for (auto& g : cl.T.seg) if (g.host == c.P_local) on_host += g.n;
+    return on_host == cl.T.total ? cl.n : 0;
+}
+
+// Whether admission rejects the call whatever its draws give: the budget is
+// exceeded already by its smallest possible count (the resident bytes only
+// grow until then), so its device count can be skipped.
+static bool surely_over_budget(const Ctx& c, const Call& cl) {
+    return c.resident_budget && c.resident_bytes + resident_cost(cl, min_local_count(c, cl)) > c.resident_budget;
+}
+
 static void admit(Ctx& c, Call& cl, uint64_t n) {
     const uint64_t cost = resident_cost(cl, n);
     if (c.resident_budget && c.resident_bytes + cost > c.resident_budget)
@@ -936,6 +953,10 @@ static Call counted_call(Ctx& c, const snnc_nodeset* src, const snnc_nodeset* tg
     }
     CountScope lane(c);
     upload_meta(c, cl);
+    if (surely_over_budget(c, cl)) {   // the caller's admission rejects it: no device count
+        *n_out = min_local_count(c, cl);
+        return cl;
+    }
     try {
         *n_out = gen_count_local(c, cl);
     } catch (...) {
@@ -1129,6 +1150,11 @@ static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const 
                     Call& cl = cls[i];
                     cl.id = next;
                     uint64_t est = count[i];
+                    if (on_device[i] && surely_over_budget(c, cl)) {
+                        // rejected at admission whatever the draws give: no device count
+                        on_device[i] = 0;
+                        est = count[i] = min_local_count(c, cl);
+                    }
                     if (on_device[i]) {
                         release_pre(c, cl);
                         cl.deferred = 0;

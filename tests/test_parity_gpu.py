@@ -360,10 +360,11 @@ def test_many_segment_sets_batched(conn):
     net.close()
 
 
-def _floyd_degrees_script():
-    # Floyd calls (no multapses) of degrees on both sides of the small sampler's limit of 32,
-    # single-segment sets (run tables inline), among fusable calls, so that a batch's fused launch
-    # holds small-sampler units next to connection items of other calls
+def _batch_mix_script():
+    # Floyd calls (no multapses) of degrees on both sides of the small sampler's limit of 32 and
+    # Bernoulli calls of sizes that end inside a tile, single-segment sets (run tables inline),
+    # among fusable calls: a batch's fused launch then holds small-sampler units, whole Bernoulli
+    # writing tiles (after alignment padding) and connection items of other calls
     b = W._Builder(1, seed=57)
     a = b.create(0, 900)
     c = b.create(0, 700)
@@ -374,15 +375,18 @@ def _floyd_degrees_script():
             src, tgt = (a, c) if k % 2 == 0 else (c, a)
             b.connect([src], [tgt], {"rule": rule, "n": K, "autapses": aut, "multapses": False}, SYN_N)
         b.connect([d], [a], {"rule": "fixed_indegree", "n": 5, "autapses": True, "multapses": True}, SYN_N)
+        for p, src, tgt in ((0.3, d, d), (0.01, a, c), (1.0, d, a), (0.2, a, a)):
+            b.connect([src], [tgt], {"rule": "pairwise_bernoulli", "p": p, "autapses": k % 2 == 1}, SYN_N)
     b.connect([a], [a], {"rule": "fixed_indegree", "n": 20, "autapses": False, "multapses": False}, SYN_N)
     b.connect([d], [d], {"rule": "fixed_outdegree", "n": 39, "autapses": False, "multapses": False}, SYN_N)
-    return b.script("floyd_degrees")
+    return b.script("batch_mix")
 
 
-def test_batched_floyd_degrees():
-    # per call and as one batch (small-degree sampling inside the batch's fused launch): the oracle's sets
+def test_batched_floyd_and_bernoulli():
+    # per call and as one batch (small-degree sampling and Bernoulli writing inside the batch's
+    # fused launch): the oracle's connections, in generation order and after Prepare
     import paper_2512_09502_amd as snnc
-    s = _floyd_degrees_script()
+    s = _batch_mix_script()
     compare_all(s, 0)
     net = snnc.Network(1, 0, s["seed"], s["dt"])
     reqs = []
