@@ -1140,6 +1140,7 @@ static void submit_many_impl(Ctx& c, uint32_t n, const snnc_nodeset* src, const 
                         c.scan_batching = false;
                         for (void* p : c.scan_owned) dfree(c, p);
                         c.scan_jobs.clear();
+                        c.first_jobs.clear();
                         c.scan_owned.clear();
                     }
                 } scan_batch{c};

@@ -1221,10 +1221,20 @@ __device__ uint8_t settle_pending(const Total& t, uint64_t i, const PendingTab& 
 constexpr uint32_t FS_NT = 1024;
 static_assert(TILE == FS_NT, "one tile per iteration of the workgroup");
 
-__global__ __launch_bounds__(FS_NT) void k_first_small(Total t, uint64_t n, uint32_t n_t, uint64_t* block,
-                                                       uint64_t words, uint64_t H, uint64_t slot_mask,
-                                                       uint8_t* first, uint64_t* voff, uint64_t* total_out) {
-    __shared__ uint32_t scratch[FS_NT / 64];
+struct FirstSmallJob {
+    Total t;
+    uint64_t n;
+    uint32_t n_t;
+    uint64_t* block;
+    uint64_t words, H, slot_mask;
+    uint8_t* first;
+    uint64_t* voff;
+    uint64_t* total_out;
+};
+
+__device__ __forceinline__ void first_small_window(const Total& t, uint64_t n, uint32_t n_t, uint64_t* block,
+                                                   uint64_t words, uint64_t H, uint64_t slot_mask, uint8_t* first,
+                                                   uint64_t* voff, uint64_t* total_out, uint32_t* scratch) {
     const uint32_t tid = threadIdx.x;
     uint64_t* tab = block;
     uint32_t* minidx = reinterpret_cast<uint32_t*>(block + H);
@@ -1291,6 +1301,20 @@ __global__ __launch_bounds__(FS_NT) void k_first_small(Total t, uint64_t n, uint
         voff[tiles] = running;
         *total_out = running;
     }
+}
+
+__global__ __launch_bounds__(FS_NT) void k_first_small(Total t, uint64_t n, uint32_t n_t, uint64_t* block,
+                                                       uint64_t words, uint64_t H, uint64_t slot_mask,
+                                                       uint8_t* first, uint64_t* voff, uint64_t* total_out) {
+    __shared__ uint32_t scratch[FS_NT / 64];
+    first_small_window(t, n, n_t, block, words, H, slot_mask, first, voff, total_out, scratch);
+}
+
+// The small windows of a batch's admission counts: one workgroup per window.
+__global__ __launch_bounds__(FS_NT) void k_first_small_multi(const FirstSmallJob* jobs) {
+    __shared__ uint32_t scratch[FS_NT / 64];
+    const FirstSmallJob j = jobs[blockIdx.x];
+    first_small_window(j.t, j.n, j.n_t, j.block, j.words, j.H, j.slot_mask, j.first, j.voff, j.total_out, scratch);
 }
 
 struct DeviceChunks {
@@ -1564,13 +1588,24 @@ uint64_t run_call(Ctx& c, Call& cl, uint32_t host, Out mode, uint32_t* mark_bits
                     voff = dalloc_n<uint64_t>(c, tiles + 1);
                     temps.insert(temps.end(), {block, first, voff});
                     uint64_t* total_out = deferred ? c.defer_slot : c.tot_pin_dev + (c.stream == c.count_stream ? 1 : 0);
-                    tstart(c, "gen_total_first");
-                    hipLaunchKernelGGL(k_first_small, dim3(1), dim3(FS_NT), 0, c.stream, r, C, (uint32_t)nt, block,
-                                       H + H / 2 + m / 32, H, m - 1, first, voff, total_out);
-                    tstop(c);
-                    HIPCHK(hipGetLastError());
-                    dfree(c, block);
                     temps.erase(std::remove(temps.begin(), temps.end(), (void*)block), temps.end());
+                    if (deferred && all_local && c.scan_batching) {
+                        // batched admission: launched with the batch's other small windows, before
+                        // the scans (no later count of this call reads its flags or offsets)
+                        const FirstSmallJob job{r, C, (uint32_t)nt, block, H + H / 2 + m / 32, H, m - 1,
+                                                first, voff, total_out};
+                        const uint8_t* b = reinterpret_cast<const uint8_t*>(&job);
+                        c.first_jobs.insert(c.first_jobs.end(), b, b + sizeof job);
+                        c.scan_owned.push_back(block);   // released after that launch
+                    } else {
+                        tstart(c, "gen_total_first");
+                        hipLaunchKernelGGL(k_first_small, dim3(1), dim3(FS_NT), 0, c.stream, r, C, (uint32_t)nt,
+                                           block, H + H / 2 + m / 32, H, m - 1, first, voff, total_out);
+                        tstop(c);
+                        const hipError_t e = hipGetLastError();
+                        dfree(c, block);
+                        HIPCHK(e);
+                    }
                 } else if (!cl.multapses && C <= c.total_hash_max) {
                     // filter: 2 bits per slot, at least 16 slots per candidate
                     uint64_t m = 1024;
@@ -2090,6 +2125,26 @@ __global__ void k_philox_blocks(uint32_t seed, uint32_t call, uint64_t e0, uint3
 }  // namespace
 
 uint64_t gen_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, Out::APPEND, nullptr); }
+
+void first_small_batch_run(Ctx& c) {
+    if (c.first_jobs.empty()) return;
+    const size_t bytes = c.first_jobs.size();
+    const unsigned n = (unsigned)(bytes / sizeof(FirstSmallJob));
+    void* dev = dalloc(c, bytes);
+    try {
+        upload(c, dev, c.first_jobs.data(), bytes);
+    } catch (...) {
+        dfree(c, dev);
+        throw;
+    }
+    c.first_jobs.clear();
+    tstart(c, "gen_total_first");
+    hipLaunchKernelGGL(k_first_small_multi, dim3(n), dim3(FS_NT), 0, c.stream, static_cast<const FirstSmallJob*>(dev));
+    tstop(c);
+    const hipError_t e = hipGetLastError();
+    dfree(c, dev);   // in stream order, after the launch
+    HIPCHK(e);
+}
 
 uint64_t gen_count_local(Ctx& c, Call& cl) { return run_call(c, cl, c.P_local, Out::COUNT, nullptr); }
 

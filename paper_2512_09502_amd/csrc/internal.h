@@ -264,6 +264,9 @@ struct Ctx {
     bool scan_batching = false;
     std::vector<ScanJob> scan_jobs;
     std::vector<void*> scan_owned;
+    // small first-occurrence windows queued the same way (launched together,
+    // one workgroup each, by scan_batch_run); the job records as bytes
+    std::vector<uint8_t> first_jobs;
     uint64_t* defer_pin = nullptr;
     uint64_t* defer_pin_dev = nullptr;
     size_t defer_cap = 0;                // requests the pinned words hold
@@ -394,6 +397,8 @@ constexpr uint64_t SCAN_BATCH_MAX = 1u << 16;
 void scan_u32_u64_later(Ctx& c, uint32_t* in, uint64_t* out, uint64_t n, uint64_t* total_dev);
 // launches every queued scan in one kernel on the active lane and frees their inputs
 void scan_batch_run(Ctx& c);
+// launches the queued small first-occurrence windows (part of scan_batch_run)
+void first_small_batch_run(Ctx& c);
 // the same over popcounts of 32-bit words
 uint64_t scan_popc_u64(Ctx& c, const uint32_t* words, uint64_t* out, uint64_t n_words, bool want_total);
 uint64_t scan_u64_u64(Ctx& c, const uint64_t* in, uint64_t* out, uint64_t n, bool want_total);

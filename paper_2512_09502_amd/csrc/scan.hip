@@ -174,6 +174,7 @@ void scan_u32_u64_later(Ctx& c, uint32_t* in, uint64_t* out, uint64_t n, uint64_
 }
 
 void scan_batch_run(Ctx& c) {
+    first_small_batch_run(c);
     if (!c.scan_jobs.empty()) {
         const size_t bytes = c.scan_jobs.size() * sizeof(ScanJob);
         ScanJob* dev = static_cast<ScanJob*>(dalloc(c, bytes));
