@@ -360,6 +360,13 @@ def test_many_segment_sets_batched(conn):
     net.close()
 
 
+@pytest.mark.parametrize("p", [1e-4, 2e-6])
+def test_bernoulli_sparse_tiles(p):
+    # most tiles of 4,096 pairs hold no connection (the writing pass skips them) or a single one
+    conn = {"rule": "pairwise_bernoulli", "p": p, "autapses": False}
+    compare_all(_one(conn, n_src=3000, n_tgt=2500), 0)
+
+
 def _batch_mix_script():
     # Floyd calls (no multapses) of degrees on both sides of the small sampler's limit of 32 and
     # Bernoulli calls of sizes that end inside a tile, single-segment sets (run tables inline),
