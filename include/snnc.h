@@ -238,7 +238,10 @@ snnc_status snnc_set_resident_budget(snnc_ctx* ctx, uint64_t bytes);
 /* Submit a Connect request (arguments as snnc_connect): validate, count,
  * admit and reserve its positions now; generate it at the next snnc_flush.
  * *call_id_out receives its call id.  Errors: as snnc_connect, plus
- * SNNC_EBUDGET when the request does not fit the resident budget. */
+ * SNNC_EBUDGET when the request does not fit the resident budget.  A request
+ * whose smallest possible count already exceeds what the budget has left (a
+ * fixed total number with every target on this host keeps exactly N) gets
+ * SNNC_EBUDGET without its count being drawn on the device. */
 snnc_status snnc_submit(snnc_ctx* ctx, const snnc_nodeset* src, const snnc_nodeset* tgt,
                         const snnc_conn_spec* conn, const snnc_syn_spec* syn, int32_t alpha, uint32_t* call_id_out);
 
