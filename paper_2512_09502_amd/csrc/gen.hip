@@ -581,21 +581,34 @@ __global__ __launch_bounds__(NT) void k_total_dist(Total rule, uint32_t host, Si
         }
         return;
     }
+    if constexpr (MODE == CNT_VALID) {
+        // valid candidates per tile: each thread takes IPT consecutive
+        // candidates (independent draws in flight); a candidate sharing its
+        // filter slot is settled first, and its flag written back
+        const uint64_t first_item = base + (uint64_t)threadIdx.x * IPT;
+        uint32_t nv = 0;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const uint64_t item = first_item + k;
+            if (item >= n_items) continue;
+            if (pend.tab && pend.first[item] == FIRST_PENDING) pend.first[item] = settle_pending(rule, item, pend);
+            Res r{};
+            uint32_t th = 0;
+            nv += (uint32_t)rule.eval(item, &r, &th);
+        }
+        uint32_t tot;
+        block_excl_scan<NT>(nv, scratch, &tot);
+        if (threadIdx.x == 0) tile_counts[tile] = tot;
+        return;
+    }
     uint32_t counted = 0;
 #pragma unroll 1
     for (int it = 0; it < IPT; ++it) {
         const uint64_t item = base + (uint64_t)it * NT + threadIdx.x;
-        if constexpr (MODE == CNT_VALID) {
-            // a candidate sharing its filter slot: settled here, and its flag written back
-            if (pend.tab && item < n_items && pend.first[item] == FIRST_PENDING)
-                pend.first[item] = settle_pending(rule, item, pend);
-        }
         Res r{};
         uint32_t th = 0;
         const uint32_t v = item < n_items ? (uint32_t)rule.eval(item, &r, &th) : 0u;
-        if constexpr (MODE == CNT_VALID) {
-            counted += v;
-        } else {
+        {
             uint32_t vtot;
             const uint32_t vpre = block_excl_scan<NT>(v, scratch, &vtot);
             const uint64_t rank = vrun + vpre;
@@ -615,7 +628,7 @@ __global__ __launch_bounds__(NT) void k_total_dist(Total rule, uint32_t host, Si
             }
         }
     }
-    if constexpr (MODE == CNT_VALID || MODE == CNT_KEEP) {
+    if constexpr (MODE == CNT_KEEP) {
         uint32_t tot;
         block_excl_scan<NT>(counted, scratch, &tot);
         if (threadIdx.x == 0) tile_counts[tile] = tot;
